@@ -1,0 +1,194 @@
+"""Pins for the oracle's H-matrix, H-LU, H-solves and Krylov solvers (no GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+import fde_inputs as fi
+from oracle import toeplitz
+from oracle.hmatrix import HLU, HLUBreakdown, HMatrix, leaves, taylor_coefficients, to_dense
+from oracle.krylov import bicgstab, dense_solve, fgmres
+from oracle.sem import SEM
+
+
+def sem_small(theta=0.5, rho=0.0, mesh=None, P=4, alpha=1.5):
+    mesh = fi.uniform_mesh(16) if mesh is None else mesh
+    return SEM(mesh, P, alpha, theta, rho)
+
+
+def test_taylor_coefficients_are_the_series_of_the_kernel():
+    """sum_nu c_nu (t-s0)^{1-a-nu} (s-s0)^nu -> (t-s)^{1-a} (Lemma, eq. (eqn:Lexpan))."""
+    al = 1.37
+    c = taylor_coefficients(al, 60)
+    t, s0, s = 3.0, 1.0, 1.4
+    approx = sum(c[n] * (t - s0) ** (1 - al - n) * (s - s0) ** n for n in range(60))
+    assert abs(approx - (t - s) ** (1 - al)) < 1e-14
+
+
+def test_block_counts_config_small():
+    H = HMatrix(sem_small(), 4, 1.0, 2)
+    assert H.counts() == (34, 24)
+
+
+def test_dense_blocks_hold_exact_entries_and_error_decays_with_rank():
+    """Near blocks are exact; ||S - H||_F falls like (lambda/(2+lambda))^R (Theorem 2, fig. matrixerror)."""
+    sem = sem_small(theta=1.0)
+    A = sem.system_matrix()
+    errs = []
+    for R in range(1, 25):
+        H = HMatrix(sem, R, 1.0, 2)
+        Ah = A[np.ix_(H.h2p, H.h2p)]
+        At = to_dense(H.root)
+        for b in leaves(H.root):
+            if b.kind == "D":
+                sl = (slice(b.tau.d0, b.tau.d1), slice(b.sigma.d0, b.sigma.d1))
+                assert np.array_equal(At[sl], b.D)
+                assert np.abs(b.D - Ah[sl]).max() <= 1e-15 * np.abs(Ah).max()
+        errs.append(np.linalg.norm(Ah - At) / np.linalg.norm(Ah))
+    for R in range(1, 14):
+        assert errs[R] < errs[R - 1] / 2.5, (R, errs[R - 1], errs[R])
+    assert errs[23] < 1e-13
+
+
+@pytest.mark.parametrize("lam", [1.0, 0.5, 0.25])
+def test_error_decay_for_several_admissibility_parameters(lam):
+    """The paper's fig. matrixerror setting on a graded mesh: decay for lambda = 1, 0.5, 0.25."""
+    sem = SEM(fi.graded_mesh(64, 5.0, 0.0, 10.0), 3, 1.6, 1.0, 0.0)
+    A = sem.system_matrix()
+    assert HMatrix(sem, 2, lam, 2).counts()[1] > 0
+    e = []
+    for R in (2, 4, 6, 8):
+        H = HMatrix(sem, R, lam, 2)
+        Ah = A[np.ix_(H.h2p, H.h2p)]
+        e.append(np.linalg.norm(Ah - to_dense(H.root)))
+    assert e[0] > e[1] > e[2] > e[3]
+    assert e[3] < e[0] * (lam / (2 + lam)) ** 4 * 10
+
+
+def test_entrywise_bound_theorem2():
+    """|B - B~| <= 8 h_i c0 gamma0 delta^R on bubble-bubble entries (eq. (eq408)), uniform mesh."""
+    sem = SEM(fi.uniform_mesh(32), 4, 1.5, 1.0, 0.0)
+    A = sem.system_matrix()
+    lam = 1.0
+    for R in (2, 4, 6):
+        H = HMatrix(sem, R, lam, 2)
+        Ah = A[np.ix_(H.h2p, H.h2p)]
+        P = sem.P
+        for b in leaves(H.root):
+            if b.kind != "R" or not (b.tau.lo >= b.sigma.hi):
+                continue
+            ap, dp = b.tau.lo, b.sigma.hi
+            s0 = 0.5 * (b.sigma.lo + b.sigma.hi)
+            c0 = (1 + lam / 2) * (R + 1 + lam / 2) / (abs(ap - dp) + abs(dp - s0)) ** sem.alpha
+            delta = lam / (2 + lam)
+            err = np.abs(Ah[b.tau.d0:b.tau.d1, b.sigma.d0:b.sigma.d1] - b.U @ b.V.T)
+            rows = np.arange(b.tau.d0, b.tau.d1)
+            cols = np.arange(b.sigma.d0, b.sigma.d1)
+            bub_r = (rows % P) != P - 1
+            bub_c = (cols % P) != P - 1
+            hmax = sem.h.max()
+            bound = 8 * hmax * c0 * sem.gamma0 * delta ** R
+            assert err[np.ix_(bub_r, bub_c)].max() <= bound
+
+
+def test_hlu_without_truncation_is_the_exact_lu():
+    """tol = 0, no rank cap: L_H U_H = A~ with L_H unit lower, U_H upper (unique LU)."""
+    sem = sem_small(theta=0.3, rho=1.0, mesh=fi.two_sided_graded_mesh(16, 3, 0.5))
+    H = HMatrix(sem, 6, 1.0, 2)
+    At = to_dense(H.root)
+    F = HLU(H, tol=0.0, kmax=10 ** 6)
+    L, U = F.dense_factors()
+    assert np.linalg.norm(L @ U - At) <= 1e-13 * np.linalg.norm(At)
+    # independent: elimination without pivoting of the dense A~
+    Ad = At.copy()
+    n = Ad.shape[0]
+    for k in range(n):
+        Ad[k + 1:, k] /= Ad[k, k]
+        Ad[k + 1:, k + 1:] -= np.outer(Ad[k + 1:, k], Ad[k, k + 1:])
+    assert np.abs(np.tril(Ad, -1) + np.eye(n) - L).max() < 1e-10
+    assert np.abs(np.triu(Ad) - U).max() <= 1e-10 * np.abs(U).max()
+
+
+@pytest.mark.parametrize("tol", [1e-2, 1e-3, 1e-5])
+def test_hlu_accuracy_follows_tolerance(tol):
+    sem = sem_small(theta=0.7, rho=0.0, mesh=fi.graded_mesh(24, 3.0, 0.0, 1.0))
+    H = HMatrix(sem, 8, 1.0, 2)
+    At = to_dense(H.root)
+    F = HLU(H, tol=tol)
+    L, U = F.dense_factors()
+    assert np.linalg.norm(L @ U - At) <= 20 * tol * np.linalg.norm(At)
+    g = np.random.default_rng(1).standard_normal(sem.Nd)
+    x = F.solve(g)
+    Ap = np.empty_like(At); Ap[np.ix_(H.h2p, H.h2p)] = At      # back to paper order
+    rel = np.linalg.norm(Ap @ x - g) / np.linalg.norm(g)
+    assert rel < 1e4 * tol
+
+
+def test_hsolve_is_forward_then_backward_substitution():
+    sem = sem_small(theta=0.5, rho=0.0)
+    H = HMatrix(sem, 4, 1.0, 2)
+    F = HLU(H, tol=1e-3)
+    L, U = F.dense_factors()
+    g = np.random.default_rng(2).standard_normal((sem.Nd, 3))
+    x = F.solve(g)
+    ref = np.linalg.solve(U, np.linalg.solve(L, g[H.h2p]))
+    xp = np.empty_like(ref); xp[H.h2p] = ref
+    assert np.abs(x - xp).max() <= 1e-12 * np.abs(xp).max()
+
+
+def test_hlu_breakdown_is_reported():
+    sem = sem_small()
+    H = HMatrix(sem, 4, 1.0, 2)
+    for b in leaves(H.root):
+        if b.kind == "D" and b.tau is b.sigma:
+            b.D[0, 0] = 0.0
+            b.D[0, :] = 0.0
+            break
+    with pytest.raises(HLUBreakdown):
+        HLU(H, tol=1e-3)
+
+
+def test_fgmres_and_bicgstab_reach_the_dense_solution():
+    inst = fi.config_small()
+    sem = SEM(inst.nodes, inst.P, inst.alpha, inst.theta, inst.rho)
+    A = sem.system_matrix()
+    G = sem.load_vector(inst.solution.f_terms)
+    Xs, kappa = dense_solve(A, G)
+    F = HLU(HMatrix(sem, 4, 1.0, 2), tol=1e-3)
+    X, info = fgmres(lambda v: A @ v, G, F.solve, restart=30, tol=1e-12)
+    assert info["converged"] and info["iters"] <= 8
+    assert np.linalg.norm(X - Xs) <= 1e-11 * np.linalg.norm(Xs)
+    X2, info2 = bicgstab(lambda v: A @ v, G, F.solve, tol=1e-13, side="right")
+    assert info2["true_relres"] < 1e-12
+    Xu = sem.interpolate_coefficients(inst.solution.u)
+    assert np.linalg.norm(X - Xu) <= 1e-12 * np.linalg.norm(Xu)
+    # no preconditioner: many more iterations
+    X3, info3 = fgmres(lambda v: A @ v, G, None, restart=30, tol=1e-12, maxit=400)
+    assert info3["iters"] > 3 * info["iters"]
+
+
+def test_table1_iteration_envelope():
+    """Example 1, P = 3, graded power-5 mesh, theta = 1: BiCGSTAB on eq. (precondsys)
+    needs at most 16 steps for R >= 2 and about 4 at R = 7 (Table 1); counts do not
+    grow with R."""
+    m = fi.example1(1.6)
+    sem = SEM(fi.graded_mesh(100, 5.0, 0.0, 10.0), 3, 1.6, 1.0, 0.0)
+    A = sem.system_matrix()
+    G = sem.load_vector(m.f_terms)
+    its = []
+    for R in (2, 3, 5, 7):
+        F = HLU(HMatrix(sem, R, 1.0, 2), tol=1e-3)
+        X, info = bicgstab(lambda v: A @ v, G, F.solve, tol=1e-13, side="left")
+        assert info["converged"] and info["true_relres"] < 1e-11
+        its.append(info["iters"])
+    assert max(its) <= 16 and its[-1] <= 4
+    assert its == sorted(its, reverse=True)
+
+
+@pytest.mark.parametrize("mesh", [fi.uniform_mesh(21), fi.geometric_mesh(17, 1.08),
+                                  fi.geometric_mesh(12, 0.9)])
+def test_toeplitz_apply_equals_dense(mesh):
+    sem = SEM(mesh, 4, 1.65, 0.35, 0.4)
+    A = sem.system_matrix()
+    x = np.random.default_rng(3).standard_normal((sem.Nd, 2))
+    assert np.linalg.norm(toeplitz.apply(sem, x) - A @ x) <= 1e-14 * np.linalg.norm(A @ x)
