@@ -92,11 +92,14 @@ class PowerSum:
     expo: np.ndarray
     side: np.ndarray  # 0 for (x-a), 1 for (b-x)
 
-    def __call__(self, x, a: float, b: float) -> np.ndarray:
+    def __call__(self, x, a: float, b: float, da=None, db=None) -> np.ndarray:
+        """Value at x; da = x - a and db = b - x may be given exactly (near the ends)."""
         x = np.asarray(x, dtype=np.float64)
+        da = (x - a) if da is None else np.asarray(da, dtype=np.float64)
+        db = (b - x) if db is None else np.asarray(db, dtype=np.float64)
         out = np.zeros_like(x)
         for c, e, s in zip(self.coef, self.expo, self.side):
-            d = (x - a) if s == 0 else (b - x)
+            d = da if s == 0 else db
             with np.errstate(divide="ignore", invalid="ignore"):
                 t = np.where(d > 0, c * np.power(np.maximum(d, 0.0), e), 0.0 if e > 0 else (c if e == 0 else np.inf))
             out = out + t
@@ -137,8 +140,9 @@ class Manufactured:
     def u(self, x) -> np.ndarray:
         return self.u_left(x, self.a, self.b)
 
-    def f(self, x) -> np.ndarray:
-        return self.f_terms(x, self.a, self.b)
+    def f(self, x, da=None, db=None) -> np.ndarray:
+        """f at x; pass da = x - a, db = b - x when known without cancellation."""
+        return self.f_terms(x, self.a, self.b, da, db)
 
 
 def _rl_terms(coef, expo, side, alpha, weight):
@@ -236,9 +240,9 @@ def random_polynomial_rhs(gen: np.random.Generator, degree: int, count: int,
 
 
 def poly_function(coef: np.ndarray, a: float):
-    """Callable x -> sum_k coef_k (x-a)^k (Horner)."""
-    def f(x):
-        x = np.asarray(x, dtype=np.float64) - a
+    """Callable x -> sum_k coef_k (x-a)^k (Horner); accepts (x, da, db) too."""
+    def f(x, da=None, db=None):
+        x = (np.asarray(x, dtype=np.float64) - a) if da is None else np.asarray(da, dtype=np.float64)
         y = np.zeros_like(x)
         for ck in coef[::-1]:
             y = y * x + ck

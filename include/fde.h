@@ -1,0 +1,204 @@
+/*
+ * fde.h -- C ABI of the MI355X (gfx950) solver for the spectral element
+ * discretisation of the one-dimensional two-sided Riemann-Liouville
+ * fractional diffusion equation, with an H-matrix preconditioner.
+ *
+ * Problem (Section 1, eq. (Model)):
+ *   -D^2 ( theta aI_x^{2-alpha} u + (1-theta) xI_b^{2-alpha} u ) + rho u = f  on (a,b),
+ *   u(a) = c1, u(b) = c2,   1 < alpha < 2,  0 <= theta <= 1,  rho >= 0.
+ * Discretisation (Section 2.2, eq. (lsys)): A X = G with A = rho M + S,
+ *   S = theta S_l + (1-theta) S_l^T, on the space S_N^P of N elements of degree P.
+ *
+ * Conventions shared by every call:
+ *  - Every function returns an int status: FDE_OK (0) or a negative FDE_E* code;
+ *    fde_last_error() gives a message for the calling thread's last failure.
+ *    No C++ exception crosses this boundary.
+ *  - Vectors are in the paper's unknown order (the vector X below eq. (lsys)):
+ *    [u^1_1..u^{P-1}_1; ...; u^1_N..u^{P-1}_N; hat_1..hat_{N-1}], Nd = N*P - 1
+ *    entries, bubbles element-major, then the hat (nodal) coefficients.
+ *    Multi-column arrays are column-major with a leading dimension >= Nd.
+ *  - Pointers named *_dev are device (HBM) pointers on the context's device;
+ *    *_host are host pointers. The caller owns every array it passes in; the
+ *    library owns the opaque handles and releases them in *_destroy.
+ *  - Work is issued on the context's HIP stream. Calls return after their
+ *    device work is enqueued unless stated otherwise (calls that fill host
+ *    outputs synchronise the stream first).
+ *  - Handles are thread-compatible, not thread-safe: use one context per
+ *    thread, or serialise calls on a context.
+ *  - Device memory the library allocates counts against the context's HBM
+ *    budget; a call that would exceed it fails with FDE_ENOMEM and frees
+ *    what it allocated.
+ */
+#ifndef FDE_H
+#define FDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define FDE_OK            0
+#define FDE_EINVAL       -1   /* bad argument: alpha not in (1,2), theta not in [0,1], P < 2, non-increasing mesh, ... */
+#define FDE_ENOMEM       -2   /* the context's HBM budget (or the device) cannot hold the request */
+#define FDE_EBREAKDOWN   -3   /* H-LU met a pivot below its floor (A~ not factorisable without pivoting) */
+#define FDE_ENOCONV      -4   /* the Krylov iteration hit maxit; X holds the last iterate, info.relres is set */
+#define FDE_EDEVICE      -5   /* a HIP runtime call failed */
+#define FDE_EUNSUPPORTED -6   /* a structure this build does not handle (message says which) */
+
+/* precision of the H-LU factors and H-solves */
+#define FDE_FP64          0   /* everything in FP64 (the plain FP64 path) */
+#define FDE_FP32          1   /* H-LU factors and H-solves in FP32 */
+
+/* Krylov method */
+#define FDE_FGMRES        0   /* right-preconditioned flexible GMRES(restart) */
+
+/* stiffness-apply strategy */
+#define FDE_APPLY_AUTO     0  /* FFT block-Toeplitz on uniform / constant-ratio meshes, dense otherwise */
+#define FDE_APPLY_DENSE    1  /* stream the element-pair moments of S_l (any mesh) */
+#define FDE_APPLY_TOEPLITZ 2  /* FFT block-Toeplitz (fails with FDE_EINVAL on other meshes) */
+
+typedef struct fde_ctx  fde_ctx;   /* device, stream, HBM budget */
+typedef struct fde_op   fde_op;    /* the FP64 SEM operator A = rho M + S on one mesh */
+typedef struct fde_hmat fde_hmat;  /* H-matrix approximation A~ = rho M + H (Section 3) */
+typedef struct fde_hlu  fde_hlu;   /* H-LU factors L_H U_H of A~ (Section 4.1) */
+
+/* H-matrix parameters (Section 3): R = number of Taylor terms (eq. (eqn:Lexpan)),
+ * lambda = admissibility parameter of eq. (admis), leaf_elems = largest leaf
+ * cluster in elements (>= 2). Defaults: R = 8, lambda = 1, leaf_elems = 8. */
+typedef struct { int R; double lambda; int leaf_elems; } fde_hparams;
+
+/* H-LU parameters (Section 4.1): after every low-rank sum the block is
+ * recompressed to the singular values above tol * sigma_1, at most rank_cap
+ * (<= 0: R) of them. precision: FDE_FP64 or FDE_FP32. pivot_floor: a leaf
+ * pivot of magnitude <= pivot_floor * max|leaf| is a breakdown. */
+typedef struct { double tol; int rank_cap; int precision; double pivot_floor; } fde_hlu_params;
+
+/* Krylov parameters (Section 4.2): stop when ||G - A X||_2 / ||G||_2 <= rtol
+ * for the true FP64 residual; restart = Krylov subspace size; maxit bounds the
+ * total number of preconditioned matrix-vector products per right-hand side. */
+typedef struct { int method; int restart; int maxit; double rtol; } fde_solve_params;
+
+/* per right-hand side result */
+typedef struct { int iters; double relres; int status; } fde_solve_info;
+
+/* f(x) evaluated by the caller, for fde_load_vector_fn */
+typedef double (*fde_fn)(double x, void* user);
+
+/* ---- context ------------------------------------------------------------ */
+
+/* device: HIP ordinal. hip_stream: a hipStream_t (e.g. torch's current stream)
+ * or NULL for the null stream. hbm_budget_bytes: 0 = no limit beyond the device. */
+int  fde_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, fde_ctx** out);
+void fde_ctx_destroy(fde_ctx* ctx);
+int  fde_ctx_set_stream(fde_ctx* ctx, void* hip_stream);
+/* bytes of device memory the context's objects currently hold */
+size_t fde_ctx_bytes_in_use(const fde_ctx* ctx);
+
+/* ---- operator (Section 2.2) ------------------------------------------- */
+
+/* Build A = rho M + theta S_l + (1-theta) S_l^T on the partition
+ * nodes_host[0] = a < ... < nodes_host[N] = b (eq. (Partition)) with degree P
+ * on every element. Assembles the FP64 element-pair moments
+ *   K^{ef}_{mn} = gamma0 int_{I_e} int_{I_f} (t-s)_+^{1-alpha} L_m(xi_e(t)) L_n(xi_f(s)) ds dt
+ * on the device: all N(N+1)/2 pairs for the dense apply, or the N
+ * block-Toeplitz generators on uniform / constant-ratio meshes (Section 4.3).
+ * Errors: FDE_EINVAL, FDE_ENOMEM, FDE_EDEVICE. */
+int  fde_op_create(fde_ctx* ctx, const double* nodes_host, int N, int P, double alpha,
+                   double theta, double rho, int apply_mode, fde_op** out);
+void fde_op_destroy(fde_op* op);
+/* Nd = N*P - 1 */
+int  fde_op_ndof(const fde_op* op);
+/* 1 if the operator uses the FFT block-Toeplitz apply, 0 for the dense apply */
+int  fde_op_is_toeplitz(const fde_op* op);
+
+/* Element-pair moments K^{ef} (P x P, row m = Legendre index on element e) for
+ * `npairs` pairs with 0 <= f <= e < N (0-based elements); out_host holds
+ * npairs*P*P doubles, pair-major, row-major inside a pair. Synchronises. */
+int  fde_op_pair_moments(fde_op* op, int npairs, const int* e_host, const int* f_host,
+                         double* out_host);
+
+/* Materialise A (Nd x Nd, column-major, paper order) into A_dev (lda >= Nd).
+ * Meant for checks at small N; O(Nd^2) memory belongs to the caller. */
+int  fde_op_dense(fde_op* op, double* A_dev, int lda);
+
+/* ---- load vector (below eq. (lsys)) ------------------------------------ */
+
+/* Quadrature nodes at which f is needed: *nq receives the count; x_host,
+ * da_host, db_host (each may be NULL) receive the nodes and their distances
+ * x - a and b - x, computed without cancellation (nq doubles each). Elements
+ * that touch a or b carry panels graded geometrically toward the endpoint and
+ * a Gauss-Jacobi end panel for the weight d^{1-alpha}, so f with an endpoint
+ * singularity d^{-alpha} x (smooth) is integrated to ~1e-15 relative when f
+ * is evaluated through the distances (x itself cannot resolve b - x below
+ * ulp(b)). */
+int  fde_load_nodes(fde_op* op, int* nq, double* x_host, double* da_host, double* db_host);
+/* G_dev (Nd) = (f, phi_i) - c1 a(phi_0, phi_i) - c2 a(phi_N, phi_i) with f given
+ * by its values f_host[q] at the nodes of fde_load_nodes (lifting of the
+ * boundary values with the boundary hats). */
+int  fde_load_vector(fde_op* op, const double* f_host, double c1, double c2, double* G_dev);
+/* Same, with f evaluated through a host callback. */
+int  fde_load_vector_fn(fde_op* op, fde_fn f, void* user, double c1, double c2, double* G_dev);
+
+/* ---- stiffness apply (Section 4.3) ------------------------------------- */
+
+/* Y = A X for nrhs columns (FP64). Dense apply streams the lower-triangular
+ * moments once and uses each block for both S_l and S_l^T; the Toeplitz apply
+ * is a zero-padded real FFT of length >= 2N along the elements. */
+int  fde_stiffness_apply(fde_op* op, int nrhs, const double* X_dev, int ldx,
+                         double* Y_dev, int ldy);
+
+/* ---- H-matrix (Section 3) --------------------------------------------- */
+
+int  fde_build_hmatrix(fde_op* op, const fde_hparams* prm, fde_hmat** out);
+void fde_hmat_destroy(fde_hmat* hm);
+/* number of dense and low-rank leaf blocks */
+int  fde_hmat_counts(const fde_hmat* hm, int* n_dense, int* n_lowrank);
+/* A~ (Nd x Nd, column-major, paper order) into out_dev. */
+int  fde_hmat_to_dense(fde_hmat* hm, double* out_dev, int ld);
+
+/* ---- H-LU and H-solves (Section 4.1) ---------------------------------- */
+
+int  fde_hlu_factor(fde_hmat* hm, const fde_hlu_params* prm, fde_hlu** out);
+void fde_hlu_destroy(fde_hlu* f);
+/* L_H (strict lower part, unit diagonal implied) and U_H packed in one
+ * Nd x Nd column-major matrix in the H-matrix's internal order; h2p_host (if
+ * not NULL) receives that order as paper indices (Nd ints). */
+int  fde_hlu_to_dense(fde_hlu* f, double* out_dev, int ld, int* h2p_host);
+/* largest rank over the low-rank blocks of the factors (synchronises) */
+int  fde_hlu_max_rank(fde_hlu* f, int* max_rank);
+/* X = U_H^{-1} L_H^{-1} B (forward then backward H-substitution), nrhs columns,
+ * FP64 in and out; the substitution runs in the factor precision. */
+int  fde_hlu_solve(fde_hlu* f, int nrhs, const double* B_dev, int ldb, double* X_dev, int ldx);
+
+/* ---- preconditioned Krylov (Section 4.2) ------------------------------- */
+
+/* Solve A X = G for nrhs columns with the H-LU as preconditioner (prec may be
+ * NULL: no preconditioner). X is overwritten (zero initial guess). info_host:
+ * nrhs entries. Returns FDE_ENOCONV if any column missed rtol. */
+int  fde_solve(fde_op* op, fde_hlu* prec, int nrhs, const double* G_dev, int ldg,
+               double* X_dev, int ldx, const fde_solve_params* prm, fde_solve_info* info_host);
+
+/* Solve n independent systems (different operators, meshes and sizes) in
+ * lock-step: every kernel of an iteration serves all of them in one launch.
+ * ops[i], precs[i] (may be NULL), nrhs[i] columns, G[i]/X[i] device arrays
+ * with leading dimensions ldg[i]/ldx[i]; info_host has sum(nrhs) entries. */
+int  fde_solve_batched(fde_ctx* ctx, int n, fde_op* const* ops, fde_hlu* const* precs,
+                       const int* nrhs, const double* const* G_dev, const int* ldg,
+                       double* const* X_dev, const int* ldx, const fde_solve_params* prm,
+                       fde_solve_info* info_host);
+
+/* ---- utilities --------------------------------------------------------- */
+
+/* n-point Gauss rule for the weight (1-x)^a (1+x)^b on [-1,1] (host; the
+ * library's own generator, used for every rule above). */
+int  fde_gauss_jacobi(int n, double a, double b, double* x_host, double* w_host);
+const char* fde_last_error(void);
+const char* fde_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDE_H */

@@ -1,0 +1,453 @@
+// Stiffness apply Y = A X = rho M X + D^T (theta K + (1-theta) K^T) D X (FP64, gfx950).
+//
+// D maps the unknowns to per-element Legendre coefficients of the derivative
+// (Section 2.2: hats have slope +-1/h, (phi_e^p)' = -(2p+1)(2/h_e) L_p), K is the
+// block-lower element operator of the moments K^{ef}.
+//
+// Dense apply (any mesh; the O(Nd^2) product of Section 4.2): the packed lower
+// triangle of K is streamed once in tiles of TE x TE element pairs through LDS;
+// each tile yields a row partial (K c) and a column partial (K^T c), so every
+// moment byte is read from HBM once and used for both S_l and S_l^T (Section 4.3
+// forms S_l^T X "in a similar way"). Partials are reduced in a fixed order
+// (deterministic, no atomics).
+//
+// Block-Toeplitz apply (uniform or constant-ratio meshes, Section 4.3 and
+// Appendix A): K^{ef} = (h_e/2)^{2-alpha} (h_f/2) Khat_{e-f}; the causal block
+// convolution and its transpose are diagonalised by a zero-padded FFT of length
+// L >= 2N (circulant embedding). Each real sequence of length L is transformed
+// as a complex sequence of length L/2 (even/odd packing) by an in-place radix-2
+// FFT in LDS, one workgroup per channel. Per frequency the P x P complex
+// symbol is applied; on a uniform mesh theta Khat + (1-theta) Khat^H is one
+// symbol, on a geometric mesh the two parts carry different diagonal scalings
+// and are transformed separately.
+#include <cmath>
+
+#include "fde_internal.h"
+
+namespace fde {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline double hat_value(const double* x, int j, int N, int P, double bc0, double bcN) {
+    if (j == 0) return bc0;
+    if (j == N) return bcN;
+    return x ? x[N * (P - 1) + j - 1] : 0.0;
+}
+
+// Legendre coefficient m of the derivative on element e
+__device__ inline double deriv_coef(const double* x, int e, int m, int N, int P, const double* h,
+                                   double bc0, double bcN) {
+    if (m == 0)
+        return (hat_value(x, e + 1, N, P, bc0, bcN) - hat_value(x, e, N, P, bc0, bcN)) / h[e];
+    if (!x) return 0.0;
+    return -(2.0 * m + 1.0) * 2.0 / h[e] * x[e * (P - 1) + m - 1];
+}
+
+// ----------------------------------------------------------------- gather
+__global__ void k_gather(int N, int P, const double* __restrict__ h, const double* __restrict__ X,
+                         int ldx, int nrhs, double bc0, double bcN, double* __restrict__ c) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)nrhs * N * P;
+    if (idx >= tot) return;
+    const int r = (int)(idx / ((int64_t)N * P));
+    const int rem = (int)(idx % ((int64_t)N * P));
+    const int e = rem / P, m = rem % P;
+    c[idx] = deriv_coef(X ? X + (int64_t)r * ldx : nullptr, e, m, N, P, h, bc0, bcN);
+}
+
+// ----------------------------------------------------------------- scatter
+__global__ void k_scatter(int N, int P, double rho, const double* __restrict__ h,
+                          const double* __restrict__ lmass, const double* __restrict__ z,
+                          const double* __restrict__ X, int ldx, int nrhs, double bc0, double bcN,
+                          double* __restrict__ Y, int ldy) {
+    const int Nd = N * P - 1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nrhs * Nd) return;
+    const int r = (int)(idx / Nd);
+    const int i = (int)(idx % Nd);
+    const double* x = X ? X + (int64_t)r * ldx : nullptr;
+    const double* zr = z + (int64_t)r * N * P;
+    const int nb = N * (P - 1);
+    const int P1 = P + 1;
+    double y;
+    auto local = [&](int e, int b) -> double {  // local coefficient b of element e
+        if (b == 0) return hat_value(x, e, N, P, bc0, bcN);
+        if (b == 1) return hat_value(x, e + 1, N, P, bc0, bcN);
+        return x ? x[e * (P - 1) + b - 2] : 0.0;
+    };
+    if (i < nb) {
+        const int e = i / (P - 1), p = i % (P - 1) + 1;
+        y = -(2.0 * p + 1.0) * 2.0 / h[e] * zr[e * P + p];
+        if (rho != 0.0) {
+            double s = 0.0;
+            for (int b = 0; b < P1; ++b) s += lmass[(1 + p) * P1 + b] * local(e, b);
+            y += rho * 0.5 * h[e] * s;
+        }
+    } else {
+        const int j = i - nb + 1;
+        y = zr[(j - 1) * P] / h[j - 1] - zr[j * P] / h[j];
+        if (rho != 0.0) {
+            double s1 = 0.0, s0 = 0.0;
+            for (int b = 0; b < P1; ++b) {
+                s1 += lmass[1 * P1 + b] * local(j - 1, b);
+                s0 += lmass[0 * P1 + b] * local(j, b);
+            }
+            y += rho * (0.5 * h[j - 1] * s1 + 0.5 * h[j] * s0);
+        }
+    }
+    Y[(int64_t)r * ldy + i] = y;
+}
+
+// ----------------------------------------------------------------- dense tiles
+__device__ inline void tile_ij(int64_t t, int* I, int* J) {
+    int64_t i = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (tri(i + 1) <= t) ++i;
+    while (tri(i) > t) --i;
+    *I = (int)i;
+    *J = (int)(t - tri(i));
+}
+
+__global__ void __launch_bounds__(kThreads) k_dense_tiles(int N, int P, int TE, const double* __restrict__ mom,
+                                                        const double* __restrict__ c, int nrhs,
+                                                        double* __restrict__ part, int64_t ntiles) {
+    extern __shared__ double Kt[];   // TE x TE x P x P
+    const int64_t t = blockIdx.x;
+    int I, J;
+    tile_ij(t, &I, &J);
+    const int e0 = I * TE, f0 = J * TE;
+    const int ne = min(TE, N - e0), nf = min(TE, N - f0);
+    const int PP = P * P;
+    const int TEP = TE * P;
+    // stage the moments: row el holds pairs (e0+el, f0..f0+nf-1), zero where f > e
+    for (int el = 0; el < ne; ++el) {
+        const int e = e0 + el;
+        const int nvalid = min(nf, e - f0 + 1);   // f <= e
+        const double* src = mom + (tri(e) + f0) * PP;
+        double* dst = Kt + (int64_t)el * TE * PP;
+        for (int q = threadIdx.x; q < TE * PP; q += kThreads) dst[q] = (q < nvalid * PP) ? src[q] : 0.0;
+    }
+    for (int q = threadIdx.x + ne * TE * PP; q < TE * TE * PP; q += kThreads) Kt[q] = 0.0;
+    __syncthreads();
+    // outputs: for each rhs, TEP row partials then TEP column partials
+    const int nout = 2 * TEP;
+    for (int q = threadIdx.x; q < nrhs * nout; q += kThreads) {
+        const int r = q / nout;
+        const int o = q % nout;
+        const double* cr = c + (int64_t)r * N * P;
+        double s = 0.0;
+        if (o < TEP) {
+            const int el = o / P, m = o % P;
+            if (el < ne) {
+                const double* krow = Kt + (int64_t)el * TE * PP + m * P;
+                for (int fl = 0; fl < nf; ++fl) {
+                    const double* cf = cr + (f0 + fl) * P;
+                    const double* kb = krow + fl * PP;
+                    for (int n = 0; n < P; ++n) s += kb[n] * cf[n];
+                }
+            }
+        } else {
+            const int fl = (o - TEP) / P, n = (o - TEP) % P;
+            if (fl < nf) {
+                for (int el = 0; el < ne; ++el) {
+                    const double* ce = cr + (e0 + el) * P;
+                    const double* kb = Kt + ((int64_t)el * TE + fl) * PP + n;
+                    for (int m = 0; m < P; ++m) s += kb[m * P] * ce[m];
+                }
+            }
+        }
+        part[((int64_t)r * ntiles + t) * nout + o] = s;
+    }
+}
+
+__global__ void k_dense_reduce(int N, int P, int TE, int nT, double theta, const double* __restrict__ part,
+                               int nrhs, int64_t ntiles, double* __restrict__ z) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nrhs * N * P) return;
+    const int r = (int)(idx / ((int64_t)N * P));
+    const int rem = (int)(idx % ((int64_t)N * P));
+    const int e = rem / P, m = rem % P;
+    const int T = e / TE, el = e % TE;
+    const int TEP = TE * P, nout = 2 * TEP;
+    const double* pr = part + (int64_t)r * ntiles * nout;
+    double sr = 0.0, sc = 0.0;
+    for (int J = 0; J <= T; ++J) sr += pr[(tri(T) + J) * nout + el * P + m];
+    for (int I = T; I < nT; ++I) sc += pr[(tri(I) + T) * nout + TEP + el * P + m];
+    z[idx] = theta * sr + (1.0 - theta) * sc;
+}
+
+// ----------------------------------------------------------------- FFT
+__device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+__device__ inline unsigned bitrev(unsigned k, int logM) { return __brev(k) >> (32 - logM); }
+
+// in-place radix-2 DIT on buf[0..M) holding bit-reversed input; tw[j] = exp(-2 pi i j / L), L = 2M
+__device__ void fft_dit(double2* buf, int M, int logM, const double2* __restrict__ tw, bool inverse) {
+    for (int s = 1; s <= logM; ++s) {
+        const int half = 1 << (s - 1);
+        const int stride = M >> (s - 1);       // W_M^{pos M/(2 half)} = W_L^{2 pos M/(2 half)}
+        for (int b = threadIdx.x; b < M / 2; b += blockDim.x) {
+            const int grp = b / half, pos = b % half;
+            const int i = grp * 2 * half + pos;
+            const int j = i + half;
+            double2 w = tw[pos * stride];
+            if (inverse) w = cconj(w);
+            const double2 u = buf[i];
+            const double2 v = cmul(buf[j], w);
+            buf[i] = cadd(u, v);
+            buf[j] = csub(u, v);
+        }
+        __syncthreads();
+    }
+}
+
+struct FwdIn {
+    // mode 0: element coefficients from X (channel m, part: 0 omega-scaled, 1 sigma-scaled, 2 unscaled)
+    // mode 1: generator entries gen[e][c]
+    int mode;
+    const double* X;
+    int ldx;
+    double bc0, bcN;
+    const double* h;
+    double alpha;
+    const double* gen;
+};
+
+__device__ inline double fwd_value(const FwdIn& in, int N, int P, int r, int ch, int part, int e) {
+    if (e >= N) return 0.0;
+    if (in.mode == 1) return in.gen[(int64_t)e * P * P + ch];
+    const double* x = in.X ? in.X + (int64_t)r * in.ldx : nullptr;
+    const double v = deriv_coef(x, e, ch, N, P, in.h, in.bc0, in.bcN);
+    if (part == 0) return v * 0.5 * in.h[e];
+    if (part == 1) return v * pow(0.5 * in.h[e], 2.0 - in.alpha);
+    return v;
+}
+
+// grid (channels, nrhs, parts): spectrum of the real sequence, k = 0..M, into out[((r*parts+part)*nch+ch)*(M+1)+k]
+__global__ void __launch_bounds__(kThreads) k_rfft_forward(int N, int P, int M, int logM, int nch, FwdIn in,
+                                                         int part_base, const double2* __restrict__ tw,
+                                                         double2* __restrict__ out) {
+    extern __shared__ double2 buf[];
+    const int ch = blockIdx.x, r = blockIdx.y, part = blockIdx.z;
+    const int mode_part = in.mode == 1 ? 0 : part_base + part;
+    for (int k = threadIdx.x; k < M; k += blockDim.x) {
+        const int src = (int)bitrev((unsigned)k, logM);
+        buf[k] = make_double2(fwd_value(in, N, P, r, ch, mode_part, 2 * src),
+                              fwd_value(in, N, P, r, ch, mode_part, 2 * src + 1));
+    }
+    __syncthreads();
+    fft_dit(buf, M, logM, tw, false);
+    double2* o = out + (((int64_t)r * gridDim.z + part) * nch + ch) * (M + 1);
+    for (int k = threadIdx.x; k <= M; k += blockDim.x) {
+        const double2 zk = buf[k % M];
+        const double2 zc = cconj(buf[(M - k) % M]);
+        const double2 E = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
+        const double2 d = make_double2(0.5 * (zk.x - zc.x), 0.5 * (zk.y - zc.y));
+        const double2 O = make_double2(d.y, -d.x);   // d / i
+        o[k] = cadd(E, cmul(tw[k], O));
+    }
+}
+
+// grid (P, nrhs): z[r][e][m] = sum over parts of scale_part(e) * irfft(spec)[e]
+struct InvOut {
+    int parts;            // 1 uniform, 2 geometric
+    double s_uniform;     // uniform: (h/2)^{3-alpha}
+    double theta, alpha;
+    const double* h;
+};
+
+__global__ void __launch_bounds__(kThreads) k_rfft_inverse(int N, int P, int M, int logM, InvOut io,
+                                                         const double2* __restrict__ tw,
+                                                         const double2* __restrict__ spec,
+                                                         double* __restrict__ z) {
+    extern __shared__ double2 buf[];
+    const int m = blockIdx.x, r = blockIdx.y;
+    for (int part = 0; part < io.parts; ++part) {
+        const double2* X = spec + (((int64_t)r * io.parts + part) * P + m) * (M + 1);
+        for (int k = threadIdx.x; k < M; k += blockDim.x) {
+            const double2 xk = X[k];
+            const double2 xc = cconj(X[M - k]);
+            const double2 E = make_double2(0.5 * (xk.x + xc.x), 0.5 * (xk.y + xc.y));
+            const double2 d = make_double2(0.5 * (xk.x - xc.x), 0.5 * (xk.y - xc.y));
+            const double2 O = cmul(d, cconj(tw[k]));
+            buf[bitrev((unsigned)k, logM)] = make_double2(E.x - O.y, E.y + O.x);   // E + i O
+        }
+        __syncthreads();
+        fft_dit(buf, M, logM, tw, true);
+        const double inv = 1.0 / M;
+        for (int k = threadIdx.x; k < M; k += blockDim.x) {
+            for (int s = 0; s < 2; ++s) {
+                const int e = 2 * k + s;
+                if (e >= N) continue;
+                const double v = (s == 0 ? buf[k].x : buf[k].y) * inv;
+                double* zp = z + ((int64_t)r * N + e) * P + m;
+                if (io.parts == 1) {
+                    *zp = io.s_uniform * v;
+                } else if (part == 0) {
+                    *zp = io.theta * pow(0.5 * io.h[e], 2.0 - io.alpha) * v;
+                } else {
+                    *zp += (1.0 - io.theta) * 0.5 * io.h[e] * v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// per frequency: uniform  Y[m] = sum_n S[m][n] X[n];
+//                geometric Yc[m] = sum_n K[m][n] Xc[n],  Yr[m] = sum_n conj(K[n][m]) Xr[n]
+__global__ void k_symbol_apply(int P, int M, int parts, const double2* __restrict__ sym,
+                               const double2* __restrict__ spec, int nrhs, double2* __restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int K1 = M + 1;
+    if (idx >= (int64_t)nrhs * K1) return;
+    const int r = (int)(idx / K1), k = (int)(idx % K1);
+    for (int part = 0; part < parts; ++part) {
+        const double2* X = spec + ((int64_t)r * parts + part) * P * K1;
+        double2* Y = out + ((int64_t)r * parts + part) * P * K1;
+        for (int m = 0; m < P; ++m) {
+            double2 s = make_double2(0.0, 0.0);
+            for (int n = 0; n < P; ++n) {
+                double2 a;
+                if (part == 0)
+                    a = sym[((int64_t)m * P + n) * K1 + k];
+                else
+                    a = cconj(sym[((int64_t)n * P + m) * K1 + k]);
+                s = cadd(s, cmul(a, X[(int64_t)n * K1 + k]));
+            }
+            Y[(int64_t)m * K1 + k] = s;
+        }
+    }
+}
+
+// symbol from the generator spectra Kw[c][k] (c = m*P + n): uniform S = theta Kw + (1-theta) Kw^H
+__global__ void k_symbol_build(int P, int M, int uniform, double theta, const double2* __restrict__ Kw,
+                               double2* __restrict__ sym) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int K1 = M + 1;
+    if (idx >= (int64_t)P * P * K1) return;
+    const int c = (int)(idx / K1), k = (int)(idx % K1);
+    const int m = c / P, n = c % P;
+    if (!uniform) {
+        sym[idx] = Kw[idx];
+        return;
+    }
+    const double2 a = Kw[(int64_t)c * K1 + k];
+    const double2 b = cconj(Kw[((int64_t)n * P + m) * K1 + k]);
+    sym[idx] = make_double2(theta * a.x + (1.0 - theta) * b.x, theta * a.y + (1.0 - theta) * b.y);
+}
+
+int dense_tile_elems(int P) {
+    int te = 64 / P;
+    if (te < 1) te = 1;
+    if (te > 32) te = 32;
+    return te;
+}
+
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+}  // namespace
+
+size_t Op::apply_ws_doubles(int nrhs) const {
+    const size_t cz = 2 * (size_t)nrhs * N * P;   // c and z
+    if (!toeplitz) {
+        const int TE = dense_tile_elems(P);
+        const int64_t nT = ceil_div(N, TE);
+        const size_t parts = (size_t)nrhs * tri(nT) * 2 * TE * P;
+        return cz + parts;
+    }
+    const int M = L / 2;
+    const int parts = uniform ? 1 : 2;
+    return cz + 2 * 2 * (size_t)nrhs * parts * P * (M + 1);   // two complex spectra buffers
+}
+
+void build_symbol(Op* op) {
+    // spectra of the P^2 generator sequences, then the symbol
+    const int P = op->P, M = op->L / 2, logM = ilog2(M);
+    DevBuf<double2> kw;
+    kw.alloc(op->ctx, (size_t)P * P * (M + 1));
+    FwdIn in{};
+    in.mode = 1;
+    in.gen = op->d_gen.p;
+    hipLaunchKernelGGL(k_rfft_forward, dim3(P * P, 1, 1), dim3(kThreads), sizeof(double2) * M,
+                       op->ctx->stream, op->N, P, M, logM, P * P, in, 0, op->d_tw.p, kw.p);
+    FDE_LAUNCH_CHECK();
+    const int64_t tot = (int64_t)P * P * (M + 1);
+    hipLaunchKernelGGL(k_symbol_build, dim3((unsigned)ceil_div((int)tot, 256)), dim3(256), 0,
+                       op->ctx->stream, P, M, op->uniform ? 1 : 0, op->theta, kw.p, op->d_sym.p);
+    FDE_LAUNCH_CHECK();
+    FDE_HIP(hipStreamSynchronize(op->ctx->stream));
+}
+
+void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int ldy, double bc0,
+                     double bcN, bool zero_x) {
+    const int N = op->N, P = op->P, Nd = op->Nd;
+    hipStream_t st = op->ctx->stream;
+    const size_t need = op->apply_ws_doubles(nrhs);
+    if (op->ws.n < need) op->ws.alloc(op->ctx, need);
+    double* c = op->ws.p;
+    double* z = c + (size_t)nrhs * N * P;
+    double* rest = z + (size_t)nrhs * N * P;
+    const double* Xin = zero_x ? nullptr : X;
+    const int64_t nzp = (int64_t)nrhs * N * P;
+    if (!op->toeplitz) {
+        const int TE = dense_tile_elems(P);
+        const int nT = ceil_div(N, TE);
+        const int64_t ntiles = tri(nT);
+        hipLaunchKernelGGL(k_gather, dim3((unsigned)((nzp + 255) / 256)), dim3(256), 0, st, N, P,
+                           op->d_h.p, Xin, ldx, nrhs, bc0, bcN, c);
+        FDE_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_dense_tiles, dim3((unsigned)ntiles), dim3(kThreads),
+                           sizeof(double) * TE * TE * P * P, st, N, P, TE, op->d_mom.p, c, nrhs, rest,
+                           ntiles);
+        FDE_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_dense_reduce, dim3((unsigned)((nzp + 255) / 256)), dim3(256), 0, st, N, P,
+                           TE, nT, op->theta, rest, nrhs, ntiles, z);
+        FDE_LAUNCH_CHECK();
+    } else {
+        const int M = op->L / 2, logM = ilog2(M);
+        const int parts = op->uniform ? 1 : 2;
+        double2* specA = reinterpret_cast<double2*>(rest);
+        double2* specB = specA + (size_t)nrhs * parts * P * (M + 1);
+        FwdIn in{};
+        in.mode = 0;
+        in.X = Xin;
+        in.ldx = ldx;
+        in.bc0 = bc0;
+        in.bcN = bcN;
+        in.h = op->d_h.p;
+        in.alpha = op->alpha;
+        hipLaunchKernelGGL(k_rfft_forward, dim3(P, nrhs, parts), dim3(kThreads), sizeof(double2) * M, st,
+                           N, P, M, logM, P, in, op->uniform ? 2 : 0, op->d_tw.p, specA);
+        FDE_LAUNCH_CHECK();
+        const int64_t nk = (int64_t)nrhs * (M + 1);
+        hipLaunchKernelGGL(k_symbol_apply, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, st, P, M,
+                           parts, op->d_sym.p, specA, nrhs, specB);
+        FDE_LAUNCH_CHECK();
+        InvOut io;
+        io.parts = parts;
+        io.s_uniform = std::pow(0.5 * op->h[0], 3.0 - op->alpha);
+        io.theta = op->theta;
+        io.alpha = op->alpha;
+        io.h = op->d_h.p;
+        hipLaunchKernelGGL(k_rfft_inverse, dim3(P, nrhs), dim3(kThreads), sizeof(double2) * M, st, N, P,
+                           M, logM, io, op->d_tw.p, specB, z);
+        FDE_LAUNCH_CHECK();
+    }
+    const int64_t ny = (int64_t)nrhs * Nd;
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, st, N, P, op->rho,
+                       op->d_h.p, op->d_lmass.p, z, Xin, ldx, nrhs, bc0, bcN, Y, ldy);
+    FDE_LAUNCH_CHECK();
+}
+
+}  // namespace fde

@@ -1,0 +1,465 @@
+// Element-pair moment blocks of the SEM stiffness matrix (FP64, gfx950).
+//
+// Section 2.2 with the kernel form of the weak form (Section 2.1) and the
+// entry formula of Section 3.2: every basis derivative is a Legendre series
+// on each element (psi_p' = -(2p+1) L_p), so S_l = D^T K D with
+//   K^{ef}_{mn} = gamma0 int_{I_e} int_{I_f} (t-s)_+^{1-alpha} L_m(xi_e(t)) L_n(xi_f(s)) ds dt.
+// One 64-lane wavefront computes one P x P block:
+//   same element  : Duffy map s = t - (1+xi) w, tensor Gauss-Jacobi (exact);
+//   adjacent      : square split on its diagonal, Duffy map per triangle,
+//                   Gauss-Jacobi in the radial variable, Gauss-Legendre panels
+//                   graded toward the nearest singular point in the angle;
+//   separated     : tensor Gauss-Legendre on panels graded geometrically
+//                   toward the gap, the node count per panel from the
+//                   Bernstein-ellipse bound of the kernel.
+// The far-field blocks are pow-bound FP64 ALU work; each is staged through LDS
+// as (weights * kernel) -> (Legendre_t * .) -> (. * Legendre_s) contractions.
+#include <cmath>
+
+#include "fde_internal.h"
+
+namespace fde {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kMaxPanelNodes = 48;   // a graded panel never needs more (rho >= 3.7)
+constexpr int kMaxP = 32;
+constexpr int kAccPerLane = (kMaxP * kMaxP + kWave - 1) / kWave;
+
+struct Geo {
+    double he, hf, gap;  // element sizes and the gap between them (gap < 0: not separated)
+    int kind;            // 0 same element, 1 adjacent, 2 separated
+};
+
+__device__ inline double legendre(int n, double x) {
+    if (n == 0) return 1.0;
+    double pm = 1.0, p = x;
+    for (int k = 1; k < n; ++k) {
+        const double pn = ((2 * k + 1) * x * p - k * pm) / (k + 1);
+        pm = p;
+        p = pn;
+    }
+    return p;
+}
+
+// nodes for a panel of length len whose nearest singular point lies dist beyond
+// its start; error target ~1e-16 for a kernel times a degree-(P-1) polynomial
+__device__ inline int panel_nodes(double len, double dist, int P) {
+    const double a = 1.0 + 2.0 * dist / len;
+    const double rho = a + sqrt(a * a - 1.0);
+    int n = (int)ceil(0.5 * (P - 1 + 36.8 / log(rho))) + 1;
+    if (n < 1) n = 1;
+    if (n > kMaxPanelNodes) n = kMaxPanelNodes;
+    return n;
+}
+
+// panel j of [0, len] graded toward 0 with gap g: [g(2^j-1), g(2^{j+1}-1)] clipped
+__device__ inline int panel_count(double len, double g) {
+    if (g >= len) return 1;
+    int j = 0;
+    while (g * (exp2((double)(j + 1)) - 1.0) < len) ++j;
+    return j + 1;
+}
+__device__ inline void panel_bounds(double len, double g, int j, double* lo, double* hi) {
+    if (g >= len) {
+        *lo = 0.0;
+        *hi = len;
+        return;
+    }
+    *lo = g * (exp2((double)j) - 1.0);
+    const double h = g * (exp2((double)(j + 1)) - 1.0);
+    *hi = h < len ? h : len;
+}
+
+__device__ inline void gl_rule(const double* gl, int n, int i, double lo, double hi, double* x,
+                               double* w) {
+    const int off = n * (n - 1) / 2;
+    const double xr = gl[off + i];
+    const double wr = gl[kMaxGL * (kMaxGL + 1) / 2 + off + i];
+    *x = 0.5 * (hi - lo) * xr + 0.5 * (hi + lo);
+    *w = 0.5 * (hi - lo) * wr;
+}
+
+// shared memory layout for one wavefront
+struct Smem {
+    double* Lt;   // P x kMaxPanelNodes
+    double* Ls;   // P x kMaxPanelNodes
+    double* T;    // P x kMaxPanelNodes
+    double* Kw;   // kMaxPanelNodes^2
+    double* nodes; // 4 x kMaxPanelNodes
+};
+
+__device__ void block_separated(const Geo& g, int P, double alpha, double gamma0,
+                                const double* gl, Smem sm, double* acc) {
+    const int lane = threadIdx.x;
+    const int pt = panel_count(g.he, g.gap);
+    const int ps = panel_count(g.hf, g.gap);
+    double* tu = sm.nodes;                         // t-panel nodes u = t - x_e and weights
+    double* tw = sm.nodes + kMaxPanelNodes;
+    double* sv = sm.nodes + 2 * kMaxPanelNodes;    // s-panel nodes v = x_{f+1} - s and weights
+    double* sw = sm.nodes + 3 * kMaxPanelNodes;
+    for (int jt = 0; jt < pt; ++jt) {
+        double tlo, thi;
+        panel_bounds(g.he, g.gap, jt, &tlo, &thi);
+        for (int js = 0; js < ps; ++js) {
+            double slo, shi;
+            panel_bounds(g.hf, g.gap, js, &slo, &shi);
+            const double d = g.gap + tlo + slo;  // smallest t - s over the panel pair
+            const int nt = panel_nodes(thi - tlo, d, P);
+            const int ns = panel_nodes(shi - slo, d, P);
+            for (int i = lane; i < nt + ns; i += kWave) {
+                const bool is_t = i < nt;
+                const int j = is_t ? i : i - nt;
+                double v, wv;
+                if (is_t)
+                    gl_rule(gl, nt, j, tlo, thi, &v, &wv);
+                else
+                    gl_rule(gl, ns, j, slo, shi, &v, &wv);
+                const double xi = is_t ? 2.0 * v / g.he - 1.0 : 1.0 - 2.0 * v / g.hf;
+                double* Lrow = is_t ? sm.Lt : sm.Ls;
+                double pm = 1.0, p = xi;
+                Lrow[j] = 1.0;
+                if (P > 1) Lrow[kMaxPanelNodes + j] = xi;
+                for (int k = 1; k + 1 < P; ++k) {
+                    const double pn = ((2 * k + 1) * xi * p - k * pm) / (k + 1);
+                    pm = p;
+                    p = pn;
+                    Lrow[(k + 1) * kMaxPanelNodes + j] = pn;
+                }
+                if (is_t) {
+                    tu[j] = v;
+                    tw[j] = wv;
+                } else {
+                    sv[j] = v;
+                    sw[j] = wv;
+                }
+            }
+            __syncthreads();
+            for (int q = lane; q < nt * ns; q += kWave) {
+                const int i = q / ns, j = q % ns;
+                sm.Kw[i * kMaxPanelNodes + j] = tw[i] * sw[j] * pow(g.gap + tu[i] + sv[j], 1.0 - alpha);
+            }
+            __syncthreads();
+            // T[m][j] = sum_i Lt[m][i] Kw[i][j]
+            for (int q = lane; q < P * ns; q += kWave) {
+                const int m = q / ns, j = q % ns;
+                double s = 0.0;
+                for (int i = 0; i < nt; ++i) s += sm.Lt[m * kMaxPanelNodes + i] * sm.Kw[i * kMaxPanelNodes + j];
+                sm.T[m * kMaxPanelNodes + j] = s;
+            }
+            __syncthreads();
+            // acc[m][n] += sum_j T[m][j] Ls[n][j]
+            int a = 0;
+            for (int q = lane; q < P * P; q += kWave, ++a) {
+                const int m = q / P, n = q % P;
+                double s = 0.0;
+                for (int j = 0; j < ns; ++j) s += sm.T[m * kMaxPanelNodes + j] * sm.Ls[n * kMaxPanelNodes + j];
+                acc[a] += gamma0 * s;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ void block_same(const Geo& g, int P, double alpha, double gamma0, const double* rules,
+                           Smem sm, double* acc) {
+    const int lane = threadIdx.x;
+    const int no = P + 1, ni = P;
+    const double* xo = rules;
+    const double* wo = rules + no;
+    const double* xi_in = rules + 2 * no;
+    const double* wi_in = rules + 2 * no + ni;
+    const double scale_in = exp2(alpha - 2.0);   // w = (1+y)/2, w^{1-alpha} dw = 2^{alpha-2} (1+y)^{1-alpha} dy
+    // T[n][o] = sum_i wi L_n(xi_o - (1+xi_o) w_i)
+    for (int q = lane; q < P * no; q += kWave) {
+        const int n = q / no, o = q % no;
+        double s = 0.0;
+        for (int i = 0; i < ni; ++i) {
+            const double w = 0.5 * (1.0 + xi_in[i]);
+            s += wi_in[i] * scale_in * legendre(n, xo[o] - (1.0 + xo[o]) * w);
+        }
+        sm.T[n * kMaxPanelNodes + o] = s;
+    }
+    __syncthreads();
+    const double c = gamma0 * pow(0.5 * g.he, 3.0 - alpha);
+    int a = 0;
+    for (int q = lane; q < P * P; q += kWave, ++a) {
+        const int m = q / P, n = q % P;
+        double s = 0.0;
+        for (int o = 0; o < no; ++o) s += wo[o] * legendre(m, xo[o]) * sm.T[n * kMaxPanelNodes + o];
+        acc[a] += c * s;
+    }
+    __syncthreads();
+}
+
+__device__ void block_adjacent(const Geo& g, int P, double alpha, double gamma0, const double* rules,
+                               const double* gl, Smem sm, double* acc) {
+    const int lane = threadIdx.x;
+    const int nr = P + 1;
+    const double* xr = rules;      // GJ(0, 2-alpha), n = P+1
+    const double* wr = rules + nr;
+    const double rscale = exp2(alpha - 3.0);   // r = (1+y)/2: r^{2-alpha} dr = 2^{alpha-3}(1+y)^{2-alpha} dy
+    const double e1 = 1.0 - alpha;
+    // triangle 1 (b <= a): I1[n][r] = sum_w (he + hf w)^{1-alpha} L_n(1 - 2 a_r w)
+    // triangle 2 (a <= b): I2[m][r] = sum_w (he w + hf)^{1-alpha} L_m(2 b_r w - 1)
+    for (int tri_ = 0; tri_ < 2; ++tri_) {
+        const double gw = tri_ == 0 ? g.he / g.hf : g.hf / g.he;   // singular point at w = -gw
+        const int np = panel_count(1.0, gw);
+        for (int q = lane; q < P * nr; q += kWave) {
+            const int n = q / nr, r = q % nr;
+            const double ar = 0.5 * (1.0 + xr[r]);
+            double s = 0.0;
+            for (int j = 0; j < np; ++j) {
+                double lo, hi;
+                panel_bounds(1.0, gw, j, &lo, &hi);
+                const int nw = panel_nodes(hi - lo, lo + gw, P);
+                for (int i = 0; i < nw; ++i) {
+                    double w, ww;
+                    gl_rule(gl, nw, i, lo, hi, &w, &ww);
+                    if (tri_ == 0)
+                        s += ww * pow(g.he + g.hf * w, e1) * legendre(n, 1.0 - 2.0 * ar * w);
+                    else
+                        s += ww * pow(g.he * w + g.hf, e1) * legendre(n, 2.0 * ar * w - 1.0);
+                }
+            }
+            sm.T[n * kMaxPanelNodes + r] = s;
+        }
+        __syncthreads();
+        const double c = gamma0 * g.he * g.hf * rscale;
+        int a = 0;
+        for (int q = lane; q < P * P; q += kWave, ++a) {
+            const int m = q / P, n = q % P;
+            double s = 0.0;
+            for (int r = 0; r < nr; ++r) {
+                const double ar = 0.5 * (1.0 + xr[r]);
+                if (tri_ == 0)
+                    s += wr[r] * legendre(m, 2.0 * ar - 1.0) * sm.T[n * kMaxPanelNodes + r];
+                else
+                    s += wr[r] * legendre(n, 1.0 - 2.0 * ar) * sm.T[m * kMaxPanelNodes + r];
+            }
+            acc[a] += c * s;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void compute_block(const Geo& g, int P, double alpha, double gamma0, const double* rules,
+                              const double* gl, double scale, double* out) {
+    extern __shared__ double smem[];
+    Smem sm;
+    sm.Lt = smem;
+    sm.Ls = sm.Lt + P * kMaxPanelNodes;
+    sm.T = sm.Ls + P * kMaxPanelNodes;
+    sm.Kw = sm.T + (P < 2 ? 2 : P) * kMaxPanelNodes;
+    sm.nodes = sm.Kw + kMaxPanelNodes * kMaxPanelNodes;
+    double acc[kAccPerLane];
+    for (int a = 0; a < kAccPerLane; ++a) acc[a] = 0.0;
+    if (g.kind == 0)
+        block_same(g, P, alpha, gamma0, rules, sm, acc);
+    else if (g.kind == 1)
+        block_adjacent(g, P, alpha, gamma0, rules, gl, sm, acc);
+    else
+        block_separated(g, P, alpha, gamma0, gl, sm, acc);
+    int a = 0;
+    for (int q = threadIdx.x; q < P * P; q += kWave, ++a) out[q] = scale * acc[a];
+}
+
+__global__ void __launch_bounds__(kWave) k_moments_dense(int N, int P, double alpha, double gamma0,
+                                                        const double* __restrict__ x,
+                                                        const double* __restrict__ h,
+                                                        const double* __restrict__ rules,
+                                                        const double* __restrict__ gl,
+                                                        double* __restrict__ mom, int64_t npairs) {
+    for (int64_t pid = blockIdx.x; pid < npairs; pid += gridDim.x) {
+        // pair index -> (e, f), f <= e, row-major over the lower triangle
+        int64_t e = (int64_t)((sqrt(8.0 * (double)pid + 1.0) - 1.0) * 0.5);
+        while (tri(e + 1) <= pid) ++e;
+        while (tri(e) > pid) --e;
+        const int64_t f = pid - tri(e);
+        Geo g;
+        g.he = h[e];
+        g.hf = h[f];
+        g.kind = (e == f) ? 0 : (f == e - 1 ? 1 : 2);
+        g.gap = (g.kind == 2) ? x[e] - x[f + 1] : 0.0;
+        compute_block(g, P, alpha, gamma0, rules, gl, 1.0, mom + pid * P * P);
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kWave) k_moments_list(int P, double alpha, double gamma0,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ h,
+                                                       const double* __restrict__ rules,
+                                                       const double* __restrict__ gl,
+                                                       const int* __restrict__ ev,
+                                                       const int* __restrict__ fv,
+                                                       double* __restrict__ out, int npairs) {
+    const int pid = blockIdx.x;
+    if (pid >= npairs) return;
+    const int e = ev[pid], f = fv[pid];
+    Geo g;
+    g.he = h[e];
+    g.hf = h[f];
+    g.kind = (e == f) ? 0 : (f == e - 1 ? 1 : 2);
+    g.gap = (g.kind == 2) ? x[e] - x[f + 1] : 0.0;
+    compute_block(g, P, alpha, gamma0, rules, gl, 1.0, out + (int64_t)pid * P * P);
+}
+
+// Toeplitz generators Khat_k at h_e = 2 with ratio r = h_{e+1}/h_e:
+// K^{ef} = (h_e/2)^{2-alpha} (h_f/2) Khat_{e-f} (Section 4.3, eq. (eq420)).
+__global__ void __launch_bounds__(kWave) k_generators(int N, int P, double alpha, double gamma0,
+                                                     double r, const double* __restrict__ rules,
+                                                     const double* __restrict__ gl,
+                                                     double* __restrict__ gen) {
+    const int k = blockIdx.x;
+    if (k >= N) return;
+    Geo g;
+    g.he = 2.0;
+    g.hf = 2.0 * pow(r, -(double)k);
+    g.kind = k == 0 ? 0 : (k == 1 ? 1 : 2);
+    double gap = 0.0;
+    for (int j = 1; j < k; ++j) gap += 2.0 * pow(r, -(double)j);
+    g.gap = gap;
+    compute_block(g, P, alpha, gamma0, rules, gl, 1.0 / (0.5 * g.hf), gen + (int64_t)k * P * P);
+}
+
+size_t moments_smem(int P) {
+    return sizeof(double) * (size_t)(3 * (P < 2 ? 2 : P) * kMaxPanelNodes + kMaxPanelNodes * kMaxPanelNodes +
+                                     4 * kMaxPanelNodes);
+}
+
+// ---------------------------------------------------------------- dense A
+// A[i][j] (paper order) = rho M + theta D^T K D + (1-theta) D^T K^T D
+__device__ inline void dof_elems(int i, int N, int P, const double* h, int* ne, int* el, int* md,
+                                 double* cf) {
+    const int nb = N * (P - 1);
+    if (i < nb) {
+        const int e = i / (P - 1), p = i % (P - 1) + 1;
+        *ne = 1;
+        el[0] = e;
+        md[0] = p;
+        cf[0] = -(2.0 * p + 1.0) * 2.0 / h[e];
+    } else {
+        const int j = i - nb + 1;  // node 1..N-1
+        *ne = 2;
+        el[0] = j - 1;
+        md[0] = 0;
+        cf[0] = 1.0 / h[j - 1];
+        el[1] = j;
+        md[1] = 0;
+        cf[1] = -1.0 / h[j];
+    }
+}
+
+__device__ inline double mom_get(const double* mom, const double* gen, bool toep, int P, int e,
+                                 int f, int m, int n, const double* h, double alpha) {
+    // K^{ef}_{mn}, f <= e
+    if (!toep) return mom[(tri(e) + f) * P * P + m * P + n];
+    const double s = pow(0.5 * h[e], 2.0 - alpha) * 0.5 * h[f];
+    return s * gen[(int64_t)(e - f) * P * P + m * P + n];
+}
+
+__global__ void k_dense_matrix(int N, int P, double alpha, double theta, double rho,
+                               const double* __restrict__ h, const double* __restrict__ mom,
+                               const double* __restrict__ gen, int toep,
+                               const double* __restrict__ lmass, double* __restrict__ A, int lda) {
+    const int Nd = N * P - 1;
+    const int i = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nd || j >= Nd) return;
+    int ni, ei[2], mi[2], nj, ej[2], mj[2];
+    double ci[2], cj[2];
+    dof_elems(i, N, P, h, &ni, ei, mi, ci);
+    dof_elems(j, N, P, h, &nj, ej, mj, cj);
+    double s = 0.0;
+    for (int a = 0; a < ni; ++a)
+        for (int b = 0; b < nj; ++b) {
+            const int e = ei[a], f = ej[b];
+            if (f <= e) s += theta * ci[a] * cj[b] * mom_get(mom, gen, toep, P, e, f, mi[a], mj[b], h, alpha);
+            if (e <= f) s += (1.0 - theta) * ci[a] * cj[b] * mom_get(mom, gen, toep, P, f, e, mj[b], mi[a], h, alpha);
+        }
+    // mass: local basis index of dof i on element e: 0 left hat, 1 right hat, 1+p bubble
+    if (rho != 0.0) {
+        const int nb = N * (P - 1);
+        for (int a = 0; a < ni; ++a) {
+            const int e = ei[a];
+            int li;
+            if (i < nb) li = 1 + (i % (P - 1)) + 1;
+            else li = (e == i - nb) ? 1 : 0;   // node j = i-nb+1: right hat of e=j-1, left hat of e=j
+            for (int b = 0; b < nj; ++b) {
+                if (ej[b] != e) continue;
+                int lj;
+                if (j < nb) lj = 1 + (j % (P - 1)) + 1;
+                else lj = (e == j - nb) ? 1 : 0;
+                s += rho * 0.5 * h[e] * lmass[li * (P + 1) + lj];
+            }
+        }
+    }
+    A[(int64_t)j * lda + i] = s;
+}
+
+// ---------------------------------------------------------------- load vector
+// G_i = sum_q w_q f(x_q) phi_i(x_q) over the quadrature nodes of the elements in supp(phi_i)
+__global__ void k_load_vector(int N, int P, const int* __restrict__ off,
+                              const double* __restrict__ xi, const double* __restrict__ w,
+                              const double* __restrict__ f, double* __restrict__ G) {
+    const int Nd = N * P - 1;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nd) return;
+    const int nb = N * (P - 1);
+    double s = 0.0;
+    if (i < nb) {
+        const int e = i / (P - 1), p = i % (P - 1) + 1;
+        for (int q = off[e]; q < off[e + 1]; ++q)
+            s += w[q] * f[q] * (legendre(p - 1, xi[q]) - legendre(p + 1, xi[q]));
+    } else {
+        const int j = i - nb + 1;
+        for (int q = off[j - 1]; q < off[j]; ++q) s += w[q] * f[q] * 0.5 * (1.0 + xi[q]);
+        for (int q = off[j]; q < off[j + 1]; ++q) s += w[q] * f[q] * 0.5 * (1.0 - xi[q]);
+    }
+    G[i] = s;
+}
+
+}  // namespace
+
+void launch_pair_moments_dense(Op* op) {
+    const int64_t npairs = tri(op->N);
+    const int grid = (int)(npairs < (1 << 22) ? npairs : (1 << 22));
+    hipLaunchKernelGGL(k_moments_dense, dim3(grid), dim3(kWave), moments_smem(op->P), op->ctx->stream,
+                       op->N, op->P, op->alpha, op->gamma0, op->d_x.p, op->d_h.p, op->d_rules.p,
+                       op->ctx->gl.p, op->d_mom.p, npairs);
+    FDE_LAUNCH_CHECK();
+}
+
+void launch_generators(Op* op) {
+    hipLaunchKernelGGL(k_generators, dim3(op->N), dim3(kWave), moments_smem(op->P), op->ctx->stream,
+                       op->N, op->P, op->alpha, op->gamma0, op->ratio, op->d_rules.p, op->ctx->gl.p,
+                       op->d_gen.p);
+    FDE_LAUNCH_CHECK();
+}
+
+void launch_pair_moments_list(Op* op, int npairs, const int* d_e, const int* d_f, double* d_out) {
+    if (npairs <= 0) return;
+    hipLaunchKernelGGL(k_moments_list, dim3(npairs), dim3(kWave), moments_smem(op->P), op->ctx->stream,
+                       op->P, op->alpha, op->gamma0, op->d_x.p, op->d_h.p, op->d_rules.p,
+                       op->ctx->gl.p, d_e, d_f, d_out, npairs);
+    FDE_LAUNCH_CHECK();
+}
+
+void launch_dense_matrix(Op* op, double* A, int lda) {
+    const int Nd = op->Nd;
+    dim3 grid(ceil_div(Nd, 128), Nd);
+    hipLaunchKernelGGL(k_dense_matrix, grid, dim3(128), 0, op->ctx->stream, op->N, op->P, op->alpha,
+                       op->theta, op->rho, op->d_h.p, op->d_mom.p, op->d_gen.p, op->toeplitz ? 1 : 0,
+                       op->d_lmass.p, A, lda);
+    FDE_LAUNCH_CHECK();
+}
+
+void launch_load_vector(Op* op, double* G) {
+    hipLaunchKernelGGL(k_load_vector, dim3(ceil_div(op->Nd, 256)), dim3(256), 0, op->ctx->stream,
+                       op->N, op->P, op->d_lq_off.p, op->d_lq_xi.p, op->d_lq_w.p, op->d_lq_f.p, G);
+    FDE_LAUNCH_CHECK();
+}
+
+}  // namespace fde

@@ -1,0 +1,501 @@
+// C entry points: context, operator, load vector, stiffness apply, utilities.
+// Every entry point catches the library's internal failures and returns a
+// status code; the message is kept per thread for fde_last_error().
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "fde_internal.h"
+
+namespace fde {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const char* fmt, ...) {
+    char buf[2048];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+void fail(int code, const char* fmt, ...) {
+    char buf[2048];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Error{code, buf};
+}
+
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+void* dev_alloc(Ctx* c, size_t bytes) {
+    if (c->budget && c->in_use + bytes > c->budget)
+        fail(FDE_ENOMEM, "HBM budget exceeded: %zu bytes in use + %zu requested > budget %zu", c->in_use,
+             bytes, c->budget);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(FDE_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    c->in_use += bytes;
+    return p;
+}
+
+void dev_free(Ctx* c, void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    if (c) c->in_use = bytes > c->in_use ? 0 : c->in_use - bytes;
+}
+
+void upload(Ctx* c, void* dst, const void* src, size_t bytes) {
+    if (bytes) FDE_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+}
+
+namespace {
+
+double nodes_for(double len, double dist, int P) {
+    const double a = 1.0 + 2.0 * dist / len;
+    const double rho = a + std::sqrt(a * a - 1.0);
+    return std::ceil(0.5 * (P + 36.8 / std::log(rho))) + 1;
+}
+
+// Quadrature nodes of the load vector on element e. Elements touching a or b
+// carry geometric panels toward that end and a Gauss-Jacobi end panel, so an
+// endpoint singularity f ~ d^{-alpha} (the behaviour of -D^2 I^{2-alpha} of a
+// function with nonzero slope at the end) is integrated to ~1e-16; elements
+// near an end are graded toward it as in the far-field moments; the rest use
+// one Gauss-Legendre panel.
+void element_load_rule(const Op* op, int e, std::vector<double>& xs, std::vector<double>& xis,
+                       std::vector<double>& ws, std::vector<double>& das, std::vector<double>& dbs) {
+    const double a = op->x.front(), b = op->x.back();
+    const double xl = op->x[e], xr = op->x[e + 1], he = xr - xl;
+    const int P = op->P;
+    const int nbase = std::max(24, P + 12);
+    // distances of a node at distance u from the element end on `side` to a and b
+    const double da_l = xl - a, db_r = b - xr;
+    auto push_dist = [&](double u, int side) {
+        if (side == 0) {
+            das.push_back(da_l + u);
+            dbs.push_back(db_r + (he - u));
+        } else {
+            das.push_back(da_l + (he - u));
+            dbs.push_back(db_r + u);
+        }
+    };
+    auto add_panel = [&](double lo, double hi, int n, int side) {
+        // lo, hi: distances from the element end on `side` (0: x_e, 1: x_{e+1})
+        n = std::min(std::max(n, 1), kMaxGL);
+        std::vector<double> gx(n), gw(n);
+        gauss_jacobi(n, 0.0, 0.0, gx.data(), gw.data());
+        for (int i = 0; i < n; ++i) {
+            const double u = 0.5 * (hi - lo) * gx[i] + 0.5 * (hi + lo);
+            const double w = 0.5 * (hi - lo) * gw[i];
+            double xv, xi;
+            if (side == 0) {
+                xv = xl + u;
+                if (xv <= xl) xv = std::nextafter(xl, xr);
+                xi = 2.0 * u / he - 1.0;
+            } else {
+                xv = xr - u;
+                if (xv >= xr) xv = std::nextafter(xr, xl);
+                xi = 1.0 - 2.0 * u / he;
+            }
+            xs.push_back(xv);
+            xis.push_back(xi);
+            ws.push_back(w);
+            push_dist(u, side);
+        }
+    };
+    const bool touch_a = (e == 0), touch_b = (e == op->N - 1);
+    if (touch_a || touch_b) {
+        // panels [s^{l+1} T, s^l T] down to 1e-12 T, then [0, delta] with the Gauss-Jacobi rule
+        // for the weight d^{1-alpha} (exact for f ~ d^{-alpha} x polynomial, times a test
+        // function vanishing at the end)
+        const double s = 0.3;
+        auto graded = [&](double top, int side, double far_dist) {
+            double hi = top;
+            for (int l = 0; hi > 1e-12 * top; ++l) {
+                const double lo = hi * s;
+                int n = 16;
+                if (l == 0) n = std::max(n, (int)nodes_for(hi - lo, far_dist, P));
+                add_panel(lo, hi, n, side);
+                hi = lo;
+            }
+            const int nj = 16;
+            std::vector<double> gx(nj), gw(nj);
+            gauss_jacobi(nj, 0.0, 1.0 - op->alpha, gx.data(), gw.data());
+            const double delta = hi;
+            for (int i = 0; i < nj; ++i) {
+                const double u = 0.5 * delta * (1.0 + gx[i]);
+                // int_0^delta F du = (delta/2)^{2-alpha} int (1+t)^{1-alpha} F u^{alpha-1} dt
+                const double w = std::pow(0.5 * delta, 2.0 - op->alpha) * gw[i] * std::pow(u, op->alpha - 1.0);
+                if (side == 0) {
+                    xs.push_back(xl + u);
+                    xis.push_back(2.0 * u / he - 1.0);
+                } else {
+                    xs.push_back(xr - u);
+                    xis.push_back(1.0 - 2.0 * u / he);
+                }
+                ws.push_back(w);
+                push_dist(u, side);
+            }
+        };
+        if (touch_a && touch_b) {
+            graded(0.5 * he, 0, 0.5 * he);
+            graded(0.5 * he, 1, 0.5 * he);
+        } else if (touch_a) {
+            graded(he, 0, b - xr + 1e-300);
+        } else {
+            graded(he, 1, xl - a + 1e-300);
+        }
+        return;
+    }
+    const double da = xl - a, db = b - xr;
+    const int side = da <= db ? 0 : 1;
+    const double g = std::min(da, db), gother = std::max(da, db);
+    if (g >= he) {
+        int n = (int)std::max<double>(nbase, nodes_for(he, g, P));
+        n = std::max(n, (int)nodes_for(he, gother, P));
+        add_panel(0.0, he, n, side);
+        return;
+    }
+    for (int j = 0;; ++j) {
+        const double lo = g * (std::exp2((double)j) - 1.0);
+        double hi = g * (std::exp2((double)(j + 1)) - 1.0);
+        const bool last = hi >= he;
+        if (last) hi = he;
+        add_panel(lo, hi, (int)std::max<double>(nbase, nodes_for(hi - lo, g + lo, P)), side);
+        if (last) break;
+    }
+}
+
+void build_load_rule(Op* op) {
+    op->lq_x.clear();
+    op->lq_xi.clear();
+    op->lq_w.clear();
+    op->lq_da.clear();
+    op->lq_db.clear();
+    op->lq_off.assign(op->N + 1, 0);
+    for (int e = 0; e < op->N; ++e) {
+        op->lq_off[e] = (int)op->lq_x.size();
+        element_load_rule(op, e, op->lq_x, op->lq_xi, op->lq_w, op->lq_da, op->lq_db);
+    }
+    op->lq_off[op->N] = (int)op->lq_x.size();
+}
+
+// (P+1)^2 mass of the reference basis [phi_L, phi_R, psi_1..psi_{P-1}] on [-1,1]
+void local_mass(int P, std::vector<double>& M) {
+    const int n = P + 3;
+    std::vector<double> gx(n), gw(n);
+    gauss_jacobi(n, 0.0, 0.0, gx.data(), gw.data());
+    const int P1 = P + 1;
+    M.assign(P1 * P1, 0.0);
+    std::vector<double> B(P1), L(P + 2);
+    for (int q = 0; q < n; ++q) {
+        const double t = gx[q];
+        L[0] = 1.0;
+        L[1] = t;
+        for (int k = 1; k + 1 < P + 2; ++k) L[k + 1] = ((2 * k + 1) * t * L[k] - k * L[k - 1]) / (k + 1);
+        B[0] = 0.5 * (1.0 - t);
+        B[1] = 0.5 * (1.0 + t);
+        for (int p = 1; p < P; ++p) B[1 + p] = L[p - 1] - L[p + 1];
+        for (int i = 0; i < P1; ++i)
+            for (int j = 0; j < P1; ++j) M[i * P1 + j] += gw[q] * B[i] * B[j];
+    }
+}
+
+void init_ctx_tables(Ctx* c) {
+    const int tot = kMaxGL * (kMaxGL + 1) / 2;
+    std::vector<double> t(2 * tot);
+    for (int n = 1; n <= kMaxGL; ++n) {
+        const int off = n * (n - 1) / 2;
+        gauss_jacobi(n, 0.0, 0.0, t.data() + off, t.data() + tot + off);
+    }
+    c->gl.alloc(c, t.size());
+    upload(c, c->gl.p, t.data(), t.size() * sizeof(double));
+    FDE_HIP(hipStreamSynchronize(c->stream));
+}
+
+void build_op(Op* op, const double* nodes, int N, int P, double alpha, double theta, double rho,
+              int mode) {
+    if (N < 1) fail(FDE_EINVAL, "N must be >= 1 (got %d)", N);
+    if (P < 2 || P > 32) fail(FDE_EINVAL, "P must be in [2, 32] (got %d)", P);
+    if (!(alpha > 1.0 && alpha < 2.0)) fail(FDE_EINVAL, "alpha must be in (1,2) (got %g)", alpha);
+    if (!(theta >= 0.0 && theta <= 1.0)) fail(FDE_EINVAL, "theta must be in [0,1] (got %g)", theta);
+    if (!(rho >= 0.0) || !std::isfinite(rho)) fail(FDE_EINVAL, "rho must be finite and >= 0 (got %g)", rho);
+    if (!nodes) fail(FDE_EINVAL, "nodes is NULL");
+    if (mode < FDE_APPLY_AUTO || mode > FDE_APPLY_TOEPLITZ) fail(FDE_EINVAL, "bad apply mode %d", mode);
+    op->N = N;
+    op->P = P;
+    op->Nd = N * P - 1;
+    op->alpha = alpha;
+    op->theta = theta;
+    op->rho = rho;
+    op->gamma0 = 1.0 / std::tgamma(2.0 - alpha);
+    op->x.assign(nodes, nodes + N + 1);
+    op->h.resize(N);
+    for (int e = 0; e < N; ++e) {
+        if (!std::isfinite(op->x[e]) || !std::isfinite(op->x[e + 1]) || !(op->x[e + 1] > op->x[e]))
+            fail(FDE_EINVAL, "mesh must be finite and strictly increasing (at node %d)", e);
+        op->h[e] = op->x[e + 1] - op->x[e];
+    }
+    // constant ratio h_{e+1}/h_e ?
+    bool geo = true;
+    double r = 1.0;
+    if (N > 1) {
+        r = op->h[1] / op->h[0];
+        for (int e = 1; e + 1 < N && geo; ++e) {
+            const double q = op->h[e + 1] / op->h[e];
+            if (std::fabs(q - r) > 1e-12 * std::max(1.0, r)) geo = false;
+        }
+    }
+    bool uni = geo && std::fabs(r - 1.0) <= 1e-12;
+    if (uni) r = 1.0;
+    if (mode == FDE_APPLY_TOEPLITZ && !geo)
+        fail(FDE_EINVAL, "Toeplitz apply needs a uniform or constant-ratio mesh");
+    // one workgroup holds a half-length complex sequence (16 bytes x L/2) in LDS
+    const bool fits = 2 * N <= 8192;
+    if (mode == FDE_APPLY_TOEPLITZ && !fits)
+        fail(FDE_EUNSUPPORTED, "Toeplitz apply supports N <= 4096 (got %d)", N);
+    op->toeplitz = geo && fits && mode != FDE_APPLY_DENSE;
+    op->uniform = uni;
+    op->ratio = r;
+    Ctx* c = op->ctx;
+    op->d_x.alloc(c, N + 1);
+    op->d_h.alloc(c, N);
+    upload(c, op->d_x.p, op->x.data(), (N + 1) * sizeof(double));
+    upload(c, op->d_h.p, op->h.data(), N * sizeof(double));
+    std::vector<double> rules(2 * (P + 1) + 2 * P);
+    gauss_jacobi(P + 1, 0.0, 2.0 - alpha, rules.data(), rules.data() + P + 1);
+    gauss_jacobi(P, 0.0, 1.0 - alpha, rules.data() + 2 * (P + 1), rules.data() + 2 * (P + 1) + P);
+    op->d_rules.alloc(c, rules.size());
+    upload(c, op->d_rules.p, rules.data(), rules.size() * sizeof(double));
+    std::vector<double> lm;
+    local_mass(P, lm);
+    op->d_lmass.alloc(c, lm.size());
+    upload(c, op->d_lmass.p, lm.data(), lm.size() * sizeof(double));
+    if (op->toeplitz) {
+        int L = 1;
+        while (L < 2 * N) L *= 2;
+        if (L < 4) L = 4;
+        op->L = L;
+        const int M = L / 2;
+        std::vector<double2> tw(M + 1);
+        for (int j = 0; j <= M; ++j) {
+            const long double ang = -2.0L * 3.14159265358979323846264338327950288L * j / L;
+            tw[j] = make_double2((double)std::cos(ang), (double)std::sin(ang));
+        }
+        op->d_tw.alloc(c, M + 1);
+        upload(c, op->d_tw.p, tw.data(), tw.size() * sizeof(double2));
+        op->d_gen.alloc(c, (size_t)N * P * P);
+        op->d_sym.alloc(c, (size_t)P * P * (M + 1));
+        launch_generators(op);
+        build_symbol(op);
+    } else {
+        op->d_mom.alloc(c, (size_t)tri(N) * P * P);
+        launch_pair_moments_dense(op);
+    }
+    build_load_rule(op);
+    FDE_HIP(hipStreamSynchronize(c->stream));
+}
+
+}  // namespace
+}  // namespace fde
+
+using namespace fde;
+
+#define FDE_API_BEGIN try {
+#define FDE_API_END                                 \
+    }                                               \
+    catch (const fde::Error& e) {                   \
+        fde::set_error("%s", e.msg.c_str());        \
+        return e.code;                              \
+    }                                               \
+    catch (const std::bad_alloc&) {                 \
+        fde::set_error("host allocation failed");   \
+        return FDE_ENOMEM;                          \
+    }                                               \
+    catch (...) {                                   \
+        fde::set_error("unexpected internal error"); \
+        return FDE_EDEVICE;                         \
+    }                                               \
+    return FDE_OK;
+
+extern "C" {
+
+const char* fde_last_error(void) { return fde::last_error_cstr(); }
+const char* fde_version(void) { return "fde-hsolve 0.1 (gfx950)"; }
+
+int fde_gauss_jacobi(int n, double a, double b, double* x, double* w) {
+    FDE_API_BEGIN
+    if (!x || !w) fail(FDE_EINVAL, "null output");
+    fde::gauss_jacobi(n, a, b, x, w);
+    FDE_API_END
+}
+
+int fde_ctx_create(int device, void* hip_stream, size_t budget, fde_ctx** out) {
+    FDE_API_BEGIN
+    if (!out) fail(FDE_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    FDE_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) fail(FDE_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    FDE_HIP(hipSetDevice(device));
+    fde_ctx* c = new fde_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->budget = budget;
+    try {
+        init_ctx_tables(c);
+    } catch (...) {
+        delete c;
+        throw;
+    }
+    *out = c;
+    FDE_API_END
+}
+
+void fde_ctx_destroy(fde_ctx* c) {
+    if (!c) return;
+    try {
+        (void)hipStreamSynchronize(c->stream);
+    } catch (...) {
+    }
+    delete c;
+}
+
+int fde_ctx_set_stream(fde_ctx* c, void* s) {
+    FDE_API_BEGIN
+    if (!c) fail(FDE_EINVAL, "null context");
+    c->stream = static_cast<hipStream_t>(s);
+    FDE_API_END
+}
+
+size_t fde_ctx_bytes_in_use(const fde_ctx* c) { return c ? c->in_use : 0; }
+
+int fde_op_create(fde_ctx* c, const double* nodes, int N, int P, double alpha, double theta, double rho,
+                  int mode, fde_op** out) {
+    FDE_API_BEGIN
+    if (!c || !out) fail(FDE_EINVAL, "null context or output");
+    *out = nullptr;
+    FDE_HIP(hipSetDevice(c->device));
+    fde_op* op = new fde_op();
+    op->ctx = c;
+    try {
+        build_op(op, nodes, N, P, alpha, theta, rho, mode);
+    } catch (...) {
+        delete op;
+        throw;
+    }
+    *out = op;
+    FDE_API_END
+}
+
+void fde_op_destroy(fde_op* op) {
+    if (!op) return;
+    (void)hipStreamSynchronize(op->ctx->stream);
+    delete op;
+}
+
+int fde_op_ndof(const fde_op* op) { return op ? op->Nd : -1; }
+int fde_op_is_toeplitz(const fde_op* op) { return op ? (op->toeplitz ? 1 : 0) : -1; }
+
+int fde_op_pair_moments(fde_op* op, int npairs, const int* e, const int* f, double* out) {
+    FDE_API_BEGIN
+    if (!op || npairs < 0 || (npairs && (!e || !f || !out))) fail(FDE_EINVAL, "bad arguments");
+    for (int i = 0; i < npairs; ++i)
+        if (e[i] < 0 || e[i] >= op->N || f[i] < 0 || f[i] > e[i])
+            fail(FDE_EINVAL, "pair %d: need 0 <= f <= e < N (e=%d f=%d)", i, e[i], f[i]);
+    if (npairs == 0) return FDE_OK;
+    Ctx* c = op->ctx;
+    DevBuf<int> de, df;
+    DevBuf<double> dout;
+    de.alloc(c, npairs);
+    df.alloc(c, npairs);
+    dout.alloc(c, (size_t)npairs * op->P * op->P);
+    upload(c, de.p, e, npairs * sizeof(int));
+    upload(c, df.p, f, npairs * sizeof(int));
+    launch_pair_moments_list(op, npairs, de.p, df.p, dout.p);
+    FDE_HIP(hipMemcpyAsync(out, dout.p, dout.bytes(), hipMemcpyDeviceToHost, c->stream));
+    FDE_HIP(hipStreamSynchronize(c->stream));
+    FDE_API_END
+}
+
+int fde_op_dense(fde_op* op, double* A, int lda) {
+    FDE_API_BEGIN
+    if (!op || !A || lda < op->Nd) fail(FDE_EINVAL, "bad arguments");
+    if (op->Nd > 65535) fail(FDE_EUNSUPPORTED, "fde_op_dense is meant for Nd <= 65535 (got %d)", op->Nd);
+    launch_dense_matrix(op, A, lda);
+    FDE_API_END
+}
+
+int fde_load_nodes(fde_op* op, int* nq, double* x, double* da, double* db) {
+    FDE_API_BEGIN
+    if (!op || !nq) fail(FDE_EINVAL, "bad arguments");
+    const size_t n = op->lq_x.size();
+    *nq = (int)n;
+    if (x) std::memcpy(x, op->lq_x.data(), n * sizeof(double));
+    if (da) std::memcpy(da, op->lq_da.data(), n * sizeof(double));
+    if (db) std::memcpy(db, op->lq_db.data(), n * sizeof(double));
+    FDE_API_END
+}
+
+int fde_load_vector(fde_op* op, const double* f, double c1, double c2, double* G) {
+    FDE_API_BEGIN
+    if (!op || !f || !G) fail(FDE_EINVAL, "bad arguments");
+    if (!std::isfinite(c1) || !std::isfinite(c2)) fail(FDE_EINVAL, "boundary values must be finite");
+    Ctx* c = op->ctx;
+    const size_t nq = op->lq_x.size();
+    if (op->d_lq_xi.n != nq) {
+        op->d_lq_xi.alloc(c, nq);
+        op->d_lq_w.alloc(c, nq);
+        op->d_lq_off.alloc(c, op->lq_off.size());
+        upload(c, op->d_lq_xi.p, op->lq_xi.data(), nq * sizeof(double));
+        upload(c, op->d_lq_w.p, op->lq_w.data(), nq * sizeof(double));
+        upload(c, op->d_lq_off.p, op->lq_off.data(), op->lq_off.size() * sizeof(int));
+        op->d_lq_f.alloc(c, nq);
+    }
+    for (size_t q = 0; q < nq; ++q)
+        if (!std::isfinite(f[q])) fail(FDE_EINVAL, "f is not finite at node %zu (x = %.17g)", q, op->lq_x[q]);
+    upload(c, op->d_lq_f.p, f, nq * sizeof(double));
+    launch_load_vector(op, G);
+    if (c1 != 0.0 || c2 != 0.0) {
+        // lifting: G -= A [0; c1, c2] through the boundary hats
+        DevBuf<double> t;
+        t.alloc(c, op->Nd);
+        stiffness_apply(op, 1, nullptr, op->Nd, t.p, op->Nd, c1, c2, true);
+        axpy_cols(c->stream, op->Nd, 1, -1.0, t.p, op->Nd, G, op->Nd);
+        FDE_HIP(hipStreamSynchronize(c->stream));
+    }
+    FDE_HIP(hipStreamSynchronize(c->stream));
+    FDE_API_END
+}
+
+int fde_load_vector_fn(fde_op* op, fde_fn fn, void* user, double c1, double c2, double* G) {
+    FDE_API_BEGIN
+    if (!op || !fn) fail(FDE_EINVAL, "bad arguments");
+    std::vector<double> fv(op->lq_x.size());
+    for (size_t q = 0; q < fv.size(); ++q) fv[q] = fn(op->lq_x[q], user);
+    const int rc = fde_load_vector(op, fv.data(), c1, c2, G);
+    if (rc != FDE_OK) return rc;
+    FDE_API_END
+}
+
+int fde_stiffness_apply(fde_op* op, int nrhs, const double* X, int ldx, double* Y, int ldy) {
+    FDE_API_BEGIN
+    if (!op || nrhs < 0 || (nrhs && (!X || !Y)) || ldx < op->Nd || ldy < op->Nd)
+        fail(FDE_EINVAL, "bad arguments");
+    if (nrhs == 0) return FDE_OK;
+    stiffness_apply(op, nrhs, X, ldx, Y, ldy, 0.0, 0.0, false);
+    FDE_API_END
+}
+
+}  // extern "C"

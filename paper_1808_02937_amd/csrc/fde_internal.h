@@ -1,0 +1,126 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fde.h"
+
+namespace fde {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+struct Error {
+    int code;
+    std::string msg;
+};
+// Throw inside the library; the C entry points catch and translate.
+[[noreturn]] void fail(int code, const char* fmt, ...);
+
+#define FDE_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            ::fde::fail(FDE_EDEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                               \
+    } while (0)
+
+#define FDE_LAUNCH_CHECK() FDE_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- quadrature
+// n-point Gauss rule for (1-x)^a (1+x)^b on [-1,1]; nodes ascending.
+void gauss_jacobi(int n, double a, double b, double* x, double* w);
+
+constexpr int kMaxGL = 64;  // Gauss-Legendre rules n = 1..kMaxGL live on the device
+
+// ---------------------------------------------------------------- memory
+struct Ctx;
+void* dev_alloc(Ctx* c, size_t bytes);
+void dev_free(Ctx* c, void* p, size_t bytes);
+
+template <class T>
+struct DevBuf {
+    Ctx* ctx = nullptr;
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { reset(); }
+    void alloc(Ctx* c, size_t count) {
+        reset();
+        ctx = c;
+        n = count;
+        p = count ? static_cast<T*>(dev_alloc(c, count * sizeof(T))) : nullptr;
+    }
+    void reset() {
+        if (p) dev_free(ctx, p, n * sizeof(T));
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t budget = 0;   // 0: unlimited
+    size_t in_use = 0;
+    DevBuf<double> gl;   // Gauss-Legendre n=1..kMaxGL: nodes then weights, offset n(n-1)/2
+};
+
+// ---------------------------------------------------------------- operator
+struct Op {
+    Ctx* ctx = nullptr;
+    int N = 0, P = 0, Nd = 0;
+    double alpha = 0, theta = 0, rho = 0, gamma0 = 0;
+    std::vector<double> x, h;
+    bool toeplitz = false;
+    bool uniform = false;
+    double ratio = 1.0;  // h_{e+1}/h_e on constant-ratio meshes
+    int L = 0;           // FFT length (power of two >= 2N)
+    // device data
+    DevBuf<double> d_x, d_h;
+    DevBuf<double> d_rules;      // GJ(0,2-alpha) n=P+1 then GJ(0,1-alpha) n=P: x then w
+    DevBuf<double> d_lmass;      // (P+1)^2 local mass in [phi_L, phi_R, psi_1..]
+    DevBuf<double> d_mom;        // dense: N(N+1)/2 pairs x P x P
+    DevBuf<double> d_gen;        // Toeplitz: N generators x P x P
+    DevBuf<double2> d_sym;       // Toeplitz: (L/2+1) x P x P spectrum of the generators
+    DevBuf<double2> d_tw;        // twiddles for the half-length complex FFT
+    // load-vector quadrature (host + device)
+    std::vector<double> lq_x, lq_xi, lq_w, lq_da, lq_db;
+    std::vector<int> lq_off;     // N+1 offsets
+    DevBuf<double> d_lq_xi, d_lq_w, d_lq_f;
+    DevBuf<int> d_lq_off;
+    // apply workspace
+    DevBuf<double> ws;
+    size_t apply_ws_doubles(int nrhs) const;
+};
+
+// kernels (assembly.hip)
+void launch_pair_moments_dense(Op* op);
+void launch_generators(Op* op);
+void launch_pair_moments_list(Op* op, int npairs, const int* d_e, const int* d_f, double* d_out);
+void launch_load_vector(Op* op, double* G);
+void launch_dense_matrix(Op* op, double* A, int lda);
+
+// apply (apply.hip): Y = A X (+ boundary values bc0/bcN of the lifting)
+void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int ldy, double bc0,
+                     double bcN, bool zero_x);
+void build_symbol(Op* op);
+
+// blas1.hip
+void axpy_cols(hipStream_t st, int n, int ncol, double a, const double* x, int ldx, double* y, int ldy);
+
+// tiny helpers
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t tri(int64_t e) { return e * (e + 1) / 2; }
+
+}  // namespace fde
+
+struct fde_ctx : fde::Ctx {};
+struct fde_op : fde::Op {};

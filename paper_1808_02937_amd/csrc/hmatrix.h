@@ -1,0 +1,112 @@
+// H-matrix data structures, the op-list ("program") format of the device
+// interpreter, and the generator that flattens the recursive H-LU and
+// H-substitutions into that list.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <vector>
+
+#include "fde_internal.h"
+
+namespace fde {
+
+// --------------------------------------------------------------- trees
+struct Cluster {
+    int e0, e1;        // elements [e0, e1)
+    int d0, d1;        // unknowns [d0, d1) in element-interleaved order
+    double lo, hi;     // union of the supports of its basis functions
+    int level;
+    int child[2] = {-1, -1};
+    bool leaf() const { return child[0] < 0; }
+    int size() const { return d1 - d0; }
+};
+
+enum BlockKind { kDense = 0, kLowRank = 1, kHier = 2 };
+
+struct Block {
+    int kind;
+    int tau, sigma;        // cluster ids (rows, cols)
+    int child[4] = {-1, -1, -1, -1};   // 2 x 2, row-major
+    // storage (element offsets in the factor arena)
+    int64_t off = 0;       // dense: m x n column-major (ld = m)
+    int64_t uoff = 0, voff = 0;   // low rank: U m x kmax (ld m), V n x kmax (ld n)
+    int slot = -1;         // rank slot (low rank)
+    int lr_id = -1;        // index among low-rank blocks
+    bool lower = false;    // low rank: row cluster right of the column cluster
+};
+
+// per low-rank block: how its Taylor factors are formed (Section 3.1-3.2)
+struct FactorSide {
+    int singular;      // 1: c_nu-type (x-c)^{1-alpha-nu} side, 0: ((x-c)/r)^nu side
+    double center, radius, sgn, mult;
+    int cluster;
+};
+
+struct LowRankDesc {
+    int block;
+    FactorSide u, v;   // U rows (block rows), V rows (block cols)
+};
+
+// --------------------------------------------------------------- program
+enum OpCode { OP_GETRF = 1, OP_TRSM = 2, OP_GEMM = 3, OP_LRSUB = 4, OP_ZERO = 5, OP_LOAD = 6, OP_STORE = 7 };
+enum Base { B_ARENA = 0, B_WORK = 1 };
+
+struct View {
+    int base;          // B_ARENA (factors) or B_WORK (right-hand sides and temporaries)
+    int rs, cs;        // element (i, j) at off + i*rs + j*cs
+    int64_t off;
+};
+
+struct OpRec {
+    int code;
+    int flags;         // TRSM: bit0 lower, bit1 unit diagonal
+    int dim[3];        // m, n, k; >= 0 static, -1 = number of right-hand sides, <= -2: rank slot -2-d
+    int blk;           // LRSUB: low-rank block id
+    float alpha, beta; // GEMM
+    View v[3];         // GEMM: C, A, B; TRSM: X, T; GETRF: A; LRSUB: X, Y; ZERO: X
+};
+
+struct LRBlockDev {    // device table for OP_LRSUB
+    int64_t uoff, voff;
+    int m, n, slot, pad;
+};
+
+struct Program {
+    std::vector<OpRec> ops;
+    int64_t work_elems = 0;   // temporaries in the work area (beyond the right-hand sides)
+};
+
+// --------------------------------------------------------------- H-matrix
+struct HMat {
+    Op* op = nullptr;
+    int R = 8, leaf = 8;
+    double lambda = 1.0;
+    std::vector<int> h2p;          // internal index -> paper index
+    std::vector<Cluster> cl;
+    std::vector<Block> bl;
+    int root = 0;
+    std::vector<int> lr_blocks;    // block ids of low-rank leaves
+    std::vector<int> dense_blocks;
+    int kmax = 8;                  // rank capacity of U, V storage
+    int64_t arena_elems = 0;
+    int nslots = 0;
+    int max_lr_rows = 0;           // largest m or n of a low-rank block
+    int max_inner = 0;             // largest inner dimension of a dense x dense product into a low-rank block
+    // FP64 copy of A~ on the device (built once; factorisations copy and convert it)
+    DevBuf<double> d_arena;
+    DevBuf<int> d_ranks;           // initial ranks
+    DevBuf<LRBlockDev> d_lr;
+    DevBuf<int> d_h2p;
+};
+
+void build_trees(HMat* hm);
+void build_hmatrix_device(HMat* hm);   // hbuild.hip
+
+// program generation (progs.cpp)
+void gen_hlu(const HMat& hm, Program& prog);
+void gen_hsolve(const HMat& hm, Program& prog);
+int64_t lrsub_scratch_elems(const HMat& hm);
+int lrsub_kprime_max(const HMat& hm);
+
+}  // namespace fde

@@ -1,0 +1,280 @@
+"""Python binding of the C ABI (include/fde.h): argument marshalling only.
+
+Device arrays are torch tensors on the context's device. A block of nrhs
+vectors is a contiguous tensor of shape (nrhs, Nd): row r is column r of the
+column-major Nd x nrhs array the library sees, with leading dimension Nd.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Callable, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi as A
+from ._abi import check, load
+
+
+def _dptr(t: torch.Tensor) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def _np_dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _as_block(t: torch.Tensor, Nd: int, device) -> torch.Tensor:
+    if t.dim() == 1:
+        t = t.unsqueeze(0)
+    if t.dtype != torch.float64 or t.device != device or not t.is_contiguous() or t.shape[-1] != Nd:
+        raise ValueError(f"expected a contiguous float64 tensor of shape (nrhs, {Nd}) on {device}")
+    return t
+
+
+def gauss_jacobi(n: int, a: float, b: float):
+    """The library's own Gauss rule for the weight (1-x)^a (1+x)^b (host)."""
+    x = np.zeros(n)
+    w = np.zeros(n)
+    check(load().fde_gauss_jacobi(n, a, b, _np_dptr(x), _np_dptr(w)))
+    return x, w
+
+
+class Context:
+    """Device, HIP stream (torch's current stream by default) and HBM budget."""
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None, budget_bytes: int = 0):
+        lib = load()
+        self.device = torch.device("cuda", device)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._stream = s
+        h = C.c_void_p()
+        check(lib.fde_ctx_create(device, C.c_void_p(s.cuda_stream), budget_bytes, C.byref(h)))
+        self.h = h
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self._stream = stream
+        check(load().fde_ctx_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+
+    def bytes_in_use(self) -> int:
+        return int(load().fde_ctx_bytes_in_use(self.h))
+
+    def synchronize(self):
+        self._stream.synchronize()
+
+    def close(self):
+        if self.h:
+            load().fde_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_MODES = {"auto": A.FDE_APPLY_AUTO, "dense": A.FDE_APPLY_DENSE, "toeplitz": A.FDE_APPLY_TOEPLITZ}
+
+
+class Operator:
+    """A = rho M + theta S_l + (1-theta) S_l^T on a mesh (Section 2.2)."""
+
+    def __init__(self, ctx: Context, nodes, P: int, alpha: float, theta: float, rho: float,
+                 apply: str = "auto"):
+        self.ctx = ctx
+        x = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64))
+        self.N = len(x) - 1
+        self.P, self.alpha, self.theta, self.rho = int(P), float(alpha), float(theta), float(rho)
+        h = C.c_void_p()
+        check(load().fde_op_create(ctx.h, _np_dptr(x), self.N, self.P, self.alpha, self.theta, self.rho,
+                                   _MODES[apply], C.byref(h)))
+        self.h = h
+        self.Nd = int(load().fde_op_ndof(h))
+        self.toeplitz = bool(load().fde_op_is_toeplitz(h))
+
+    def close(self):
+        if self.h:
+            load().fde_op_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pair_moments(self, e: Sequence[int], f: Sequence[int]) -> np.ndarray:
+        e = np.ascontiguousarray(e, dtype=np.int32)
+        f = np.ascontiguousarray(f, dtype=np.int32)
+        out = np.zeros((len(e), self.P, self.P))
+        check(load().fde_op_pair_moments(self.h, len(e), e.ctypes.data_as(A.ip), f.ctypes.data_as(A.ip),
+                                         _np_dptr(out)))
+        return out
+
+    def dense(self) -> torch.Tensor:
+        """A (Nd x Nd) on the device."""
+        At = torch.empty((self.Nd, self.Nd), dtype=torch.float64, device=self.ctx.device)  # At[j, i] = A[i, j]
+        check(load().fde_op_dense(self.h, _dptr(At), self.Nd))
+        return At.t()
+
+    def load_nodes(self):
+        """(x, x - a, b - x) of the load-vector quadrature nodes."""
+        n = C.c_int()
+        check(load().fde_load_nodes(self.h, C.byref(n), None, None, None))
+        x, da, db = np.zeros(n.value), np.zeros(n.value), np.zeros(n.value)
+        check(load().fde_load_nodes(self.h, C.byref(n), _np_dptr(x), _np_dptr(da), _np_dptr(db)))
+        return x, da, db
+
+    def load_vector(self, f, c1: float = 0.0, c2: float = 0.0) -> torch.Tensor:
+        """G = (f, phi) with lifting of c1, c2.
+
+        f: values at the nodes of load_nodes(), or a vectorised callable f(x) or
+        f(x, da, db) (the latter receives the exact distances to a and b)."""
+        if callable(f):
+            x, da, db = self.load_nodes()
+            try:
+                vals = f(x, da, db)
+            except TypeError:
+                vals = f(x)
+            fv = np.ascontiguousarray(np.asarray(vals, dtype=np.float64))
+        else:
+            fv = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+        G = torch.empty(self.Nd, dtype=torch.float64, device=self.ctx.device)
+        check(load().fde_load_vector(self.h, _np_dptr(fv), float(c1), float(c2), _dptr(G)))
+        return G
+
+    def apply(self, X: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        X2 = _as_block(X, self.Nd, self.ctx.device)
+        Y = torch.empty_like(X2) if out is None else _as_block(out, self.Nd, self.ctx.device)
+        check(load().fde_stiffness_apply(self.h, X2.shape[0], _dptr(X2), X2.stride(0), _dptr(Y), Y.stride(0)))
+        return Y.view_as(X) if out is None else out
+
+
+class HMatrix:
+    """A~ = rho M + H (Section 3)."""
+
+    def __init__(self, op: Operator, R: int = 8, lam: float = 1.0, leaf_elems: int = 8):
+        self.op = op
+        p = A.HParams(int(R), float(lam), int(leaf_elems))
+        h = C.c_void_p()
+        check(load().fde_build_hmatrix(op.h, C.byref(p), C.byref(h)))
+        self.h = h
+
+    def counts(self):
+        nd, nr = C.c_int(), C.c_int()
+        check(load().fde_hmat_counts(self.h, C.byref(nd), C.byref(nr)))
+        return nd.value, nr.value
+
+    def dense(self) -> torch.Tensor:
+        Nd = self.op.Nd
+        At = torch.empty((Nd, Nd), dtype=torch.float64, device=self.op.ctx.device)
+        check(load().fde_hmat_to_dense(self.h, _dptr(At), Nd))
+        return At.t()
+
+    def close(self):
+        if self.h:
+            load().fde_hmat_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HLU:
+    """H-LU factors L_H U_H of A~ (Section 4.1)."""
+
+    def __init__(self, hm: HMatrix, tol: float = 1e-3, rank_cap: int = 0, precision: str = "fp32",
+                 pivot_floor: float = 1e-14):
+        self.hm = hm
+        self.Nd = hm.op.Nd
+        self.device = hm.op.ctx.device
+        prec = {"fp64": A.FDE_FP64, "fp32": A.FDE_FP32}[precision]
+        p = A.HLUParams(float(tol), int(rank_cap), prec, float(pivot_floor))
+        h = C.c_void_p()
+        check(load().fde_hlu_factor(hm.h, C.byref(p), C.byref(h)))
+        self.h = h
+
+    def solve(self, B: torch.Tensor) -> torch.Tensor:
+        B2 = _as_block(B, self.Nd, self.device)
+        X = torch.empty_like(B2)
+        check(load().fde_hlu_solve(self.h, B2.shape[0], _dptr(B2), B2.stride(0), _dptr(X), X.stride(0)))
+        return X.view_as(B)
+
+    def dense(self):
+        """(packed L\\U in the internal order as an Nd x Nd tensor, h2p order)."""
+        Nd = self.Nd
+        Ft = torch.empty((Nd, Nd), dtype=torch.float64, device=self.device)
+        h2p = np.zeros(Nd, dtype=np.int32)
+        check(load().fde_hlu_to_dense(self.h, _dptr(Ft), Nd, h2p.ctypes.data_as(A.ip)))
+        return Ft.t(), h2p
+
+    def max_rank(self) -> int:
+        r = C.c_int()
+        check(load().fde_hlu_max_rank(self.h, C.byref(r)))
+        return r.value
+
+    def close(self):
+        if self.h:
+            load().fde_hlu_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _solve_params(rtol, restart, maxit):
+    return A.SolveParams(A.FDE_FGMRES, int(restart), int(maxit), float(rtol))
+
+
+def solve(op: Operator, G: torch.Tensor, prec: Optional[HLU] = None, rtol: float = 1e-10,
+          restart: int = 30, maxit: int = 500, raise_on_noconv: bool = True):
+    """X with ||G - A X|| <= rtol ||G|| per column (right-preconditioned FGMRES). Returns (X, infos)."""
+    G2 = _as_block(G, op.Nd, op.ctx.device)
+    X = torch.empty_like(G2)
+    nrhs = G2.shape[0]
+    info = (A.SolveInfo * nrhs)()
+    p = _solve_params(rtol, restart, maxit)
+    rc = load().fde_solve(op.h, prec.h if prec is not None else None, nrhs, _dptr(G2), G2.stride(0),
+                          _dptr(X), X.stride(0), C.byref(p), info)
+    if rc != A.FDE_ENOCONV or raise_on_noconv:
+        check(rc)
+    infos = [dict(iters=i.iters, relres=i.relres, status=i.status) for i in info]
+    return X.view_as(G), infos
+
+
+def solve_batched(ctx: Context, ops: Sequence[Operator], Gs: Sequence[torch.Tensor],
+                  precs: Optional[Sequence[Optional[HLU]]] = None, rtol: float = 1e-10,
+                  restart: int = 30, maxit: int = 500, raise_on_noconv: bool = True,
+                  outs: Optional[Sequence[torch.Tensor]] = None):
+    """Solve several independent systems in lock-step launches. Returns (Xs, infos per system)."""
+    n = len(ops)
+    precs = precs if precs is not None else [None] * n
+    G2 = [_as_block(G, op.Nd, ctx.device) for G, op in zip(Gs, ops)]
+    Xs = [torch.empty_like(g) for g in G2] if outs is None else [_as_block(x, op.Nd, ctx.device)
+                                                                 for x, op in zip(outs, ops)]
+    nr = (C.c_int * n)(*[g.shape[0] for g in G2])
+    ldg = (C.c_int * n)(*[g.stride(0) for g in G2])
+    ldx = (C.c_int * n)(*[x.stride(0) for x in Xs])
+    op_h = (C.c_void_p * n)(*[o.h.value for o in ops])
+    pr_h = (C.c_void_p * n)(*[(p.h.value if p is not None else None) for p in precs])
+    g_p = (C.c_void_p * n)(*[g.data_ptr() for g in G2])
+    x_p = (C.c_void_p * n)(*[x.data_ptr() for x in Xs])
+    tot = sum(g.shape[0] for g in G2)
+    info = (A.SolveInfo * tot)()
+    p = _solve_params(rtol, restart, maxit)
+    rc = load().fde_solve_batched(ctx.h, n, op_h, pr_h, nr, g_p, ldg, x_p, ldx, C.byref(p), info)
+    if rc != A.FDE_ENOCONV or raise_on_noconv:
+        check(rc)
+    out, k = [], 0
+    for g in G2:
+        out.append([dict(iters=info[k + j].iters, relres=info[k + j].relres, status=info[k + j].status)
+                    for j in range(g.shape[0])])
+        k += g.shape[0]
+    return [x.view_as(g0) for x, g0 in zip(Xs, Gs)], out
