@@ -1,6 +1,7 @@
 """ctypes declarations of the C ABI in include/fde.h (argument marshalling only)."""
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 
@@ -81,6 +82,21 @@ SIGNATURES = {
 }
 
 _lib = None
+_shutting_down = False
+
+
+def _mark_shutdown():
+    global _shutting_down
+    _shutting_down = True
+
+
+# Finalisers that run while the interpreter exits must not call into the HIP
+# runtime (it may already be tearing down); the process releases those handles.
+atexit.register(_mark_shutdown)
+
+
+def shutting_down() -> bool:
+    return _shutting_down
 
 
 def load():

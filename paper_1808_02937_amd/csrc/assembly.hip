@@ -17,6 +17,7 @@
 #include <cmath>
 
 #include "fde_internal.h"
+#include "sem_device.h"
 
 namespace fde {
 
@@ -330,73 +331,12 @@ size_t moments_smem(int P) {
 }
 
 // ---------------------------------------------------------------- dense A
-// A[i][j] (paper order) = rho M + theta D^T K D + (1-theta) D^T K^T D
-__device__ inline void dof_elems(int i, int N, int P, const double* h, int* ne, int* el, int* md,
-                                 double* cf) {
-    const int nb = N * (P - 1);
-    if (i < nb) {
-        const int e = i / (P - 1), p = i % (P - 1) + 1;
-        *ne = 1;
-        el[0] = e;
-        md[0] = p;
-        cf[0] = -(2.0 * p + 1.0) * 2.0 / h[e];
-    } else {
-        const int j = i - nb + 1;  // node 1..N-1
-        *ne = 2;
-        el[0] = j - 1;
-        md[0] = 0;
-        cf[0] = 1.0 / h[j - 1];
-        el[1] = j;
-        md[1] = 0;
-        cf[1] = -1.0 / h[j];
-    }
-}
-
-__device__ inline double mom_get(const double* mom, const double* gen, bool toep, int P, int e,
-                                 int f, int m, int n, const double* h, double alpha) {
-    // K^{ef}_{mn}, f <= e
-    if (!toep) return mom[(tri(e) + f) * P * P + m * P + n];
-    const double s = pow(0.5 * h[e], 2.0 - alpha) * 0.5 * h[f];
-    return s * gen[(int64_t)(e - f) * P * P + m * P + n];
-}
-
-__global__ void k_dense_matrix(int N, int P, double alpha, double theta, double rho,
-                               const double* __restrict__ h, const double* __restrict__ mom,
-                               const double* __restrict__ gen, int toep,
-                               const double* __restrict__ lmass, double* __restrict__ A, int lda) {
-    const int Nd = N * P - 1;
+__global__ void k_dense_matrix(SemDev s, double* __restrict__ A, int lda) {
+    const int Nd = s.N * s.P - 1;
     const int i = blockIdx.y;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Nd || j >= Nd) return;
-    int ni, ei[2], mi[2], nj, ej[2], mj[2];
-    double ci[2], cj[2];
-    dof_elems(i, N, P, h, &ni, ei, mi, ci);
-    dof_elems(j, N, P, h, &nj, ej, mj, cj);
-    double s = 0.0;
-    for (int a = 0; a < ni; ++a)
-        for (int b = 0; b < nj; ++b) {
-            const int e = ei[a], f = ej[b];
-            if (f <= e) s += theta * ci[a] * cj[b] * mom_get(mom, gen, toep, P, e, f, mi[a], mj[b], h, alpha);
-            if (e <= f) s += (1.0 - theta) * ci[a] * cj[b] * mom_get(mom, gen, toep, P, f, e, mj[b], mi[a], h, alpha);
-        }
-    // mass: local basis index of dof i on element e: 0 left hat, 1 right hat, 1+p bubble
-    if (rho != 0.0) {
-        const int nb = N * (P - 1);
-        for (int a = 0; a < ni; ++a) {
-            const int e = ei[a];
-            int li;
-            if (i < nb) li = 1 + (i % (P - 1)) + 1;
-            else li = (e == i - nb) ? 1 : 0;   // node j = i-nb+1: right hat of e=j-1, left hat of e=j
-            for (int b = 0; b < nj; ++b) {
-                if (ej[b] != e) continue;
-                int lj;
-                if (j < nb) lj = 1 + (j % (P - 1)) + 1;
-                else lj = (e == j - nb) ? 1 : 0;
-                s += rho * 0.5 * h[e] * lmass[li * (P + 1) + lj];
-            }
-        }
-    }
-    A[(int64_t)j * lda + i] = s;
+    A[(int64_t)j * lda + i] = sem_entry(s, i, j);
 }
 
 // ---------------------------------------------------------------- load vector
@@ -450,9 +390,7 @@ void launch_pair_moments_list(Op* op, int npairs, const int* d_e, const int* d_f
 void launch_dense_matrix(Op* op, double* A, int lda) {
     const int Nd = op->Nd;
     dim3 grid(ceil_div(Nd, 128), Nd);
-    hipLaunchKernelGGL(k_dense_matrix, grid, dim3(128), 0, op->ctx->stream, op->N, op->P, op->alpha,
-                       op->theta, op->rho, op->d_h.p, op->d_mom.p, op->d_gen.p, op->toeplitz ? 1 : 0,
-                       op->d_lmass.p, A, lda);
+    hipLaunchKernelGGL(k_dense_matrix, grid, dim3(128), 0, op->ctx->stream, sem_dev(op), A, lda);
     FDE_LAUNCH_CHECK();
 }
 

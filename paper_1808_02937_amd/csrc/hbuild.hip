@@ -1,0 +1,150 @@
+// H-matrix construction on the device (Section 3), FP64.
+//
+// Dense blocks hold the exact entries of A = rho M + S (text after eq.
+// (approxmat)); low-rank blocks hold the factors of the truncated Taylor
+// expansion of (t-s)^{1-alpha} (eq. (eqn:Lexpan)):
+//   Q_{i,nu} = gamma0 int h_nu(t) phi_i'(t) dt,   W_{j,nu} = int g_nu(s) phi_j'(s) ds
+// (Section 3.2), each integral a Gauss-Legendre sum over the one or two
+// elements supporting phi_i. Powers are normalised by the expansion
+// cluster's radius r, (s - s0)^nu -> ((s - s0)/r)^nu with r^nu moved to the
+// other factor, so both factors stay O(1) in FP32.
+#include "hbuild.h"
+#include "sem_device.h"
+
+namespace fde {
+
+namespace {
+
+__global__ void k_hbuild_dense(SemDev s, const DenseBlkDev* __restrict__ blks, const int* __restrict__ h2p,
+                               double* __restrict__ arena) {
+    const DenseBlkDev b = blks[blockIdx.x];
+    for (int q = threadIdx.x; q < b.m * b.n; q += blockDim.x) {
+        const int i = q % b.m, j = q / b.m;
+        arena[b.off + q] = sem_entry(s, h2p[b.r0 + i], h2p[b.c0 + j]);
+    }
+}
+
+__global__ void k_hbuild_factors(int P, int R, double alpha, const double* __restrict__ x,
+                                 const double* __restrict__ h, const double* __restrict__ gl,
+                                 const FacSideDev* __restrict__ sides, double* __restrict__ arena) {
+    const FacSideDev f = sides[blockIdx.x];
+    const int nq = f.sing ? min(kMaxGL, P + 24) : min(kMaxGL, (R + P) / 2 + 2);
+    const int off_n = nq * (nq - 1) / 2;
+    const int wbase = kMaxGL * (kMaxGL + 1) / 2;
+    for (int q = threadIdx.x; q < f.rows * R; q += blockDim.x) {
+        const int i = q % f.rows, nu = q / f.rows;
+        double val = 0.0;
+        if (f.mult != 0.0) {
+            const int d = f.d0 + i;
+            const int e = d / P, l = d % P;
+            double coef = 1.0;
+            if (f.sing) {
+                for (int k = 1; k <= nu; ++k) coef *= (alpha + k - 2.0) / k;
+                if (f.alt && (nu & 1)) coef = -coef;
+                coef *= pow(f.r, (double)nu);
+            }
+            int ne, el[2], mm[2];
+            double cf[2];
+            if (l < P - 1) {
+                ne = 1;
+                el[0] = e;
+                mm[0] = l + 1;
+                cf[0] = -(2.0 * (l + 1) + 1.0) * 2.0 / h[e];
+            } else {
+                ne = 2;
+                el[0] = e;
+                mm[0] = 0;
+                cf[0] = 1.0 / h[e];
+                el[1] = e + 1;
+                mm[1] = 0;
+                cf[1] = -1.0 / h[e + 1];
+            }
+            for (int a = 0; a < ne; ++a) {
+                const int ee = el[a];
+                const double xl = x[ee], he = h[ee];
+                double s = 0.0;
+                for (int k = 0; k < nq; ++k) {
+                    const double xr = gl[off_n + k], w = gl[wbase + off_n + k];
+                    const double xx = xl + 0.5 * he * (1.0 + xr);
+                    const double F = f.sing ? pow(f.sgn * (xx - f.c), 1.0 - alpha - nu)
+                                            : pow((xx - f.c) / f.r, (double)nu);
+                    s += w * F * legendre_at(mm[a], xr);
+                }
+                val += cf[a] * 0.5 * he * s;
+            }
+            val *= f.mult * coef;
+        }
+        arena[f.off + i + (int64_t)nu * f.rows] = val;
+    }
+}
+
+template <class S, class D>
+__global__ void k_segcopy(const S* __restrict__ src, D* __restrict__ dst, const SegDev* __restrict__ segs) {
+    const SegDev sg = segs[blockIdx.x];
+    for (int64_t q = threadIdx.x; q < sg.len; q += blockDim.x) dst[sg.dst + q] = (D)src[sg.src + q];
+}
+
+template <class T>
+__global__ void k_to_dense(const T* __restrict__ arena, const int* __restrict__ ranks,
+                           const LeafDev* __restrict__ leaves, const int* __restrict__ perm, int unit_lower,
+                           double* __restrict__ out, int ld) {
+    const LeafDev b = leaves[blockIdx.x];
+    const int k = b.slot >= 0 ? ranks[b.slot] : 0;
+    for (int q = threadIdx.x; q < b.m * b.n; q += blockDim.x) {
+        const int i = q % b.m, j = q / b.m;
+        double v;
+        if (b.lowrank) {
+            v = 0.0;
+            for (int l = 0; l < k; ++l)
+                v += (double)arena[b.uoff + i + (int64_t)l * b.m] * (double)arena[b.voff + j + (int64_t)l * b.n];
+        } else {
+            v = (double)arena[b.off + q];
+        }
+        int r = b.r0 + i, c = b.c0 + j;
+        (void)unit_lower;
+        if (perm) {
+            r = perm[r];
+            c = perm[c];
+        }
+        out[(int64_t)c * ld + r] = v;
+    }
+}
+
+}  // namespace
+
+void launch_hbuild_dense(Op* op, int nblk, const DenseBlkDev* d_blks, const int* d_h2p, double* arena) {
+    if (nblk == 0) return;
+    hipLaunchKernelGGL(k_hbuild_dense, dim3(nblk), dim3(256), 0, op->ctx->stream, sem_dev(op), d_blks, d_h2p,
+                       arena);
+    FDE_LAUNCH_CHECK();
+}
+
+void launch_hbuild_factors(Op* op, int R, int nsides, const FacSideDev* d_sides, double* arena) {
+    if (nsides == 0) return;
+    hipLaunchKernelGGL(k_hbuild_factors, dim3(nsides), dim3(256), 0, op->ctx->stream, op->P, R, op->alpha,
+                       op->d_x.p, op->d_h.p, op->ctx->gl.p, d_sides, arena);
+    FDE_LAUNCH_CHECK();
+}
+
+template <class S, class D>
+void launch_segcopy(hipStream_t st, int nseg, const SegDev* d_segs, const S* src, D* dst) {
+    if (nseg == 0) return;
+    hipLaunchKernelGGL((k_segcopy<S, D>), dim3(nseg), dim3(256), 0, st, src, dst, d_segs);
+    FDE_LAUNCH_CHECK();
+}
+template void launch_segcopy<double, double>(hipStream_t, int, const SegDev*, const double*, double*);
+template void launch_segcopy<double, float>(hipStream_t, int, const SegDev*, const double*, float*);
+
+template <class T>
+void launch_to_dense(hipStream_t st, int nleaf, const LeafDev* d_leaves, const T* arena, const int* ranks,
+                     const int* perm, double* out, int ld) {
+    if (nleaf == 0) return;
+    hipLaunchKernelGGL((k_to_dense<T>), dim3(nleaf), dim3(256), 0, st, arena, ranks, d_leaves, perm, 0, out, ld);
+    FDE_LAUNCH_CHECK();
+}
+template void launch_to_dense<double>(hipStream_t, int, const LeafDev*, const double*, const int*, const int*,
+                                      double*, int);
+template void launch_to_dense<float>(hipStream_t, int, const LeafDev*, const float*, const int*, const int*,
+                                     double*, int);
+
+}  // namespace fde

@@ -1,0 +1,43 @@
+// Device interpreter of H-arithmetic programs (H-LU and H-substitutions).
+#pragma once
+
+#include "hmatrix.h"
+
+namespace fde {
+
+constexpr int kInterpThreads = 256;
+constexpr int kMaxKp = 256;   // widest [U, X] recompressed in one OP_LRSUB
+
+template <class T>
+struct Inst {
+    const OpRec* ops;
+    int nops;
+    T* arena;                 // factors
+    T* work;                  // temporaries
+    T* rhs;                   // right-hand sides (Nd x nrhs, ld Nd) of an H-solve
+    int* ranks;               // rank per low-rank block
+    const LRBlockDev* lr;     // low-rank block table
+    T* scr;                   // recompression scratch (T)
+    double* scrd;             // recompression scratch (FP64 core)
+    int64_t mrmax;            // scratch row capacity
+    int kpmax;                // scratch k' capacity
+    const int* h2p;
+    int Nd;
+    const double* B;          // H-solve input (paper order, FP64); B + step * bstep at step `step`
+    int ldb;
+    double* X;                // H-solve output; X + step * xstep
+    int ldx;
+    int64_t bstep, xstep;
+    int nrhs;
+    double tol;
+    int kmax;
+    double pivot_floor;
+    int* status;              // [0] status code, [1] op index of a breakdown
+};
+
+template <class T>
+void launch_interp(hipStream_t st, int ninst, const Inst<T>* d_insts, int step = 0);
+template <class T>
+void launch_interp_one(hipStream_t st, const Inst<T>& d);
+
+}  // namespace fde

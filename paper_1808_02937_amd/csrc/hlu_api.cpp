@@ -1,0 +1,337 @@
+// C entry points of the H-matrix (Section 3) and the H-LU / H-solves (Section 4.1).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "hbuild.h"
+#include "hlu.h"
+
+using namespace fde;
+
+
+
+
+namespace {
+
+std::vector<LeafDev> leaf_table(const HTree& t) {
+    std::vector<LeafDev> v;
+    for (int b : t.dense_blocks) {
+        const Block& B = t.bl[b];
+        LeafDev l{};
+        l.off = B.off;
+        l.r0 = t.cl[B.tau].d0;
+        l.c0 = t.cl[B.sigma].d0;
+        l.m = t.cl[B.tau].size();
+        l.n = t.cl[B.sigma].size();
+        l.lowrank = 0;
+        l.slot = -1;
+        v.push_back(l);
+    }
+    for (int b : t.lr_blocks) {
+        const Block& B = t.bl[b];
+        LeafDev l{};
+        l.uoff = B.uoff;
+        l.voff = B.voff;
+        l.r0 = t.cl[B.tau].d0;
+        l.c0 = t.cl[B.sigma].d0;
+        l.m = t.cl[B.tau].size();
+        l.n = t.cl[B.sigma].size();
+        l.lowrank = 1;
+        l.slot = B.slot;
+        v.push_back(l);
+    }
+    return v;
+}
+
+template <class V>
+void upload_vec(Ctx* c, DevBuf<V>& buf, const std::vector<V>& v) {
+    buf.alloc(c, v.size());
+    if (!v.empty()) FDE_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, c->stream));
+}
+
+void build_hmat(fde_hmat* hm, Op* op, const fde_hparams* prm) {
+    const int R = prm ? prm->R : 8;
+    const double lam = prm ? prm->lambda : 1.0;
+    const int leaf = prm ? prm->leaf_elems : 8;
+    if (R < 1 || R > 64) fail(FDE_EINVAL, "R must be in [1, 64] (got %d)", R);
+    if (!(lam > 0.0) || !std::isfinite(lam)) fail(FDE_EINVAL, "lambda must be > 0 (got %g)", lam);
+    if (leaf < 2) fail(FDE_EINVAL, "leaf_elems must be >= 2 (got %d)", leaf);
+    Ctx* c = op->ctx;
+    HTree& t = hm->t;
+    t.op = op;
+    t.R = R;
+    t.leaf = leaf;
+    t.lambda = lam;
+    t.kmax = R;
+    build_trees(&t);
+    hm->d_arena.alloc(c, t.arena_elems);
+    upload_vec(c, hm->d_h2p, t.h2p);
+    // dense near blocks: exact entries of A
+    std::vector<DenseBlkDev> dbl;
+    for (int b : t.dense_blocks) {
+        const Block& B = t.bl[b];
+        dbl.push_back(DenseBlkDev{B.off, t.cl[B.tau].d0, t.cl[B.sigma].d0, t.cl[B.tau].size(), t.cl[B.sigma].size()});
+    }
+    DevBuf<DenseBlkDev> d_dbl;
+    upload_vec(c, d_dbl, dbl);
+    launch_hbuild_dense(op, (int)dbl.size(), d_dbl.p, hm->d_h2p.p, hm->d_arena.p);
+    // low-rank factors from the Taylor expansion (Lemma; Section 3.2)
+    std::vector<FacSideDev> sides;
+    hm->init_rank.assign(t.lr_blocks.size(), R);
+    for (size_t k = 0; k < t.lr_blocks.size(); ++k) {
+        const Block& B = t.bl[t.lr_blocks[k]];
+        const Cluster& Tc = t.cl[B.lower ? B.tau : B.sigma];   // t-cluster (right)
+        const Cluster& Sc = t.cl[B.lower ? B.sigma : B.tau];   // s-cluster (left)
+        const double rT = 0.5 * (Tc.hi - Tc.lo), rS = 0.5 * (Sc.hi - Sc.lo);
+        FacSideDev ts{}, ss{};
+        if (rS <= rT) {   // expand in s about the centre of the s-cluster
+            const double s0 = 0.5 * (Sc.lo + Sc.hi);
+            ts = FacSideDev{0, Tc.d0, Tc.size(), 1, 0, s0, rS, 1.0, op->gamma0};
+            ss = FacSideDev{0, Sc.d0, Sc.size(), 0, 0, s0, rS, 1.0, 1.0};
+        } else {          // expand in t about the centre of the t-cluster
+            const double t0 = 0.5 * (Tc.lo + Tc.hi);
+            ts = FacSideDev{0, Tc.d0, Tc.size(), 0, 0, t0, rT, 1.0, 1.0};
+            ss = FacSideDev{0, Sc.d0, Sc.size(), 1, 1, t0, rT, -1.0, op->gamma0};
+        }
+        FacSideDev u = B.lower ? ts : ss, v = B.lower ? ss : ts;
+        const double w = B.lower ? op->theta : 1.0 - op->theta;
+        u.mult *= w;
+        u.off = B.uoff;
+        v.off = B.voff;
+        if (w == 0.0) {
+            hm->init_rank[k] = 0;
+            v.mult = 0.0;
+        }
+        sides.push_back(u);
+        sides.push_back(v);
+    }
+    DevBuf<FacSideDev> d_sides;
+    upload_vec(c, d_sides, sides);
+    launch_hbuild_factors(op, R, (int)sides.size(), d_sides.p, hm->d_arena.p);
+    upload_vec(c, hm->d_ranks, hm->init_rank);
+    FDE_HIP(hipStreamSynchronize(c->stream));
+}
+
+template <class T>
+void factor_run(HLUObj* f) {
+    Ctx* c = f->op->ctx;
+    Inst<T> d = f->inst<T>(false, 0, nullptr, 0, nullptr, 0);
+    launch_interp_one<T>(c->stream, d);
+    int st[2] = {0, 0};
+    FDE_HIP(hipMemcpyAsync(st, f->status.p, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    FDE_HIP(hipStreamSynchronize(c->stream));
+    if (st[0] == FDE_EBREAKDOWN) fail(FDE_EBREAKDOWN, "H-LU breakdown: leaf pivot below the floor (op %d)", st[1]);
+    if (st[0] != 0) fail(FDE_EDEVICE, "H-LU status %d", st[0]);
+}
+
+void factor(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
+    Op* op = hm->t.op;
+    Ctx* c = op->ctx;
+    f->hm = hm;
+    f->op = op;
+    f->tol = prm ? prm->tol : 1e-3;
+    f->prec = prm ? prm->precision : FDE_FP32;
+    f->pivot_floor = prm ? prm->pivot_floor : 1e-14;
+    const int cap = prm && prm->rank_cap > 0 ? prm->rank_cap : hm->t.R;
+    if (!(f->tol >= 0.0) || !std::isfinite(f->tol)) fail(FDE_EINVAL, "tol must be >= 0");
+    if (f->prec != FDE_FP32 && f->prec != FDE_FP64) fail(FDE_EINVAL, "precision must be FDE_FP32 or FDE_FP64");
+    if (!(f->pivot_floor >= 0.0)) fail(FDE_EINVAL, "pivot_floor must be >= 0");
+    f->kmax = std::max(cap, hm->t.R);
+    f->t = hm->t;
+    assign_storage(&f->t, f->kmax);
+    f->esz = f->prec == FDE_FP64 ? 8 : 4;
+    gen_hlu(f->t, f->lu);
+    gen_hsolve(f->t, f->sv);
+    f->kpmax = lrsub_kprime_max(f->t, f->lu);
+    if (f->kpmax > kMaxKp)
+        fail(FDE_EUNSUPPORTED, "H-LU needs recompression of width %d > %d", f->kpmax, kMaxKp);
+    lrsub_scratch(f->t, f->lu, &f->scr_t, &f->scr_d);
+    validate_program(f->t, f->lu, f->t.arena_elems, f->lu.work_elems, 1, false);
+    validate_program(f->t, f->sv, f->t.arena_elems, f->sv.work_elems, 1, true);
+    validate_program(f->t, f->sv, f->t.arena_elems, f->sv.work_elems, 64, true);
+    f->arena.alloc(c, f->t.arena_elems * f->esz);
+    f->work_lu.alloc(c, std::max<int64_t>(f->lu.work_elems, 1) * f->esz);
+    f->scr.alloc(c, f->scr_t * f->esz);
+    f->scrd.alloc(c, f->scr_d);
+    f->status.alloc(c, 2);
+    FDE_HIP(hipMemsetAsync(f->status.p, 0, 2 * sizeof(int), c->stream));
+    upload_vec(c, f->h2p, f->t.h2p);
+    upload_vec(c, f->ranks, hm->init_rank);
+    upload_vec(c, f->ops_lu, f->lu.ops);
+    upload_vec(c, f->ops_sv, f->sv.ops);
+    std::vector<LRBlockDev> lrt;
+    for (int b : f->t.lr_blocks) {
+        const Block& B = f->t.bl[b];
+        lrt.push_back(LRBlockDev{B.uoff, B.voff, f->t.cl[B.tau].size(), f->t.cl[B.sigma].size(), B.slot, 0});
+    }
+    upload_vec(c, f->lr, lrt);
+    // copy A~ into the factor layout, converting to the factor precision
+    std::vector<SegDev> segs;
+    for (int b : f->t.dense_blocks) {
+        const Block &S = hm->t.bl[b], &D = f->t.bl[b];
+        segs.push_back(SegDev{S.off, D.off, (int64_t)f->t.cl[S.tau].size() * f->t.cl[S.sigma].size()});
+    }
+    for (int b : f->t.lr_blocks) {
+        const Block &S = hm->t.bl[b], &D = f->t.bl[b];
+        const int R = hm->t.R;
+        segs.push_back(SegDev{S.uoff, D.uoff, (int64_t)f->t.cl[S.tau].size() * R});
+        segs.push_back(SegDev{S.voff, D.voff, (int64_t)f->t.cl[S.sigma].size() * R});
+    }
+    DevBuf<SegDev> d_segs;
+    upload_vec(c, d_segs, segs);
+    if (f->prec == FDE_FP64) {
+        launch_segcopy<double, double>(c->stream, (int)segs.size(), d_segs.p, hm->d_arena.p,
+                                       reinterpret_cast<double*>(f->arena.p));
+        factor_run<double>(f);
+    } else {
+        launch_segcopy<double, float>(c->stream, (int)segs.size(), d_segs.p, hm->d_arena.p,
+                                      reinterpret_cast<float*>(f->arena.p));
+        factor_run<float>(f);
+    }
+}
+
+}  // namespace
+
+namespace fde {
+
+void hlu_prepare_solve(HLUObj* f, int nrhs) {
+    if (nrhs > f->sv_nrhs_cap) {
+        Ctx* c = f->op->ctx;
+        const int64_t cap = std::max<int64_t>(nrhs, 1);
+        f->sv_rhs.alloc(c, (int64_t)f->op->Nd * cap * f->esz);
+        f->sv_work.alloc(c, std::max<int64_t>(f->sv.work_elems, 1) * cap * f->esz);
+        f->sv_nrhs_cap = cap;
+    }
+}
+
+void hlu_solve(HLUObj* f, int nrhs, const double* B, int ldb, double* X, int ldx) {
+    hlu_prepare_solve(f, nrhs);
+    hipStream_t st = f->op->ctx->stream;
+    if (f->prec == FDE_FP64)
+        launch_interp_one<double>(st, f->inst<double>(true, nrhs, B, ldb, X, ldx));
+    else
+        launch_interp_one<float>(st, f->inst<float>(true, nrhs, B, ldb, X, ldx));
+}
+
+}  // namespace fde
+
+#define FDE_API_BEGIN try {
+#define FDE_API_END                                   \
+    }                                                 \
+    catch (const fde::Error& e) {                     \
+        fde::set_error("%s", e.msg.c_str());          \
+        return e.code;                                \
+    }                                                 \
+    catch (const std::bad_alloc&) {                   \
+        fde::set_error("host allocation failed");     \
+        return FDE_ENOMEM;                            \
+    }                                                 \
+    catch (...) {                                     \
+        fde::set_error("unexpected internal error");  \
+        return FDE_EDEVICE;                           \
+    }                                                 \
+    return FDE_OK;
+
+extern "C" {
+
+int fde_build_hmatrix(fde_op* op, const fde_hparams* prm, fde_hmat** out) {
+    FDE_API_BEGIN
+    if (!op || !out) fail(FDE_EINVAL, "null argument");
+    *out = nullptr;
+    fde_hmat* hm = new fde_hmat();
+    try {
+        build_hmat(hm, op, prm);
+    } catch (...) {
+        delete hm;
+        throw;
+    }
+    *out = hm;
+    FDE_API_END
+}
+
+void fde_hmat_destroy(fde_hmat* hm) {
+    if (!hm) return;
+    (void)hipDeviceSynchronize();
+    delete hm;
+}
+
+int fde_hmat_counts(const fde_hmat* hm, int* nd, int* nr) {
+    FDE_API_BEGIN
+    if (!hm) fail(FDE_EINVAL, "null H-matrix");
+    if (nd) *nd = (int)hm->t.dense_blocks.size();
+    if (nr) *nr = (int)hm->t.lr_blocks.size();
+    FDE_API_END
+}
+
+int fde_hmat_to_dense(fde_hmat* hm, double* out, int ld) {
+    FDE_API_BEGIN
+    if (!hm || !out || ld < hm->t.op->Nd) fail(FDE_EINVAL, "bad arguments");
+    Ctx* c = hm->t.op->ctx;
+    std::vector<LeafDev> lv = leaf_table(hm->t);
+    DevBuf<LeafDev> d_lv;
+    upload_vec(c, d_lv, lv);
+    launch_to_dense<double>(c->stream, (int)lv.size(), d_lv.p, hm->d_arena.p, hm->d_ranks.p, hm->d_h2p.p, out, ld);
+    FDE_HIP(hipStreamSynchronize(c->stream));
+    FDE_API_END
+}
+
+int fde_hlu_factor(fde_hmat* hm, const fde_hlu_params* prm, fde_hlu** out) {
+    FDE_API_BEGIN
+    if (!hm || !out) fail(FDE_EINVAL, "null argument");
+    *out = nullptr;
+    fde_hlu* f = new fde_hlu();
+    try {
+        factor(f, hm, prm);
+    } catch (...) {
+        delete f;
+        throw;
+    }
+    *out = f;
+    FDE_API_END
+}
+
+void fde_hlu_destroy(fde_hlu* f) {
+    if (!f) return;
+    (void)hipDeviceSynchronize();
+    delete f;
+}
+
+int fde_hlu_to_dense(fde_hlu* f, double* out, int ld, int* h2p) {
+    FDE_API_BEGIN
+    if (!f || !out || ld < f->op->Nd) fail(FDE_EINVAL, "bad arguments");
+    Ctx* c = f->op->ctx;
+    std::vector<LeafDev> lv = leaf_table(f->t);
+    DevBuf<LeafDev> d_lv;
+    upload_vec(c, d_lv, lv);
+    if (f->prec == FDE_FP64)
+        launch_to_dense<double>(c->stream, (int)lv.size(), d_lv.p, reinterpret_cast<double*>(f->arena.p), f->ranks.p,
+                                nullptr, out, ld);
+    else
+        launch_to_dense<float>(c->stream, (int)lv.size(), d_lv.p, reinterpret_cast<float*>(f->arena.p), f->ranks.p,
+                               nullptr, out, ld);
+    FDE_HIP(hipStreamSynchronize(c->stream));
+    if (h2p) std::memcpy(h2p, f->t.h2p.data(), f->t.h2p.size() * sizeof(int));
+    FDE_API_END
+}
+
+int fde_hlu_max_rank(fde_hlu* f, int* mr) {
+    FDE_API_BEGIN
+    if (!f || !mr) fail(FDE_EINVAL, "bad arguments");
+    std::vector<int> r(f->t.lr_blocks.size());
+    if (!r.empty()) {
+        FDE_HIP(hipMemcpyAsync(r.data(), f->ranks.p, r.size() * sizeof(int), hipMemcpyDeviceToHost, f->op->ctx->stream));
+        FDE_HIP(hipStreamSynchronize(f->op->ctx->stream));
+    }
+    *mr = r.empty() ? 0 : *std::max_element(r.begin(), r.end());
+    FDE_API_END
+}
+
+int fde_hlu_solve(fde_hlu* f, int nrhs, const double* B, int ldb, double* X, int ldx) {
+    FDE_API_BEGIN
+    if (!f || nrhs < 0 || (nrhs && (!B || !X)) || ldb < f->op->Nd || ldx < f->op->Nd) fail(FDE_EINVAL, "bad arguments");
+    if (nrhs == 0) return FDE_OK;
+    hlu_solve(f, nrhs, B, ldb, X, ldx);
+    FDE_API_END
+}
+
+}  // extern "C"

@@ -23,7 +23,7 @@ namespace fde {
 
 namespace {
 
-int make_cluster(HMat* hm, int e0, int e1, int level, int depth) {
+int make_cluster(HTree* hm, int e0, int e1, int level, int depth) {
     const Op* op = hm->op;
     const int N = op->N, P = op->P;
     Cluster c;
@@ -52,7 +52,7 @@ bool admissible(const Cluster& t, const Cluster& s, double lam) {
     return dist > 0.0 && diam <= lam * dist;
 }
 
-int make_block(HMat* hm, int t, int s) {
+int make_block(HTree* hm, int t, int s) {
     Block b;
     b.tau = t;
     b.sigma = s;
@@ -79,7 +79,7 @@ int make_block(HMat* hm, int t, int s) {
     return id;
 }
 
-void collect(HMat* hm, int b) {
+void collect(HTree* hm, int b) {
     Block& B = hm->bl[b];
     if (B.kind == kHier) {
         for (int k = 0; k < 4; ++k) collect(hm, B.child[k]);
@@ -93,7 +93,7 @@ void collect(HMat* hm, int b) {
 
 }  // namespace
 
-void build_trees(HMat* hm) {
+void build_trees(HTree* hm) {
     const Op* op = hm->op;
     const int N = op->N, P = op->P;
     // internal order
@@ -110,7 +110,12 @@ void build_trees(HMat* hm) {
     hm->dense_blocks.clear();
     hm->lr_blocks.clear();
     collect(hm, hm->root);
-    // storage: dense blocks, then U and V of low-rank blocks with kmax columns
+    assign_storage(hm, hm->kmax);
+}
+
+// storage: dense blocks, then U and V of the low-rank blocks with kmax columns each
+void assign_storage(HTree* hm, int kmax) {
+    hm->kmax = kmax;
     int64_t off = 0;
     hm->max_lr_rows = 0;
     for (int b : hm->dense_blocks) {

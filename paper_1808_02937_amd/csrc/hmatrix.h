@@ -50,7 +50,7 @@ struct LowRankDesc {
 
 // --------------------------------------------------------------- program
 enum OpCode { OP_GETRF = 1, OP_TRSM = 2, OP_GEMM = 3, OP_LRSUB = 4, OP_ZERO = 5, OP_LOAD = 6, OP_STORE = 7 };
-enum Base { B_ARENA = 0, B_WORK = 1 };
+enum Base { B_ARENA = 0, B_WORK = 1, B_RHS = 2, B_WORK_NRHS = 3 };
 
 struct View {
     int base;          // B_ARENA (factors) or B_WORK (right-hand sides and temporaries)
@@ -74,11 +74,13 @@ struct LRBlockDev {    // device table for OP_LRSUB
 
 struct Program {
     std::vector<OpRec> ops;
-    int64_t work_elems = 0;   // temporaries in the work area (beyond the right-hand sides)
+    int64_t work_elems = 0;   // temporaries (H-solve: in rows, times the number of right-hand sides)
+    int kx_max = 0;           // widest update X Y^T recompressed into a low-rank block
 };
 
 // --------------------------------------------------------------- H-matrix
-struct HMat {
+// host-side trees and storage layout (copyable: each factorisation lays out its own copy)
+struct HTree {
     Op* op = nullptr;
     int R = 8, leaf = 8;
     double lambda = 1.0;
@@ -92,21 +94,26 @@ struct HMat {
     int64_t arena_elems = 0;
     int nslots = 0;
     int max_lr_rows = 0;           // largest m or n of a low-rank block
-    int max_inner = 0;             // largest inner dimension of a dense x dense product into a low-rank block
-    // FP64 copy of A~ on the device (built once; factorisations copy and convert it)
+};
+
+struct HMat {
+    HTree t;
+    std::vector<int> init_rank;    // rank of each low-rank block after the build (R or 0)
+    // FP64 copy of A~ on the device in the layout of t (kmax = R)
     DevBuf<double> d_arena;
-    DevBuf<int> d_ranks;           // initial ranks
-    DevBuf<LRBlockDev> d_lr;
     DevBuf<int> d_h2p;
 };
 
-void build_trees(HMat* hm);
+void build_trees(HTree* hm);
+void assign_storage(HTree* hm, int kmax);
 void build_hmatrix_device(HMat* hm);   // hbuild.hip
 
 // program generation (progs.cpp)
-void gen_hlu(const HMat& hm, Program& prog);
-void gen_hsolve(const HMat& hm, Program& prog);
-int64_t lrsub_scratch_elems(const HMat& hm);
-int lrsub_kprime_max(const HMat& hm);
+void gen_hlu(const HTree& hm, Program& prog);
+void gen_hsolve(const HTree& hm, Program& prog);
+int lrsub_kprime_max(const HTree& hm, const Program& lu);
+void lrsub_scratch(const HTree& hm, const Program& lu, int64_t* t_elems, int64_t* d_elems);
+void validate_program(const HTree& hm, const Program& prog, int64_t arena_elems, int64_t work_elems,
+                      int nrhs_max, bool solve);
 
 }  // namespace fde

@@ -1,0 +1,233 @@
+// Host driver of the batched, right-preconditioned FGMRES(m) (Section 4.2).
+//
+// The paper preconditions A X = G with the H-LU of A~ and iterates with
+// BiCGSTAB (eq. (precondsys)); here the preconditioner is applied on the right
+// inside flexible GMRES, because a mixed-precision H-solve is not an exactly
+// linear operator, and the iteration stops on the true FP64 residual
+// ||G - A X|| / ||G|| (recomputed with the full stiffness apply at the end of
+// every cycle), so the FP32 preconditioner never limits the final accuracy.
+//
+// Every system (one right-hand side of one operator) advances in lock-step:
+// each Arnoldi step is one batched H-solve launch, one stiffness apply per
+// operator and one fused CGS2/Givens launch; the host reads back one integer
+// (how many systems are still in their cycle) per step.
+#include <algorithm>
+#include <cstring>
+
+#include "hlu.h"
+#include "krylov.h"
+
+namespace fde {
+
+namespace {
+
+struct Group {
+    Op* op;
+    HLUObj* prec;
+    int nr;
+    const double* G;
+    int ldg;
+    double* X;
+    int ldx;
+    int sys0;
+    DevBuf<double> V, Z, W, R;
+    DevBuf<char> rhs, work;   // H-solve buffers of this group
+};
+
+template <class T>
+Inst<T> group_inst(Group& g, int m) {
+    Inst<T> d = g.prec->inst<T>(true, g.nr, g.V.p, g.op->Nd, g.Z.p, g.op->Nd);
+    d.work = reinterpret_cast<T*>(g.work.p);
+    d.rhs = reinterpret_cast<T*>(g.rhs.p);
+    d.bstep = (int64_t)g.op->Nd * g.nr;
+    d.xstep = (int64_t)g.op->Nd * g.nr;
+    (void)m;
+    return d;
+}
+
+void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nrhs, const double* const* G,
+         const int* ldg, double* const* X, const int* ldx, const fde_solve_params* prm, fde_solve_info* info,
+         int* rc_out) {
+    const int m = prm ? prm->restart : 30;
+    const int maxit = prm ? prm->maxit : 500;
+    const double rtol = prm ? prm->rtol : 1e-10;
+    const int method = prm ? prm->method : FDE_FGMRES;
+    if (method != FDE_FGMRES) fail(FDE_EINVAL, "unknown Krylov method %d", method);
+    if (m < 1 || m > kMaxRestart) fail(FDE_EINVAL, "restart must be in [1, %d] (got %d)", kMaxRestart, m);
+    if (maxit < 1) fail(FDE_EINVAL, "maxit must be >= 1");
+    if (!(rtol > 0.0)) fail(FDE_EINVAL, "rtol must be > 0");
+    hipStream_t st = c->stream;
+    std::vector<Group> groups(n);
+    int ns = 0;
+    for (int i = 0; i < n; ++i) {
+        Op* op = ops[i];
+        if (!op || op->ctx != c) fail(FDE_EINVAL, "system %d: operator missing or from another context", i);
+        if (nrhs[i] < 0 || (nrhs[i] > 0 && (!G[i] || !X[i])) || ldg[i] < op->Nd || ldx[i] < op->Nd)
+            fail(FDE_EINVAL, "system %d: bad right-hand side arguments", i);
+        HLUObj* f = precs ? precs[i] : nullptr;
+        if (f && f->op != op) fail(FDE_EINVAL, "system %d: preconditioner built for another operator", i);
+        Group& g = groups[i];
+        g.op = op;
+        g.prec = f;
+        g.nr = nrhs[i];
+        g.G = G[i];
+        g.ldg = ldg[i];
+        g.X = X[i];
+        g.ldx = ldx[i];
+        g.sys0 = ns;
+        ns += g.nr;
+    }
+    if (ns == 0) {
+        *rc_out = FDE_OK;
+        return;
+    }
+    std::vector<SysDev> sys;
+    std::vector<int> mask(ns, 0);
+    std::vector<Inst<float>> i32;
+    std::vector<Inst<double>> i64;
+    for (auto& g : groups) {
+        if (g.nr == 0) continue;
+        const int64_t bs = (int64_t)g.op->Nd * g.nr;
+        g.V.alloc(c, (m + 1) * bs);
+        g.Z.alloc(c, m * bs);
+        g.W.alloc(c, bs);
+        g.R.alloc(c, bs);
+        FDE_HIP(hipMemsetAsync(g.V.p, 0, g.V.bytes(), st));
+        FDE_HIP(hipMemsetAsync(g.Z.p, 0, g.Z.bytes(), st));
+        for (int k = 0; k < g.nr; ++k) {
+            SysDev s{};
+            s.V = g.V.p;
+            s.Z = g.Z.p;
+            s.W = g.W.p;
+            s.R = g.R.p;
+            s.G = g.G + (int64_t)k * g.ldg;
+            s.X = g.X + (int64_t)k * g.ldx;
+            s.bs = bs;
+            s.Nd = g.op->Nd;
+            s.c = k;
+            sys.push_back(s);
+            mask[g.sys0 + k] = g.prec ? 0 : 1;
+        }
+        if (g.prec) {
+            g.rhs.alloc(c, bs * g.prec->esz);
+            g.work.alloc(c, std::max<int64_t>(g.prec->sv.work_elems, 1) * g.nr * g.prec->esz);
+            if (g.prec->prec == FDE_FP64)
+                i64.push_back(group_inst<double>(g, m));
+            else
+                i32.push_back(group_inst<float>(g, m));
+        }
+    }
+    DevBuf<SysDev> d_sys;
+    DevBuf<SysState> d_ss;
+    DevBuf<int> d_mask, d_count;
+    DevBuf<Inst<float>> d_i32;
+    DevBuf<Inst<double>> d_i64;
+    d_sys.alloc(c, sys.size());
+    d_ss.alloc(c, ns);
+    d_mask.alloc(c, ns);
+    d_count.alloc(c, 1);
+    FDE_HIP(hipMemcpyAsync(d_sys.p, sys.data(), sys.size() * sizeof(SysDev), hipMemcpyHostToDevice, st));
+    FDE_HIP(hipMemcpyAsync(d_mask.p, mask.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+    if (!i32.empty()) {
+        d_i32.alloc(c, i32.size());
+        FDE_HIP(hipMemcpyAsync(d_i32.p, i32.data(), i32.size() * sizeof(Inst<float>), hipMemcpyHostToDevice, st));
+    }
+    if (!i64.empty()) {
+        d_i64.alloc(c, i64.size());
+        FDE_HIP(hipMemcpyAsync(d_i64.p, i64.data(), i64.size() * sizeof(Inst<double>), hipMemcpyHostToDevice, st));
+    }
+    const bool any_copy = std::any_of(mask.begin(), mask.end(), [](int v) { return v != 0; });
+    fg_gnorm(st, ns, d_sys.p, d_ss.p);
+    fg_zero_x(st, ns, d_sys.p);
+    std::vector<SysState> hs(ns);
+    bool first = true;
+    for (;;) {
+        fg_cycle_start(st, ns, d_sys.p, d_ss.p, first ? 1 : 0, maxit);
+        first = false;
+        for (int j = 0; j < m; ++j) {
+            if (any_copy) fg_copy_step(st, ns, d_sys.p, d_mask.p, j);
+            if (!i32.empty()) launch_interp<float>(st, (int)i32.size(), d_i32.p, j);
+            if (!i64.empty()) launch_interp<double>(st, (int)i64.size(), d_i64.p, j);
+            for (auto& g : groups)
+                if (g.nr) stiffness_apply(g.op, g.nr, g.Z.p + (int64_t)j * g.op->Nd * g.nr, g.op->Nd, g.W.p,
+                                          g.op->Nd, 0.0, 0.0, false);
+            fg_arnoldi(st, ns, d_sys.p, d_ss.p, j, m, rtol, maxit);
+            int active = 0;
+            fg_count_active(st, ns, d_ss.p, d_count.p);
+            FDE_HIP(hipMemcpyAsync(&active, d_count.p, sizeof(int), hipMemcpyDeviceToHost, st));
+            FDE_HIP(hipStreamSynchronize(st));
+            if (active == 0) break;
+        }
+        fg_update(st, ns, d_sys.p, d_ss.p);
+        for (auto& g : groups)
+            if (g.nr) stiffness_apply(g.op, g.nr, g.X, g.ldx, g.R.p, g.op->Nd, 0.0, 0.0, false);
+        fg_check(st, ns, d_sys.p, d_ss.p, rtol);
+        FDE_HIP(hipMemcpyAsync(hs.data(), d_ss.p, ns * sizeof(SysState), hipMemcpyDeviceToHost, st));
+        FDE_HIP(hipStreamSynchronize(st));
+        bool more = false;
+        for (const auto& s : hs)
+            if (!s.conv && s.status == 0 && s.iters < maxit) more = true;
+        if (!more) break;
+    }
+    int rc = FDE_OK;
+    for (int k = 0; k < ns; ++k) {
+        info[k].iters = hs[k].iters;
+        info[k].relres = hs[k].relres;
+        info[k].status = hs[k].conv ? FDE_OK : (hs[k].status ? FDE_EINVAL : FDE_ENOCONV);
+        if (!hs[k].conv) rc = FDE_ENOCONV;
+    }
+    *rc_out = rc;
+}
+
+}  // namespace
+
+}  // namespace fde
+
+using namespace fde;
+
+extern "C" {
+
+int fde_solve(fde_op* op, fde_hlu* prec, int nrhs, const double* G, int ldg, double* X, int ldx,
+              const fde_solve_params* prm, fde_solve_info* info) {
+    int rc = FDE_OK;
+    try {
+        if (!op || !info) fail(FDE_EINVAL, "null operator or info");
+        fde_op* ops[1] = {op};
+        fde_hlu* precs[1] = {prec};
+        const double* Gs[1] = {G};
+        double* Xs[1] = {X};
+        run(op->ctx, 1, ops, precs, &nrhs, Gs, &ldg, Xs, &ldx, prm, info, &rc);
+    } catch (const Error& e) {
+        set_error("%s", e.msg.c_str());
+        return e.code;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return FDE_EDEVICE;
+    }
+    if (rc == FDE_ENOCONV) set_error("FGMRES did not reach rtol within maxit for at least one right-hand side");
+    return rc;
+}
+
+int fde_solve_batched(fde_ctx* ctx, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nrhs,
+                      const double* const* G, const int* ldg, double* const* X, const int* ldx,
+                      const fde_solve_params* prm, fde_solve_info* info) {
+    int rc = FDE_OK;
+    try {
+        if (!ctx || n < 0 || (n > 0 && (!ops || !nrhs || !G || !ldg || !X || !ldx || !info)))
+            fail(FDE_EINVAL, "bad arguments");
+        std::vector<fde_op*> o(ops, ops + n);
+        std::vector<fde_hlu*> p(n, nullptr);
+        if (precs) std::copy(precs, precs + n, p.begin());
+        run(ctx, n, (fde_op* const*)o.data(), (fde_hlu* const*)p.data(), nrhs, G, ldg, X, ldx, prm, info, &rc);
+    } catch (const Error& e) {
+        set_error("%s", e.msg.c_str());
+        return e.code;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return FDE_EDEVICE;
+    }
+    if (rc == FDE_ENOCONV) set_error("FGMRES did not reach rtol within maxit for at least one right-hand side");
+    return rc;
+}
+
+}  // extern "C"

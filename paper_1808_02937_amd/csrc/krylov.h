@@ -1,0 +1,37 @@
+// Batched right-preconditioned FGMRES(m) (Section 4.2) on the device.
+#pragma once
+
+#include "fde_internal.h"
+
+namespace fde {
+
+constexpr int kMaxRestart = 64;
+
+struct SysDev {            // one right-hand side of one operator
+    double* V;             // Krylov basis of the operator group: block i at V + i*bs, column c at + c*Nd
+    double* Z;             // preconditioned basis, same layout
+    double* W;             // A z_j for the group (Nd x nr)
+    double* R;             // A x for the group (Nd x nr)
+    const double* G;       // right-hand side column
+    double* X;             // solution column
+    int64_t bs;            // block stride Nd * nr
+    int Nd, c;
+};
+
+struct SysState {
+    double H[(kMaxRestart + 1) * kMaxRestart];
+    double cs[kMaxRestart], sn[kMaxRestart], g[kMaxRestart + 1], y[kMaxRestart];
+    double gnorm, relres, est;
+    int active, jend, iters, conv, status, pad;
+};
+
+void fg_gnorm(hipStream_t st, int ns, const SysDev* sys, SysState* ss);
+void fg_zero_x(hipStream_t st, int ns, const SysDev* sys);
+void fg_cycle_start(hipStream_t st, int ns, const SysDev* sys, SysState* ss, int first, int maxit);
+void fg_copy_step(hipStream_t st, int ns, const SysDev* sys, const int* mask, int j);
+void fg_arnoldi(hipStream_t st, int ns, const SysDev* sys, SysState* ss, int j, int m, double rtol, int maxit);
+void fg_count_active(hipStream_t st, int ns, const SysState* ss, int* out);
+void fg_update(hipStream_t st, int ns, const SysDev* sys, SysState* ss);
+void fg_check(hipStream_t st, int ns, const SysDev* sys, SysState* ss, double rtol);
+
+}  // namespace fde

@@ -1,0 +1,276 @@
+// Kernels of the batched FGMRES: one 256-thread workgroup per system (one
+// right-hand side of one operator) for every reduction, so each system's
+// arithmetic is independent of what else is in the batch (a result is the
+// same alone and in a mix).
+//
+// Arnoldi step (fused): classical Gram-Schmidt against the basis, repeated
+// once (CGS2), normalisation, Givens update of the Hessenberg column and of
+// the residual estimate |g_{j+1}|.
+#include <cmath>
+
+#include "krylov.h"
+
+namespace fde {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kW = kT / 64;
+constexpr int kChunk = 16;
+
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+struct Red {
+    double w[kW][kChunk];
+    double dots[kMaxRestart + 1];
+    double s;
+};
+
+__device__ inline double block_sum(double v, Red& r) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) r.w[wave][0] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kW; ++w) s += r.w[w][0];
+    __syncthreads();
+    return s;
+}
+
+// dots[i] = v_i . w for i < nv (vectors v_i = base + i*stride), deterministic order
+__device__ void block_dots(const double* base, int64_t stride, int nv, const double* w, int n, Red& r) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < nv; c0 += kChunk) {
+        const int cn = min(kChunk, nv - c0);
+        double part[kChunk];
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) part[c] = 0.0;
+        for (int i = threadIdx.x; i < n; i += kT) {
+            const double wi = w[i];
+#pragma unroll
+            for (int c = 0; c < kChunk; ++c)
+                if (c < cn) part[c] += base[(int64_t)(c0 + c) * stride + i] * wi;
+        }
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) {
+            const double v = wave_sum(part[c]);
+            if (c < cn && lane == 0) r.w[wave][c] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < cn) {
+            double s = 0.0;
+            for (int q = 0; q < kW; ++q) s += r.w[q][threadIdx.x];
+            r.dots[c0 + threadIdx.x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_gnorm(const SysDev* __restrict__ sys, SysState* __restrict__ ss) {
+    __shared__ Red r;
+    const SysDev d = sys[blockIdx.x];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < d.Nd; i += kT) v += d.G[i] * d.G[i];
+    v = block_sum(v, r);
+    if (threadIdx.x == 0) {
+        SysState& s = ss[blockIdx.x];
+        s.gnorm = sqrt(v);
+        s.iters = 0;
+        s.conv = 0;
+        s.status = 0;
+        s.active = 0;
+        s.jend = 0;
+        s.relres = 1.0;
+        if (!(s.gnorm > 0.0)) {
+            s.conv = 1;
+            s.relres = 0.0;
+            if (!(s.gnorm == 0.0)) s.status = -5;   // not finite
+        }
+    }
+}
+
+__global__ void k_zero_x(const SysDev* __restrict__ sys) {
+    const SysDev d = sys[blockIdx.y];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.Nd; i += gridDim.x * blockDim.x) d.X[i] = 0.0;
+}
+
+__global__ void k_cycle_start(const SysDev* __restrict__ sys, SysState* __restrict__ ss, int first, int maxit) {
+    __shared__ Red r;
+    const SysDev d = sys[blockIdx.x];
+    SysState& s = ss[blockIdx.x];
+    if (s.conv || s.iters >= maxit) {
+        if (threadIdx.x == 0) s.active = 0;
+        return;
+    }
+    double* v0 = d.V + (int64_t)d.c * d.Nd;
+    const double* Rc = d.R + (int64_t)d.c * d.Nd;
+    double nn = 0.0;
+    for (int i = threadIdx.x; i < d.Nd; i += kT) {
+        const double ri = d.G[i] - (first ? 0.0 : Rc[i]);
+        v0[i] = ri;
+        nn += ri * ri;
+    }
+    const double beta = sqrt(block_sum(nn, r));
+    const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+    for (int i = threadIdx.x; i < d.Nd; i += kT) v0[i] *= inv;
+    if (threadIdx.x == 0) {
+        for (int k = 0; k <= kMaxRestart; ++k) s.g[k] = 0.0;
+        s.g[0] = beta;
+        s.jend = 0;
+        s.active = beta > 0.0 ? 1 : 0;
+        s.est = beta;
+    }
+}
+
+__global__ void k_copy_step(const SysDev* __restrict__ sys, const int* __restrict__ mask, int j) {
+    const SysDev d = sys[blockIdx.y];
+    if (!mask[blockIdx.y]) return;
+    const double* v = d.V + (int64_t)j * d.bs + (int64_t)d.c * d.Nd;
+    double* z = d.Z + (int64_t)j * d.bs + (int64_t)d.c * d.Nd;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.Nd; i += gridDim.x * blockDim.x) z[i] = v[i];
+}
+
+__global__ void __launch_bounds__(kT) k_arnoldi(const SysDev* __restrict__ sys, SysState* __restrict__ ss, int j,
+                                                int m, double rtol, int maxit) {
+    __shared__ Red r;
+    __shared__ double hcol[kMaxRestart + 1];
+    const SysDev d = sys[blockIdx.x];
+    SysState& s = ss[blockIdx.x];
+    if (!s.active) return;
+    const int n = d.Nd;
+    double* w = d.W + (int64_t)d.c * n;
+    const double* V0 = d.V + (int64_t)d.c * n;
+    for (int pass = 0; pass < 2; ++pass) {
+        block_dots(V0, d.bs, j + 1, w, n, r);
+        for (int i = threadIdx.x; i < n; i += kT) {
+            double acc = 0.0;
+            for (int k = 0; k <= j; ++k) acc += r.dots[k] * V0[(int64_t)k * d.bs + i];
+            w[i] -= acc;
+        }
+        if (threadIdx.x <= j) hcol[threadIdx.x] = (pass == 0 ? 0.0 : hcol[threadIdx.x]) + r.dots[threadIdx.x];
+        __syncthreads();
+    }
+    double nn = 0.0;
+    for (int i = threadIdx.x; i < n; i += kT) nn += w[i] * w[i];
+    const double hn = sqrt(block_sum(nn, r));
+    const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+    double* v1 = d.V + (int64_t)(j + 1) * d.bs + (int64_t)d.c * n;
+    if (j + 1 < m + 1)
+        for (int i = threadIdx.x; i < n; i += kT) v1[i] = w[i] * inv;
+    if (threadIdx.x == 0) {
+        hcol[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {
+            const double t = s.cs[i] * hcol[i] + s.sn[i] * hcol[i + 1];
+            hcol[i + 1] = -s.sn[i] * hcol[i] + s.cs[i] * hcol[i + 1];
+            hcol[i] = t;
+        }
+        const double den = hypot(hcol[j], hcol[j + 1]);
+        const double c = den > 0.0 ? hcol[j] / den : 1.0, sn = den > 0.0 ? hcol[j + 1] / den : 0.0;
+        s.cs[j] = c;
+        s.sn[j] = sn;
+        hcol[j] = den;
+        hcol[j + 1] = 0.0;
+        for (int i = 0; i <= j + 1; ++i) s.H[i + j * (kMaxRestart + 1)] = hcol[i];
+        s.g[j + 1] = -sn * s.g[j];
+        s.g[j] = c * s.g[j];
+        s.est = fabs(s.g[j + 1]);
+        s.iters += 1;
+        const bool done = !(s.est > rtol * s.gnorm) || j + 1 >= m || s.iters >= maxit || !(hn > 0.0) ||
+                          !isfinite(s.est);
+        if (done) {
+            s.active = 0;
+            s.jend = j + 1;
+        }
+    }
+}
+
+__global__ void k_count_active(const SysState* __restrict__ ss, int ns, int* out) {
+    __shared__ Red r;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < ns; i += kT) v += ss[i].active;
+    v = block_sum(v, r);
+    if (threadIdx.x == 0) *out = (int)v;
+}
+
+__global__ void k_update(const SysDev* __restrict__ sys, SysState* __restrict__ ss) {
+    const SysDev d = sys[blockIdx.x];
+    SysState& s = ss[blockIdx.x];
+    const int k = s.jend;
+    if (k <= 0) return;
+    if (threadIdx.x == 0) {
+        for (int i = k - 1; i >= 0; --i) {
+            double t = s.g[i];
+            for (int l = i + 1; l < k; ++l) t -= s.H[i + l * (kMaxRestart + 1)] * s.y[l];
+            s.y[i] = t / s.H[i + i * (kMaxRestart + 1)];
+        }
+    }
+    __syncthreads();
+    const double* Z0 = d.Z + (int64_t)d.c * d.Nd;
+    for (int i = threadIdx.x; i < d.Nd; i += kT) {
+        double acc = 0.0;
+        for (int l = 0; l < k; ++l) acc += s.y[l] * Z0[(int64_t)l * d.bs + i];
+        d.X[i] += acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s.jend = 0;
+}
+
+__global__ void k_check(const SysDev* __restrict__ sys, SysState* __restrict__ ss, double rtol) {
+    __shared__ Red r;
+    const SysDev d = sys[blockIdx.x];
+    SysState& s = ss[blockIdx.x];
+    if (s.conv) return;
+    const double* Rc = d.R + (int64_t)d.c * d.Nd;
+    double nn = 0.0;
+    for (int i = threadIdx.x; i < d.Nd; i += kT) {
+        const double ri = d.G[i] - Rc[i];
+        nn += ri * ri;
+    }
+    const double rn = sqrt(block_sum(nn, r));
+    if (threadIdx.x == 0) {
+        s.relres = rn / s.gnorm;
+        s.conv = s.relres <= rtol ? 1 : 0;
+        if (!isfinite(s.relres)) s.status = -5;
+    }
+}
+
+}  // namespace
+
+void fg_gnorm(hipStream_t st, int ns, const SysDev* sys, SysState* ss) {
+    hipLaunchKernelGGL(k_gnorm, dim3(ns), dim3(kT), 0, st, sys, ss);
+    FDE_LAUNCH_CHECK();
+}
+void fg_zero_x(hipStream_t st, int ns, const SysDev* sys) {
+    hipLaunchKernelGGL(k_zero_x, dim3(16, ns), dim3(256), 0, st, sys);
+    FDE_LAUNCH_CHECK();
+}
+void fg_cycle_start(hipStream_t st, int ns, const SysDev* sys, SysState* ss, int first, int maxit) {
+    hipLaunchKernelGGL(k_cycle_start, dim3(ns), dim3(kT), 0, st, sys, ss, first, maxit);
+    FDE_LAUNCH_CHECK();
+}
+void fg_copy_step(hipStream_t st, int ns, const SysDev* sys, const int* mask, int j) {
+    hipLaunchKernelGGL(k_copy_step, dim3(16, ns), dim3(256), 0, st, sys, mask, j);
+    FDE_LAUNCH_CHECK();
+}
+void fg_arnoldi(hipStream_t st, int ns, const SysDev* sys, SysState* ss, int j, int m, double rtol, int maxit) {
+    hipLaunchKernelGGL(k_arnoldi, dim3(ns), dim3(kT), 0, st, sys, ss, j, m, rtol, maxit);
+    FDE_LAUNCH_CHECK();
+}
+void fg_count_active(hipStream_t st, int ns, const SysState* ss, int* out) {
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(kT), 0, st, ss, ns, out);
+    FDE_LAUNCH_CHECK();
+}
+void fg_update(hipStream_t st, int ns, const SysDev* sys, SysState* ss) {
+    hipLaunchKernelGGL(k_update, dim3(ns), dim3(kT), 0, st, sys, ss);
+    FDE_LAUNCH_CHECK();
+}
+void fg_check(hipStream_t st, int ns, const SysDev* sys, SysState* ss, double rtol) {
+    hipLaunchKernelGGL(k_check, dim3(ns), dim3(kT), 0, st, sys, ss, rtol);
+    FDE_LAUNCH_CHECK();
+}
+
+}  // namespace fde

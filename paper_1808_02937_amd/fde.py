@@ -7,6 +7,7 @@ column-major Nd x nrhs array the library sees, with leading dimension Nd.
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 from typing import Callable, Optional, Sequence
 
 import numpy as np
@@ -22,6 +23,33 @@ def _dptr(t: torch.Tensor) -> C.c_void_p:
 
 def _np_dptr(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class _Handle:
+    """Owns one library handle; closing it first closes every handle created from it
+    (so a garbage-collection cycle can never free a parent before its children)."""
+
+    _destroy = None
+
+    def _init_handle(self, h, parent=None):
+        self.h = h
+        self._children = weakref.WeakSet()
+        if parent is not None:
+            parent._children.add(self)
+
+    def close(self):
+        for c in list(getattr(self, "_children", ())):
+            c.close()
+        if getattr(self, "h", None):
+            if not A.shutting_down():
+                getattr(load(), self._destroy)(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _as_block(t: torch.Tensor, Nd: int, device) -> torch.Tensor:
@@ -40,8 +68,10 @@ def gauss_jacobi(n: int, a: float, b: float):
     return x, w
 
 
-class Context:
+class Context(_Handle):
     """Device, HIP stream (torch's current stream by default) and HBM budget."""
+
+    _destroy = "fde_ctx_destroy"
 
     def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None, budget_bytes: int = 0):
         lib = load()
@@ -50,7 +80,7 @@ class Context:
         self._stream = s
         h = C.c_void_p()
         check(lib.fde_ctx_create(device, C.c_void_p(s.cuda_stream), budget_bytes, C.byref(h)))
-        self.h = h
+        self._init_handle(h)
 
     def set_stream(self, stream: torch.cuda.Stream):
         self._stream = stream
@@ -62,23 +92,14 @@ class Context:
     def synchronize(self):
         self._stream.synchronize()
 
-    def close(self):
-        if self.h:
-            load().fde_ctx_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
 
 _MODES = {"auto": A.FDE_APPLY_AUTO, "dense": A.FDE_APPLY_DENSE, "toeplitz": A.FDE_APPLY_TOEPLITZ}
 
 
-class Operator:
+class Operator(_Handle):
     """A = rho M + theta S_l + (1-theta) S_l^T on a mesh (Section 2.2)."""
+
+    _destroy = "fde_op_destroy"
 
     def __init__(self, ctx: Context, nodes, P: int, alpha: float, theta: float, rho: float,
                  apply: str = "auto"):
@@ -89,20 +110,9 @@ class Operator:
         h = C.c_void_p()
         check(load().fde_op_create(ctx.h, _np_dptr(x), self.N, self.P, self.alpha, self.theta, self.rho,
                                    _MODES[apply], C.byref(h)))
-        self.h = h
+        self._init_handle(h, ctx)
         self.Nd = int(load().fde_op_ndof(h))
         self.toeplitz = bool(load().fde_op_is_toeplitz(h))
-
-    def close(self):
-        if self.h:
-            load().fde_op_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
     def pair_moments(self, e: Sequence[int], f: Sequence[int]) -> np.ndarray:
         e = np.ascontiguousarray(e, dtype=np.int32)
@@ -151,15 +161,17 @@ class Operator:
         return Y.view_as(X) if out is None else out
 
 
-class HMatrix:
+class HMatrix(_Handle):
     """A~ = rho M + H (Section 3)."""
+
+    _destroy = "fde_hmat_destroy"
 
     def __init__(self, op: Operator, R: int = 8, lam: float = 1.0, leaf_elems: int = 8):
         self.op = op
         p = A.HParams(int(R), float(lam), int(leaf_elems))
         h = C.c_void_p()
         check(load().fde_build_hmatrix(op.h, C.byref(p), C.byref(h)))
-        self.h = h
+        self._init_handle(h, op)
 
     def counts(self):
         nd, nr = C.c_int(), C.c_int()
@@ -172,20 +184,11 @@ class HMatrix:
         check(load().fde_hmat_to_dense(self.h, _dptr(At), Nd))
         return At.t()
 
-    def close(self):
-        if self.h:
-            load().fde_hmat_destroy(self.h)
-            self.h = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
-
-class HLU:
+class HLU(_Handle):
     """H-LU factors L_H U_H of A~ (Section 4.1)."""
+
+    _destroy = "fde_hlu_destroy"
 
     def __init__(self, hm: HMatrix, tol: float = 1e-3, rank_cap: int = 0, precision: str = "fp32",
                  pivot_floor: float = 1e-14):
@@ -196,7 +199,7 @@ class HLU:
         p = A.HLUParams(float(tol), int(rank_cap), prec, float(pivot_floor))
         h = C.c_void_p()
         check(load().fde_hlu_factor(hm.h, C.byref(p), C.byref(h)))
-        self.h = h
+        self._init_handle(h, hm)
 
     def solve(self, B: torch.Tensor) -> torch.Tensor:
         B2 = _as_block(B, self.Nd, self.device)
@@ -216,17 +219,6 @@ class HLU:
         r = C.c_int()
         check(load().fde_hlu_max_rank(self.h, C.byref(r)))
         return r.value
-
-    def close(self):
-        if self.h:
-            load().fde_hlu_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
 
 def _solve_params(rtol, restart, maxit):

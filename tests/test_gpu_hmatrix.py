@@ -1,0 +1,133 @@
+"""GPU parity: H-matrix build, H-LU (FP64 and FP32) and H-solves vs the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import fde_inputs as fi
+from oracle.hmatrix import HLU as OHLU
+from oracle.hmatrix import HMatrix as OHMatrix
+from oracle.hmatrix import to_dense
+from oracle.sem import SEM
+from tests.gpu_common import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (nodes, P, alpha, theta, rho, R, leaf)
+    "small": (fi.uniform_mesh(16), 4, 1.5, 0.5, 0.0, 4, 2),
+    "graded_theta1": (fi.graded_mesh(40, 5.0, 0.0, 10.0), 3, 1.6, 1.0, 0.0, 5, 2),
+    "two_sided": (fi.two_sided_graded_mesh(48, 6, 0.5), 5, 1.7, 0.4, 0.0, 6, 4),
+    "uniform_theta0": (fi.uniform_mesh(37), 3, 1.25, 0.0, 1.0, 6, 4),
+    "geometric": (fi.geometric_mesh(30, 1.1), 6, 1.85, 0.7, 2.0, 8, 4),
+}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    fde = need_gpu()
+    return fde.Context(0)
+
+
+def build(ctx, name):
+    import paper_1808_02937_amd as fde
+    nodes, P, al, th, rho, R, leaf = CASES[name]
+    sem = SEM(nodes, P, al, th, rho)
+    op = fde.Operator(ctx, nodes, P, al, th, rho)
+    hm = fde.HMatrix(op, R=R, lam=1.0, leaf_elems=leaf)
+    oh = OHMatrix(sem, R, 1.0, leaf)
+    return sem, op, hm, oh
+
+
+def to_paper(Mh, h2p):
+    out = np.empty_like(Mh)
+    out[np.ix_(h2p, h2p)] = Mh
+    return out
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hmatrix_matches_oracle(ctx, name):
+    say(f"hmatrix {name}")
+    sem, op, hm, oh = build(ctx, name)
+    assert hm.counts() == oh.counts()
+    At = hm.dense().cpu().numpy()
+    ref = to_paper(to_dense(oh.root), oh.h2p)
+    assert np.abs(At - ref).max() <= 1e-13 * np.abs(ref).max(), np.abs(At - ref).max() / np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hlu_fp64_without_truncation_is_exact_lu(ctx, name):
+    import paper_1808_02937_amd as fde
+    say(f"hlu fp64 exact {name}")
+    sem, op, hm, oh = build(ctx, name)
+    lu = fde.HLU(hm, tol=0.0, rank_cap=48, precision="fp64", pivot_floor=0.0)
+    F, h2p = lu.dense()
+    F = F.cpu().numpy()
+    n = F.shape[0]
+    L = np.tril(F, -1) + np.eye(n)
+    U = np.triu(F)
+    Ah = to_dense(oh.root)
+    assert np.linalg.norm(L @ U - Ah) <= 1e-12 * np.linalg.norm(Ah)
+    ofac = OHLU(oh, tol=0.0, kmax=48, pivot_floor=0.0)
+    Lo, Uo = ofac.dense_factors()
+    assert np.abs(L - Lo).max() <= 1e-9 * max(1.0, np.abs(Lo).max())
+    assert np.abs(U - Uo).max() <= 1e-9 * np.abs(Uo).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hlu_fp64_truncated_matches_oracle(ctx, name):
+    import paper_1808_02937_amd as fde
+    say(f"hlu fp64 tol {name}")
+    sem, op, hm, oh = build(ctx, name)
+    R = CASES[name][5]
+    lu = fde.HLU(hm, tol=1e-3, precision="fp64", pivot_floor=1e-14)
+    ofac = OHLU(oh, tol=1e-3, pivot_floor=1e-14)
+    assert lu.max_rank() <= R
+    g = np.random.default_rng(11).standard_normal((3, sem.Nd))
+    x = lu.solve(torch.tensor(g, device="cuda")).cpu().numpy()
+    xo = ofac.solve(g.T).T
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    say(f"  fp64 hsolve vs oracle {err:.2e}")
+    assert err <= 1e-9
+    F, _ = lu.dense()
+    F = F.cpu().numpy()
+    n = F.shape[0]
+    Ah = to_dense(oh.root)
+    LU = (np.tril(F, -1) + np.eye(n)) @ np.triu(F)
+    assert np.linalg.norm(LU - Ah) <= 20 * 1e-3 * np.linalg.norm(Ah)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hlu_fp32_solve_bound(ctx, name):
+    import paper_1808_02937_amd as fde
+    say(f"hlu fp32 {name}")
+    sem, op, hm, oh = build(ctx, name)
+    lu = fde.HLU(hm, tol=1e-3, precision="fp32")
+    ofac = OHLU(oh, tol=1e-3)
+    g = np.random.default_rng(12).standard_normal((2, sem.Nd))
+    x = lu.solve(torch.tensor(g, device="cuda")).cpu().numpy()
+    xo = ofac.solve(g.T).T
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    say(f"  fp32 hsolve vs fp64 oracle {err:.2e}")
+    assert err <= 2e-2
+
+
+def test_hsolve_multi_rhs_equals_single(ctx):
+    import paper_1808_02937_amd as fde
+    say("hsolve multi rhs")
+    sem, op, hm, oh = build(ctx, "two_sided")
+    lu = fde.HLU(hm, tol=1e-3, precision="fp64")
+    g = torch.tensor(np.random.default_rng(13).standard_normal((70, sem.Nd)), device="cuda")
+    X = lu.solve(g)
+    for j in (0, 33, 69):
+        xj = lu.solve(g[j].contiguous())
+        assert torch.allclose(X[j], xj, rtol=0, atol=1e-13 * float(xj.abs().max()))
+
+
+def test_breakdown_is_reported(ctx):
+    import paper_1808_02937_amd as fde
+    from paper_1808_02937_amd._abi import FDE_EBREAKDOWN, FDEError
+    say("breakdown")
+    sem, op, hm, oh = build(ctx, "small")
+    with pytest.raises(FDEError) as ei:
+        fde.HLU(hm, tol=1e-3, precision="fp64", pivot_floor=10.0)
+    assert ei.value.code == FDE_EBREAKDOWN
