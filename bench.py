@@ -1,0 +1,222 @@
+"""Benchmark: FDE solves/sec at 1e-10 relative residual, mixed (FP32 H-LU) vs FP64 GPU path.
+
+Workload (one step = the whole hot path over one batch): uniform mesh on (0,1),
+N = 1024 elements, P = 8 (Nd = 8191), rho = 1, the 3 x 3 grid alpha in
+{1.2, 1.5, 1.8} x theta in {0.3, 0.5, 0.8}; each operator gets one seeded
+smooth right-hand side (8 polynomial modes, closed-form fractional terms).
+Per step and operator: assembly of the block-Toeplitz generators and FFT
+symbol, load vector, H-matrix (R = 8, lambda = 1, leaf 8 elements), H-LU
+(FP32, tol 1e-3, one launch for all operators), then one batched
+preconditioned FGMRES solve of all nine systems to ||G - A X|| / ||G|| <= 1e-10.
+
+Prints one JSON line. Extra fields report the plain FP64 path, the solve phase
+with cached factors, the phase split, p50/p99 latency, the roofline of the
+dominant kernel and the CPU oracle baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import fde_inputs as fi  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_instances(N=1024, P=8):
+    out = []
+    for a in fi.UNIFORM_GRID_ALPHAS:
+        for t in fi.UNIFORM_GRID_THETAS:
+            out.append(fi.config_uniform_grid(a, t, N=N, P=P))
+    return out
+
+
+class Pipeline:
+    def __init__(self, fde, ctx, insts, precision):
+        self.fde, self.ctx, self.insts, self.precision = fde, ctx, insts, precision
+
+    def setup(self):
+        fde = self.fde
+        ops, Gs, hms = [], [], []
+        for inst in self.insts:
+            op = fde.Operator(self.ctx, inst.nodes, inst.P, inst.alpha, inst.theta, inst.rho)
+            ops.append(op)
+            Gs.append(op.load_vector(inst.rhs[0]))
+            hms.append(fde.HMatrix(op, R=inst.R, lam=1.0, leaf_elems=inst.leaf))
+        lus = fde.factor_batched(hms, tol=1e-3, precision=self.precision)
+        return ops, Gs, hms, lus
+
+    def solve(self, ops, Gs, lus):
+        return self.fde.solve_batched(self.ctx, ops, Gs, lus, rtol=1e-10, restart=30, maxit=300)
+
+    def step(self):
+        ops, Gs, hms, lus = self.setup()
+        Xs, infos = self.solve(ops, Gs, lus)
+        for o in ops:
+            o.close()
+        return infos
+
+
+def timed(torch, fn, reps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def kernel_time_ms(torch, fn, reps):
+    """Average GPU time of fn() from HIP events on the stream the library launches on."""
+    s = torch.cuda.current_stream()
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline():
+    """The oracle on one of the nine operators (alpha=1.5, theta=0.5), end to end."""
+    from threadpoolctl import threadpool_info
+    from oracle import toeplitz
+    from oracle.hmatrix import HLU, HMatrix
+    from oracle.krylov import fgmres
+    from oracle.sem import SEM
+    inst = fi.config_uniform_grid(1.5, 0.5)
+    t0 = time.perf_counter()
+    sem = SEM(inst.nodes, inst.P, inst.alpha, inst.theta, inst.rho)
+    G = sem.load_vector(inst.solution.f_terms)
+    Kh = toeplitz.generators(sem, 1.0)
+    A = toeplitz.dense_matrix(sem, Kh)
+    H = HMatrix(sem, inst.R, 1.0, inst.leaf, A=A)
+    F = HLU(H, tol=1e-3)
+    X, info = fgmres(lambda v: toeplitz.apply(sem, v, Kh), G, F.solve, tol=1e-10)
+    dt = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": 1.0 / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": ("one of the nine operators (alpha=1.5, theta=0.5, N=1024, P=8) end to end in the FP64 "
+                       f"oracle: load vector, generators + dense A, H-matrix, H-LU, FGMRES ({info['iters']} its, "
+                       f"relres {info['relres']:.1e}); {dt:.1f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="skip the extra measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the solver has no multi-GPU path",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_1808_02937_amd as fde
+    torch.cuda.init()
+    ctx = fde.Context(0)
+    insts = make_instances()
+    nsys = len(insts)
+    mixed = Pipeline(fde, ctx, insts, "fp32")
+    fp64 = Pipeline(fde, ctx, insts, "fp64")
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        mixed.step()
+    log(f"timing {args.steps} steps")
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = None
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        infos = mixed.step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        log(f"step {k}: {lat[-1] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms_per_step = total / args.steps * 1e3
+    value = nsys * args.steps / total
+    relres = max(i[0]["relres"] for i in infos)
+    iters = [i[0]["iters"] for i in infos]
+    assert relres <= 1e-10, relres
+    out = {"metric": "FDE solves/sec at 1e-10 rel residual (mixed vs FP64 GPU) + p50/p99 latency",
+           "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 (H-LU and H-solves f32)", "data": "synthetic",
+           "config": {"workload": "uniform N=1024 P=8 (Nd=8191), 3x3 alpha x theta grid, rho=1, 1 RHS each, "
+                                  "H-LU R=8 FP32 tol 1e-3, FGMRES(30) to 1e-10 true residual, end to end",
+                      "systems_per_step": nsys},
+           "iters": iters, "max_relres": relres,
+           "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
+                          "definition": "batch completion time (every request of a step arrives at its start)"}}
+    # roofline of the dominant kernel: the H-LU interpreter launch (all nine factorisations)
+    ops_r, Gs_r, hms_r, lus_r = mixed.setup()
+    st = [lu.stats() for lu in lus_r]
+    flops = sum(x[0] for x in st)
+    kms = st[0][1]
+    achieved = flops / (kms * 1e-3) / 1e12
+    out["roofline"] = {"kernel": "k_interp<float> (batched H-LU, one workgroup per operator)", "bound": "alu",
+                       "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                       "flops_per_launch": flops, "launch_ms": kms}
+    for o in ops_r:
+        o.close()
+    if not args.quick:
+        # plain FP64 path, same algorithm
+        log("fp64 path")
+        fp64.step()
+        t64, _ = timed(torch, fp64.step, max(1, args.steps // 2))
+        out["fp64_path"] = {"value": nsys / t64, "unit": "solves/s", "ms_per_step": t64 * 1e3}
+        # solve phase with cached factors
+        ops, Gs, hms, lus = mixed.setup()
+        ts, r = timed(torch, lambda: mixed.solve(ops, Gs, lus), 5)
+        ops64, Gs64, hms64, lus64 = fp64.setup()
+        ts64, _ = timed(torch, lambda: fp64.solve(ops64, Gs64, lus64), 5)
+        out["cached_factors"] = {"mixed": nsys / ts, "fp64": nsys / ts64, "unit": "solves/s",
+                                 "mixed_ms": ts * 1e3, "fp64_ms": ts64 * 1e3}
+        # phase split of one mixed step
+        ph = {}
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ops2 = [fde.Operator(ctx, i.nodes, i.P, i.alpha, i.theta, i.rho) for i in insts]
+        torch.cuda.synchronize(); ph["operators_ms"] = (time.perf_counter() - t) * 1e3; t = time.perf_counter()
+        Gs2 = [o.load_vector(i.rhs[0]) for o, i in zip(ops2, insts)]
+        torch.cuda.synchronize(); ph["load_vector_ms"] = (time.perf_counter() - t) * 1e3; t = time.perf_counter()
+        hms2 = [fde.HMatrix(o, R=i.R, lam=1.0, leaf_elems=i.leaf) for o, i in zip(ops2, insts)]
+        torch.cuda.synchronize(); ph["hmatrix_ms"] = (time.perf_counter() - t) * 1e3; t = time.perf_counter()
+        lus2 = fde.factor_batched(hms2, tol=1e-3, precision="fp32")
+        torch.cuda.synchronize(); ph["hlu_ms"] = (time.perf_counter() - t) * 1e3; t = time.perf_counter()
+        mixed.solve(ops2, Gs2, lus2)
+        torch.cuda.synchronize(); ph["solve_ms"] = (time.perf_counter() - t) * 1e3
+        out["phases_ms"] = ph
+        # kernel-level: one H-solve (interpreter) and one stiffness apply, HIP events on the library stream
+        v = torch.randn(1, ops[0].Nd, dtype=torch.float64, device="cuda")
+        t_hs = kernel_time_ms(torch, lambda: lus[0].solve(v), 20)
+        t_ap = kernel_time_ms(torch, lambda: ops[0].apply(v), 50)
+        out["kernels_ms"] = {"hsolve_fp32": t_hs, "apply_toeplitz": t_ap}
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -162,11 +162,22 @@ int  fde_hmat_to_dense(fde_hmat* hm, double* out_dev, int ld);
 /* ---- H-LU and H-solves (Section 4.1) ---------------------------------- */
 
 int  fde_hlu_factor(fde_hmat* hm, const fde_hlu_params* prm, fde_hlu** out);
+/* Factor n H-matrices (any sizes) with the same parameters in one device
+ * launch, one workgroup per H-matrix; out[i] receives each factor. On any
+ * failure no factor is returned (out[] all NULL) and the status of the first
+ * failing H-matrix is returned. */
+int  fde_hlu_factor_batched(int n, fde_hmat* const* hms, const fde_hlu_params* prm, fde_hlu** out);
 void fde_hlu_destroy(fde_hlu* f);
 /* L_H (strict lower part, unit diagonal implied) and U_H packed in one
  * Nd x Nd column-major matrix in the H-matrix's internal order; h2p_host (if
  * not NULL) receives that order as paper indices (Nd ints). */
 int  fde_hlu_to_dense(fde_hlu* f, double* out_dev, int ld, int* h2p_host);
+/* Work of the last factorisation and of the H-solves since the factorisation:
+ * floating-point operations the device executed (counted per op with its
+ * actual dimensions and ranks) and the factorisation launch time measured with
+ * HIP events on the context stream (ms; for a batched factorisation the whole
+ * launch). Any output may be NULL. Synchronises. */
+int  fde_hlu_stats(fde_hlu* f, double* factor_flops, double* factor_kernel_ms, double* solve_flops);
 /* largest rank over the low-rank blocks of the factors (synchronises) */
 int  fde_hlu_max_rank(fde_hlu* f, int* max_rank);
 /* X = U_H^{-1} L_H^{-1} B (forward then backward H-substitution), nrhs columns,

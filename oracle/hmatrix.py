@@ -181,7 +181,8 @@ def lowrank_factors(sem: SEM, T: Cluster, S: Cluster, h2p, R: int):
 class HMatrix:
     """A~ = rho M + H in element-interleaved order (eq. (approxsys))."""
 
-    def __init__(self, sem: SEM, R: int, lam: float = 1.0, leaf_elems: int = 8):
+    def __init__(self, sem: SEM, R: int, lam: float = 1.0, leaf_elems: int = 8, A: np.ndarray = None):
+        """A (optional): the dense system matrix in paper order, to take the dense blocks from."""
         self.sem = sem
         self.R = R
         self.lam = lam
@@ -193,7 +194,7 @@ class HMatrix:
             rows = self.h2p[b.tau.d0:b.tau.d1]
             cols = self.h2p[b.sigma.d0:b.sigma.d1]
             if b.kind == "D":
-                b.D = sem.block(rows, cols)
+                b.D = sem.block(rows, cols) if A is None else A[np.ix_(rows, cols)].copy()
             elif b.tau.lo >= b.sigma.hi:           # lower: theta * Q W^T
                 Qt, Ws = lowrank_factors(sem, b.tau, b.sigma, self.h2p, R)
                 b.U, b.V = (th * Qt, Ws) if th != 0.0 else (Qt[:, :0], Ws[:, :0])

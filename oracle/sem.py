@@ -89,6 +89,9 @@ class SEM:
         On element e, (phi_e^p)' = -(2p+1) (2/h_e) L_p(xi_e) and a hat has slope
         +-1/h_e, a multiple of L_0 (Section 2.2).
         """
+        key = "_D1" if with_boundary else "_D0"
+        if getattr(self, key, None) is not None:
+            return getattr(self, key)
         N, P, h = self.N, self.P, self.h
         rows, cols, vals = [], [], []
         for e in range(N):
@@ -103,7 +106,9 @@ class SEM:
             rows.append(0); cols.append(self.Nd); vals.append(-1.0 / h[0])
             rows.append((N - 1) * P); cols.append(self.Nd + 1); vals.append(1.0 / h[N - 1])
             ncol += 2
-        return sp.csr_matrix((vals, (rows, cols)), shape=(N * P, ncol))
+        D = sp.csr_matrix((vals, (rows, cols)), shape=(N * P, ncol))
+        setattr(self, key, D)
+        return D
 
     # ---- element-pair moments K^{ef} ----
     def pair_moment(self, e: int, f: int) -> np.ndarray:

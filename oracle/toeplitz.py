@@ -64,3 +64,22 @@ def apply(sem: SEM, X: np.ndarray, Khat: np.ndarray = None) -> np.ndarray:
     ye = sem.theta * sig[:, None, None] * Yc + (1.0 - sem.theta) * omg[:, None, None] * Yr
     Y = D.T @ ye.reshape(N * P, -1) + sem.rho * (sem.mass_sparse() @ X2)
     return Y[:, 0] if X.ndim == 1 else Y
+
+
+def dense_matrix(sem: SEM, Khat: np.ndarray = None) -> np.ndarray:
+    """A (Nd x Nd, paper order) from the generators: the block-Toeplitz K, then D^T K D + rho M."""
+    r = mesh_ratio(sem)
+    assert r is not None, "mesh is not uniform or geometric"
+    if Khat is None:
+        Khat = generators(sem, r)
+    N, P = sem.N, sem.P
+    sig = (0.5 * sem.h) ** (2.0 - sem.alpha)
+    omg = 0.5 * sem.h
+    K = np.zeros((N * P, N * P))
+    for e in range(N):
+        for f in range(e + 1):
+            K[e * P:(e + 1) * P, f * P:(f + 1) * P] = sig[e] * omg[f] * Khat[e - f]
+    D = sem.derivative_map()
+    KD = np.asarray(D.T @ (sem.theta * K + (1.0 - sem.theta) * K.T))
+    S = np.asarray((D.T @ KD.T).T)
+    return S + sem.rho * sem.mass_sparse().toarray()

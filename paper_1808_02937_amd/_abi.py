@@ -69,9 +69,11 @@ SIGNATURES = {
     "fde_hmat_counts": (i32, [vp, ip, ip]),
     "fde_hmat_to_dense": (i32, [vp, vp, i32]),
     "fde_hlu_factor": (i32, [vp, C.POINTER(HLUParams), C.POINTER(vp)]),
+    "fde_hlu_factor_batched": (i32, [i32, C.POINTER(vp), C.POINTER(HLUParams), C.POINTER(vp)]),
     "fde_hlu_destroy": (None, [vp]),
     "fde_hlu_to_dense": (i32, [vp, vp, i32, ip]),
     "fde_hlu_max_rank": (i32, [vp, ip]),
+    "fde_hlu_stats": (i32, [vp, dp, dp, dp]),
     "fde_hlu_solve": (i32, [vp, i32, vp, i32, vp, i32]),
     "fde_solve": (i32, [vp, vp, i32, vp, i32, vp, i32, C.POINTER(SolveParams), C.POINTER(SolveInfo)]),
     "fde_solve_batched": (i32, [vp, i32, C.POINTER(vp), C.POINTER(vp), ip, C.POINTER(vp), ip,

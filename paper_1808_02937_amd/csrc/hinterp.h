@@ -33,7 +33,13 @@ struct Inst {
     int kmax;
     double pivot_floor;
     int* status;              // [0] status code, [1] op index of a breakdown
+    unsigned long long* prof; // optional: per op code, [2c] wall-clock ticks, [2c+1] count
+    double* flops;            // executed floating-point operations (accumulated by thread 0)
 };
+
+// FDE_PROFILE_OPS=1 in the environment: time every interpreter op by type
+bool profile_ops_enabled();
+void print_op_profile(const char* what, const unsigned long long* host_prof, int device);
 
 template <class T>
 void launch_interp(hipStream_t st, int ninst, const Inst<T>* d_insts, int step = 0);

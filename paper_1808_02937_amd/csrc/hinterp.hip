@@ -11,6 +11,8 @@
 // truncation to a prescribed tolerance of Section 4.1). LOAD/STORE move FP64
 // vectors in the paper's order to and from the internal order.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "hinterp.h"
 
@@ -27,6 +29,8 @@ struct Shared {
     int order[kMaxKp];
     int flag;
     int r;
+    int sweeps;
+    double lrsub_flops;
 };
 
 __device__ inline double wave_sum(double v) {
@@ -90,14 +94,36 @@ __device__ void op_gemm(const Inst<T>& d, const OpRec& o) {
     const T alpha = (T)o.alpha, beta = (T)o.beta;
     const int64_t mn = (int64_t)m * n;
     const int ars = o.v[1].rs, acs = o.v[1].cs, brs = o.v[2].rs, bcs = o.v[2].cs;
-    for (int64_t idx = threadIdx.x; idx < mn; idx += kT) {
+    const int crs = o.v[0].rs, ccs = o.v[0].cs;
+    if (mn <= 0) return;
+    if (mn * 4 >= kT || k < 64) {
+        // one thread per output
+        for (int64_t idx = threadIdx.x; idx < mn; idx += kT) {
+            const int i = (int)(idx % m), j = (int)(idx / m);
+            const T* a = A + (int64_t)i * ars;
+            const T* b = B + (int64_t)j * bcs;
+            T s = 0;
+            for (int l = 0; l < k; ++l) s += a[(int64_t)l * acs] * b[(int64_t)l * brs];
+            T* c = C + (int64_t)i * crs + (int64_t)j * ccs;
+            *c = (beta == T(0) ? T(0) : beta * *c) + alpha * s;
+        }
+        return;
+    }
+    // few outputs, long inner dimension: a group of G lanes per output, reduced by shuffles
+    int G = 64;
+    while (G > 1 && (int64_t)G * mn > kT) G >>= 1;
+    const int ngroups = kT / G, gid = threadIdx.x / G, gl = threadIdx.x % G;
+    for (int64_t idx = gid; idx < mn; idx += ngroups) {
         const int i = (int)(idx % m), j = (int)(idx / m);
         const T* a = A + (int64_t)i * ars;
         const T* b = B + (int64_t)j * bcs;
-        T s = 0;
-        for (int l = 0; l < k; ++l) s += a[(int64_t)l * acs] * b[(int64_t)l * brs];
-        T* c = C + (int64_t)i * o.v[0].rs + (int64_t)j * o.v[0].cs;
-        *c = (beta == T(0) ? T(0) : beta * *c) + alpha * s;
+        double s = 0.0;
+        for (int l = gl; l < k; l += G) s += (double)a[(int64_t)l * acs] * (double)b[(int64_t)l * brs];
+        s = group_sum(s, G);
+        if (gl == 0) {
+            T* c = C + (int64_t)i * crs + (int64_t)j * ccs;
+            *c = (beta == T(0) ? T(0) : beta * *c) + alpha * (T)s;
+        }
     }
 }
 
@@ -121,6 +147,41 @@ __device__ void op_trsm(const Inst<T>& d, const OpRec& o) {
     const int xrs = o.v[0].rs, xcs = o.v[0].cs, trs = o.v[1].rs, tcs = o.v[1].cs;
     const bool lower = o.flags & 1, unit = o.flags & 2;
     auto Tat = [&](int i, int j) -> T { return Tm[(int64_t)i * trs + (int64_t)j * tcs]; };
+    if (w <= kW && n <= 256) {
+        // one wavefront per column: lane l holds rows l, l+64, l+128, l+192; no barriers
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        if (wave < w) {
+            T* x = X + (int64_t)wave * xcs;
+            T xr[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = lane + 64 * r;
+                xr[r] = row < n ? x[(int64_t)row * xrs] : T(0);
+            }
+            for (int s = 0; s < n; ++s) {
+                const int i = lower ? s : n - 1 - s;
+                const int slot = i >> 6, src = i & 63;
+                T own = xr[0];
+#pragma unroll
+                for (int r = 1; r < 4; ++r)
+                    if (slot == r) own = xr[r];
+                T xi = __shfl(own, src, 64);
+                if (!unit) xi /= Tat(i, i);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = lane + 64 * r;
+                    if (row == i) xr[r] = xi;
+                    if (row < n && (lower ? row > i : row < i)) xr[r] -= Tat(row, i) * xi;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = lane + 64 * r;
+                if (row < n) x[(int64_t)row * xrs] = xr[r];
+            }
+        }
+        return;
+    }
     if (w >= 64) {
         for (int j = threadIdx.x; j < w; j += kT) {
             T* x = X + (int64_t)j * xcs;
@@ -253,8 +314,12 @@ __device__ void jacobi_svd(double* M, double* W, int kp, Shared& sh) {
     while (G > 1 && G * npairs > kT) G >>= 1;
     const int ngroups = kT / G;
     const int gid = threadIdx.x / G, gl = threadIdx.x % G;
+    if (threadIdx.x == 0) sh.sweeps = 0;
     for (int sweep = 0; sweep < 40; ++sweep) {
-        if (threadIdx.x == 0) sh.flag = 0;
+        if (threadIdx.x == 0) {
+            sh.flag = 0;
+            sh.sweeps = sweep + 1;
+        }
         __syncthreads();
         for (int round = 0; round < n2 - 1; ++round) {
             for (int pi = gid; pi < npairs; pi += ngroups) {
@@ -303,6 +368,7 @@ __device__ void jacobi_svd(double* M, double* W, int kp, Shared& sh) {
 template <class T>
 __device__ void op_lrsub(const Inst<T>& d, const OpRec& o, Shared& sh) {
     const int kx = dimval(d, o.dim[2]);
+    if (threadIdx.x == 0) sh.lrsub_flops = 0.0;
     if (kx <= 0) return;
     const LRBlockDev L = d.lr[o.blk];
     T* U = d.arena + L.uoff;
@@ -338,6 +404,10 @@ __device__ void op_lrsub(const Inst<T>& d, const OpRec& o, Shared& sh) {
     }
     __syncthreads();
     jacobi_svd(Md, Wd, kp, sh);
+    if (threadIdx.x == 0) {
+        const double K = kp;
+        sh.lrsub_flops = 4.0 * (m + n) * K * K + 2.0 * K * K * K / 3.0 + sh.sweeps * K * (K - 1.0) / 2.0 * 12.0 * K;
+    }
     for (int j = threadIdx.x; j < kp; j += kT) {
         double s = 0.0;
         for (int i = 0; i < kp; ++i) s += Md[i + (int64_t)j * kp] * Md[i + (int64_t)j * kp];
@@ -360,6 +430,7 @@ __device__ void op_lrsub(const Inst<T>& d, const OpRec& o, Shared& sh) {
         if (r > d.kmax) r = d.kmax;
         sh.r = r;
         d.ranks[L.slot] = r;
+        sh.lrsub_flops += 2.0 * (m + n) * (double)kp * r;
     }
     __syncthreads();
     const int r = sh.r;
@@ -380,6 +451,25 @@ __device__ void op_lrsub(const Inst<T>& d, const OpRec& o, Shared& sh) {
     __syncthreads();
 }
 
+// floating-point operations of one op at its actual dimensions (evaluated before the op runs;
+// the recompression adds the part that depends on the rank it finds)
+template <class T>
+__device__ double op_flops(const Inst<T>& d, const OpRec& o) {
+    switch (o.code) {
+        case OP_GEMM:
+            return 2.0 * dimval(d, o.dim[0]) * dimval(d, o.dim[1]) * dimval(d, o.dim[2]);
+        case OP_TRSM: {
+            const double n = dimval(d, o.dim[0]);
+            return n * n * dimval(d, o.dim[1]);
+        }
+        case OP_GETRF: {
+            const double n = o.dim[0];
+            return 2.0 * n * n * n / 3.0;
+        }
+        default: return 0.0;
+    }
+}
+
 template <class T>
 __device__ void run_program(const Inst<T>& d, Shared& sh, int step) {
     const int nops = d.nops;
@@ -387,6 +477,10 @@ __device__ void run_program(const Inst<T>& d, Shared& sh, int step) {
     double* Xs = d.X + (int64_t)step * d.xstep;
     for (int pc = 0; pc < nops; ++pc) {
         const OpRec o = d.ops[pc];
+        unsigned long long t0 = 0;
+        if (d.prof && threadIdx.x == 0) t0 = wall_clock64();
+        double fl = 0.0;
+        if (threadIdx.x == 0) fl = op_flops(d, o);
         switch (o.code) {
             case OP_GEMM: op_gemm(d, o); break;
             case OP_ZERO: op_zero(d, o); break;
@@ -410,6 +504,14 @@ __device__ void run_program(const Inst<T>& d, Shared& sh, int step) {
             default: break;
         }
         __syncthreads();
+        if (threadIdx.x == 0) {
+            if (o.code == OP_LRSUB) fl += sh.lrsub_flops;
+            atomicAdd(d.flops, fl);
+        }
+        if (d.prof && threadIdx.x == 0) {
+            atomicAdd(&d.prof[2 * o.code], (unsigned long long)(wall_clock64() - t0));
+            atomicAdd(&d.prof[2 * o.code + 1], 1ull);
+        }
     }
 }
 
@@ -426,6 +528,23 @@ __global__ void __launch_bounds__(kT) k_interp_one(const Inst<T> d) {
 }
 
 }  // namespace
+
+bool profile_ops_enabled() {
+    const char* e = getenv("FDE_PROFILE_OPS");
+    return e && e[0] == '1';
+}
+
+void print_op_profile(const char* what, const unsigned long long* p, int device) {
+    int rate_khz = 0;
+    (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device);
+    const double ms_per_tick = rate_khz > 0 ? 1.0 / rate_khz : 0.0;
+    static const char* names[8] = {"-", "GETRF", "TRSM", "GEMM", "LRSUB", "ZERO", "LOAD", "STORE"};
+    fprintf(stderr, "[fde ops] %s:", what);
+    for (int c = 1; c < 8; ++c)
+        if (p[2 * c + 1]) fprintf(stderr, " %s %llu x %.3f ms = %.2f ms;", names[c], p[2 * c + 1],
+                                  p[2 * c] * ms_per_tick / p[2 * c + 1], p[2 * c] * ms_per_tick);
+    fprintf(stderr, "\n");
+}
 
 template <class T>
 void launch_interp(hipStream_t st, int ninst, const Inst<T>* d_insts, int step) {

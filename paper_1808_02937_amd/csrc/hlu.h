@@ -23,6 +23,9 @@ struct HLUObj {
     DevBuf<char> arena, work_lu, scr, sv_rhs, sv_work;
     DevBuf<double> scrd;
     DevBuf<int> ranks, status, h2p;
+    DevBuf<unsigned long long> prof;   // op profile (FDE_PROFILE_OPS=1)
+    DevBuf<double> flops;              // [0] factorisation, [1] H-solves
+    double factor_ms = 0.0;
     DevBuf<LRBlockDev> lr;
     DevBuf<OpRec> ops_lu, ops_sv;
     int64_t scr_t = 0, scr_d = 0;
@@ -55,6 +58,8 @@ struct HLUObj {
         d.kmax = kmax;
         d.pivot_floor = pivot_floor;
         d.status = status.p;
+        d.prof = prof.p;
+        d.flops = flops.p + (solve ? 1 : 0);
         return d;
     }
 };

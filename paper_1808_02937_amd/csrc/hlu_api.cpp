@@ -112,19 +112,49 @@ void build_hmat(fde_hmat* hm, Op* op, const fde_hparams* prm) {
     FDE_HIP(hipStreamSynchronize(c->stream));
 }
 
+void report_profile(HLUObj* f, const char* what) {
+    if (!f->prof.p) return;
+    unsigned long long h[16];
+    FDE_HIP(hipMemcpy(h, f->prof.p, sizeof h, hipMemcpyDeviceToHost));
+    print_op_profile(what, h, f->op->ctx->device);
+    FDE_HIP(hipMemset(f->prof.p, 0, sizeof h));
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair() {
+        FDE_HIP(hipEventCreate(&a));
+        FDE_HIP(hipEventCreate(&b));
+    }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    float ms() {
+        float t = 0.f;
+        FDE_HIP(hipEventElapsedTime(&t, a, b));
+        return t;
+    }
+};
+
 template <class T>
 void factor_run(HLUObj* f) {
     Ctx* c = f->op->ctx;
     Inst<T> d = f->inst<T>(false, 0, nullptr, 0, nullptr, 0);
+    EventPair ev;
+    FDE_HIP(hipEventRecord(ev.a, c->stream));
     launch_interp_one<T>(c->stream, d);
+    FDE_HIP(hipEventRecord(ev.b, c->stream));
     int st[2] = {0, 0};
     FDE_HIP(hipMemcpyAsync(st, f->status.p, sizeof st, hipMemcpyDeviceToHost, c->stream));
     FDE_HIP(hipStreamSynchronize(c->stream));
+    f->factor_ms = ev.ms();
     if (st[0] == FDE_EBREAKDOWN) fail(FDE_EBREAKDOWN, "H-LU breakdown: leaf pivot below the floor (op %d)", st[1]);
     if (st[0] != 0) fail(FDE_EDEVICE, "H-LU status %d", st[0]);
+    report_profile(f, "H-LU");
 }
 
-void factor(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
+void factor_prepare(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
     Op* op = hm->t.op;
     Ctx* c = op->ctx;
     f->hm = hm;
@@ -155,6 +185,12 @@ void factor(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
     f->scrd.alloc(c, f->scr_d);
     f->status.alloc(c, 2);
     FDE_HIP(hipMemsetAsync(f->status.p, 0, 2 * sizeof(int), c->stream));
+    f->flops.alloc(c, 2);
+    FDE_HIP(hipMemsetAsync(f->flops.p, 0, 2 * sizeof(double), c->stream));
+    if (profile_ops_enabled()) {
+        f->prof.alloc(c, 16);
+        FDE_HIP(hipMemsetAsync(f->prof.p, 0, 16 * sizeof(unsigned long long), c->stream));
+    }
     upload_vec(c, f->h2p, f->t.h2p);
     upload_vec(c, f->ranks, hm->init_rank);
     upload_vec(c, f->ops_lu, f->lu.ops);
@@ -179,15 +215,45 @@ void factor(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
     }
     DevBuf<SegDev> d_segs;
     upload_vec(c, d_segs, segs);
-    if (f->prec == FDE_FP64) {
+    if (f->prec == FDE_FP64)
         launch_segcopy<double, double>(c->stream, (int)segs.size(), d_segs.p, hm->d_arena.p,
                                        reinterpret_cast<double*>(f->arena.p));
-        factor_run<double>(f);
-    } else {
+    else
         launch_segcopy<double, float>(c->stream, (int)segs.size(), d_segs.p, hm->d_arena.p,
                                       reinterpret_cast<float*>(f->arena.p));
+    FDE_HIP(hipStreamSynchronize(c->stream));   // the segment table is freed on return
+}
+
+void factor(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
+    factor_prepare(f, hm, prm);
+    if (f->prec == FDE_FP64)
+        factor_run<double>(f);
+    else
         factor_run<float>(f);
+}
+
+template <class T>
+void factor_batch_run(Ctx* c, std::vector<HLUObj*>& fs) {
+    std::vector<Inst<T>> ins;
+    for (HLUObj* f : fs) ins.push_back(f->inst<T>(false, 0, nullptr, 0, nullptr, 0));
+    DevBuf<Inst<T>> d_ins;
+    upload_vec(c, d_ins, ins);
+    EventPair ev;
+    FDE_HIP(hipEventRecord(ev.a, c->stream));
+    launch_interp<T>(c->stream, (int)ins.size(), d_ins.p, 0);
+    FDE_HIP(hipEventRecord(ev.b, c->stream));
+    std::vector<int> st(2 * fs.size());
+    for (size_t i = 0; i < fs.size(); ++i)
+        FDE_HIP(hipMemcpyAsync(&st[2 * i], fs[i]->status.p, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    FDE_HIP(hipStreamSynchronize(c->stream));
+    const float ms = ev.ms();
+    for (HLUObj* f : fs) f->factor_ms = ms;
+    for (size_t i = 0; i < fs.size(); ++i) {
+        if (st[2 * i] == FDE_EBREAKDOWN)
+            fail(FDE_EBREAKDOWN, "H-LU breakdown in H-matrix %zu: leaf pivot below the floor (op %d)", i, st[2 * i + 1]);
+        if (st[2 * i] != 0) fail(FDE_EDEVICE, "H-LU status %d in H-matrix %zu", st[2 * i], i);
     }
+    for (HLUObj* f : fs) report_profile(f, "H-LU (batched)");
 }
 
 }  // namespace
@@ -290,9 +356,41 @@ int fde_hlu_factor(fde_hmat* hm, const fde_hlu_params* prm, fde_hlu** out) {
     FDE_API_END
 }
 
+int fde_hlu_factor_batched(int n, fde_hmat* const* hms, const fde_hlu_params* prm, fde_hlu** out) {
+    FDE_API_BEGIN
+    if (n < 0 || (n > 0 && (!hms || !out))) fail(FDE_EINVAL, "bad arguments");
+    for (int i = 0; i < n; ++i) out[i] = nullptr;
+    if (n == 0) return FDE_OK;
+    std::vector<HLUObj*> fs;
+    Ctx* c = nullptr;
+    try {
+        for (int i = 0; i < n; ++i) {
+            if (!hms[i]) fail(FDE_EINVAL, "H-matrix %d is NULL", i);
+            if (!c) c = hms[i]->t.op->ctx;
+            if (hms[i]->t.op->ctx != c) fail(FDE_EINVAL, "H-matrices from different contexts");
+            fde_hlu* f = new fde_hlu();
+            fs.push_back(f);
+            factor_prepare(f, hms[i], prm);
+        }
+        std::vector<HLUObj*> f32, f64;
+        for (HLUObj* f : fs) (f->prec == FDE_FP64 ? f64 : f32).push_back(f);
+        if (!f32.empty()) factor_batch_run<float>(c, f32);
+        if (!f64.empty()) factor_batch_run<double>(c, f64);
+    } catch (...) {
+        for (HLUObj* f : fs) delete static_cast<fde_hlu*>(f);
+        throw;
+    }
+    for (int i = 0; i < n; ++i) out[i] = static_cast<fde_hlu*>(fs[i]);
+    FDE_API_END
+}
+
 void fde_hlu_destroy(fde_hlu* f) {
     if (!f) return;
     (void)hipDeviceSynchronize();
+    try {
+        report_profile(f, "H-solves");
+    } catch (...) {
+    }
     delete f;
 }
 
@@ -311,6 +409,18 @@ int fde_hlu_to_dense(fde_hlu* f, double* out, int ld, int* h2p) {
                                nullptr, out, ld);
     FDE_HIP(hipStreamSynchronize(c->stream));
     if (h2p) std::memcpy(h2p, f->t.h2p.data(), f->t.h2p.size() * sizeof(int));
+    FDE_API_END
+}
+
+int fde_hlu_stats(fde_hlu* f, double* factor_flops, double* factor_ms, double* solve_flops) {
+    FDE_API_BEGIN
+    if (!f) fail(FDE_EINVAL, "null factor");
+    double fl[2] = {0.0, 0.0};
+    FDE_HIP(hipMemcpyAsync(fl, f->flops.p, sizeof fl, hipMemcpyDeviceToHost, f->op->ctx->stream));
+    FDE_HIP(hipStreamSynchronize(f->op->ctx->stream));
+    if (factor_flops) *factor_flops = fl[0];
+    if (factor_ms) *factor_ms = f->factor_ms;
+    if (solve_flops) *solve_flops = fl[1];
     FDE_API_END
 }
 

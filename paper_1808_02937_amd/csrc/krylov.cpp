@@ -40,6 +40,7 @@ Inst<T> group_inst(Group& g, int m) {
     d.work = reinterpret_cast<T*>(g.work.p);
     d.rhs = reinterpret_cast<T*>(g.rhs.p);
     d.bstep = (int64_t)g.op->Nd * g.nr;
+    d.flops = g.prec->flops.p + 1;
     d.xstep = (int64_t)g.op->Nd * g.nr;
     (void)m;
     return d;

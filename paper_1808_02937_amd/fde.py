@@ -215,10 +215,36 @@ class HLU(_Handle):
         check(load().fde_hlu_to_dense(self.h, _dptr(Ft), Nd, h2p.ctypes.data_as(A.ip)))
         return Ft.t(), h2p
 
+    def stats(self):
+        """(factor flops, factorisation launch ms, H-solve flops so far)."""
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        check(load().fde_hlu_stats(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
     def max_rank(self) -> int:
         r = C.c_int()
         check(load().fde_hlu_max_rank(self.h, C.byref(r)))
         return r.value
+
+
+def factor_batched(hms: Sequence[HMatrix], tol: float = 1e-3, rank_cap: int = 0, precision: str = "fp32",
+                   pivot_floor: float = 1e-14):
+    """H-LU of several H-matrices in one device launch (one workgroup each)."""
+    n = len(hms)
+    prec = {"fp64": A.FDE_FP64, "fp32": A.FDE_FP32}[precision]
+    p = A.HLUParams(float(tol), int(rank_cap), prec, float(pivot_floor))
+    arr = (C.c_void_p * n)(*[hm.h.value for hm in hms])
+    out = (C.c_void_p * n)()
+    check(load().fde_hlu_factor_batched(n, arr, C.byref(p), out))
+    res = []
+    for hm, h in zip(hms, out):
+        obj = HLU.__new__(HLU)
+        obj.hm = hm
+        obj.Nd = hm.op.Nd
+        obj.device = hm.op.ctx.device
+        obj._init_handle(C.c_void_p(h), hm)
+        res.append(obj)
+    return res
 
 
 def _solve_params(rtol, restart, maxit):

@@ -192,3 +192,13 @@ def test_toeplitz_apply_equals_dense(mesh):
     A = sem.system_matrix()
     x = np.random.default_rng(3).standard_normal((sem.Nd, 2))
     assert np.linalg.norm(toeplitz.apply(sem, x) - A @ x) <= 1e-14 * np.linalg.norm(A @ x)
+
+
+def test_dense_from_generators_and_hmatrix_with_given_matrix():
+    sem = SEM(fi.uniform_mesh(19), 4, 1.45, 0.6, 0.8)
+    A = sem.system_matrix()
+    Ag = toeplitz.dense_matrix(sem)
+    assert np.abs(A - Ag).max() <= 1e-14 * np.abs(A).max()
+    H1 = HMatrix(sem, 5, 1.0, 2)
+    H2 = HMatrix(sem, 5, 1.0, 2, A=Ag)
+    assert np.abs(to_dense(H1.root) - to_dense(H2.root)).max() <= 1e-14 * np.abs(A).max()
