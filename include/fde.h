@@ -161,12 +161,41 @@ int  fde_hmat_to_dense(fde_hmat* hm, double* out_dev, int ld);
 
 /* ---- H-LU and H-solves (Section 4.1) ---------------------------------- */
 
+/* The recursion of Section 4.1 is flattened into an op list and scheduled in
+ * levels: the ops of a level are independent (they touch no element another
+ * op of the level writes) and run concurrently, one workgroup each, one
+ * kernel launch per level. The op lists depend only on the structure (mesh,
+ * H-matrix parameters, rank capacity); a context keeps the 8 most recently
+ * used ones and frees them when it is destroyed. */
 int  fde_hlu_factor(fde_hmat* hm, const fde_hlu_params* prm, fde_hlu** out);
-/* Factor n H-matrices (any sizes) with the same parameters in one device
- * launch, one workgroup per H-matrix; out[i] receives each factor. On any
+/* Factor n H-matrices (any sizes) with the same parameters together: launch l
+ * runs level l of every factorisation; out[i] receives each factor. On any
  * failure no factor is returned (out[] all NULL) and the status of the first
  * failing H-matrix is returned. */
 int  fde_hlu_factor_batched(int n, fde_hmat* const* hms, const fde_hlu_params* prm, fde_hlu** out);
+
+/* Host-only plan of the H-LU of an operator on `nodes` (N+1 increasing
+ * abscissae, polynomial degree P) with H-matrix parameters hp (NULL: defaults)
+ * and rank capacity rank_cap (<= 0: R): sizes of its op lists and schedule and
+ * the device memory one factorisation allocates. Needs no device. check != 0
+ * also replays the program element by element and verifies that the schedule
+ * orders every pair of conflicting accesses and that temporaries sharing
+ * memory are never live in the same level (slow: for tests); a violation
+ * returns FDE_EDEVICE. */
+typedef struct {
+    long long ops;             /* ops of the H-LU program */
+    int levels;                /* levels of its schedule (critical path, in ops) */
+    int max_width;             /* most ops in one level */
+    long long solve_ops;       /* ops of the H-solve program */
+    long long arena_elems;     /* factor storage, elements of the factor precision */
+    long long work_elems;      /* H-LU temporaries, elements of the factor precision */
+    long long scratch_elems;   /* recompression scratch, elements of the factor precision */
+    long long scratch_f64;     /* recompression scratch, doubles */
+    long long bytes_fp32;      /* device bytes one FP32 factorisation allocates */
+    long long bytes_fp64;      /* device bytes one FP64 factorisation allocates */
+} fde_hlu_plan_info;
+int  fde_hlu_plan(const double* nodes_host, int N, int P, const fde_hparams* hp, int rank_cap, int check,
+                  fde_hlu_plan_info* out);
 void fde_hlu_destroy(fde_hlu* f);
 /* L_H (strict lower part, unit diagonal implied) and U_H packed in one
  * Nd x Nd column-major matrix in the H-matrix's internal order; h2p_host (if

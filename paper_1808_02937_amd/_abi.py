@@ -46,6 +46,15 @@ class SolveInfo(C.Structure):
     _fields_ = [("iters", i32), ("relres", f64), ("status", i32)]
 
 
+ll = C.c_longlong
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("ops", ll), ("levels", i32), ("max_width", i32), ("solve_ops", ll), ("arena_elems", ll),
+                ("work_elems", ll), ("scratch_elems", ll), ("scratch_f64", ll), ("bytes_fp32", ll),
+                ("bytes_fp64", ll)]
+
+
 FN = C.CFUNCTYPE(C.c_double, C.c_double, C.c_void_p)
 
 # name -> (restype, argtypes); every symbol declared in include/fde.h
@@ -70,6 +79,7 @@ SIGNATURES = {
     "fde_hmat_to_dense": (i32, [vp, vp, i32]),
     "fde_hlu_factor": (i32, [vp, C.POINTER(HLUParams), C.POINTER(vp)]),
     "fde_hlu_factor_batched": (i32, [i32, C.POINTER(vp), C.POINTER(HLUParams), C.POINTER(vp)]),
+    "fde_hlu_plan": (i32, [dp, i32, i32, C.POINTER(HParams), i32, i32, C.POINTER(PlanInfo)]),
     "fde_hlu_destroy": (None, [vp]),
     "fde_hlu_to_dense": (i32, [vp, vp, i32, ip]),
     "fde_hlu_max_rank": (i32, [vp, ip]),

@@ -93,8 +93,8 @@ void element_load_rule(const Op* op, int e, std::vector<double>& xs, std::vector
     auto add_panel = [&](double lo, double hi, int n, int side) {
         // lo, hi: distances from the element end on `side` (0: x_e, 1: x_{e+1})
         n = std::min(std::max(n, 1), kMaxGL);
-        std::vector<double> gx(n), gw(n);
-        gauss_jacobi(n, 0.0, 0.0, gx.data(), gw.data());
+        const double* gx = gauss_legendre_table() + n * (n - 1) / 2;
+        const double* gw = gx + kMaxGL * (kMaxGL + 1) / 2;
         for (int i = 0; i < n; ++i) {
             const double u = 0.5 * (hi - lo) * gx[i] + 0.5 * (hi + lo);
             const double w = 0.5 * (hi - lo) * gw[i];
@@ -213,14 +213,9 @@ void local_mass(int P, std::vector<double>& M) {
 }
 
 void init_ctx_tables(Ctx* c) {
-    const int tot = kMaxGL * (kMaxGL + 1) / 2;
-    std::vector<double> t(2 * tot);
-    for (int n = 1; n <= kMaxGL; ++n) {
-        const int off = n * (n - 1) / 2;
-        gauss_jacobi(n, 0.0, 0.0, t.data() + off, t.data() + tot + off);
-    }
-    c->gl.alloc(c, t.size());
-    upload(c, c->gl.p, t.data(), t.size() * sizeof(double));
+    const size_t cnt = (size_t)kMaxGL * (kMaxGL + 1);
+    c->gl.alloc(c, cnt);
+    upload(c, c->gl.p, gauss_legendre_table(), cnt * sizeof(double));
     FDE_HIP(hipStreamSynchronize(c->stream));
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstdarg>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -36,6 +37,9 @@ struct Error {
 void gauss_jacobi(int n, double a, double b, double* x, double* w);
 
 constexpr int kMaxGL = 64;  // Gauss-Legendre rules n = 1..kMaxGL live on the device
+// Gauss-Legendre rules n = 1..kMaxGL: nodes of rule n at offset n(n-1)/2, the weights
+// kMaxGL(kMaxGL+1)/2 entries further; computed on first use, read-only afterwards
+const double* gauss_legendre_table();
 
 // ---------------------------------------------------------------- memory
 struct Ctx;
@@ -65,12 +69,16 @@ struct DevBuf {
     size_t bytes() const { return n * sizeof(T); }
 };
 
+struct Plan;   // H-LU and H-solve programs of one H-matrix structure (hlu.h)
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     size_t budget = 0;   // 0: unlimited
     size_t in_use = 0;
     DevBuf<double> gl;   // Gauss-Legendre n=1..kMaxGL: nodes then weights, offset n(n-1)/2
+    // most recently used plans first, keyed by the structure they were made for
+    std::vector<std::pair<std::string, std::shared_ptr<Plan>>> plans;
 };
 
 // ---------------------------------------------------------------- operator

@@ -6,7 +6,7 @@
 namespace fde {
 
 constexpr int kInterpThreads = 256;
-constexpr int kMaxKp = 256;   // widest [U, X] recompressed in one OP_LRSUB
+constexpr int kMaxKp = kMaxKprime;
 
 template <class T>
 struct Inst {
@@ -17,10 +17,8 @@ struct Inst {
     T* rhs;                   // right-hand sides (Nd x nrhs, ld Nd) of an H-solve
     int* ranks;               // rank per low-rank block
     const LRBlockDev* lr;     // low-rank block table
-    T* scr;                   // recompression scratch (T)
+    T* scr;                   // recompression scratch (T); each OP_LRSUB uses its own part
     double* scrd;             // recompression scratch (FP64 core)
-    int64_t mrmax;            // scratch row capacity
-    int kpmax;                // scratch k' capacity
     const int* h2p;
     int Nd;
     const double* B;          // H-solve input (paper order, FP64); B + step * bstep at step `step`
@@ -41,9 +39,13 @@ struct Inst {
 bool profile_ops_enabled();
 void print_op_profile(const char* what, const unsigned long long* host_prof, int device);
 
+// serial: one workgroup runs the whole op list of each instance
 template <class T>
 void launch_interp(hipStream_t st, int ninst, const Inst<T>* d_insts, int step = 0);
 template <class T>
 void launch_interp_one(hipStream_t st, const Inst<T>& d);
+// one level of level-scheduled programs: workgroup b runs op tasks[b].y of instance tasks[b].x
+template <class T>
+void launch_level(hipStream_t st, int ntasks, const Inst<T>* d_insts, const int2* d_tasks);
 
 }  // namespace fde

@@ -24,10 +24,12 @@ constexpr int kT = kInterpThreads;
 constexpr int kW = kT / 64;
 
 struct Shared {
+    double part[1024];
     double red[kW][32];
     double dots[kMaxKp];
     int order[kMaxKp];
     int flag;
+    int stop;
     int r;
     int sweeps;
     double lrsub_flops;
@@ -365,25 +367,306 @@ __device__ void jacobi_svd(double* M, double* W, int kp, Shared& sh) {
     }
 }
 
+// ----- fast recompression for k' <= 32: FP64 Gram matrices + wavefront one-sided Jacobi
+
+// one-sided (Hestenes) Jacobi run by one wavefront: lane j holds column j of M (kp x kp, column-major
+// in global scratch); on return M holds the rotated columns, W the accumulated rotations and
+// nrm[j] = ||rotated column j||. Both lanes of a pair form the same dot products in the same order.
+template <int KP>
+__device__ void wave_jacobi(double* M, double* W, double* nrm, int kp) {
+    const int lane = threadIdx.x & 63;
+    double col[KP], w[KP];
+#pragma unroll
+    for (int i = 0; i < KP; ++i) {
+        col[i] = (lane < kp && i < kp) ? M[i + lane * kp] : 0.0;
+        w[i] = (i == lane) ? 1.0 : 0.0;
+    }
+    const int n2 = kp + (kp & 1);
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        bool rotated = false;
+        for (int r = 0; r < n2 - 1; ++r) {
+            int partner;
+            if (lane >= n2)
+                partner = lane;
+            else if (lane == n2 - 1)
+                partner = r;
+            else if (lane == r)
+                partner = n2 - 1;
+            else
+                partner = (((2 * r - lane) % (n2 - 1)) + (n2 - 1)) % (n2 - 1);
+            double a = 0.0, g = 0.0;
+#pragma unroll
+            for (int i = 0; i < KP; ++i) {
+                const double pv = __shfl(col[i], partner, 64);
+                a += col[i] * col[i];
+                g += (lane < partner) ? col[i] * pv : pv * col[i];
+            }
+            const double b = __shfl(a, partner, 64);
+            const bool valid = lane < kp && partner < kp && partner != lane;
+            const bool prole = lane < partner;
+            const double ap = prole ? a : b, aq = prole ? b : a;
+            const bool rot = valid && g != 0.0 && fabs(g) > 1e-15 * sqrt(ap * aq);
+            double c = 1.0, s = 0.0;
+            if (rot) {
+                const double zeta = (aq - ap) / (2.0 * g);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                c = 1.0 / sqrt(1.0 + t * t);
+                s = c * t;
+                rotated = true;
+            }
+#pragma unroll
+            for (int i = 0; i < KP; ++i) {
+                const double pv = __shfl(col[i], partner, 64);
+                const double pw = __shfl(w[i], partner, 64);
+                if (rot) {
+                    col[i] = prole ? c * col[i] - s * pv : s * pv + c * col[i];
+                    w[i] = prole ? c * w[i] - s * pw : s * pw + c * w[i];
+                }
+            }
+        }
+        if (!__any(rotated)) break;
+    }
+    if (lane < kp) {
+        double nn = 0.0;
+#pragma unroll
+        for (int i = 0; i < KP; ++i)
+            if (i < kp) {
+                M[i + lane * kp] = col[i];
+                W[i + lane * kp] = w[i];
+                nn += col[i] * col[i];
+            }
+        nrm[lane] = sqrt(nn);
+    }
+}
+
+template <class T>
+struct Cat {   // the columns of [A, sb * B]: rows i, A m x ka, B m x kb
+    const T* A;
+    int ars, acs, ka;
+    const T* B;
+    int brs, bcs, kb;
+    double sb;
+    __device__ double at(int i, int c) const {
+        return c < ka ? (double)A[(int64_t)i * ars + (int64_t)c * acs]
+                      : sb * (double)B[(int64_t)i * brs + (int64_t)(c - ka) * bcs];
+    }
+};
+
+// G (kp x kp, FP64, global scratch) = Cat^T Cat; threads split (entry, row slice); part in LDS
+template <class T>
+__device__ void gram(const Cat<T>& U, int m, int kp, double* G, double* part) {
+    const int nent = kp * (kp + 1) / 2;
+    int S = kT / nent;
+    if (S < 1) S = 1;
+    if (S > 64) S = 64;
+    for (int t = threadIdx.x; t < nent * S; t += kT) {
+        const int e = t % nent, sl = t / nent;
+        int q = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (q * (q + 1) / 2 > e) --q;
+        while ((q + 1) * (q + 2) / 2 <= e) ++q;
+        const int p = e - q * (q + 1) / 2;   // p <= q
+        const int r0 = (int)((int64_t)m * sl / S), r1 = (int)((int64_t)m * (sl + 1) / S);
+        double acc = 0.0;
+        for (int i = r0; i < r1; ++i) acc += U.at(i, p) * U.at(i, q);
+        part[t] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nent; e += kT) {
+        double acc = 0.0;
+        for (int sl = 0; sl < S; ++sl) acc += part[sl * nent + e];
+        int q = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (q * (q + 1) / 2 > e) --q;
+        while ((q + 1) * (q + 2) / 2 <= e) ++q;
+        const int p = e - q * (q + 1) / 2;
+        G[p + q * kp] = acc;
+        G[q + p * kp] = acc;
+    }
+    __syncthreads();
+}
+
+// From the eigen-decomposition G = W diag(lam) W^T (rotated columns in G, norms lam):
+// R = diag(sqrt lam) W^T and F = W diag(lam^{+1/2}) (pseudo-inverse square root)
+__device__ void side_factors(const double* W, const double* lam, int kp, double* R, double* F) {
+    double lmax = 0.0;
+    for (int j = 0; j < kp; ++j) lmax = fmax(lmax, lam[j]);
+    const double floor_ = kp * 2.3e-16 * lmax;
+    for (int idx = threadIdx.x; idx < kp * kp; idx += kT) {
+        const int i = idx % kp, j = idx / kp;
+        const double li = lam[i];
+        const bool keep = li > floor_ && li > 0.0;
+        R[i + j * kp] = keep ? sqrt(li) * W[j + i * kp] : 0.0;         // R[i][j] = sqrt(lam_i) W[j][i]
+        const double lj = lam[j];
+        F[i + j * kp] = (lj > floor_ && lj > 0.0) ? W[i + j * kp] / sqrt(lj) : 0.0;
+    }
+}
+
+// C = A B (kp x kp, column-major, FP64 scratch)
+__device__ void small_mm(const double* A, const double* B, double* C, int kp) {
+    for (int idx = threadIdx.x; idx < kp * kp; idx += kT) {
+        const int i = idx % kp, j = idx / kp;
+        double s = 0.0;
+        for (int l = 0; l < kp; ++l) s += A[i + l * kp] * B[l + j * kp];
+        C[i + j * kp] = s;
+    }
+}
+
+template <class T>
+__device__ void op_lrsub_fast(const Inst<T>& d, const OpRec& o, Shared& sh, const LRBlockDev& L, int kc, int kx) {
+    T* U = d.arena + L.uoff;
+    T* V = d.arena + L.voff;
+    const int m = L.m, n = L.n, kp = kc + kx;
+    const int wave = threadIdx.x >> 6;
+    const T* Xp = vptr(d, o.v[0]);
+    const T* Yp = vptr(d, o.v[1]);
+    const Cat<T> Uc{U, 1, m, kc, Xp, o.v[0].rs, o.v[0].cs, kx, -1.0};
+    const Cat<T> Vc{V, 1, n, kc, Yp, o.v[1].rs, o.v[1].cs, kx, 1.0};
+    const int K2 = kp * kp;
+    double* base = d.scrd + o.sofs_d;
+    double *Gu = base, *Gv = Gu + K2, *Wu = Gv + K2, *Wv = Wu + K2, *Ru = Wv + K2, *Rv = Ru + K2;
+    double *Fu = Rv + K2, *Fv = Fu + K2, *Mc = Fv + K2, *Wm = Mc + K2, *T1 = Wm + K2, *T2 = T1 + K2;
+    double *lu = T2 + K2, *lv = lu + 32, *sg = lv + 32;
+    double* Qs = sg + 32;   // FP64 copy of the orthogonalised rows for the second pass (max rows x kp)
+    double* part = sh.part;
+    gram(Uc, m, kp, Gu, part);
+    gram(Vc, n, kp, Gv, part);
+    if (wave == 0) {
+        if (kp <= 16) wave_jacobi<16>(Gu, Wu, lu, kp); else wave_jacobi<32>(Gu, Wu, lu, kp);
+    } else if (wave == 1) {
+        if (kp <= 16) wave_jacobi<16>(Gv, Wv, lv, kp); else wave_jacobi<32>(Gv, Wv, lv, kp);
+    }
+    __syncthreads();
+    side_factors(Wu, lu, kp, Ru, Fu);
+    side_factors(Wv, lv, kp, Rv, Fv);
+    __syncthreads();
+    if (sizeof(T) == 8) {
+        // second pass: Q1 = U' F, G2 = Q1^T Q1 = W2 diag(l2) W2^T, R <- R2 R1, F <- F1 F2
+        for (int side = 0; side < 2; ++side) {
+            const Cat<T>& C = side == 0 ? Uc : Vc;
+            const int rows = side == 0 ? m : n;
+            double* F = side == 0 ? Fu : Fv;
+            double* R = side == 0 ? Ru : Rv;
+            for (int i = threadIdx.x; i < rows; i += kT) {
+                double row[32];
+#pragma unroll
+                for (int l = 0; l < 32; ++l) row[l] = l < kp ? C.at(i, l) : 0.0;
+                for (int c = 0; c < kp; ++c) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int l = 0; l < 32; ++l)
+                        if (l < kp) s += row[l] * F[l + c * kp];
+                    Qs[(int64_t)i + (int64_t)c * rows] = s;
+                }
+            }
+            __syncthreads();
+            const Cat<double> Q{Qs, 1, rows, kp, nullptr, 0, 0, 0, 0.0};
+            gram(Q, rows, kp, Gu, part);
+            if (wave == 0) {
+                if (kp <= 16) wave_jacobi<16>(Gu, Wu, lu, kp); else wave_jacobi<32>(Gu, Wu, lu, kp);
+            }
+            __syncthreads();
+            side_factors(Wu, lu, kp, T1, T2);   // T1 = R2, T2 = F2
+            __syncthreads();
+            small_mm(T1, R, Mc, kp);             // R2 R1
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < K2; idx += kT) R[idx] = Mc[idx];
+            __syncthreads();
+            small_mm(F, T2, Mc, kp);             // F1 F2
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < K2; idx += kT) F[idx] = Mc[idx];
+            __syncthreads();
+        }
+    }
+    // core M = R_u R_v^T and its SVD
+    for (int idx = threadIdx.x; idx < K2; idx += kT) {
+        const int i = idx % kp, j = idx / kp;
+        double s = 0.0;
+        for (int l = 0; l < kp; ++l) s += Ru[i + l * kp] * Rv[j + l * kp];
+        Mc[idx] = s;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        if (kp <= 16) wave_jacobi<16>(Mc, Wm, sg, kp); else wave_jacobi<32>(Mc, Wm, sg, kp);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < kp; j += kT) {
+        int r = 0;
+        const double sj = sg[j];
+        for (int i = 0; i < kp; ++i) r += (sg[i] > sj || (sg[i] == sj && i < j)) ? 1 : 0;
+        sh.order[r] = j;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double smax = sg[sh.order[0]];
+        int r = 0;
+        if (smax > 0.0)
+            while (r < kp && sg[sh.order[r]] > d.tol * smax) ++r;
+        if (r > d.kmax) r = d.kmax;
+        sh.r = r;
+        d.ranks[L.slot] = r;
+        const double K = kp;
+        sh.lrsub_flops = 2.0 * (m + n) * K * (K + 1.0) * (sizeof(T) == 8 ? 2.0 : 1.0) + 2.0 * (m + n) * K * r;
+    }
+    __syncthreads();
+    const int r = sh.r;
+    // Cu[:, c] = F_u * (M W)[:, order c] ; Cv[:, c] = F_v * W_m[:, order c]   (kp x r, into T1 / T2)
+    for (int idx = threadIdx.x; idx < kp * r; idx += kT) {
+        const int i = idx % kp, c = idx / kp, jc = sh.order[c];
+        double su = 0.0, sv = 0.0;
+        for (int l = 0; l < kp; ++l) {
+            su += Fu[i + l * kp] * Mc[l + jc * kp];
+            sv += Fv[i + l * kp] * Wm[l + jc * kp];
+        }
+        T1[i + c * kp] = su;
+        T2[i + c * kp] = sv;
+    }
+    __syncthreads();
+    // row-local, in place: U[i, :r] = U'[i, :] Cu, V[j, :r] = V'[j, :] Cv
+    for (int i = threadIdx.x; i < m + n; i += kT) {
+        const bool isu = i < m;
+        const int row = isu ? i : i - m;
+        const Cat<T>& C = isu ? Uc : Vc;
+        const double* Cm = isu ? T1 : T2;
+        T* out = isu ? U : V;
+        const int ld = isu ? m : n;
+        double rv[32];
+#pragma unroll
+        for (int l = 0; l < 32; ++l) rv[l] = l < kp ? C.at(row, l) : 0.0;
+        for (int c = 0; c < r; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int l = 0; l < 32; ++l)
+                if (l < kp) s += rv[l] * Cm[l + c * kp];
+            out[row + (int64_t)c * ld] = (T)s;
+        }
+    }
+    __syncthreads();
+}
+
 template <class T>
 __device__ void op_lrsub(const Inst<T>& d, const OpRec& o, Shared& sh) {
     const int kx = dimval(d, o.dim[2]);
     if (threadIdx.x == 0) sh.lrsub_flops = 0.0;
     if (kx <= 0) return;
     const LRBlockDev L = d.lr[o.blk];
+    // k' <= 32: Gram-based recompression (accurate to ~kappa^2 eps in the kept directions)
+    if (d.ranks[L.slot] + kx <= 32) {
+        op_lrsub_fast(d, o, sh, L, d.ranks[L.slot], kx);
+        return;
+    }
     T* U = d.arena + L.uoff;
     T* V = d.arena + L.voff;
     const int m = L.m, n = L.n, kc = d.ranks[L.slot], kp = kc + kx;
     const T* Xp = vptr(d, o.v[0]);
     const T* Yp = vptr(d, o.v[1]);
     const int xrs = o.v[0].rs, xcs = o.v[0].cs, yrs = o.v[1].rs, ycs = o.v[1].cs;
-    T* Up = d.scr;
-    T* Vp = Up + d.mrmax * d.kpmax;
-    T* Ru = Vp + d.mrmax * d.kpmax;
-    T* Rv = Ru + (int64_t)d.kpmax * d.kpmax;
-    double* Md = d.scrd;
-    double* Wd = Md + (int64_t)d.kpmax * d.kpmax;
-    double* sig = Wd + (int64_t)d.kpmax * d.kpmax;
+    // private scratch of this op: [U, -X], [V, Y], R_u, R_v; FP64 core, rotations, singular values
+    T* Up = d.scr + o.sofs_t;
+    T* Vp = Up + (int64_t)m * kp;
+    T* Ru = Vp + (int64_t)n * kp;
+    T* Rv = Ru + (int64_t)kp * kp;
+    double* Md = d.scrd + o.sofs_d;
+    double* Wd = Md + (int64_t)kp * kp;
+    double* sig = Wd + (int64_t)kp * kp;
     for (int64_t idx = threadIdx.x; idx < (int64_t)m * kp; idx += kT) {
         const int i = (int)(idx % m), c = (int)(idx / m);
         Up[idx] = c < kc ? U[i + (int64_t)c * m] : -Xp[(int64_t)i * xrs + (int64_t)(c - kc) * xcs];
@@ -470,49 +753,56 @@ __device__ double op_flops(const Inst<T>& d, const OpRec& o) {
     }
 }
 
+// one op; false when a leaf pivot broke down (the status is set)
+template <class T>
+__device__ bool run_op(const Inst<T>& d, int pc, Shared& sh, int step) {
+    const OpRec o = d.ops[pc];
+    unsigned long long t0 = 0;
+    if (d.prof && threadIdx.x == 0) t0 = wall_clock64();
+    double fl = 0.0;
+    if (threadIdx.x == 0) fl = op_flops(d, o);
+    bool ok = true;
+    switch (o.code) {
+        case OP_GEMM: op_gemm(d, o); break;
+        case OP_ZERO: op_zero(d, o); break;
+        case OP_TRSM: op_trsm(d, o); break;
+        case OP_LRSUB: op_lrsub(d, o, sh); break;
+        case OP_GETRF: ok = op_getrf(d, o, sh, pc); break;
+        case OP_LOAD: {
+            const double* Bs = d.B + (int64_t)step * d.bstep;
+            for (int64_t idx = threadIdx.x; idx < (int64_t)d.Nd * d.nrhs; idx += kT) {
+                const int h = (int)(idx % d.Nd), j = (int)(idx / d.Nd);
+                d.rhs[idx] = (T)Bs[(int64_t)j * d.ldb + d.h2p[h]];
+            }
+            break;
+        }
+        case OP_STORE: {
+            double* Xs = d.X + (int64_t)step * d.xstep;
+            for (int64_t idx = threadIdx.x; idx < (int64_t)d.Nd * d.nrhs; idx += kT) {
+                const int h = (int)(idx % d.Nd), j = (int)(idx / d.Nd);
+                Xs[(int64_t)j * d.ldx + d.h2p[h]] = (double)d.rhs[idx];
+            }
+            break;
+        }
+        default: break;
+    }
+    if (!ok) return false;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (o.code == OP_LRSUB) fl += sh.lrsub_flops;
+        atomicAdd(d.flops, fl);
+    }
+    if (d.prof && threadIdx.x == 0) {
+        atomicAdd(&d.prof[2 * o.code], (unsigned long long)(wall_clock64() - t0));
+        atomicAdd(&d.prof[2 * o.code + 1], 1ull);
+    }
+    return true;
+}
+
 template <class T>
 __device__ void run_program(const Inst<T>& d, Shared& sh, int step) {
-    const int nops = d.nops;
-    const double* Bs = d.B + (int64_t)step * d.bstep;
-    double* Xs = d.X + (int64_t)step * d.xstep;
-    for (int pc = 0; pc < nops; ++pc) {
-        const OpRec o = d.ops[pc];
-        unsigned long long t0 = 0;
-        if (d.prof && threadIdx.x == 0) t0 = wall_clock64();
-        double fl = 0.0;
-        if (threadIdx.x == 0) fl = op_flops(d, o);
-        switch (o.code) {
-            case OP_GEMM: op_gemm(d, o); break;
-            case OP_ZERO: op_zero(d, o); break;
-            case OP_TRSM: op_trsm(d, o); break;
-            case OP_LRSUB: op_lrsub(d, o, sh); break;
-            case OP_GETRF:
-                if (!op_getrf(d, o, sh, pc)) return;
-                break;
-            case OP_LOAD:
-                for (int64_t idx = threadIdx.x; idx < (int64_t)d.Nd * d.nrhs; idx += kT) {
-                    const int h = (int)(idx % d.Nd), j = (int)(idx / d.Nd);
-                    d.rhs[idx] = (T)Bs[(int64_t)j * d.ldb + d.h2p[h]];
-                }
-                break;
-            case OP_STORE:
-                for (int64_t idx = threadIdx.x; idx < (int64_t)d.Nd * d.nrhs; idx += kT) {
-                    const int h = (int)(idx % d.Nd), j = (int)(idx / d.Nd);
-                    Xs[(int64_t)j * d.ldx + d.h2p[h]] = (double)d.rhs[idx];
-                }
-                break;
-            default: break;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            if (o.code == OP_LRSUB) fl += sh.lrsub_flops;
-            atomicAdd(d.flops, fl);
-        }
-        if (d.prof && threadIdx.x == 0) {
-            atomicAdd(&d.prof[2 * o.code], (unsigned long long)(wall_clock64() - t0));
-            atomicAdd(&d.prof[2 * o.code + 1], 1ull);
-        }
-    }
+    for (int pc = 0; pc < d.nops; ++pc)
+        if (!run_op(d, pc, sh, step)) return;
 }
 
 template <class T>
@@ -525,6 +815,20 @@ template <class T>
 __global__ void __launch_bounds__(kT) k_interp_one(const Inst<T> d) {
     __shared__ Shared sh;
     run_program(d, sh, 0);
+}
+
+// one level: the ops of a level are independent, earlier levels have completed (kernel order)
+template <class T>
+__global__ void __launch_bounds__(kT) k_level(const Inst<T>* __restrict__ insts, const int2* __restrict__ tasks) {
+    __shared__ Shared sh;
+    const int2 tk = tasks[blockIdx.x];
+    const Inst<T>& d = insts[tk.x];
+    // after a breakdown in an earlier level the rest of that factorisation is skipped; the
+    // status is read once and shared so that every thread takes the same branch
+    if (threadIdx.x == 0) sh.stop = d.status[0];
+    __syncthreads();
+    if (sh.stop != 0) return;
+    run_op(d, tk.y, sh, 0);
 }
 
 }  // namespace
@@ -562,5 +866,14 @@ void launch_interp_one(hipStream_t st, const Inst<T>& d) {
 }
 template void launch_interp_one<float>(hipStream_t, const Inst<float>&);
 template void launch_interp_one<double>(hipStream_t, const Inst<double>&);
+
+template <class T>
+void launch_level(hipStream_t st, int ntasks, const Inst<T>* d_insts, const int2* d_tasks) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL((k_level<T>), dim3(ntasks), dim3(kT), 0, st, d_insts, d_tasks);
+    FDE_LAUNCH_CHECK();
+}
+template void launch_level<float>(hipStream_t, int, const Inst<float>*, const int2*);
+template void launch_level<double>(hipStream_t, int, const Inst<double>*, const int2*);
 
 }  // namespace fde

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <algorithm>
+#include <memory>
 
 #include "hinterp.h"
 
@@ -11,41 +12,54 @@ struct fde_hmat : fde::HMat {
 
 namespace fde {
 
+// Everything about a factorisation that depends only on the structure of the
+// H-matrix (mesh, leaf size, admissibility, rank capacity): the level-scheduled
+// H-LU program, the H-solve program, the low-rank block table and the index
+// map, on the host and on the device. Read-only once made; shared by every
+// factorisation of that structure in a context.
+struct Plan {
+    HTree t;               // t.op is cleared: a plan outlives the operator it was made for
+    Program lu, sv;
+    int kpmax = 0;
+    DevBuf<OpRec> ops_lu, ops_sv;
+    DevBuf<LRBlockDev> lr;
+    DevBuf<int> h2p;
+};
+
+// the plan for a factorisation with rank capacity kmax of an H-matrix (cached per context)
+std::shared_ptr<const Plan> get_plan(Ctx* c, const HTree& hmt, int kmax);
+// host-only plan (no device copies), for sizing and checking
+void make_plan_host(const HTree& hmt, int kmax, Plan& p, bool check);
+
 struct HLUObj {
     fde_hmat* hm = nullptr;
     Op* op = nullptr;
-    HTree t;
+    std::shared_ptr<const Plan> plan;
+    const HTree& t() const { return plan->t; }
     int prec = FDE_FP32;
     double tol = 1e-3, pivot_floor = 0.0;
     int kmax = 8;
-    Program lu, sv;
     size_t esz = 4;               // bytes per factor element
     DevBuf<char> arena, work_lu, scr, sv_rhs, sv_work;
     DevBuf<double> scrd;
-    DevBuf<int> ranks, status, h2p;
+    DevBuf<int> ranks, status;
     DevBuf<unsigned long long> prof;   // op profile (FDE_PROFILE_OPS=1)
     DevBuf<double> flops;              // [0] factorisation, [1] H-solves
     double factor_ms = 0.0;
-    DevBuf<LRBlockDev> lr;
-    DevBuf<OpRec> ops_lu, ops_sv;
-    int64_t scr_t = 0, scr_d = 0;
-    int kpmax = 0;
     int64_t sv_nrhs_cap = 0;
     template <class T>
     Inst<T> inst(bool solve, int nrhs, const double* B, int ldb, double* X, int ldx) {
         Inst<T> d{};
-        d.ops = solve ? ops_sv.p : ops_lu.p;
-        d.nops = (int)(solve ? sv.ops.size() : lu.ops.size());
+        d.ops = solve ? plan->ops_sv.p : plan->ops_lu.p;
+        d.nops = (int)(solve ? plan->sv.ops.size() : plan->lu.ops.size());
         d.arena = reinterpret_cast<T*>(arena.p);
         d.work = reinterpret_cast<T*>(solve ? sv_work.p : work_lu.p);
         d.rhs = reinterpret_cast<T*>(sv_rhs.p);
         d.ranks = ranks.p;
-        d.lr = lr.p;
+        d.lr = plan->lr.p;
         d.scr = reinterpret_cast<T*>(scr.p);
         d.scrd = scrd.p;
-        d.mrmax = std::max(t.max_lr_rows, 1);
-        d.kpmax = kpmax;
-        d.h2p = h2p.p;
+        d.h2p = plan->h2p.p;
         d.Nd = op->Nd;
         d.B = B;
         d.ldb = ldb;

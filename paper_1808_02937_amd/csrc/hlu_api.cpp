@@ -49,20 +49,30 @@ void upload_vec(Ctx* c, DevBuf<V>& buf, const std::vector<V>& v) {
     if (!v.empty()) FDE_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, c->stream));
 }
 
-void build_hmat(fde_hmat* hm, Op* op, const fde_hparams* prm) {
+void tree_params(HTree& t, Op* op, const fde_hparams* prm) {
     const int R = prm ? prm->R : 8;
     const double lam = prm ? prm->lambda : 1.0;
     const int leaf = prm ? prm->leaf_elems : 8;
     if (R < 1 || R > 64) fail(FDE_EINVAL, "R must be in [1, 64] (got %d)", R);
     if (!(lam > 0.0) || !std::isfinite(lam)) fail(FDE_EINVAL, "lambda must be > 0 (got %g)", lam);
     if (leaf < 2) fail(FDE_EINVAL, "leaf_elems must be >= 2 (got %d)", leaf);
-    Ctx* c = op->ctx;
-    HTree& t = hm->t;
     t.op = op;
     t.R = R;
     t.leaf = leaf;
     t.lambda = lam;
     t.kmax = R;
+}
+
+int rank_capacity(const HTree& t, const fde_hlu_params* prm) {
+    const int cap = prm && prm->rank_cap > 0 ? prm->rank_cap : t.R;
+    return std::max(cap, t.R);
+}
+
+void build_hmat(fde_hmat* hm, Op* op, const fde_hparams* prm) {
+    Ctx* c = op->ctx;
+    HTree& t = hm->t;
+    tree_params(t, op, prm);
+    const int R = t.R;
     build_trees(&t);
     hm->d_arena.alloc(c, t.arena_elems);
     upload_vec(c, hm->d_h2p, t.h2p);
@@ -137,21 +147,62 @@ struct EventPair {
     }
 };
 
+bool serial_requested() {
+    const char* e = getenv("FDE_HLU_SERIAL");
+    return e && e[0] == '1';
+}
+
+// Factorise a batch of H-LUs of one precision. Level-scheduled: launch l runs level l of
+// every factorisation (one workgroup per op); FDE_HLU_SERIAL=1 runs each op list in one
+// workgroup instead (the same ops in the same level order, one at a time).
 template <class T>
-void factor_run(HLUObj* f) {
-    Ctx* c = f->op->ctx;
-    Inst<T> d = f->inst<T>(false, 0, nullptr, 0, nullptr, 0);
+void factor_batch_run(Ctx* c, std::vector<HLUObj*>& fs, const char* what) {
+    std::vector<Inst<T>> ins;
+    for (HLUObj* f : fs) ins.push_back(f->inst<T>(false, 0, nullptr, 0, nullptr, 0));
+    DevBuf<Inst<T>> d_ins;
+    upload_vec(c, d_ins, ins);
+    const bool serial = serial_requested();
+    std::vector<int2> tasks;
+    std::vector<int> loff(1, 0);
+    if (!serial) {
+        size_t nlev = 0, ntot = 0;
+        for (HLUObj* f : fs) {
+            nlev = std::max(nlev, f->plan->lu.level_off.size() - 1);
+            ntot += f->plan->lu.ops.size();
+        }
+        tasks.reserve(ntot);
+        for (size_t l = 0; l < nlev; ++l) {
+            for (size_t i = 0; i < fs.size(); ++i) {
+                const std::vector<int>& lo = fs[i]->plan->lu.level_off;
+                if (l + 1 >= lo.size()) continue;
+                for (int pc = lo[l]; pc < lo[l + 1]; ++pc) tasks.push_back(make_int2((int)i, pc));
+            }
+            loff.push_back((int)tasks.size());
+        }
+    }
+    DevBuf<int2> d_tasks;
+    upload_vec(c, d_tasks, tasks);
     EventPair ev;
     FDE_HIP(hipEventRecord(ev.a, c->stream));
-    launch_interp_one<T>(c->stream, d);
+    if (serial) {
+        launch_interp<T>(c->stream, (int)ins.size(), d_ins.p, 0);
+    } else {
+        for (size_t l = 0; l + 1 < loff.size(); ++l)
+            launch_level<T>(c->stream, loff[l + 1] - loff[l], d_ins.p, d_tasks.p + loff[l]);
+    }
     FDE_HIP(hipEventRecord(ev.b, c->stream));
-    int st[2] = {0, 0};
-    FDE_HIP(hipMemcpyAsync(st, f->status.p, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    std::vector<int> st(2 * fs.size());
+    for (size_t i = 0; i < fs.size(); ++i)
+        FDE_HIP(hipMemcpyAsync(&st[2 * i], fs[i]->status.p, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     FDE_HIP(hipStreamSynchronize(c->stream));
-    f->factor_ms = ev.ms();
-    if (st[0] == FDE_EBREAKDOWN) fail(FDE_EBREAKDOWN, "H-LU breakdown: leaf pivot below the floor (op %d)", st[1]);
-    if (st[0] != 0) fail(FDE_EDEVICE, "H-LU status %d", st[0]);
-    report_profile(f, "H-LU");
+    const float ms = ev.ms();
+    for (HLUObj* f : fs) f->factor_ms = ms;
+    for (size_t i = 0; i < fs.size(); ++i) {
+        if (st[2 * i] == FDE_EBREAKDOWN)
+            fail(FDE_EBREAKDOWN, "H-LU breakdown in H-matrix %zu: leaf pivot below the floor (op %d)", i, st[2 * i + 1]);
+        if (st[2 * i] != 0) fail(FDE_EDEVICE, "H-LU status %d in H-matrix %zu", st[2 * i], i);
+    }
+    for (HLUObj* f : fs) report_profile(f, what);
 }
 
 void factor_prepare(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
@@ -162,27 +213,17 @@ void factor_prepare(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
     f->tol = prm ? prm->tol : 1e-3;
     f->prec = prm ? prm->precision : FDE_FP32;
     f->pivot_floor = prm ? prm->pivot_floor : 1e-14;
-    const int cap = prm && prm->rank_cap > 0 ? prm->rank_cap : hm->t.R;
     if (!(f->tol >= 0.0) || !std::isfinite(f->tol)) fail(FDE_EINVAL, "tol must be >= 0");
     if (f->prec != FDE_FP32 && f->prec != FDE_FP64) fail(FDE_EINVAL, "precision must be FDE_FP32 or FDE_FP64");
     if (!(f->pivot_floor >= 0.0)) fail(FDE_EINVAL, "pivot_floor must be >= 0");
-    f->kmax = std::max(cap, hm->t.R);
-    f->t = hm->t;
-    assign_storage(&f->t, f->kmax);
+    f->kmax = rank_capacity(hm->t, prm);
     f->esz = f->prec == FDE_FP64 ? 8 : 4;
-    gen_hlu(f->t, f->lu);
-    gen_hsolve(f->t, f->sv);
-    f->kpmax = lrsub_kprime_max(f->t, f->lu);
-    if (f->kpmax > kMaxKp)
-        fail(FDE_EUNSUPPORTED, "H-LU needs recompression of width %d > %d", f->kpmax, kMaxKp);
-    lrsub_scratch(f->t, f->lu, &f->scr_t, &f->scr_d);
-    validate_program(f->t, f->lu, f->t.arena_elems, f->lu.work_elems, 1, false);
-    validate_program(f->t, f->sv, f->t.arena_elems, f->sv.work_elems, 1, true);
-    validate_program(f->t, f->sv, f->t.arena_elems, f->sv.work_elems, 64, true);
-    f->arena.alloc(c, f->t.arena_elems * f->esz);
-    f->work_lu.alloc(c, std::max<int64_t>(f->lu.work_elems, 1) * f->esz);
-    f->scr.alloc(c, f->scr_t * f->esz);
-    f->scrd.alloc(c, f->scr_d);
+    f->plan = get_plan(c, hm->t, f->kmax);
+    const Plan& P = *f->plan;
+    f->arena.alloc(c, P.t.arena_elems * f->esz);
+    f->work_lu.alloc(c, std::max<int64_t>(P.lu.work_elems, 1) * f->esz);
+    f->scr.alloc(c, P.lu.scr_t * f->esz);
+    f->scrd.alloc(c, P.lu.scr_d);
     f->status.alloc(c, 2);
     FDE_HIP(hipMemsetAsync(f->status.p, 0, 2 * sizeof(int), c->stream));
     f->flops.alloc(c, 2);
@@ -191,27 +232,18 @@ void factor_prepare(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
         f->prof.alloc(c, 16);
         FDE_HIP(hipMemsetAsync(f->prof.p, 0, 16 * sizeof(unsigned long long), c->stream));
     }
-    upload_vec(c, f->h2p, f->t.h2p);
     upload_vec(c, f->ranks, hm->init_rank);
-    upload_vec(c, f->ops_lu, f->lu.ops);
-    upload_vec(c, f->ops_sv, f->sv.ops);
-    std::vector<LRBlockDev> lrt;
-    for (int b : f->t.lr_blocks) {
-        const Block& B = f->t.bl[b];
-        lrt.push_back(LRBlockDev{B.uoff, B.voff, f->t.cl[B.tau].size(), f->t.cl[B.sigma].size(), B.slot, 0});
-    }
-    upload_vec(c, f->lr, lrt);
     // copy A~ into the factor layout, converting to the factor precision
     std::vector<SegDev> segs;
-    for (int b : f->t.dense_blocks) {
-        const Block &S = hm->t.bl[b], &D = f->t.bl[b];
-        segs.push_back(SegDev{S.off, D.off, (int64_t)f->t.cl[S.tau].size() * f->t.cl[S.sigma].size()});
+    for (int b : P.t.dense_blocks) {
+        const Block &S = hm->t.bl[b], &D = P.t.bl[b];
+        segs.push_back(SegDev{S.off, D.off, (int64_t)P.t.cl[S.tau].size() * P.t.cl[S.sigma].size()});
     }
-    for (int b : f->t.lr_blocks) {
-        const Block &S = hm->t.bl[b], &D = f->t.bl[b];
+    for (int b : P.t.lr_blocks) {
+        const Block &S = hm->t.bl[b], &D = P.t.bl[b];
         const int R = hm->t.R;
-        segs.push_back(SegDev{S.uoff, D.uoff, (int64_t)f->t.cl[S.tau].size() * R});
-        segs.push_back(SegDev{S.voff, D.voff, (int64_t)f->t.cl[S.sigma].size() * R});
+        segs.push_back(SegDev{S.uoff, D.uoff, (int64_t)P.t.cl[S.tau].size() * R});
+        segs.push_back(SegDev{S.voff, D.voff, (int64_t)P.t.cl[S.sigma].size() * R});
     }
     DevBuf<SegDev> d_segs;
     upload_vec(c, d_segs, segs);
@@ -226,46 +258,79 @@ void factor_prepare(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
 
 void factor(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
     factor_prepare(f, hm, prm);
+    std::vector<HLUObj*> one{f};
     if (f->prec == FDE_FP64)
-        factor_run<double>(f);
+        factor_batch_run<double>(f->op->ctx, one, "H-LU");
     else
-        factor_run<float>(f);
+        factor_batch_run<float>(f->op->ctx, one, "H-LU");
 }
 
-template <class T>
-void factor_batch_run(Ctx* c, std::vector<HLUObj*>& fs) {
-    std::vector<Inst<T>> ins;
-    for (HLUObj* f : fs) ins.push_back(f->inst<T>(false, 0, nullptr, 0, nullptr, 0));
-    DevBuf<Inst<T>> d_ins;
-    upload_vec(c, d_ins, ins);
-    EventPair ev;
-    FDE_HIP(hipEventRecord(ev.a, c->stream));
-    launch_interp<T>(c->stream, (int)ins.size(), d_ins.p, 0);
-    FDE_HIP(hipEventRecord(ev.b, c->stream));
-    std::vector<int> st(2 * fs.size());
-    for (size_t i = 0; i < fs.size(); ++i)
-        FDE_HIP(hipMemcpyAsync(&st[2 * i], fs[i]->status.p, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    FDE_HIP(hipStreamSynchronize(c->stream));
-    const float ms = ev.ms();
-    for (HLUObj* f : fs) f->factor_ms = ms;
-    for (size_t i = 0; i < fs.size(); ++i) {
-        if (st[2 * i] == FDE_EBREAKDOWN)
-            fail(FDE_EBREAKDOWN, "H-LU breakdown in H-matrix %zu: leaf pivot below the floor (op %d)", i, st[2 * i + 1]);
-        if (st[2 * i] != 0) fail(FDE_EDEVICE, "H-LU status %d in H-matrix %zu", st[2 * i], i);
-    }
-    for (HLUObj* f : fs) report_profile(f, "H-LU (batched)");
+// cache key: everything the programs depend on -- the mesh and the H-matrix and rank parameters
+std::string plan_key(const HTree& t, int kmax) {
+    const Op* op = t.op;
+    std::string k;
+    auto put = [&](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+    const int ints[5] = {op->N, op->P, t.leaf, t.R, kmax};
+    put(ints, sizeof ints);
+    put(&t.lambda, sizeof t.lambda);
+    put(op->x.data(), op->x.size() * sizeof(double));
+    return k;
 }
 
 }  // namespace
 
 namespace fde {
 
+void make_plan_host(const HTree& hmt, int kmax, Plan& p, bool check) {
+    p.t = hmt;
+    assign_storage(&p.t, kmax);
+    gen_hlu(p.t, p.lu);
+    Program original;
+    if (check) original = p.lu;
+    schedule_levels(p.t, p.lu);
+    if (check) check_schedule(p.t, original, p.lu);
+    gen_hsolve(p.t, p.sv);
+    p.kpmax = lrsub_kprime_max(p.t, p.lu);
+    if (p.kpmax > kMaxKp) fail(FDE_EUNSUPPORTED, "H-LU needs recompression of width %d > %d", p.kpmax, kMaxKp);
+    validate_program(p.t, p.lu, p.t.arena_elems, p.lu.work_elems, 1, false);
+    validate_program(p.t, p.sv, p.t.arena_elems, p.sv.work_elems, 1, true);
+    validate_program(p.t, p.sv, p.t.arena_elems, p.sv.work_elems, 64, true);
+}
+
+std::shared_ptr<const Plan> get_plan(Ctx* c, const HTree& hmt, int kmax) {
+    constexpr size_t kCached = 8;
+    const std::string key = plan_key(hmt, kmax);
+    for (size_t i = 0; i < c->plans.size(); ++i)
+        if (c->plans[i].first == key) {
+            auto hit = c->plans[i];
+            c->plans.erase(c->plans.begin() + i);
+            c->plans.insert(c->plans.begin(), hit);
+            return hit.second;
+        }
+    auto p = std::make_shared<Plan>();
+    make_plan_host(hmt, kmax, *p, false);
+    upload_vec(c, p->h2p, p->t.h2p);
+    upload_vec(c, p->ops_lu, p->lu.ops);
+    upload_vec(c, p->ops_sv, p->sv.ops);
+    std::vector<LRBlockDev> lrt;
+    for (int b : p->t.lr_blocks) {
+        const Block& B = p->t.bl[b];
+        lrt.push_back(LRBlockDev{B.uoff, B.voff, p->t.cl[B.tau].size(), p->t.cl[B.sigma].size(), B.slot, 0});
+    }
+    upload_vec(c, p->lr, lrt);
+    FDE_HIP(hipStreamSynchronize(c->stream));   // host copies of the tables may move later
+    p->t.op = nullptr;
+    c->plans.insert(c->plans.begin(), {key, p});
+    if (c->plans.size() > kCached) c->plans.pop_back();
+    return p;
+}
+
 void hlu_prepare_solve(HLUObj* f, int nrhs) {
     if (nrhs > f->sv_nrhs_cap) {
         Ctx* c = f->op->ctx;
         const int64_t cap = std::max<int64_t>(nrhs, 1);
         f->sv_rhs.alloc(c, (int64_t)f->op->Nd * cap * f->esz);
-        f->sv_work.alloc(c, std::max<int64_t>(f->sv.work_elems, 1) * cap * f->esz);
+        f->sv_work.alloc(c, std::max<int64_t>(f->plan->sv.work_elems, 1) * cap * f->esz);
         f->sv_nrhs_cap = cap;
     }
 }
@@ -341,6 +406,43 @@ int fde_hmat_to_dense(fde_hmat* hm, double* out, int ld) {
     FDE_API_END
 }
 
+int fde_hlu_plan(const double* nodes, int N, int P, const fde_hparams* hp, int rank_cap, int check,
+                 fde_hlu_plan_info* out) {
+    FDE_API_BEGIN
+    if (!nodes || !out) fail(FDE_EINVAL, "null argument");
+    if (N < 1) fail(FDE_EINVAL, "N must be >= 1 (got %d)", N);
+    if (P < 2 || P > 32) fail(FDE_EINVAL, "P must be in [2, 32] (got %d)", P);
+    for (int e = 0; e < N; ++e)
+        if (!std::isfinite(nodes[e]) || !std::isfinite(nodes[e + 1]) || !(nodes[e + 1] > nodes[e]))
+            fail(FDE_EINVAL, "mesh must be finite and strictly increasing (at node %d)", e);
+    Op op;   // host fields only
+    op.N = N;
+    op.P = P;
+    op.Nd = N * P - 1;
+    op.x.assign(nodes, nodes + N + 1);
+    HTree t;
+    tree_params(t, &op, hp);
+    build_trees(&t);
+    fde_hlu_params hl{};
+    hl.rank_cap = rank_cap;
+    Plan p;
+    make_plan_host(t, rank_capacity(t, &hl), p, check != 0);
+    fde_hlu_plan_info& r = *out;
+    r = fde_hlu_plan_info{};
+    r.ops = (long long)p.lu.ops.size();
+    r.levels = (int)p.lu.level_off.size() - 1;
+    for (int l = 0; l < r.levels; ++l) r.max_width = std::max(r.max_width, p.lu.level_off[l + 1] - p.lu.level_off[l]);
+    r.solve_ops = (long long)p.sv.ops.size();
+    r.arena_elems = p.t.arena_elems;
+    r.work_elems = std::max<int64_t>(p.lu.work_elems, 1);
+    r.scratch_elems = p.lu.scr_t;
+    r.scratch_f64 = p.lu.scr_d;
+    const long long fixed = 8 * r.scratch_f64 + 4 * (long long)p.t.nslots + 8 + 16;   // + status, flop counters
+    r.bytes_fp32 = 4 * (r.arena_elems + r.work_elems + r.scratch_elems) + fixed;
+    r.bytes_fp64 = 8 * (r.arena_elems + r.work_elems + r.scratch_elems) + fixed;
+    FDE_API_END
+}
+
 int fde_hlu_factor(fde_hmat* hm, const fde_hlu_params* prm, fde_hlu** out) {
     FDE_API_BEGIN
     if (!hm || !out) fail(FDE_EINVAL, "null argument");
@@ -374,8 +476,8 @@ int fde_hlu_factor_batched(int n, fde_hmat* const* hms, const fde_hlu_params* pr
         }
         std::vector<HLUObj*> f32, f64;
         for (HLUObj* f : fs) (f->prec == FDE_FP64 ? f64 : f32).push_back(f);
-        if (!f32.empty()) factor_batch_run<float>(c, f32);
-        if (!f64.empty()) factor_batch_run<double>(c, f64);
+        if (!f32.empty()) factor_batch_run<float>(c, f32, "H-LU (batched)");
+        if (!f64.empty()) factor_batch_run<double>(c, f64, "H-LU (batched)");
     } catch (...) {
         for (HLUObj* f : fs) delete static_cast<fde_hlu*>(f);
         throw;
@@ -398,7 +500,7 @@ int fde_hlu_to_dense(fde_hlu* f, double* out, int ld, int* h2p) {
     FDE_API_BEGIN
     if (!f || !out || ld < f->op->Nd) fail(FDE_EINVAL, "bad arguments");
     Ctx* c = f->op->ctx;
-    std::vector<LeafDev> lv = leaf_table(f->t);
+    std::vector<LeafDev> lv = leaf_table(f->t());
     DevBuf<LeafDev> d_lv;
     upload_vec(c, d_lv, lv);
     if (f->prec == FDE_FP64)
@@ -408,7 +510,7 @@ int fde_hlu_to_dense(fde_hlu* f, double* out, int ld, int* h2p) {
         launch_to_dense<float>(c->stream, (int)lv.size(), d_lv.p, reinterpret_cast<float*>(f->arena.p), f->ranks.p,
                                nullptr, out, ld);
     FDE_HIP(hipStreamSynchronize(c->stream));
-    if (h2p) std::memcpy(h2p, f->t.h2p.data(), f->t.h2p.size() * sizeof(int));
+    if (h2p) std::memcpy(h2p, f->t().h2p.data(), f->t().h2p.size() * sizeof(int));
     FDE_API_END
 }
 
@@ -427,7 +529,7 @@ int fde_hlu_stats(fde_hlu* f, double* factor_flops, double* factor_ms, double* s
 int fde_hlu_max_rank(fde_hlu* f, int* mr) {
     FDE_API_BEGIN
     if (!f || !mr) fail(FDE_EINVAL, "bad arguments");
-    std::vector<int> r(f->t.lr_blocks.size());
+    std::vector<int> r(f->t().lr_blocks.size());
     if (!r.empty()) {
         FDE_HIP(hipMemcpyAsync(r.data(), f->ranks.p, r.size() * sizeof(int), hipMemcpyDeviceToHost, f->op->ctx->stream));
         FDE_HIP(hipStreamSynchronize(f->op->ctx->stream));

@@ -49,6 +49,8 @@ struct LowRankDesc {
 };
 
 // --------------------------------------------------------------- program
+constexpr int kMaxKprime = 256;   // widest [U, X] recompressed in one OP_LRSUB
+
 enum OpCode { OP_GETRF = 1, OP_TRSM = 2, OP_GEMM = 3, OP_LRSUB = 4, OP_ZERO = 5, OP_LOAD = 6, OP_STORE = 7 };
 enum Base { B_ARENA = 0, B_WORK = 1, B_RHS = 2, B_WORK_NRHS = 3 };
 
@@ -65,6 +67,8 @@ struct OpRec {
     int blk;           // LRSUB: low-rank block id
     float alpha, beta; // GEMM
     View v[3];         // GEMM: C, A, B; TRSM: X, T; GETRF: A; LRSUB: X, Y; ZERO: X
+    int64_t sofs_t;    // LRSUB: private scratch (elements of the factor type, then doubles)
+    int64_t sofs_d;
 };
 
 struct LRBlockDev {    // device table for OP_LRSUB
@@ -72,10 +76,20 @@ struct LRBlockDev {    // device table for OP_LRSUB
     int m, n, slot, pad;
 };
 
+struct TempRegion {
+    int64_t off;       // element offset in the work space
+    int rows, cols;    // column-major, ld = rows
+};
+
 struct Program {
     std::vector<OpRec> ops;
     int64_t work_elems = 0;   // temporaries (H-solve: in rows, times the number of right-hand sides)
     int kx_max = 0;           // widest update X Y^T recompressed into a low-rank block
+    std::vector<TempRegion> temps;   // factorisation: every temporary, never reused before scheduling
+    // level schedule (schedule_levels): ops[level_off[l] .. level_off[l+1]) are independent
+    std::vector<int> level_off;
+    std::vector<int> origin;         // program-order index of every scheduled op
+    int64_t scr_t = 0, scr_d = 0;    // recompression scratch of one level (factor type, doubles)
 };
 
 // --------------------------------------------------------------- H-matrix
@@ -112,7 +126,15 @@ void build_hmatrix_device(HMat* hm);   // hbuild.hip
 void gen_hlu(const HTree& hm, Program& prog);
 void gen_hsolve(const HTree& hm, Program& prog);
 int lrsub_kprime_max(const HTree& hm, const Program& lu);
-void lrsub_scratch(const HTree& hm, const Program& lu, int64_t* t_elems, int64_t* d_elems);
+// scratch one OP_LRSUB needs at most (elements of the factor type, doubles)
+void lrsub_need(const HTree& hm, const OpRec& o, int64_t* t_elems, int64_t* d_elems);
+// schedule.cpp: reorder a factorisation program into levels of mutually independent ops
+// (every op after all ops it conflicts with), give the temporaries memory by their level
+// lifetimes and every OP_LRSUB private scratch within its level
+void schedule_levels(const HTree& hm, Program& prog);
+// element-by-element check of a schedule against the program order it came from
+// (host, slow: tests and diagnostics); fails with FDE_EDEVICE on a violated dependency
+void check_schedule(const HTree& hm, const Program& original, const Program& scheduled);
 void validate_program(const HTree& hm, const Program& prog, int64_t arena_elems, int64_t work_elems,
                       int nrhs_max, bool solve);
 

@@ -111,7 +111,7 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
         }
         if (g.prec) {
             g.rhs.alloc(c, bs * g.prec->esz);
-            g.work.alloc(c, std::max<int64_t>(g.prec->sv.work_elems, 1) * g.nr * g.prec->esz);
+            g.work.alloc(c, std::max<int64_t>(g.prec->plan->sv.work_elems, 1) * g.nr * g.prec->esz);
             if (g.prec->prec == FDE_FP64)
                 i64.push_back(group_inst<double>(g, m));
             else

@@ -54,7 +54,8 @@ class Gen {
         return rows_of(s, c0.size(), c.size() - c0.size());
     }
 
-    // ---- temporaries (stack)
+    // ---- temporaries: a stack in the H-substitutions; in the factorisation every
+    // temporary is distinct (the level schedule gives them memory afterwards)
     Slab alloc(int rows_, int width, int cap) {
         Slab s;
         s.rows = rows_;
@@ -64,12 +65,15 @@ class Gen {
             top_ += rows_;
         } else {
             s.v = View{B_WORK, 1, rows_, top_};
+            p_.temps.push_back(TempRegion{top_, rows_, cap});
             top_ += (int64_t)rows_ * cap;
         }
         high_ = std::max(high_, top_);
         return s;
     }
-    void release(const Slab& s) { top_ = s.v.off; }
+    void release(const Slab& s) {
+        if (solve_) top_ = s.v.off;
+    }
     int cap(int width) const { return width >= 0 ? width : hm_.kmax; }
 
     // ---- emitters
@@ -285,7 +289,7 @@ class Gen {
 }  // namespace
 
 void gen_hlu(const HTree& hm, Program& prog) {
-    prog.ops.clear();
+    prog = Program{};
     Gen g(hm, prog, false);
     g.hlu(hm.root);
     prog.work_elems = g.high();
@@ -293,7 +297,7 @@ void gen_hlu(const HTree& hm, Program& prog) {
 }
 
 void gen_hsolve(const HTree& hm, Program& prog) {
-    prog.ops.clear();
+    prog = Program{};
     Gen g(hm, prog, true);
     OpRec ld{};
     ld.code = OP_LOAD;
@@ -311,11 +315,15 @@ void gen_hsolve(const HTree& hm, Program& prog) {
 
 int lrsub_kprime_max(const HTree& hm, const Program& lu) { return hm.kmax + std::max(lu.kx_max, 1); }
 
-void lrsub_scratch(const HTree& hm, const Program& lu, int64_t* t_elems, int64_t* d_elems) {
-    const int kp = lrsub_kprime_max(hm, lu);
-    const int64_t mr = std::max(hm.max_lr_rows, 1);
-    *t_elems = 2 * mr * kp + 2 * (int64_t)kp * kp;
-    *d_elems = 2 * (int64_t)kp * kp + 2 * kp;
+void lrsub_need(const HTree& hm, const OpRec& o, int64_t* t_elems, int64_t* d_elems) {
+    const Block& b = hm.bl[hm.lr_blocks[o.blk]];
+    const int64_t m = hm.cl[b.tau].size(), n = hm.cl[b.sigma].size();
+    const int64_t kp = hm.kmax + (o.dim[2] >= 0 ? o.dim[2] : hm.kmax);
+    const int64_t kf = std::min<int64_t>(kp, 32);
+    // QR path: [U, -X] and [V, Y] copies and both triangles; FP64 core, rotations, singular values
+    *t_elems = (m + n) * kp + 2 * kp * kp;
+    // Gram path (k' <= 32): twelve k' x k' FP64 matrices, three 32-vectors, one side's rows x k'
+    *d_elems = std::max(2 * kp * kp + 2 * kp, 12 * kf * kf + 3 * 32 + std::max(m, n) * kf);
 }
 
 // Every view an op touches must stay inside its region; checked on the host with
@@ -367,6 +375,12 @@ void validate_program(const HTree& hm, const Program& prog, int64_t arena_elems,
                 const int64_t k = dimv(o.dim[2]);
                 check(o.v[0], hm.cl[b.tau].size(), k, (int)pc, "lrsub X");
                 check(o.v[1], hm.cl[b.sigma].size(), k, (int)pc, "lrsub Y");
+                if (hm.kmax + k > kMaxKprime) fail(FDE_EUNSUPPORTED, "program op %zu: recompression width %lld > %d", pc,
+                                                   (long long)(hm.kmax + k), kMaxKprime);
+                int64_t nt, nd;
+                lrsub_need(hm, o, &nt, &nd);
+                if (o.sofs_t < 0 || o.sofs_d < 0 || o.sofs_t + nt > prog.scr_t || o.sofs_d + nd > prog.scr_d)
+                    fail(FDE_EDEVICE, "program op %zu: recompression scratch out of range", pc);
                 break;
             }
             case OP_LOAD:

@@ -115,4 +115,19 @@ void gauss_jacobi(int n, double a, double b, double* x, double* w) {
     }
 }
 
+const double* gauss_legendre_table() {
+    // built once per process (thread-safe static initialisation); the rules are
+    // used by every panel of every load-vector quadrature and by the device table
+    static const std::vector<double> table = [] {
+        const int tot = kMaxGL * (kMaxGL + 1) / 2;
+        std::vector<double> t(2 * tot);
+        for (int n = 1; n <= kMaxGL; ++n) {
+            const int off = n * (n - 1) / 2;
+            gauss_jacobi(n, 0.0, 0.0, t.data() + off, t.data() + tot + off);
+        }
+        return t;
+    }();
+    return table.data();
+}
+
 }  // namespace fde

@@ -68,6 +68,18 @@ def gauss_jacobi(n: int, a: float, b: float):
     return x, w
 
 
+def plan_hlu(nodes, P: int, R: int = 8, lam: float = 1.0, leaf_elems: int = 8, rank_cap: int = 0,
+             check_schedule: bool = False) -> dict:
+    """Host-only plan of an H-LU (op and level counts, device bytes per factorisation);
+    check_schedule also verifies the level schedule element by element (slow)."""
+    x = np.ascontiguousarray(nodes, dtype=np.float64)
+    info = A.PlanInfo()
+    hp = A.HParams(R, lam, leaf_elems)
+    check(load().fde_hlu_plan(_np_dptr(x), len(x) - 1, P, C.byref(hp), rank_cap, int(check_schedule),
+                              C.byref(info)))
+    return {name: getattr(info, name) for name, _ in A.PlanInfo._fields_}
+
+
 class Context(_Handle):
     """Device, HIP stream (torch's current stream by default) and HBM budget."""
 
@@ -229,7 +241,7 @@ class HLU(_Handle):
 
 def factor_batched(hms: Sequence[HMatrix], tol: float = 1e-3, rank_cap: int = 0, precision: str = "fp32",
                    pivot_floor: float = 1e-14):
-    """H-LU of several H-matrices in one device launch (one workgroup each)."""
+    """H-LU of several H-matrices together: each kernel launch runs one level of every factorisation."""
     n = len(hms)
     prec = {"fp64": A.FDE_FP64, "fp32": A.FDE_FP32}[precision]
     p = A.HLUParams(float(tol), int(rank_cap), prec, float(pivot_floor))
