@@ -77,6 +77,7 @@ struct Ctx {
     size_t budget = 0;   // 0: unlimited
     size_t in_use = 0;
     DevBuf<double> gl;   // Gauss-Legendre n=1..kMaxGL: nodes then weights, offset n(n-1)/2
+    size_t lds_limit = 0;   // largest dynamic LDS of one workgroup (bytes)
     // most recently used plans first, keyed by the structure they were made for
     std::vector<std::pair<std::string, std::shared_ptr<Plan>>> plans;
 };

@@ -27,6 +27,8 @@ struct Inst {
     int ldx;
     int64_t bstep, xstep;
     int nrhs;
+    int nslots;               // low-rank blocks (rank slots)
+    int work_rows;            // H-solve temporaries, rows (times the number of right-hand sides)
     double tol;
     int kmax;
     double pivot_floor;
@@ -44,6 +46,19 @@ template <class T>
 void launch_interp(hipStream_t st, int ninst, const Inst<T>* d_insts, int step = 0);
 template <class T>
 void launch_interp_one(hipStream_t st, const Inst<T>& d);
+// H-solve with the right-hand sides in LDS: workgroup b solves columns [c*wc, c*wc + wc) of
+// instance b / nchunk (c = b % nchunk); lds_bytes from hsolve_lds_bytes
+template <class T>
+void launch_hsolve(hipStream_t st, int ninst, int nchunk, int wc, const Inst<T>* d_insts, int step,
+                   size_t lds_bytes);
+template <class T>
+void launch_hsolve_one(hipStream_t st, const Inst<T>& d, int nchunk, int wc, size_t lds_bytes);
+// LDS bytes of one workgroup of the LDS H-solve for wc columns
+size_t hsolve_lds_bytes(int Nd, int work_rows, int nslots, int wc, size_t esz);
+constexpr int kHsolveMaxCols = 8;
+// largest dynamic LDS of one workgroup on the device (bytes)
+size_t device_lds_limit(int device);
+
 // one level of level-scheduled programs: workgroup b runs op tasks[b].y of instance tasks[b].x
 template <class T>
 void launch_level(hipStream_t st, int ntasks, const Inst<T>* d_insts, const int2* d_tasks);

@@ -15,6 +15,7 @@
 #include <cstdlib>
 
 #include "hinterp.h"
+#include "tri_wave.h"
 
 namespace fde {
 
@@ -23,8 +24,37 @@ namespace {
 constexpr int kT = kInterpThreads;
 constexpr int kW = kT / 64;
 
+constexpr int kSK = 32;   // widest k' of the small recompression
+constexpr int kCH = 32;   // rows per staged chunk
+
+struct LrsLds {
+    double A[2][kCH * kSK];   // staged rows of both sides (row-major, stride kSK); later C_u, C_v
+    double G[2][kSK * kSK];   // Gram matrices; then the core M and rotations Z; then C_u, C_v
+    double R[2][kSK * kSK];   // Cholesky factors R[a][j] (row a, original column j)
+    double sig[kSK];
+    int perm[2][kSK], perm2[2][kSK];
+    int q[2], q2[2];
+};
+
+constexpr int kGT = 64;            // GEMM output tile (rows and columns)
+constexpr int kGK = 32;            // GEMM k chunk
+template <class T>
+struct GemmLds {
+    T A[kGT][kGK + 1];             // A tile, row-major (padded)
+    T B[kGK][kGT + 1];             // B tile, row-major (padded)
+};
+constexpr int kLU = 64;            // GETRF leaves staged in LDS up to this size
+struct GetrfLds {
+    double A[kLU * (kLU + 1)];     // column-major, ld kLU + 1 (as T)
+};
+
 struct Shared {
-    double part[1024];
+    union {
+        LrsLds ls;
+        GemmLds<double> gd;
+        GemmLds<float> gf;
+        GetrfLds lu;
+    };
     double red[kW][32];
     double dots[kMaxKp];
     int order[kMaxKp];
@@ -88,44 +118,118 @@ __device__ inline int dimval(const Inst<T>& d, int code) {
 
 // ------------------------------------------------------------------ GEMM / ZERO
 template <class T>
-__device__ void op_gemm(const Inst<T>& d, const OpRec& o) {
+__device__ inline GemmLds<T>& gemm_lds(Shared& sh);
+template <>
+__device__ inline GemmLds<double>& gemm_lds<double>(Shared& sh) { return sh.gd; }
+template <>
+__device__ inline GemmLds<float>& gemm_lds<float>(Shared& sh) { return sh.gf; }
+
+// C = beta C + alpha A B. Blocks of at least 16 x 16 outputs go through LDS tiles (64 x 64
+// outputs, k in chunks of 32; each thread a 4 x 4 register tile); thin products use G lanes
+// per output, consecutive lanes along k, reduced by shuffles, or one thread per output.
+template <class T>
+__device__ __attribute__((noinline)) void op_gemm(const Inst<T>& d, const OpRec& o, Shared& sh) {
     const int m = dimval(d, o.dim[0]), n = dimval(d, o.dim[1]), k = dimval(d, o.dim[2]);
     T* C = vptr(d, o.v[0]);
     const T* A = vptr(d, o.v[1]);
     const T* B = vptr(d, o.v[2]);
     const T alpha = (T)o.alpha, beta = (T)o.beta;
-    const int64_t mn = (int64_t)m * n;
     const int ars = o.v[1].rs, acs = o.v[1].cs, brs = o.v[2].rs, bcs = o.v[2].cs;
     const int crs = o.v[0].rs, ccs = o.v[0].cs;
-    if (mn <= 0) return;
-    if (mn * 4 >= kT || k < 64) {
-        // one thread per output
-        for (int64_t idx = threadIdx.x; idx < mn; idx += kT) {
+    if (m <= 0 || n <= 0) return;
+    const int t = threadIdx.x;
+    if (m >= 16 && n >= 16 && k >= 4) {
+        GemmLds<T>& L = gemm_lds<T>(sh);
+        const int ti = t % 16, tj = t / 16;   // rows 4 ti .. 4 ti + 3, columns 4 tj .. 4 tj + 3 of a tile
+        for (int i0 = 0; i0 < m; i0 += kGT)
+            for (int j0 = 0; j0 < n; j0 += kGT) {
+                T acc[4][4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+                for (int l0 = 0; l0 < k; l0 += kGK) {
+                    // stage: consecutive threads along whichever index is contiguous in memory
+                    for (int idx = t; idx < kGT * kGK; idx += kT) {
+                        int i, l;
+                        if (ars == 1) {
+                            i = idx % kGT;
+                            l = idx / kGT;
+                        } else {
+                            l = idx % kGK;
+                            i = idx / kGK;
+                        }
+                        const int gi = i0 + i, gl = l0 + l;
+                        L.A[i][l] = (gi < m && gl < k) ? A[(int64_t)gi * ars + (int64_t)gl * acs] : T(0);
+                    }
+                    for (int idx = t; idx < kGK * kGT; idx += kT) {
+                        int l, j;
+                        if (brs == 1) {
+                            l = idx % kGK;
+                            j = idx / kGK;
+                        } else {
+                            j = idx % kGT;
+                            l = idx / kGT;
+                        }
+                        const int gl = l0 + l, gj = j0 + j;
+                        L.B[l][j] = (gl < k && gj < n) ? B[(int64_t)gl * brs + (int64_t)gj * bcs] : T(0);
+                    }
+                    __syncthreads();
+                    const int kl = min(kGK, k - l0);
+                    for (int l = 0; l < kl; ++l) {
+                        T av[4], bv[4];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) av[a] = L.A[4 * ti + a][l];
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) bv[b] = L.B[l][4 * tj + b];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a)
+#pragma unroll
+                            for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+                    }
+                    __syncthreads();
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int gi = i0 + 4 * ti + a, gj = j0 + 4 * tj + b;
+                        if (gi < m && gj < n) {
+                            T* c = C + (int64_t)gi * crs + (int64_t)gj * ccs;
+                            *c = (beta == T(0) ? T(0) : beta * *c) + alpha * acc[a][b];
+                        }
+                    }
+            }
+        return;
+    }
+    const int64_t mn = (int64_t)m * n;
+    int G = 1;
+    while (2 * G * mn <= kT && 2 * G <= 64) G <<= 1;
+    if (G >= 2 && k >= 2 * G) {
+        const int ngroups = kT / G, gid = t / G, gl = t % G;
+        for (int64_t idx = gid; idx < mn; idx += ngroups) {
             const int i = (int)(idx % m), j = (int)(idx / m);
             const T* a = A + (int64_t)i * ars;
             const T* b = B + (int64_t)j * bcs;
-            T s = 0;
-            for (int l = 0; l < k; ++l) s += a[(int64_t)l * acs] * b[(int64_t)l * brs];
-            T* c = C + (int64_t)i * crs + (int64_t)j * ccs;
-            *c = (beta == T(0) ? T(0) : beta * *c) + alpha * s;
+            double s = 0.0;
+            for (int l = gl; l < k; l += G) s += (double)a[(int64_t)l * acs] * (double)b[(int64_t)l * brs];
+            for (int o2 = G / 2; o2 > 0; o2 >>= 1) s += __shfl_xor(s, o2, 64);
+            if (gl == 0) {
+                T* c = C + (int64_t)i * crs + (int64_t)j * ccs;
+                *c = (beta == T(0) ? T(0) : beta * *c) + alpha * (T)s;
+            }
         }
         return;
     }
-    // few outputs, long inner dimension: a group of G lanes per output, reduced by shuffles
-    int G = 64;
-    while (G > 1 && (int64_t)G * mn > kT) G >>= 1;
-    const int ngroups = kT / G, gid = threadIdx.x / G, gl = threadIdx.x % G;
-    for (int64_t idx = gid; idx < mn; idx += ngroups) {
+    for (int64_t idx = t; idx < mn; idx += kT) {
         const int i = (int)(idx % m), j = (int)(idx / m);
         const T* a = A + (int64_t)i * ars;
         const T* b = B + (int64_t)j * bcs;
-        double s = 0.0;
-        for (int l = gl; l < k; l += G) s += (double)a[(int64_t)l * acs] * (double)b[(int64_t)l * brs];
-        s = group_sum(s, G);
-        if (gl == 0) {
-            T* c = C + (int64_t)i * crs + (int64_t)j * ccs;
-            *c = (beta == T(0) ? T(0) : beta * *c) + alpha * (T)s;
-        }
+        T s = 0;
+#pragma unroll 8
+        for (int l = 0; l < k; ++l) s += a[(int64_t)l * acs] * b[(int64_t)l * brs];
+        T* c = C + (int64_t)i * crs + (int64_t)j * ccs;
+        *c = (beta == T(0) ? T(0) : beta * *c) + alpha * s;
     }
 }
 
@@ -141,7 +245,7 @@ __device__ void op_zero(const Inst<T>& d, const OpRec& o) {
 
 // ------------------------------------------------------------------ TRSM
 template <class T>
-__device__ void op_trsm(const Inst<T>& d, const OpRec& o) {
+__device__ __attribute__((noinline)) void op_trsm(const Inst<T>& d, const OpRec& o) {
     const int n = dimval(d, o.dim[0]), w = dimval(d, o.dim[1]);
     if (n <= 0 || w <= 0) return;
     T* X = vptr(d, o.v[0]);
@@ -149,6 +253,10 @@ __device__ void op_trsm(const Inst<T>& d, const OpRec& o) {
     const int xrs = o.v[0].rs, xcs = o.v[0].cs, trs = o.v[1].rs, tcs = o.v[1].cs;
     const bool lower = o.flags & 1, unit = o.flags & 2;
     auto Tat = [&](int i, int j) -> T { return Tm[(int64_t)i * trs + (int64_t)j * tcs]; };
+    if (n <= 64) {
+        tri_wave(Tm, trs, tcs, n, lower, unit, X, xrs, xcs, w, (int)(threadIdx.x >> 6), kW);
+        return;
+    }
     if (w <= kW && n <= 256) {
         // one wavefront per column: lane l holds rows l, l+64, l+128, l+192; no barriers
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -221,34 +329,53 @@ __device__ void op_trsm(const Inst<T>& d, const OpRec& o) {
 }
 
 // ------------------------------------------------------------------ GETRF
+// LU without pivoting of a dense leaf (unit lower L): right-looking, in LDS for leaves up to
+// kLU (one barrier after the multipliers and one after each rank-one update)
 template <class T>
-__device__ bool op_getrf(const Inst<T>& d, const OpRec& o, Shared& sh, int pc) {
+__device__ __attribute__((noinline)) bool op_getrf(const Inst<T>& d, const OpRec& o, Shared& sh, int pc) {
     const int n = o.dim[0];
     T* A = vptr(d, o.v[0]);
     const int rs = o.v[0].rs, cs = o.v[0].cs;
     auto at = [&](int i, int j) -> T& { return A[(int64_t)i * rs + (int64_t)j * cs]; };
+    const bool lds = n <= kLU;
+    T* S = reinterpret_cast<T*>(sh.lu.A);
+    constexpr int ld = kLU + 1;
     double amax = 0.0;
-    for (int idx = threadIdx.x; idx < n * n; idx += kT) amax = fmax(amax, fabs((double)at(idx % n, idx / n)));
-    amax = block_max(amax, sh);
-    for (int k = 0; k < n; ++k) {
-        const T akk = at(k, k);
+    for (int idx = threadIdx.x; idx < n * n; idx += kT) {
+        const int i = idx % n, j = idx / n;
+        const T v = at(i, j);
+        if (lds) S[i + j * ld] = v;
+        amax = fmax(amax, fabs((double)v));
+    }
+    amax = block_max(amax, sh);   // contains barriers
+    auto el = [&](int i, int j) -> T& { return lds ? S[i + j * ld] : at(i, j); };
+    bool ok = true;
+    for (int kk = 0; kk < n; ++kk) {
+        const T akk = el(kk, kk);
         if (!(fabs((double)akk) > d.pivot_floor * amax) || !(fabs((double)akk) > 0.0)) {
             if (threadIdx.x == 0) {
                 d.status[0] = FDE_EBREAKDOWN;
                 d.status[1] = pc;
             }
-            return false;
+            ok = false;
+            break;
         }
-        for (int i = k + 1 + threadIdx.x; i < n; i += kT) at(i, k) /= akk;
+        const T inv = T(1) / akk;
+        for (int i = kk + 1 + threadIdx.x; i < n; i += kT) el(i, kk) *= inv;
         __syncthreads();
-        const int r = n - k - 1;
+        const int r = n - kk - 1;
         for (int idx = threadIdx.x; idx < r * r; idx += kT) {
-            const int i = k + 1 + idx % r, j = k + 1 + idx / r;
-            at(i, j) -= at(i, k) * at(k, j);
+            const int i = kk + 1 + idx % r, j = kk + 1 + idx / r;
+            el(i, j) -= el(i, kk) * el(kk, j);
         }
         __syncthreads();
     }
-    return true;
+    if (ok && lds)
+        for (int idx = threadIdx.x; idx < n * n; idx += kT) {
+            const int i = idx % n, j = idx / n;
+            at(i, j) = S[i + j * ld];
+        }
+    return ok;
 }
 
 // ------------------------------------------------------------------ LRSUB
@@ -367,290 +494,352 @@ __device__ void jacobi_svd(double* M, double* W, int kp, Shared& sh) {
     }
 }
 
-// ----- fast recompression for k' <= 32: FP64 Gram matrices + wavefront one-sided Jacobi
+// ----- small recompression (k' <= kSK): Cholesky QR of both sides, one small SVD
+//
+// With A_u = [U_C, -X] (m x k') and A_v = [V_C, Y] (n x k'), U_C V_C^T - X Y^T = A_u A_v^T.
+// The Gram matrices A^T A (FP64) are factorised by pivoted Cholesky, P^T G P = R^T R with R
+// upper trapezoidal (rank q: pivots below a relative floor are dropped), so that
+// A P = Q R with orthonormal Q = (A P)[:, :q] R11^{-1}. For FP64 factors a second Gram of Q
+// refines R (Cholesky QR2). Then A_u A_v^T = Q_u M Q_v^T with the small core
+// M = (R_u P_u^T)(R_v P_v^T)^T, whose SVD M = W S Z^T (one-sided Jacobi) is truncated to the
+// singular values above tol * s_1 (at most kmax): U_C <- A_u C_u, V_C <- A_v C_v with
+// C_u = P_u R11_u^{-1} (W S)_r and C_v = P_v R11_v^{-1} Z_r.
 
-// one-sided (Hestenes) Jacobi run by one wavefront: lane j holds column j of M (kp x kp, column-major
-// in global scratch); on return M holds the rotated columns, W the accumulated rotations and
-// nrm[j] = ||rotated column j||. Both lanes of a pair form the same dot products in the same order.
-template <int KP>
-__device__ void wave_jacobi(double* M, double* W, double* nrm, int kp) {
-    const int lane = threadIdx.x & 63;
-    double col[KP], w[KP];
-#pragma unroll
-    for (int i = 0; i < KP; ++i) {
-        col[i] = (lane < kp && i < kp) ? M[i + lane * kp] : 0.0;
-        w[i] = (i == lane) ? 1.0 : 0.0;
+// one side's column c at row i of [F, sgn * G] (F: current factor, ld rows; G: update view)
+template <class T>
+struct Side {
+    const T* F;
+    int ldf, kc;
+    const T* G;
+    int grs, gcs;
+    double sgn;
+    int rows;
+    __device__ double at(int i, int c) const {
+        return c < kc ? (double)F[i + (int64_t)c * ldf] : sgn * (double)G[(int64_t)i * grs + (int64_t)(c - kc) * gcs];
     }
-    const int n2 = kp + (kp & 1);
-    for (int sweep = 0; sweep < 40; ++sweep) {
+};
+
+// stage rows [c0, c0 + kCH) of both sides into LDS (row-major, stride kSK; zero beyond the rows)
+template <class T>
+__device__ void stage_rows(const Side<T>& su, const Side<T>& sv, int c0, int kp, LrsLds& S) {
+    for (int idx = threadIdx.x; idx < 2 * kCH * kp; idx += kT) {
+        const int s = idx / (kCH * kp), rem = idx % (kCH * kp);
+        const int c = rem / kCH, rr = rem % kCH, i = c0 + rr;
+        double v = 0.0;
+        if (s == 0) {
+            if (i < su.rows) v = su.at(i, c);
+        } else {
+            if (i < sv.rows) v = sv.at(i, c);
+        }
+        S.A[s][rr * kSK + c] = v;
+    }
+}
+
+__device__ inline void tri_index(int e, int& p, int& q) {   // e -> (p <= q) of the upper triangle
+    q = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while (q * (q + 1) / 2 > e) --q;
+    while ((q + 1) * (q + 2) / 2 <= e) ++q;
+    p = e - q * (q + 1) / 2;
+}
+
+// Gram matrices of the staged rows, accumulated in LDS over the caller's chunk loop: entry
+// (p <= q) of either side always belongs to the same thread, so there is no race
+__device__ inline void gram_clear(LrsLds& S) {
+    for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) (&S.G[0][0])[idx] = 0.0;
+}
+__device__ inline void gram_accumulate(LrsLds& S, int k0, int k1) {
+    const int n0 = k0 * (k0 + 1) / 2, n1 = k1 * (k1 + 1) / 2;
+    for (int e = threadIdx.x; e < n0 + n1; e += kT) {
+        const int s = e < n0 ? 0 : 1, el = e < n0 ? e : e - n0;
+        int p, q;
+        tri_index(el, p, q);
+        const double* A = S.A[s];
+        double a = 0.0;
+#pragma unroll 4
+        for (int rr = 0; rr < kCH; ++rr) a += A[rr * kSK + p] * A[rr * kSK + q];
+        S.G[s][p * kSK + q] += a;
+    }
+}
+__device__ inline void gram_mirror(LrsLds& S, int k0, int k1) {
+    const int n0 = k0 * (k0 + 1) / 2, n1 = k1 * (k1 + 1) / 2;
+    for (int e = threadIdx.x; e < n0 + n1; e += kT) {
+        const int s = e < n0 ? 0 : 1, el = e < n0 ? e : e - n0;
+        int p, q;
+        tri_index(el, p, q);
+        S.G[s][q * kSK + p] = S.G[s][p * kSK + q];
+    }
+}
+
+// Cholesky of the k x k Gram G (LDS, ld kSK) by one wavefront, lane j = index j. With pivoting
+// the largest remaining diagonal is taken next and the factorisation stops when it falls to
+// floor_rel times the largest initial diagonal; without it the order is 0, 1, ... (R rows
+// refer to the current order). On return R[a][j] (a < q) holds row a of R in original
+// column j, perm[a] the a-th pivot and *q the rank.
+__device__ void wave_cholesky(double* G, double* R, int* perm, int* q_out, int k, bool pivot, double floor_rel) {
+    const int j = threadIdx.x & 63;
+    const bool in = j < k;
+    bool rem = in;
+    double d0 = in ? G[j * kSK + j] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) d0 = fmax(d0, __shfl_xor(d0, o, 64));
+    for (int a = 0; a < k; ++a)
+        if (in) R[a * kSK + j] = 0.0;
+    int q = k;
+    for (int a = 0; a < k; ++a) {
+        double dv = rem ? G[j * kSK + j] : -1.0;
+        int pj = j;
+        if (!pivot) {
+            dv = (j == a) ? G[j * kSK + j] : -1.0;
+        }
+        for (int o = 32; o > 0; o >>= 1) {   // argmax, ties to the smaller index
+            const double ov = __shfl_xor(dv, o, 64);
+            const int op = __shfl_xor(pj, o, 64);
+            if (ov > dv || (ov == dv && op < pj)) {
+                dv = ov;
+                pj = op;
+            }
+        }
+        if (!(dv > floor_rel * d0) || !(dv > 0.0)) {
+            q = a;
+            break;
+        }
+        const int p = pj;
+        const double lp = sqrt(dv);
+        if (j == p) rem = false;
+        const double lj = in ? (j == p ? lp : (rem ? G[j * kSK + p] / lp : 0.0)) : 0.0;
+        if (in) R[a * kSK + j] = lj;
+        if (j == 0) perm[a] = p;
+        if (rem)
+            for (int i = 0; i < k; ++i) G[i * kSK + j] -= R[a * kSK + i] * lj;
+    }
+    if (j == 0) *q_out = q;
+}
+
+// one-sided Jacobi on the columns of M (rows x cols, column-major ld kSK) by one wavefront; Z
+// (cols x cols) accumulates the rotations; nrm[c] = norm of rotated column c on return
+__device__ void wave_jacobi_lds(double* M, double* Z, double* nrm, int rows, int cols, double conv) {
+    const int lane = threadIdx.x & 63;
+    for (int i = lane; i < cols * cols; i += 64) Z[(i % cols) + (i / cols) * kSK] = (i % cols == i / cols) ? 1.0 : 0.0;
+    const int n2 = cols + (cols & 1);
+    const int npairs = n2 / 2;
+    int G = 64;
+    while (G > 1 && G * npairs > 64) G >>= 1;
+    const int pi = lane / G, gl = lane % G;
+    const int len = max(rows, cols);
+    for (int sweep = 0; sweep < 30; ++sweep) {
         bool rotated = false;
-        for (int r = 0; r < n2 - 1; ++r) {
-            int partner;
-            if (lane >= n2)
-                partner = lane;
-            else if (lane == n2 - 1)
-                partner = r;
-            else if (lane == r)
-                partner = n2 - 1;
-            else
-                partner = (((2 * r - lane) % (n2 - 1)) + (n2 - 1)) % (n2 - 1);
-            double a = 0.0, g = 0.0;
-#pragma unroll
-            for (int i = 0; i < KP; ++i) {
-                const double pv = __shfl(col[i], partner, 64);
-                a += col[i] * col[i];
-                g += (lane < partner) ? col[i] * pv : pv * col[i];
-            }
-            const double b = __shfl(a, partner, 64);
-            const bool valid = lane < kp && partner < kp && partner != lane;
-            const bool prole = lane < partner;
-            const double ap = prole ? a : b, aq = prole ? b : a;
-            const bool rot = valid && g != 0.0 && fabs(g) > 1e-15 * sqrt(ap * aq);
-            double c = 1.0, s = 0.0;
-            if (rot) {
-                const double zeta = (aq - ap) / (2.0 * g);
-                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                c = 1.0 / sqrt(1.0 + t * t);
-                s = c * t;
-                rotated = true;
-            }
-#pragma unroll
-            for (int i = 0; i < KP; ++i) {
-                const double pv = __shfl(col[i], partner, 64);
-                const double pw = __shfl(w[i], partner, 64);
-                if (rot) {
-                    col[i] = prole ? c * col[i] - s * pv : s * pv + c * col[i];
-                    w[i] = prole ? c * w[i] - s * pw : s * pw + c * w[i];
+        for (int round = 0; round < n2 - 1; ++round) {
+            int p = -1, q = -1;
+            if (pi < npairs) {
+                if (pi == 0) {
+                    p = round;
+                    q = n2 - 1;
+                } else {
+                    p = (round + pi) % (n2 - 1);
+                    q = (round - pi + n2 - 1) % (n2 - 1);
                 }
+            }
+            const bool valid = p >= 0 && p < cols && q < cols;
+            double a = 0.0, b = 0.0, g = 0.0;
+            if (valid)
+                for (int i = gl; i < rows; i += G) {
+                    const double mp = M[i + p * kSK], mq = M[i + q * kSK];
+                    a += mp * mp;
+                    b += mq * mq;
+                    g += mp * mq;
+                }
+            for (int o = G / 2; o > 0; o >>= 1) {
+                a += __shfl_xor(a, o, 64);
+                b += __shfl_xor(b, o, 64);
+                g += __shfl_xor(g, o, 64);
+            }
+            if (valid && g != 0.0 && fabs(g) > conv * sqrt(a * b)) {
+                const double zeta = (b - a) / (2.0 * g);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                for (int i = gl; i < len; i += G) {
+                    if (i < rows) {
+                        const double mp = M[i + p * kSK], mq = M[i + q * kSK];
+                        M[i + p * kSK] = c * mp - sn * mq;
+                        M[i + q * kSK] = sn * mp + c * mq;
+                    }
+                    if (i < cols) {
+                        const double zp = Z[i + p * kSK], zq = Z[i + q * kSK];
+                        Z[i + p * kSK] = c * zp - sn * zq;
+                        Z[i + q * kSK] = sn * zp + c * zq;
+                    }
+                }
+                rotated = true;
             }
         }
         if (!__any(rotated)) break;
     }
-    if (lane < kp) {
-        double nn = 0.0;
-#pragma unroll
-        for (int i = 0; i < KP; ++i)
-            if (i < kp) {
-                M[i + lane * kp] = col[i];
-                W[i + lane * kp] = w[i];
-                nn += col[i] * col[i];
-            }
-        nrm[lane] = sqrt(nn);
-    }
-}
-
-template <class T>
-struct Cat {   // the columns of [A, sb * B]: rows i, A m x ka, B m x kb
-    const T* A;
-    int ars, acs, ka;
-    const T* B;
-    int brs, bcs, kb;
-    double sb;
-    __device__ double at(int i, int c) const {
-        return c < ka ? (double)A[(int64_t)i * ars + (int64_t)c * acs]
-                      : sb * (double)B[(int64_t)i * brs + (int64_t)(c - ka) * bcs];
-    }
-};
-
-// G (kp x kp, FP64, global scratch) = Cat^T Cat; threads split (entry, row slice); part in LDS
-template <class T>
-__device__ void gram(const Cat<T>& U, int m, int kp, double* G, double* part) {
-    const int nent = kp * (kp + 1) / 2;
-    int S = kT / nent;
-    if (S < 1) S = 1;
-    if (S > 64) S = 64;
-    for (int t = threadIdx.x; t < nent * S; t += kT) {
-        const int e = t % nent, sl = t / nent;
-        int q = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while (q * (q + 1) / 2 > e) --q;
-        while ((q + 1) * (q + 2) / 2 <= e) ++q;
-        const int p = e - q * (q + 1) / 2;   // p <= q
-        const int r0 = (int)((int64_t)m * sl / S), r1 = (int)((int64_t)m * (sl + 1) / S);
-        double acc = 0.0;
-        for (int i = r0; i < r1; ++i) acc += U.at(i, p) * U.at(i, q);
-        part[t] = acc;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nent; e += kT) {
-        double acc = 0.0;
-        for (int sl = 0; sl < S; ++sl) acc += part[sl * nent + e];
-        int q = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while (q * (q + 1) / 2 > e) --q;
-        while ((q + 1) * (q + 2) / 2 <= e) ++q;
-        const int p = e - q * (q + 1) / 2;
-        G[p + q * kp] = acc;
-        G[q + p * kp] = acc;
-    }
-    __syncthreads();
-}
-
-// From the eigen-decomposition G = W diag(lam) W^T (rotated columns in G, norms lam):
-// R = diag(sqrt lam) W^T and F = W diag(lam^{+1/2}) (pseudo-inverse square root)
-__device__ void side_factors(const double* W, const double* lam, int kp, double* R, double* F) {
-    double lmax = 0.0;
-    for (int j = 0; j < kp; ++j) lmax = fmax(lmax, lam[j]);
-    const double floor_ = kp * 2.3e-16 * lmax;
-    for (int idx = threadIdx.x; idx < kp * kp; idx += kT) {
-        const int i = idx % kp, j = idx / kp;
-        const double li = lam[i];
-        const bool keep = li > floor_ && li > 0.0;
-        R[i + j * kp] = keep ? sqrt(li) * W[j + i * kp] : 0.0;         // R[i][j] = sqrt(lam_i) W[j][i]
-        const double lj = lam[j];
-        F[i + j * kp] = (lj > floor_ && lj > 0.0) ? W[i + j * kp] / sqrt(lj) : 0.0;
-    }
-}
-
-// C = A B (kp x kp, column-major, FP64 scratch)
-__device__ void small_mm(const double* A, const double* B, double* C, int kp) {
-    for (int idx = threadIdx.x; idx < kp * kp; idx += kT) {
-        const int i = idx % kp, j = idx / kp;
+    for (int c = lane; c < cols; c += 64) {
         double s = 0.0;
-        for (int l = 0; l < kp; ++l) s += A[i + l * kp] * B[l + j * kp];
-        C[i + j * kp] = s;
+        for (int i = 0; i < rows; ++i) s += M[i + c * kSK] * M[i + c * kSK];
+        nrm[c] = sqrt(s);
     }
 }
 
 template <class T>
-__device__ void op_lrsub_fast(const Inst<T>& d, const OpRec& o, Shared& sh, const LRBlockDev& L, int kc, int kx) {
+__device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const OpRec& o, Shared& sh, const LRBlockDev& L, int kc, int kx) {
+    LrsLds& S = sh.ls;
     T* U = d.arena + L.uoff;
     T* V = d.arena + L.voff;
     const int m = L.m, n = L.n, kp = kc + kx;
     const int wave = threadIdx.x >> 6;
+    const bool f64 = sizeof(T) == 8;
     const T* Xp = vptr(d, o.v[0]);
     const T* Yp = vptr(d, o.v[1]);
-    const Cat<T> Uc{U, 1, m, kc, Xp, o.v[0].rs, o.v[0].cs, kx, -1.0};
-    const Cat<T> Vc{V, 1, n, kc, Yp, o.v[1].rs, o.v[1].cs, kx, 1.0};
-    const int K2 = kp * kp;
-    double* base = d.scrd + o.sofs_d;
-    double *Gu = base, *Gv = Gu + K2, *Wu = Gv + K2, *Wv = Wu + K2, *Ru = Wv + K2, *Rv = Ru + K2;
-    double *Fu = Rv + K2, *Fv = Fu + K2, *Mc = Fv + K2, *Wm = Mc + K2, *T1 = Wm + K2, *T2 = T1 + K2;
-    double *lu = T2 + K2, *lv = lu + 32, *sg = lv + 32;
-    double* Qs = sg + 32;   // FP64 copy of the orthogonalised rows for the second pass (max rows x kp)
-    double* part = sh.part;
-    gram(Uc, m, kp, Gu, part);
-    gram(Vc, n, kp, Gv, part);
-    if (wave == 0) {
-        if (kp <= 16) wave_jacobi<16>(Gu, Wu, lu, kp); else wave_jacobi<32>(Gu, Wu, lu, kp);
-    } else if (wave == 1) {
-        if (kp <= 16) wave_jacobi<16>(Gv, Wv, lv, kp); else wave_jacobi<32>(Gv, Wv, lv, kp);
+    const Side<T> su{U, m, kc, Xp, o.v[0].rs, o.v[0].cs, -1.0, m};
+    const Side<T> sv{V, n, kc, Yp, o.v[1].rs, o.v[1].cs, 1.0, n};
+    const int rmax = max(m, n);
+    // Gram matrices
+    gram_clear(S);
+    for (int c0 = 0; c0 < rmax; c0 += kCH) {
+        stage_rows(su, sv, c0, kp, S);
+        __syncthreads();
+        gram_accumulate(S, kp, kp);
+        __syncthreads();
     }
+    gram_mirror(S, kp, kp);
     __syncthreads();
-    side_factors(Wu, lu, kp, Ru, Fu);
-    side_factors(Wv, lv, kp, Rv, Fv);
+    const double floor_rel = f64 ? 1e-14 : 1e-12;
+    if (wave < 2) wave_cholesky(S.G[wave], S.R[wave], S.perm[wave], &S.q[wave], kp, true, floor_rel);
     __syncthreads();
-    if (sizeof(T) == 8) {
-        // second pass: Q1 = U' F, G2 = Q1^T Q1 = W2 diag(l2) W2^T, R <- R2 R1, F <- F1 F2
-        for (int side = 0; side < 2; ++side) {
-            const Cat<T>& C = side == 0 ? Uc : Vc;
-            const int rows = side == 0 ? m : n;
-            double* F = side == 0 ? Fu : Fv;
-            double* R = side == 0 ? Ru : Rv;
-            for (int i = threadIdx.x; i < rows; i += kT) {
-                double row[32];
+    if (f64) {
+        // second pass: rows of Q1 = (A P)[:, :q] R11^{-1} (forward substitution per row), their
+        // Gram G2 = R2^T R2 and R <- R2 R
+        const int q0 = S.q[0], q1 = S.q[1];
+        gram_clear(S);
+        for (int c0 = 0; c0 < rmax; c0 += kCH) {
+            stage_rows(su, sv, c0, kp, S);
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < 2 * kCH; idx += kT) {
+                const int s = idx / kCH, rr = idx % kCH, q = S.q[s];
+                double* row = &S.A[s][rr * kSK];
+                double y[kSK];
 #pragma unroll
-                for (int l = 0; l < 32; ++l) row[l] = l < kp ? C.at(i, l) : 0.0;
-                for (int c = 0; c < kp; ++c) {
-                    double s = 0.0;
+                for (int b = 0; b < kSK; ++b) y[b] = 0.0;
+                // y R11 = a P: y_b = (a_{perm b} - sum_{c<b} y_c R[c][perm b]) / R[b][perm b]
+                for (int b = 0; b < q; ++b) {
+                    const int pb = S.perm[s][b];
+                    double v = row[pb];
 #pragma unroll
-                    for (int l = 0; l < 32; ++l)
-                        if (l < kp) s += row[l] * F[l + c * kp];
-                    Qs[(int64_t)i + (int64_t)c * rows] = s;
+                    for (int c = 0; c < kSK; ++c)
+                        if (c < b) v -= y[c] * S.R[s][c * kSK + pb];
+                    v /= S.R[s][b * kSK + pb];
+#pragma unroll
+                    for (int c = 0; c < kSK; ++c)
+                        if (c == b) y[c] = v;
                 }
+#pragma unroll
+                for (int b = 0; b < kSK; ++b) row[b] = b < q ? y[b] : 0.0;
             }
             __syncthreads();
-            const Cat<double> Q{Qs, 1, rows, kp, nullptr, 0, 0, 0, 0.0};
-            gram(Q, rows, kp, Gu, part);
-            if (wave == 0) {
-                if (kp <= 16) wave_jacobi<16>(Gu, Wu, lu, kp); else wave_jacobi<32>(Gu, Wu, lu, kp);
-            }
-            __syncthreads();
-            side_factors(Wu, lu, kp, T1, T2);   // T1 = R2, T2 = F2
-            __syncthreads();
-            small_mm(T1, R, Mc, kp);             // R2 R1
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < K2; idx += kT) R[idx] = Mc[idx];
-            __syncthreads();
-            small_mm(F, T2, Mc, kp);             // F1 F2
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < K2; idx += kT) F[idx] = Mc[idx];
+            gram_accumulate(S, q0, q1);
             __syncthreads();
         }
+        gram_mirror(S, q0, q1);
+        __syncthreads();
+        if (wave < 2) {
+            // G2 (q x q) = L2 L2^T without pivoting, in A[wave] as scratch for R2 (row a, col b)
+            wave_cholesky(S.G[wave], S.A[wave], S.perm2[wave], &S.q2[wave], S.q[wave], false, 1e-30);
+        }
+        __syncthreads();
+        // R <- R2 R (rows a < q2): R'[a][j] = sum_{b >= a} R2[a][b] R[b][j]; R2 row a in A[s][a*kSK + b]
+        for (int idx = threadIdx.x; idx < 2 * kSK * kp; idx += kT) {
+            const int s = idx / (kSK * kp), rem = idx % (kSK * kp), a = rem / kp, j = rem % kp;
+            double v = 0.0;
+            if (a < S.q2[s])
+                for (int b = a; b < S.q[s]; ++b) v += S.A[s][a * kSK + b] * S.R[s][b * kSK + j];
+            S.G[s][a * kSK + j] = v;   // G no longer needed: holds R' for the copy below
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 2 * kSK * kp; idx += kT) {
+            const int s = idx / (kSK * kp), rem = idx % (kSK * kp), a = rem / kp, j = rem % kp;
+            S.R[s][a * kSK + j] = S.G[s][a * kSK + j];
+        }
+        if (threadIdx.x < 2) S.q[threadIdx.x] = S.q2[threadIdx.x];
+        __syncthreads();
     }
-    // core M = R_u R_v^T and its SVD
-    for (int idx = threadIdx.x; idx < K2; idx += kT) {
-        const int i = idx % kp, j = idx / kp;
-        double s = 0.0;
-        for (int l = 0; l < kp; ++l) s += Ru[i + l * kp] * Rv[j + l * kp];
-        Mc[idx] = s;
+    const int qu = S.q[0], qv = S.q[1];
+    // core M = (R_u P_u^T)(R_v P_v^T)^T (qu x qv, column-major ld kSK) in G[0]; Z in G[1]
+    for (int idx = threadIdx.x; idx < qu * qv; idx += kT) {
+        const int a = idx % qu, b = idx / qu;
+        double v = 0.0;
+        for (int j = 0; j < kp; ++j) v += S.R[0][a * kSK + j] * S.R[1][b * kSK + j];
+        S.G[0][a + b * kSK] = v;
     }
     __syncthreads();
-    if (wave == 0) {
-        if (kp <= 16) wave_jacobi<16>(Mc, Wm, sg, kp); else wave_jacobi<32>(Mc, Wm, sg, kp);
-    }
+    if (wave == 0 && qu > 0 && qv > 0) wave_jacobi_lds(S.G[0], S.G[1], S.sig, qu, qv, f64 ? 1e-15 : 1e-9);
     __syncthreads();
-    for (int j = threadIdx.x; j < kp; j += kT) {
-        int r = 0;
-        const double sj = sg[j];
-        for (int i = 0; i < kp; ++i) r += (sg[i] > sj || (sg[i] == sj && i < j)) ? 1 : 0;
-        sh.order[r] = j;
+    for (int j = threadIdx.x; j < qv; j += kT) {
+        int rank = 0;
+        const double sj = S.sig[j];
+        for (int i = 0; i < qv; ++i) rank += (S.sig[i] > sj || (S.sig[i] == sj && i < j)) ? 1 : 0;
+        sh.order[rank] = j;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const double smax = sg[sh.order[0]];
         int r = 0;
-        if (smax > 0.0)
-            while (r < kp && sg[sh.order[r]] > d.tol * smax) ++r;
+        if (qu > 0 && qv > 0) {
+            const double smax = S.sig[sh.order[0]];
+            if (smax > 0.0)
+                while (r < qv && S.sig[sh.order[r]] > d.tol * smax) ++r;
+        }
         if (r > d.kmax) r = d.kmax;
         sh.r = r;
-        d.ranks[L.slot] = r;
         const double K = kp;
-        sh.lrsub_flops = 2.0 * (m + n) * K * (K + 1.0) * (sizeof(T) == 8 ? 2.0 : 1.0) + 2.0 * (m + n) * K * r;
+        sh.lrsub_flops = (m + n) * K * (K + 1.0) * (f64 ? 3.0 : 1.0) + 2.0 * (m + n) * K * r + 2.0 * K * K * K / 3.0 +
+                         2.0 * K * K * K;
     }
     __syncthreads();
     const int r = sh.r;
-    // Cu[:, c] = F_u * (M W)[:, order c] ; Cv[:, c] = F_v * W_m[:, order c]   (kp x r, into T1 / T2)
-    for (int idx = threadIdx.x; idx < kp * r; idx += kT) {
-        const int i = idx % kp, c = idx / kp, jc = sh.order[c];
-        double su = 0.0, sv = 0.0;
-        for (int l = 0; l < kp; ++l) {
-            su += Fu[i + l * kp] * Mc[l + jc * kp];
-            sv += Fv[i + l * kp] * Wm[l + jc * kp];
-        }
-        T1[i + c * kp] = su;
-        T2[i + c * kp] = sv;
-    }
+    // C_u (kp x r) = P_u R11_u^{-1} (M Z)_order and C_v = P_v R11_v^{-1} Z_order, by back
+    // substitution, one lane per (side, output column); into A[side] (row l, column c)
+    for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) (&S.A[0][0])[idx] = 0.0;
     __syncthreads();
-    // row-local, in place: U[i, :r] = U'[i, :] Cu, V[j, :r] = V'[j, :] Cv
-    for (int i = threadIdx.x; i < m + n; i += kT) {
-        const bool isu = i < m;
-        const int row = isu ? i : i - m;
-        const Cat<T>& C = isu ? Uc : Vc;
-        const double* Cm = isu ? T1 : T2;
-        T* out = isu ? U : V;
-        const int ld = isu ? m : n;
-        double rv[32];
-#pragma unroll
-        for (int l = 0; l < 32; ++l) rv[l] = l < kp ? C.at(row, l) : 0.0;
-        for (int c = 0; c < r; ++c) {
-            double s = 0.0;
-#pragma unroll
-            for (int l = 0; l < 32; ++l)
-                if (l < kp) s += rv[l] * Cm[l + c * kp];
-            out[row + (int64_t)c * ld] = (T)s;
+    if (threadIdx.x < 2 * r) {
+        const int s = threadIdx.x / r, c = threadIdx.x % r, jc = sh.order[c];
+        const int q = S.q[s];
+        const double* rhs = s == 0 ? &S.G[0][jc * kSK] : &S.G[1][jc * kSK];   // column jc (length q)
+        double* C = S.A[s];
+        for (int a = q - 1; a >= 0; --a) {
+            const int pa = S.perm[s][a];
+            double v = rhs[a];
+            for (int b = a + 1; b < q; ++b) v -= S.R[s][a * kSK + S.perm[s][b]] * C[S.perm[s][b] * kSK + c];
+            C[pa * kSK + c] = v / S.R[s][a * kSK + pa];
         }
     }
     __syncthreads();
+    // move C_u, C_v to G (M and Z are no longer needed) so that A can stage rows again
+    for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) (&S.G[0][0])[idx] = (&S.A[0][0])[idx];
+    __syncthreads();
+    // U_C <- A_u C_u, V_C <- A_v C_v, chunk by chunk (a chunk is staged before its rows are written)
+    for (int c0 = 0; c0 < rmax; c0 += kCH) {
+        stage_rows(su, sv, c0, kp, S);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 2 * kCH * r; idx += kT) {
+            const int s = idx / (kCH * r), rem = idx % (kCH * r), rr = rem % kCH, c = rem / kCH, i = c0 + rr;
+            if (i >= (s == 0 ? m : n)) continue;
+            double v = 0.0;
+            for (int l = 0; l < kp; ++l) v += S.A[s][rr * kSK + l] * S.G[s][l * kSK + c];
+            T* out = s == 0 ? U : V;
+            out[i + (int64_t)c * (s == 0 ? m : n)] = (T)v;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.ranks[L.slot] = r;
 }
 
 template <class T>
-__device__ void op_lrsub(const Inst<T>& d, const OpRec& o, Shared& sh) {
+__device__ __attribute__((noinline)) void op_lrsub(const Inst<T>& d, const OpRec& o, Shared& sh) {
     const int kx = dimval(d, o.dim[2]);
     if (threadIdx.x == 0) sh.lrsub_flops = 0.0;
     if (kx <= 0) return;
     const LRBlockDev L = d.lr[o.blk];
-    // k' <= 32: Gram-based recompression (accurate to ~kappa^2 eps in the kept directions)
-    if (d.ranks[L.slot] + kx <= 32) {
-        op_lrsub_fast(d, o, sh, L, d.ranks[L.slot], kx);
+    if (d.ranks[L.slot] + kx <= kSK) {
+        op_lrsub_small(d, o, sh, L, d.ranks[L.slot], kx);
         return;
     }
     T* U = d.arena + L.uoff;
@@ -763,11 +952,39 @@ __device__ bool run_op(const Inst<T>& d, int pc, Shared& sh, int step) {
     if (threadIdx.x == 0) fl = op_flops(d, o);
     bool ok = true;
     switch (o.code) {
-        case OP_GEMM: op_gemm(d, o); break;
+        case OP_GEMM: op_gemm(d, o, sh); break;
         case OP_ZERO: op_zero(d, o); break;
         case OP_TRSM: op_trsm(d, o); break;
         case OP_LRSUB: op_lrsub(d, o, sh); break;
         case OP_GETRF: ok = op_getrf(d, o, sh, pc); break;
+        case OP_LRMV: {
+            // t = V^T X, then Y += alpha U t
+            const LRBlockDev L = d.lr[o.blk];
+            const int rc = -2 - L.slot;
+            OpRec g1{};
+            g1.code = OP_GEMM;
+            g1.v[0] = o.v[2];
+            g1.v[1] = View{B_ARENA, L.n, 1, L.voff};
+            g1.v[2] = o.v[1];
+            g1.dim[0] = rc;
+            g1.dim[1] = o.dim[1];
+            g1.dim[2] = L.n;
+            g1.alpha = 1.f;
+            g1.beta = 0.f;
+            op_gemm(d, g1, sh);
+            __syncthreads();
+            OpRec g2 = g1;
+            g2.v[0] = o.v[0];
+            g2.v[1] = View{B_ARENA, 1, L.m, L.uoff};
+            g2.v[2] = o.v[2];
+            g2.dim[0] = L.m;
+            g2.dim[2] = rc;
+            g2.alpha = o.alpha;
+            g2.beta = 1.f;
+            op_gemm(d, g2, sh);
+            if (threadIdx.x == 0) fl = op_flops(d, g1) + op_flops(d, g2);
+            break;
+        }
         case OP_LOAD: {
             const double* Bs = d.B + (int64_t)step * d.bstep;
             for (int64_t idx = threadIdx.x; idx < (int64_t)d.Nd * d.nrhs; idx += kT) {
@@ -808,7 +1025,8 @@ __device__ void run_program(const Inst<T>& d, Shared& sh, int step) {
 template <class T>
 __global__ void __launch_bounds__(kT) k_interp(const Inst<T>* __restrict__ insts, int step) {
     __shared__ Shared sh;
-    run_program(insts[blockIdx.x], sh, step);
+    const Inst<T> d = insts[blockIdx.x];
+    run_program(d, sh, step);
 }
 
 template <class T>
@@ -822,7 +1040,7 @@ template <class T>
 __global__ void __launch_bounds__(kT) k_level(const Inst<T>* __restrict__ insts, const int2* __restrict__ tasks) {
     __shared__ Shared sh;
     const int2 tk = tasks[blockIdx.x];
-    const Inst<T>& d = insts[tk.x];
+    const Inst<T> d = insts[tk.x];
     // after a breakdown in an earlier level the rest of that factorisation is skipped; the
     // status is read once and shared so that every thread takes the same branch
     if (threadIdx.x == 0) sh.stop = d.status[0];
@@ -842,9 +1060,9 @@ void print_op_profile(const char* what, const unsigned long long* p, int device)
     int rate_khz = 0;
     (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device);
     const double ms_per_tick = rate_khz > 0 ? 1.0 / rate_khz : 0.0;
-    static const char* names[8] = {"-", "GETRF", "TRSM", "GEMM", "LRSUB", "ZERO", "LOAD", "STORE"};
+    static const char* names[kOpCodes] = {"-", "GETRF", "TRSM", "GEMM", "LRSUB", "ZERO", "LOAD", "STORE", "LRMV"};
     fprintf(stderr, "[fde ops] %s:", what);
-    for (int c = 1; c < 8; ++c)
+    for (int c = 1; c < kOpCodes; ++c)
         if (p[2 * c + 1]) fprintf(stderr, " %s %llu x %.3f ms = %.2f ms;", names[c], p[2 * c + 1],
                                   p[2 * c] * ms_per_tick / p[2 * c + 1], p[2 * c] * ms_per_tick);
     fprintf(stderr, "\n");

@@ -21,6 +21,7 @@ struct Plan {
     HTree t;               // t.op is cleared: a plan outlives the operator it was made for
     Program lu, sv;
     int kpmax = 0;
+    bool sv_lds = false;   // every H-solve op works on all right-hand-side columns (LDS kernel usable)
     DevBuf<OpRec> ops_lu, ops_sv;
     DevBuf<LRBlockDev> lr;
     DevBuf<int> h2p;
@@ -68,6 +69,8 @@ struct HLUObj {
         d.bstep = 0;
         d.xstep = 0;
         d.nrhs = nrhs;
+        d.nslots = plan->t.nslots;
+        d.work_rows = (int)plan->sv.work_elems;
         d.tol = tol;
         d.kmax = kmax;
         d.pivot_floor = pivot_floor;
@@ -85,4 +88,6 @@ struct fde_hlu : fde::HLUObj {};
 namespace fde {
 void hlu_prepare_solve(HLUObj* f, int nrhs);
 void hlu_solve(HLUObj* f, int nrhs, const double* B, int ldb, double* X, int ldx);
+// columns per workgroup of the LDS H-solve for these factors and nrhs columns (0: does not fit)
+int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes);
 }  // namespace fde

@@ -124,7 +124,7 @@ void build_hmat(fde_hmat* hm, Op* op, const fde_hparams* prm) {
 
 void report_profile(HLUObj* f, const char* what) {
     if (!f->prof.p) return;
-    unsigned long long h[16];
+    unsigned long long h[kProfSlots];
     FDE_HIP(hipMemcpy(h, f->prof.p, sizeof h, hipMemcpyDeviceToHost));
     print_op_profile(what, h, f->op->ctx->device);
     FDE_HIP(hipMemset(f->prof.p, 0, sizeof h));
@@ -229,8 +229,8 @@ void factor_prepare(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
     f->flops.alloc(c, 2);
     FDE_HIP(hipMemsetAsync(f->flops.p, 0, 2 * sizeof(double), c->stream));
     if (profile_ops_enabled()) {
-        f->prof.alloc(c, 16);
-        FDE_HIP(hipMemsetAsync(f->prof.p, 0, 16 * sizeof(unsigned long long), c->stream));
+        f->prof.alloc(c, kProfSlots);
+        FDE_HIP(hipMemsetAsync(f->prof.p, 0, kProfSlots * sizeof(unsigned long long), c->stream));
     }
     upload_vec(c, f->ranks, hm->init_rank);
     // copy A~ into the factor layout, converting to the factor precision
@@ -290,6 +290,9 @@ void make_plan_host(const HTree& hmt, int kmax, Plan& p, bool check) {
     schedule_levels(p.t, p.lu);
     if (check) check_schedule(p.t, original, p.lu);
     gen_hsolve(p.t, p.sv);
+    p.sv_lds = true;
+    for (const OpRec& o : p.sv.ops)
+        if ((o.code == OP_GEMM || o.code == OP_TRSM || o.code == OP_LRMV) && o.dim[1] != -1) p.sv_lds = false;
     p.kpmax = lrsub_kprime_max(p.t, p.lu);
     if (p.kpmax > kMaxKp) fail(FDE_EUNSUPPORTED, "H-LU needs recompression of width %d > %d", p.kpmax, kMaxKp);
     validate_program(p.t, p.lu, p.t.arena_elems, p.lu.work_elems, 1, false);
@@ -335,9 +338,33 @@ void hlu_prepare_solve(HLUObj* f, int nrhs) {
     }
 }
 
+int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes) {
+    if (!f->plan->sv_lds || nrhs <= 0) return 0;
+    if (!c->lds_limit) c->lds_limit = device_lds_limit(c->device);
+    const Plan& P = *f->plan;
+    int wc = std::min(nrhs, kHsolveMaxCols);
+    auto need = [&](int w) { return hsolve_lds_bytes(f->op->Nd, (int)P.sv.work_elems, P.t.nslots, w, f->esz); };
+    while (wc > 1 && need(wc) > c->lds_limit) --wc;
+    if (need(wc) > c->lds_limit) return 0;
+    *lds_bytes = need(wc);
+    return wc;
+}
+
 void hlu_solve(HLUObj* f, int nrhs, const double* B, int ldb, double* X, int ldx) {
+    Ctx* c = f->op->ctx;
+    hipStream_t st = c->stream;
+    size_t lds = 0;
+    const int wc = hsolve_cols(c, f, nrhs, &lds);
+    if (wc > 0) {
+        // right-hand sides in LDS, one workgroup per chunk of wc columns
+        const int nchunk = (nrhs + wc - 1) / wc;
+        if (f->prec == FDE_FP64)
+            launch_hsolve_one<double>(st, f->inst<double>(true, nrhs, B, ldb, X, ldx), nchunk, wc, lds);
+        else
+            launch_hsolve_one<float>(st, f->inst<float>(true, nrhs, B, ldb, X, ldx), nchunk, wc, lds);
+        return;
+    }
     hlu_prepare_solve(f, nrhs);
-    hipStream_t st = f->op->ctx->stream;
     if (f->prec == FDE_FP64)
         launch_interp_one<double>(st, f->inst<double>(true, nrhs, B, ldb, X, ldx));
     else

@@ -51,7 +51,10 @@ struct LowRankDesc {
 // --------------------------------------------------------------- program
 constexpr int kMaxKprime = 256;   // widest [U, X] recompressed in one OP_LRSUB
 
-enum OpCode { OP_GETRF = 1, OP_TRSM = 2, OP_GEMM = 3, OP_LRSUB = 4, OP_ZERO = 5, OP_LOAD = 6, OP_STORE = 7 };
+// OP_LRMV (H-substitutions): Y += alpha U (V^T X) for low-rank block blk, through temporary v[2]
+enum OpCode { OP_GETRF = 1, OP_TRSM = 2, OP_GEMM = 3, OP_LRSUB = 4, OP_ZERO = 5, OP_LOAD = 6, OP_STORE = 7, OP_LRMV = 8 };
+constexpr int kOpCodes = 9;
+constexpr int kProfSlots = 2 * kOpCodes;   // per op code: wall-clock ticks, count
 enum Base { B_ARENA = 0, B_WORK = 1, B_RHS = 2, B_WORK_NRHS = 3 };
 
 struct View {
@@ -66,7 +69,7 @@ struct OpRec {
     int dim[3];        // m, n, k; >= 0 static, -1 = number of right-hand sides, <= -2: rank slot -2-d
     int blk;           // LRSUB: low-rank block id
     float alpha, beta; // GEMM
-    View v[3];         // GEMM: C, A, B; TRSM: X, T; GETRF: A; LRSUB: X, Y; ZERO: X
+    View v[3];         // GEMM: C, A, B; TRSM: X, T; GETRF: A; LRSUB: X, Y; ZERO: X; LRMV: Y, X, t
     int64_t sofs_t;    // LRSUB: private scratch (elements of the factor type, then doubles)
     int64_t sofs_d;
 };

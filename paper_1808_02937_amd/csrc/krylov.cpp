@@ -138,6 +138,32 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
         FDE_HIP(hipMemcpyAsync(d_i64.p, i64.data(), i64.size() * sizeof(Inst<double>), hipMemcpyHostToDevice, st));
     }
     const bool any_copy = std::any_of(mask.begin(), mask.end(), [](int v) { return v != 0; });
+    // LDS H-solve: one launch per precision, columns in chunks of a common width; the LDS size
+    // is that of the largest system; any group that does not fit sends its precision to the
+    // global-memory interpreter
+    struct HsLaunch {
+        bool lds = true;
+        int wc = kHsolveMaxCols, nchunk = 1;
+        size_t bytes = 0;
+    } hs32, hs64;
+    for (auto& g : groups) {
+        if (!g.nr || !g.prec) continue;
+        HsLaunch& h = g.prec->prec == FDE_FP64 ? hs64 : hs32;
+        size_t b = 0;
+        const int w = hsolve_cols(c, g.prec, g.nr, &b);
+        if (w == 0) h.lds = false;
+        else h.wc = std::min(h.wc, w);
+    }
+    for (HsLaunch* h : {&hs32, &hs64}) {
+        if (!h->lds) continue;
+        for (auto& g : groups) {
+            if (!g.nr || !g.prec || (g.prec->prec == FDE_FP64) != (h == &hs64)) continue;
+            h->nchunk = std::max(h->nchunk, (g.nr + h->wc - 1) / h->wc);
+            const Plan& P = *g.prec->plan;
+            h->bytes = std::max(h->bytes, hsolve_lds_bytes(g.op->Nd, (int)P.sv.work_elems, P.t.nslots, h->wc, g.prec->esz));
+        }
+        if (!c->lds_limit || h->bytes > c->lds_limit) h->lds = false;
+    }
     fg_gnorm(st, ns, d_sys.p, d_ss.p);
     fg_zero_x(st, ns, d_sys.p);
     std::vector<SysState> hs(ns);
@@ -147,8 +173,18 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
         first = false;
         for (int j = 0; j < m; ++j) {
             if (any_copy) fg_copy_step(st, ns, d_sys.p, d_mask.p, j);
-            if (!i32.empty()) launch_interp<float>(st, (int)i32.size(), d_i32.p, j);
-            if (!i64.empty()) launch_interp<double>(st, (int)i64.size(), d_i64.p, j);
+            if (!i32.empty()) {
+                if (hs32.lds)
+                    launch_hsolve<float>(st, (int)i32.size(), hs32.nchunk, hs32.wc, d_i32.p, j, hs32.bytes);
+                else
+                    launch_interp<float>(st, (int)i32.size(), d_i32.p, j);
+            }
+            if (!i64.empty()) {
+                if (hs64.lds)
+                    launch_hsolve<double>(st, (int)i64.size(), hs64.nchunk, hs64.wc, d_i64.p, j, hs64.bytes);
+                else
+                    launch_interp<double>(st, (int)i64.size(), d_i64.p, j);
+            }
             for (auto& g : groups)
                 if (g.nr) stiffness_apply(g.op, g.nr, g.Z.p + (int64_t)j * g.op->Nd * g.nr, g.op->Nd, g.W.p,
                                           g.op->Nd, 0.0, 0.0, false);

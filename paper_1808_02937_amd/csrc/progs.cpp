@@ -126,8 +126,22 @@ class Gen {
             gemm(Y.v, dense(A), X.v, rows(A), X.width, cols(A), alpha, 1.f);
         } else if (a.kind == kLowRank) {
             Slab t = alloc(hm_.kmax, X.width, solve_ ? 1 : cap(X.width));
-            gemm(t.v, T(V(A).v), X.v, rank_code(a), X.width, cols(A), 1.f, 0.f);
-            gemm(Y.v, U(A).v, t.v, rows(A), X.width, rank_code(a), alpha, 1.f);
+            if (solve_) {
+                OpRec o{};
+                o.code = OP_LRMV;
+                o.blk = a.lr_id;
+                o.v[0] = Y.v;
+                o.v[1] = X.v;
+                o.v[2] = t.v;
+                o.dim[0] = rows(A);
+                o.dim[1] = X.width;
+                o.dim[2] = rank_code(a);
+                o.alpha = alpha;
+                p_.ops.push_back(o);
+            } else {
+                gemm(t.v, T(V(A).v), X.v, rank_code(a), X.width, cols(A), 1.f, 0.f);
+                gemm(Y.v, U(A).v, t.v, rows(A), X.width, rank_code(a), alpha, 1.f);
+            }
             release(t);
         } else {
             for (int i = 0; i < 2; ++i)
@@ -381,6 +395,18 @@ void validate_program(const HTree& hm, const Program& prog, int64_t arena_elems,
                 lrsub_need(hm, o, &nt, &nd);
                 if (o.sofs_t < 0 || o.sofs_d < 0 || o.sofs_t + nt > prog.scr_t || o.sofs_d + nd > prog.scr_d)
                     fail(FDE_EDEVICE, "program op %zu: recompression scratch out of range", pc);
+                break;
+            }
+            case OP_LRMV: {
+                if (!solve) fail(FDE_EDEVICE, "program op %zu: low-rank product op in a factorisation", pc);
+                if (o.blk < 0 || o.blk >= (int)hm.lr_blocks.size()) fail(FDE_EDEVICE, "program op %zu: bad block", pc);
+                const Block& b = hm.bl[hm.lr_blocks[o.blk]];
+                const int64_t w = dimv(o.dim[1]);
+                if (o.dim[0] != hm.cl[b.tau].size() || o.dim[2] != -2 - b.slot)
+                    fail(FDE_EDEVICE, "program op %zu: low-rank product dimensions", pc);
+                check(o.v[0], hm.cl[b.tau].size(), w, (int)pc, "lrmv Y");
+                check(o.v[1], hm.cl[b.sigma].size(), w, (int)pc, "lrmv X");
+                check(o.v[2], hm.kmax, w, (int)pc, "lrmv t");
                 break;
             }
             case OP_LOAD:

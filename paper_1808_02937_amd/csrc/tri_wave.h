@@ -1,0 +1,67 @@
+// Triangular solve with a dense leaf of at most 64 rows, one wavefront per right-hand-side
+// column (shared by the H-LU and the H-substitutions).
+//
+// Lane i owns row i. The row is divided by its diagonal entry (lane-local), which turns the
+// system into a unit triangular one; the lane's row of the scaled factor stays in registers
+// for every column the wavefront solves, and each solved entry is broadcast with readlane,
+// so the substitution itself touches neither LDS nor memory and needs no barrier. All factor
+// loads are unconditional (addresses clamped into the leaf) so they are in flight together;
+// the next column is loaded while the current one is solved.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fde {
+
+__device__ inline float lane_bcast(float x, int s) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), s));
+}
+__device__ inline double lane_bcast(double x, int s) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), s);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), s);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// X (n x w; element (i, j) at X[i*xrs + j*xcs]) <- T^{-1} X, T n x n (element (i, s) at
+// Tm[i*trs + s*tcs]), lower or upper, unit diagonal or not; n <= 64. The calling wavefront
+// `wave` of `nwaves` solves columns wave, wave + nwaves, ...
+template <class T>
+__device__ inline void tri_wave(const T* Tm, int trs, int tcs, int n, bool lower, bool unit, T* X, int xrs, int xcs,
+                                int w, int wave, int nwaves) {
+    if (wave >= w || n <= 0) return;
+    const int lane = threadIdx.x & 63;
+    const bool act = lane < n;
+    const int li = min(lane, n - 1);
+    T tr[64];
+#pragma unroll
+    for (int s = 0; s < 64; ++s) tr[s] = Tm[(int64_t)li * trs + (int64_t)min(s, n - 1) * tcs];
+    const T diag = Tm[(int64_t)li * trs + (int64_t)li * tcs];
+    const T dinv = (!unit && act) ? T(1) / diag : T(1);
+#pragma unroll
+    for (int s = 0; s < 64; ++s) tr[s] = (s < n && act) ? tr[s] * dinv : T(0);
+    T xn = X[(int64_t)li * xrs + (int64_t)wave * xcs];
+    for (int j = wave; j < w; j += nwaves) {
+        T x = act ? xn * dinv : T(0);
+        const int jn = j + nwaves;
+        if (jn < w) xn = X[(int64_t)li * xrs + (int64_t)jn * xcs];
+        if (lower) {
+#pragma unroll
+            for (int s = 0; s < 64; ++s)
+                if (s < n) {
+                    const T xs = lane_bcast(x, s);
+                    if (lane > s) x -= tr[s] * xs;
+                }
+        } else {
+#pragma unroll
+            for (int s = 63; s >= 0; --s)
+                if (s < n) {
+                    const T xs = lane_bcast(x, s);
+                    if (lane < s) x -= tr[s] * xs;
+                }
+        }
+        if (act) X[(int64_t)lane * xrs + (int64_t)j * xcs] = x;
+    }
+}
+
+}  // namespace fde
