@@ -141,6 +141,14 @@ int  fde_load_nodes(fde_op* op, int* nq, double* x_host, double* da_host, double
 int  fde_load_vector(fde_op* op, const double* f_host, double c1, double c2, double* G_dev);
 /* Same, with f evaluated through a host callback. */
 int  fde_load_vector_fn(fde_op* op, fde_fn f, void* user, double c1, double c2, double* G_dev);
+/* Same, for f(x) = sum_k coef[k] d_k(x)^expo[k] with d_k = x - a (side[k] = 0)
+ * or b - x (side[k] = 1), evaluated on the device at the nodes of
+ * fde_load_nodes through their exact distances. This is the form of the
+ * right-hand side that Section 5 derives from a solution given as a sum of
+ * powers (a Riemann-Liouville derivative of d^mu is a multiple of
+ * d^{mu-alpha}). nterms <= 64; host arrays, read before return. */
+int  fde_load_vector_powers(fde_op* op, int nterms, const double* coef_host, const double* expo_host,
+                            const int* side_host, double c1, double c2, double* G_dev);
 
 /* ---- stiffness apply (Section 4.3) ------------------------------------- */
 

@@ -14,6 +14,7 @@
 //                   Bernstein-ellipse bound of the kernel.
 // The far-field blocks are pow-bound FP64 ALU work; each is staged through LDS
 // as (weights * kernel) -> (Legendre_t * .) -> (. * Legendre_s) contractions.
+#include <algorithm>
 #include <cmath>
 
 #include "fde_internal.h"
@@ -391,6 +392,28 @@ void launch_dense_matrix(Op* op, double* A, int lda) {
     const int Nd = op->Nd;
     dim3 grid(ceil_div(Nd, 128), Nd);
     hipLaunchKernelGGL(k_dense_matrix, grid, dim3(128), 0, op->ctx->stream, sem_dev(op), A, lda);
+    FDE_LAUNCH_CHECK();
+}
+
+namespace {
+// f(x_q) = sum_k coef_k d_k^{expo_k} at every load-vector node, d_k the exact distance to a
+// (side 0) or to b (side 1)
+__global__ void k_eval_powers(int nq, const double* __restrict__ da, const double* __restrict__ db, int nt,
+                              const double* __restrict__ coef, const double* __restrict__ expo,
+                              const int* __restrict__ side, double* __restrict__ f) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+        const double a = da[q], b = db[q];
+        double s = 0.0;
+        for (int k = 0; k < nt; ++k) s += coef[k] * pow(side[k] ? b : a, expo[k]);
+        f[q] = s;
+    }
+}
+}  // namespace
+
+void launch_eval_powers(Op* op, int nt, const double* d_coef, const double* d_expo, const int* d_side) {
+    const int nq = (int)op->lq_x.size();
+    hipLaunchKernelGGL(k_eval_powers, dim3(std::min(ceil_div(nq, 256), 1024)), dim3(256), 0, op->ctx->stream, nq,
+                       op->d_lq_da.p, op->d_lq_db.p, nt, d_coef, d_expo, d_side, op->d_lq_f.p);
     FDE_LAUNCH_CHECK();
 }
 

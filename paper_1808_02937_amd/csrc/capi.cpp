@@ -443,24 +443,28 @@ int fde_load_nodes(fde_op* op, int* nq, double* x, double* da, double* db) {
     FDE_API_END
 }
 
-int fde_load_vector(fde_op* op, const double* f, double c1, double c2, double* G) {
-    FDE_API_BEGIN
-    if (!op || !f || !G) fail(FDE_EINVAL, "bad arguments");
-    if (!std::isfinite(c1) || !std::isfinite(c2)) fail(FDE_EINVAL, "boundary values must be finite");
+namespace {
+
+void load_rule_to_device(Op* op) {
     Ctx* c = op->ctx;
     const size_t nq = op->lq_x.size();
-    if (op->d_lq_xi.n != nq) {
-        op->d_lq_xi.alloc(c, nq);
-        op->d_lq_w.alloc(c, nq);
-        op->d_lq_off.alloc(c, op->lq_off.size());
-        upload(c, op->d_lq_xi.p, op->lq_xi.data(), nq * sizeof(double));
-        upload(c, op->d_lq_w.p, op->lq_w.data(), nq * sizeof(double));
-        upload(c, op->d_lq_off.p, op->lq_off.data(), op->lq_off.size() * sizeof(int));
-        op->d_lq_f.alloc(c, nq);
-    }
-    for (size_t q = 0; q < nq; ++q)
-        if (!std::isfinite(f[q])) fail(FDE_EINVAL, "f is not finite at node %zu (x = %.17g)", q, op->lq_x[q]);
-    upload(c, op->d_lq_f.p, f, nq * sizeof(double));
+    if (op->d_lq_xi.n == nq) return;
+    op->d_lq_xi.alloc(c, nq);
+    op->d_lq_w.alloc(c, nq);
+    op->d_lq_da.alloc(c, nq);
+    op->d_lq_db.alloc(c, nq);
+    op->d_lq_off.alloc(c, op->lq_off.size());
+    upload(c, op->d_lq_xi.p, op->lq_xi.data(), nq * sizeof(double));
+    upload(c, op->d_lq_w.p, op->lq_w.data(), nq * sizeof(double));
+    upload(c, op->d_lq_da.p, op->lq_da.data(), nq * sizeof(double));
+    upload(c, op->d_lq_db.p, op->lq_db.data(), nq * sizeof(double));
+    upload(c, op->d_lq_off.p, op->lq_off.data(), op->lq_off.size() * sizeof(int));
+    op->d_lq_f.alloc(c, nq);
+}
+
+// G from the values in d_lq_f, then the lifting of the boundary values
+void assemble_load(Op* op, double c1, double c2, double* G) {
+    Ctx* c = op->ctx;
     launch_load_vector(op, G);
     if (c1 != 0.0 || c2 != 0.0) {
         // lifting: G -= A [0; c1, c2] through the boundary hats
@@ -470,6 +474,49 @@ int fde_load_vector(fde_op* op, const double* f, double c1, double c2, double* G
         axpy_cols(c->stream, op->Nd, 1, -1.0, t.p, op->Nd, G, op->Nd);
         FDE_HIP(hipStreamSynchronize(c->stream));
     }
+}
+
+}  // namespace
+
+int fde_load_vector_powers(fde_op* op, int nterms, const double* coef, const double* expo, const int* side,
+                           double c1, double c2, double* G) {
+    FDE_API_BEGIN
+    if (!op || !G || nterms < 0 || nterms > 64 || (nterms > 0 && (!coef || !expo || !side)))
+        fail(FDE_EINVAL, "bad arguments");
+    if (!std::isfinite(c1) || !std::isfinite(c2)) fail(FDE_EINVAL, "boundary values must be finite");
+    for (int k = 0; k < nterms; ++k) {
+        if (!std::isfinite(coef[k]) || !std::isfinite(expo[k])) fail(FDE_EINVAL, "term %d is not finite", k);
+        if (side[k] != 0 && side[k] != 1) fail(FDE_EINVAL, "term %d: side must be 0 or 1", k);
+    }
+    Ctx* c = op->ctx;
+    load_rule_to_device(op);
+    DevBuf<double> d_ce;
+    DevBuf<int> d_s;
+    const int nt = std::max(nterms, 1);
+    d_ce.alloc(c, 2 * nt);
+    d_s.alloc(c, nt);
+    if (nterms > 0) {
+        upload(c, d_ce.p, coef, nterms * sizeof(double));
+        upload(c, d_ce.p + nt, expo, nterms * sizeof(double));
+        upload(c, d_s.p, side, nterms * sizeof(int));
+    }
+    launch_eval_powers(op, nterms, d_ce.p, d_ce.p + nt, d_s.p);
+    assemble_load(op, c1, c2, G);
+    FDE_HIP(hipStreamSynchronize(c->stream));   // the coefficient buffers are freed on return
+    FDE_API_END
+}
+
+int fde_load_vector(fde_op* op, const double* f, double c1, double c2, double* G) {
+    FDE_API_BEGIN
+    if (!op || !f || !G) fail(FDE_EINVAL, "bad arguments");
+    if (!std::isfinite(c1) || !std::isfinite(c2)) fail(FDE_EINVAL, "boundary values must be finite");
+    Ctx* c = op->ctx;
+    const size_t nq = op->lq_x.size();
+    load_rule_to_device(op);
+    for (size_t q = 0; q < nq; ++q)
+        if (!std::isfinite(f[q])) fail(FDE_EINVAL, "f is not finite at node %zu (x = %.17g)", q, op->lq_x[q]);
+    upload(c, op->d_lq_f.p, f, nq * sizeof(double));
+    assemble_load(op, c1, c2, G);
     FDE_HIP(hipStreamSynchronize(c->stream));
     FDE_API_END
 }

@@ -103,7 +103,7 @@ struct Op {
     // load-vector quadrature (host + device)
     std::vector<double> lq_x, lq_xi, lq_w, lq_da, lq_db;
     std::vector<int> lq_off;     // N+1 offsets
-    DevBuf<double> d_lq_xi, d_lq_w, d_lq_f;
+    DevBuf<double> d_lq_xi, d_lq_w, d_lq_f, d_lq_da, d_lq_db;
     DevBuf<int> d_lq_off;
     // apply workspace
     DevBuf<double> ws;
@@ -115,6 +115,8 @@ void launch_pair_moments_dense(Op* op);
 void launch_generators(Op* op);
 void launch_pair_moments_list(Op* op, int npairs, const int* d_e, const int* d_f, double* d_out);
 void launch_load_vector(Op* op, double* G);
+// d_lq_f <- sum_k coef_k d_k^{expo_k} at the load-vector nodes (device coefficient arrays)
+void launch_eval_powers(Op* op, int nt, const double* d_coef, const double* d_expo, const int* d_side);
 void launch_dense_matrix(Op* op, double* A, int lda);
 
 // apply (apply.hip): Y = A X (+ boundary values bc0/bcN of the lifting)

@@ -24,6 +24,10 @@ __global__ void k_hbuild_dense(SemDev s, const DenseBlkDev* __restrict__ blks, c
     }
 }
 
+// One thread per row of a factor side; all R expansion terms of the row at once: at each
+// quadrature node the first power is one pow() and the following ones come by repeated
+// multiplication with the same ratio ((x-c)/r, or 1/(sgn(x-c)) for the singular side).
+constexpr int kNuChunk = 16;
 __global__ void k_hbuild_factors(int P, int R, double alpha, const double* __restrict__ x,
                                  const double* __restrict__ h, const double* __restrict__ gl,
                                  const FacSideDev* __restrict__ sides, double* __restrict__ arena) {
@@ -31,50 +35,69 @@ __global__ void k_hbuild_factors(int P, int R, double alpha, const double* __res
     const int nq = f.sing ? min(kMaxGL, P + 24) : min(kMaxGL, (R + P) / 2 + 2);
     const int off_n = nq * (nq - 1) / 2;
     const int wbase = kMaxGL * (kMaxGL + 1) / 2;
-    for (int q = threadIdx.x; q < f.rows * R; q += blockDim.x) {
-        const int i = q % f.rows, nu = q / f.rows;
-        double val = 0.0;
-        if (f.mult != 0.0) {
-            const int d = f.d0 + i;
-            const int e = d / P, l = d % P;
-            double coef = 1.0;
-            if (f.sing) {
-                for (int k = 1; k <= nu; ++k) coef *= (alpha + k - 2.0) / k;
-                if (f.alt && (nu & 1)) coef = -coef;
-                coef *= pow(f.r, (double)nu);
-            }
-            int ne, el[2], mm[2];
-            double cf[2];
-            if (l < P - 1) {
-                ne = 1;
-                el[0] = e;
-                mm[0] = l + 1;
-                cf[0] = -(2.0 * (l + 1) + 1.0) * 2.0 / h[e];
-            } else {
-                ne = 2;
-                el[0] = e;
-                mm[0] = 0;
-                cf[0] = 1.0 / h[e];
-                el[1] = e + 1;
-                mm[1] = 0;
-                cf[1] = -1.0 / h[e + 1];
-            }
+    for (int i = threadIdx.x; i < f.rows; i += blockDim.x) {
+        if (f.mult == 0.0) {
+            for (int nu = 0; nu < R; ++nu) arena[f.off + i + (int64_t)nu * f.rows] = 0.0;
+            continue;
+        }
+        const int d = f.d0 + i;
+        const int e = d / P, l = d % P;
+        int ne, el[2], mm[2];
+        double cf[2];
+        if (l < P - 1) {
+            ne = 1;
+            el[0] = e;
+            mm[0] = l + 1;
+            cf[0] = -(2.0 * (l + 1) + 1.0) * 2.0 / h[e];
+        } else {
+            ne = 2;
+            el[0] = e;
+            mm[0] = 0;
+            cf[0] = 1.0 / h[e];
+            el[1] = e + 1;
+            mm[1] = 0;
+            cf[1] = -1.0 / h[e + 1];
+        }
+        for (int nu0 = 0; nu0 < R; nu0 += kNuChunk) {
+            double acc[kNuChunk];
+#pragma unroll
+            for (int u = 0; u < kNuChunk; ++u) acc[u] = 0.0;
             for (int a = 0; a < ne; ++a) {
                 const int ee = el[a];
                 const double xl = x[ee], he = h[ee];
-                double s = 0.0;
+                const double scale = cf[a] * 0.5 * he;
                 for (int k = 0; k < nq; ++k) {
                     const double xr = gl[off_n + k], w = gl[wbase + off_n + k];
                     const double xx = xl + 0.5 * he * (1.0 + xr);
-                    const double F = f.sing ? pow(f.sgn * (xx - f.c), 1.0 - alpha - nu)
-                                            : pow((xx - f.c) / f.r, (double)nu);
-                    s += w * F * legendre_at(mm[a], xr);
+                    double F, step;
+                    if (f.sing) {
+                        const double b = f.sgn * (xx - f.c);
+                        F = pow(b, 1.0 - alpha - nu0);
+                        step = 1.0 / b;
+                    } else {
+                        const double b = (xx - f.c) / f.r;
+                        F = pow(b, (double)nu0);
+                        step = b;
+                    }
+                    const double wl = scale * w * legendre_at(mm[a], xr);
+#pragma unroll
+                    for (int u = 0; u < kNuChunk; ++u) {
+                        acc[u] += wl * F;
+                        F *= step;
+                    }
                 }
-                val += cf[a] * 0.5 * he * s;
             }
-            val *= f.mult * coef;
+            for (int u = 0; u < kNuChunk && nu0 + u < R; ++u) {
+                const int nu = nu0 + u;
+                double coef = 1.0;
+                if (f.sing) {
+                    for (int k = 1; k <= nu; ++k) coef *= (alpha + k - 2.0) / k;
+                    if (f.alt && (nu & 1)) coef = -coef;
+                    coef *= pow(f.r, (double)nu);
+                }
+                arena[f.off + i + (int64_t)nu * f.rows] = acc[u] * f.mult * coef;
+            }
         }
-        arena[f.off + i + (int64_t)nu * f.rows] = val;
     }
 }
 

@@ -41,9 +41,10 @@ struct Inst {
 bool profile_ops_enabled();
 void print_op_profile(const char* what, const unsigned long long* host_prof, int device);
 
-// serial: one workgroup runs the whole op list of each instance
+// serial: one workgroup runs the whole op list of each instance (variant as for launch_level;
+// a factorisation run serially and by levels uses the same variant, so both give the same bits)
 template <class T>
-void launch_interp(hipStream_t st, int ninst, const Inst<T>* d_insts, int step = 0);
+void launch_interp(hipStream_t st, int ninst, const Inst<T>* d_insts, int step = 0, int variant = 0);
 template <class T>
 void launch_interp_one(hipStream_t st, const Inst<T>& d);
 // H-solve with the right-hand sides in LDS: workgroup b solves columns [c*wc, c*wc + wc) of
@@ -59,8 +60,9 @@ constexpr int kHsolveMaxCols = 8;
 // largest dynamic LDS of one workgroup on the device (bytes)
 size_t device_lds_limit(int device);
 
-// one level of level-scheduled programs: workgroup b runs op tasks[b].y of instance tasks[b].x
+// one level of level-scheduled programs: workgroup b runs op tasks[b].y of instance tasks[b].x.
+// variant: widest recompression the programs can need -- 16 or 32 (small path only), 0 (any)
 template <class T>
-void launch_level(hipStream_t st, int ntasks, const Inst<T>* d_insts, const int2* d_tasks);
+void launch_level(hipStream_t st, int ntasks, const Inst<T>* d_insts, const int2* d_tasks, int variant);
 
 }  // namespace fde

@@ -24,18 +24,6 @@ namespace {
 constexpr int kT = kInterpThreads;
 constexpr int kW = kT / 64;
 
-constexpr int kSK = 32;   // widest k' of the small recompression
-constexpr int kCH = 32;   // rows per staged chunk
-
-struct LrsLds {
-    double A[2][kCH * kSK];   // staged rows of both sides (row-major, stride kSK); later C_u, C_v
-    double G[2][kSK * kSK];   // Gram matrices; then the core M and rotations Z; then C_u, C_v
-    double R[2][kSK * kSK];   // Cholesky factors R[a][j] (row a, original column j)
-    double sig[kSK];
-    int perm[2][kSK], perm2[2][kSK];
-    int q[2], q2[2];
-};
-
 constexpr int kGT = 64;            // GEMM output tile (rows and columns)
 constexpr int kGK = 32;            // GEMM k chunk
 template <class T>
@@ -43,21 +31,34 @@ struct GemmLds {
     T A[kGT][kGK + 1];             // A tile, row-major (padded)
     T B[kGK][kGT + 1];             // B tile, row-major (padded)
 };
-constexpr int kLU = 64;            // GETRF leaves staged in LDS up to this size
-struct GetrfLds {
-    double A[kLU * (kLU + 1)];     // column-major, ld kLU + 1 (as T)
+constexpr int kLU = 64;            // GETRF leaves factored in registers up to this size
+
+// small recompression (k' <= KS): staged rows, Gram matrices, Cholesky factors
+template <int KS>
+struct LrsLds {
+    static constexpr int K = KS;                     // widest k'
+    static constexpr int CH = KS <= 16 ? 64 : 32;    // rows per staged chunk
+    double A[2][CH * KS];   // staged rows of both sides (row-major, stride K); later C_u, C_v
+    double G[2][KS * KS];   // Gram matrices; then the core M and rotations Z; then C_u, C_v
+    double R[2][KS * KS];   // Cholesky factors R[a][j] (row a, original column j)
+    double sig[KS];
+    int perm[2][KS], perm2[2][KS];
+    int q[2], q2[2];
 };
 
+// LDS of one interpreter workgroup. KS: widest recompression of the small path; GENERAL: the
+// variant also carries the Gram-Schmidt path for wider ones (and its larger register file)
+template <class T, int KS, bool GENERAL>
 struct Shared {
+    static constexpr int kSmall = KS;
+    static constexpr bool kGeneral = GENERAL;
     union {
-        LrsLds ls;
-        GemmLds<double> gd;
-        GemmLds<float> gf;
-        GetrfLds lu;
+        LrsLds<KS> ls;
+        GemmLds<T> gm;
     };
     double red[kW][32];
-    double dots[kMaxKp];
-    int order[kMaxKp];
+    double dots[GENERAL ? kMaxKp : 1];
+    int order[GENERAL ? kMaxKp : KS];
     int flag;
     int stop;
     int r;
@@ -78,7 +79,8 @@ __device__ inline double group_sum(double v, int G) {
     return v;
 }
 
-__device__ inline double block_sum(double v, Shared& sh) {
+template <class SH>
+__device__ inline double block_sum(double v, SH& sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     v = wave_sum(v);
     __syncthreads();
@@ -89,7 +91,8 @@ __device__ inline double block_sum(double v, Shared& sh) {
     __syncthreads();
     return s;
 }
-__device__ inline double block_max(double v, Shared& sh) {
+template <class SH>
+__device__ inline double block_max(double v, SH& sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     v = wave_max(v);
     __syncthreads();
@@ -117,18 +120,11 @@ __device__ inline int dimval(const Inst<T>& d, int code) {
 }
 
 // ------------------------------------------------------------------ GEMM / ZERO
-template <class T>
-__device__ inline GemmLds<T>& gemm_lds(Shared& sh);
-template <>
-__device__ inline GemmLds<double>& gemm_lds<double>(Shared& sh) { return sh.gd; }
-template <>
-__device__ inline GemmLds<float>& gemm_lds<float>(Shared& sh) { return sh.gf; }
-
 // C = beta C + alpha A B. Blocks of at least 16 x 16 outputs go through LDS tiles (64 x 64
 // outputs, k in chunks of 32; each thread a 4 x 4 register tile); thin products use G lanes
 // per output, consecutive lanes along k, reduced by shuffles, or one thread per output.
-template <class T>
-__device__ __attribute__((noinline)) void op_gemm(const Inst<T>& d, const OpRec& o, Shared& sh) {
+template <class T, class SH>
+__device__ __attribute__((noinline)) void op_gemm(const Inst<T>& d, const OpRec& o, SH& sh) {
     const int m = dimval(d, o.dim[0]), n = dimval(d, o.dim[1]), k = dimval(d, o.dim[2]);
     T* C = vptr(d, o.v[0]);
     const T* A = vptr(d, o.v[1]);
@@ -139,7 +135,7 @@ __device__ __attribute__((noinline)) void op_gemm(const Inst<T>& d, const OpRec&
     if (m <= 0 || n <= 0) return;
     const int t = threadIdx.x;
     if (m >= 16 && n >= 16 && k >= 4) {
-        GemmLds<T>& L = gemm_lds<T>(sh);
+        GemmLds<T>& L = sh.gm;
         const int ti = t % 16, tj = t / 16;   // rows 4 ti .. 4 ti + 3, columns 4 tj .. 4 tj + 3 of a tile
         for (int i0 = 0; i0 < m; i0 += kGT)
             for (int j0 = 0; j0 < n; j0 += kGT) {
@@ -329,59 +325,89 @@ __device__ __attribute__((noinline)) void op_trsm(const Inst<T>& d, const OpRec&
 }
 
 // ------------------------------------------------------------------ GETRF
-// LU without pivoting of a dense leaf (unit lower L): right-looking, in LDS for leaves up to
-// kLU (one barrier after the multipliers and one after each rank-one update)
-template <class T>
-__device__ __attribute__((noinline)) bool op_getrf(const Inst<T>& d, const OpRec& o, Shared& sh, int pc) {
+// LU without pivoting of a dense leaf (unit lower L), right-looking. Leaves up to kLU = 64 rows:
+// one wavefront, lane i holds row i in registers; both loops are unrolled, so at step k the
+// pivot row is broadcast entry by entry with readlane and every lane updates its own row, with
+// no LDS traffic and no barrier. Larger leaves: in place, two barriers per step.
+template <class T, class SH>
+__device__ __attribute__((noinline)) bool op_getrf(const Inst<T>& d, const OpRec& o, SH& sh, int pc) {
     const int n = o.dim[0];
     T* A = vptr(d, o.v[0]);
     const int rs = o.v[0].rs, cs = o.v[0].cs;
     auto at = [&](int i, int j) -> T& { return A[(int64_t)i * rs + (int64_t)j * cs]; };
-    const bool lds = n <= kLU;
-    T* S = reinterpret_cast<T*>(sh.lu.A);
-    constexpr int ld = kLU + 1;
-    double amax = 0.0;
-    for (int idx = threadIdx.x; idx < n * n; idx += kT) {
-        const int i = idx % n, j = idx / n;
-        const T v = at(i, j);
-        if (lds) S[i + j * ld] = v;
-        amax = fmax(amax, fabs((double)v));
+    if (n <= kLU) {
+        if (threadIdx.x < 64) {
+            const int i = threadIdx.x;
+            const int ri = min(i, n - 1);
+            T a[kLU];
+#pragma unroll
+            for (int j = 0; j < kLU; ++j) a[j] = A[(int64_t)ri * rs + (int64_t)min(j, n - 1) * cs];
+            double amax = 0.0;
+#pragma unroll
+            for (int j = 0; j < kLU; ++j) {
+                if (i >= n || j >= n) a[j] = T(0);
+                amax = fmax(amax, fabs((double)a[j]));
+            }
+            for (int o2 = 32; o2 > 0; o2 >>= 1) amax = fmax(amax, __shfl_xor(amax, o2, 64));
+            int fail_at = -1;
+#pragma unroll
+            for (int k = 0; k < kLU; ++k) {
+                if (k < n && fail_at < 0) {
+                    const T akk = lane_bcast(a[k], k);
+                    if (!(fabs((double)akk) > d.pivot_floor * amax) || !(fabs((double)akk) > 0.0)) {
+                        fail_at = k;
+                    } else {
+                        const T l = i > k ? a[k] / akk : T(0);
+                        if (i > k) a[k] = l;
+#pragma unroll
+                        for (int j = k + 1; j < kLU; ++j) a[j] -= l * lane_bcast(a[j], k);
+                    }
+                }
+            }
+            if (fail_at < 0 && i < n)
+#pragma unroll
+                for (int j = 0; j < kLU; ++j)
+                    if (j < n) A[(int64_t)i * rs + (int64_t)j * cs] = a[j];
+            if (i == 0) sh.flag = fail_at;
+        }
+        __syncthreads();
+        if (sh.flag >= 0) {
+            if (threadIdx.x == 0) {
+                d.status[0] = FDE_EBREAKDOWN;
+                d.status[1] = pc;
+            }
+            return false;
+        }
+        return true;
     }
-    amax = block_max(amax, sh);   // contains barriers
-    auto el = [&](int i, int j) -> T& { return lds ? S[i + j * ld] : at(i, j); };
-    bool ok = true;
-    for (int kk = 0; kk < n; ++kk) {
-        const T akk = el(kk, kk);
+    double amax = 0.0;
+    for (int idx = threadIdx.x; idx < n * n; idx += kT) amax = fmax(amax, fabs((double)at(idx % n, idx / n)));
+    amax = block_max(amax, sh);
+    for (int k = 0; k < n; ++k) {
+        const T akk = at(k, k);
         if (!(fabs((double)akk) > d.pivot_floor * amax) || !(fabs((double)akk) > 0.0)) {
             if (threadIdx.x == 0) {
                 d.status[0] = FDE_EBREAKDOWN;
                 d.status[1] = pc;
             }
-            ok = false;
-            break;
+            return false;
         }
-        const T inv = T(1) / akk;
-        for (int i = kk + 1 + threadIdx.x; i < n; i += kT) el(i, kk) *= inv;
+        for (int i = k + 1 + threadIdx.x; i < n; i += kT) at(i, k) /= akk;
         __syncthreads();
-        const int r = n - kk - 1;
+        const int r = n - k - 1;
         for (int idx = threadIdx.x; idx < r * r; idx += kT) {
-            const int i = kk + 1 + idx % r, j = kk + 1 + idx / r;
-            el(i, j) -= el(i, kk) * el(kk, j);
+            const int i = k + 1 + idx % r, j = k + 1 + idx / r;
+            at(i, j) -= at(i, k) * at(k, j);
         }
         __syncthreads();
     }
-    if (ok && lds)
-        for (int idx = threadIdx.x; idx < n * n; idx += kT) {
-            const int i = idx % n, j = idx / n;
-            at(i, j) = S[i + j * ld];
-        }
-    return ok;
+    return true;
 }
 
 // ------------------------------------------------------------------ LRSUB
 // thin QR of Q (rows x kp, ld rows) in place, R (kp x kp, ld kp)
-template <class T>
-__device__ void qr_cgs2(T* Q, int rows, int kp, T* R, Shared& sh) {
+template <class T, class SH>
+__device__ void qr_cgs2(T* Q, int rows, int kp, T* R, SH& sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const double eps = sizeof(T) == 4 ? 1.2e-7 : 2.3e-16;
     for (int j = 0; j < kp; ++j) {
@@ -436,7 +462,8 @@ __device__ void qr_cgs2(T* Q, int rows, int kp, T* R, Shared& sh) {
 }
 
 // one-sided Jacobi on the columns of M (kp x kp, FP64); W accumulates the rotations
-__device__ void jacobi_svd(double* M, double* W, int kp, Shared& sh) {
+template <class SH>
+__device__ void jacobi_svd(double* M, double* W, int kp, SH& sh) {
     const int n2 = kp + (kp & 1);
     const int npairs = n2 / 2;
     int G = 64;
@@ -520,8 +547,9 @@ struct Side {
 };
 
 // stage rows [c0, c0 + kCH) of both sides into LDS (row-major, stride kSK; zero beyond the rows)
-template <class T>
-__device__ void stage_rows(const Side<T>& su, const Side<T>& sv, int c0, int kp, LrsLds& S) {
+template <class T, class LS>
+__device__ void stage_rows(const Side<T>& su, const Side<T>& sv, int c0, int kp, LS& S) {
+    constexpr int kSK = LS::K, kCH = LS::CH;
     for (int idx = threadIdx.x; idx < 2 * kCH * kp; idx += kT) {
         const int s = idx / (kCH * kp), rem = idx % (kCH * kp);
         const int c = rem / kCH, rr = rem % kCH, i = c0 + rr;
@@ -536,7 +564,7 @@ __device__ void stage_rows(const Side<T>& su, const Side<T>& sv, int c0, int kp,
 }
 
 __device__ inline void tri_index(int e, int& p, int& q) {   // e -> (p <= q) of the upper triangle
-    q = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    q = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
     while (q * (q + 1) / 2 > e) --q;
     while ((q + 1) * (q + 2) / 2 <= e) ++q;
     p = e - q * (q + 1) / 2;
@@ -544,10 +572,14 @@ __device__ inline void tri_index(int e, int& p, int& q) {   // e -> (p <= q) of 
 
 // Gram matrices of the staged rows, accumulated in LDS over the caller's chunk loop: entry
 // (p <= q) of either side always belongs to the same thread, so there is no race
-__device__ inline void gram_clear(LrsLds& S) {
+template <class LS>
+__device__ inline void gram_clear(LS& S) {
+    constexpr int kSK = LS::K;
     for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) (&S.G[0][0])[idx] = 0.0;
 }
-__device__ inline void gram_accumulate(LrsLds& S, int k0, int k1) {
+template <class LS>
+__device__ inline void gram_accumulate(LS& S, int k0, int k1) {
+    constexpr int kSK = LS::K, kCH = LS::CH;
     const int n0 = k0 * (k0 + 1) / 2, n1 = k1 * (k1 + 1) / 2;
     for (int e = threadIdx.x; e < n0 + n1; e += kT) {
         const int s = e < n0 ? 0 : 1, el = e < n0 ? e : e - n0;
@@ -560,7 +592,9 @@ __device__ inline void gram_accumulate(LrsLds& S, int k0, int k1) {
         S.G[s][p * kSK + q] += a;
     }
 }
-__device__ inline void gram_mirror(LrsLds& S, int k0, int k1) {
+template <class LS>
+__device__ inline void gram_mirror(LS& S, int k0, int k1) {
+    constexpr int kSK = LS::K;
     const int n0 = k0 * (k0 + 1) / 2, n1 = k1 * (k1 + 1) / 2;
     for (int e = threadIdx.x; e < n0 + n1; e += kT) {
         const int s = e < n0 ? 0 : 1, el = e < n0 ? e : e - n0;
@@ -570,119 +604,155 @@ __device__ inline void gram_mirror(LrsLds& S, int k0, int k1) {
     }
 }
 
-// Cholesky of the k x k Gram G (LDS, ld kSK) by one wavefront, lane j = index j. With pivoting
-// the largest remaining diagonal is taken next and the factorisation stops when it falls to
-// floor_rel times the largest initial diagonal; without it the order is 0, 1, ... (R rows
-// refer to the current order). On return R[a][j] (a < q) holds row a of R in original
-// column j, perm[a] the a-th pivot and *q the rank.
-__device__ void wave_cholesky(double* G, double* R, int* perm, int* q_out, int k, bool pivot, double floor_rel) {
+// Cholesky of the k x k Gram G (LDS, ld kSK) by one wavefront, lane j = index j, in registers:
+// lane j holds column j and its current diagonal; the pivot is wave-uniform and the new column of
+// L is broadcast with readlane for the Schur update. With pivoting the largest remaining diagonal
+// is taken next and the factorisation stops when it falls to floor_rel times the largest initial
+// diagonal; without it the order is 0, 1, ... On return R[a][j] (a < q, LDS) holds row a of R in
+// original column j, perm[a] the a-th pivot and *q the rank.
+template <int kSK>
+__device__ void wave_cholesky(const double* G, double* R, int* perm, int* q_out, int k, bool pivot, double floor_rel) {
     const int j = threadIdx.x & 63;
     const bool in = j < k;
+    double g[kSK];
+#pragma unroll
+    for (int i = 0; i < kSK; ++i) g[i] = (in && i < k) ? G[i * kSK + j] : 0.0;
+    double dj = in ? G[j * kSK + j] : 0.0;
     bool rem = in;
-    double d0 = in ? G[j * kSK + j] : 0.0;
+    double d0 = dj;
+#pragma unroll
     for (int o = 32; o > 0; o >>= 1) d0 = fmax(d0, __shfl_xor(d0, o, 64));
     for (int a = 0; a < k; ++a)
         if (in) R[a * kSK + j] = 0.0;
     int q = k;
-    for (int a = 0; a < k; ++a) {
-        double dv = rem ? G[j * kSK + j] : -1.0;
-        int pj = j;
-        if (!pivot) {
-            dv = (j == a) ? G[j * kSK + j] : -1.0;
-        }
-        for (int o = 32; o > 0; o >>= 1) {   // argmax, ties to the smaller index
-            const double ov = __shfl_xor(dv, o, 64);
-            const int op = __shfl_xor(pj, o, 64);
-            if (ov > dv || (ov == dv && op < pj)) {
-                dv = ov;
-                pj = op;
+    bool done = false;
+#pragma unroll
+    for (int a = 0; a < kSK; ++a) {
+        if (a < k && !done) {
+            double dv = pivot ? (rem ? dj : -1.0) : (j == a ? dj : -1.0);
+            int pj = j;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {   // argmax, ties to the smaller index
+                const double ov = __shfl_xor(dv, o, 64);
+                const int op = __shfl_xor(pj, o, 64);
+                if (ov > dv || (ov == dv && op < pj)) {
+                    dv = ov;
+                    pj = op;
+                }
+            }
+            const int p = __builtin_amdgcn_readfirstlane(pj);
+            dv = __shfl(dv, 0, 64);
+            if (!(dv > floor_rel * d0) || !(dv > 0.0)) {
+                q = a;
+                done = true;
+            } else {
+                const double lp = sqrt(dv);
+                if (j == p) rem = false;
+                double gp = 0.0;
+#pragma unroll
+                for (int i = 0; i < kSK; ++i)
+                    if (i == p) gp = g[i];
+                const double lj = in ? (j == p ? lp : (rem ? gp / lp : 0.0)) : 0.0;
+                if (in) R[a * kSK + j] = lj;
+                if (j == 0) perm[a] = p;
+                if (rem) {
+#pragma unroll
+                    for (int i = 0; i < kSK; ++i)
+                        if (i < k) g[i] -= lane_bcast(lj, i) * lj;
+                    dj -= lj * lj;
+                }
             }
         }
-        if (!(dv > floor_rel * d0) || !(dv > 0.0)) {
-            q = a;
-            break;
-        }
-        const int p = pj;
-        const double lp = sqrt(dv);
-        if (j == p) rem = false;
-        const double lj = in ? (j == p ? lp : (rem ? G[j * kSK + p] / lp : 0.0)) : 0.0;
-        if (in) R[a * kSK + j] = lj;
-        if (j == 0) perm[a] = p;
-        if (rem)
-            for (int i = 0; i < k; ++i) G[i * kSK + j] -= R[a * kSK + i] * lj;
     }
     if (j == 0) *q_out = q;
 }
 
-// one-sided Jacobi on the columns of M (rows x cols, column-major ld kSK) by one wavefront; Z
-// (cols x cols) accumulates the rotations; nrm[c] = norm of rotated column c on return
+// one-sided Jacobi on the columns of M (rows x cols, column-major ld kSK, LDS) by one wavefront,
+// in registers: column c is held by kLpc = 64 / kSK lanes, each with kSK / kLpc interleaved rows
+// of M and of the rotations Z. In each round of the round-robin order a lane fetches its partner
+// column's rows (one shuffle per row), the pair's dot products are reduced over the column's
+// lanes, and both columns of the pair apply the same rotation. On return M holds the rotated
+// columns, Z (cols x cols, LDS) the rotations and nrm[c] the norm of rotated column c.
+template <int kSK, class W>
 __device__ void wave_jacobi_lds(double* M, double* Z, double* nrm, int rows, int cols, double conv) {
+    constexpr int kLpc = 64 / kSK, kNr = kSK / kLpc;
     const int lane = threadIdx.x & 63;
-    for (int i = lane; i < cols * cols; i += 64) Z[(i % cols) + (i / cols) * kSK] = (i % cols == i / cols) ? 1.0 : 0.0;
+    const int c = lane / kLpc, sub = lane % kLpc;
+    W m[kNr], z[kNr];
+#pragma unroll
+    for (int u = 0; u < kNr; ++u) {
+        const int row = sub + u * kLpc;
+        m[u] = (c < cols && row < rows) ? (W)M[row + c * kSK] : W(0);
+        z[u] = (c < cols && row == c) ? W(1) : W(0);
+    }
     const int n2 = cols + (cols & 1);
-    const int npairs = n2 / 2;
-    int G = 64;
-    while (G > 1 && G * npairs > 64) G >>= 1;
-    const int pi = lane / G, gl = lane % G;
-    const int len = max(rows, cols);
     for (int sweep = 0; sweep < 30; ++sweep) {
         bool rotated = false;
         for (int round = 0; round < n2 - 1; ++round) {
-            int p = -1, q = -1;
-            if (pi < npairs) {
-                if (pi == 0) {
-                    p = round;
-                    q = n2 - 1;
-                } else {
-                    p = (round + pi) % (n2 - 1);
-                    q = (round - pi + n2 - 1) % (n2 - 1);
-                }
+            int partner;
+            if (c >= n2)
+                partner = c;
+            else if (c == n2 - 1)
+                partner = round;
+            else if (c == round)
+                partner = n2 - 1;
+            else
+                partner = (((2 * round - c) % (n2 - 1)) + (n2 - 1)) % (n2 - 1);
+            const bool valid = c < cols && partner < cols && partner != c;
+            const int src = (valid ? partner : c) * kLpc + sub;
+            W pm[kNr], pz[kNr];
+#pragma unroll
+            for (int u = 0; u < kNr; ++u) {
+                pm[u] = __shfl(m[u], src, 64);
+                pz[u] = __shfl(z[u], src, 64);
             }
-            const bool valid = p >= 0 && p < cols && q < cols;
-            double a = 0.0, b = 0.0, g = 0.0;
-            if (valid)
-                for (int i = gl; i < rows; i += G) {
-                    const double mp = M[i + p * kSK], mq = M[i + q * kSK];
-                    a += mp * mp;
-                    b += mq * mq;
-                    g += mp * mq;
-                }
-            for (int o = G / 2; o > 0; o >>= 1) {
+            W a = 0, b = 0, g = 0;
+#pragma unroll
+            for (int u = 0; u < kNr; ++u) {
+                a += m[u] * m[u];
+                b += pm[u] * pm[u];
+                g += m[u] * pm[u];
+            }
+#pragma unroll
+            for (int o = kLpc / 2; o > 0; o >>= 1) {
                 a += __shfl_xor(a, o, 64);
                 b += __shfl_xor(b, o, 64);
                 g += __shfl_xor(g, o, 64);
             }
-            if (valid && g != 0.0 && fabs(g) > conv * sqrt(a * b)) {
-                const double zeta = (b - a) / (2.0 * g);
-                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-                for (int i = gl; i < len; i += G) {
-                    if (i < rows) {
-                        const double mp = M[i + p * kSK], mq = M[i + q * kSK];
-                        M[i + p * kSK] = c * mp - sn * mq;
-                        M[i + q * kSK] = sn * mp + c * mq;
-                    }
-                    if (i < cols) {
-                        const double zp = Z[i + p * kSK], zq = Z[i + q * kSK];
-                        Z[i + p * kSK] = c * zp - sn * zq;
-                        Z[i + q * kSK] = sn * zp + c * zq;
-                    }
+            const bool lower = c < partner;
+            const W ap = lower ? a : b, aq = lower ? b : a;
+            if (valid && g != W(0) && fabs(g) > (W)conv * sqrt(ap * aq)) {
+                const W zeta = (aq - ap) / (W(2) * g);
+                const W t = (zeta >= W(0) ? W(1) : W(-1)) / (fabs(zeta) + sqrt(W(1) + zeta * zeta));
+                const W cs = W(1) / sqrt(W(1) + t * t), sn = cs * t;
+#pragma unroll
+                for (int u = 0; u < kNr; ++u) {
+                    m[u] = lower ? cs * m[u] - sn * pm[u] : sn * pm[u] + cs * m[u];
+                    z[u] = lower ? cs * z[u] - sn * pz[u] : sn * pz[u] + cs * z[u];
                 }
                 rotated = true;
             }
         }
         if (!__any(rotated)) break;
     }
-    for (int c = lane; c < cols; c += 64) {
-        double s = 0.0;
-        for (int i = 0; i < rows; ++i) s += M[i + c * kSK] * M[i + c * kSK];
-        nrm[c] = sqrt(s);
+    double nn = 0.0;
+#pragma unroll
+    for (int u = 0; u < kNr; ++u) {
+        const int row = sub + u * kLpc;
+        if (c < cols && row < rows) M[row + c * kSK] = (double)m[u];
+        if (c < cols && row < cols) Z[row + c * kSK] = (double)z[u];
+        nn += (double)m[u] * (double)m[u];
     }
+#pragma unroll
+    for (int o = kLpc / 2; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 64);
+    if (c < cols && sub == 0) nrm[c] = sqrt(nn);
 }
 
-template <class T>
-__device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const OpRec& o, Shared& sh, const LRBlockDev& L, int kc, int kx) {
-    LrsLds& S = sh.ls;
+template <class T, class SH>
+__device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const OpRec& o, SH& sh, const LRBlockDev& L, int kc, int kx) {
+    auto& S = sh.ls;
+    constexpr int kSK = SH::kSmall;
+    constexpr int kCH = decltype(sh.ls)::CH;
     T* U = d.arena + L.uoff;
     T* V = d.arena + L.voff;
     const int m = L.m, n = L.n, kp = kc + kx;
@@ -693,6 +763,14 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
     const Side<T> su{U, m, kc, Xp, o.v[0].rs, o.v[0].cs, -1.0, m};
     const Side<T> sv{V, n, kc, Yp, o.v[1].rs, o.v[1].cs, 1.0, n};
     const int rmax = max(m, n);
+    unsigned long long tph = (d.prof && threadIdx.x == 0) ? wall_clock64() : 0ull;
+    auto phase = [&](int k) {   // op profile: time of each phase (thread 0)
+        if (d.prof && threadIdx.x == 0) {
+            const unsigned long long t = wall_clock64();
+            atomicAdd(&d.prof[2 * kOpCodes + k], t - tph);
+            tph = t;
+        }
+    };
     // Gram matrices
     gram_clear(S);
     for (int c0 = 0; c0 < rmax; c0 += kCH) {
@@ -703,9 +781,11 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
     }
     gram_mirror(S, kp, kp);
     __syncthreads();
+    phase(0);
     const double floor_rel = f64 ? 1e-14 : 1e-12;
-    if (wave < 2) wave_cholesky(S.G[wave], S.R[wave], S.perm[wave], &S.q[wave], kp, true, floor_rel);
+    if (wave < 2) wave_cholesky<kSK>(S.G[wave], S.R[wave], S.perm[wave], &S.q[wave], kp, true, floor_rel);
     __syncthreads();
+    phase(1);
     if (f64) {
         // second pass: rows of Q1 = (A P)[:, :q] R11^{-1} (forward substitution per row), their
         // Gram G2 = R2^T R2 and R <- R2 R
@@ -743,7 +823,7 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
         __syncthreads();
         if (wave < 2) {
             // G2 (q x q) = L2 L2^T without pivoting, in A[wave] as scratch for R2 (row a, col b)
-            wave_cholesky(S.G[wave], S.A[wave], S.perm2[wave], &S.q2[wave], S.q[wave], false, 1e-30);
+            wave_cholesky<kSK>(S.G[wave], S.A[wave], S.perm2[wave], &S.q2[wave], S.q[wave], false, 1e-30);
         }
         __syncthreads();
         // R <- R2 R (rows a < q2): R'[a][j] = sum_{b >= a} R2[a][b] R[b][j]; R2 row a in A[s][a*kSK + b]
@@ -762,6 +842,7 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
         if (threadIdx.x < 2) S.q[threadIdx.x] = S.q2[threadIdx.x];
         __syncthreads();
     }
+    phase(2);
     const int qu = S.q[0], qv = S.q[1];
     // core M = (R_u P_u^T)(R_v P_v^T)^T (qu x qv, column-major ld kSK) in G[0]; Z in G[1]
     for (int idx = threadIdx.x; idx < qu * qv; idx += kT) {
@@ -771,8 +852,11 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
         S.G[0][a + b * kSK] = v;
     }
     __syncthreads();
-    if (wave == 0 && qu > 0 && qv > 0) wave_jacobi_lds(S.G[0], S.G[1], S.sig, qu, qv, f64 ? 1e-15 : 1e-9);
+    // the SVD of the small core runs in the factor precision (the Gram matrices and their
+    // Cholesky factors stay FP64)
+    if (wave == 0 && qu > 0 && qv > 0) wave_jacobi_lds<kSK, T>(S.G[0], S.G[1], S.sig, qu, qv, f64 ? 1e-15 : 1e-7);
     __syncthreads();
+    phase(3);
     for (int j = threadIdx.x; j < qv; j += kT) {
         int rank = 0;
         const double sj = S.sig[j];
@@ -797,7 +881,7 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
     const int r = sh.r;
     // C_u (kp x r) = P_u R11_u^{-1} (M Z)_order and C_v = P_v R11_v^{-1} Z_order, by back
     // substitution, one lane per (side, output column); into A[side] (row l, column c)
-    for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) (&S.A[0][0])[idx] = 0.0;
+    for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) S.A[idx / (kSK * kSK)][idx % (kSK * kSK)] = 0.0;
     __syncthreads();
     if (threadIdx.x < 2 * r) {
         const int s = threadIdx.x / r, c = threadIdx.x % r, jc = sh.order[c];
@@ -813,8 +897,12 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
     }
     __syncthreads();
     // move C_u, C_v to G (M and Z are no longer needed) so that A can stage rows again
-    for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) (&S.G[0][0])[idx] = (&S.A[0][0])[idx];
+    for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) {
+        const int sd = idx / (kSK * kSK), e = idx % (kSK * kSK);
+        S.G[sd][e] = S.A[sd][e];
+    }
     __syncthreads();
+    phase(4);
     // U_C <- A_u C_u, V_C <- A_v C_v, chunk by chunk (a chunk is staged before its rows are written)
     for (int c0 = 0; c0 < rmax; c0 += kCH) {
         stage_rows(su, sv, c0, kp, S);
@@ -830,18 +918,27 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
         __syncthreads();
     }
     if (threadIdx.x == 0) d.ranks[L.slot] = r;
+    phase(5);
 }
 
-template <class T>
-__device__ __attribute__((noinline)) void op_lrsub(const Inst<T>& d, const OpRec& o, Shared& sh) {
+template <class T, class SH>
+__device__ __attribute__((noinline)) void op_lrsub(const Inst<T>& d, const OpRec& o, SH& sh) {
     const int kx = dimval(d, o.dim[2]);
     if (threadIdx.x == 0) sh.lrsub_flops = 0.0;
     if (kx <= 0) return;
     const LRBlockDev L = d.lr[o.blk];
-    if (d.ranks[L.slot] + kx <= kSK) {
+    if (d.ranks[L.slot] + kx <= SH::kSmall) {
         op_lrsub_small(d, o, sh, L, d.ranks[L.slot], kx);
         return;
     }
+    if constexpr (!SH::kGeneral) {
+        // the host picks this variant only for programs whose widths fit the small path
+        if (threadIdx.x == 0) {
+            d.status[0] = FDE_EDEVICE;
+            d.status[1] = -1;
+        }
+        return;
+    } else {
     T* U = d.arena + L.uoff;
     T* V = d.arena + L.voff;
     const int m = L.m, n = L.n, kc = d.ranks[L.slot], kp = kc + kx;
@@ -921,6 +1018,7 @@ __device__ __attribute__((noinline)) void op_lrsub(const Inst<T>& d, const OpRec
         V[j + (int64_t)c * n] = (T)s;
     }
     __syncthreads();
+    }
 }
 
 // floating-point operations of one op at its actual dimensions (evaluated before the op runs;
@@ -943,8 +1041,8 @@ __device__ double op_flops(const Inst<T>& d, const OpRec& o) {
 }
 
 // one op; false when a leaf pivot broke down (the status is set)
-template <class T>
-__device__ bool run_op(const Inst<T>& d, int pc, Shared& sh, int step) {
+template <class T, class SH>
+__device__ bool run_op(const Inst<T>& d, int pc, SH& sh, int step) {
     const OpRec o = d.ops[pc];
     unsigned long long t0 = 0;
     if (d.prof && threadIdx.x == 0) t0 = wall_clock64();
@@ -1016,29 +1114,29 @@ __device__ bool run_op(const Inst<T>& d, int pc, Shared& sh, int step) {
     return true;
 }
 
-template <class T>
-__device__ void run_program(const Inst<T>& d, Shared& sh, int step) {
+template <class T, class SH>
+__device__ void run_program(const Inst<T>& d, SH& sh, int step) {
     for (int pc = 0; pc < d.nops; ++pc)
         if (!run_op(d, pc, sh, step)) return;
 }
 
-template <class T>
+template <class T, int KS, bool GENERAL>
 __global__ void __launch_bounds__(kT) k_interp(const Inst<T>* __restrict__ insts, int step) {
-    __shared__ Shared sh;
+    __shared__ Shared<T, KS, GENERAL> sh;
     const Inst<T> d = insts[blockIdx.x];
     run_program(d, sh, step);
 }
 
 template <class T>
 __global__ void __launch_bounds__(kT) k_interp_one(const Inst<T> d) {
-    __shared__ Shared sh;
+    __shared__ Shared<T, 32, true> sh;
     run_program(d, sh, 0);
 }
 
 // one level: the ops of a level are independent, earlier levels have completed (kernel order)
-template <class T>
+template <class T, int KS, bool GENERAL>
 __global__ void __launch_bounds__(kT) k_level(const Inst<T>* __restrict__ insts, const int2* __restrict__ tasks) {
-    __shared__ Shared sh;
+    __shared__ Shared<T, KS, GENERAL> sh;
     const int2 tk = tasks[blockIdx.x];
     const Inst<T> d = insts[tk.x];
     // after a breakdown in an earlier level the rest of that factorisation is skipped; the
@@ -1065,17 +1163,28 @@ void print_op_profile(const char* what, const unsigned long long* p, int device)
     for (int c = 1; c < kOpCodes; ++c)
         if (p[2 * c + 1]) fprintf(stderr, " %s %llu x %.3f ms = %.2f ms;", names[c], p[2 * c + 1],
                                   p[2 * c] * ms_per_tick / p[2 * c + 1], p[2 * c] * ms_per_tick);
+    static const char* phases[kProfPhases] = {"gram", "cholesky", "second pass", "core svd", "factors", "products"};
+    const unsigned long long nl = p[2 * OP_LRSUB + 1];
+    if (nl && p[2 * kOpCodes + 1]) {
+        fprintf(stderr, "\n[fde ops]   small recompression phases (ms per op):");
+        for (int k = 0; k < kProfPhases; ++k) fprintf(stderr, " %s %.4f;", phases[k], p[2 * kOpCodes + k] * ms_per_tick / nl);
+    }
     fprintf(stderr, "\n");
 }
 
 template <class T>
-void launch_interp(hipStream_t st, int ninst, const Inst<T>* d_insts, int step) {
+void launch_interp(hipStream_t st, int ninst, const Inst<T>* d_insts, int step, int variant) {
     if (ninst <= 0) return;
-    hipLaunchKernelGGL((k_interp<T>), dim3(ninst), dim3(kT), 0, st, d_insts, step);
+    if (variant == 16)
+        hipLaunchKernelGGL((k_interp<T, 16, false>), dim3(ninst), dim3(kT), 0, st, d_insts, step);
+    else if (variant == 32)
+        hipLaunchKernelGGL((k_interp<T, 32, false>), dim3(ninst), dim3(kT), 0, st, d_insts, step);
+    else
+        hipLaunchKernelGGL((k_interp<T, 32, true>), dim3(ninst), dim3(kT), 0, st, d_insts, step);
     FDE_LAUNCH_CHECK();
 }
-template void launch_interp<float>(hipStream_t, int, const Inst<float>*, int);
-template void launch_interp<double>(hipStream_t, int, const Inst<double>*, int);
+template void launch_interp<float>(hipStream_t, int, const Inst<float>*, int, int);
+template void launch_interp<double>(hipStream_t, int, const Inst<double>*, int, int);
 
 template <class T>
 void launch_interp_one(hipStream_t st, const Inst<T>& d) {
@@ -1086,12 +1195,17 @@ template void launch_interp_one<float>(hipStream_t, const Inst<float>&);
 template void launch_interp_one<double>(hipStream_t, const Inst<double>&);
 
 template <class T>
-void launch_level(hipStream_t st, int ntasks, const Inst<T>* d_insts, const int2* d_tasks) {
+void launch_level(hipStream_t st, int ntasks, const Inst<T>* d_insts, const int2* d_tasks, int variant) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL((k_level<T>), dim3(ntasks), dim3(kT), 0, st, d_insts, d_tasks);
+    if (variant == 16)
+        hipLaunchKernelGGL((k_level<T, 16, false>), dim3(ntasks), dim3(kT), 0, st, d_insts, d_tasks);
+    else if (variant == 32)
+        hipLaunchKernelGGL((k_level<T, 32, false>), dim3(ntasks), dim3(kT), 0, st, d_insts, d_tasks);
+    else
+        hipLaunchKernelGGL((k_level<T, 32, true>), dim3(ntasks), dim3(kT), 0, st, d_insts, d_tasks);
     FDE_LAUNCH_CHECK();
 }
-template void launch_level<float>(hipStream_t, int, const Inst<float>*, const int2*);
-template void launch_level<double>(hipStream_t, int, const Inst<double>*, const int2*);
+template void launch_level<float>(hipStream_t, int, const Inst<float>*, const int2*, int);
+template void launch_level<double>(hipStream_t, int, const Inst<double>*, const int2*, int);
 
 }  // namespace fde

@@ -22,9 +22,11 @@ struct Plan {
     Program lu, sv;
     int kpmax = 0;
     bool sv_lds = false;   // every H-solve op works on all right-hand-side columns (LDS kernel usable)
+    int lu_variant = 0;    // H-LU kernel variant: widest possible recompression 16, 32, or 0 (wider)
     DevBuf<OpRec> ops_lu, ops_sv;
     DevBuf<LRBlockDev> lr;
     DevBuf<int> h2p;
+    std::vector<int> lr_rows;   // larger dimension of each low-rank block (diagnostics)
 };
 
 // the plan for a factorisation with rank capacity kmax of an H-matrix (cached per context)

@@ -162,6 +162,12 @@ void factor_batch_run(Ctx* c, std::vector<HLUObj*>& fs, const char* what) {
     DevBuf<Inst<T>> d_ins;
     upload_vec(c, d_ins, ins);
     const bool serial = serial_requested();
+    int variant = 16;
+    for (HLUObj* f : fs) {
+        const int v = f->plan->lu_variant;
+        if (v == 0 || variant == 0) variant = 0;
+        else variant = std::max(variant, v);
+    }
     std::vector<int2> tasks;
     std::vector<int> loff(1, 0);
     if (!serial) {
@@ -183,14 +189,67 @@ void factor_batch_run(Ctx* c, std::vector<HLUObj*>& fs, const char* what) {
     DevBuf<int2> d_tasks;
     upload_vec(c, d_tasks, tasks);
     EventPair ev;
+    const char* pl = getenv("FDE_PROFILE_LEVELS");
+    const bool prof_levels = pl && pl[0] == '1' && !serial;
+    std::vector<hipEvent_t> lev_ev;
+    if (prof_levels) {
+        lev_ev.resize(loff.size());
+        for (auto& e : lev_ev) FDE_HIP(hipEventCreate(&e));
+    }
     FDE_HIP(hipEventRecord(ev.a, c->stream));
     if (serial) {
-        launch_interp<T>(c->stream, (int)ins.size(), d_ins.p, 0);
+        launch_interp<T>(c->stream, (int)ins.size(), d_ins.p, 0, variant);
     } else {
-        for (size_t l = 0; l + 1 < loff.size(); ++l)
-            launch_level<T>(c->stream, loff[l + 1] - loff[l], d_ins.p, d_tasks.p + loff[l]);
+        for (size_t l = 0; l + 1 < loff.size(); ++l) {
+            if (prof_levels) FDE_HIP(hipEventRecord(lev_ev[l], c->stream));
+            launch_level<T>(c->stream, loff[l + 1] - loff[l], d_ins.p, d_tasks.p + loff[l], variant);
+        }
+        if (prof_levels) FDE_HIP(hipEventRecord(lev_ev.back(), c->stream));
     }
     FDE_HIP(hipEventRecord(ev.b, c->stream));
+    if (prof_levels) {
+        // per level: time, tasks and the op mix of the first factorisation; the slowest levels
+        FDE_HIP(hipEventSynchronize(lev_ev.back()));
+        struct Row {
+            float ms;
+            size_t l;
+        };
+        std::vector<Row> rows;
+        float tot = 0.f;
+        for (size_t l = 0; l + 1 < loff.size(); ++l) {
+            float ms = 0.f;
+            FDE_HIP(hipEventElapsedTime(&ms, lev_ev[l], lev_ev[l + 1]));
+            rows.push_back({ms, l});
+            tot += ms;
+        }
+        std::sort(rows.begin(), rows.end(), [](const Row& a, const Row& b) { return a.ms > b.ms; });
+        const auto& lo = fs[0]->plan->lu.level_off;
+        fprintf(stderr, "[fde levels] %zu levels, %.3f ms; slowest:\n", rows.size(), tot);
+        for (size_t r = 0; r < std::min<size_t>(rows.size(), 12); ++r) {
+            const size_t l = rows[r].l;
+            int cnt[kOpCodes] = {0};
+            int maxm = 0;
+            if (l + 1 < lo.size())
+                for (int pc = lo[l]; pc < lo[l + 1]; ++pc) {
+                    const OpRec& o = fs[0]->plan->lu.ops[pc];
+                    cnt[o.code]++;
+                    if (o.code == OP_LRSUB) maxm = std::max(maxm, fs[0]->plan->lr_rows[o.blk]);
+                }
+            fprintf(stderr, "  level %zu: %.3f ms, %d tasks; getrf %d trsm %d gemm %d lrsub %d (largest %d rows) zero %d\n",
+                    l, rows[r].ms, loff[l + 1] - loff[l], cnt[OP_GETRF], cnt[OP_TRSM], cnt[OP_GEMM], cnt[OP_LRSUB],
+                    maxm, cnt[OP_ZERO]);
+        }
+        float bucket[4] = {0, 0, 0, 0};
+        int bn[4] = {0, 0, 0, 0};
+        for (const Row& r : rows) {
+            const int b = r.ms < 0.05f ? 0 : r.ms < 0.2f ? 1 : r.ms < 1.f ? 2 : 3;
+            bucket[b] += r.ms;
+            bn[b]++;
+        }
+        fprintf(stderr, "  levels <50us: %d (%.2f ms), <200us: %d (%.2f ms), <1ms: %d (%.2f ms), >=1ms: %d (%.2f ms)\n",
+                bn[0], bucket[0], bn[1], bucket[1], bn[2], bucket[2], bn[3], bucket[3]);
+        for (auto& e : lev_ev) (void)hipEventDestroy(e);
+    }
     std::vector<int> st(2 * fs.size());
     for (size_t i = 0; i < fs.size(); ++i)
         FDE_HIP(hipMemcpyAsync(&st[2 * i], fs[i]->status.p, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -294,6 +353,10 @@ void make_plan_host(const HTree& hmt, int kmax, Plan& p, bool check) {
     for (const OpRec& o : p.sv.ops)
         if ((o.code == OP_GEMM || o.code == OP_TRSM || o.code == OP_LRMV) && o.dim[1] != -1) p.sv_lds = false;
     p.kpmax = lrsub_kprime_max(p.t, p.lu);
+    int widest = 0;
+    for (const OpRec& o : p.lu.ops)
+        if (o.code == OP_LRSUB) widest = std::max(widest, p.t.kmax + (o.dim[2] >= 0 ? o.dim[2] : p.t.kmax));
+    p.lu_variant = widest <= 16 ? 16 : widest <= 32 ? 32 : 0;
     if (p.kpmax > kMaxKp) fail(FDE_EUNSUPPORTED, "H-LU needs recompression of width %d > %d", p.kpmax, kMaxKp);
     validate_program(p.t, p.lu, p.t.arena_elems, p.lu.work_elems, 1, false);
     validate_program(p.t, p.sv, p.t.arena_elems, p.sv.work_elems, 1, true);
@@ -321,6 +384,7 @@ std::shared_ptr<const Plan> get_plan(Ctx* c, const HTree& hmt, int kmax) {
         lrt.push_back(LRBlockDev{B.uoff, B.voff, p->t.cl[B.tau].size(), p->t.cl[B.sigma].size(), B.slot, 0});
     }
     upload_vec(c, p->lr, lrt);
+    for (const LRBlockDev& b : lrt) p->lr_rows.push_back(std::max(b.m, b.n));
     FDE_HIP(hipStreamSynchronize(c->stream));   // host copies of the tables may move later
     p->t.op = nullptr;
     c->plans.insert(c->plans.begin(), {key, p});

@@ -166,6 +166,18 @@ class Operator(_Handle):
         check(load().fde_load_vector(self.h, _np_dptr(fv), float(c1), float(c2), _dptr(G)))
         return G
 
+    def load_vector_powers(self, coef, expo, side, c1: float = 0.0, c2: float = 0.0) -> torch.Tensor:
+        """G for f = sum_k coef_k d_k^expo_k (d = x - a for side 0, b - x for side 1), f on the device."""
+        c = np.ascontiguousarray(coef, dtype=np.float64)
+        e = np.ascontiguousarray(expo, dtype=np.float64)
+        sd = np.ascontiguousarray(side, dtype=np.int32)
+        if not (len(c) == len(e) == len(sd)):
+            raise ValueError("coef, expo and side must have the same length")
+        G = torch.empty(self.Nd, dtype=torch.float64, device=self.ctx.device)
+        check(load().fde_load_vector_powers(self.h, len(c), _np_dptr(c), _np_dptr(e), sd.ctypes.data_as(A.ip),
+                                            float(c1), float(c2), _dptr(G)))
+        return G
+
     def apply(self, X: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         X2 = _as_block(X, self.Nd, self.ctx.device)
         Y = torch.empty_like(X2) if out is None else _as_block(out, self.Nd, self.ctx.device)

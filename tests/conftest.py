@@ -13,12 +13,15 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: CPU test that takes more than ~20 s")
 
 
-@pytest.hookimpl(trylast=True)
 def pytest_sessionfinish(session, exitstatus):
-    """End the process with pytest's status once results are reported when the GPU was used:
+    session.config._fde_exitstatus = int(exitstatus)
+
+
+@pytest.hookimpl(trylast=True)
+def pytest_unconfigure(config):
+    """After the report is printed, end the process with pytest's status when the GPU was used:
     native HIP/torch teardown at interpreter exit can crash after every test has finished,
     which would replace the real status with a signal."""
-    import sys
     if "torch" in sys.modules and "paper_1808_02937_amd" in sys.modules:
         try:
             import torch
@@ -26,7 +29,6 @@ def pytest_sessionfinish(session, exitstatus):
                 torch.cuda.synchronize()
                 sys.stdout.flush()
                 sys.stderr.flush()
-                import os
-                os._exit(int(exitstatus))
+                os._exit(getattr(config, "_fde_exitstatus", 0))
         except Exception:
             pass
