@@ -29,6 +29,10 @@ struct Inst {
     int nrhs;
     int nslots;               // low-rank blocks (rank slots)
     int work_rows;            // H-solve temporaries, rows (times the number of right-hand sides)
+    const HsStep* hs_steps;   // leaf-step H-solve: 2 * hs_nleaf steps, their items and t computations
+    const HsItem* hs_items;
+    const HsTcomp* hs_tc;
+    int hs_nleaf, hs_tslots;
     double tol;
     int kmax;
     double pivot_floor;
@@ -54,8 +58,9 @@ void launch_hsolve(hipStream_t st, int ninst, int nchunk, int wc, const Inst<T>*
                    size_t lds_bytes);
 template <class T>
 void launch_hsolve_one(hipStream_t st, const Inst<T>& d, int nchunk, int wc, size_t lds_bytes);
-// LDS bytes of one workgroup of the LDS H-solve for wc columns
-size_t hsolve_lds_bytes(int Nd, int work_rows, int nslots, int wc, size_t esz);
+// LDS bytes of one workgroup of the leaf-step H-solve for wc columns
+size_t hsolve_lds_bytes(int Nd, int tslots, int kmax, int nslots, int wc, size_t esz);
+constexpr int kHsolveMaxRow = 64;   // leaf-step H-solve: leaves of at most this many rows
 constexpr int kHsolveMaxCols = 8;
 // largest dynamic LDS of one workgroup on the device (bytes)
 size_t device_lds_limit(int device);

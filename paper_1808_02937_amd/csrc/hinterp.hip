@@ -1163,11 +1163,17 @@ void print_op_profile(const char* what, const unsigned long long* p, int device)
     for (int c = 1; c < kOpCodes; ++c)
         if (p[2 * c + 1]) fprintf(stderr, " %s %llu x %.3f ms = %.2f ms;", names[c], p[2 * c + 1],
                                   p[2 * c] * ms_per_tick / p[2 * c + 1], p[2 * c] * ms_per_tick);
-    static const char* phases[kProfPhases] = {"gram", "cholesky", "second pass", "core svd", "factors", "products"};
+    static const char* phases[kProfPhases] = {"gram", "cholesky", "second pass", "core svd", "factors", "products",
+                                              "gather", "solve", "t"};
     const unsigned long long nl = p[2 * OP_LRSUB + 1];
     if (nl && p[2 * kOpCodes + 1]) {
         fprintf(stderr, "\n[fde ops]   small recompression phases (ms per op):");
-        for (int k = 0; k < kProfPhases; ++k) fprintf(stderr, " %s %.4f;", phases[k], p[2 * kOpCodes + k] * ms_per_tick / nl);
+        for (int k = 0; k < 6; ++k) fprintf(stderr, " %s %.4f;", phases[k], p[2 * kOpCodes + k] * ms_per_tick / nl);
+    }
+    const unsigned long long ns = p[2 * OP_TRSM + 1];
+    if (p[2 * kOpCodes + 6] && ns) {
+        fprintf(stderr, "\n[fde ops]   leaf-step H-solve phases (ms per step):");
+        for (int k = 6; k < 9; ++k) fprintf(stderr, " %s %.4f;", phases[k], p[2 * kOpCodes + k] * ms_per_tick / ns);
     }
     fprintf(stderr, "\n");
 }

@@ -26,6 +26,10 @@ struct Plan {
     DevBuf<OpRec> ops_lu, ops_sv;
     DevBuf<LRBlockDev> lr;
     DevBuf<int> h2p;
+    HsTables hs;            // leaf-step H-solve
+    DevBuf<HsStep> d_hs_steps;
+    DevBuf<HsItem> d_hs_items;
+    DevBuf<HsTcomp> d_hs_tc;
     std::vector<int> lr_rows;   // larger dimension of each low-rank block (diagnostics)
 };
 
@@ -73,6 +77,11 @@ struct HLUObj {
         d.nrhs = nrhs;
         d.nslots = plan->t.nslots;
         d.work_rows = (int)plan->sv.work_elems;
+        d.hs_steps = plan->d_hs_steps.p;
+        d.hs_items = plan->d_hs_items.p;
+        d.hs_tc = plan->d_hs_tc.p;
+        d.hs_nleaf = plan->hs.nleaf;
+        d.hs_tslots = plan->hs.tslots;
         d.tol = tol;
         d.kmax = kmax;
         d.pivot_floor = pivot_floor;

@@ -349,9 +349,9 @@ void make_plan_host(const HTree& hmt, int kmax, Plan& p, bool check) {
     schedule_levels(p.t, p.lu);
     if (check) check_schedule(p.t, original, p.lu);
     gen_hsolve(p.t, p.sv);
-    p.sv_lds = true;
-    for (const OpRec& o : p.sv.ops)
-        if ((o.code == OP_GEMM || o.code == OP_TRSM || o.code == OP_LRMV) && o.dim[1] != -1) p.sv_lds = false;
+    gen_hsolve_steps(p.t, p.hs);
+    validate_hsolve_steps(p.t, p.hs);
+    p.sv_lds = p.hs.maxrow <= kHsolveMaxRow;
     p.kpmax = lrsub_kprime_max(p.t, p.lu);
     int widest = 0;
     for (const OpRec& o : p.lu.ops)
@@ -384,6 +384,9 @@ std::shared_ptr<const Plan> get_plan(Ctx* c, const HTree& hmt, int kmax) {
         lrt.push_back(LRBlockDev{B.uoff, B.voff, p->t.cl[B.tau].size(), p->t.cl[B.sigma].size(), B.slot, 0});
     }
     upload_vec(c, p->lr, lrt);
+    upload_vec(c, p->d_hs_steps, p->hs.steps);
+    upload_vec(c, p->d_hs_items, p->hs.items);
+    upload_vec(c, p->d_hs_tc, p->hs.tcomp);
     for (const LRBlockDev& b : lrt) p->lr_rows.push_back(std::max(b.m, b.n));
     FDE_HIP(hipStreamSynchronize(c->stream));   // host copies of the tables may move later
     p->t.op = nullptr;
@@ -407,7 +410,7 @@ int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes) {
     if (!c->lds_limit) c->lds_limit = device_lds_limit(c->device);
     const Plan& P = *f->plan;
     int wc = std::min(nrhs, kHsolveMaxCols);
-    auto need = [&](int w) { return hsolve_lds_bytes(f->op->Nd, (int)P.sv.work_elems, P.t.nslots, w, f->esz); };
+    auto need = [&](int w) { return hsolve_lds_bytes(f->op->Nd, P.hs.tslots, f->kmax, P.t.nslots, w, f->esz); };
     while (wc > 1 && need(wc) > c->lds_limit) --wc;
     if (need(wc) > c->lds_limit) return 0;
     *lds_bytes = need(wc);

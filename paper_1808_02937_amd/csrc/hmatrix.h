@@ -54,7 +54,7 @@ constexpr int kMaxKprime = 256;   // widest [U, X] recompressed in one OP_LRSUB
 // OP_LRMV (H-substitutions): Y += alpha U (V^T X) for low-rank block blk, through temporary v[2]
 enum OpCode { OP_GETRF = 1, OP_TRSM = 2, OP_GEMM = 3, OP_LRSUB = 4, OP_ZERO = 5, OP_LOAD = 6, OP_STORE = 7, OP_LRMV = 8 };
 constexpr int kOpCodes = 9;
-constexpr int kProfPhases = 6;             // small recompression phases
+constexpr int kProfPhases = 9;             // small recompression phases, then H-solve step phases
 constexpr int kProfSlots = 2 * kOpCodes + kProfPhases;   // per op code: wall-clock ticks, count; phases
 enum Base { B_ARENA = 0, B_WORK = 1, B_RHS = 2, B_WORK_NRHS = 3 };
 
@@ -96,6 +96,44 @@ struct Program {
     int64_t scr_t = 0, scr_d = 0;    // recompression scratch of one level (factor type, doubles)
 };
 
+// --------------------------------------------------------------- leaf-step H-solve
+// The forward (L, unit lower) and backward (U) H-substitutions as 2 x (number of leaves)
+// steps. Step of leaf i: x_i <- T_ii^{-1} (x_i - sum of the contributions of solved leaves),
+// the contributions being chunks of <= kHsChunk columns of dense off-diagonal leaf blocks
+// (times solved entries of x) and rows of low-rank factors U_B (times t_B = V_B^T x_sigma,
+// computed once the column cluster sigma of B is solved).
+constexpr int kHsChunk = 8;
+
+struct HsItem {        // one contribution to the rows of a leaf
+    int64_t off;       // dense: first column of the chunk; low rank: U_B + first row of the leaf
+    int ld;            // leading dimension (dense: leaf rows; low rank: |tau|)
+    int col0;          // dense: x index of the chunk's first column
+    int ncol;          // dense: columns in the chunk (<= kHsChunk); low rank: 0
+    int slot;          // low rank: rank slot
+    int tslot;         // low rank: t buffer slot
+};
+
+struct HsTcomp {       // t_B = V_B^T x_sigma once sigma is solved
+    int64_t voff;
+    int ld;            // |sigma|
+    int col0;          // sigma's first internal index
+    int slot, tslot;
+};
+
+struct HsStep {
+    int64_t diag;      // dense diagonal leaf (packed L\U), ld = nrow
+    int row0, nrow;
+    int it0, it1;      // items [it0, it1)
+    int tc0, tc1;      // t computations [tc0, tc1) after the leaf is solved
+};
+
+struct HsTables {
+    std::vector<HsStep> steps;   // forward (leaf order), then backward (reverse leaf order)
+    std::vector<HsItem> items;
+    std::vector<HsTcomp> tcomp;
+    int nleaf = 0, tslots = 0, maxrow = 0;
+};
+
 // --------------------------------------------------------------- H-matrix
 // host-side trees and storage layout (copyable: each factorisation lays out its own copy)
 struct HTree {
@@ -121,6 +159,10 @@ struct HMat {
     DevBuf<double> d_arena;
     DevBuf<int> d_h2p;
 };
+
+void gen_hsolve_steps(const HTree& hm, HsTables& tab);
+// every table entry inside the factor storage and the vector, before the tables reach the device
+void validate_hsolve_steps(const HTree& hm, const HsTables& tab);
 
 void build_trees(HTree* hm);
 void assign_storage(HTree* hm, int kmax);

@@ -1,14 +1,20 @@
-// Forward and backward H-substitution (Section 4.1) with the right-hand sides
-// resident in LDS.
+// Forward and backward H-substitution (Section 4.1) by leaf steps, with the
+// right-hand sides resident in LDS.
 //
-// The H-solve program is a chain of small ops -- triangular solves with the
-// dense diagonal leaves and products with dense or low-rank off-diagonal
-// blocks -- most of which depend on the previous one through the solution
-// vector. One workgroup runs the whole chain for a chunk of right-hand-side
-// columns: the chunk (Nd x wc), the temporaries and the current ranks sit in
-// LDS for the whole solve, so every op reads only its factor block from HBM
-// (coalesced along the stored dimension) and the vector entries from LDS. The
-// next op record is fetched while the current op runs.
+// One workgroup (512 threads) solves a chunk of wc right-hand-side columns of
+// one instance. The chunk (Nd x wc), the short vectors t_B = V_B^T x_sigma of
+// the low-rank blocks in flight and the ranks stay in LDS for the whole solve;
+// only factor blocks are read from HBM. The step of leaf i (host tables, see
+// gen_hsolve_steps):
+//   A. the eight wavefronts split the contributions to the leaf's rows (chunks
+//      of dense off-diagonal blocks times solved entries, rows of U_B times t_B)
+//      and leave partial sums in LDS; the wavefronts that will solve also load
+//      their row of the diagonal leaf meanwhile;
+//   B. wavefront j sums the partials of column j and solves with the diagonal
+//      leaf in registers (row-scaled unit triangular substitution, readlane);
+//   C. for every low-rank block whose column cluster is now solved, each
+//      wavefront forms one entry of t_B = V_B^T x_sigma (a coalesced dot
+//      product reduced by shuffles).
 #include "hinterp.h"
 #include "tri_wave.h"
 
@@ -20,265 +26,240 @@ constexpr int kHT = 512;
 constexpr int kHW = kHT / 64;
 
 template <class T>
-struct Lds {
-    T* X;      // Nd x wc, ld Nd
-    T* W;      // temporaries: offset off * wc, ld rows
-    T* red;    // kHT * wc partial sums
-    int* rk;   // ranks
-    int wc;
-};
-
-template <class T>
-__device__ inline T* lptr(const Lds<T>& L, const View& v) {
-    return v.base == B_RHS ? L.X + v.off : L.W + v.off * L.wc;
-}
-
-template <class T>
-__device__ inline int hdim(const Lds<T>& L, int code) {
-    return code >= 0 ? code : (code == -1 ? L.wc : L.rk[-2 - code]);
-}
-
-template <class T>
-__device__ inline T group_sum(T v, int G) {
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+__device__ inline T wave_sum_t(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-// C (LDS) = beta C + alpha A (HBM factor) B (LDS)
+// one contribution item with its factor values (a chunk of a dense block or kHsChunk columns of
+// U_B rows; a low-rank item of rank above kHsChunk takes the rest synchronously)
+// items per wavefront and step whose values are prefetched (register budget)
 template <class T>
-__device__ void hs_gemm(const Inst<T>& d, const Lds<T>& L, const OpRec& o) {
-    const int m = hdim(L, o.dim[0]), n = hdim(L, o.dim[1]), k = hdim(L, o.dim[2]);
-    if (m <= 0 || n <= 0) return;
-    T* C = lptr(L, o.v[0]);
-    const T* B = lptr(L, o.v[2]);
-    const T* A = d.arena + o.v[1].off;
-    const int ars = o.v[1].rs, acs = o.v[1].cs, brs = o.v[2].rs, bcs = o.v[2].cs;
-    const int crs = o.v[0].rs, ccs = o.v[0].cs;
-    const T alpha = (T)o.alpha, beta = (T)o.beta;
-    const int t = threadIdx.x;
-    auto put = [&](int i, int j, T s) {
-        T* c = C + (int64_t)i * crs + (int64_t)j * ccs;
-        *c = (beta == T(0) ? T(0) : beta * *c) + alpha * s;
-    };
-    if (k <= 0) {
-        for (int idx = t; idx < m * n; idx += kHT) put(idx % m, idx / m, T(0));
-        return;
+struct kIpwOf {
+    static constexpr int value = 2;
+};
+struct ItemRef {
+    int64_t off;
+    int ld, col0, ncol, slot, tslot;
+    bool live;
+};
+
+__device__ inline ItemRef load_item(const HsItem* items, int it, int it1) {
+    ItemRef r{};
+    r.live = it < it1;
+    if (r.live) {
+        const HsItem m = items[it];
+        r.off = m.off;
+        r.ld = m.ld;
+        r.col0 = m.col0;
+        r.ncol = m.ncol;
+        r.slot = m.slot;
+        r.tslot = m.tslot;
     }
-    if (acs == 1 && ars != 1) {
-        // A stored transposed (a factor read as V^T or U^T): G lanes per output, consecutive lanes
-        // along the contiguous dimension k, reduced by shuffles
-        int G = 64;
-        while (G > 1 && G * m * n > kHT) G >>= 1;
-        const int ng = kHT / G, gid = t / G, gl = t % G;
-        for (int idx = gid; idx < m * n; idx += ng) {
-            const int i = idx % m, j = idx / m;
-            const T* a = A + (int64_t)i * ars;
-            const T* b = B + (int64_t)j * bcs;
-            T s = 0;
-            for (int l = gl; l < k; l += G) s += a[l] * b[(int64_t)l * brs];
-            s = group_sum(s, G);
-            if (gl == 0) put(i, j, s);
-        }
-        return;
+    return r;
+}
+
+template <class T>
+__device__ void hsteps_body(const Inst<T>& d, int c0, int wc, int step, char* smem) {
+    const int Nd = d.Nd, L = d.hs_nleaf, kmax = d.kmax;
+    wc = min(wc, d.nrhs - c0);
+    if (wc <= 0) return;
+    T* X = reinterpret_cast<T*>(smem);                 // Nd x wc, ld Nd
+    T* tb = X + (int64_t)Nd * wc;                       // tslots x kmax x wc
+    T* part = tb + (int64_t)d.hs_tslots * kmax * wc;    // kHW x 64 x wc partial sums
+    int* rk = reinterpret_cast<int*>(part + kHT * wc);
+    // the wavefront index is uniform across the wavefront: item records then load as scalars
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int s = threadIdx.x; s < d.nslots; s += kHT) rk[s] = d.ranks[s];
+    const double* Bs = d.B + (int64_t)step * d.bstep + (int64_t)c0 * d.ldb;
+    double* Xs = d.X + (int64_t)step * d.xstep + (int64_t)c0 * d.ldx;
+    for (int idx = threadIdx.x; idx < Nd * wc; idx += kHT) {
+        const int h = idx % Nd, j = idx / Nd;
+        X[idx] = (T)Bs[(int64_t)j * d.ldb + d.h2p[h]];
     }
-    if (2 * m >= kHT || k <= 8) {
-        // one thread per row, all columns of the chunk
-        for (int i = t; i < m; i += kHT) {
-            T s[kHsolveMaxCols];
+    double flops = 0.0;
+    const int nsteps = 2 * L;
+    constexpr int kIpw = kIpwOf<T>::value;
+    // pipeline state: factor values of this step's first items (per wavefront), the item records
+    // of the next step, and the diagonal row of this step
+    HsStep st = d.hs_steps[0];
+    ItemRef cur[kIpw], nxt[kIpw];
+    T av[kIpw][kHsChunk];
+    T tr[64];
+    T diag = T(1);
+    auto load_values = [&](const ItemRef* r, int n) {
+        const int li = min(lane, n - 1);
 #pragma unroll
-            for (int j = 0; j < kHsolveMaxCols; ++j) s[j] = 0;
-#pragma unroll 8
-            for (int l = 0; l < k; ++l) {
-                const T a = A[(int64_t)i * ars + (int64_t)l * acs];
+        for (int k = 0; k < kIpw; ++k)
 #pragma unroll
-                for (int j = 0; j < kHsolveMaxCols; ++j)
-                    if (j < n) s[j] += a * B[(int64_t)l * brs + (int64_t)j * bcs];
+            for (int c = 0; c < kHsChunk; ++c) {
+                const int cc = r[k].ncol > 0 ? min(c, r[k].ncol - 1) : c;
+                av[k][c] = r[k].live ? d.arena[r[k].off + li + (int64_t)cc * r[k].ld] : T(0);
             }
+    };
+    auto load_diag = [&](const HsStep& sx) {
+        const int n = sx.nrow, li = min(lane, n - 1);
+        const T* Tm = d.arena + sx.diag;
 #pragma unroll
-            for (int j = 0; j < kHsolveMaxCols; ++j)
-                if (j < n) put(i, j, s[j]);
-        }
-        return;
+        for (int c = 0; c < 64; ++c) tr[c] = Tm[li + (int64_t)min(c, n - 1) * n];
+        diag = Tm[li + (int64_t)li * n];
+    };
+#pragma unroll
+    for (int k = 0; k < kIpw; ++k) cur[k] = load_item(d.hs_items, st.it0 + wave + k * kHW, st.it1);
+    load_values(cur, st.nrow);
+    if (wave < wc) load_diag(st);
+    HsStep stn = st;
+    if (nsteps > 1) {
+        stn = d.hs_steps[1];
+#pragma unroll
+        for (int k = 0; k < kIpw; ++k) nxt[k] = load_item(d.hs_items, stn.it0 + wave + k * kHW, stn.it1);
     }
-    // few rows, longer k: S slices of k per row, partial sums through LDS
-    int S = 1;
-    while (2 * S * m <= kHT && 2 * S <= k) S <<= 1;
-    const int i = t % m, sl = t / m;
-    if (sl < S) {
-        T s[kHsolveMaxCols];
+    __syncthreads();
+    unsigned long long tph = (d.prof && threadIdx.x == 0) ? wall_clock64() : 0ull;
+    auto phase = [&](int k) {   // op profile: step phases (thread 0); TRSM counts the steps
+        if (d.prof && threadIdx.x == 0) {
+            const unsigned long long t = wall_clock64();
+            atomicAdd(&d.prof[2 * kOpCodes + k], t - tph);
+            if (k == 7) atomicAdd(&d.prof[2 * OP_TRSM + 1], 1ull);
+            tph = t;
+        }
+    };
+    for (int s = 0; s < nsteps; ++s) {
+        const bool fwd = s < L;
+        const int n = st.nrow;
+        const int li = min(lane, n - 1);
+        // A: partial sums of the contributions to the leaf's rows (row = lane)
+        T acc[kHsolveMaxCols];
 #pragma unroll
-        for (int j = 0; j < kHsolveMaxCols; ++j) s[j] = 0;
-#pragma unroll 8
-        for (int l = sl; l < k; l += S) {
-            const T a = A[(int64_t)i * ars + (int64_t)l * acs];
+        for (int j = 0; j < kHsolveMaxCols; ++j) acc[j] = T(0);
 #pragma unroll
-            for (int j = 0; j < kHsolveMaxCols; ++j)
-                if (j < n) s[j] += a * B[(int64_t)l * brs + (int64_t)j * bcs];
+        for (int k = 0; k < kIpw; ++k) {
+            if (!cur[k].live) continue;
+            const ItemRef& m = cur[k];
+            if (m.ncol > 0) {
+                if (lane == 0) flops += 2.0 * n * m.ncol * wc;
+#pragma unroll
+                for (int c = 0; c < kHsChunk; ++c)
+                    if (c < m.ncol)
+#pragma unroll
+                        for (int j = 0; j < kHsolveMaxCols; ++j)
+                            if (j < wc) acc[j] += av[k][c] * X[m.col0 + c + (int64_t)j * Nd];
+            } else {
+                const int r = rk[m.slot];
+                if (lane == 0) flops += 2.0 * n * r * wc;
+                const T* t = tb + (int64_t)m.tslot * kmax * wc;
+#pragma unroll
+                for (int c = 0; c < kHsChunk; ++c)
+                    if (c < r)
+#pragma unroll
+                        for (int j = 0; j < kHsolveMaxCols; ++j)
+                            if (j < wc) acc[j] += av[k][c] * t[c * wc + j];
+                for (int c = kHsChunk; c < r; ++c) {   // ranks above kHsChunk: the rest directly
+                    const T a = d.arena[m.off + li + (int64_t)c * m.ld];
+                    for (int j = 0; j < wc; ++j) acc[j] += a * t[c * wc + j];
+                }
+            }
+        }
+        // items beyond the prefetched ones (steps with more than kIpw items per wavefront)
+        for (int it = st.it0 + wave + kIpw * kHW; it < st.it1; it += kHW) {
+            const HsItem m = d.hs_items[it];
+            const T* A = d.arena + m.off + li;
+            const int cols = m.ncol > 0 ? m.ncol : rk[m.slot];
+            if (lane == 0) flops += 2.0 * n * cols * wc;
+            const T* t = m.ncol > 0 ? nullptr : tb + (int64_t)m.tslot * kmax * wc;
+            for (int c0u = 0; c0u < cols; c0u += kHsChunk) {
+                T a[kHsChunk];   // eight loads in flight together (clamped columns)
+#pragma unroll
+                for (int c = 0; c < kHsChunk; ++c) a[c] = A[(int64_t)min(c0u + c, cols - 1) * m.ld];
+#pragma unroll
+                for (int c = 0; c < kHsChunk; ++c)
+                    if (c0u + c < cols)
+                        for (int j = 0; j < wc; ++j)
+                            acc[j] += a[c] * (m.ncol > 0 ? X[m.col0 + c0u + c + (int64_t)j * Nd] : t[(c0u + c) * wc + j]);
+            }
         }
 #pragma unroll
         for (int j = 0; j < kHsolveMaxCols; ++j)
-            if (j < n) L.red[(sl * m + i) * n + j] = s[j];
-    }
-    __syncthreads();
-    for (int idx = t; idx < m * n; idx += kHT) {
-        const int ii = idx % m, j = idx / m;
-        T s = 0;
-        for (int q = 0; q < S; ++q) s += L.red[(q * m + ii) * n + j];
-        put(ii, j, s);
-    }
-}
-
-// X (LDS, n x w) <- T^{-1} X with T a dense factor leaf (HBM)
-template <class T>
-__device__ void hs_trsm(const Inst<T>& d, const Lds<T>& L, const OpRec& o) {
-    const int n = hdim(L, o.dim[0]), w = hdim(L, o.dim[1]);
-    if (n <= 0 || w <= 0) return;
-    T* X = lptr(L, o.v[0]);
-    const T* Tm = d.arena + o.v[1].off;
-    const int xrs = o.v[0].rs, xcs = o.v[0].cs, trs = o.v[1].rs, tcs = o.v[1].cs;
-    const bool lower = o.flags & 1, unit = o.flags & 2;
-    if (n <= 64) {
-        tri_wave(Tm, trs, tcs, n, lower, unit, X, xrs, xcs, w, (int)(threadIdx.x >> 6), kHW);
-        return;
-    }
-    // larger leaves: column-oriented substitution, one barrier per step
-    for (int st = 0; st < n; ++st) {
-        const int i = lower ? st : n - 1 - st;
-        if (!unit) {
-            if ((int)threadIdx.x < w) X[(int64_t)i * xrs + (int64_t)threadIdx.x * xcs] /= Tm[(int64_t)i * trs + (int64_t)i * tcs];
+            if (j < wc) part[(wave * 64 + lane) * wc + j] = acc[j];
+        // prefetch: factor values of the next step's items, the records of the step after
+        HsStep st2 = stn;
+        if (s + 1 < nsteps) {
+            load_values(nxt, stn.nrow);
+#pragma unroll
+            for (int k = 0; k < kIpw; ++k) cur[k] = nxt[k];
+            if (s + 2 < nsteps) {
+                st2 = d.hs_steps[s + 2];
+#pragma unroll
+                for (int k = 0; k < kIpw; ++k) nxt[k] = load_item(d.hs_items, st2.it0 + wave + k * kHW, st2.it1);
+            }
+        }
+        __syncthreads();
+        phase(6);
+        // B: wavefront j sums the partials of column j and solves with the diagonal leaf
+        if (wave < wc) {
+            const int j = wave;
+            const bool act = lane < n;
+            T y = act ? X[st.row0 + lane + (int64_t)j * Nd] : T(0);
+#pragma unroll
+            for (int w = 0; w < kHW; ++w) y -= part[(w * 64 + lane) * wc + j];
+            const T dinv = (!fwd && act) ? T(1) / diag : T(1);
+            if (lane == 0) flops += (double)n * n;
+#pragma unroll
+            for (int c = 0; c < 64; ++c) tr[c] = (c < n && act) ? tr[c] * dinv : T(0);
+            T x = act ? y * dinv : T(0);
+            if (fwd) {
+#pragma unroll
+                for (int c = 0; c < 64; ++c)
+                    if (c < n) {
+                        const T xs = lane_bcast(x, c);
+                        if (lane > c) x -= tr[c] * xs;
+                    }
+            } else {
+#pragma unroll
+                for (int c = 63; c >= 0; --c)
+                    if (c < n) {
+                        const T xs = lane_bcast(x, c);
+                        if (lane < c) x -= tr[c] * xs;
+                    }
+            }
+            if (act) X[st.row0 + lane + (int64_t)j * Nd] = x;
+            if (s + 1 < nsteps) load_diag(stn);   // the next step's diagonal row, in flight during C and A
+        }
+        __syncthreads();
+        phase(7);
+        // C: t_B = V_B^T x_sigma for the blocks whose column cluster is now solved; the (block,
+        // column) pairs are spread over the wavefronts
+        if (st.tc1 > st.tc0) {
+            const int npair = (st.tc1 - st.tc0) * kmax;
+            for (int pq = wave; pq < npair; pq += kHW) {
+                const HsTcomp tcm = d.hs_tc[st.tc0 + pq / kmax];
+                const int c = pq % kmax;
+                const int r = rk[tcm.slot];
+                T* t = tb + (int64_t)tcm.tslot * kmax * wc;
+                if (lane == 0 && c == 0) flops += 2.0 * tcm.ld * r * wc;
+                const T* v = d.arena + tcm.voff + (int64_t)c * tcm.ld;
+                for (int j = 0; j < wc; ++j) {
+                    T sum = 0;
+                    if (c < r) {
+#pragma unroll 4
+                        for (int k = lane; k < tcm.ld; k += 64) sum += v[k] * X[tcm.col0 + k + (int64_t)j * Nd];
+                    }
+                    sum = wave_sum_t(sum);
+                    if (lane == 0) t[c * wc + j] = sum;
+                }
+            }
             __syncthreads();
         }
-        const int lo = lower ? i + 1 : 0, cnt = lower ? n - i - 1 : i;
-        for (int idx = threadIdx.x; idx < cnt * w; idx += kHT) {
-            const int l = lo + idx % cnt, j = idx / cnt;
-            X[(int64_t)l * xrs + (int64_t)j * xcs] -= Tm[(int64_t)l * trs + (int64_t)i * tcs] * X[(int64_t)i * xrs + (int64_t)j * xcs];
-        }
-        __syncthreads();
+        phase(8);
+        st = stn;
+        stn = st2;
     }
-}
-
-// Y (LDS, m x w) += alpha U (V^T X) for a low-rank factor block: t = V^T X into the temporary,
-// then Y += alpha U t. The rows of U a thread will need are loaded before the first phase, so
-// their latency overlaps the V^T X reduction.
-constexpr int kLrmvPre = 16;
-template <class T>
-__device__ void hs_lrmv(const Inst<T>& d, const Lds<T>& L, const OpRec& o) {
-    const LRBlockDev B = d.lr[o.blk];
-    const int m = B.m, n = B.n, r = L.rk[B.slot], w = hdim(L, o.dim[1]);
-    if (r <= 0 || w <= 0) return;
-    T* Y = lptr(L, o.v[0]);
-    const T* X = lptr(L, o.v[1]);
-    T* t = lptr(L, o.v[2]);
-    const int yrs = o.v[0].rs, ycs = o.v[0].cs, xrs = o.v[1].rs, xcs = o.v[1].cs, trs = o.v[2].rs, tcs = o.v[2].cs;
-    const T* U = d.arena + B.uoff;
-    const T* V = d.arena + B.voff;
-    const T alpha = (T)o.alpha;
-    const int tid = threadIdx.x;
-    const bool pre = m <= kHT && r <= kLrmvPre;
-    T u[kLrmvPre];
-    if (pre) {
-        // unconditional loads (clamped row and column) so that they are all in flight together
-        const int row = min(tid, m - 1);
-#pragma unroll
-        for (int c = 0; c < kLrmvPre; ++c) u[c] = U[row + (int64_t)min(c, r - 1) * m];
-#pragma unroll
-        for (int c = 0; c < kLrmvPre; ++c) u[c] = c < r ? u[c] : T(0);
+    for (int idx = threadIdx.x; idx < Nd * wc; idx += kHT) {
+        const int h = idx % Nd, j = idx / Nd;
+        Xs[(int64_t)j * d.ldx + d.h2p[h]] = (double)X[idx];
     }
-    // t(c, j) = sum_l V(l, c) X(l, j): G lanes per output, consecutive lanes along l (contiguous in V)
-    int G = 64;
-    while (G > 1 && G * r * w > kHT) G >>= 1;
-    const int ng = kHT / G, gid = tid / G, gl = tid % G;
-    for (int idx = gid; idx < r * w; idx += ng) {
-        const int c = idx % r, j = idx / r;
-        const T* v = V + (int64_t)c * n;
-        const T* x = X + (int64_t)j * xcs;
-        T s = 0;
-        for (int l = gl; l < n; l += G) s += v[l] * x[(int64_t)l * xrs];
-        s = group_sum(s, G);
-        if (gl == 0) t[(int64_t)c * trs + (int64_t)j * tcs] = s;
-    }
-    __syncthreads();
-    if (pre) {
-        if (tid < m)
-            for (int j = 0; j < w; ++j) {
-                T s = 0;
-#pragma unroll
-                for (int c = 0; c < kLrmvPre; ++c)
-                    if (c < r) s += u[c] * t[(int64_t)c * trs + (int64_t)j * tcs];
-                Y[(int64_t)tid * yrs + (int64_t)j * ycs] += alpha * s;
-            }
-        return;
-    }
-    for (int i = tid; i < m; i += kHT)
-        for (int j = 0; j < w; ++j) {
-            T s = 0;
-            for (int c = 0; c < r; ++c) s += U[i + (int64_t)c * m] * t[(int64_t)c * trs + (int64_t)j * tcs];
-            Y[(int64_t)i * yrs + (int64_t)j * ycs] += alpha * s;
-        }
-}
-
-template <class T>
-__device__ void hsolve_body(const Inst<T>& d, int c0, int wc, int step, char* smem) {
-    const int Nd = d.Nd;
-    wc = min(wc, d.nrhs - c0);
-    if (wc <= 0) return;
-    Lds<T> L;
-    L.X = reinterpret_cast<T*>(smem);
-    L.W = L.X + (int64_t)Nd * wc;
-    L.red = L.W + (int64_t)d.work_rows * wc;
-    L.rk = reinterpret_cast<int*>(L.red + kHT * wc);
-    L.wc = wc;
-    for (int s = threadIdx.x; s < d.nslots; s += kHT) L.rk[s] = d.ranks[s];
-    const double* Bs = d.B + (int64_t)step * d.bstep + (int64_t)c0 * d.ldb;
-    double* Xs = d.X + (int64_t)step * d.xstep + (int64_t)c0 * d.ldx;
-    double flops = 0.0;
-    __syncthreads();
-    OpRec nxt = d.ops[0];
-    for (int pc = 0; pc < d.nops; ++pc) {
-        const OpRec o = nxt;
-        if (pc + 1 < d.nops) nxt = d.ops[pc + 1];
-        unsigned long long t0 = 0;
-        if (d.prof && threadIdx.x == 0) t0 = wall_clock64();
-        switch (o.code) {
-            case OP_LOAD:
-                for (int idx = threadIdx.x; idx < Nd * wc; idx += kHT) {
-                    const int h = idx % Nd, j = idx / Nd;
-                    L.X[idx] = (T)Bs[(int64_t)j * d.ldb + d.h2p[h]];
-                }
-                break;
-            case OP_STORE:
-                for (int idx = threadIdx.x; idx < Nd * wc; idx += kHT) {
-                    const int h = idx % Nd, j = idx / Nd;
-                    Xs[(int64_t)j * d.ldx + d.h2p[h]] = (double)L.X[idx];
-                }
-                break;
-            case OP_GEMM:
-                hs_gemm(d, L, o);
-                if (threadIdx.x == 0) flops += 2.0 * hdim(L, o.dim[0]) * hdim(L, o.dim[1]) * hdim(L, o.dim[2]);
-                break;
-            case OP_LRMV:
-                hs_lrmv(d, L, o);
-                if (threadIdx.x == 0) {
-                    const LRBlockDev B = d.lr[o.blk];
-                    flops += 2.0 * (B.m + B.n) * L.rk[B.slot] * hdim(L, o.dim[1]);
-                }
-                break;
-            case OP_TRSM:
-                hs_trsm(d, L, o);
-                if (threadIdx.x == 0) {
-                    const double n = hdim(L, o.dim[0]);
-                    flops += n * n * hdim(L, o.dim[1]);
-                }
-                break;
-            default: break;
-        }
-        __syncthreads();
-        if (d.prof && threadIdx.x == 0) {
-            atomicAdd(&d.prof[2 * o.code], (unsigned long long)(wall_clock64() - t0));
-            atomicAdd(&d.prof[2 * o.code + 1], 1ull);
-        }
-    }
-    if (threadIdx.x == 0) atomicAdd(d.flops, flops);
+    if (lane == 0) atomicAdd(d.flops, flops);
 }
 
 template <class T>
@@ -286,13 +267,13 @@ __global__ void __launch_bounds__(kHT) k_hsolve(const Inst<T>* __restrict__ inst
     extern __shared__ __align__(16) char smem[];
     const int i = blockIdx.x / nchunk, c = blockIdx.x % nchunk;
     const Inst<T> d = insts[i];
-    hsolve_body(d, c * wc, wc, step, smem);
+    hsteps_body(d, c * wc, wc, step, smem);
 }
 
 template <class T>
 __global__ void __launch_bounds__(kHT) k_hsolve_one(const Inst<T> d, int wc) {
     extern __shared__ __align__(16) char smem[];
-    hsolve_body(d, blockIdx.x * wc, wc, 0, smem);
+    hsteps_body(d, blockIdx.x * wc, wc, 0, smem);
 }
 
 template <class K>
@@ -304,8 +285,8 @@ void allow_lds(K kernel, size_t bytes) {
 
 }  // namespace
 
-size_t hsolve_lds_bytes(int Nd, int work_rows, int nslots, int wc, size_t esz) {
-    return ((size_t)Nd + work_rows + kHT) * wc * esz + (size_t)nslots * sizeof(int) + 16;
+size_t hsolve_lds_bytes(int Nd, int tslots, int kmax, int nslots, int wc, size_t esz) {
+    return ((size_t)Nd + (size_t)tslots * kmax + kHT) * wc * esz + (size_t)nslots * sizeof(int) + 16;
 }
 
 size_t device_lds_limit(int device) {

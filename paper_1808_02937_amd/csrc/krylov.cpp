@@ -160,7 +160,7 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
             if (!g.nr || !g.prec || (g.prec->prec == FDE_FP64) != (h == &hs64)) continue;
             h->nchunk = std::max(h->nchunk, (g.nr + h->wc - 1) / h->wc);
             const Plan& P = *g.prec->plan;
-            h->bytes = std::max(h->bytes, hsolve_lds_bytes(g.op->Nd, (int)P.sv.work_elems, P.t.nslots, h->wc, g.prec->esz));
+            h->bytes = std::max(h->bytes, hsolve_lds_bytes(g.op->Nd, P.hs.tslots, g.prec->kmax, P.t.nslots, h->wc, g.prec->esz));
         }
         if (!c->lds_limit || h->bytes > c->lds_limit) h->lds = false;
     }
