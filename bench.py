@@ -119,6 +119,88 @@ def cpu_baseline():
                        f"relres {info['relres']:.1e}); {dt:.1f} s")}
 
 
+def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=1808029375, batch_cap=16):
+    """A request stream (Section 5's problem class, many keys): a pool of 24 problems -- N
+    log-uniform in [128, 1024], P in {4, 6, 8}, alpha ~ U(1.1, 1.9), theta ~ U(0, 1), rho in
+    {0, 1}, uniform or two-sided graded mesh -- requested with Zipf(1.1) reuse, each request
+    U{1..16} right-hand sides. Arrivals are Poisson at `load` times the saturated rate measured
+    first; the server takes every request that has arrived (at most batch_cap) as one batch.
+    Latency = completion - arrival over n_req requests after n_warm warm-up requests."""
+    gen = np.random.default_rng(seed)
+    pool = []
+    for _ in range(24):
+        N = int(round(np.exp(gen.uniform(np.log(128), np.log(1024)))))
+        P = int(gen.choice([4, 6, 8]))
+        graded = bool(gen.integers(0, 2))
+        nodes = fi.two_sided_graded_mesh(N) if graded else fi.uniform_mesh(N)
+        pool.append((nodes, P, float(gen.uniform(1.1, 1.9)), float(gen.uniform(0.0, 1.0)), float(gen.integers(0, 2))))
+    w = 1.0 / np.arange(1, len(pool) + 1) ** 1.1
+    w /= w.sum()
+    total = n_req + n_warm
+    keys = gen.choice(len(pool), size=total, p=w)
+    nrhs = gen.integers(1, 17, size=total)
+    srv = fde.Server(ctx, R=8, leaf_elems=8, tol=1e-3, precision="fp32", rtol=1e-10)
+    tg = torch.Generator(device="cuda").manual_seed(seed)
+
+    def make(i):
+        nodes, P = pool[keys[i]][0], pool[keys[i]][1]
+        Nd = (len(nodes) - 1) * P - 1
+        return pool[keys[i]], torch.randn(int(nrhs[i]), Nd, dtype=torch.float64, device="cuda", generator=tg)
+
+    def serve(batch):
+        probs, Gs = zip(*[make(i) for i in batch])
+        _, infos, cached = srv.solve(list(probs), list(Gs))
+        torch.cuda.synchronize()
+        for inf in infos:
+            for (_, rel, st) in inf:
+                if st != 0 or not rel <= 1e-10:
+                    raise RuntimeError(f"serving: a request did not converge ({st}, {rel})")
+        return sum(cached)
+
+    # every key built once, then the saturated rate with all factors cached (back-to-back batches)
+    for k in range(len(pool)):
+        first = int(np.argmax(keys == k)) if (keys == k).any() else None
+        if first is not None:
+            serve([first])
+    t = time.perf_counter()
+    served = 0
+    i = 0
+    while i < 200:
+        batch = list(range(i, min(i + batch_cap, 200)))
+        serve(batch)
+        served += len(batch)
+        i += batch_cap
+    sat = served / (time.perf_counter() - t)   # requests/s
+    rate = load * sat
+    arrivals = np.cumsum(gen.exponential(1.0 / rate, size=total))
+    lat = np.zeros(total)
+    hits = 0
+    t0 = time.perf_counter()
+    nxt = 0
+    while nxt < total:
+        now = time.perf_counter() - t0
+        if arrivals[nxt] > now:
+            time.sleep(min(arrivals[nxt] - now, 0.002))
+            continue
+        batch = []
+        while nxt < total and arrivals[nxt] <= now and len(batch) < batch_cap:
+            batch.append(nxt)
+            nxt += 1
+        hits += serve(batch)
+        done = time.perf_counter() - t0
+        for r in batch:
+            lat[r] = done - arrivals[r]
+    elapsed = time.perf_counter() - t0
+    meas = lat[n_warm:] * 1e3
+    st = srv.stats()
+    srv.close()
+    return {"requests": n_req, "warmup_requests": n_warm, "keys": len(pool), "rhs_per_request": "U{1..16}",
+            "saturated_requests_per_s": sat, "arrival_rate_per_s": rate, "load": load,
+            "p50_ms": float(np.percentile(meas, 50)), "p99_ms": float(np.percentile(meas, 99)),
+            "mean_ms": float(meas.mean()), "solves_per_s": float(nrhs.sum() / elapsed),
+            "cache": st, "definition": "latency = completion - arrival; Poisson arrivals; continuous batching"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +303,12 @@ def main():
         t_hs = kernel_time_ms(torch, lambda: lus[0].solve(v), 20)
         t_ap = kernel_time_ms(torch, lambda: ops[0].apply(v), 50)
         out["kernels_ms"] = {"hsolve_fp32": t_hs, "apply_toeplitz": t_ap}
+        log("serving stream")
+        out["serving"] = serving_stream(fde, torch, ctx)
+        out["latency_ms"] = {"p50": out["serving"]["p50_ms"], "p99": out["serving"]["p99_ms"],
+                             "definition": "request completion - arrival, serving stream (see serving)",
+                             "batch_p50": float(np.percentile(lat, 50) * 1e3),
+                             "batch_p99": float(np.percentile(lat, 99) * 1e3)}
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline()

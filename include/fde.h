@@ -243,6 +243,34 @@ int  fde_solve_batched(fde_ctx* ctx, int n, fde_op* const* ops, fde_hlu* const* 
 /* n-point Gauss rule for the weight (1-x)^a (1+x)^b on [-1,1] (host; the
  * library's own generator, used for every rule above). */
 int  fde_gauss_jacobi(int n, double a, double b, double* x_host, double* w_host);
+/* ---- serving (many problems, many right-hand sides) -------------------- */
+
+/* A problem: the operator of eq. (Model) on nodes[0..N] with degree P. */
+typedef struct { const double* nodes; int N; int P; double alpha; double theta; double rho; } fde_problem;
+typedef struct fde_server fde_server;   /* solver cache over one context */
+
+/* A server keeps, per problem, the operator and the H-LU factors (H-matrix
+ * parameters hp, H-LU parameters lp; NULL: defaults) and serves batches of
+ * right-hand sides with the Krylov parameters sp. budget_bytes (0: none)
+ * bounds the device bytes its cached problems hold: before factors are built
+ * the least recently used problems that the batch does not use are evicted. */
+int  fde_server_create(fde_ctx* ctx, const fde_hparams* hp, const fde_hlu_params* lp,
+                       const fde_solve_params* sp, size_t budget_bytes, fde_server** out);
+void fde_server_destroy(fde_server* s);
+/* Solve n requests: request i asks for nrhs[i] solutions X[i] (device, ld
+ * ldx[i]) of problem probs[i] with right-hand sides G[i] (device, ld ldg[i]).
+ * Problems without cached factors are built in one batched H-LU, then all
+ * right-hand sides are solved by one batched FGMRES. info: sum(nrhs) entries
+ * in request order (host); cached[i] (host, optional): 1 if the factors were
+ * cached. A problem that cannot fit the budget gets status FDE_ENOMEM in
+ * its info entries and the call returns FDE_ENOMEM after serving the rest. */
+int  fde_server_solve(fde_server* s, int n, const fde_problem* probs, const int* nrhs,
+                      const double* const* G_dev, const int* ldg, double* const* X_dev, const int* ldx,
+                      fde_solve_info* info, int* cached);
+/* cached problems, their device bytes, and the cache's hits, misses and evictions */
+int  fde_server_stats(const fde_server* s, int* entries, size_t* bytes, long long* hits, long long* misses,
+                      long long* evictions);
+
 const char* fde_last_error(void);
 const char* fde_version(void);
 

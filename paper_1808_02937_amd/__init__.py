@@ -5,5 +5,5 @@ All numerical work runs in the HIP library libfde.so (C ABI in include/fde.h);
 this package only marshals arguments and owns device buffers through PyTorch.
 """
 from ._abi import FDEError, load  # noqa: F401
-from .fde import (Context, HLU, HMatrix, Operator, factor_batched, gauss_jacobi, plan_hlu,  # noqa: F401
-                  solve, solve_batched)
+from .fde import (Context, HLU, HMatrix, Operator, Server, factor_batched, gauss_jacobi,  # noqa: F401
+                  plan_hlu, solve, solve_batched)

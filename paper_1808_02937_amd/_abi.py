@@ -55,6 +55,10 @@ class PlanInfo(C.Structure):
                 ("bytes_fp64", ll)]
 
 
+class Problem(C.Structure):
+    _fields_ = [("nodes", dp), ("N", i32), ("P", i32), ("alpha", f64), ("theta", f64), ("rho", f64)]
+
+
 FN = C.CFUNCTYPE(C.c_double, C.c_double, C.c_void_p)
 
 # name -> (restype, argtypes); every symbol declared in include/fde.h
@@ -89,6 +93,13 @@ SIGNATURES = {
     "fde_solve": (i32, [vp, vp, i32, vp, i32, vp, i32, C.POINTER(SolveParams), C.POINTER(SolveInfo)]),
     "fde_solve_batched": (i32, [vp, i32, C.POINTER(vp), C.POINTER(vp), ip, C.POINTER(vp), ip,
                                 C.POINTER(vp), ip, C.POINTER(SolveParams), C.POINTER(SolveInfo)]),
+    "fde_server_create": (i32, [vp, C.POINTER(HParams), C.POINTER(HLUParams), C.POINTER(SolveParams), sz,
+                                C.POINTER(vp)]),
+    "fde_server_destroy": (None, [vp]),
+    "fde_server_solve": (i32, [vp, i32, C.POINTER(Problem), ip, C.POINTER(vp), ip, C.POINTER(vp), ip,
+                               C.POINTER(SolveInfo), ip]),
+    "fde_server_stats": (i32, [vp, ip, C.POINTER(sz), C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
+                               C.POINTER(C.c_longlong)]),
     "fde_gauss_jacobi": (i32, [i32, f64, f64, dp, dp]),
     "fde_last_error": (C.c_char_p, []),
     "fde_version": (C.c_char_p, []),

@@ -219,6 +219,21 @@ void init_ctx_tables(Ctx* c) {
     FDE_HIP(hipStreamSynchronize(c->stream));
 }
 
+// constant ratio h_{e+1}/h_e (uniform: ratio 1)?
+bool mesh_ratio(const double* x, int N, double* ratio) {
+    bool geo = true;
+    double r = 1.0;
+    if (N > 1) {
+        r = (x[2] - x[1]) / (x[1] - x[0]);
+        for (int e = 1; e + 1 < N && geo; ++e) {
+            const double q = (x[e + 2] - x[e + 1]) / (x[e + 1] - x[e]);
+            if (std::fabs(q - r) > 1e-12 * std::max(1.0, r)) geo = false;
+        }
+    }
+    *ratio = r;
+    return geo;
+}
+
 void build_op(Op* op, const double* nodes, int N, int P, double alpha, double theta, double rho,
               int mode) {
     if (N < 1) fail(FDE_EINVAL, "N must be >= 1 (got %d)", N);
@@ -303,26 +318,33 @@ void build_op(Op* op, const double* nodes, int N, int P, double alpha, double th
 }
 
 }  // namespace
+
+size_t op_device_bytes(const double* x, int N, int P, int nrhs) {
+    double r;
+    const bool geo = mesh_ratio(x, N, &r);
+    const bool toeplitz = geo && 2 * N <= 8192;
+    size_t b = 8 * ((size_t)2 * N + 1) + 8 * (4 * (size_t)P + 2) + 8 * (size_t)(P + 1) * (P + 1);
+    const size_t nq = (size_t)N * 48 + 256;   // load-vector nodes (graded panels near the ends)
+    b += nq * 8 * 5 + (size_t)(N + 1) * 4;
+    const size_t cz = 2 * (size_t)nrhs * N * P;
+    if (toeplitz) {
+        int L = 4;
+        while (L < 2 * N) L *= 2;
+        const size_t M = L / 2;
+        b += 16 * (M + 1) + 8 * (size_t)N * P * P + 16 * (size_t)P * P * (M + 1);
+        b += 8 * (cz + 8 * (size_t)nrhs * P * (M + 1));
+    } else {
+        b += 8 * (size_t)tri(N) * P * P;
+        b += 8 * (cz + (size_t)nrhs * tri(N / 8 + 1) * 2 * 8 * P);   // apply partial sums (upper bound)
+    }
+    return b;
+}
+
 }  // namespace fde
 
 using namespace fde;
 
-#define FDE_API_BEGIN try {
-#define FDE_API_END                                 \
-    }                                               \
-    catch (const fde::Error& e) {                   \
-        fde::set_error("%s", e.msg.c_str());        \
-        return e.code;                              \
-    }                                               \
-    catch (const std::bad_alloc&) {                 \
-        fde::set_error("host allocation failed");   \
-        return FDE_ENOMEM;                          \
-    }                                               \
-    catch (...) {                                   \
-        fde::set_error("unexpected internal error"); \
-        return FDE_EDEVICE;                         \
-    }                                               \
-    return FDE_OK;
+
 
 extern "C" {
 

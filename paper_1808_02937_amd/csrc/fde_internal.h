@@ -32,6 +32,32 @@ struct Error {
 
 #define FDE_LAUNCH_CHECK() FDE_HIP(hipGetLastError())
 
+// C entry points: library errors become status codes and a message (no exception crosses the ABI)
+#define FDE_API_BEGIN try {
+#define FDE_API_END                                 \
+    }                                               \
+    catch (const fde::Error& e) {                   \
+        fde::set_error("%s", e.msg.c_str());        \
+        return e.code;                              \
+    }                                               \
+    catch (const std::bad_alloc&) {                 \
+        fde::set_error("host allocation failed");   \
+        return FDE_ENOMEM;                          \
+    }                                               \
+    catch (...) {                                   \
+        fde::set_error("unexpected internal error"); \
+        return FDE_EDEVICE;                         \
+    }                                               \
+    return FDE_OK;
+
+// a status from another entry point, as an error of this one (its message is kept)
+inline void check_rc(int rc) {
+    if (rc != FDE_OK) {
+        const char* m = fde_last_error();
+        throw Error{rc, m ? std::string(m) : std::string()};
+    }
+}
+
 // ---------------------------------------------------------------- quadrature
 // n-point Gauss rule for (1-x)^a (1+x)^b on [-1,1]; nodes ascending.
 void gauss_jacobi(int n, double a, double b, double* x, double* w);
@@ -109,6 +135,9 @@ struct Op {
     DevBuf<double> ws;
     size_t apply_ws_doubles(int nrhs) const;
 };
+
+// device bytes an operator on nodes x (N elements, degree P) holds after an apply of nrhs columns
+size_t op_device_bytes(const double* x, int N, int P, int nrhs);
 
 // kernels (assembly.hip)
 void launch_pair_moments_dense(Op* op);

@@ -440,22 +440,7 @@ void hlu_solve(HLUObj* f, int nrhs, const double* B, int ldb, double* X, int ldx
 
 }  // namespace fde
 
-#define FDE_API_BEGIN try {
-#define FDE_API_END                                   \
-    }                                                 \
-    catch (const fde::Error& e) {                     \
-        fde::set_error("%s", e.msg.c_str());          \
-        return e.code;                                \
-    }                                                 \
-    catch (const std::bad_alloc&) {                   \
-        fde::set_error("host allocation failed");     \
-        return FDE_ENOMEM;                            \
-    }                                                 \
-    catch (...) {                                     \
-        fde::set_error("unexpected internal error");  \
-        return FDE_EDEVICE;                           \
-    }                                                 \
-    return FDE_OK;
+
 
 extern "C" {
 

@@ -320,3 +320,57 @@ def solve_batched(ctx: Context, ops: Sequence[Operator], Gs: Sequence[torch.Tens
                     for j in range(g.shape[0])])
         k += g.shape[0]
     return [x.view_as(g0) for x, g0 in zip(Xs, Gs)], out
+
+
+class Server(_Handle):
+    """Solver cache and batched serving over one context (fde_server_*)."""
+
+    _destroy = "fde_server_destroy"
+
+    def __init__(self, ctx: Context, R: int = 8, lam: float = 1.0, leaf_elems: int = 8, tol: float = 1e-3,
+                 rank_cap: int = 0, precision: str = "fp32", pivot_floor: float = 1e-14, rtol: float = 1e-10,
+                 restart: int = 30, maxit: int = 500, budget_bytes: int = 0):
+        lib = load()
+        self.ctx = ctx
+        hp = A.HParams(int(R), float(lam), int(leaf_elems))
+        prec = {"fp64": A.FDE_FP64, "fp32": A.FDE_FP32}[precision]
+        lp = A.HLUParams(float(tol), int(rank_cap), prec, float(pivot_floor))
+        sp = _solve_params(rtol, restart, maxit)
+        h = C.c_void_p()
+        check(lib.fde_server_create(ctx.h, C.byref(hp), C.byref(lp), C.byref(sp), int(budget_bytes), C.byref(h)))
+        self._init_handle(h, ctx)
+
+    def solve(self, problems, Gs):
+        """problems: list of (nodes, P, alpha, theta, rho); Gs: list of (nrhs, Nd) float64 device tensors.
+        Returns (Xs, infos per request, cached flags)."""
+        n = len(problems)
+        keep = []
+        probs = (A.Problem * n)()
+        for i, (nodes, P, alpha, theta, rho) in enumerate(problems):
+            x = np.ascontiguousarray(nodes, dtype=np.float64)
+            keep.append(x)
+            probs[i] = A.Problem(_np_dptr(x), len(x) - 1, int(P), float(alpha), float(theta), float(rho))
+        blocks = [_as_block(G, int(len(keep[i]) - 1) * int(problems[i][1]) - 1, self.ctx.device) for i, G in enumerate(Gs)]
+        Xs = [torch.empty_like(B) for B in blocks]
+        nr = (C.c_int * n)(*[B.shape[0] for B in blocks])
+        ld = (C.c_int * n)(*[B.shape[1] for B in blocks])
+        Gp = (C.c_void_p * n)(*[B.data_ptr() for B in blocks])
+        Xp = (C.c_void_p * n)(*[X.data_ptr() for X in Xs])
+        ns = sum(B.shape[0] for B in blocks)
+        info = (A.SolveInfo * max(ns, 1))()
+        cached = (C.c_int * n)()
+        rc = load().fde_server_solve(self.h, n, probs, nr, Gp, ld, Xp, ld, info, cached)
+        if rc not in (A.FDE_OK, A.FDE_ENOCONV, A.FDE_ENOMEM):
+            check(rc)
+        out, k = [], 0
+        for B in blocks:
+            out.append([(info[k + j].iters, info[k + j].relres, info[k + j].status) for j in range(B.shape[0])])
+            k += B.shape[0]
+        return Xs, out, [bool(c) for c in cached]
+
+    def stats(self) -> dict:
+        e = C.c_int()
+        b = C.c_size_t()
+        hi, mi, ev = C.c_longlong(), C.c_longlong(), C.c_longlong()
+        check(load().fde_server_stats(self.h, C.byref(e), C.byref(b), C.byref(hi), C.byref(mi), C.byref(ev)))
+        return {"entries": e.value, "bytes": b.value, "hits": hi.value, "misses": mi.value, "evictions": ev.value}
