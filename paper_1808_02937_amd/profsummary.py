@@ -1,4 +1,4 @@
-"""Summarise a rocprofv3 --kernel-trace --stats CSV run into a short markdown table.
+"""Summarise a rocprofv3 --kernel-trace --stats CSV run into short markdown tables.
 
 usage: python -m paper_1808_02937_amd.profsummary <dir-with-*_kernel_stats.csv> "<command>" > out.md
 """
@@ -26,20 +26,19 @@ def main():
     for r in rows[:15]:
         print(f"| {short(r['Name'])} | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.2f} | "
               f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
-    # split launches of the interpreter by grid size (batched H-LU: grid = number of operators, one long launch)
+    # level launches of the H-LU (one kernel per level of the schedule) and H-solve launches
     tr = list(csv.DictReader(open(trace)))
     by = defaultdict(list)
     for t in tr:
-        if "k_interp" in t["Kernel_Name"]:
-            dur = (int(t["End_Timestamp"]) - int(t["Start_Timestamp"])) / 1e6
-            kind = "H-LU" if dur > 200 else "H-solve"
-            by[(short(t["Kernel_Name"]), kind, t["Grid_Size_X"])].append(dur)
+        name = short(t["Kernel_Name"])
+        if name.startswith("k_level") or name.startswith("k_hsolve"):
+            dur = (int(t["End_Timestamp"]) - int(t["Start_Timestamp"])) / 1e3
+            by[(name, t["Grid_Size_X"] if name.startswith("k_hsolve") else "per level")].append(dur)
     if by:
-        print("\n| interpreter launch | kind | grid x (threads) | launches | avg ms |")
-        print("|---|---|---|---|---|")
-        for (k, kind, g), v in sorted(by.items()):
-            print(f"| {k} | {kind} | {g} | {len(v)} | {sum(v) / len(v):.3f} |")
-
+        print("\n| kernel | grid x (threads) | launches | avg us | max us | total ms |")
+        print("|---|---|---|---|---|---|")
+        for (k, g), v in sorted(by.items()):
+            print(f"| {k} | {g} | {len(v)} | {sum(v) / len(v):.1f} | {max(v):.1f} | {sum(v) / 1e3:.2f} |")
 
 if __name__ == "__main__":
     main()
