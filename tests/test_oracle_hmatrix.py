@@ -1,5 +1,6 @@
 """Pins for the oracle's H-matrix, H-LU, H-solves and Krylov solvers (no GPU)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -167,12 +168,22 @@ def test_fgmres_and_bicgstab_reach_the_dense_solution():
     assert info3["iters"] > 3 * info["iters"]
 
 
-def test_table1_iteration_envelope():
-    """Example 1, P = 3, graded power-5 mesh, theta = 1: BiCGSTAB on eq. (precondsys)
-    needs at most 16 steps for R >= 2 and about 4 at R = 7 (Table 1); counts do not
-    grow with R."""
+def _golden_iterations():
+    """The iteration counts of Tables 1 and 2, from tests/golden (with their citation)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "table1_table2_bicgstab_iterations.txt")
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            tab, key, *counts = line.split()
+            out[(tab, int(key))] = [int(c) for c in counts]
+    return out
+
+
+def _example1_counts(N, P):
+    """Preconditioned BiCGSTAB steps of Example 1 for R = 2, 3, 5, 7, counted as the paper counts
+    them (two per step)."""
     m = fi.example1(1.6)
-    sem = SEM(fi.graded_mesh(100, 5.0, 0.0, 10.0), 3, 1.6, 1.0, 0.0)
+    sem = SEM(fi.graded_mesh(N, 5.0, 0.0, 10.0), P, 1.6, 1.0, 0.0)
     A = sem.system_matrix()
     G = sem.load_vector(m.f_terms)
     its = []
@@ -180,8 +191,26 @@ def test_table1_iteration_envelope():
         F = HLU(HMatrix(sem, R, 1.0, 2), tol=1e-3)
         X, info = bicgstab(lambda v: A @ v, G, F.solve, tol=1e-13, side="left")
         assert info["converged"] and info["true_relres"] < 1e-11
-        its.append(info["iters"])
-    assert max(its) <= 16 and its[-1] <= 4
+        its.append(2 * info["iters"])
+    return its
+
+
+def test_table1_iterations_n100():
+    """Example 1, P = 3, N = 100 (Table 1, first row): the oracle's preconditioned BiCGSTAB takes
+    exactly the printed number of steps for every rank."""
+    assert _example1_counts(100, 3) == _golden_iterations()[("table1", 100)]
+
+
+@pytest.mark.slow
+def test_table2_iterations_p3():
+    """Example 1, N = 300, P = 3 (Table 2, first row): within one BiCGSTAB step of the printed
+    counts, never fewer steps at a higher rank, and the printed count at R = 5 and 7. (The
+    paper leaves the leaf size and the stopping norm unstated; at N = 300 they decide one step
+    at R = 2 and 3.)"""
+    its = _example1_counts(300, 3)
+    ref = _golden_iterations()[("table2", 3)]
+    assert all(abs(a - b) <= 2 for a, b in zip(its, ref)), (its, ref)
+    assert its[2:] == ref[2:], (its, ref)
     assert its == sorted(its, reverse=True)
 
 
