@@ -1,15 +1,22 @@
-// Interpreter of H-arithmetic programs: one 256-thread workgroup runs the op
-// list of one instance (one operator's H-LU or H-solve); a launch serves many
-// instances of different sizes at once.
+// Device execution of H-arithmetic programs (H-LU and H-substitutions).
+//
+// k_level runs one level of level-scheduled programs: workgroup b executes one op
+// of one instance, and the ops of a level touch disjoint memory. k_interp runs a
+// whole op list per workgroup, one instance each (the serial order, and
+// H-solves whose right-hand sides do not fit in LDS); a launch of either kernel
+// serves many instances of different sizes at once.
 //
 // Ops: GETRF (dense LU without pivoting, Section 4.1 takes L_H unit lower and
 // no pivoting; a pivot below the floor is a breakdown), TRSM, GEMM, ZERO, and
-// LRSUB -- C <- trunc(U_C V_C^T - X Y^T): thin QR of [U_C, -X] and [V_C, Y] by
-// classical Gram-Schmidt with one reorthogonalisation, the small core
-// R_u R_v^T decomposed by one-sided (Hestenes) Jacobi in FP64, and the
-// singular values above tol * sigma_1 kept, at most kmax of them (the
+// LRSUB -- C <- trunc(U_C V_C^T - X Y^T). Up to the variant's width KS the
+// recompression works on Gram matrices (pivoted Cholesky, a second pass in FP64,
+// the core R_u R_v^T decomposed by one-sided Jacobi in registers); wider sums
+// take a thin QR of [U_C, -X] and [V_C, Y] by classical Gram-Schmidt with one
+// reorthogonalisation and a one-sided Jacobi SVD of the core in FP64. Either way
+// the singular values above tol * sigma_1 are kept, at most kmax of them (the
 // truncation to a prescribed tolerance of Section 4.1). LOAD/STORE move FP64
-// vectors in the paper's order to and from the internal order.
+// vectors in the paper's order to and from the internal order; LRMV applies a
+// low-rank block to a vector.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
