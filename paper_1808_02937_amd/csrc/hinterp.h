@@ -29,9 +29,8 @@ struct Inst {
     int nrhs;
     int nslots;               // low-rank blocks (rank slots)
     int work_rows;            // H-solve temporaries, rows (times the number of right-hand sides)
-    const HsStep* hs_steps;   // leaf-step H-solve: 2 * hs_nleaf steps, their items and t computations
-    const HsItem* hs_items;
-    const HsTcomp* hs_tc;
+    const HsStep* hs_steps;   // leaf-step H-solve: 2 * hs_nleaf steps and their records
+    const HsRec* hs_recs;
     int hs_nleaf, hs_tslots;
     double tol;
     int kmax;

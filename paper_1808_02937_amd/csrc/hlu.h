@@ -28,8 +28,7 @@ struct Plan {
     DevBuf<int> h2p;
     HsTables hs;            // leaf-step H-solve
     DevBuf<HsStep> d_hs_steps;
-    DevBuf<HsItem> d_hs_items;
-    DevBuf<HsTcomp> d_hs_tc;
+    DevBuf<HsRec> d_hs_recs;
     std::vector<int> lr_rows;   // larger dimension of each low-rank block (diagnostics)
 };
 
@@ -78,8 +77,7 @@ struct HLUObj {
         d.nslots = plan->t.nslots;
         d.work_rows = (int)plan->sv.work_elems;
         d.hs_steps = plan->d_hs_steps.p;
-        d.hs_items = plan->d_hs_items.p;
-        d.hs_tc = plan->d_hs_tc.p;
+        d.hs_recs = plan->d_hs_recs.p;
         d.hs_nleaf = plan->hs.nleaf;
         d.hs_tslots = plan->hs.tslots;
         d.tol = tol;

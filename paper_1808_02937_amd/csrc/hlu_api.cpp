@@ -351,7 +351,7 @@ void make_plan_host(const HTree& hmt, int kmax, Plan& p, bool check) {
     gen_hsolve(p.t, p.sv);
     gen_hsolve_steps(p.t, p.hs);
     validate_hsolve_steps(p.t, p.hs);
-    p.sv_lds = p.hs.maxrow <= kHsolveMaxRow;
+    p.sv_lds = p.hs.ok && p.hs.maxrow <= kHsolveMaxRow;
     p.kpmax = lrsub_kprime_max(p.t, p.lu);
     int widest = 0;
     for (const OpRec& o : p.lu.ops)
@@ -385,8 +385,7 @@ std::shared_ptr<const Plan> get_plan(Ctx* c, const HTree& hmt, int kmax) {
     }
     upload_vec(c, p->lr, lrt);
     upload_vec(c, p->d_hs_steps, p->hs.steps);
-    upload_vec(c, p->d_hs_items, p->hs.items);
-    upload_vec(c, p->d_hs_tc, p->hs.tcomp);
+    upload_vec(c, p->d_hs_recs, p->hs.recs);
     for (const LRBlockDev& b : lrt) p->lr_rows.push_back(std::max(b.m, b.n));
     FDE_HIP(hipStreamSynchronize(c->stream));   // host copies of the tables may move later
     p->t.op = nullptr;
@@ -409,9 +408,11 @@ int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes) {
     if (!f->plan->sv_lds || nrhs <= 0) return 0;
     if (!c->lds_limit) c->lds_limit = device_lds_limit(c->device);
     const Plan& P = *f->plan;
-    int wc = std::min(nrhs, kHsolveMaxCols);
+    // chunk widths are 1, 2, 4 or 8 columns (one kernel per width)
+    int wc = 1;
+    while (wc * 2 <= std::min(nrhs, kHsolveMaxCols)) wc *= 2;
     auto need = [&](int w) { return hsolve_lds_bytes(f->op->Nd, P.hs.tslots, f->kmax, P.t.nslots, w, f->esz); };
-    while (wc > 1 && need(wc) > c->lds_limit) --wc;
+    while (wc > 1 && need(wc) > c->lds_limit) wc /= 2;
     if (need(wc) > c->lds_limit) return 0;
     *lds_bytes = need(wc);
     return wc;

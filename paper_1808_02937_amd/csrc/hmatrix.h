@@ -98,40 +98,42 @@ struct Program {
 
 // --------------------------------------------------------------- leaf-step H-solve
 // The forward (L, unit lower) and backward (U) H-substitutions as 2 x (number of leaves)
-// steps. Step of leaf i: x_i <- T_ii^{-1} (x_i - sum of the contributions of solved leaves),
-// the contributions being chunks of <= kHsChunk columns of dense off-diagonal leaf blocks
-// (times solved entries of x) and rows of low-rank factors U_B (times t_B = V_B^T x_sigma,
-// computed once the column cluster sigma of B is solved).
+// steps, pipelined by one leaf. Step p of a direction solves the leaf at position p:
+//   phase 1: the contributions of leaf p-1 (solved in the step before) to the rows of leaf p
+//            (chunks of <= kHsChunk columns of dense blocks), and the increments
+//            t_B += V_B(rows of leaf p-1)^T x_{p-1} of the low-rank blocks whose column
+//            cluster sigma holds leaf p-1;
+//   phase 2: the triangular solve of leaf p and, meanwhile, every other contribution to the
+//            rows of leaf p+1: dense chunks from leaves <= p-1 and rows U_B t_B of low-rank
+//            blocks whose sigma ends at or before leaf p-1.
+// The pipelining needs every low-rank block to couple leaves at least two apart, which holds
+// when admissible clusters are separated by a cluster; the generator checks it.
 constexpr int kHsChunk = 8;
 
-struct HsItem {        // one contribution to the rows of a leaf
-    int64_t off;       // dense: first column of the chunk; low rank: U_B + first row of the leaf
-    int ld;            // leading dimension (dense: leaf rows; low rank: |tau|)
-    int col0;          // dense: x index of the chunk's first column
-    int ncol;          // dense: columns in the chunk (<= kHsChunk); low rank: 0
-    int slot;          // low rank: rank slot
-    int tslot;         // low rank: t buffer slot
+enum HsKind { HS_DENSE = 0, HS_LOWRANK = 1, HS_INC_FIRST = 2, HS_INC = 3 };
+
+struct HsRec {         // one unit of work of a step (32 bytes)
+    int64_t off;       // dense: the chunk's first column; low rank: U_B (or V_B) at the leaf's first row
+    int ld;            // leading dimension (dense: rows of the row leaf; U_B: |tau|; V_B: |sigma|)
+    int col0;          // dense: x index of the chunk's first column; increment: x index of the leaf's first row
+    int n;             // dense: columns (1..kHsChunk); increment: rows of the leaf; low rank: 0
+    int slot;          // low rank and increments: rank slot of B
+    int tslot;         // low rank and increments: t buffer slot of B
+    int kind;          // HsKind
 };
 
-struct HsTcomp {       // t_B = V_B^T x_sigma once sigma is solved
-    int64_t voff;
-    int ld;            // |sigma|
-    int col0;          // sigma's first internal index
-    int slot, tslot;
-};
-
-struct HsStep {
+struct HsStep {        // 32 bytes
     int64_t diag;      // dense diagonal leaf (packed L\U), ld = nrow
-    int row0, nrow;
-    int it0, it1;      // items [it0, it1)
-    int tc0, tc1;      // t computations [tc0, tc1) after the leaf is solved
+    int row0, nrow;    // the leaf solved in this step
+    int rec0;          // records [rec0, rec0 + nlate + ninc + nearly): late chunks, increments, early items
+    int nlate, ninc, nearly;
 };
 
 struct HsTables {
     std::vector<HsStep> steps;   // forward (leaf order), then backward (reverse leaf order)
-    std::vector<HsItem> items;
-    std::vector<HsTcomp> tcomp;
-    int nleaf = 0, tslots = 0, maxrow = 0;
+    std::vector<HsRec> recs;
+    int nleaf = 0, tslots = 0, maxrow = 0, maxrec = 0;
+    bool ok = false;             // false: the structure does not allow the pipelined steps
 };
 
 // --------------------------------------------------------------- H-matrix
@@ -160,7 +162,7 @@ struct HMat {
     DevBuf<int> d_h2p;
 };
 
-void gen_hsolve_steps(const HTree& hm, HsTables& tab);
+void gen_hsolve_steps(const HTree& hm, HsTables& tab);   // sets tab.ok
 // every table entry inside the factor storage and the vector, before the tables reach the device
 void validate_hsolve_steps(const HTree& hm, const HsTables& tab);
 
