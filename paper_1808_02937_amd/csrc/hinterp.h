@@ -32,6 +32,7 @@ struct Inst {
     const HsStep* hs_steps;   // leaf-step H-solve: 2 * hs_nleaf steps and their records
     const HsRec* hs_recs;
     int hs_nleaf, hs_tslots;
+    int hs_wc;                // leaf-step H-solve: columns per workgroup (1, 2, 4 or 8)
     double tol;
     int kmax;
     double pivot_floor;
@@ -50,8 +51,9 @@ template <class T>
 void launch_interp(hipStream_t st, int ninst, const Inst<T>* d_insts, int step = 0, int variant = 0);
 template <class T>
 void launch_interp_one(hipStream_t st, const Inst<T>& d);
-// H-solve with the right-hand sides in LDS: workgroup b solves columns [c*wc, c*wc + wc) of
-// instance b / nchunk (c = b % nchunk); lds_bytes from hsolve_lds_bytes
+// H-solve with the right-hand sides in LDS: workgroup b solves columns [c*w, c*w + w) of
+// instance b / nchunk (c = b % nchunk, w = its hs_wc <= wc, wc in {1, 2, 4, 8}); lds_bytes
+// from hsolve_lds_bytes, the largest over the instances
 template <class T>
 void launch_hsolve(hipStream_t st, int ninst, int nchunk, int wc, const Inst<T>* d_insts, int step,
                    size_t lds_bytes);

@@ -1171,7 +1171,8 @@ void print_op_profile(const char* what, const unsigned long long* p, int device)
         if (p[2 * c + 1]) fprintf(stderr, " %s %llu x %.3f ms = %.2f ms;", names[c], p[2 * c + 1],
                                   p[2 * c] * ms_per_tick / p[2 * c + 1], p[2 * c] * ms_per_tick);
     static const char* phases[kProfPhases] = {"gram", "cholesky", "second pass", "core svd", "factors", "products",
-                                              "phase 1", "phase 2", "-"};
+                                              "phase 1", "phase 2 after the solve", "phase 2 solve",
+                                              "phase 2 helpers"};
     const unsigned long long nl = p[2 * OP_LRSUB + 1];
     if (nl && p[2 * kOpCodes + 1]) {
         fprintf(stderr, "\n[fde ops]   small recompression phases (ms per op):");
@@ -1180,7 +1181,7 @@ void print_op_profile(const char* what, const unsigned long long* p, int device)
     const unsigned long long ns = p[2 * OP_TRSM + 1];
     if (p[2 * kOpCodes + 6] && ns) {
         fprintf(stderr, "\n[fde ops]   leaf-step H-solve phases (ms per step):");
-        for (int k = 6; k < 8; ++k) fprintf(stderr, " %s %.4f;", phases[k], p[2 * kOpCodes + k] * ms_per_tick / ns);
+        for (int k = 6; k < 10; ++k) fprintf(stderr, " %s %.4f;", phases[k], p[2 * kOpCodes + k] * ms_per_tick / ns);
     }
     fprintf(stderr, "\n");
 }

@@ -351,7 +351,8 @@ void make_plan_host(const HTree& hmt, int kmax, Plan& p, bool check) {
     gen_hsolve(p.t, p.sv);
     gen_hsolve_steps(p.t, p.hs);
     validate_hsolve_steps(p.t, p.hs);
-    p.sv_lds = p.hs.ok && p.hs.maxrow <= kHsolveMaxRow;
+    // the LDS H-solve: pipelined steps, leaves of at most 64 rows, at most 64 records a step
+    p.sv_lds = p.hs.ok && p.hs.maxrow <= kHsolveMaxRow && p.hs.maxrec <= 64;
     p.kpmax = lrsub_kprime_max(p.t, p.lu);
     int widest = 0;
     for (const OpRec& o : p.lu.ops)
@@ -426,10 +427,15 @@ void hlu_solve(HLUObj* f, int nrhs, const double* B, int ldb, double* X, int ldx
     if (wc > 0) {
         // right-hand sides in LDS, one workgroup per chunk of wc columns
         const int nchunk = (nrhs + wc - 1) / wc;
-        if (f->prec == FDE_FP64)
-            launch_hsolve_one<double>(st, f->inst<double>(true, nrhs, B, ldb, X, ldx), nchunk, wc, lds);
-        else
-            launch_hsolve_one<float>(st, f->inst<float>(true, nrhs, B, ldb, X, ldx), nchunk, wc, lds);
+        if (f->prec == FDE_FP64) {
+            Inst<double> d = f->inst<double>(true, nrhs, B, ldb, X, ldx);
+            d.hs_wc = wc;
+            launch_hsolve_one<double>(st, d, nchunk, wc, lds);
+        } else {
+            Inst<float> d = f->inst<float>(true, nrhs, B, ldb, X, ldx);
+            d.hs_wc = wc;
+            launch_hsolve_one<float>(st, d, nchunk, wc, lds);
+        }
         return;
     }
     hlu_prepare_solve(f, nrhs);

@@ -54,7 +54,7 @@ constexpr int kMaxKprime = 256;   // widest [U, X] recompressed in one OP_LRSUB
 // OP_LRMV (H-substitutions): Y += alpha U (V^T X) for low-rank block blk, through temporary v[2]
 enum OpCode { OP_GETRF = 1, OP_TRSM = 2, OP_GEMM = 3, OP_LRSUB = 4, OP_ZERO = 5, OP_LOAD = 6, OP_STORE = 7, OP_LRMV = 8 };
 constexpr int kOpCodes = 9;
-constexpr int kProfPhases = 9;             // small recompression phases, then H-solve step phases
+constexpr int kProfPhases = 10;            // small recompression phases, then H-solve step phases
 constexpr int kProfSlots = 2 * kOpCodes + kProfPhases;   // per op code: wall-clock ticks, count; phases
 enum Base { B_ARENA = 0, B_WORK = 1, B_RHS = 2, B_WORK_NRHS = 3 };
 

@@ -3,23 +3,24 @@
 //
 // One workgroup (512 threads, eight wavefronts) solves a chunk of wc right-hand-side
 // columns of one instance. The chunk (Nd x wc), the short vectors t_B of the
-// low-rank blocks in flight, the ranks and one staged diagonal leaf stay in LDS for
+// low-rank blocks in flight, the ranks and the staged diagonal leaves stay in LDS for
 // the whole solve; only factor blocks and the step tables are read from HBM. Step p
 // (host tables, see HsStep):
 //   phase 1, all wavefronts: the chunks of the dense block between leaf p and the
-//     leaf solved just before, into per-wavefront partial sums; the increments
+//     leaf solved just before, into per-wavefront partial sums, and the increments
 //     t_B += V_B(rows of that leaf)^T x of the low-rank blocks whose column cluster
-//     holds it (a wavefront per block, reduced by a butterfly over the lanes); the
-//     solving wavefronts also read the staged diagonal leaf into registers;
+//     holds it (a wavefront per block, reduced by a butterfly over the lanes);
 //   phase 2: wavefront j < wc sums the partials of column j and solves with the
-//     diagonal leaf (row-scaled unit triangular substitution, readlane broadcasts);
+//     staged diagonal leaf (lane = row, readlane broadcasts; the leaf's strict
+//     triangle was staged with zeros elsewhere, so the substitution needs no masks);
 //     the other wavefronts gather every remaining contribution to the next leaf's
-//     rows (dense chunks from older leaves, rows of U_B times t_B) and stage the
-//     next diagonal leaf in LDS.
+//     rows (dense chunks from older leaves, rows of U_B times t_B) and stage the next
+//     diagonal leaf in the other LDS buffer.
 // Two barriers per step. Only the dense chunk of the previous leaf and the triangular
-// solve are on the dependent chain from one leaf to the next; factor values of the
-// next step and step records two steps ahead are loaded while a step runs (vector
-// loads, so the waits for them do not serialise with LDS traffic).
+// solve are on the dependent chain from one leaf to the next. Factor values of the
+// next step, its diagonal leaf and step records two steps ahead are loaded while a
+// step runs, as global (vector-memory) loads issued identically by every wavefront,
+// so the compiler's waits for them are exact and they stay in flight across barriers.
 #include "hinterp.h"
 #include "tri_wave.h"
 
@@ -32,15 +33,19 @@ constexpr int kHW = kHT / 64;
 
 static_assert(sizeof(HsRec) == 32 && sizeof(HsStep) == 32, "H-solve records are loaded as two 16-byte vectors");
 
-// items per wavefront and step whose factor values are loaded a step ahead (register budget),
-// and elements per lane of one batch of the diagonal staging
-template <class T>
+// Items per wavefront and step whose factor values are loaded a step ahead, and columns of the
+// next diagonal leaf per helper loaded a step ahead (the rest are loaded when needed). The
+// loads in flight per wavefront stay within the 63 the vector-memory counter tracks (beyond
+// that the compiler can only wait for all of them): 8 kP1 + 8 kP2 + kD + 4 record loads.
+template <class T, int WC>
 struct HsDepth {
-    static constexpr int kP1 = 2, kP2 = 3, kD = 16;
+    static constexpr int kP1 = 3, kP2 = 3;
+    static constexpr int kD = WC == 1 ? 10 : WC == 2 ? 11 : WC == 4 ? 16 : 10;
 };
-template <>
-struct HsDepth<double> {
-    static constexpr int kP1 = 1, kP2 = 1, kD = 8;
+template <int WC>
+struct HsDepth<double, WC> {
+    static constexpr int kP1 = 2, kP2 = 2;
+    static constexpr int kD = WC == 1 ? 10 : WC == 2 ? 11 : WC == 4 ? 16 : 10;
 };
 
 // global-memory view of a pointer: loads through it are vector-memory loads counted by vmcnt
@@ -54,19 +59,6 @@ __device__ inline const __attribute__((address_space(1))) T* gmem(const T* p) {
 struct Vec8 {
     int a[8];
 };
-
-__device__ inline Vec8 load8(const void* p, bool live) {
-    Vec8 v;
-    if (live) {
-        const auto q = gmem(reinterpret_cast<const int*>(p));
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v.a[i] = q[i];
-    } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v.a[i] = 0;
-    }
-    return v;
-}
 
 struct StepS {
     int64_t diag;
@@ -87,50 +79,32 @@ __device__ inline StepS step_of(const Vec8& v) {
     return s;
 }
 
-__device__ inline Vec8 load_step(const HsStep* steps, int s, int nsteps) { return load8(steps + s, s < nsteps); }
+// 32 bytes loaded by every lane whatever `live` (an invalid entry reads `dummy`, a valid
+// address, and gives zeros): no load sits on a branch
+__device__ inline Vec8 load8_all(const void* p, bool live, const void* dummy) {
+    const auto q = gmem(reinterpret_cast<const int*>(live ? p : dummy));
+    Vec8 v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v.a[i] = q[i];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v.a[i] = live ? v.a[i] : 0;
+    return v;
+}
 
-// lane l holds record rec0 + l of the step (l < its record count, at most 64)
-__device__ inline Vec8 load_recs(const HsRec* recs, const StepS& s, int lane) {
+__device__ inline Vec8 load_step(const HsStep* steps, int s, int nsteps) {
+    return load8_all(steps + min(s, nsteps - 1), s < nsteps, steps);
+}
+
+// lane l holds record rec0 + l of the step (a step has at most 64 records)
+__device__ inline Vec8 load_recs(const HsRec* recs, const StepS& s, int lane, const HsStep* steps) {
     const int n = s.nlate + s.ninc + s.nearly;
-    return load8(recs + s.rec0 + lane, lane < n);
+    return load8_all(recs + s.rec0 + min(lane, max(n - 1, 0)), lane < n, steps);
 }
 
 struct RecS {
     int64_t off;
     int ld, col0, n, slot, tslot, kind;
 };
-
-// record k (wave-uniform) of a step: from the lanes for k < 64, else straight from memory
-__device__ inline RecS rec_of(const Vec8& v, int k, const HsRec* recs, const StepS& s) {
-    int a[8];
-    if (k < 64) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) a[i] = __builtin_amdgcn_readlane(v.a[i], k);
-    } else {
-        const Vec8 w = load8(recs + s.rec0 + k, true);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) a[i] = __builtin_amdgcn_readfirstlane(w.a[i]);
-    }
-    RecS r;
-    r.off = ((int64_t)a[1] << 32) | (unsigned)a[0];
-    r.ld = a[2];
-    r.col0 = a[3];
-    r.n = a[4];
-    r.slot = a[5];
-    r.tslot = a[6];
-    r.kind = a[7];
-    return r;
-}
-
-// kHsChunk columns of a factor block starting at column c0, row = lane (rows and columns clamped
-// into the block, so every load is in bounds and they are all in flight together)
-template <class T>
-__device__ inline void load_cols(T (&v)[kHsChunk], const T* arena, const RecS& r, int rows, int cols, int c0, int lane) {
-    const int li = min(lane, rows - 1), cl = max(cols, 1) - 1;
-    const auto a = gmem(arena + r.off + li);
-#pragma unroll
-    for (int c = 0; c < kHsChunk; ++c) v[c] = a[(int64_t)min(c0 + c, cl) * r.ld];
-}
 
 // lane l ends with the sum over the wavefront of v[(l >> 3) & 7]: each exchange halves the
 // values a lane holds (10 shuffles for 8 sums instead of 48)
@@ -156,25 +130,59 @@ __device__ inline T reduce8(const T (&v)[8], int lane) {
     return s;
 }
 
-// WC: columns of a chunk (1, 2, 4 or 8); the last chunk of a solve may use fewer (wce)
+// fields of record k of a step from the lanes (k < 64, wave-uniform)
+__device__ inline RecS rec_lane(const Vec8& v, int k) {
+    int a[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = __builtin_amdgcn_readlane(v.a[i], k);
+    RecS r;
+    r.off = ((int64_t)a[1] << 32) | (unsigned)a[0];
+    r.ld = a[2];
+    r.col0 = a[3];
+    r.n = a[4];
+    r.slot = a[5];
+    r.tslot = a[6];
+    r.kind = a[7];
+    return r;
+}
+
+// kHsChunk columns of a block at `off` (ld), row = lane, rows and columns clamped
+template <class T>
+__device__ inline void load_block(T (&v)[kHsChunk], const T* arena, int64_t off, int ld, int rows, int cols, int c0,
+                                  int lane) {
+    const int li = min(lane, rows - 1), cl = max(cols, 1) - 1;
+    const auto a = gmem(arena + off + li);
+#pragma unroll
+    for (int c = 0; c < kHsChunk; ++c) v[c] = a[(int64_t)min(c0 + c, cl) * ld];
+}
+
+// One workgroup: chunk c0 / wc of instance d, wc = d.hs_wc <= WC columns (the last chunk may
+// use fewer, wce). Every wavefront issues the same global loads in every step, whatever its
+// role and the number of items (empty slots load a valid dummy address), so the waits the
+// compiler inserts for prefetched values are exact and the prefetches stay in flight across
+// the barriers.
 template <class T, int WC>
-__device__ void hsteps_body(const Inst<T>& d, int c0, int step, char* smem) {
-    using D = HsDepth<T>;
-    constexpr int wc = WC;
-    const int Nd = d.Nd, kmax = d.kmax, nsteps = 2 * d.hs_nleaf;
-    const int wce = min(WC, d.nrhs - c0);
-    if (wce <= 0) return;
+__device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int chunk, int step, char* smem) {
+    using D = HsDepth<T, WC>;
+    const int wc = d.hs_wc;
+    const int c0 = chunk * wc;
+    const int Nd = d.Nd, kmax = d.kmax, nsteps = 2 * d.hs_nleaf, L = d.hs_nleaf;
+    const int wce = min(wc, d.nrhs - c0);
+    if (wce <= 0 || wc > WC) return;
     T* X = reinterpret_cast<T*>(smem);                    // Nd x wc, ld Nd
     T* tb = X + (int64_t)Nd * wc;                          // tslots x kmax x wc
     T* part1 = tb + (int64_t)d.hs_tslots * kmax * wc;      // kHW x 64 x wc (phase 1 partial sums)
     T* part2 = part1 + kHT * wc;                           // 2 x kHW x 64 x wc (early sums, by step parity)
-    T* Dg = part2 + 2 * kHT * wc;                          // staged diagonal leaf, ld kHsolveMaxRow
-    int* rk = reinterpret_cast<int*>(Dg + kHsolveMaxRow * kHsolveMaxRow);
+    // staged diagonal leaf (64 x 64, ld 64) and its diagonal entries, two buffers by step parity:
+    // the solve of step s reads buffer s & 1 while the helpers stage step s + 1 in the other
+    T* Dg2 = part2 + 2 * kHT * wc;
+    T* Dd2 = Dg2 + 2 * kHsolveMaxRow * kHsolveMaxRow;
+    int* rk = reinterpret_cast<int*>(Dd2 + 2 * kHsolveMaxRow);
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // phase 2 roles: waves [0, wce) solve; helpers h0 .. h0 + nh - 1 gather for the next leaf
+    // phase 2 roles: waves [0, wce) solve; helpers h0 .. 7 gather for the next leaf and stage
     const int h0 = wc < kHW ? wc : 0, nh = kHW - h0;
     const bool helper = wave >= h0;
-    const int hw = wave - h0;
+    const int hw = helper ? wave - h0 : 0;
     const T* arena = d.arena;
     const HsStep* steps = d.hs_steps;
     const HsRec* recs = d.hs_recs;
@@ -189,226 +197,287 @@ __device__ void hsteps_body(const Inst<T>& d, int c0, int step, char* smem) {
     StepS S0 = step_of(load_step(steps, 0, nsteps));
     StepS S1 = step_of(load_step(steps, 1, nsteps));
     StepS S2 = step_of(load_step(steps, 2, nsteps));
-    Vec8 R0 = load_recs(recs, S0, lane), R1 = load_recs(recs, S1, lane), R2;
-    // the diagonal of step 0 (column c of the leaf at Dg + c * kHsolveMaxRow)
-    for (int c = wave; c < S0.nrow; c += kHW)
-        if (lane < S0.nrow) Dg[lane + c * kHsolveMaxRow] = gmem(arena)[S0.diag + lane + (int64_t)c * S0.nrow];
-    __syncthreads();   // ranks in LDS before the prefetches read them
-    T av1[D::kP1][kHsChunk], av2[D::kP2][kHsChunk];
-    // factor values of this wavefront's first phase-1 items of step S (late chunks: rows of S's
-    // leaf; increments: rows of the previous leaf, columns up to the rank)
+    Vec8 R0 = load_recs(recs, S0, lane, steps), R1 = load_recs(recs, S1, lane, steps), R2;
+    // the staged leaf of a step: the strict lower (forward) or upper (backward) triangle, zero
+    // elsewhere and in the rows and columns beyond the leaf, so the substitution needs no masks;
+    // backward steps also keep the diagonal in Dd
+    auto stage = [&](T v, int c, int nd, bool fwdst, int buf) {
+        int ln = lane;   // opaque: the per-column masks are not hoisted out of the step loop
+        asm volatile("" : "+v"(ln));
+        const bool in = ln < nd && c < nd;
+        T* Dg = Dg2 + buf * kHsolveMaxRow * kHsolveMaxRow;
+        Dg[ln + c * kHsolveMaxRow] = (in && (fwdst ? c < ln : c > ln)) ? v : T(0);
+        if (c == ln) Dd2[buf * kHsolveMaxRow + ln] = in ? v : T(1);
+    };
+    for (int c = wave; c < kHsolveMaxRow; c += kHW) {
+        const bool in = lane < S0.nrow && c < S0.nrow;
+        stage(in ? gmem(arena)[S0.diag + lane + (int64_t)c * S0.nrow] : T(0), c, S0.nrow, 0 < L, 0);
+    }
+    __syncthreads();   // ranks and the first leaf in LDS
+    T av1[D::kP1][kHsChunk], av2[D::kP2][kHsChunk], dv[D::kD];
+    // phase-1 values of step S: wavefront w takes items w, w + 8, ... (late chunks: rows of S's
+    // leaf; increments: rows of the leaf before, columns up to the rank)
     auto prefetch1 = [&](const StepS& S, const Vec8& R) {
+        const int np = S.nlate + S.ninc;
 #pragma unroll
         for (int i = 0; i < D::kP1; ++i) {
             const int k = wave + kHW * i;
-            if (k < S.nlate + S.ninc) {
-                const RecS r = rec_of(R, k, recs, S);
-                if (k < S.nlate) load_cols(av1[i], arena, r, S.nrow, r.n, 0, lane);
-                else load_cols(av1[i], arena, r, r.n, rk[r.slot], 0, lane);
-            }
+            const bool live = k < np;
+            const RecS r = rec_lane(R, min(k, 63));
+            const bool late = k < S.nlate;
+            const int cols = late ? r.n : rk[live && !late ? r.slot : 0];
+            load_block(av1[i], arena, live ? r.off : 0, live ? r.ld : 0, live ? (late ? S.nrow : r.n) : 1,
+                       live ? cols : 1, 0, lane);
         }
     };
-    // early items go to kHW partial-sum slots (item e to slot e % kHW), whatever the number of
-    // helpers, so the order of every sum is the same for every chunk width; helper hw takes
-    // slots hw, hw + nh, ... and their items in that order
+    // early values of step S (rows of the next leaf, `rows`): helper hw takes items hw, hw + nh, ...
     auto prefetch2 = [&](const StepS& S, const Vec8& R, int rows) {
-        if (!helper) return;
-        int i = 0;
-        for (int v = hw; v < min(kHW, S.nearly) && i < D::kP2; v += nh)
-            for (int e = v; e < S.nearly && i < D::kP2; e += kHW, ++i) {
-                const RecS r = rec_of(R, S.nlate + S.ninc + e, recs, S);
+        const int base = S.nlate + S.ninc;
 #pragma unroll
-                for (int i2 = 0; i2 < D::kP2; ++i2)
-                    if (i2 == i) load_cols(av2[i2], arena, r, rows, r.kind == HS_DENSE ? r.n : rk[r.slot], 0, lane);
-            }
+        for (int i = 0; i < D::kP2; ++i) {
+            const int e = hw + nh * i;
+            const bool live = helper && e < S.nearly;
+            const RecS r = rec_lane(R, min(base + e, 63));
+            const int cols = r.kind == HS_DENSE ? r.n : rk[live && r.kind != HS_DENSE ? r.slot : 0];
+            load_block(av2[i], arena, live ? r.off : 0, live ? r.ld : 0, live ? rows : 1, live ? cols : 1, 0, lane);
+        }
+    };
+    // leaf of step S staged by the helpers, helper hw taking columns hw, hw + nh, ...
+    auto prefetch_diag = [&](const StepS& S) {
+#pragma unroll
+        for (int q = 0; q < D::kD; ++q) {
+            const int c = hw + q * nh;
+            const bool live = helper && lane < S.nrow && c < S.nrow;
+            dv[q] = gmem(arena)[live ? S.diag + lane + (int64_t)c * S.nrow : 0];
+        }
     };
     prefetch1(S0, R0);
     prefetch2(S0, R0, S1.nrow);
+    prefetch_diag(S1);
+    // op profile: step phases timed by thread 0 and the first helper's lane 0, added to the
+    // profile once after the loop (no atomics in the loop: a pending flat atomic makes every
+    // later wait for a prefetched value a wait for all loads)
     unsigned long long tph = (d.prof && threadIdx.x == 0) ? wall_clock64() : 0ull;
-    auto phase = [&](int k) {   // op profile: step phases (thread 0); TRSM counts the steps
+    unsigned long long pt[4] = {0ull, 0ull, 0ull, 0ull};
+    auto phase = [&](int k) {
         if (d.prof && threadIdx.x == 0) {
             const unsigned long long t = wall_clock64();
-            atomicAdd(&d.prof[2 * kOpCodes + k], t - tph);
-            if (k == 7) atomicAdd(&d.prof[2 * OP_TRSM + 1], 1ull);
+            pt[k - 6] += t - tph;
             tph = t;
         }
     };
     int nearly_prev = 0;   // early items gathered for this step's leaf in the step before
-    T tr[kHsolveMaxRow];
     T dinv = T(1);
+    Vec8 S3v;
     for (int s = 0; s < nsteps; ++s) {
-        const bool fwd = s < d.hs_nleaf;
-        const Vec8 S3v = load_step(steps, s + 3, nsteps);
+        const bool fwd = s < L;
         // ---------------- phase 1
         const int n = S0.nrow;
-        if (wave < wce) {
-            // the lane's row, divided by its diagonal entry going backward (unit triangular
-            // system); columns c >= n are stale and never used
-            const int li = min(lane, n - 1);
-            dinv = fwd ? T(1) : T(1) / Dg[li + li * kHsolveMaxRow];
-#pragma unroll
-            for (int c = 0; c < kHsolveMaxRow; ++c) tr[c] = Dg[li + c * kHsolveMaxRow] * dinv;
-        }
+        if (wave < wce) dinv = fwd ? T(1) : T(1) / Dd2[(s & 1) * kHsolveMaxRow + lane];   // backward: row / diagonal
         {
-            T acc[wc];
+            T acc[WC];
 #pragma unroll
-            for (int j = 0; j < wc; ++j) acc[j] = T(0);
+            for (int j = 0; j < WC; ++j) acc[j] = T(0);
             const int np1 = S0.nlate + S0.ninc;
-            for (int k = wave, i = 0; k < np1; k += kHW, ++i) {
-                const RecS r = rec_of(R0, k, recs, S0);
-                T vv[kHsChunk];
-                if (i < D::kP1) {
+            // t_B (+)= V_B(rows of the leaf before, columns cb..cb+7)^T x of that leaf
+            auto inc_chunk = [&](const RecS& r, const T (&vv)[kHsChunk], int cb) {
+                const int rank = rk[r.slot], m = r.n;
+                T* t = tb + (int64_t)r.tslot * kmax * wc;
+                const bool first = r.kind == HS_INC_FIRST;
 #pragma unroll
-                    for (int i2 = 0; i2 < D::kP1; ++i2)
-                        if (i2 == i)
+                for (int j = 0; j < WC; ++j) {
+                    if (j >= wc) break;
+                    const T xj = lane < m ? X[r.col0 + lane + (int64_t)j * Nd] : T(0);
+                    T pr[kHsChunk];
 #pragma unroll
-                            for (int c = 0; c < kHsChunk; ++c) vv[c] = av1[i2][c];
-                } else if (k < S0.nlate) {
-                    load_cols(vv, arena, r, n, r.n, 0, lane);
-                } else {
-                    load_cols(vv, arena, r, r.n, rk[r.slot], 0, lane);
+                    for (int c = 0; c < kHsChunk; ++c) pr[c] = cb + c < rank ? vv[c] * xj : T(0);
+                    const T sum = reduce8(pr, lane);
+                    const int c = cb + ((lane >> 3) & 7);
+                    if ((lane & 7) == 0 && c < rank) {
+                        T* tc = t + (int64_t)c * wc + j;
+                        *tc = first ? sum : *tc + sum;
+                    }
                 }
+            };
+            // one item of phase 1 with its first kHsChunk columns in vv (no load in here)
+            auto p1_item = [&](int k, const T (&vv)[kHsChunk]) {
+                const RecS r = rec_lane(R0, k);
                 if (k < S0.nlate) {
                     // late chunk: rows of this leaf times entries of the leaf solved just before
-                    if (lane == 0) flops += 2.0 * n * r.n * wc;
+                    if (lane == 0) flops += 2.0 * n * r.n * wce;
 #pragma unroll
                     for (int c = 0; c < kHsChunk; ++c)
                         if (c < r.n)
 #pragma unroll
-                            for (int j = 0; j < wc; ++j) acc[j] += vv[c] * X[r.col0 + c + (int64_t)j * Nd];
+                            for (int j = 0; j < WC; ++j)
+                                if (j < wc) acc[j] += vv[c] * X[r.col0 + c + (int64_t)j * Nd];
                 } else {
                     // increment of t_B by the rows of the leaf solved just before
-                    const int rank = rk[r.slot], m = r.n;
-                    if (lane == 0) flops += 2.0 * m * rank * wc;
-                    T* t = tb + (int64_t)r.tslot * kmax * wc;
-                    const bool first = r.kind == HS_INC_FIRST;
-                    for (int cb = 0; cb < rank; cb += kHsChunk) {
-                        if (cb > 0) load_cols(vv, arena, r, m, rank, cb, lane);
+                    if (lane == 0) flops += 2.0 * r.n * rk[r.slot] * wce;
+                    inc_chunk(r, vv, 0);
+                }
+            };
+            // the prefetched items (static register indices, no load before their use) ...
 #pragma unroll
-                        for (int j = 0; j < wc; ++j) {
-                            const T xj = lane < m ? X[r.col0 + lane + (int64_t)j * Nd] : T(0);
-                            T pr[kHsChunk];
-#pragma unroll
-                            for (int c = 0; c < kHsChunk; ++c) pr[c] = cb + c < rank ? vv[c] * xj : T(0);
-                            const T sum = reduce8(pr, lane);
-                            const int c = cb + ((lane >> 3) & 7);
-                            if ((lane & 7) == 0 && c < rank) {
-                                T* tc = t + (int64_t)c * wc + j;
-                                *tc = first ? sum : *tc + sum;
-                            }
-                        }
-                    }
+            for (int i = 0; i < D::kP1; ++i) {
+                const int k = wave + kHW * i;
+                if (k < np1) p1_item(k, av1[i]);
+            }
+            // ... then, rarely, items beyond the prefetch depth and columns of ranks above kHsChunk
+            for (int k = wave + kHW * D::kP1; k < np1; k += kHW) {
+                const RecS r = rec_lane(R0, k);
+                T vv[kHsChunk];
+                if (k < S0.nlate) load_block(vv, arena, r.off, r.ld, n, r.n, 0, lane);
+                else load_block(vv, arena, r.off, r.ld, r.n, rk[r.slot], 0, lane);
+                p1_item(k, vv);
+            }
+            for (int k = wave; k < np1; k += kHW) {
+                if (k < S0.nlate) continue;
+                const RecS r = rec_lane(R0, k);
+                const int rank = rk[r.slot];
+                for (int cb = kHsChunk; cb < rank; cb += kHsChunk) {
+                    T vv[kHsChunk];
+                    load_block(vv, arena, r.off, r.ld, r.n, rank, cb, lane);
+                    inc_chunk(r, vv, cb);
                 }
             }
             if (wave < S0.nlate) {
 #pragma unroll
-                for (int j = 0; j < wc; ++j) part1[(wave * 64 + lane) * wc + j] = acc[j];
+                for (int j = 0; j < WC; ++j)
+                    if (j < wc) part1[(wave * 64 + lane) * wc + j] = acc[j];
             }
         }
-        // the next step's phase-1 values; the records two steps ahead
+        // the next step's phase-1 values, the records two steps ahead, the step after those
         prefetch1(S1, R1);
-        R2 = load_recs(recs, S2, lane);
+        R2 = load_recs(recs, S2, lane, steps);
+        S3v = load_step(steps, s + 3, nsteps);
         __syncthreads();
         phase(6);
         // ---------------- phase 2
         if (wave < wce) {
             // solve: y = b - late partials - early partials; T^{-1} y with the leaf in registers
             const int j = wave;
-            const bool act = lane < n;
-            T y = act ? X[S0.row0 + lane + (int64_t)j * Nd] : T(0);
-            const int nw1 = min(kHW, S0.nlate), nw2 = min(kHW, nearly_prev);
+            T y = lane < n ? X[S0.row0 + lane + (int64_t)j * Nd] : T(0);
+            const int nw1 = min(kHW, S0.nlate), nw2 = min(nh, nearly_prev);
             const T* p2 = part2 + (s & 1) * kHT * wc;
             for (int w = 0; w < nw1; ++w) y -= part1[(w * 64 + lane) * wc + j];
             for (int h = 0; h < nw2; ++h) y -= p2[(h * 64 + lane) * wc + j];
             if (lane == 0) flops += (double)n * n;
-            T x = act ? y * dinv : T(0);
-            // an opaque copy of the lane index: the 64 per-column lane masks below are then formed
-            // where they are used instead of being hoisted out of the step loop (64 mask pairs
-            // held in scalar registers across the loop would spill)
-            int ln = lane;
-            asm volatile("" : "+v"(ln));
+            T x = y * dinv;
+            // the staged triangle is zero outside the leaf, so blocks of 8 columns up to n need no
+            // masks; the lane's row is read from LDS a block ahead of the substitution
+            const T* drow = Dg2 + (s & 1) * kHsolveMaxRow * kHsolveMaxRow + lane;
+            T cur[8], nxt[8];
             if (fwd) {
 #pragma unroll
-                for (int c = 0; c < kHsolveMaxRow; ++c) {
-                    if (c < n) {
-                        const T xs = lane_bcast(x, c);
-                        if (ln > c) x -= tr[c] * xs;
-                    }
+                for (int i = 0; i < 8; ++i) cur[i] = drow[i * kHsolveMaxRow];
+#pragma unroll
+                for (int cb = 0; cb < kHsolveMaxRow; cb += 8) {
+                    if (cb >= n) break;
+                    if (cb + 8 < kHsolveMaxRow)
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) nxt[i] = drow[(cb + 8 + i) * kHsolveMaxRow];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) x -= cur[i] * lane_bcast(x, cb + i);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) cur[i] = nxt[i];
                 }
             } else {
+                const int top = ((n - 1) / 8) * 8;   // first block holding a column < n
 #pragma unroll
-                for (int c = kHsolveMaxRow - 1; c >= 0; --c) {
-                    if (c < n) {
-                        const T xs = lane_bcast(x, c);
-                        if (ln < c) x -= tr[c] * xs;
-                    }
+                for (int i = 0; i < 8; ++i) cur[i] = drow[(top + i) * kHsolveMaxRow] * dinv;
+                for (int cb = top; cb >= 0; cb -= 8) {
+                    if (cb >= 8)
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) nxt[i] = drow[(cb - 8 + i) * kHsolveMaxRow] * dinv;
+#pragma unroll
+                    for (int i = 7; i >= 0; --i) x -= cur[i] * lane_bcast(x, cb + i);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) cur[i] = nxt[i];
                 }
             }
-            if (act) X[S0.row0 + lane + (int64_t)j * Nd] = x;
+            if (lane < n) X[S0.row0 + lane + (int64_t)j * Nd] = x;
+            phase(8);   // thread 0 (a solving wavefront): the triangular solve done
         }
         if (helper) {
-            // stage the next diagonal leaf, helper hw taking columns hw, hw + nh, ...; the first
-            // batch is in flight during the gather below
-            const int nd = S1.nrow;
-            const bool rowok = lane < nd;
-            T dv[D::kD];
+            const unsigned long long th0 = (d.prof && lane == 0 && hw == 0) ? wall_clock64() : 0ull;
+            // the next leaf into LDS (loaded a step ago)
+            const bool fwd1 = s + 1 < L;
 #pragma unroll
             for (int q = 0; q < D::kD; ++q) {
                 const int c = hw + q * nh;
-                dv[q] = (rowok && c < nd) ? gmem(arena)[S1.diag + lane + (int64_t)c * nd] : T(0);
+                if (c < kHsolveMaxRow) stage(dv[q], c, S1.nrow, fwd1, (s + 1) & 1);
             }
             // early items: contributions to the next leaf's rows from leaves before this one
-            const int m = S1.nrow;
-            int i = 0;
-            for (int v = hw; v < min(kHW, S0.nearly); v += nh) {
-                T acc[wc];
+            const int m = S1.nrow, base = S0.nlate + S0.ninc;
+            if (hw < S0.nearly) {
+                T acc[WC];
 #pragma unroll
-                for (int j = 0; j < wc; ++j) acc[j] = T(0);
-                for (int e = v; e < S0.nearly; e += kHW, ++i) {
-                    const RecS r = rec_of(R0, S0.nlate + S0.ninc + e, recs, S0);
-                    const int cols = r.kind == HS_DENSE ? r.n : rk[r.slot];
-                    if (lane == 0) flops += 2.0 * m * cols * wc;
-                    const T* t = tb + (int64_t)r.tslot * kmax * wc;
-                    for (int cb = 0; cb < cols; cb += kHsChunk) {
+                for (int j = 0; j < WC; ++j) acc[j] = T(0);
+                // columns cb..cb+7 of an early item (dense chunk, or U_B rows times t_B)
+                auto p2_chunk = [&](const RecS& r, const T (&vv)[kHsChunk], int cb, int cols) {
+                    if (r.kind == HS_DENSE) {
+#pragma unroll
+                        for (int c = 0; c < kHsChunk; ++c)
+                            if (c < cols)
+#pragma unroll
+                                for (int j = 0; j < WC; ++j)
+                                    if (j < wc) acc[j] += vv[c] * X[r.col0 + c + (int64_t)j * Nd];
+                    } else {
+                        const T* t = tb + (int64_t)r.tslot * kmax * wc;
+#pragma unroll
+                        for (int c = 0; c < kHsChunk; ++c)
+                            if (cb + c < cols)
+#pragma unroll
+                                for (int j = 0; j < WC; ++j)
+                                    if (j < wc) acc[j] += vv[c] * t[(cb + c) * wc + j];
+                    }
+                };
+                auto cols_of = [&](const RecS& r) { return r.kind == HS_DENSE ? r.n : rk[r.slot]; };
+                // the prefetched items first (no load before their use) ...
+#pragma unroll
+                for (int i = 0; i < D::kP2; ++i) {
+                    const int e = hw + nh * i;
+                    if (e < S0.nearly) {
+                        const RecS r = rec_lane(R0, base + e);
+                        const int cols = cols_of(r);
+                        if (lane == 0) flops += 2.0 * m * cols * wce;
+                        p2_chunk(r, av2[i], 0, cols);
+                    }
+                }
+                // ... then, rarely, items beyond the prefetch depth and ranks above kHsChunk
+                for (int e = hw + nh * D::kP2; e < S0.nearly; e += nh) {
+                    const RecS r = rec_lane(R0, base + e);
+                    const int cols = cols_of(r);
+                    if (lane == 0) flops += 2.0 * m * cols * wce;
+                    T vv[kHsChunk];
+                    load_block(vv, arena, r.off, r.ld, m, cols, 0, lane);
+                    p2_chunk(r, vv, 0, cols);
+                }
+                for (int e = hw; e < S0.nearly; e += nh) {
+                    const RecS r = rec_lane(R0, base + e);
+                    const int cols = cols_of(r);
+                    for (int cb = kHsChunk; cb < cols; cb += kHsChunk) {
                         T vv[kHsChunk];
-                        if (cb == 0 && i < D::kP2) {
-#pragma unroll
-                            for (int i2 = 0; i2 < D::kP2; ++i2)
-                                if (i2 == i)
-#pragma unroll
-                                    for (int c = 0; c < kHsChunk; ++c) vv[c] = av2[i2][c];
-                        } else {
-                            load_cols(vv, arena, r, m, cols, cb, lane);
-                        }
-                        if (r.kind == HS_DENSE) {
-#pragma unroll
-                            for (int c = 0; c < kHsChunk; ++c)
-                                if (c < cols)
-#pragma unroll
-                                    for (int j = 0; j < wc; ++j) acc[j] += vv[c] * X[r.col0 + c + (int64_t)j * Nd];
-                        } else {
-#pragma unroll
-                            for (int c = 0; c < kHsChunk; ++c)
-                                if (cb + c < cols)
-#pragma unroll
-                                    for (int j = 0; j < wc; ++j) acc[j] += vv[c] * t[(cb + c) * wc + j];
-                        }
+                        load_block(vv, arena, r.off, r.ld, m, cols, cb, lane);
+                        p2_chunk(r, vv, cb, cols);
                     }
                 }
                 T* p2 = part2 + ((s + 1) & 1) * kHT * wc;
 #pragma unroll
-                for (int j = 0; j < wc; ++j) p2[(v * 64 + lane) * wc + j] = acc[j];
+                for (int j = 0; j < WC; ++j)
+                    if (j < wc) p2[(hw * 64 + lane) * wc + j] = acc[j];
             }
-            // the next step's early values (rows of the leaf after next)
-            prefetch2(S1, R1, S2.nrow);
-#pragma unroll
-            for (int q = 0; q < D::kD; ++q) {
-                const int c = hw + q * nh;
-                if (rowok && c < nd) Dg[lane + c * kHsolveMaxRow] = dv[q];
+            // columns of the next leaf beyond the prefetch depth (chunks of several columns)
+            for (int c = hw + D::kD * nh; c < kHsolveMaxRow; c += nh) {
+                const bool in = lane < S1.nrow && c < S1.nrow;
+                stage(in ? gmem(arena)[S1.diag + lane + (int64_t)c * S1.nrow] : T(0), c, S1.nrow, fwd1, (s + 1) & 1);
             }
-            for (int c = hw + D::kD * nh; c < nd; c += nh)
-                if (rowok) Dg[lane + c * kHsolveMaxRow] = gmem(arena)[S1.diag + lane + (int64_t)c * nd];
+            if (d.prof && lane == 0 && hw == 0) pt[3] += wall_clock64() - th0;   // the first helper
         }
+        // every wavefront: the leaf after next, the next step's early values
+        prefetch_diag(S2);
+        prefetch2(S1, R1, S2.nrow);
         __syncthreads();
         phase(7);
         nearly_prev = S0.nearly;
@@ -423,6 +492,11 @@ __device__ void hsteps_body(const Inst<T>& d, int c0, int step, char* smem) {
         Xs[(int64_t)j * d.ldx + d.h2p[h]] = (double)X[idx];
     }
     if (lane == 0) atomicAdd(d.flops, flops);
+    if (d.prof && (threadIdx.x == 0 || (lane == 0 && helper && hw == 0))) {
+        for (int k = 0; k < 4; ++k)
+            if (pt[k]) atomicAdd(&d.prof[2 * kOpCodes + 6 + k], pt[k]);
+        if (threadIdx.x == 0) atomicAdd(&d.prof[2 * OP_TRSM + 1], (unsigned long long)nsteps);
+    }
 }
 
 template <class T, int WC>
@@ -430,13 +504,13 @@ __global__ void __launch_bounds__(kHT) k_hsolve(const Inst<T>* __restrict__ inst
     extern __shared__ __align__(16) char smem[];
     const int i = blockIdx.x / nchunk, c = blockIdx.x % nchunk;
     const Inst<T> d = insts[i];
-    hsteps_body<T, WC>(d, c * WC, step, smem);
+    hsteps_body<T, WC>(d, c, step, smem);
 }
 
 template <class T, int WC>
 __global__ void __launch_bounds__(kHT) k_hsolve_one(const Inst<T> d) {
     extern __shared__ __align__(16) char smem[];
-    hsteps_body<T, WC>(d, blockIdx.x * WC, 0, smem);
+    hsteps_body<T, WC>(d, blockIdx.x, 0, smem);
 }
 
 template <class K>
@@ -449,8 +523,8 @@ void allow_lds(K kernel, size_t bytes) {
 }  // namespace
 
 size_t hsolve_lds_bytes(int Nd, int tslots, int kmax, int nslots, int wc, size_t esz) {
-    return ((size_t)Nd + (size_t)tslots * kmax + 3 * kHT) * wc * esz + (size_t)kHsolveMaxRow * kHsolveMaxRow * esz +
-           (size_t)nslots * sizeof(int) + 16;
+    return ((size_t)Nd + (size_t)tslots * kmax + 3 * kHT) * wc * esz +
+           2 * (size_t)(kHsolveMaxRow + 1) * kHsolveMaxRow * esz + (size_t)nslots * sizeof(int) + 16;
 }
 
 size_t device_lds_limit(int device) {

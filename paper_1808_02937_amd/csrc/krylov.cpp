@@ -86,6 +86,11 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
     std::vector<int> mask(ns, 0);
     std::vector<Inst<float>> i32;
     std::vector<Inst<double>> i64;
+    struct HsLaunch {
+        bool lds = true;
+        int wc = 1, nchunk = 1;
+        size_t bytes = 0;
+    } hs32, hs64;
     for (auto& g : groups) {
         if (g.nr == 0) continue;
         const int64_t bs = (int64_t)g.op->Nd * g.nr;
@@ -112,10 +117,26 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
         if (g.prec) {
             g.rhs.alloc(c, bs * g.prec->esz);
             g.work.alloc(c, std::max<int64_t>(g.prec->plan->sv.work_elems, 1) * g.nr * g.prec->esz);
-            if (g.prec->prec == FDE_FP64)
+            // LDS H-solve: each system with its own chunk width (as when solved alone); a launch per
+            // precision sized for the largest; any system that does not fit sends its precision
+            // to the global-memory interpreter
+            HsLaunch& h = g.prec->prec == FDE_FP64 ? hs64 : hs32;
+            size_t b = 0;
+            const int w = hsolve_cols(c, g.prec, g.nr, &b);
+            if (w == 0) {
+                h.lds = false;
+            } else {
+                h.wc = std::max(h.wc, w);
+                h.nchunk = std::max(h.nchunk, (g.nr + w - 1) / w);
+                h.bytes = std::max(h.bytes, b);
+            }
+            if (g.prec->prec == FDE_FP64) {
                 i64.push_back(group_inst<double>(g, m));
-            else
+                i64.back().hs_wc = w;
+            } else {
                 i32.push_back(group_inst<float>(g, m));
+                i32.back().hs_wc = w;
+            }
         }
     }
     DevBuf<SysDev> d_sys;
@@ -138,32 +159,6 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
         FDE_HIP(hipMemcpyAsync(d_i64.p, i64.data(), i64.size() * sizeof(Inst<double>), hipMemcpyHostToDevice, st));
     }
     const bool any_copy = std::any_of(mask.begin(), mask.end(), [](int v) { return v != 0; });
-    // LDS H-solve: one launch per precision, columns in chunks of a common width; the LDS size
-    // is that of the largest system; any group that does not fit sends its precision to the
-    // global-memory interpreter
-    struct HsLaunch {
-        bool lds = true;
-        int wc = kHsolveMaxCols, nchunk = 1;
-        size_t bytes = 0;
-    } hs32, hs64;
-    for (auto& g : groups) {
-        if (!g.nr || !g.prec) continue;
-        HsLaunch& h = g.prec->prec == FDE_FP64 ? hs64 : hs32;
-        size_t b = 0;
-        const int w = hsolve_cols(c, g.prec, g.nr, &b);
-        if (w == 0) h.lds = false;
-        else h.wc = std::min(h.wc, w);
-    }
-    for (HsLaunch* h : {&hs32, &hs64}) {
-        if (!h->lds) continue;
-        for (auto& g : groups) {
-            if (!g.nr || !g.prec || (g.prec->prec == FDE_FP64) != (h == &hs64)) continue;
-            h->nchunk = std::max(h->nchunk, (g.nr + h->wc - 1) / h->wc);
-            const Plan& P = *g.prec->plan;
-            h->bytes = std::max(h->bytes, hsolve_lds_bytes(g.op->Nd, P.hs.tslots, g.prec->kmax, P.t.nslots, h->wc, g.prec->esz));
-        }
-        if (!c->lds_limit || h->bytes > c->lds_limit) h->lds = false;
-    }
     fg_gnorm(st, ns, d_sys.p, d_ss.p);
     fg_zero_x(st, ns, d_sys.p);
     std::vector<SysState> hs(ns);
