@@ -90,11 +90,18 @@ typedef double (*fde_fn)(double x, void* user);
 /* ---- context ------------------------------------------------------------ */
 
 /* device: HIP ordinal. hip_stream: a hipStream_t (e.g. torch's current stream)
- * or NULL for the null stream. hbm_budget_bytes: 0 = no limit beyond the device. */
+ * or NULL for the null stream. hbm_budget_bytes: 0 = no limit beyond the device.
+ * The context keeps device blocks its objects free and hands them to later
+ * requests (stream-ordered: all library work is queued on the context stream);
+ * those cached bytes count against the budget and are returned to the device
+ * first when a request would exceed it, and when the context is destroyed.
+ * Destroy every object of a context before the context. */
 int  fde_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, fde_ctx** out);
 void fde_ctx_destroy(fde_ctx* ctx);
+/* switch the context to another stream (waits for the work queued on the old one) */
 int  fde_ctx_set_stream(fde_ctx* ctx, void* hip_stream);
-/* bytes of device memory the context's objects currently hold */
+/* bytes of device memory the context's live objects currently hold (rounded up
+ * to the allocator's block sizes; cached free blocks are not counted) */
 size_t fde_ctx_bytes_in_use(const fde_ctx* ctx);
 
 /* ---- operator (Section 2.2) ------------------------------------------- */

@@ -35,24 +35,75 @@ void fail(int code, const char* fmt, ...) {
 
 const char* last_error_cstr() { return g_last_error.c_str(); }
 
+namespace {
+
+// block sizes: multiples of 256 bytes up to 64 KiB, then of 1/8 of the power of two below
+size_t block_size(size_t bytes) {
+    if (bytes <= 65536) return (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+    size_t p = 65536;
+    while (p * 2 <= bytes) p *= 2;
+    const size_t g = p / 8;
+    return (bytes + g - 1) / g * g;
+}
+
+void release_pool(Ctx* c) {
+    if (c->pool.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->pool) (void)hipFree(kv.second);
+    c->pool.clear();
+    c->pooled = 0;
+}
+
+constexpr size_t kPoolCap = size_t(8) << 30;   // cached bytes kept at most
+
+}  // namespace
+
+Ctx::~Ctx() { release_pool(this); }
+
 void* dev_alloc(Ctx* c, size_t bytes) {
-    if (c->budget && c->in_use + bytes > c->budget)
-        fail(FDE_ENOMEM, "HBM budget exceeded: %zu bytes in use + %zu requested > budget %zu", c->in_use,
-             bytes, c->budget);
+    const size_t sz = block_size(bytes);
+    // a cached block of this size class or at most twice as large
+    auto it = c->pool.lower_bound(sz);
+    if (it != c->pool.end() && it->first <= 2 * sz) {
+        void* p = it->second;
+        const size_t have = it->first;
+        if (!(c->budget && c->in_use + have > c->budget)) {
+            c->pool.erase(it);
+            c->pooled -= have;
+            c->in_use += have;
+            c->live[p] = have;
+            return p;
+        }
+    }
+    if (c->budget && c->in_use + sz > c->budget)
+        fail(FDE_ENOMEM, "HBM budget exceeded: %zu bytes in use + %zu requested > budget %zu", c->in_use, sz,
+             c->budget);
+    if (c->budget && c->in_use + c->pooled + sz > c->budget) release_pool(c);
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess && !c->pool.empty()) {   // the device is full of cached blocks: return them, retry
+        (void)hipGetLastError();
+        release_pool(c);
+        e = hipMalloc(&p, sz);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        fail(FDE_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        fail(FDE_ENOMEM, "hipMalloc(%zu) failed: %s", sz, hipGetErrorString(e));
     }
-    c->in_use += bytes;
+    c->in_use += sz;
+    c->live[p] = sz;
     return p;
 }
 
 void dev_free(Ctx* c, void* p, size_t bytes) {
     if (!p) return;
-    (void)hipFree(p);
-    if (c) c->in_use = bytes > c->in_use ? 0 : c->in_use - bytes;
+    auto it = c->live.find(p);
+    const size_t sz = it != c->live.end() ? it->second : block_size(bytes);
+    if (it != c->live.end()) c->live.erase(it);
+    c->in_use = sz > c->in_use ? 0 : c->in_use - sz;
+    c->pool.emplace(sz, p);
+    c->pooled += sz;
+    if (c->pooled > kPoolCap) release_pool(c);
 }
 
 void upload(Ctx* c, void* dst, const void* src, size_t bytes) {
@@ -392,6 +443,8 @@ void fde_ctx_destroy(fde_ctx* c) {
 int fde_ctx_set_stream(fde_ctx* c, void* s) {
     FDE_API_BEGIN
     if (!c) fail(FDE_EINVAL, "null context");
+    // cached blocks may still be in use by work queued on the old stream
+    FDE_HIP(hipStreamSynchronize(c->stream));
     c->stream = static_cast<hipStream_t>(s);
     FDE_API_END
 }

@@ -3,6 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <unordered_map>
+
 #include <cstdarg>
 #include <cstdint>
 #include <memory>
@@ -101,7 +104,14 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     size_t budget = 0;   // 0: unlimited
-    size_t in_use = 0;
+    size_t in_use = 0;   // bytes of live blocks
+    // Stream-ordered cache of device blocks: a block freed by the library is kept and handed to
+    // a later request on the same stream (work queued on one stream runs in order, so no wait is
+    // needed). Cached bytes count against the budget and are released first when it is tight.
+    std::multimap<size_t, void*> pool;    // free blocks by size
+    std::unordered_map<void*, size_t> live;
+    size_t pooled = 0;
+    ~Ctx();
     DevBuf<double> gl;   // Gauss-Legendre n=1..kMaxGL: nodes then weights, offset n(n-1)/2
     size_t lds_limit = 0;   // largest dynamic LDS of one workgroup (bytes)
     // most recently used plans first, keyed by the structure they were made for
