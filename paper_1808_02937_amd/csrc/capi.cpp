@@ -58,7 +58,25 @@ constexpr size_t kPoolCap = size_t(8) << 30;   // cached bytes kept at most
 
 }  // namespace
 
-Ctx::~Ctx() { release_pool(this); }
+constexpr size_t kStageBytes = size_t(32) << 20;   // pinned staging ring
+
+// wait for the oldest staged copy and recycle its event
+void retire_oldest(Ctx* c) {
+    Ctx::Staged s = c->staged.front();
+    c->staged.pop_front();
+    (void)hipEventSynchronize(s.ev);
+    c->spare_events.push_back(s.ev);
+}
+
+Ctx::~Ctx() {
+    (void)hipStreamSynchronize(stream);
+    plans.clear();   // members holding blocks give them back before the cache is released
+    gl.reset();
+    while (!staged.empty()) retire_oldest(this);
+    for (hipEvent_t e : spare_events) (void)hipEventDestroy(e);
+    if (stage) (void)hipHostFree(stage);
+    release_pool(this);
+}
 
 void* dev_alloc(Ctx* c, size_t bytes) {
     const size_t sz = block_size(bytes);
@@ -107,7 +125,35 @@ void dev_free(Ctx* c, void* p, size_t bytes) {
 }
 
 void upload(Ctx* c, void* dst, const void* src, size_t bytes) {
-    if (bytes) FDE_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+    if (!bytes) return;
+    if (bytes > kStageBytes / 4) {   // large tables: a direct copy (it waits for the stream)
+        FDE_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+        return;
+    }
+    if (!c->stage) FDE_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->stage), kStageBytes, hipHostMallocDefault));
+    // copies that have completed free their regions
+    while (!c->staged.empty() && hipEventQuery(c->staged.front().ev) == hipSuccess) retire_oldest(c);
+    const size_t need = (bytes + 255) / 256 * 256;
+    size_t start = c->stage_head + need <= kStageBytes ? c->stage_head : 0;
+    for (;;) {
+        bool busy = false;
+        for (const Ctx::Staged& s : c->staged)
+            if (start < s.end && s.start < start + need) busy = true;
+        if (!busy) break;
+        retire_oldest(c);
+    }
+    std::memcpy(c->stage + start, src, bytes);
+    FDE_HIP(hipMemcpyAsync(dst, c->stage + start, bytes, hipMemcpyHostToDevice, c->stream));
+    hipEvent_t ev;
+    if (!c->spare_events.empty()) {
+        ev = c->spare_events.back();
+        c->spare_events.pop_back();
+    } else {
+        FDE_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    FDE_HIP(hipEventRecord(ev, c->stream));
+    c->staged.push_back(Ctx::Staged{start, start + need, ev});
+    c->stage_head = start + need;
 }
 
 namespace {
@@ -365,7 +411,6 @@ void build_op(Op* op, const double* nodes, int N, int P, double alpha, double th
         launch_pair_moments_dense(op);
     }
     build_load_rule(op);
-    FDE_HIP(hipStreamSynchronize(c->stream));
 }
 
 }  // namespace
@@ -471,8 +516,7 @@ int fde_op_create(fde_ctx* c, const double* nodes, int N, int P, double alpha, d
 
 void fde_op_destroy(fde_op* op) {
     if (!op) return;
-    (void)hipStreamSynchronize(op->ctx->stream);
-    delete op;
+    delete op;   // its blocks return to the context's stream-ordered cache
 }
 
 int fde_op_ndof(const fde_op* op) { return op ? op->Nd : -1; }
@@ -547,7 +591,6 @@ void assemble_load(Op* op, double c1, double c2, double* G) {
         t.alloc(c, op->Nd);
         stiffness_apply(op, 1, nullptr, op->Nd, t.p, op->Nd, c1, c2, true);
         axpy_cols(c->stream, op->Nd, 1, -1.0, t.p, op->Nd, G, op->Nd);
-        FDE_HIP(hipStreamSynchronize(c->stream));
     }
 }
 
@@ -577,7 +620,6 @@ int fde_load_vector_powers(fde_op* op, int nterms, const double* coef, const dou
     }
     launch_eval_powers(op, nterms, d_ce.p, d_ce.p + nt, d_s.p);
     assemble_load(op, c1, c2, G);
-    FDE_HIP(hipStreamSynchronize(c->stream));   // the coefficient buffers are freed on return
     FDE_API_END
 }
 
@@ -592,7 +634,6 @@ int fde_load_vector(fde_op* op, const double* f, double c1, double c2, double* G
         if (!std::isfinite(f[q])) fail(FDE_EINVAL, "f is not finite at node %zu (x = %.17g)", q, op->lq_x[q]);
     upload(c, op->d_lq_f.p, f, nq * sizeof(double));
     assemble_load(op, c1, c2, G);
-    FDE_HIP(hipStreamSynchronize(c->stream));
     FDE_API_END
 }
 

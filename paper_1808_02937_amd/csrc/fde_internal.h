@@ -3,8 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <deque>
 #include <map>
 #include <unordered_map>
+#include <vector>
 
 #include <cstdarg>
 #include <cstdint>
@@ -74,6 +76,8 @@ const double* gauss_legendre_table();
 struct Ctx;
 void* dev_alloc(Ctx* c, size_t bytes);
 void dev_free(Ctx* c, void* p, size_t bytes);
+// host -> device copy on the context stream; returns at once (the source may be reused)
+void upload(Ctx* c, void* dst, const void* src, size_t bytes);
 
 template <class T>
 struct DevBuf {
@@ -111,6 +115,17 @@ struct Ctx {
     std::multimap<size_t, void*> pool;    // free blocks by size
     std::unordered_map<void*, size_t> live;
     size_t pooled = 0;
+    // Pinned staging ring for host-to-device uploads: the data is copied into the ring and the
+    // copy to the device is asynchronous (an upload from pageable memory would wait for all work
+    // queued on the stream); a region is reused once the event recorded after its copy has fired.
+    struct Staged {
+        size_t start, end;
+        hipEvent_t ev;
+    };
+    char* stage = nullptr;
+    size_t stage_head = 0;
+    std::deque<Staged> staged;
+    std::vector<hipEvent_t> spare_events;
     ~Ctx();
     DevBuf<double> gl;   // Gauss-Legendre n=1..kMaxGL: nodes then weights, offset n(n-1)/2
     size_t lds_limit = 0;   // largest dynamic LDS of one workgroup (bytes)

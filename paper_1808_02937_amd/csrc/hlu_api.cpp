@@ -46,7 +46,7 @@ std::vector<LeafDev> leaf_table(const HTree& t) {
 template <class V>
 void upload_vec(Ctx* c, DevBuf<V>& buf, const std::vector<V>& v) {
     buf.alloc(c, v.size());
-    if (!v.empty()) FDE_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, c->stream));
+    upload(c, buf.p, v.data(), v.size() * sizeof(V));
 }
 
 void tree_params(HTree& t, Op* op, const fde_hparams* prm) {
@@ -119,7 +119,6 @@ void build_hmat(fde_hmat* hm, Op* op, const fde_hparams* prm) {
     upload_vec(c, d_sides, sides);
     launch_hbuild_factors(op, R, (int)sides.size(), d_sides.p, hm->d_arena.p);
     upload_vec(c, hm->d_ranks, hm->init_rank);
-    FDE_HIP(hipStreamSynchronize(c->stream));
 }
 
 void report_profile(HLUObj* f, const char* what) {
@@ -312,7 +311,6 @@ void factor_prepare(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
     else
         launch_segcopy<double, float>(c->stream, (int)segs.size(), d_segs.p, hm->d_arena.p,
                                       reinterpret_cast<float*>(f->arena.p));
-    FDE_HIP(hipStreamSynchronize(c->stream));   // the segment table is freed on return
 }
 
 void factor(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
@@ -388,7 +386,6 @@ std::shared_ptr<const Plan> get_plan(Ctx* c, const HTree& hmt, int kmax) {
     upload_vec(c, p->d_hs_steps, p->hs.steps);
     upload_vec(c, p->d_hs_recs, p->hs.recs);
     for (const LRBlockDev& b : lrt) p->lr_rows.push_back(std::max(b.m, b.n));
-    FDE_HIP(hipStreamSynchronize(c->stream));   // host copies of the tables may move later
     p->t.op = nullptr;
     c->plans.insert(c->plans.begin(), {key, p});
     if (c->plans.size() > kCached) c->plans.pop_back();
@@ -468,8 +465,7 @@ int fde_build_hmatrix(fde_op* op, const fde_hparams* prm, fde_hmat** out) {
 
 void fde_hmat_destroy(fde_hmat* hm) {
     if (!hm) return;
-    (void)hipDeviceSynchronize();
-    delete hm;
+    delete hm;   // its blocks return to the context's stream-ordered cache
 }
 
 int fde_hmat_counts(const fde_hmat* hm, int* nd, int* nr) {
@@ -574,10 +570,12 @@ int fde_hlu_factor_batched(int n, fde_hmat* const* hms, const fde_hlu_params* pr
 
 void fde_hlu_destroy(fde_hlu* f) {
     if (!f) return;
-    (void)hipDeviceSynchronize();
-    try {
-        report_profile(f, "H-solves");
-    } catch (...) {
+    if (f->prof.p) {   // op profile (FDE_PROFILE_OPS=1): read after the queued solves
+        (void)hipDeviceSynchronize();
+        try {
+            report_profile(f, "H-solves");
+        } catch (...) {
+        }
     }
     delete f;
 }

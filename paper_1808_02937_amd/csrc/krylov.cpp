@@ -148,15 +148,15 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
     d_ss.alloc(c, ns);
     d_mask.alloc(c, ns);
     d_count.alloc(c, 1);
-    FDE_HIP(hipMemcpyAsync(d_sys.p, sys.data(), sys.size() * sizeof(SysDev), hipMemcpyHostToDevice, st));
-    FDE_HIP(hipMemcpyAsync(d_mask.p, mask.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+    upload(c, d_sys.p, sys.data(), sys.size() * sizeof(SysDev));
+    upload(c, d_mask.p, mask.data(), ns * sizeof(int));
     if (!i32.empty()) {
         d_i32.alloc(c, i32.size());
-        FDE_HIP(hipMemcpyAsync(d_i32.p, i32.data(), i32.size() * sizeof(Inst<float>), hipMemcpyHostToDevice, st));
+        upload(c, d_i32.p, i32.data(), i32.size() * sizeof(Inst<float>));
     }
     if (!i64.empty()) {
         d_i64.alloc(c, i64.size());
-        FDE_HIP(hipMemcpyAsync(d_i64.p, i64.data(), i64.size() * sizeof(Inst<double>), hipMemcpyHostToDevice, st));
+        upload(c, d_i64.p, i64.data(), i64.size() * sizeof(Inst<double>));
     }
     const bool any_copy = std::any_of(mask.begin(), mask.end(), [](int v) { return v != 0; });
     fg_gnorm(st, ns, d_sys.p, d_ss.p);
