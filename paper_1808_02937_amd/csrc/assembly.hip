@@ -320,8 +320,17 @@ __global__ void __launch_bounds__(kWave) k_generators(int N, int P, double alpha
     g.he = 2.0;
     g.hf = 2.0 * pow(r, -(double)k);
     g.kind = k == 0 ? 0 : (k == 1 ? 1 : 2);
+    // the k-1 elements between: 2 sum_{j=1}^{k-1} q^j, q = 1/r, in closed form
+    // (q expm1((k-1) ln q) / expm1(ln q), accurate also for q near 1)
     double gap = 0.0;
-    for (int j = 1; j < k; ++j) gap += 2.0 * pow(r, -(double)j);
+    if (k > 1) {
+        if (r == 1.0) {
+            gap = 2.0 * (k - 1);
+        } else {
+            const double lq = -log(r);
+            gap = 2.0 * exp(lq) * expm1((k - 1) * lq) / expm1(lq);
+        }
+    }
     g.gap = gap;
     compute_block(g, P, alpha, gamma0, rules, gl, 1.0 / (0.5 * g.hf), gen + (int64_t)k * P * P);
 }
@@ -341,25 +350,80 @@ __global__ void k_dense_matrix(SemDev s, double* __restrict__ A, int lda) {
 }
 
 // ---------------------------------------------------------------- load vector
-// G_i = sum_q w_q f(x_q) phi_i(x_q) over the quadrature nodes of the elements in supp(phi_i)
-__global__ void k_load_vector(int N, int P, const int* __restrict__ off,
-                              const double* __restrict__ xi, const double* __restrict__ w,
-                              const double* __restrict__ f, double* __restrict__ G) {
-    const int Nd = N * P - 1;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Nd) return;
-    const int nb = N * (P - 1);
-    double s = 0.0;
-    if (i < nb) {
-        const int e = i / (P - 1), p = i % (P - 1) + 1;
-        for (int q = off[e]; q < off[e + 1]; ++q)
-            s += w[q] * f[q] * (legendre(p - 1, xi[q]) - legendre(p + 1, xi[q]));
-    } else {
-        const int j = i - nb + 1;
-        for (int q = off[j - 1]; q < off[j]; ++q) s += w[q] * f[q] * 0.5 * (1.0 + xi[q]);
-        for (int q = off[j]; q < off[j + 1]; ++q) s += w[q] * f[q] * 0.5 * (1.0 - xi[q]);
+// G_i = sum_q w_q f(x_q) phi_i(x_q) over the quadrature nodes of the elements in supp(phi_i).
+// One wavefront per element, the lanes striding over the element's nodes (24 on most elements,
+// hundreds on the graded end elements): at a node the Legendre values L_0..L_P by the
+// three-term recurrence give the bubbles psi_p = L_{p-1} - L_{p+1}; the per-lane sums are
+// reduced over the wavefront. The two hat halves (1 -+ xi)/2 of the element go to `hat`, and a
+// second kernel adds the halves of the two elements around each interior node.
+constexpr int kLvMaxP = 32;
+
+// lane l ends with the wavefront sum of v[(l >> 1) & 31] (31 shuffles for 32 sums)
+__device__ __attribute__((always_inline)) inline double reduce32(double (&a)[32], int lane) {
+#pragma unroll
+    for (int st = 0; st < 5; ++st) {
+        const int o = 32 >> st, half = 16 >> st;
+        const bool hi = lane & o;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            // the two values as opaque registers: a select between array elements would otherwise
+            // become a load at a lane-dependent index (the array then lives in scratch memory)
+            double lo = a[i], up = a[i + half];
+            asm volatile("" : "+v"(lo), "+v"(up));
+            const double send = hi ? lo : up, keep = hi ? up : lo;
+            a[i] = keep + __shfl_xor(send, o, 64);
+        }
     }
-    G[i] = s;
+    return a[0] + __shfl_xor(a[0], 1, 64);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_load_elements(int N, int P, const int* __restrict__ off,
+                                                       const double* __restrict__ xi, const double* __restrict__ w,
+                                                       const double* __restrict__ f, double* __restrict__ G,
+                                                       double* __restrict__ hat) {
+    const int lane = threadIdx.x & 63;
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= N) return;
+    double acc[32], hl = 0.0, hr = 0.0;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc[i] = 0.0;
+    for (int q = off[e] + lane; q < off[e + 1]; q += 64) {
+        const double x = xi[q], wf = w[q] * f[q];
+        // psi_p = L_{p-1} - L_{p+1}, with L_{p+1} from the three-term recurrence as p advances
+        double Lm = 1.0, Lc = x;   // L_{p-1}, L_p
+#pragma unroll
+        for (int p = 1; p < kLvMaxP; ++p)
+            if (p < P) {
+                const double Ln = ((2.0 * p + 1.0) * x * Lc - p * Lm) * (1.0 / (p + 1.0));
+                acc[p - 1] += wf * (Lm - Ln);
+                Lm = Lc;
+                Lc = Ln;
+            }
+        hl += wf * 0.5 * (1.0 - x);
+        hr += wf * 0.5 * (1.0 + x);
+    }
+    const double sb = reduce32(acc, lane);
+    const int p = ((lane >> 1) & 31) + 1;
+    if ((lane & 1) == 0 && p < P) G[(int64_t)e * (P - 1) + p - 1] = sb;
+    hl = wave_sum(hl);
+    hr = wave_sum(hr);
+    if (lane == 0) {
+        hat[2 * e] = hl;
+        hat[2 * e + 1] = hr;
+    }
+}
+
+// hat j (interior node j = 1..N-1): right half of element j-1 plus left half of element j
+__global__ void k_load_hats(int N, int P, const double* __restrict__ hat, double* __restrict__ G) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (j >= N) return;
+    G[(int64_t)N * (P - 1) + j - 1] = hat[2 * (j - 1) + 1] + hat[2 * j];
 }
 
 }  // namespace
@@ -418,9 +482,17 @@ void launch_eval_powers(Op* op, int nt, const double* d_coef, const double* d_ex
 }
 
 void launch_load_vector(Op* op, double* G) {
-    hipLaunchKernelGGL(k_load_vector, dim3(ceil_div(op->Nd, 256)), dim3(256), 0, op->ctx->stream,
-                       op->N, op->P, op->d_lq_off.p, op->d_lq_xi.p, op->d_lq_w.p, op->d_lq_f.p, G);
+    if (op->P > kLvMaxP) fail(FDE_EUNSUPPORTED, "load vector: P <= %d", kLvMaxP);
+    DevBuf<double> hat;
+    hat.alloc(op->ctx, 2 * (size_t)op->N);
+    hipLaunchKernelGGL(k_load_elements, dim3(ceil_div(op->N, 4)), dim3(256), 0, op->ctx->stream, op->N, op->P,
+                       op->d_lq_off.p, op->d_lq_xi.p, op->d_lq_w.p, op->d_lq_f.p, G, hat.p);
     FDE_LAUNCH_CHECK();
+    if (op->N > 1) {
+        hipLaunchKernelGGL(k_load_hats, dim3(ceil_div(op->N - 1, 256)), dim3(256), 0, op->ctx->stream, op->N, op->P,
+                           hat.p, G);
+        FDE_LAUNCH_CHECK();
+    }
 }
 
 }  // namespace fde

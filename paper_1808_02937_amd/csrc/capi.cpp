@@ -281,6 +281,8 @@ void build_load_rule(Op* op) {
     op->lq_da.clear();
     op->lq_db.clear();
     op->lq_off.assign(op->N + 1, 0);
+    const size_t guess = (size_t)op->N * std::max(24, op->P + 12) + 2048;   // interior panels, graded ends
+    for (auto* v : {&op->lq_x, &op->lq_xi, &op->lq_w, &op->lq_da, &op->lq_db}) v->reserve(guess);
     for (int e = 0; e < op->N; ++e) {
         op->lq_off[e] = (int)op->lq_x.size();
         element_load_rule(op, e, op->lq_x, op->lq_xi, op->lq_w, op->lq_da, op->lq_db);
@@ -396,9 +398,10 @@ void build_op(Op* op, const double* nodes, int N, int P, double alpha, double th
         op->L = L;
         const int M = L / 2;
         std::vector<double2> tw(M + 1);
+        // exp(-2 pi i j / L): j / L is exact (L a power of two), cos and sin in FP64
         for (int j = 0; j <= M; ++j) {
-            const long double ang = -2.0L * 3.14159265358979323846264338327950288L * j / L;
-            tw[j] = make_double2((double)std::cos(ang), (double)std::sin(ang));
+            const double ang = -2.0 * 3.14159265358979323846 * ((double)j / L);
+            tw[j] = make_double2(std::cos(ang), std::sin(ang));
         }
         op->d_tw.alloc(c, M + 1);
         upload(c, op->d_tw.p, tw.data(), tw.size() * sizeof(double2));

@@ -27,7 +27,9 @@ struct LeafDev {       // leaf block for reconstruction
 };
 
 void launch_hbuild_dense(Op* op, int nblk, const DenseBlkDev* d_blks, const int* d_h2p, double* arena);
-void launch_hbuild_factors(Op* op, int R, int nsides, const FacSideDev* d_sides, double* arena);
+// sides: host copy of the table at d_sides (the launch splits every side into chunks of rows)
+void launch_hbuild_factors(Op* op, int R, const std::vector<FacSideDev>& sides, const FacSideDev* d_sides,
+                           double* arena);
 template <class S, class D>
 void launch_segcopy(hipStream_t st, int nseg, const SegDev* d_segs, const S* src, D* dst);
 template <class T>

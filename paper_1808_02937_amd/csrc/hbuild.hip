@@ -24,79 +24,87 @@ __global__ void k_hbuild_dense(SemDev s, const DenseBlkDev* __restrict__ blks, c
     }
 }
 
-// One thread per row of a factor side; all R expansion terms of the row at once: at each
-// quadrature node the first power is one pow() and the following ones come by repeated
-// multiplication with the same ratio ((x-c)/r, or 1/(sgn(x-c)) for the singular side).
+// One thread per row of a factor side, a workgroup per chunk of kRowsPerChunk rows of one side
+// (sides range from a leaf to half the matrix, so chunks keep the workgroups even); all R
+// expansion terms of the row at once: at each quadrature node the first power is one pow()
+// (none for the regular side's nu = 0) and the following ones come by repeated multiplication
+// with the same ratio ((x-c)/r, or 1/(sgn(x-c)) for the singular side).
 constexpr int kNuChunk = 16;
-__global__ void k_hbuild_factors(int P, int R, double alpha, const double* __restrict__ x,
-                                 const double* __restrict__ h, const double* __restrict__ gl,
-                                 const FacSideDev* __restrict__ sides, double* __restrict__ arena) {
-    const FacSideDev f = sides[blockIdx.x];
+constexpr int kRowsPerChunk = 128;
+__global__ void __launch_bounds__(kRowsPerChunk) k_hbuild_factors(int P, int R, double alpha,
+                                                                  const double* __restrict__ x,
+                                                                  const double* __restrict__ h,
+                                                                  const double* __restrict__ gl,
+                                                                  const FacSideDev* __restrict__ sides,
+                                                                  const int2* __restrict__ chunks,
+                                                                  double* __restrict__ arena) {
+    const int2 ch = chunks[blockIdx.x];
+    const FacSideDev f = sides[ch.x];
     const int nq = f.sing ? min(kMaxGL, P + 24) : min(kMaxGL, (R + P) / 2 + 2);
     const int off_n = nq * (nq - 1) / 2;
     const int wbase = kMaxGL * (kMaxGL + 1) / 2;
-    for (int i = threadIdx.x; i < f.rows; i += blockDim.x) {
-        if (f.mult == 0.0) {
-            for (int nu = 0; nu < R; ++nu) arena[f.off + i + (int64_t)nu * f.rows] = 0.0;
-            continue;
-        }
-        const int d = f.d0 + i;
-        const int e = d / P, l = d % P;
-        int ne, el[2], mm[2];
-        double cf[2];
-        if (l < P - 1) {
-            ne = 1;
-            el[0] = e;
-            mm[0] = l + 1;
-            cf[0] = -(2.0 * (l + 1) + 1.0) * 2.0 / h[e];
-        } else {
-            ne = 2;
-            el[0] = e;
-            mm[0] = 0;
-            cf[0] = 1.0 / h[e];
-            el[1] = e + 1;
-            mm[1] = 0;
-            cf[1] = -1.0 / h[e + 1];
-        }
-        for (int nu0 = 0; nu0 < R; nu0 += kNuChunk) {
-            double acc[kNuChunk];
+    const int i = ch.y + threadIdx.x;
+    if (i >= f.rows) return;
+    if (f.mult == 0.0) {
+        for (int nu = 0; nu < R; ++nu) arena[f.off + i + (int64_t)nu * f.rows] = 0.0;
+        return;
+    }
+    const int d = f.d0 + i;
+    const int e = d / P, l = d % P;
+    int ne, el[2], mm[2];
+    double cf[2];
+    if (l < P - 1) {
+        ne = 1;
+        el[0] = e;
+        mm[0] = l + 1;
+        cf[0] = -(2.0 * (l + 1) + 1.0) * 2.0 / h[e];
+    } else {
+        ne = 2;
+        el[0] = e;
+        mm[0] = 0;
+        cf[0] = 1.0 / h[e];
+        el[1] = e + 1;
+        mm[1] = 0;
+        cf[1] = -1.0 / h[e + 1];
+    }
+    for (int nu0 = 0; nu0 < R; nu0 += kNuChunk) {
+        double acc[kNuChunk];
 #pragma unroll
-            for (int u = 0; u < kNuChunk; ++u) acc[u] = 0.0;
-            for (int a = 0; a < ne; ++a) {
-                const int ee = el[a];
-                const double xl = x[ee], he = h[ee];
-                const double scale = cf[a] * 0.5 * he;
-                for (int k = 0; k < nq; ++k) {
-                    const double xr = gl[off_n + k], w = gl[wbase + off_n + k];
-                    const double xx = xl + 0.5 * he * (1.0 + xr);
-                    double F, step;
-                    if (f.sing) {
-                        const double b = f.sgn * (xx - f.c);
-                        F = pow(b, 1.0 - alpha - nu0);
-                        step = 1.0 / b;
-                    } else {
-                        const double b = (xx - f.c) / f.r;
-                        F = pow(b, (double)nu0);
-                        step = b;
-                    }
-                    const double wl = scale * w * legendre_at(mm[a], xr);
-#pragma unroll
-                    for (int u = 0; u < kNuChunk; ++u) {
-                        acc[u] += wl * F;
-                        F *= step;
-                    }
-                }
-            }
-            for (int u = 0; u < kNuChunk && nu0 + u < R; ++u) {
-                const int nu = nu0 + u;
-                double coef = 1.0;
+        for (int u = 0; u < kNuChunk; ++u) acc[u] = 0.0;
+        for (int a = 0; a < ne; ++a) {
+            const int ee = el[a];
+            const double xl = x[ee], he = h[ee];
+            const double scale = cf[a] * 0.5 * he;
+            for (int k = 0; k < nq; ++k) {
+                const double xr = gl[off_n + k], w = gl[wbase + off_n + k];
+                const double xx = xl + 0.5 * he * (1.0 + xr);
+                double F, step;
                 if (f.sing) {
-                    for (int k = 1; k <= nu; ++k) coef *= (alpha + k - 2.0) / k;
-                    if (f.alt && (nu & 1)) coef = -coef;
-                    coef *= pow(f.r, (double)nu);
+                    const double b = f.sgn * (xx - f.c);
+                    F = pow(b, 1.0 - alpha - nu0);
+                    step = 1.0 / b;
+                } else {
+                    const double b = (xx - f.c) / f.r;
+                    F = nu0 == 0 ? 1.0 : pow(b, (double)nu0);
+                    step = b;
                 }
-                arena[f.off + i + (int64_t)nu * f.rows] = acc[u] * f.mult * coef;
+                const double wl = scale * w * legendre_at(mm[a], xr);
+#pragma unroll
+                for (int u = 0; u < kNuChunk; ++u) {
+                    acc[u] += wl * F;
+                    F *= step;
+                }
             }
+        }
+        for (int u = 0; u < kNuChunk && nu0 + u < R; ++u) {
+            const int nu = nu0 + u;
+            double coef = 1.0;
+            if (f.sing) {
+                for (int k = 1; k <= nu; ++k) coef *= (alpha + k - 2.0) / k;
+                if (f.alt && (nu & 1)) coef = -coef;
+                coef *= pow(f.r, (double)nu);
+            }
+            arena[f.off + i + (int64_t)nu * f.rows] = acc[u] * f.mult * coef;
         }
     }
 }
@@ -142,10 +150,18 @@ void launch_hbuild_dense(Op* op, int nblk, const DenseBlkDev* d_blks, const int*
     FDE_LAUNCH_CHECK();
 }
 
-void launch_hbuild_factors(Op* op, int R, int nsides, const FacSideDev* d_sides, double* arena) {
-    if (nsides == 0) return;
-    hipLaunchKernelGGL(k_hbuild_factors, dim3(nsides), dim3(256), 0, op->ctx->stream, op->P, R, op->alpha,
-                       op->d_x.p, op->d_h.p, op->ctx->gl.p, d_sides, arena);
+void launch_hbuild_factors(Op* op, int R, const std::vector<FacSideDev>& sides, const FacSideDev* d_sides,
+                           double* arena) {
+    if (sides.empty()) return;
+    std::vector<int2> chunks;
+    for (size_t k = 0; k < sides.size(); ++k)
+        for (int r0 = 0; r0 < sides[k].rows; r0 += kRowsPerChunk) chunks.push_back(make_int2((int)k, r0));
+    if (chunks.empty()) return;
+    DevBuf<int2> d_chunks;
+    d_chunks.alloc(op->ctx, chunks.size());
+    upload(op->ctx, d_chunks.p, chunks.data(), chunks.size() * sizeof(int2));
+    hipLaunchKernelGGL(k_hbuild_factors, dim3((unsigned)chunks.size()), dim3(kRowsPerChunk), 0, op->ctx->stream,
+                       op->P, R, op->alpha, op->d_x.p, op->d_h.p, op->ctx->gl.p, d_sides, d_chunks.p, arena);
     FDE_LAUNCH_CHECK();
 }
 

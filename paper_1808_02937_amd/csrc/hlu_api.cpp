@@ -117,7 +117,7 @@ void build_hmat(fde_hmat* hm, Op* op, const fde_hparams* prm) {
     }
     DevBuf<FacSideDev> d_sides;
     upload_vec(c, d_sides, sides);
-    launch_hbuild_factors(op, R, (int)sides.size(), d_sides.p, hm->d_arena.p);
+    launch_hbuild_factors(op, R, sides, d_sides.p, hm->d_arena.p);
     upload_vec(c, hm->d_ranks, hm->init_rank);
 }
 
