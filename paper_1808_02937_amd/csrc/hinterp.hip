@@ -1048,9 +1048,12 @@ __device__ double op_flops(const Inst<T>& d, const OpRec& o) {
 }
 
 // one op; false when a leaf pivot broke down (the status is set)
+// d and the op record are referenced where they live (global memory): the op functions are
+// separate (not inlined) functions, and a local copy handed to them by reference would be
+// written to every lane's scratch memory for each op
 template <class T, class SH>
 __device__ bool run_op(const Inst<T>& d, int pc, SH& sh, int step) {
-    const OpRec o = d.ops[pc];
+    const OpRec& o = d.ops[pc];
     unsigned long long t0 = 0;
     if (d.prof && threadIdx.x == 0) t0 = wall_clock64();
     double fl = 0.0;
@@ -1130,7 +1133,7 @@ __device__ void run_program(const Inst<T>& d, SH& sh, int step) {
 template <class T, int KS, bool GENERAL>
 __global__ void __launch_bounds__(kT) k_interp(const Inst<T>* __restrict__ insts, int step) {
     __shared__ Shared<T, KS, GENERAL> sh;
-    const Inst<T> d = insts[blockIdx.x];
+    const Inst<T>& d = insts[blockIdx.x];
     run_program(d, sh, step);
 }
 
@@ -1145,7 +1148,7 @@ template <class T, int KS, bool GENERAL>
 __global__ void __launch_bounds__(kT) k_level(const Inst<T>* __restrict__ insts, const int2* __restrict__ tasks) {
     __shared__ Shared<T, KS, GENERAL> sh;
     const int2 tk = tasks[blockIdx.x];
-    const Inst<T> d = insts[tk.x];
+    const Inst<T>& d = insts[tk.x];
     // after a breakdown in an earlier level the rest of that factorisation is skipped; the
     // status is read once and shared so that every thread takes the same branch
     if (threadIdx.x == 0) sh.stop = d.status[0];

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 
 #include "hbuild.h"
 #include "hlu.h"
@@ -247,6 +248,35 @@ void factor_batch_run(Ctx* c, std::vector<HLUObj*>& fs, const char* what) {
         }
         fprintf(stderr, "  levels <50us: %d (%.2f ms), <200us: %d (%.2f ms), <1ms: %d (%.2f ms), >=1ms: %d (%.2f ms)\n",
                 bn[0], bucket[0], bn[1], bucket[1], bn[2], bucket[2], bn[3], bucket[3]);
+        // levels by their heaviest op: recompression by block rows, else the first op code present
+        struct Agg {
+            int n = 0;
+            float ms = 0.f;
+            int tasks = 0;
+        };
+        std::map<std::string, Agg> kinds;
+        for (const Row& r : rows) {
+            const size_t l = r.l;
+            int maxm = -1, has[kOpCodes] = {0};
+            for (int pc = lo[l]; pc < lo[l + 1]; ++pc) {
+                const OpRec& o = fs[0]->plan->lu.ops[pc];
+                has[o.code] = 1;
+                if (o.code == OP_LRSUB) maxm = std::max(maxm, fs[0]->plan->lr_rows[o.blk]);
+            }
+            std::string k;
+            if (maxm >= 0) k = "lrsub<=" + std::to_string(maxm);
+            else if (has[OP_GETRF]) k = "getrf";
+            else if (has[OP_TRSM]) k = "trsm";
+            else if (has[OP_GEMM]) k = "gemm";
+            else k = "other";
+            Agg& a = kinds[k];
+            a.n++;
+            a.ms += r.ms;
+            a.tasks += loff[l + 1] - loff[l];
+        }
+        for (auto& kv : kinds)
+            fprintf(stderr, "  levels led by %s: %d levels, %.2f ms (%.1f us each), %.0f tasks each\n", kv.first.c_str(),
+                    kv.second.n, kv.second.ms, 1e3 * kv.second.ms / kv.second.n, (double)kv.second.tasks / kv.second.n);
         for (auto& e : lev_ev) (void)hipEventDestroy(e);
     }
     std::vector<int> st(2 * fs.size());
