@@ -39,6 +39,7 @@ struct Inst {
     int* status;              // [0] status code, [1] op index of a breakdown
     unsigned long long* prof; // optional: per op code, [2c] wall-clock ticks, [2c+1] count
     double* flops;            // executed floating-point operations (accumulated by thread 0)
+    double* op_flops;         // if set: op pc adds its operations to op_flops[pc] (no shared counter)
 };
 
 // FDE_PROFILE_OPS=1 in the environment: time every interpreter op by type

@@ -364,8 +364,12 @@ __device__ __attribute__((noinline)) bool op_getrf(const Inst<T>& d, const OpRec
                     if (!(fabs((double)akk) > d.pivot_floor * amax) || !(fabs((double)akk) > 0.0)) {
                         fail_at = k;
                     } else {
-                        const T l = i > k ? a[k] / akk : T(0);
-                        if (i > k) a[k] = l;
+                        // an opaque copy of the row index: the 64 per-step row masks are formed here
+                        // rather than hoisted and held in registers across the elimination
+                        int ii = i;
+                        asm volatile("" : "+v"(ii));
+                        const T l = ii > k ? a[k] / akk : T(0);
+                        if (ii > k) a[k] = l;
 #pragma unroll
                         for (int j = k + 1; j < kLU; ++j) a[j] -= l * lane_bcast(a[j], k);
                     }
@@ -1115,7 +1119,9 @@ __device__ bool run_op(const Inst<T>& d, int pc, SH& sh, int step) {
     __syncthreads();
     if (threadIdx.x == 0) {
         if (o.code == OP_LRSUB) fl += sh.lrsub_flops;
-        atomicAdd(d.flops, fl);
+        // a factorisation runs every op once: its own slot, no counter shared by the whole level
+        if (d.op_flops) d.op_flops[pc] = fl;
+        else atomicAdd(d.flops, fl);
     }
     if (d.prof && threadIdx.x == 0) {
         atomicAdd(&d.prof[2 * o.code], (unsigned long long)(wall_clock64() - t0));

@@ -51,6 +51,7 @@ struct HLUObj {
     DevBuf<int> ranks, status;
     DevBuf<unsigned long long> prof;   // op profile (FDE_PROFILE_OPS=1)
     DevBuf<double> flops;              // [0] factorisation, [1] H-solves
+    DevBuf<double> lu_flops;           // per op of the factorisation (summed when asked for)
     double factor_ms = 0.0;
     int64_t sv_nrhs_cap = 0;
     template <class T>
@@ -86,6 +87,7 @@ struct HLUObj {
         d.status = status.p;
         d.prof = prof.p;
         d.flops = flops.p + (solve ? 1 : 0);
+        d.op_flops = solve ? nullptr : lu_flops.p;
         return d;
     }
 };

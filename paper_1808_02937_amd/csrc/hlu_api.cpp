@@ -316,6 +316,8 @@ void factor_prepare(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
     FDE_HIP(hipMemsetAsync(f->status.p, 0, 2 * sizeof(int), c->stream));
     f->flops.alloc(c, 2);
     FDE_HIP(hipMemsetAsync(f->flops.p, 0, 2 * sizeof(double), c->stream));
+    f->lu_flops.alloc(c, std::max<size_t>(f->plan->lu.ops.size(), 1));
+    FDE_HIP(hipMemsetAsync(f->lu_flops.p, 0, f->lu_flops.bytes(), c->stream));
     if (profile_ops_enabled()) {
         f->prof.alloc(c, kProfSlots);
         FDE_HIP(hipMemsetAsync(f->prof.p, 0, kProfSlots * sizeof(unsigned long long), c->stream));
@@ -632,8 +634,13 @@ int fde_hlu_stats(fde_hlu* f, double* factor_flops, double* factor_ms, double* s
     FDE_API_BEGIN
     if (!f) fail(FDE_EINVAL, "null factor");
     double fl[2] = {0.0, 0.0};
+    std::vector<double> per_op(f->lu_flops.n);
     FDE_HIP(hipMemcpyAsync(fl, f->flops.p, sizeof fl, hipMemcpyDeviceToHost, f->op->ctx->stream));
+    if (!per_op.empty())
+        FDE_HIP(hipMemcpyAsync(per_op.data(), f->lu_flops.p, f->lu_flops.bytes(), hipMemcpyDeviceToHost,
+                               f->op->ctx->stream));
     FDE_HIP(hipStreamSynchronize(f->op->ctx->stream));
+    for (double v : per_op) fl[0] += v;
     if (factor_flops) *factor_flops = fl[0];
     if (factor_ms) *factor_ms = f->factor_ms;
     if (solve_flops) *solve_flops = fl[1];
