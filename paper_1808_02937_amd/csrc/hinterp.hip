@@ -615,6 +615,36 @@ __device__ inline void gram_mirror(LS& S, int k0, int k1) {
     }
 }
 
+// largest dv over lanes 0 .. kSK-1 (kSK = 16 or 32) and its lane index pj, ties to the smaller
+// index; wave-uniform on return. Each row of 16 lanes is reduced by DPP rotations, the rows'
+// winners are read with readlane.
+template <int kSK>
+__device__ inline void argmax_rows(double& dv, int& pj) {
+    static_assert(kSK == 16 || kSK == 32, "pivot search covers one or two rows of 16 lanes");
+    auto take = [&](double ov, int op) {
+        if (ov > dv || (ov == dv && op < pj)) {
+            dv = ov;
+            pj = op;
+        }
+    };
+    take(dpp_move<dpp_row_ror(8)>(dv), dpp_move<dpp_row_ror(8)>(pj));
+    take(dpp_move<dpp_row_ror(4)>(dv), dpp_move<dpp_row_ror(4)>(pj));
+    take(dpp_move<dpp_row_ror(2)>(dv), dpp_move<dpp_row_ror(2)>(pj));
+    take(dpp_move<dpp_row_ror(1)>(dv), dpp_move<dpp_row_ror(1)>(pj));
+    const double v0 = lane_bcast(dv, 0);
+    const int p0 = __builtin_amdgcn_readlane(pj, 0);
+    if (kSK == 32) {
+        const double v1 = lane_bcast(dv, 16);
+        const int p1 = __builtin_amdgcn_readlane(pj, 16);
+        const bool second = v1 > v0 || (v1 == v0 && p1 < p0);
+        dv = second ? v1 : v0;
+        pj = second ? p1 : p0;
+    } else {
+        dv = v0;
+        pj = p0;
+    }
+}
+
 // Cholesky of the k x k Gram G (LDS, ld kSK) by one wavefront, lane j = index j, in registers:
 // lane j holds column j and its current diagonal; the pivot is wave-uniform and the new column of
 // L is broadcast with readlane for the Schur update. With pivoting the largest remaining diagonal
@@ -631,8 +661,8 @@ __device__ void wave_cholesky(const double* G, double* R, int* perm, int* q_out,
     double dj = in ? G[j * kSK + j] : 0.0;
     bool rem = in;
     double d0 = dj;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) d0 = fmax(d0, __shfl_xor(d0, o, 64));
+    int p0 = j;
+    argmax_rows<kSK>(d0, p0);
     for (int a = 0; a < k; ++a)
         if (in) R[a * kSK + j] = 0.0;
     int q = k;
@@ -642,28 +672,19 @@ __device__ void wave_cholesky(const double* G, double* R, int* perm, int* q_out,
         if (a < k && !done) {
             double dv = pivot ? (rem ? dj : -1.0) : (j == a ? dj : -1.0);
             int pj = j;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {   // argmax, ties to the smaller index
-                const double ov = __shfl_xor(dv, o, 64);
-                const int op = __shfl_xor(pj, o, 64);
-                if (ov > dv || (ov == dv && op < pj)) {
-                    dv = ov;
-                    pj = op;
-                }
-            }
+            argmax_rows<kSK>(dv, pj);
             const int p = __builtin_amdgcn_readfirstlane(pj);
-            dv = __shfl(dv, 0, 64);
             if (!(dv > floor_rel * d0) || !(dv > 0.0)) {
                 q = a;
                 done = true;
             } else {
-                const double lp = sqrt(dv);
+                const double lp = sqrt(dv), inv = 1.0 / lp;
                 if (j == p) rem = false;
                 double gp = 0.0;
 #pragma unroll
                 for (int i = 0; i < kSK; ++i)
                     if (i == p) gp = g[i];
-                const double lj = in ? (j == p ? lp : (rem ? gp / lp : 0.0)) : 0.0;
+                const double lj = in ? (j == p ? lp : (rem ? gp * inv : 0.0)) : 0.0;
                 if (in) R[a * kSK + j] = lj;
                 if (j == 0) perm[a] = p;
                 if (rem) {
@@ -678,12 +699,42 @@ __device__ void wave_cholesky(const double* G, double* R, int* perm, int* q_out,
     if (j == 0) *q_out = q;
 }
 
+// sum over the kLpc consecutive lanes that hold one column (kLpc = 1, 2 or 4); every lane of the
+// group gets the same bits (the butterfly adds the same pairs in the same order)
+template <int kLpc, class W>
+__device__ inline W column_sum(W v) {
+    static_assert(kLpc == 1 || kLpc == 2 || kLpc == 4, "a column spans at most one quad");
+    if (kLpc >= 2) v += dpp_move<kDppXor1>(v);
+    if (kLpc >= 4) v += dpp_move<kDppXor2>(v);
+    return v;
+}
+
+// Jacobi rotation (c, s) = (cs, cs * t) that zeroes the off-diagonal g of the 2 x 2 Gram
+// [[ap, g], [g, aq]] (the smaller root t of t^2 + 2 zeta t - 1 = 0). FP32 uses the hardware
+// reciprocal and square-root approximations: both columns take the same (cs, sn), so M Z stays
+// the product of the original M with the accumulated Z whatever their last-bit error.
+__device__ inline void jacobi_rotation(float ap, float aq, float g, float& cs, float& sn) {
+    const float zeta = (aq - ap) * __builtin_amdgcn_rcpf(g + g);
+    const float t0 = __builtin_amdgcn_rcpf(fabsf(zeta) + __builtin_amdgcn_sqrtf(fmaf(zeta, zeta, 1.0f)));
+    const float t = zeta >= 0.0f ? t0 : -t0;
+    cs = __builtin_amdgcn_rsqf(fmaf(t, t, 1.0f));
+    sn = cs * t;
+}
+__device__ inline void jacobi_rotation(double ap, double aq, double g, double& cs, double& sn) {
+    const double zeta = (aq - ap) / (g + g);
+    const double t0 = 1.0 / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+    const double t = zeta >= 0.0 ? t0 : -t0;
+    cs = 1.0 / sqrt(fma(t, t, 1.0));
+    sn = cs * t;
+}
+
 // one-sided Jacobi on the columns of M (rows x cols, column-major ld kSK, LDS) by one wavefront,
 // in registers: column c is held by kLpc = 64 / kSK lanes, each with kSK / kLpc interleaved rows
 // of M and of the rotations Z. In each round of the round-robin order a lane fetches its partner
-// column's rows (one shuffle per row), the pair's dot products are reduced over the column's
-// lanes, and both columns of the pair apply the same rotation. On return M holds the rotated
-// columns, Z (cols x cols, LDS) the rotations and nrm[c] the norm of rotated column c.
+// column's rows (one shuffle per row), the pair's dot products are summed over the column's
+// lanes, and both columns of the pair apply the same rotation. A pair counts as orthogonal when
+// g^2 <= conv^2 ap aq. On return M holds the rotated columns, Z (cols x cols, LDS) the rotations
+// and nrm[c] the norm of rotated column c.
 template <int kSK, class W>
 __device__ void wave_jacobi_lds(double* M, double* Z, double* nrm, int rows, int cols, double conv) {
     constexpr int kLpc = 64 / kSK, kNr = kSK / kLpc;
@@ -696,19 +747,19 @@ __device__ void wave_jacobi_lds(double* M, double* Z, double* nrm, int rows, int
         m[u] = (c < cols && row < rows) ? (W)M[row + c * kSK] : W(0);
         z[u] = (c < cols && row == c) ? W(1) : W(0);
     }
-    const int n2 = cols + (cols & 1);
+    const W conv2 = (W)(conv * conv);
+    const int n2 = cols + (cols & 1), nm1 = n2 - 1;
+    // round-robin: in round r column c < n2 - 1 meets (2 r - c) mod (n2 - 1), or n2 - 1 when that
+    // is c itself; column n2 - 1 meets r. pr tracks (2 r - c) mod (n2 - 1) from round to round.
+    const int pr0 = c < nm1 ? (nm1 - c) % nm1 : 0;
     for (int sweep = 0; sweep < 30; ++sweep) {
         bool rotated = false;
-        for (int round = 0; round < n2 - 1; ++round) {
-            int partner;
-            if (c >= n2)
-                partner = c;
-            else if (c == n2 - 1)
-                partner = round;
-            else if (c == round)
-                partner = n2 - 1;
-            else
-                partner = (((2 * round - c) % (n2 - 1)) + (n2 - 1)) % (n2 - 1);
+        int pr = pr0;
+        for (int round = 0; round < nm1; ++round) {
+            const int partner = c >= n2 ? c : (c == nm1 ? round : (c == round ? nm1 : pr));
+            pr += 2;
+            if (pr >= nm1) pr -= nm1;
+            if (pr >= nm1) pr -= nm1;
             const bool valid = c < cols && partner < cols && partner != c;
             const int src = (valid ? partner : c) * kLpc + sub;
             W pm[kNr], pz[kNr];
@@ -724,24 +775,22 @@ __device__ void wave_jacobi_lds(double* M, double* Z, double* nrm, int rows, int
                 b += pm[u] * pm[u];
                 g += m[u] * pm[u];
             }
-#pragma unroll
-            for (int o = kLpc / 2; o > 0; o >>= 1) {
-                a += __shfl_xor(a, o, 64);
-                b += __shfl_xor(b, o, 64);
-                g += __shfl_xor(g, o, 64);
-            }
+            a = column_sum<kLpc>(a);
+            b = column_sum<kLpc>(b);
+            g = column_sum<kLpc>(g);
             const bool lower = c < partner;
             const W ap = lower ? a : b, aq = lower ? b : a;
-            if (valid && g != W(0) && fabs(g) > (W)conv * sqrt(ap * aq)) {
-                const W zeta = (aq - ap) / (W(2) * g);
-                const W t = (zeta >= W(0) ? W(1) : W(-1)) / (fabs(zeta) + sqrt(W(1) + zeta * zeta));
-                const W cs = W(1) / sqrt(W(1) + t * t), sn = cs * t;
+            if (valid && g * g > conv2 * (ap * aq)) {
+                W cs, sn;
+                jacobi_rotation(ap, aq, g, cs, sn);
+                if (sn != W(0)) {
 #pragma unroll
-                for (int u = 0; u < kNr; ++u) {
-                    m[u] = lower ? cs * m[u] - sn * pm[u] : sn * pm[u] + cs * m[u];
-                    z[u] = lower ? cs * z[u] - sn * pz[u] : sn * pz[u] + cs * z[u];
+                    for (int u = 0; u < kNr; ++u) {
+                        m[u] = lower ? cs * m[u] - sn * pm[u] : sn * pm[u] + cs * m[u];
+                        z[u] = lower ? cs * z[u] - sn * pz[u] : sn * pz[u] + cs * z[u];
+                    }
+                    rotated = true;
                 }
-                rotated = true;
             }
         }
         if (!__any(rotated)) break;
@@ -754,8 +803,7 @@ __device__ void wave_jacobi_lds(double* M, double* Z, double* nrm, int rows, int
         if (c < cols && row < cols) Z[row + c * kSK] = (double)z[u];
         nn += (double)m[u] * (double)m[u];
     }
-#pragma unroll
-    for (int o = kLpc / 2; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 64);
+    nn = column_sum<kLpc>(nn);
     if (c < cols && sub == 0) nrm[c] = sqrt(nn);
 }
 
@@ -865,7 +913,7 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
     __syncthreads();
     // the SVD of the small core runs in the factor precision (the Gram matrices and their
     // Cholesky factors stay FP64)
-    if (wave == 0 && qu > 0 && qv > 0) wave_jacobi_lds<kSK, T>(S.G[0], S.G[1], S.sig, qu, qv, f64 ? 1e-15 : 1e-7);
+    if (wave == 0 && qu > 0 && qv > 0) wave_jacobi_lds<kSK, T>(S.G[0], S.G[1], S.sig, qu, qv, f64 ? 1e-15 : 1e-6);
     __syncthreads();
     phase(3);
     for (int j = threadIdx.x; j < qv; j += kT) {

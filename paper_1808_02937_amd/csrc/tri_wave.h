@@ -23,6 +23,29 @@ __device__ inline double lane_bcast(double x, int s) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Lane exchange within a row of 16 lanes through the DPP operand modifier (no LDS round trip).
+// CTRL is a DPP control word: quad_perm(s0, s1, s2, s3) = s0 | s1 << 2 | s2 << 4 | s3 << 6
+// (lane i of each quad reads lane s_i), row_ror(n) = 0x120 + n (lane i of each row reads lane
+// (i + n) mod 16 of the row).
+constexpr int kDppXor1 = 0xB1;   // quad_perm(1, 0, 3, 2)
+constexpr int kDppXor2 = 0x4E;   // quad_perm(2, 3, 0, 1)
+constexpr int dpp_row_ror(int n) { return 0x120 + n; }
+template <int CTRL>
+__device__ inline int dpp_move(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ inline float dpp_move(float x) {
+    return __int_as_float(dpp_move<CTRL>(__float_as_int(x)));
+}
+template <int CTRL>
+__device__ inline double dpp_move(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_move<CTRL>((int)(b & 0xffffffffll));
+    const int hi = dpp_move<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // X (n x w; element (i, j) at X[i*xrs + j*xcs]) <- T^{-1} X, T n x n (element (i, s) at
 // Tm[i*trs + s*tcs]), lower or upper, unit diagonal or not; n <= 64. The calling wavefront
 // `wave` of `nwaves` solves columns wave, wave + nwaves, ...
