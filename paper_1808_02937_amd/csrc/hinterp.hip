@@ -45,7 +45,8 @@ template <int KS>
 struct LrsLds {
     static constexpr int K = KS;                     // widest k'
     static constexpr int CH = KS <= 16 ? 64 : 32;    // rows per staged chunk
-    double A[2][CH * KS];   // staged rows of both sides (row-major, stride K); later C_u, C_v
+    static constexpr int LD = KS + 1;                // row stride of staged rows (odd: no bank conflicts along a column)
+    double A[2][CH * LD];   // staged rows of both sides (row-major, stride LD); later C_u, C_v (ld K)
     double G[2][KS * KS];   // Gram matrices; then the core M and rotations Z; then C_u, C_v
     double R[2][KS * KS];   // Cholesky factors R[a][j] (row a, original column j)
     double sig[KS];
@@ -557,20 +558,48 @@ struct Side {
     }
 };
 
-// stage rows [c0, c0 + kCH) of both sides into LDS (row-major, stride kSK; zero beyond the rows)
+// Rows [c0, c0 + kCH) of both sides, staged through registers: element t of a thread is side
+// s = t / (kEl / 2), column c and chunk row rr, consecutive threads along rr (coalesced down the
+// factor columns). All loads of a chunk are issued before any is used (addresses of elements
+// outside the block are clamped to the factor's first entry), so a chunk costs one memory latency,
+// and the next chunk is loaded while the current one is used.
+template <class LS>
+struct RowChunk {
+    static constexpr int kEl = 2 * LS::CH * LS::K / kT;
+    static_assert(kEl * kT == 2 * LS::CH * LS::K, "a chunk is a whole number of elements per thread");
+};
 template <class T, class LS>
-__device__ void stage_rows(const Side<T>& su, const Side<T>& sv, int c0, int kp, LS& S) {
-    constexpr int kSK = LS::K, kCH = LS::CH;
-    for (int idx = threadIdx.x; idx < 2 * kCH * kp; idx += kT) {
-        const int s = idx / (kCH * kp), rem = idx % (kCH * kp);
+__device__ __attribute__((always_inline)) inline void load_rows(const Side<T>& su, const Side<T>& sv, int c0, int kp,
+                                                                T* v) {
+    constexpr int kSK = LS::K, kCH = LS::CH, kEl = RowChunk<LS>::kEl;
+    // opaque thread index: the per-element addresses are formed here, not hoisted out of the
+    // caller's chunk loop and held in registers across it
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+#pragma unroll
+    for (int t = 0; t < kEl; ++t) {
+        const Side<T>& sd = t < kEl / 2 ? su : sv;
+        const int rem = (tid + t * kT) % (kCH * kSK);
+        const int c = rem / kCH, i = c0 + rem % kCH;
+        const bool ok = i < sd.rows && c < kp;
+        const T* p = c < sd.kc ? sd.F + i + (int64_t)c * sd.ldf
+                               : sd.G + (int64_t)i * sd.grs + (int64_t)(c - sd.kc) * sd.gcs;
+        v[t] = gmem(ok ? p : sd.F)[0];
+    }
+}
+template <class T, class LS>
+__device__ __attribute__((always_inline)) inline void store_rows(const Side<T>& su, const Side<T>& sv, int c0, int kp,
+                                                                 const T* v, LS& S) {
+    constexpr int kSK = LS::K, kCH = LS::CH, kLD = LS::LD, kEl = RowChunk<LS>::kEl;
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+#pragma unroll
+    for (int t = 0; t < kEl; ++t) {
+        const Side<T>& sd = t < kEl / 2 ? su : sv;
+        const int rem = (tid + t * kT) % (kCH * kSK);
         const int c = rem / kCH, rr = rem % kCH, i = c0 + rr;
-        double v = 0.0;
-        if (s == 0) {
-            if (i < su.rows) v = su.at(i, c);
-        } else {
-            if (i < sv.rows) v = sv.at(i, c);
-        }
-        S.A[s][rr * kSK + c] = v;
+        const bool ok = i < sd.rows && c < kp;
+        S.A[t < kEl / 2 ? 0 : 1][rr * kLD + c] = ok ? (c < sd.kc ? (double)v[t] : sd.sgn * (double)v[t]) : 0.0;
     }
 }
 
@@ -590,7 +619,7 @@ __device__ inline void gram_clear(LS& S) {
 }
 template <class LS>
 __device__ inline void gram_accumulate(LS& S, int k0, int k1) {
-    constexpr int kSK = LS::K, kCH = LS::CH;
+    constexpr int kSK = LS::K, kCH = LS::CH, kLD = LS::LD;
     const int n0 = k0 * (k0 + 1) / 2, n1 = k1 * (k1 + 1) / 2;
     for (int e = threadIdx.x; e < n0 + n1; e += kT) {
         const int s = e < n0 ? 0 : 1, el = e < n0 ? e : e - n0;
@@ -598,8 +627,8 @@ __device__ inline void gram_accumulate(LS& S, int k0, int k1) {
         tri_index(el, p, q);
         const double* A = S.A[s];
         double a = 0.0;
-#pragma unroll 4
-        for (int rr = 0; rr < kCH; ++rr) a += A[rr * kSK + p] * A[rr * kSK + q];
+#pragma unroll 8
+        for (int rr = 0; rr < kCH; ++rr) a += A[rr * kLD + p] * A[rr * kLD + q];
         S.G[s][p * kSK + q] += a;
     }
 }
@@ -651,8 +680,18 @@ __device__ inline void argmax_rows(double& dv, int& pj) {
 // is taken next and the factorisation stops when it falls to floor_rel times the largest initial
 // diagonal; without it the order is 0, 1, ... On return R[a][j] (a < q, LDS) holds row a of R in
 // original column j, perm[a] the a-th pivot and *q the rank.
+template <class T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+// LDS view of a pointer into the workgroup's shared memory (accesses become LDS instructions in a
+// function that is not inlined into the kernel)
+template <class T>
+__device__ inline lds_ptr<T> lmem(T* p) {
+    return (lds_ptr<T>)p;
+}
+
 template <int kSK>
-__device__ void wave_cholesky(const double* G, double* R, int* perm, int* q_out, int k, bool pivot, double floor_rel) {
+__device__ __attribute__((noinline)) void wave_cholesky(lds_ptr<const double> G, lds_ptr<double> R, lds_ptr<int> perm,
+                                                        lds_ptr<int> q_out, int k, bool pivot, double floor_rel) {
     const int j = threadIdx.x & 63;
     const bool in = j < k;
     double g[kSK];
@@ -687,10 +726,9 @@ __device__ void wave_cholesky(const double* G, double* R, int* perm, int* q_out,
                 const double lj = in ? (j == p ? lp : (rem ? gp * inv : 0.0)) : 0.0;
                 if (in) R[a * kSK + j] = lj;
                 if (j == 0) perm[a] = p;
-                if (rem) {
+                if (rem) {   // lj is 0 on lanes k .. kSK-1: their entries of g stay untouched
 #pragma unroll
-                    for (int i = 0; i < kSK; ++i)
-                        if (i < k) g[i] -= lane_bcast(lj, i) * lj;
+                    for (int i = 0; i < kSK; ++i) g[i] -= lane_bcast(lj, i) * lj;
                     dj -= lj * lj;
                 }
             }
@@ -811,7 +849,8 @@ template <class T, class SH>
 __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const OpRec& o, SH& sh, const LRBlockDev& L, int kc, int kx) {
     auto& S = sh.ls;
     constexpr int kSK = SH::kSmall;
-    constexpr int kCH = decltype(sh.ls)::CH;
+    using LS = typename std::remove_reference<decltype(S)>::type;
+    constexpr int kCH = LS::CH, kLD = LS::LD, kEl = RowChunk<LS>::kEl;
     T* U = d.arena + L.uoff;
     T* V = d.arena + L.voff;
     const int m = L.m, n = L.n, kp = kc + kx;
@@ -822,19 +861,25 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
     const Side<T> su{U, m, kc, Xp, o.v[0].rs, o.v[0].cs, -1.0, m};
     const Side<T> sv{V, n, kc, Yp, o.v[1].rs, o.v[1].cs, 1.0, n};
     const int rmax = max(m, n);
-    unsigned long long tph = (d.prof && threadIdx.x == 0) ? wall_clock64() : 0ull;
+    unsigned long long* const prof = d.prof;   // read once: later stores may alias the instance
+    const double tol = d.tol;
+    const int kmax = d.kmax;
+    unsigned long long tph = (prof && threadIdx.x == 0) ? wall_clock64() : 0ull;
     auto phase = [&](int k) {   // op profile: time of each phase (thread 0)
-        if (d.prof && threadIdx.x == 0) {
+        if (prof && threadIdx.x == 0) {
             const unsigned long long t = wall_clock64();
-            atomicAdd(&d.prof[2 * kOpCodes + k], t - tph);
+            atomicAdd(&prof[2 * kOpCodes + k], t - tph);
             tph = t;
         }
     };
+    T rows[kEl];   // the chunk in flight
     // Gram matrices
     gram_clear(S);
+    load_rows<T, LS>(su, sv, 0, kp, rows);
     for (int c0 = 0; c0 < rmax; c0 += kCH) {
-        stage_rows(su, sv, c0, kp, S);
+        store_rows<T, LS>(su, sv, c0, kp, rows, S);
         __syncthreads();
+        if (c0 + kCH < rmax) load_rows<T, LS>(su, sv, c0 + kCH, kp, rows);
         gram_accumulate(S, kp, kp);
         __syncthreads();
     }
@@ -842,7 +887,9 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
     __syncthreads();
     phase(0);
     const double floor_rel = f64 ? 1e-14 : 1e-12;
-    if (wave < 2) wave_cholesky<kSK>(S.G[wave], S.R[wave], S.perm[wave], &S.q[wave], kp, true, floor_rel);
+    if (wave < 2)
+        wave_cholesky<kSK>(lmem<const double>(S.G[wave]), lmem(S.R[wave]), lmem(S.perm[wave]), lmem(&S.q[wave]), kp, true,
+                           floor_rel);
     __syncthreads();
     phase(1);
     if (f64) {
@@ -850,12 +897,14 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
         // Gram G2 = R2^T R2 and R <- R2 R
         const int q0 = S.q[0], q1 = S.q[1];
         gram_clear(S);
+        load_rows<T, LS>(su, sv, 0, kp, rows);
         for (int c0 = 0; c0 < rmax; c0 += kCH) {
-            stage_rows(su, sv, c0, kp, S);
+            store_rows<T, LS>(su, sv, c0, kp, rows, S);
             __syncthreads();
+            if (c0 + kCH < rmax) load_rows<T, LS>(su, sv, c0 + kCH, kp, rows);
             for (int idx = threadIdx.x; idx < 2 * kCH; idx += kT) {
                 const int s = idx / kCH, rr = idx % kCH, q = S.q[s];
-                double* row = &S.A[s][rr * kSK];
+                double* row = &S.A[s][rr * kLD];
                 double y[kSK];
 #pragma unroll
                 for (int b = 0; b < kSK; ++b) y[b] = 0.0;
@@ -882,7 +931,8 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
         __syncthreads();
         if (wave < 2) {
             // G2 (q x q) = L2 L2^T without pivoting, in A[wave] as scratch for R2 (row a, col b)
-            wave_cholesky<kSK>(S.G[wave], S.A[wave], S.perm2[wave], &S.q2[wave], S.q[wave], false, 1e-30);
+            wave_cholesky<kSK>(lmem<const double>(S.G[wave]), lmem(S.A[wave]), lmem(S.perm2[wave]), lmem(&S.q2[wave]),
+                               S.q[wave], false, 1e-30);
         }
         __syncthreads();
         // R <- R2 R (rows a < q2): R'[a][j] = sum_{b >= a} R2[a][b] R[b][j]; R2 row a in A[s][a*kSK + b]
@@ -928,9 +978,9 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
         if (qu > 0 && qv > 0) {
             const double smax = S.sig[sh.order[0]];
             if (smax > 0.0)
-                while (r < qv && S.sig[sh.order[r]] > d.tol * smax) ++r;
+                while (r < qv && S.sig[sh.order[r]] > tol * smax) ++r;
         }
-        if (r > d.kmax) r = d.kmax;
+        if (r > kmax) r = kmax;
         sh.r = r;
         const double K = kp;
         sh.lrsub_flops = (m + n) * K * (K + 1.0) * (f64 ? 3.0 : 1.0) + 2.0 * (m + n) * K * r + 2.0 * K * K * K / 3.0 +
@@ -963,14 +1013,16 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
     __syncthreads();
     phase(4);
     // U_C <- A_u C_u, V_C <- A_v C_v, chunk by chunk (a chunk is staged before its rows are written)
+    load_rows<T, LS>(su, sv, 0, kp, rows);
     for (int c0 = 0; c0 < rmax; c0 += kCH) {
-        stage_rows(su, sv, c0, kp, S);
+        store_rows<T, LS>(su, sv, c0, kp, rows, S);
         __syncthreads();
+        if (c0 + kCH < rmax) load_rows<T, LS>(su, sv, c0 + kCH, kp, rows);
         for (int idx = threadIdx.x; idx < 2 * kCH * r; idx += kT) {
             const int s = idx / (kCH * r), rem = idx % (kCH * r), rr = rem % kCH, c = rem / kCH, i = c0 + rr;
             if (i >= (s == 0 ? m : n)) continue;
             double v = 0.0;
-            for (int l = 0; l < kp; ++l) v += S.A[s][rr * kSK + l] * S.G[s][l * kSK + c];
+            for (int l = 0; l < kp; ++l) v += S.A[s][rr * kLD + l] * S.G[s][l * kSK + c];
             T* out = s == 0 ? U : V;
             out[i + (int64_t)c * (s == 0 ? m : n)] = (T)v;
         }

@@ -48,13 +48,6 @@ struct HsDepth<double, WC> {
     static constexpr int kD = WC == 1 ? 10 : WC == 2 ? 11 : WC == 4 ? 16 : 10;
 };
 
-// global-memory view of a pointer: loads through it are vector-memory loads counted by vmcnt
-// alone (a flat load also counts on the counter that LDS reads wait for)
-template <class T>
-__device__ inline const __attribute__((address_space(1))) T* gmem(const T* p) {
-    return (const __attribute__((address_space(1))) T*)p;
-}
-
 // 32 bytes per lane: a step record (same for every lane) or lane l's record of a step
 struct Vec8 {
     int a[8];

@@ -13,6 +13,13 @@
 
 namespace fde {
 
+// global-memory view of a pointer: loads through it are vector-memory loads counted by vmcnt
+// alone (a flat load also counts on the counter that LDS reads wait for)
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T* gmem(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+
 __device__ inline float lane_bcast(float x, int s) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), s));
 }
