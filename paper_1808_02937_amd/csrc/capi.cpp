@@ -71,6 +71,7 @@ void retire_oldest(Ctx* c) {
 Ctx::~Ctx() {
     (void)hipStreamSynchronize(stream);
     plans.clear();   // members holding blocks give them back before the cache is released
+    lu_tasks.reset();
     gl.reset();
     while (!staged.empty()) retire_oldest(this);
     for (hipEvent_t e : spare_events) (void)hipEventDestroy(e);

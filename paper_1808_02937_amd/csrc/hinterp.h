@@ -16,7 +16,6 @@ struct Inst {
     T* work;                  // temporaries
     T* rhs;                   // right-hand sides (Nd x nrhs, ld Nd) of an H-solve
     int* ranks;               // rank per low-rank block
-    const LRBlockDev* lr;     // low-rank block table
     T* scr;                   // recompression scratch (T); each OP_LRSUB uses its own part
     double* scrd;             // recompression scratch (FP64 core)
     const int* h2p;
@@ -67,9 +66,16 @@ constexpr int kHsolveMaxCols = 8;
 // largest dynamic LDS of one workgroup on the device (bytes)
 size_t device_lds_limit(int device);
 
-// one level of level-scheduled programs: workgroup b runs op tasks[b].y of instance tasks[b].x.
+// one op of a factorisation in a batch: its record (in the instance's device program), the
+// instance and the op's index in its program
+struct LevelTask {
+    const OpRec* op;
+    int inst, pc;
+};
+
+// one level of level-scheduled programs: workgroup b runs op tasks[b].pc of instance tasks[b].inst.
 // variant: widest recompression the programs can need -- 16 or 32 (small path only), 0 (any)
 template <class T>
-void launch_level(hipStream_t st, int ntasks, const Inst<T>* d_insts, const int2* d_tasks, int variant);
+void launch_level(hipStream_t st, int ntasks, const Inst<T>* d_insts, const LevelTask* d_tasks, int variant);
 
 }  // namespace fde

@@ -64,6 +64,8 @@ struct Shared {
         LrsLds<KS> ls;
         GemmLds<T> gm;
     };
+    OpRec op;        // level kernel: this workgroup's op, rank-dependent sizes resolved
+    Inst<T> inst;    // level kernel: its instance
     double red[kW][32];
     double dots[GENERAL ? kMaxKp : 1];
     int order[GENERAL ? kMaxKp : KS];
@@ -1037,9 +1039,10 @@ __device__ __attribute__((noinline)) void op_lrsub(const Inst<T>& d, const OpRec
     const int kx = dimval(d, o.dim[2]);
     if (threadIdx.x == 0) sh.lrsub_flops = 0.0;
     if (kx <= 0) return;
-    const LRBlockDev L = d.lr[o.blk];
-    if (d.ranks[L.slot] + kx <= SH::kSmall) {
-        op_lrsub_small(d, o, sh, L, d.ranks[L.slot], kx);
+    const LRBlockDev L = o.lb;
+    const int kc0 = L.rank >= 0 ? L.rank : d.ranks[L.slot];
+    if (kc0 + kx <= SH::kSmall) {
+        op_lrsub_small(d, o, sh, L, kc0, kx);
         return;
     }
     if constexpr (!SH::kGeneral) {
@@ -1052,7 +1055,7 @@ __device__ __attribute__((noinline)) void op_lrsub(const Inst<T>& d, const OpRec
     } else {
     T* U = d.arena + L.uoff;
     T* V = d.arena + L.voff;
-    const int m = L.m, n = L.n, kc = d.ranks[L.slot], kp = kc + kx;
+    const int m = L.m, n = L.n, kc = kc0, kp = kc + kx;
     const T* Xp = vptr(d, o.v[0]);
     const T* Yp = vptr(d, o.v[1]);
     const int xrs = o.v[0].rs, xcs = o.v[0].cs, yrs = o.v[1].rs, ycs = o.v[1].cs;
@@ -1151,13 +1154,12 @@ __device__ double op_flops(const Inst<T>& d, const OpRec& o) {
     }
 }
 
-// one op; false when a leaf pivot broke down (the status is set)
-// d and the op record are referenced where they live (global memory): the op functions are
-// separate (not inlined) functions, and a local copy handed to them by reference would be
+// op pc (record o); false when a leaf pivot broke down (the status is set). d and o are
+// referenced where they live (global memory, or the level kernel's LDS copies): the op functions
+// are separate (not inlined) functions, and a local copy handed to them by reference would be
 // written to every lane's scratch memory for each op
 template <class T, class SH>
-__device__ bool run_op(const Inst<T>& d, int pc, SH& sh, int step) {
-    const OpRec& o = d.ops[pc];
+__device__ bool run_op(const Inst<T>& d, const OpRec& o, int pc, SH& sh, int step) {
     unsigned long long t0 = 0;
     if (d.prof && threadIdx.x == 0) t0 = wall_clock64();
     double fl = 0.0;
@@ -1171,7 +1173,7 @@ __device__ bool run_op(const Inst<T>& d, int pc, SH& sh, int step) {
         case OP_GETRF: ok = op_getrf(d, o, sh, pc); break;
         case OP_LRMV: {
             // t = V^T X, then Y += alpha U t
-            const LRBlockDev L = d.lr[o.blk];
+            const LRBlockDev L = o.lb;
             const int rc = -2 - L.slot;
             OpRec g1{};
             g1.code = OP_GEMM;
@@ -1233,7 +1235,7 @@ __device__ bool run_op(const Inst<T>& d, int pc, SH& sh, int step) {
 template <class T, class SH>
 __device__ void run_program(const Inst<T>& d, SH& sh, int step) {
     for (int pc = 0; pc < d.nops; ++pc)
-        if (!run_op(d, pc, sh, step)) return;
+        if (!run_op(d, d.ops[pc], pc, sh, step)) return;
 }
 
 template <class T, int KS, bool GENERAL>
@@ -1250,17 +1252,41 @@ __global__ void __launch_bounds__(kT) k_interp_one(const Inst<T> d) {
 }
 
 // one level: the ops of a level are independent, earlier levels have completed (kernel order)
+// thread t < 4 of a workgroup whose op and instance sit in LDS: dimension t (< 3) of the op, or
+// (t == 3) the rank of its low-rank block, resolved from the rank slots
+template <class SH>
+__device__ inline void resolve_dims(SH& sh, int t) {
+    const bool lrb = sh.op.code == OP_LRSUB || sh.op.code == OP_LRMV;
+    const int code = t < 3 ? sh.op.dim[t] : (lrb ? -2 - sh.op.lb.slot : 0);
+    const int v = code >= 0 ? code : (code == -1 ? sh.inst.nrhs : gmem(sh.inst.ranks)[-2 - code]);
+    if (t < 3)
+        sh.op.dim[t] = v;
+    else if (lrb)
+        sh.op.lb.rank = v;
+}
+
 template <class T, int KS, bool GENERAL>
-__global__ void __launch_bounds__(kT) k_level(const Inst<T>* __restrict__ insts, const int2* __restrict__ tasks) {
+__global__ void __launch_bounds__(kT) k_level(const Inst<T>* __restrict__ insts, const LevelTask* __restrict__ tasks) {
     __shared__ Shared<T, KS, GENERAL> sh;
-    const int2 tk = tasks[blockIdx.x];
-    const Inst<T>& d = insts[tk.x];
-    // after a breakdown in an earlier level the rest of that factorisation is skipped; the
-    // status is read once and shared so that every thread takes the same branch
-    if (threadIdx.x == 0) sh.stop = d.status[0];
+    const LevelTask tk = tasks[blockIdx.x];
+    // one round of loads, in parallel: the op record and the instance (one word per thread)
+    constexpr int kOpW = sizeof(OpRec) / 4, kInstW = sizeof(Inst<T>) / 4;
+    static_assert(sizeof(OpRec) % 4 == 0 && sizeof(Inst<T>) % 4 == 0 && kOpW + kInstW < kT, "op and instance copies");
+    const int t = threadIdx.x;
+    if (t < kOpW)
+        reinterpret_cast<int*>(&sh.op)[t] = gmem(reinterpret_cast<const int*>(tk.op))[t];
+    else if (t < kOpW + kInstW)
+        reinterpret_cast<int*>(&sh.inst)[t - kOpW] = gmem(reinterpret_cast<const int*>(insts + tk.inst))[t - kOpW];
+    __syncthreads();
+    // after a breakdown in an earlier level the rest of that factorisation is skipped (the status
+    // is shared so that every thread takes the same branch); sizes given by ranks, and the rank of
+    // the op's low-rank block, are read once (ranks change only between levels: the ops of a level
+    // are independent)
+    if (t == 4) sh.stop = gmem(sh.inst.status)[0];
+    if (t < 4) resolve_dims(sh, t);
     __syncthreads();
     if (sh.stop != 0) return;
-    run_op(d, tk.y, sh, 0);
+    run_op(sh.inst, sh.op, tk.pc, sh, 0);
 }
 
 }  // namespace
@@ -1318,7 +1344,7 @@ template void launch_interp_one<float>(hipStream_t, const Inst<float>&);
 template void launch_interp_one<double>(hipStream_t, const Inst<double>&);
 
 template <class T>
-void launch_level(hipStream_t st, int ntasks, const Inst<T>* d_insts, const int2* d_tasks, int variant) {
+void launch_level(hipStream_t st, int ntasks, const Inst<T>* d_insts, const LevelTask* d_tasks, int variant) {
     if (ntasks <= 0) return;
     if (variant == 16)
         hipLaunchKernelGGL((k_level<T, 16, false>), dim3(ntasks), dim3(kT), 0, st, d_insts, d_tasks);
@@ -1328,7 +1354,7 @@ void launch_level(hipStream_t st, int ntasks, const Inst<T>* d_insts, const int2
         hipLaunchKernelGGL((k_level<T, 32, true>), dim3(ntasks), dim3(kT), 0, st, d_insts, d_tasks);
     FDE_LAUNCH_CHECK();
 }
-template void launch_level<float>(hipStream_t, int, const Inst<float>*, const int2*, int);
-template void launch_level<double>(hipStream_t, int, const Inst<double>*, const int2*, int);
+template void launch_level<float>(hipStream_t, int, const Inst<float>*, const LevelTask*, int);
+template void launch_level<double>(hipStream_t, int, const Inst<double>*, const LevelTask*, int);
 
 }  // namespace fde

@@ -24,7 +24,6 @@ struct Plan {
     bool sv_lds = false;   // every H-solve op works on all right-hand-side columns (LDS kernel usable)
     int lu_variant = 0;    // H-LU kernel variant: widest possible recompression 16, 32, or 0 (wider)
     DevBuf<OpRec> ops_lu, ops_sv;
-    DevBuf<LRBlockDev> lr;
     DevBuf<int> h2p;
     HsTables hs;            // leaf-step H-solve
     DevBuf<HsStep> d_hs_steps;
@@ -63,7 +62,6 @@ struct HLUObj {
         d.work = reinterpret_cast<T*>(solve ? sv_work.p : work_lu.p);
         d.rhs = reinterpret_cast<T*>(sv_rhs.p);
         d.ranks = ranks.p;
-        d.lr = plan->lr.p;
         d.scr = reinterpret_cast<T*>(scr.p);
         d.scrd = scrd.p;
         d.h2p = plan->h2p.p;

@@ -152,6 +152,46 @@ bool serial_requested() {
     return e && e[0] == '1';
 }
 
+// The ops of a batch of factorisations in level order (level l of every instance, then level
+// l + 1), with level offsets. It depends only on the plans, so the last one is kept in the context.
+struct BatchTasks {
+    std::vector<std::shared_ptr<const Plan>> plans;
+    DevBuf<LevelTask> tasks;
+    std::vector<int> loff;
+};
+
+const BatchTasks& batch_tasks(Ctx* c, const std::vector<HLUObj*>& fs) {
+    auto* cached = static_cast<BatchTasks*>(c->lu_tasks.get());
+    if (cached && cached->plans.size() == fs.size()) {
+        bool same = true;
+        for (size_t i = 0; i < fs.size() && same; ++i) same = cached->plans[i] == fs[i]->plan;
+        if (same) return *cached;
+    }
+    auto bt = std::make_shared<BatchTasks>();
+    for (HLUObj* f : fs) bt->plans.push_back(f->plan);
+    size_t nlev = 0, ntot = 0;
+    for (HLUObj* f : fs) {
+        nlev = std::max(nlev, f->plan->lu.level_off.size() - 1);
+        ntot += f->plan->lu.ops.size();
+    }
+    std::vector<LevelTask> tasks;
+    tasks.reserve(ntot);
+    bt->loff.assign(1, 0);
+    for (size_t l = 0; l < nlev; ++l) {
+        for (size_t i = 0; i < fs.size(); ++i) {
+            const Plan& P = *fs[i]->plan;
+            const std::vector<int>& lo = P.lu.level_off;
+            if (l + 1 >= lo.size()) continue;
+            for (int pc = lo[l]; pc < lo[l + 1]; ++pc)
+                tasks.push_back(LevelTask{P.ops_lu.p + pc, (int)i, pc});
+        }
+        bt->loff.push_back((int)tasks.size());
+    }
+    upload_vec(c, bt->tasks, tasks);
+    c->lu_tasks = bt;
+    return *bt;
+}
+
 // Factorise a batch of H-LUs of one precision. Level-scheduled: launch l runs level l of
 // every factorisation (one workgroup per op); FDE_HLU_SERIAL=1 runs each op list in one
 // workgroup instead (the same ops in the same level order, one at a time).
@@ -168,26 +208,10 @@ void factor_batch_run(Ctx* c, std::vector<HLUObj*>& fs, const char* what) {
         if (v == 0 || variant == 0) variant = 0;
         else variant = std::max(variant, v);
     }
-    std::vector<int2> tasks;
-    std::vector<int> loff(1, 0);
-    if (!serial) {
-        size_t nlev = 0, ntot = 0;
-        for (HLUObj* f : fs) {
-            nlev = std::max(nlev, f->plan->lu.level_off.size() - 1);
-            ntot += f->plan->lu.ops.size();
-        }
-        tasks.reserve(ntot);
-        for (size_t l = 0; l < nlev; ++l) {
-            for (size_t i = 0; i < fs.size(); ++i) {
-                const std::vector<int>& lo = fs[i]->plan->lu.level_off;
-                if (l + 1 >= lo.size()) continue;
-                for (int pc = lo[l]; pc < lo[l + 1]; ++pc) tasks.push_back(make_int2((int)i, pc));
-            }
-            loff.push_back((int)tasks.size());
-        }
-    }
-    DevBuf<int2> d_tasks;
-    upload_vec(c, d_tasks, tasks);
+    static const std::vector<int> no_levels(1, 0);
+    const BatchTasks* bt = serial ? nullptr : &batch_tasks(c, fs);
+    const std::vector<int>& loff = bt ? bt->loff : no_levels;
+    const LevelTask* d_tasks = bt ? bt->tasks.p : nullptr;
     EventPair ev;
     const char* pl = getenv("FDE_PROFILE_LEVELS");
     const bool prof_levels = pl && pl[0] == '1' && !serial;
@@ -202,7 +226,7 @@ void factor_batch_run(Ctx* c, std::vector<HLUObj*>& fs, const char* what) {
     } else {
         for (size_t l = 0; l + 1 < loff.size(); ++l) {
             if (prof_levels) FDE_HIP(hipEventRecord(lev_ev[l], c->stream));
-            launch_level<T>(c->stream, loff[l + 1] - loff[l], d_ins.p, d_tasks.p + loff[l], variant);
+            launch_level<T>(c->stream, loff[l + 1] - loff[l], d_ins.p, d_tasks + loff[l], variant);
         }
         if (prof_levels) FDE_HIP(hipEventRecord(lev_ev.back(), c->stream));
     }
@@ -407,14 +431,20 @@ std::shared_ptr<const Plan> get_plan(Ctx* c, const HTree& hmt, int kmax) {
     auto p = std::make_shared<Plan>();
     make_plan_host(hmt, kmax, *p, false);
     upload_vec(c, p->h2p, p->t.h2p);
-    upload_vec(c, p->ops_lu, p->lu.ops);
-    upload_vec(c, p->ops_sv, p->sv.ops);
     std::vector<LRBlockDev> lrt;
     for (int b : p->t.lr_blocks) {
         const Block& B = p->t.bl[b];
-        lrt.push_back(LRBlockDev{B.uoff, B.voff, p->t.cl[B.tau].size(), p->t.cl[B.sigma].size(), B.slot, 0});
+        lrt.push_back(LRBlockDev{B.uoff, B.voff, (int)p->t.cl[B.tau].size(), (int)p->t.cl[B.sigma].size(), B.slot, -1});
     }
-    upload_vec(c, p->lr, lrt);
+    // the device copy of a program carries the record of the block each LRSUB / LRMV works on
+    auto device_ops = [&](const Program& pr) {
+        std::vector<OpRec> v = pr.ops;
+        for (OpRec& o : v)
+            if ((o.code == OP_LRSUB || o.code == OP_LRMV) && o.blk >= 0) o.lb = lrt[o.blk];
+        return v;
+    };
+    upload_vec(c, p->ops_lu, device_ops(p->lu));
+    upload_vec(c, p->ops_sv, device_ops(p->sv));
     upload_vec(c, p->d_hs_steps, p->hs.steps);
     upload_vec(c, p->d_hs_recs, p->hs.recs);
     for (const LRBlockDev& b : lrt) p->lr_rows.push_back(std::max(b.m, b.n));

@@ -64,6 +64,13 @@ struct View {
     int64_t off;
 };
 
+// a low-rank block as an op on it sees it: factor offsets in the arena, rows, columns, rank slot;
+// rank >= 0 is its rank when the op runs (resolved on the device), -1 to read it from the slot
+struct LRBlockDev {
+    int64_t uoff, voff;
+    int m, n, slot, rank;
+};
+
 struct OpRec {
     int code;
     int flags;         // TRSM: bit0 lower, bit1 unit diagonal
@@ -73,11 +80,7 @@ struct OpRec {
     View v[3];         // GEMM: C, A, B; TRSM: X, T; GETRF: A; LRSUB: X, Y; ZERO: X; LRMV: Y, X, t
     int64_t sofs_t;    // LRSUB: private scratch (elements of the factor type, then doubles)
     int64_t sofs_d;
-};
-
-struct LRBlockDev {    // device table for OP_LRSUB
-    int64_t uoff, voff;
-    int m, n, slot, pad;
+    LRBlockDev lb;     // LRSUB, LRMV: block blk (filled in the device copy of a program)
 };
 
 struct TempRegion {
@@ -94,6 +97,11 @@ struct Program {
     std::vector<int> level_off;
     std::vector<int> origin;         // program-order index of every scheduled op
     int64_t scr_t = 0, scr_d = 0;    // recompression scratch of one level (factor type, doubles)
+    // dependencies (schedule_levels): scheduled op i may start once the scheduled ops
+    // deps[dep_off[i] .. dep_off[i+1]) have finished (all earlier in the level order). They cover
+    // every conflicting access to the same memory, temporaries sharing memory included; recompression
+    // scratch is private to a level and not covered.
+    std::vector<int> dep_off, deps;
 };
 
 // --------------------------------------------------------------- leaf-step H-solve

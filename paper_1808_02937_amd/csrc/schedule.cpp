@@ -104,10 +104,19 @@ class Regions {
     int slot0_ = 0;
 };
 
-inline bool overlap(const Rect& a, const Acc& b) {
+// an earlier access as the dependency list sees it: every op on its own (no merged reads)
+struct OpAcc {
+    int r0, r1, c0, c1;
+    int pc;
+    bool write;
+};
+
+template <class A>
+inline bool overlap(const Rect& a, const A& b) {
     return a.r0 < b.r1 && b.r0 < a.r1 && a.c0 < b.c1 && b.c0 < a.c1;
 }
-inline bool contains(const Rect& a, const Acc& b) {
+template <class A>
+inline bool contains(const Rect& a, const A& b) {
     return a.r0 <= b.r0 && b.r1 <= a.r1 && a.c0 <= b.c0 && b.c1 <= a.c1;
 }
 
@@ -168,11 +177,27 @@ void schedule_levels(const HTree& hm, Program& prog) {
     const size_t nops = prog.ops.size();
     Regions R(hm, prog);
     std::vector<std::vector<Acc>> hist(R.size());
+    std::vector<std::vector<OpAcc>> ohist(R.size());
+    std::vector<std::vector<int>> preds(nops);   // program order
     std::vector<int> level(nops, 0);
     std::vector<Rect> rd, wr;
     int nlev = 0;
     for (size_t pc = 0; pc < nops; ++pc) {
         accesses(hm, R, prog.ops[pc], rd, wr);
+        // dependencies: the last writes of what the op reads, every access since of what it writes
+        std::vector<int>& pp = preds[pc];
+        for (const Rect& x : rd)
+            for (const OpAcc& a : ohist[x.region])
+                if (a.write && overlap(x, a)) pp.push_back(a.pc);
+        for (const Rect& x : wr)
+            for (const OpAcc& a : ohist[x.region])
+                if (overlap(x, a)) pp.push_back(a.pc);
+        for (const Rect& x : wr) {
+            auto& h = ohist[x.region];
+            h.erase(std::remove_if(h.begin(), h.end(), [&](const OpAcc& a) { return contains(x, a); }), h.end());
+        }
+        for (const Rect& x : rd) ohist[x.region].push_back(OpAcc{x.r0, x.r1, x.c0, x.c1, (int)pc, false});
+        for (const Rect& x : wr) ohist[x.region].push_back(OpAcc{x.r0, x.r1, x.c0, x.c1, (int)pc, true});
         int L = 0;
         for (const Rect& x : rd)
             for (const Acc& a : hist[x.region])
@@ -211,11 +236,13 @@ void schedule_levels(const HTree& hm, Program& prog) {
         auto it = std::upper_bound(tstart.begin(), tstart.end(), off);
         return (size_t)(it - tstart.begin()) - 1;
     };
+    std::vector<std::vector<int>> temp_ops(nt);   // ops (program order) that use each temporary
     auto touch = [&](size_t pc, const View& v) {
         if (v.base != B_WORK || nt == 0) return;
         const size_t t = temp_of(v.off);
         first[t] = std::min(first[t], level[pc]);
         last[t] = std::max(last[t], level[pc]);
+        if (temp_ops[t].empty() || temp_ops[t].back() != (int)pc) temp_ops[t].push_back((int)pc);
     };
     auto views_used = [](const OpRec& o) {
         switch (o.code) {
@@ -235,6 +262,7 @@ void schedule_levels(const HTree& hm, Program& prog) {
     using Live = std::pair<int, size_t>;   // (last level, temp)
     std::priority_queue<Live, std::vector<Live>, std::greater<Live>> live;
     int64_t top = 0;
+    std::map<int64_t, size_t> owner;   // offset -> temporary that used the memory last
     for (size_t t : torder) {
         if (first[t] > last[t]) continue;   // never used
         while (!live.empty() && live.top().first < first[t]) {
@@ -247,11 +275,15 @@ void schedule_levels(const HTree& hm, Program& prog) {
         if (!fl.empty()) {
             newoff[t] = fl.back();
             fl.pop_back();
+            // memory handed on: every op on t waits for every op on its previous owner
+            for (int pc : temp_ops[t])
+                for (int q : temp_ops[owner.at(newoff[t])]) preds[pc].push_back(q);
         } else {
             newoff[t] = top;
             top += sz;
         }
         live.push(Live{last[t], t});
+        owner[newoff[t]] = t;
     }
     for (size_t pc = 0; pc < nops; ++pc) {
         OpRec& o = prog.ops[pc];
@@ -276,6 +308,23 @@ void schedule_levels(const HTree& hm, Program& prog) {
         prog.origin[i] = (int)idx[i];
     }
     prog.ops.swap(ops);
+    // dependency lists in the level order (sorted, no repeats)
+    {
+        std::vector<int> where(nops);
+        for (size_t i = 0; i < nops; ++i) where[idx[i]] = (int)i;
+        prog.dep_off.assign(nops + 1, 0);
+        prog.deps.clear();
+        for (size_t i = 0; i < nops; ++i) {
+            std::vector<int> d;
+            for (int q : preds[idx[i]]) d.push_back(where[q]);
+            std::sort(d.begin(), d.end());
+            d.erase(std::unique(d.begin(), d.end()), d.end());
+            for (int q : d)
+                if (q >= (int)i) fail(FDE_EDEVICE, "schedule: op %zu depends on a later op", i);
+            prog.deps.insert(prog.deps.end(), d.begin(), d.end());
+            prog.dep_off[i + 1] = (int)prog.deps.size();
+        }
+    }
     prog.level_off.assign(nlev + 1, 0);
     for (size_t i = 0; i < nops; ++i) prog.level_off[level[idx[i]]]++;   // counts at index level
     // counts sit at 1..nlev; turn into offsets of levels 0..nlev-1
@@ -305,6 +354,115 @@ void schedule_levels(const HTree& hm, Program& prog) {
     prog.scr_t = std::max<int64_t>(prog.scr_t, 1);
     prog.scr_d = std::max<int64_t>(prog.scr_d, 1);
 }
+
+namespace {
+
+// memory an op touches, element by element: views (m x n, read or written) and rank slots, with
+// dynamic dimensions at their bounds (the views of recompression scratch are not included)
+struct Use {
+    View v;
+    int64_t m, n;
+    bool write;
+};
+void op_uses(const HTree& hm, const OpRec& o, size_t pc, std::vector<Use>& uses, std::vector<std::pair<int, bool>>& slots) {
+    auto dimv = [&](int d) -> int64_t { return d >= 0 ? d : hm.kmax; };
+    uses.clear();
+    slots.clear();
+    for (int k = 0; k < 3; ++k)
+        if (o.dim[k] <= -2) slots.push_back({-2 - o.dim[k], false});
+    switch (o.code) {
+        case OP_GEMM: {
+            const int64_t m = dimv(o.dim[0]), n = dimv(o.dim[1]), k = dimv(o.dim[2]);
+            uses.push_back({o.v[1], m, k, false});
+            uses.push_back({o.v[2], k, n, false});
+            uses.push_back({o.v[0], m, n, true});
+            break;
+        }
+        case OP_TRSM:
+            uses.push_back({o.v[1], dimv(o.dim[0]), dimv(o.dim[0]), false});
+            uses.push_back({o.v[0], dimv(o.dim[0]), dimv(o.dim[1]), true});
+            break;
+        case OP_GETRF: uses.push_back({o.v[0], o.dim[0], o.dim[0], true}); break;
+        case OP_ZERO: uses.push_back({o.v[0], dimv(o.dim[0]), dimv(o.dim[1]), true}); break;
+        case OP_LRSUB: {
+            const Block& b = hm.bl[hm.lr_blocks[o.blk]];
+            const int64_t m = hm.cl[b.tau].size(), n = hm.cl[b.sigma].size(), k = dimv(o.dim[2]);
+            uses.push_back({o.v[0], m, k, false});
+            uses.push_back({o.v[1], n, k, false});
+            uses.push_back({View{B_ARENA, 1, (int)m, b.uoff}, m, hm.kmax, true});
+            uses.push_back({View{B_ARENA, 1, (int)n, b.voff}, n, hm.kmax, true});
+            slots.push_back({b.slot, true});
+            break;
+        }
+        default: fail(FDE_EDEVICE, "schedule check: op %zu has code %d", pc, o.code);
+    }
+}
+
+// every element of a use, as an index into [arena | work space]
+template <class F>
+void each_element(const Use& u, int64_t AE, F&& fn) {
+    for (int64_t j = 0; j < u.n; ++j)
+        for (int64_t i = 0; i < u.m; ++i) {
+            const int64_t o = u.v.off + i * u.v.rs + j * u.v.cs;
+            fn(u.v.base == B_ARENA ? o : AE + o);
+        }
+}
+
+// Dependency lists: replay the scheduled program in its level order over the memory it really
+// uses (temporaries sharing memory included) and verify that every pair of conflicting accesses is
+// ordered by the dependency graph (the earlier op is an ancestor of the later one). Ancestor sets
+// are quadratic in the op count: programs above 20000 ops get only the cheap checks.
+void check_deps(const HTree& hm, const Program& sp) {
+    const size_t nops = sp.ops.size();
+    if (sp.dep_off.size() != nops + 1 || (size_t)sp.dep_off.back() != sp.deps.size())
+        fail(FDE_EDEVICE, "dependency check: table does not cover the program");
+    for (size_t i = 0; i < nops; ++i)
+        for (int k = sp.dep_off[i]; k < sp.dep_off[i + 1]; ++k)
+            if (sp.deps[k] < 0 || (size_t)sp.deps[k] >= i) fail(FDE_EDEVICE, "dependency check: op %zu waits for a later op", i);
+    if (nops > 20000) return;
+    const size_t W = (nops + 63) / 64;
+    std::vector<uint64_t> anc(nops * W, 0);
+    for (size_t i = 0; i < nops; ++i)
+        for (int k = sp.dep_off[i]; k < sp.dep_off[i + 1]; ++k) {
+            const size_t q = sp.deps[k];
+            for (size_t w = 0; w < W; ++w) anc[i * W + w] |= anc[q * W + w];
+            anc[i * W + q / 64] |= 1ull << (q % 64);
+        }
+    auto ancestor = [&](size_t q, size_t i) { return (anc[i * W + q / 64] >> (q % 64)) & 1ull; };
+    const int64_t AE = hm.arena_elems, WE = sp.work_elems, NS = hm.nslots;
+    std::vector<int> lastw(AE + WE + NS, -1);
+    std::vector<std::vector<int>> readers(AE + WE + NS);
+    std::vector<Use> uses;
+    std::vector<std::pair<int, bool>> slots;
+    for (size_t i = 0; i < nops; ++i) {
+        op_uses(hm, sp.ops[i], i, uses, slots);
+        auto verify = [&](int64_t e, bool write) {
+            if (e < 0 || e >= AE + WE + NS) fail(FDE_EDEVICE, "dependency check: op %zu outside its memory", i);
+            if (lastw[e] >= 0 && (size_t)lastw[e] != i && !ancestor(lastw[e], i))
+                fail(FDE_EDEVICE, "dependency check: op %zu does not wait for op %d", i, lastw[e]);
+            if (write)
+                for (int r : readers[e])
+                    if ((size_t)r != i && !ancestor(r, i)) fail(FDE_EDEVICE, "dependency check: op %zu does not wait for op %d", i, r);
+        };
+        for (const Use& u : uses) each_element(u, AE, [&](int64_t e) { verify(e, u.write); });
+        for (auto& sl : slots) verify(AE + WE + sl.first, sl.second);
+        auto record = [&](int64_t e, bool write) {
+            if (write) {
+                lastw[e] = (int)i;
+                readers[e].clear();
+            } else if (readers[e].empty() || readers[e].back() != (int)i) {
+                readers[e].push_back((int)i);
+            }
+        };
+        for (const Use& u : uses)
+            if (!u.write) each_element(u, AE, [&](int64_t e) { record(e, false); });
+        for (const Use& u : uses)
+            if (u.write) each_element(u, AE, [&](int64_t e) { record(e, true); });
+        for (auto& sl : slots) record(AE + WE + sl.first, sl.second);
+    }
+}
+
+}  // namespace
 
 // Independent check: replay the original program element by element and verify that every
 // pair of conflicting accesses is ordered by the levels of the scheduled ops, and that no two
@@ -338,56 +496,15 @@ void check_schedule(const HTree& hm, const Program& original, const Program& sch
     // element-wise replay in program order over the arena, the slots and the ORIGINAL temporaries
     const int64_t AE = hm.arena_elems, WE = original.work_elems, NS = hm.nslots;
     std::vector<int> lw(AE + WE + NS, 0), lr(AE + WE + NS, 0);
-    auto dimv = [&](int d) -> int64_t { return d >= 0 ? d : hm.kmax; };
-    struct Use {
-        View v;
-        int64_t m, n;
-        bool write;
-    };
     std::vector<Use> uses;
     std::vector<std::pair<int, bool>> slots;
     // every access of an op is checked against the earlier ops before any of them is recorded
     // (an op may read and write the same elements)
-    auto each = [&](const Use& u, auto&& fn) {
-        for (int64_t j = 0; j < u.n; ++j)
-            for (int64_t i = 0; i < u.m; ++i) {
-                const int64_t o = u.v.off + i * u.v.rs + j * u.v.cs;
-                fn(u.v.base == B_ARENA ? o : AE + o);
-            }
-    };
+    auto each = [&](const Use& u, auto&& fn) { each_element(u, AE, fn); };
     for (size_t pc = 0; pc < nops; ++pc) {
         const OpRec& o = original.ops[pc];
         const int L = level[pc];
-        uses.clear();
-        slots.clear();
-        for (int k = 0; k < 3; ++k)
-            if (o.dim[k] <= -2) slots.push_back({-2 - o.dim[k], false});
-        switch (o.code) {
-            case OP_GEMM: {
-                const int64_t m = dimv(o.dim[0]), n = dimv(o.dim[1]), k = dimv(o.dim[2]);
-                uses.push_back({o.v[1], m, k, false});
-                uses.push_back({o.v[2], k, n, false});
-                uses.push_back({o.v[0], m, n, true});
-                break;
-            }
-            case OP_TRSM:
-                uses.push_back({o.v[1], dimv(o.dim[0]), dimv(o.dim[0]), false});
-                uses.push_back({o.v[0], dimv(o.dim[0]), dimv(o.dim[1]), true});
-                break;
-            case OP_GETRF: uses.push_back({o.v[0], o.dim[0], o.dim[0], true}); break;
-            case OP_ZERO: uses.push_back({o.v[0], dimv(o.dim[0]), dimv(o.dim[1]), true}); break;
-            case OP_LRSUB: {
-                const Block& b = hm.bl[hm.lr_blocks[o.blk]];
-                const int64_t m = hm.cl[b.tau].size(), n = hm.cl[b.sigma].size(), k = dimv(o.dim[2]);
-                uses.push_back({o.v[0], m, k, false});
-                uses.push_back({o.v[1], n, k, false});
-                uses.push_back({View{B_ARENA, 1, (int)m, b.uoff}, m, hm.kmax, true});
-                uses.push_back({View{B_ARENA, 1, (int)n, b.voff}, n, hm.kmax, true});
-                slots.push_back({b.slot, true});
-                break;
-            }
-            default: fail(FDE_EDEVICE, "schedule check: op code %d", o.code);
-        }
+        op_uses(hm, o, pc, uses, slots);
         auto verify = [&](int64_t e, bool write) {
             if (e < 0 || e >= AE + WE + NS) fail(FDE_EDEVICE, "schedule check: op %zu outside its memory", pc);
             if (L <= lw[e] || (write && L <= lr[e]))
@@ -451,6 +568,7 @@ void check_schedule(const HTree& hm, const Program& original, const Program& sch
                 fail(FDE_EDEVICE, "schedule check: temporaries %zu and %zu share memory while both live", t, u);
         }
     }
+    check_deps(hm, scheduled);
 }
 
 }  // namespace fde
