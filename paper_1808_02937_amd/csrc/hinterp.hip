@@ -145,40 +145,53 @@ __device__ __attribute__((noinline)) void op_gemm(const Inst<T>& d, const OpRec&
     if (m <= 0 || n <= 0) return;
     const int t = threadIdx.x;
     if (m >= 16 && n >= 16 && k >= 4) {
+        // The loads of an operand's stage are issued before any is used (addresses of elements
+        // outside the operand are clamped to its first entry), and the 16 entries of C a thread
+        // updates are read together after the products: a tile costs a few memory latencies
+        // rather than one per element.
         GemmLds<T>& L = sh.gm;
+        constexpr int kEl = kGT * kGK / kT;   // tile elements per thread and operand
         const int ti = t % 16, tj = t / 16;   // rows 4 ti .. 4 ti + 3, columns 4 tj .. 4 tj + 3 of a tile
         for (int i0 = 0; i0 < m; i0 += kGT)
             for (int j0 = 0; j0 < n; j0 += kGT) {
-                T acc[4][4];
+                T acc[16];
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+                for (int e = 0; e < 16; ++e) acc[e] = T(0);
                 for (int l0 = 0; l0 < k; l0 += kGK) {
                     // stage: consecutive threads along whichever index is contiguous in memory
-                    for (int idx = t; idx < kGT * kGK; idx += kT) {
-                        int i, l;
-                        if (ars == 1) {
-                            i = idx % kGT;
-                            l = idx / kGT;
-                        } else {
-                            l = idx % kGK;
-                            i = idx / kGK;
+                    int tid = t;   // opaque: element addresses are formed here, not held across the loops
+                    asm volatile("" : "+v"(tid));
+                    {
+                        T v[kEl];
+#pragma unroll
+                        for (int e = 0; e < kEl; ++e) {
+                            const int idx = tid + e * kT;
+                            const int i = ars == 1 ? idx % kGT : idx / kGK, l = ars == 1 ? idx / kGT : idx % kGK;
+                            const bool ok = i0 + i < m && l0 + l < k;
+                            v[e] = gmem(A)[ok ? (int64_t)(i0 + i) * ars + (int64_t)(l0 + l) * acs : 0];
                         }
-                        const int gi = i0 + i, gl = l0 + l;
-                        L.A[i][l] = (gi < m && gl < k) ? A[(int64_t)gi * ars + (int64_t)gl * acs] : T(0);
+#pragma unroll
+                        for (int e = 0; e < kEl; ++e) {
+                            const int idx = tid + e * kT;
+                            const int i = ars == 1 ? idx % kGT : idx / kGK, l = ars == 1 ? idx / kGT : idx % kGK;
+                            L.A[i][l] = (i0 + i < m && l0 + l < k) ? v[e] : T(0);
+                        }
                     }
-                    for (int idx = t; idx < kGK * kGT; idx += kT) {
-                        int l, j;
-                        if (brs == 1) {
-                            l = idx % kGK;
-                            j = idx / kGK;
-                        } else {
-                            j = idx % kGT;
-                            l = idx / kGT;
+                    {
+                        T v[kEl];
+#pragma unroll
+                        for (int e = 0; e < kEl; ++e) {
+                            const int idx = tid + e * kT;
+                            const int l = brs == 1 ? idx % kGK : idx / kGT, j = brs == 1 ? idx / kGK : idx % kGT;
+                            const bool ok = l0 + l < k && j0 + j < n;
+                            v[e] = gmem(B)[ok ? (int64_t)(l0 + l) * brs + (int64_t)(j0 + j) * bcs : 0];
                         }
-                        const int gl = l0 + l, gj = j0 + j;
-                        L.B[l][j] = (gl < k && gj < n) ? B[(int64_t)gl * brs + (int64_t)gj * bcs] : T(0);
+#pragma unroll
+                        for (int e = 0; e < kEl; ++e) {
+                            const int idx = tid + e * kT;
+                            const int l = brs == 1 ? idx % kGK : idx / kGT, j = brs == 1 ? idx / kGK : idx % kGT;
+                            L.B[l][j] = (l0 + l < k && j0 + j < n) ? v[e] : T(0);
+                        }
                     }
                     __syncthreads();
                     const int kl = min(kGK, k - l0);
@@ -191,20 +204,26 @@ __device__ __attribute__((noinline)) void op_gemm(const Inst<T>& d, const OpRec&
 #pragma unroll
                         for (int a = 0; a < 4; ++a)
 #pragma unroll
-                            for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+                            for (int b = 0; b < 4; ++b) acc[4 * a + b] += av[a] * bv[b];
                     }
                     __syncthreads();
                 }
+                int tid = t;
+                asm volatile("" : "+v"(tid));
+                const int ri = tid % 16, rj = tid / 16;
+                T cv[16];
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+                for (int e = 0; e < 16; ++e) {
+                    const int gi = i0 + 4 * ri + e / 4, gj = j0 + 4 * rj + e % 4;
+                    const bool ok = beta != T(0) && gi < m && gj < n;
+                    cv[e] = gmem(C)[ok ? (int64_t)gi * crs + (int64_t)gj * ccs : 0];
+                }
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int gi = i0 + 4 * ti + a, gj = j0 + 4 * tj + b;
-                        if (gi < m && gj < n) {
-                            T* c = C + (int64_t)gi * crs + (int64_t)gj * ccs;
-                            *c = (beta == T(0) ? T(0) : beta * *c) + alpha * acc[a][b];
-                        }
-                    }
+                for (int e = 0; e < 16; ++e) {
+                    const int gi = i0 + 4 * ri + e / 4, gj = j0 + 4 * rj + e % 4;
+                    if (gi < m && gj < n)
+                        C[(int64_t)gi * crs + (int64_t)gj * ccs] = (beta == T(0) ? T(0) : beta * cv[e]) + alpha * acc[e];
+                }
             }
         return;
     }
@@ -218,6 +237,7 @@ __device__ __attribute__((noinline)) void op_gemm(const Inst<T>& d, const OpRec&
             const T* a = A + (int64_t)i * ars;
             const T* b = B + (int64_t)j * bcs;
             double s = 0.0;
+#pragma unroll 4
             for (int l = gl; l < k; l += G) s += (double)a[(int64_t)l * acs] * (double)b[(int64_t)l * brs];
             for (int o2 = G / 2; o2 > 0; o2 >>= 1) s += __shfl_xor(s, o2, 64);
             if (gl == 0) {
