@@ -55,7 +55,10 @@ __device__ inline double dpp_move(double x) {
 
 // X (n x w; element (i, j) at X[i*xrs + j*xcs]) <- T^{-1} X, T n x n (element (i, s) at
 // Tm[i*trs + s*tcs]), lower or upper, unit diagonal or not; n <= 64. The calling wavefront
-// `wave` of `nwaves` solves columns wave, wave + nwaves, ...
+// `wave` of `nwaves` solves columns wave, wave + nwaves, ..., kTriCols of them at a time as
+// independent chains (the broadcast of one column's solved entry overlaps the others' updates).
+// Rows and steps beyond n carry zeros, so every wavefront runs all 64 steps without branches.
+constexpr int kTriCols = 4;
 template <class T>
 __device__ inline void tri_wave(const T* Tm, int trs, int tcs, int n, bool lower, bool unit, T* X, int xrs, int xcs,
                                 int w, int wave, int nwaves) {
@@ -70,27 +73,37 @@ __device__ inline void tri_wave(const T* Tm, int trs, int tcs, int n, bool lower
     const T dinv = (!unit && act) ? T(1) / diag : T(1);
 #pragma unroll
     for (int s = 0; s < 64; ++s) tr[s] = (s < n && act) ? tr[s] * dinv : T(0);
-    T xn = X[(int64_t)li * xrs + (int64_t)wave * xcs];
-    for (int j = wave; j < w; j += nwaves) {
-        T x = act ? xn * dinv : T(0);
-        const int jn = j + nwaves;
-        if (jn < w) xn = X[(int64_t)li * xrs + (int64_t)jn * xcs];
+    for (int j0 = wave; j0 < w; j0 += nwaves * kTriCols) {
+        T x[kTriCols];
+#pragma unroll
+        for (int c = 0; c < kTriCols; ++c) {
+            const int j = min(j0 + c * nwaves, w - 1);
+            x[c] = X[(int64_t)li * xrs + (int64_t)j * xcs];
+        }
+#pragma unroll
+        for (int c = 0; c < kTriCols; ++c) x[c] = act ? x[c] * dinv : T(0);
         if (lower) {
 #pragma unroll
             for (int s = 0; s < 64; ++s)
-                if (s < n) {
-                    const T xs = lane_bcast(x, s);
-                    if (lane > s) x -= tr[s] * xs;
+#pragma unroll
+                for (int c = 0; c < kTriCols; ++c) {
+                    const T xs = lane_bcast(x[c], s);
+                    if (lane > s) x[c] -= tr[s] * xs;
                 }
         } else {
 #pragma unroll
             for (int s = 63; s >= 0; --s)
-                if (s < n) {
-                    const T xs = lane_bcast(x, s);
-                    if (lane < s) x -= tr[s] * xs;
+#pragma unroll
+                for (int c = 0; c < kTriCols; ++c) {
+                    const T xs = lane_bcast(x[c], s);
+                    if (lane < s) x[c] -= tr[s] * xs;
                 }
         }
-        if (act) X[(int64_t)lane * xrs + (int64_t)j * xcs] = x;
+#pragma unroll
+        for (int c = 0; c < kTriCols; ++c) {
+            const int j = j0 + c * nwaves;
+            if (act && j < w) X[(int64_t)lane * xrs + (int64_t)j * xcs] = x[c];
+        }
     }
 }
 
