@@ -625,47 +625,6 @@ __device__ __attribute__((always_inline)) inline void store_rows(const Side<T>& 
     }
 }
 
-__device__ inline void tri_index(int e, int& p, int& q) {   // e -> (p <= q) of the upper triangle
-    q = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
-    while (q * (q + 1) / 2 > e) --q;
-    while ((q + 1) * (q + 2) / 2 <= e) ++q;
-    p = e - q * (q + 1) / 2;
-}
-
-// Gram matrices of the staged rows, accumulated in LDS over the caller's chunk loop: entry
-// (p <= q) of either side always belongs to the same thread, so there is no race
-template <class LS>
-__device__ inline void gram_clear(LS& S) {
-    constexpr int kSK = LS::K;
-    for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) (&S.G[0][0])[idx] = 0.0;
-}
-template <class LS>
-__device__ inline void gram_accumulate(LS& S, int k0, int k1) {
-    constexpr int kSK = LS::K, kCH = LS::CH, kLD = LS::LD;
-    const int n0 = k0 * (k0 + 1) / 2, n1 = k1 * (k1 + 1) / 2;
-    for (int e = threadIdx.x; e < n0 + n1; e += kT) {
-        const int s = e < n0 ? 0 : 1, el = e < n0 ? e : e - n0;
-        int p, q;
-        tri_index(el, p, q);
-        const double* A = S.A[s];
-        double a = 0.0;
-#pragma unroll 8
-        for (int rr = 0; rr < kCH; ++rr) a += A[rr * kLD + p] * A[rr * kLD + q];
-        S.G[s][p * kSK + q] += a;
-    }
-}
-template <class LS>
-__device__ inline void gram_mirror(LS& S, int k0, int k1) {
-    constexpr int kSK = LS::K;
-    const int n0 = k0 * (k0 + 1) / 2, n1 = k1 * (k1 + 1) / 2;
-    for (int e = threadIdx.x; e < n0 + n1; e += kT) {
-        const int s = e < n0 ? 0 : 1, el = e < n0 ? e : e - n0;
-        int p, q;
-        tri_index(el, p, q);
-        S.G[s][q * kSK + p] = S.G[s][p * kSK + q];
-    }
-}
-
 // largest dv over lanes 0 .. kSK-1 (kSK = 16 or 32) and its lane index pj, ties to the smaller
 // index; wave-uniform on return. Each row of 16 lanes is reduced by DPP rotations, the rows'
 // winners are read with readlane.
@@ -693,6 +652,60 @@ __device__ inline void argmax_rows(double& dv, int& pj) {
     } else {
         dv = v0;
         pj = p0;
+    }
+}
+
+// Gram matrices G_s = A_s^T A_s of the staged rows of both sides on the FP64 matrix cores, in
+// 16 x 16 tiles accumulated in registers over the caller's chunk loop. Tile (ti, tj) of side s
+// takes one v_mfma_f64_16x16x4 per four staged rows: lane l brings row 4 kk + l / 16 at column
+// 16 ti + l % 16 (A operand: entry (l % 16, l / 16) of the 16 x 4 factor) and at column
+// 16 tj + l % 16 (B operand: entry (l / 16, l % 16) of the 4 x 16 factor); register v of lane l
+// holds entry (4 v + l / 16, l % 16) of the 16 x 16 result. The waves take the tiles of both sides
+// round robin. Rows beyond the block and columns beyond k' are staged as zeros, so every entry of
+// G outside k' x k' comes out 0.
+typedef double v4d __attribute__((ext_vector_type(4)));
+template <class LS>
+struct GramTiles {
+    static constexpr int T = LS::K / 16, kJobs = 2 * T * T, kPerWave = (kJobs + kW - 1) / kW;
+    static_assert(LS::K % 16 == 0 && LS::CH % 4 == 0, "Gram tiles of 16 x 16, four rows per instruction");
+    v4d acc[kPerWave];
+};
+template <class LS>
+__device__ inline void gram_tiles_clear(GramTiles<LS>& g) {
+#pragma unroll
+    for (int u = 0; u < GramTiles<LS>::kPerWave; ++u) g.acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+}
+template <class LS>
+__device__ inline void gram_tiles_accumulate(const LS& S, GramTiles<LS>& g) {
+    using G = GramTiles<LS>;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < G::kPerWave; ++u) {
+        const int jb = wave + u * kW;
+        if (jb < G::kJobs) {
+            const int sd = jb / (G::T * G::T), ti = (jb % (G::T * G::T)) / G::T, tj = jb % G::T;
+            const double* A = S.A[sd] + (lane >> 4) * LS::LD + (lane & 15);
+#pragma unroll 4
+            for (int kk = 0; kk < LS::CH / 4; ++kk) {
+                const double a = A[4 * kk * LS::LD + 16 * ti], b = A[4 * kk * LS::LD + 16 * tj];
+                g.acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, g.acc[u], 0, 0, 0);
+            }
+        }
+    }
+}
+template <class LS>
+__device__ inline void gram_tiles_store(LS& S, const GramTiles<LS>& g) {
+    using G = GramTiles<LS>;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < G::kPerWave; ++u) {
+        const int jb = wave + u * kW;
+        if (jb < G::kJobs) {
+            const int sd = jb / (G::T * G::T), ti = (jb % (G::T * G::T)) / G::T, tj = jb % G::T;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                S.G[sd][(16 * ti + 4 * v + (lane >> 4)) * LS::K + 16 * tj + (lane & 15)] = g.acc[u][v];
+        }
     }
 }
 
@@ -896,16 +909,17 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
     };
     T rows[kEl];   // the chunk in flight
     // Gram matrices
-    gram_clear(S);
+    GramTiles<LS> gt;
+    gram_tiles_clear(gt);
     load_rows<T, LS>(su, sv, 0, kp, rows);
     for (int c0 = 0; c0 < rmax; c0 += kCH) {
         store_rows<T, LS>(su, sv, c0, kp, rows, S);
         __syncthreads();
         if (c0 + kCH < rmax) load_rows<T, LS>(su, sv, c0 + kCH, kp, rows);
-        gram_accumulate(S, kp, kp);
+        gram_tiles_accumulate(S, gt);
         __syncthreads();
     }
-    gram_mirror(S, kp, kp);
+    gram_tiles_store(S, gt);
     __syncthreads();
     phase(0);
     const double floor_rel = f64 ? 1e-14 : 1e-12;
@@ -917,8 +931,8 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
     if (f64) {
         // second pass: rows of Q1 = (A P)[:, :q] R11^{-1} (forward substitution per row), their
         // Gram G2 = R2^T R2 and R <- R2 R
-        const int q0 = S.q[0], q1 = S.q[1];
-        gram_clear(S);
+        GramTiles<LS> g2;
+        gram_tiles_clear(g2);
         load_rows<T, LS>(su, sv, 0, kp, rows);
         for (int c0 = 0; c0 < rmax; c0 += kCH) {
             store_rows<T, LS>(su, sv, c0, kp, rows, S);
@@ -946,10 +960,10 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
                 for (int b = 0; b < kSK; ++b) row[b] = b < q ? y[b] : 0.0;
             }
             __syncthreads();
-            gram_accumulate(S, q0, q1);
+            gram_tiles_accumulate(S, g2);
             __syncthreads();
         }
-        gram_mirror(S, q0, q1);
+        gram_tiles_store(S, g2);
         __syncthreads();
         if (wave < 2) {
             // G2 (q x q) = L2 L2^T without pivoting, in A[wave] as scratch for R2 (row a, col b)
