@@ -880,6 +880,83 @@ __device__ void wave_jacobi_lds(double* M, double* Z, double* nrm, int rows, int
     if (c < cols && sub == 0) nrm[c] = sqrt(nn);
 }
 
+// value of lane n (0..15, unrolled loop index) of the calling lane's 16-lane row
+__device__ __attribute__((always_inline)) inline double row_bcast16(double v, int n) {
+    switch (n) {
+#define FDE_ROWB(k) \
+    case k: return dpp_move<dpp_row_newbcast(k)>(v);
+        FDE_ROWB(0) FDE_ROWB(1) FDE_ROWB(2) FDE_ROWB(3) FDE_ROWB(4) FDE_ROWB(5) FDE_ROWB(6) FDE_ROWB(7)
+        FDE_ROWB(8) FDE_ROWB(9) FDE_ROWB(10) FDE_ROWB(11) FDE_ROWB(12) FDE_ROWB(13) FDE_ROWB(14) FDE_ROWB(15)
+#undef FDE_ROWB
+        default: return v;
+    }
+}
+
+// rows [c0, c0 + CH) of U_C = A_u C_u and V_C = A_v C_v from the staged rows (A) and C_u, C_v (G);
+// zeros staged beyond k' and zero rows of C beyond k' make the sums run over all K columns
+template <class T, class LS>
+__device__ __attribute__((noinline)) void products_chunk(lds_ptr<LS> Sp, int c0, int r, int m, int n, T* U, T* V) {
+    auto& S = *Sp;
+    constexpr int kSK = LS::K, kCH = LS::CH, kLD = LS::LD;
+    for (int idx = threadIdx.x; idx < 2 * kCH * r; idx += kT) {
+        const int s = idx / (kCH * r), rem = idx % (kCH * r), rr = rem % kCH, c = rem / kCH, i = c0 + rr;
+        if (i >= (s == 0 ? m : n)) continue;
+        double v = 0.0;
+#pragma unroll 4
+        for (int l = 0; l < kSK; ++l) v += S.A[s][rr * kLD + l] * S.G[s][l * kSK + c];
+        T* out = s == 0 ? U : V;
+        out[i + (int64_t)c * (s == 0 ? m : n)] = (T)v;
+    }
+}
+
+// C_u = P_u R11_u^{-1} (M Z)_order and C_v = P_v R11_v^{-1} Z_order of the small recompression
+// with k' <= 16, by back substitution in the pivot order, into G[side] (row l, column c); called by
+// every thread of the workgroup (it holds barriers)
+template <class LS>
+__device__ __attribute__((noinline)) void solve_factors16(lds_ptr<LS> Sp, lds_ptr<const int> order, int r) {
+    auto& S = *Sp;   // LDS-qualified: its accesses are LDS instructions
+    constexpr int kSK = LS::K;
+    static_assert(kSK == 16, "rows of R11 held in registers, one per lane of a 16-lane column group");
+    const int wave = threadIdx.x >> 6;
+    // waves 2 s and 2 s + 1 solve side s, four columns at a time: lane l holds row a = l % 16 of
+    // R11 (pivot order) and of column c = 4 (wave % 2) + l / 16 (+ 8 per round); the solved
+    // entry of row b is broadcast to its column's 16 lanes (one DPP row) with row_newbcast. Rows
+    // and steps beyond q carry zeros, so all 16 steps run without branches.
+    const int lane = threadIdx.x & 63, sd = wave >> 1, cl = lane >> 4, a = lane & 15;
+    const int q = S.q[sd];
+    const bool row = a < q;
+    double rr[16];
+#pragma unroll
+    for (int bb = 0; bb < 16; ++bb) rr[bb] = (row && bb < q) ? S.R[sd][a * kSK + S.perm[sd][bb]] : 0.0;
+    const double dinv = row ? 1.0 / S.R[sd][a * kSK + S.perm[sd][a]] : 0.0;
+    const int pa = row ? S.perm[sd][a] : 0;
+    constexpr int kRounds = (16 + 7) / 8;   // r <= kSK columns, 8 per round
+    double y[kRounds];
+#pragma unroll
+    for (int u = 0; u < kRounds; ++u) {
+        const int c = 8 * u + 4 * (wave & 1) + cl;
+        y[u] = (row && c < r) ? S.G[sd][order[c] * kSK + a] : 0.0;
+    }
+    __syncthreads();   // M and Z read: G becomes C
+    for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) S.G[idx / (kSK * kSK)][idx % (kSK * kSK)] = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kRounds; ++u) {
+        if (8 * u < r) {
+            double v = y[u];
+#pragma unroll
+            for (int bb = 15; bb >= 0; --bb) {
+                if (a == bb) v *= dinv;
+                const double yb = row_bcast16(v, bb);
+                if (a < bb) v -= rr[bb] * yb;
+            }
+            const int c = 8 * u + 4 * (wave & 1) + cl;
+            if (row && c < r) S.G[sd][pa * kSK + c] = v;
+        }
+    }
+    __syncthreads();
+}
+
 template <class T, class SH>
 __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const OpRec& o, SH& sh, const LRBlockDev& L, int kc, int kx) {
     auto& S = sh.ls;
@@ -1025,44 +1102,48 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
     __syncthreads();
     const int r = sh.r;
     // C_u (kp x r) = P_u R11_u^{-1} (M Z)_order and C_v = P_v R11_v^{-1} Z_order, by back
-    // substitution, one lane per (side, output column); into A[side] (row l, column c)
-    for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) S.A[idx / (kSK * kSK)][idx % (kSK * kSK)] = 0.0;
-    __syncthreads();
-    if (threadIdx.x < 2 * r) {
-        const int s = threadIdx.x / r, c = threadIdx.x % r, jc = sh.order[c];
-        const int q = S.q[s];
-        const double* rhs = s == 0 ? &S.G[0][jc * kSK] : &S.G[1][jc * kSK];   // column jc (length q)
-        double* C = S.A[s];
-        for (int a = q - 1; a >= 0; --a) {
-            const int pa = S.perm[s][a];
-            double v = rhs[a];
-            for (int b = a + 1; b < q; ++b) v -= S.R[s][a * kSK + S.perm[s][b]] * C[S.perm[s][b] * kSK + c];
-            C[pa * kSK + c] = v / S.R[s][a * kSK + pa];
+    // substitution in the pivot order, into G[side] (row l, column c; M and Z are read first)
+    if constexpr (kSK == 16) {
+        solve_factors16(lmem(&S), lmem<const int>(sh.order), r);
+    } else {
+        // one lane per (side, output column), into A[side], then moved to G
+        for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) S.A[idx / (kSK * kSK)][idx % (kSK * kSK)] = 0.0;
+        __syncthreads();
+        if (threadIdx.x < 2 * r) {
+            const int sd = threadIdx.x / r, c = threadIdx.x % r, jc = sh.order[c];
+            const int q = S.q[sd];
+            const double* rhs = &S.G[sd][jc * kSK];   // column jc (length q)
+            double* C = S.A[sd];
+            for (int a = q - 1; a >= 0; --a) {
+                const int pa = S.perm[sd][a];
+                double v = rhs[a];
+                for (int bb = a + 1; bb < q; ++bb) v -= S.R[sd][a * kSK + S.perm[sd][bb]] * C[S.perm[sd][bb] * kSK + c];
+                C[pa * kSK + c] = v / S.R[sd][a * kSK + pa];
+            }
         }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) {
+            const int sd = idx / (kSK * kSK), e = idx % (kSK * kSK);
+            S.G[sd][e] = S.A[sd][e];
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    // move C_u, C_v to G (M and Z are no longer needed) so that A can stage rows again
-    for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) {
-        const int sd = idx / (kSK * kSK), e = idx % (kSK * kSK);
-        S.G[sd][e] = S.A[sd][e];
-    }
-    __syncthreads();
     phase(4);
-    // U_C <- A_u C_u, V_C <- A_v C_v, chunk by chunk (a chunk is staged before its rows are written)
-    load_rows<T, LS>(su, sv, 0, kp, rows);
-    for (int c0 = 0; c0 < rmax; c0 += kCH) {
-        store_rows<T, LS>(su, sv, c0, kp, rows, S);
-        __syncthreads();
-        if (c0 + kCH < rmax) load_rows<T, LS>(su, sv, c0 + kCH, kp, rows);
-        for (int idx = threadIdx.x; idx < 2 * kCH * r; idx += kT) {
-            const int s = idx / (kCH * r), rem = idx % (kCH * r), rr = rem % kCH, c = rem / kCH, i = c0 + rr;
-            if (i >= (s == 0 ? m : n)) continue;
-            double v = 0.0;
-            for (int l = 0; l < kp; ++l) v += S.A[s][rr * kLD + l] * S.G[s][l * kSK + c];
-            T* out = s == 0 ? U : V;
-            out[i + (int64_t)c * (s == 0 ? m : n)] = (T)v;
+    // U_C <- A_u C_u, V_C <- A_v C_v, chunk by chunk (a chunk is staged before its rows are written).
+    // With the small path's LDS-only factors and a single chunk, the rows staged for the Gram
+    // matrices are still in place (FP64 factors overwrite them in the second pass).
+    const bool staged = kSK == 16 && !f64 && rmax <= kCH;
+    if (staged) {
+        products_chunk<T>(lmem(&S), 0, r, m, n, U, V);
+    } else {
+        load_rows<T, LS>(su, sv, 0, kp, rows);
+        for (int c0 = 0; c0 < rmax; c0 += kCH) {
+            store_rows<T, LS>(su, sv, c0, kp, rows, S);
+            __syncthreads();
+            if (c0 + kCH < rmax) load_rows<T, LS>(su, sv, c0 + kCH, kp, rows);
+            products_chunk<T>(lmem(&S), c0, r, m, n, U, V);
+            __syncthreads();
         }
-        __syncthreads();
     }
     if (threadIdx.x == 0) d.ranks[L.slot] = r;
     phase(5);

@@ -33,10 +33,12 @@ __device__ inline double lane_bcast(double x, int s) {
 // Lane exchange within a row of 16 lanes through the DPP operand modifier (no LDS round trip).
 // CTRL is a DPP control word: quad_perm(s0, s1, s2, s3) = s0 | s1 << 2 | s2 << 4 | s3 << 6
 // (lane i of each quad reads lane s_i), row_ror(n) = 0x120 + n (lane i of each row reads lane
-// (i + n) mod 16 of the row).
+// (i + n) mod 16 of the row), row_newbcast(n) = 0x150 + n (every lane of each row reads lane n
+// of the row).
 constexpr int kDppXor1 = 0xB1;   // quad_perm(1, 0, 3, 2)
 constexpr int kDppXor2 = 0x4E;   // quad_perm(2, 3, 0, 1)
 constexpr int dpp_row_ror(int n) { return 0x120 + n; }
+constexpr int dpp_row_newbcast(int n) { return 0x150 + n; }
 template <int CTRL>
 __device__ inline int dpp_move(int x) {
     return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, false);
