@@ -29,6 +29,33 @@ import fde_inputs as fi  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
+# HBM traffic of one level launch of the batched H-LU (the dominant kernel), from two rocprofv3
+# --pmc runs of `bench.py --steps 1 --warmup 0 --quick` (FETCH_SIZE, then WRITE_SIZE; KiB per
+# dispatch, averaged over the k_level dispatches), each scaled by what the same counter reads for a
+# plain 256 MiB device copy (FETCH_SIZE reads half the bytes copied: x2; WRITE_SIZE reads them
+# all: x1). Valid for the kernel sources whose digest is recorded; `traffic` is null once they change.
+LEVEL_TRAFFIC = {"fetch_kib": 4160.0, "write_kib": 5821.4, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "sources_sha256": "8e57de766620e491f58d4e3a73b1edbebd99818159f55222ebb5d0239f129ce3"}
+LEVEL_SOURCES = ("paper_1808_02937_amd/csrc/hinterp.hip", "paper_1808_02937_amd/csrc/hinterp.h",
+                 "paper_1808_02937_amd/csrc/tri_wave.h", "paper_1808_02937_amd/csrc/hmatrix.h",
+                 "paper_1808_02937_amd/build.py")
+
+
+def level_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in LEVEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def level_traffic_bytes():
+    t = LEVEL_TRAFFIC
+    if t["sources_sha256"] != level_sources_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -68,6 +95,7 @@ class Pipeline:
         Xs, infos = self.solve(ops, Gs, lus)
         for o in ops:
             o.close()
+        self.last_lus = lus   # the roofline reads the factorisation's device counters and HIP-event time
         return infos
 
 
@@ -253,22 +281,24 @@ def main():
            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
                           "definition": "batch completion time (every request of a step arrives at its start)"}}
     # roofline of the dominant kernel: the level launches of the batched H-LU (launch l runs
-    # level l of all nine factorisations; the nine share one structure, so one launch per level)
-    ops_r, Gs_r, hms_r, lus_r = mixed.setup()
-    st = [lu.stats() for lu in lus_r]
+    # level l of all nine factorisations; the nine share one structure, so one launch per level),
+    # from the last timed step: its device-counted flops and its HIP-event time on the library stream
+    st = [lu.stats() for lu in mixed.last_lus]
     flops = sum(x[0] for x in st)
     kms = st[0][1]
     inst0 = mixed.insts[0]
     plan = fde.plan_hlu(inst0.nodes, inst0.P, R=inst0.R, leaf_elems=inst0.leaf)
     nlaunch = plan["levels"]
     achieved = flops / (kms * 1e-3) / 1e12
+    traffic = level_traffic_bytes()
     out["roofline"] = {"kernel": "k_level<float> (batched H-LU, one launch per level, one workgroup per op)",
                        "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                       "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+                       "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                       "traffic_GBps": None if traffic is None else traffic / (kms / nlaunch * 1e-3) / 1e9,
                        "launches": nlaunch, "flops_per_launch": flops / nlaunch, "launch_ms": kms / nlaunch,
                        "hlu_ms": kms, "ops_per_factorisation": plan["ops"]}
-    for o in ops_r:
-        o.close()
+    mixed.last_lus = None
     if not args.quick:
         # plain FP64 path, same algorithm
         log("fp64 path")
