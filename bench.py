@@ -90,12 +90,16 @@ class Pipeline:
     def solve(self, ops, Gs, lus):
         return self.fde.solve_batched(self.ctx, ops, Gs, lus, rtol=1e-10, restart=30, maxit=300)
 
-    def step(self):
+    def step(self, keep=False):
         ops, Gs, hms, lus = self.setup()
         Xs, infos = self.solve(ops, Gs, lus)
-        for o in ops:
-            o.close()
-        self.last_lus = lus   # the roofline reads the factorisation's device counters and HIP-event time
+        if keep:
+            # the roofline reads this step's factorisations (device counters, HIP-event time)
+            # after the timed region; their operators are closed then
+            self.kept = (ops, lus)
+        else:
+            for o in ops:
+                o.close()
         return infos
 
 
@@ -259,7 +263,7 @@ def main():
     infos = None
     for k in range(args.steps):
         ts = time.perf_counter()
-        infos = mixed.step()
+        infos = mixed.step(keep=(k == args.steps - 1))
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
         log(f"step {k}: {lat[-1] * 1e3:.1f} ms")
@@ -283,7 +287,8 @@ def main():
     # roofline of the dominant kernel: the level launches of the batched H-LU (launch l runs
     # level l of all nine factorisations; the nine share one structure, so one launch per level),
     # from the last timed step: its device-counted flops and its HIP-event time on the library stream
-    st = [lu.stats() for lu in mixed.last_lus]
+    kept_ops, kept_lus = mixed.kept
+    st = [lu.stats() for lu in kept_lus]
     flops = sum(x[0] for x in st)
     kms = st[0][1]
     inst0 = mixed.insts[0]
@@ -298,7 +303,9 @@ def main():
                        "traffic_GBps": None if traffic is None else traffic / (kms / nlaunch * 1e-3) / 1e9,
                        "launches": nlaunch, "flops_per_launch": flops / nlaunch, "launch_ms": kms / nlaunch,
                        "hlu_ms": kms, "ops_per_factorisation": plan["ops"]}
-    mixed.last_lus = None
+    for o in kept_ops:
+        o.close()
+    mixed.kept = None
     if not args.quick:
         # plain FP64 path, same algorithm
         log("fp64 path")

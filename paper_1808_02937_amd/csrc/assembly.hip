@@ -462,6 +462,52 @@ void launch_dense_matrix(Op* op, double* A, int lda) {
 namespace {
 // f(x_q) = sum_k coef_k d_k^{expo_k} at every load-vector node, d_k the exact distance to a
 // (side 0) or to b (side 1)
+// load-vector nodes, one wavefront per panel, lane i = node i: a Gauss-Legendre node mapped to the
+// panel [lo, hi] measured from the element end `side`, with its reference coordinate, weight and
+// distances to a and b formed from the element's own end distances (no cancellation near the
+// ends); explicit panels are copied
+__global__ void k_load_rule(int np, const LoadPanel* __restrict__ pan, const double* __restrict__ ex,
+                            const double* __restrict__ gl, const double* __restrict__ xm, int N, double* __restrict__ x,
+                            double* __restrict__ xi, double* __restrict__ w, double* __restrict__ da,
+                            double* __restrict__ db) {
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6), i = threadIdx.x & 63;
+    if (p >= np) return;
+    const LoadPanel pn = pan[p];
+    if (i >= pn.n) return;
+    const int q = pn.node0 + i;
+    if (pn.ex >= 0) {
+        const double* e = ex + 5 * (size_t)(pn.ex + i);
+        x[q] = e[0];
+        xi[q] = e[1];
+        w[q] = e[2];
+        da[q] = e[3];
+        db[q] = e[4];
+        return;
+    }
+    const double a = xm[0], b = xm[N];
+    const double xl = xm[pn.elem], xr = xm[pn.elem + 1], he = xr - xl;
+    const double da_l = xl - a, db_r = b - xr;
+    const int off = pn.n * (pn.n - 1) / 2;
+    const double gx = gl[off + i], gw = gl[kMaxGL * (kMaxGL + 1) / 2 + off + i];
+    const double u = 0.5 * (pn.hi - pn.lo) * gx + 0.5 * (pn.hi + pn.lo);
+    w[q] = 0.5 * (pn.hi - pn.lo) * gw;
+    if (pn.side == 0) {
+        double xv = xl + u;
+        if (xv <= xl) xv = nextafter(xl, xr);
+        x[q] = xv;
+        xi[q] = 2.0 * u / he - 1.0;
+        da[q] = da_l + u;
+        db[q] = db_r + (he - u);
+    } else {
+        double xv = xr - u;
+        if (xv >= xr) xv = nextafter(xr, xl);
+        x[q] = xv;
+        xi[q] = 1.0 - 2.0 * u / he;
+        da[q] = da_l + (he - u);
+        db[q] = db_r + u;
+    }
+}
+
 __global__ void k_eval_powers(int nq, const double* __restrict__ da, const double* __restrict__ db, int nt,
                               const double* __restrict__ coef, const double* __restrict__ expo,
                               const int* __restrict__ side, double* __restrict__ f) {
@@ -474,8 +520,16 @@ __global__ void k_eval_powers(int nq, const double* __restrict__ da, const doubl
 }
 }  // namespace
 
+void launch_load_rule(Op* op, int npanels, const LoadPanel* d_panels, const double* d_ex) {
+    if (npanels <= 0) return;
+    hipLaunchKernelGGL(k_load_rule, dim3(ceil_div(npanels, 4)), dim3(256), 0, op->ctx->stream, npanels, d_panels, d_ex,
+                       op->ctx->gl.p, op->d_x.p, op->N, op->d_lq_x.p, op->d_lq_xi.p, op->d_lq_w.p, op->d_lq_da.p,
+                       op->d_lq_db.p);
+    FDE_LAUNCH_CHECK();
+}
+
 void launch_eval_powers(Op* op, int nt, const double* d_coef, const double* d_expo, const int* d_side) {
-    const int nq = (int)op->lq_x.size();
+    const int nq = op->lq_n;
     hipLaunchKernelGGL(k_eval_powers, dim3(std::min(ceil_div(nq, 256), 1024)), dim3(256), 0, op->ctx->stream, nq,
                        op->d_lq_da.p, op->d_lq_db.p, nt, d_coef, d_expo, d_side, op->d_lq_f.p);
     FDE_LAUNCH_CHECK();

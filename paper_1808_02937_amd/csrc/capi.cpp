@@ -165,52 +165,25 @@ double nodes_for(double len, double dist, int P) {
     return std::ceil(0.5 * (P + 36.8 / std::log(rho))) + 1;
 }
 
-// Quadrature nodes of the load vector on element e. Elements touching a or b
+// Quadrature panels of the load vector on element e. Elements touching a or b
 // carry geometric panels toward that end and a Gauss-Jacobi end panel, so an
 // endpoint singularity f ~ d^{-alpha} (the behaviour of -D^2 I^{2-alpha} of a
 // function with nonzero slope at the end) is integrated to ~1e-16; elements
 // near an end are graded toward it as in the far-field moments; the rest use
-// one Gauss-Legendre panel.
-void element_load_rule(const Op* op, int e, std::vector<double>& xs, std::vector<double>& xis,
-                       std::vector<double>& ws, std::vector<double>& das, std::vector<double>& dbs) {
+// one Gauss-Legendre panel. Gauss-Legendre panels are expanded into nodes on the
+// device; the Gauss-Jacobi end panels (their weights carry the singular factor)
+// are given node by node (x, xi, w, d_a, d_b).
+void element_load_panels(const Op* op, int e, std::vector<LoadPanel>& pans, std::vector<double>& ex, int& nodes) {
     const double a = op->x.front(), b = op->x.back();
     const double xl = op->x[e], xr = op->x[e + 1], he = xr - xl;
     const int P = op->P;
     const int nbase = std::max(24, P + 12);
-    // distances of a node at distance u from the element end on `side` to a and b
     const double da_l = xl - a, db_r = b - xr;
-    auto push_dist = [&](double u, int side) {
-        if (side == 0) {
-            das.push_back(da_l + u);
-            dbs.push_back(db_r + (he - u));
-        } else {
-            das.push_back(da_l + (he - u));
-            dbs.push_back(db_r + u);
-        }
-    };
     auto add_panel = [&](double lo, double hi, int n, int side) {
         // lo, hi: distances from the element end on `side` (0: x_e, 1: x_{e+1})
         n = std::min(std::max(n, 1), kMaxGL);
-        const double* gx = gauss_legendre_table() + n * (n - 1) / 2;
-        const double* gw = gx + kMaxGL * (kMaxGL + 1) / 2;
-        for (int i = 0; i < n; ++i) {
-            const double u = 0.5 * (hi - lo) * gx[i] + 0.5 * (hi + lo);
-            const double w = 0.5 * (hi - lo) * gw[i];
-            double xv, xi;
-            if (side == 0) {
-                xv = xl + u;
-                if (xv <= xl) xv = std::nextafter(xl, xr);
-                xi = 2.0 * u / he - 1.0;
-            } else {
-                xv = xr - u;
-                if (xv >= xr) xv = std::nextafter(xr, xl);
-                xi = 1.0 - 2.0 * u / he;
-            }
-            xs.push_back(xv);
-            xis.push_back(xi);
-            ws.push_back(w);
-            push_dist(u, side);
-        }
+        pans.push_back(LoadPanel{lo, hi, e, side, n, nodes, -1, 0});
+        nodes += n;
     };
     const bool touch_a = (e == 0), touch_b = (e == op->N - 1);
     if (touch_a || touch_b) {
@@ -231,20 +204,19 @@ void element_load_rule(const Op* op, int e, std::vector<double>& xs, std::vector
             std::vector<double> gx(nj), gw(nj);
             gauss_jacobi(nj, 0.0, 1.0 - op->alpha, gx.data(), gw.data());
             const double delta = hi;
+            const int ex0 = (int)(ex.size() / 5);
             for (int i = 0; i < nj; ++i) {
                 const double u = 0.5 * delta * (1.0 + gx[i]);
                 // int_0^delta F du = (delta/2)^{2-alpha} int (1+t)^{1-alpha} F u^{alpha-1} dt
                 const double w = std::pow(0.5 * delta, 2.0 - op->alpha) * gw[i] * std::pow(u, op->alpha - 1.0);
-                if (side == 0) {
-                    xs.push_back(xl + u);
-                    xis.push_back(2.0 * u / he - 1.0);
-                } else {
-                    xs.push_back(xr - u);
-                    xis.push_back(1.0 - 2.0 * u / he);
-                }
-                ws.push_back(w);
-                push_dist(u, side);
+                const double xv = side == 0 ? xl + u : xr - u;
+                const double xi = side == 0 ? 2.0 * u / he - 1.0 : 1.0 - 2.0 * u / he;
+                const double da = side == 0 ? da_l + u : da_l + (he - u);
+                const double db = side == 0 ? db_r + (he - u) : db_r + u;
+                ex.insert(ex.end(), {xv, xi, w, da, db});
             }
+            pans.push_back(LoadPanel{0.0, delta, e, side, nj, nodes, ex0, 0});
+            nodes += nj;
         };
         if (touch_a && touch_b) {
             graded(0.5 * he, 0, 0.5 * he);
@@ -275,20 +247,49 @@ void element_load_rule(const Op* op, int e, std::vector<double>& xs, std::vector
     }
 }
 
+// the load-vector rule on the device: panels on the host (a few per element), nodes expanded by
+// a kernel; the host copies of x, d_a, d_b are fetched only when asked for (host_load_rule)
 void build_load_rule(Op* op) {
+    Ctx* c = op->ctx;
+    std::vector<LoadPanel> pans;
+    std::vector<double> ex;
+    pans.reserve((size_t)op->N + 64);
+    op->lq_off.assign(op->N + 1, 0);
+    int nodes = 0;
+    for (int e = 0; e < op->N; ++e) {
+        op->lq_off[e] = nodes;
+        element_load_panels(op, e, pans, ex, nodes);
+    }
+    op->lq_off[op->N] = nodes;
+    op->lq_n = nodes;
     op->lq_x.clear();
-    op->lq_xi.clear();
-    op->lq_w.clear();
     op->lq_da.clear();
     op->lq_db.clear();
-    op->lq_off.assign(op->N + 1, 0);
-    const size_t guess = (size_t)op->N * std::max(24, op->P + 12) + 2048;   // interior panels, graded ends
-    for (auto* v : {&op->lq_x, &op->lq_xi, &op->lq_w, &op->lq_da, &op->lq_db}) v->reserve(guess);
-    for (int e = 0; e < op->N; ++e) {
-        op->lq_off[e] = (int)op->lq_x.size();
-        element_load_rule(op, e, op->lq_x, op->lq_xi, op->lq_w, op->lq_da, op->lq_db);
-    }
-    op->lq_off[op->N] = (int)op->lq_x.size();
+    for (auto* d : {&op->d_lq_x, &op->d_lq_xi, &op->d_lq_w, &op->d_lq_da, &op->d_lq_db, &op->d_lq_f})
+        d->alloc(c, (size_t)nodes);
+    op->d_lq_off.alloc(c, op->lq_off.size());
+    upload(c, op->d_lq_off.p, op->lq_off.data(), op->lq_off.size() * sizeof(int));
+    DevBuf<LoadPanel> d_pans;
+    DevBuf<double> d_ex;
+    d_pans.alloc(c, pans.size());
+    upload(c, d_pans.p, pans.data(), pans.size() * sizeof(LoadPanel));
+    d_ex.alloc(c, std::max<size_t>(ex.size(), 1));
+    if (!ex.empty()) upload(c, d_ex.p, ex.data(), ex.size() * sizeof(double));
+    launch_load_rule(op, (int)pans.size(), d_pans.p, d_ex.p);
+}
+
+// host copies of the load-vector nodes and their distances to a and b
+void host_load_rule(Op* op) {
+    const size_t n = (size_t)op->lq_n;
+    if (op->lq_x.size() == n) return;
+    Ctx* c = op->ctx;
+    op->lq_x.resize(n);
+    op->lq_da.resize(n);
+    op->lq_db.resize(n);
+    FDE_HIP(hipMemcpyAsync(op->lq_x.data(), op->d_lq_x.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    FDE_HIP(hipMemcpyAsync(op->lq_da.data(), op->d_lq_da.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    FDE_HIP(hipMemcpyAsync(op->lq_db.data(), op->d_lq_db.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    FDE_HIP(hipStreamSynchronize(c->stream));
 }
 
 // (P+1)^2 mass of the reference basis [phi_L, phi_R, psi_1..psi_{P-1}] on [-1,1]
@@ -558,6 +559,7 @@ int fde_op_dense(fde_op* op, double* A, int lda) {
 int fde_load_nodes(fde_op* op, int* nq, double* x, double* da, double* db) {
     FDE_API_BEGIN
     if (!op || !nq) fail(FDE_EINVAL, "bad arguments");
+    host_load_rule(op);
     const size_t n = op->lq_x.size();
     *nq = (int)n;
     if (x) std::memcpy(x, op->lq_x.data(), n * sizeof(double));
@@ -568,22 +570,6 @@ int fde_load_nodes(fde_op* op, int* nq, double* x, double* da, double* db) {
 
 namespace {
 
-void load_rule_to_device(Op* op) {
-    Ctx* c = op->ctx;
-    const size_t nq = op->lq_x.size();
-    if (op->d_lq_xi.n == nq) return;
-    op->d_lq_xi.alloc(c, nq);
-    op->d_lq_w.alloc(c, nq);
-    op->d_lq_da.alloc(c, nq);
-    op->d_lq_db.alloc(c, nq);
-    op->d_lq_off.alloc(c, op->lq_off.size());
-    upload(c, op->d_lq_xi.p, op->lq_xi.data(), nq * sizeof(double));
-    upload(c, op->d_lq_w.p, op->lq_w.data(), nq * sizeof(double));
-    upload(c, op->d_lq_da.p, op->lq_da.data(), nq * sizeof(double));
-    upload(c, op->d_lq_db.p, op->lq_db.data(), nq * sizeof(double));
-    upload(c, op->d_lq_off.p, op->lq_off.data(), op->lq_off.size() * sizeof(int));
-    op->d_lq_f.alloc(c, nq);
-}
 
 // G from the values in d_lq_f, then the lifting of the boundary values
 void assemble_load(Op* op, double c1, double c2, double* G) {
@@ -611,7 +597,6 @@ int fde_load_vector_powers(fde_op* op, int nterms, const double* coef, const dou
         if (side[k] != 0 && side[k] != 1) fail(FDE_EINVAL, "term %d: side must be 0 or 1", k);
     }
     Ctx* c = op->ctx;
-    load_rule_to_device(op);
     DevBuf<double> d_ce;
     DevBuf<int> d_s;
     const int nt = std::max(nterms, 1);
@@ -632,10 +617,12 @@ int fde_load_vector(fde_op* op, const double* f, double c1, double c2, double* G
     if (!op || !f || !G) fail(FDE_EINVAL, "bad arguments");
     if (!std::isfinite(c1) || !std::isfinite(c2)) fail(FDE_EINVAL, "boundary values must be finite");
     Ctx* c = op->ctx;
-    const size_t nq = op->lq_x.size();
-    load_rule_to_device(op);
+    const size_t nq = (size_t)op->lq_n;
     for (size_t q = 0; q < nq; ++q)
-        if (!std::isfinite(f[q])) fail(FDE_EINVAL, "f is not finite at node %zu (x = %.17g)", q, op->lq_x[q]);
+        if (!std::isfinite(f[q])) {
+            host_load_rule(op);
+            fail(FDE_EINVAL, "f is not finite at node %zu (x = %.17g)", q, op->lq_x[q]);
+        }
     upload(c, op->d_lq_f.p, f, nq * sizeof(double));
     assemble_load(op, c1, c2, G);
     FDE_API_END
@@ -644,6 +631,7 @@ int fde_load_vector(fde_op* op, const double* f, double c1, double c2, double* G
 int fde_load_vector_fn(fde_op* op, fde_fn fn, void* user, double c1, double c2, double* G) {
     FDE_API_BEGIN
     if (!op || !fn) fail(FDE_EINVAL, "bad arguments");
+    host_load_rule(op);
     std::vector<double> fv(op->lq_x.size());
     for (size_t q = 0; q < fv.size(); ++q) fv[q] = fn(op->lq_x[q], user);
     const int rc = fde_load_vector(op, fv.data(), c1, c2, G);

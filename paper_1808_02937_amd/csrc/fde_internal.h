@@ -153,15 +153,27 @@ struct Op {
     DevBuf<double> d_gen;        // Toeplitz: N generators x P x P
     DevBuf<double2> d_sym;       // Toeplitz: (L/2+1) x P x P spectrum of the generators
     DevBuf<double2> d_tw;        // twiddles for the half-length complex FFT
-    // load-vector quadrature (host + device)
-    std::vector<double> lq_x, lq_xi, lq_w, lq_da, lq_db;
+    // load-vector quadrature: lq_n nodes on the device (element e owns [lq_off[e], lq_off[e+1]));
+    // host copies of x and the end distances only once asked for
+    int lq_n = 0;
     std::vector<int> lq_off;     // N+1 offsets
-    DevBuf<double> d_lq_xi, d_lq_w, d_lq_f, d_lq_da, d_lq_db;
+    std::vector<double> lq_x, lq_da, lq_db;
+    DevBuf<double> d_lq_x, d_lq_xi, d_lq_w, d_lq_f, d_lq_da, d_lq_db;
     DevBuf<int> d_lq_off;
     // apply workspace
     DevBuf<double> ws;
     size_t apply_ws_doubles(int nrhs) const;
 };
+
+// a Gauss-Legendre panel [lo, hi] (distances from the end `side` of element elem: 0 left, 1 right)
+// of n nodes, the first at node0; ex >= 0: n nodes given explicitly from entry ex of the explicit
+// list (x, xi, w, d_a, d_b per node)
+struct LoadPanel {
+    double lo, hi;
+    int elem, side, n, node0, ex, pad;
+};
+// expand npanels panels into the operator's load-vector nodes (d_lq_x, d_lq_xi, d_lq_w, d_lq_da, d_lq_db)
+void launch_load_rule(Op* op, int npanels, const LoadPanel* d_panels, const double* d_ex);
 
 // device bytes an operator on nodes x (N elements, degree P) holds after an apply of nrhs columns
 size_t op_device_bytes(const double* x, int N, int P, int nrhs);
