@@ -28,9 +28,12 @@ __global__ void k_hbuild_dense(SemDev s, const DenseBlkDev* __restrict__ blks, c
 // (sides range from a leaf to half the matrix, so chunks keep the workgroups even); all R
 // expansion terms of the row at once: at each quadrature node the first power is one pow()
 // (none for the regular side's nu = 0) and the following ones come by repeated multiplication
-// with the same ratio ((x-c)/r, or 1/(sgn(x-c)) for the singular side).
+// with the same ratio ((x-c)/r, or 1/(sgn(x-c)) for the singular side). The workgroup first
+// stages its Gauss-Legendre rule and the Legendre values L_m(x_k), m <= P, in LDS, so the node
+// loop reads neither memory nor a recurrence.
 constexpr int kNuChunk = 16;
 constexpr int kRowsPerChunk = 128;
+constexpr int kFacMaxP = 32;
 __global__ void __launch_bounds__(kRowsPerChunk) k_hbuild_factors(int P, int R, double alpha,
                                                                   const double* __restrict__ x,
                                                                   const double* __restrict__ h,
@@ -38,11 +41,27 @@ __global__ void __launch_bounds__(kRowsPerChunk) k_hbuild_factors(int P, int R, 
                                                                   const FacSideDev* __restrict__ sides,
                                                                   const int2* __restrict__ chunks,
                                                                   double* __restrict__ arena) {
+    __shared__ double s_x[kMaxGL], s_w[kMaxGL], s_leg[(kFacMaxP + 1) * kMaxGL];
     const int2 ch = chunks[blockIdx.x];
     const FacSideDev f = sides[ch.x];
     const int nq = f.sing ? min(kMaxGL, P + 24) : min(kMaxGL, (R + P) / 2 + 2);
     const int off_n = nq * (nq - 1) / 2;
     const int wbase = kMaxGL * (kMaxGL + 1) / 2;
+    for (int k = threadIdx.x; k < nq; k += blockDim.x) {
+        const double xk = gl[off_n + k];
+        s_x[k] = xk;
+        s_w[k] = gl[wbase + off_n + k];
+        double pm = 1.0, pc = xk;   // L_0, L_1
+        s_leg[k] = 1.0;
+        if (P >= 1) s_leg[kMaxGL + k] = xk;
+        for (int m = 1; m < P; ++m) {
+            const double pn = ((2 * m + 1) * xk * pc - m * pm) / (m + 1);
+            pm = pc;
+            pc = pn;
+            s_leg[(m + 1) * kMaxGL + k] = pc;
+        }
+    }
+    __syncthreads();
     const int i = ch.y + threadIdx.x;
     if (i >= f.rows) return;
     if (f.mult == 0.0) {
@@ -75,8 +94,9 @@ __global__ void __launch_bounds__(kRowsPerChunk) k_hbuild_factors(int P, int R, 
             const int ee = el[a];
             const double xl = x[ee], he = h[ee];
             const double scale = cf[a] * 0.5 * he;
+            const double* leg = s_leg + mm[a] * kMaxGL;
             for (int k = 0; k < nq; ++k) {
-                const double xr = gl[off_n + k], w = gl[wbase + off_n + k];
+                const double xr = s_x[k], w = s_w[k];
                 const double xx = xl + 0.5 * he * (1.0 + xr);
                 double F, step;
                 if (f.sing) {
@@ -88,7 +108,7 @@ __global__ void __launch_bounds__(kRowsPerChunk) k_hbuild_factors(int P, int R, 
                     F = nu0 == 0 ? 1.0 : pow(b, (double)nu0);
                     step = b;
                 }
-                const double wl = scale * w * legendre_at(mm[a], xr);
+                const double wl = scale * w * leg[k];
 #pragma unroll
                 for (int u = 0; u < kNuChunk; ++u) {
                     acc[u] += wl * F;
@@ -153,6 +173,7 @@ void launch_hbuild_dense(Op* op, int nblk, const DenseBlkDev* d_blks, const int*
 void launch_hbuild_factors(Op* op, int R, const std::vector<FacSideDev>& sides, const FacSideDev* d_sides,
                            double* arena) {
     if (sides.empty()) return;
+    if (op->P > kFacMaxP) fail(FDE_EUNSUPPORTED, "H-matrix factors: P <= %d (got %d)", kFacMaxP, op->P);
     std::vector<int2> chunks;
     for (size_t k = 0; k < sides.size(); ++k)
         for (int r0 = 0; r0 < sides[k].rows; r0 += kRowsPerChunk) chunks.push_back(make_int2((int)k, r0));
