@@ -386,7 +386,7 @@ void build_symbol(Op* op) {
     hipLaunchKernelGGL(k_symbol_build, dim3((unsigned)ceil_div((int)tot, 256)), dim3(256), 0,
                        op->ctx->stream, P, M, op->uniform ? 1 : 0, op->theta, kw.p, op->d_sym.p);
     FDE_LAUNCH_CHECK();
-    FDE_HIP(hipStreamSynchronize(op->ctx->stream));
+    // kw goes back to the context's stream-ordered cache: work queued later on the stream reuses it
 }
 
 void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int ldy, double bc0,
