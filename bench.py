@@ -14,6 +14,7 @@ with cached factors, the phase split, p50/p99 latency, the roofline of the
 dominant kernel and the CPU oracle baseline.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -263,6 +264,11 @@ def main():
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
         mixed.step()
+    # one full collection before the timed region, and the objects alive then kept out of later
+    # ones: a collection of the whole heap (torch, numpy, the warm-up's objects) inside a timed
+    # step costs tens of milliseconds of host time
+    gc.collect()
+    gc.freeze()
     log(f"timing {args.steps} steps")
     lat = []
     torch.cuda.synchronize()
