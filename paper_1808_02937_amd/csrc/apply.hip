@@ -390,11 +390,15 @@ void build_symbol(Op* op) {
 }
 
 void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int ldy, double bc0,
-                     double bcN, bool zero_x) {
+                     double bcN, bool zero_x, hipStream_t on) {
     const int N = op->N, P = op->P, Nd = op->Nd;
-    hipStream_t st = op->ctx->stream;
+    hipStream_t st = on ? on : op->ctx->stream;
     const size_t need = op->apply_ws_doubles(nrhs);
-    if (op->ws.n < need) op->ws.alloc(op->ctx, need);
+    if (op->ws.n < need) {
+        // blocks come from the context's cache, ordered on its stream: another stream must not get one
+        if (on && on != op->ctx->stream) fail(FDE_EDEVICE, "apply workspace not reserved before a side-stream apply");
+        op->ws.alloc(op->ctx, need);
+    }
     double* c = op->ws.p;
     double* z = c + (size_t)nrhs * N * P;
     double* rest = z + (size_t)nrhs * N * P;

@@ -72,6 +72,9 @@ Ctx::~Ctx() {
     (void)hipStreamSynchronize(stream);
     plans.clear();   // members holding blocks give them back before the cache is released
     lu_tasks.reset();
+    for (hipStream_t s : side) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : side_done) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
     gl.reset();
     while (!staged.empty()) retire_oldest(this);
     for (hipEvent_t e : spare_events) (void)hipEventDestroy(e);

@@ -133,6 +133,11 @@ struct Ctx {
     std::vector<std::pair<std::string, std::shared_ptr<Plan>>> plans;
     // task list of the last batched factorisation (it depends only on the batch's plans)
     std::shared_ptr<void> lu_tasks;
+    // side streams (default priority) for independent small work forked from and joined back into
+    // `stream`: the per-operator applies of a batched Krylov step
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_done;
+    hipEvent_t fork_ev = nullptr;
 };
 
 // ---------------------------------------------------------------- operator
@@ -188,8 +193,10 @@ void launch_eval_powers(Op* op, int nt, const double* d_coef, const double* d_ex
 void launch_dense_matrix(Op* op, double* A, int lda);
 
 // apply (apply.hip): Y = A X (+ boundary values bc0/bcN of the lifting)
+// on: the stream to run on (nullptr: the context's); on another stream the workspace for nrhs
+// columns must already exist (reserve_apply on the context's stream)
 void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int ldy, double bc0,
-                     double bcN, bool zero_x);
+                     double bcN, bool zero_x, hipStream_t on = nullptr);
 void build_symbol(Op* op);
 
 // blas1.hip

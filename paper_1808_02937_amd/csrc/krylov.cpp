@@ -34,6 +34,53 @@ struct Group {
     DevBuf<char> rhs, work;   // H-solve buffers of this group
 };
 
+// The per-operator applies of a Krylov step are independent small kernel chains (a few
+// workgroups each). They run concurrently: the groups are spread over the context's stream and up
+// to kSideStreams side streams, forked after the work queued so far and joined back before the
+// next step. Groups of one operator share a stream, since the operator's workspace is theirs.
+constexpr int kSideStreams = 3;
+
+void ensure_side_streams(Ctx* c) {
+    if (!c->side.empty()) return;
+    for (int k = 0; k < kSideStreams; ++k) {
+        hipStream_t s = nullptr;
+        FDE_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        c->side.push_back(s);
+        hipEvent_t e = nullptr;
+        FDE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->side_done.push_back(e);
+    }
+    FDE_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+}
+
+// fn(group, stream) for every group with right-hand sides
+template <class F>
+void apply_groups(Ctx* c, std::vector<Group>& groups, F fn) {
+    int active = 0;
+    for (auto& g : groups)
+        if (g.nr) ++active;
+    if (active <= 1) {
+        for (auto& g : groups)
+            if (g.nr) fn(g, c->stream);
+        return;
+    }
+    ensure_side_streams(c);
+    FDE_HIP(hipEventRecord(c->fork_ev, c->stream));
+    for (hipStream_t s : c->side) FDE_HIP(hipStreamWaitEvent(s, c->fork_ev, 0));
+    std::vector<Op*> seen;   // operator -> stream slot (0: the context's stream)
+    for (auto& g : groups) {
+        if (!g.nr) continue;
+        size_t slot = std::find(seen.begin(), seen.end(), g.op) - seen.begin();
+        if (slot == seen.size()) seen.push_back(g.op);
+        const int k = (int)(slot % (kSideStreams + 1));
+        fn(g, k == 0 ? c->stream : c->side[k - 1]);
+    }
+    for (int k = 0; k < kSideStreams; ++k) {
+        FDE_HIP(hipEventRecord(c->side_done[k], c->side[k]));
+        FDE_HIP(hipStreamWaitEvent(c->stream, c->side_done[k], 0));
+    }
+}
+
 template <class T>
 Inst<T> group_inst(Group& g, int m) {
     Inst<T> d = g.prec->inst<T>(true, g.nr, g.V.p, g.op->Nd, g.Z.p, g.op->Nd);
@@ -159,6 +206,13 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
         upload(c, d_i64.p, i64.data(), i64.size() * sizeof(Inst<double>));
     }
     const bool any_copy = std::any_of(mask.begin(), mask.end(), [](int v) { return v != 0; });
+    // apply workspaces come from the context's cache, ordered on its stream: reserve them here,
+    // before any apply runs on a side stream
+    for (auto& g : groups)
+        if (g.nr) {
+            const size_t need = g.op->apply_ws_doubles(g.nr);
+            if (g.op->ws.n < need) g.op->ws.alloc(c, need);
+        }
     fg_gnorm(st, ns, d_sys.p, d_ss.p);
     fg_zero_x(st, ns, d_sys.p);
     std::vector<SysState> hs(ns);
@@ -180,9 +234,10 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
                 else
                     launch_interp<double>(st, (int)i64.size(), d_i64.p, j);
             }
-            for (auto& g : groups)
-                if (g.nr) stiffness_apply(g.op, g.nr, g.Z.p + (int64_t)j * g.op->Nd * g.nr, g.op->Nd, g.W.p,
-                                          g.op->Nd, 0.0, 0.0, false);
+            apply_groups(c, groups, [&](Group& g, hipStream_t s) {
+                stiffness_apply(g.op, g.nr, g.Z.p + (int64_t)j * g.op->Nd * g.nr, g.op->Nd, g.W.p, g.op->Nd, 0.0, 0.0,
+                                false, s);
+            });
             fg_arnoldi(st, ns, d_sys.p, d_ss.p, j, m, rtol, maxit);
             int active = 0;
             fg_count_active(st, ns, d_ss.p, d_count.p);
@@ -191,8 +246,9 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
             if (active == 0) break;
         }
         fg_update(st, ns, d_sys.p, d_ss.p);
-        for (auto& g : groups)
-            if (g.nr) stiffness_apply(g.op, g.nr, g.X, g.ldx, g.R.p, g.op->Nd, 0.0, 0.0, false);
+        apply_groups(c, groups, [&](Group& g, hipStream_t s) {
+            stiffness_apply(g.op, g.nr, g.X, g.ldx, g.R.p, g.op->Nd, 0.0, 0.0, false, s);
+        });
         fg_check(st, ns, d_sys.p, d_ss.p, rtol);
         FDE_HIP(hipMemcpyAsync(hs.data(), d_ss.p, ns * sizeof(SysState), hipMemcpyDeviceToHost, st));
         FDE_HIP(hipStreamSynchronize(st));
