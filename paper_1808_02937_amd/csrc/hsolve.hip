@@ -48,6 +48,11 @@ struct HsDepth<double, WC> {
     static constexpr int kD = WC == 1 ? 10 : WC == 2 ? 11 : WC == 4 ? 16 : 10;
 };
 
+// a * b + c rounded once, whatever the surrounding selects (the masked products below must
+// round as the unmasked ones would, in every chunk-width instance of the kernel)
+__device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // 32 bytes per lane: a step record (same for every lane) or lane l's record of a step
 struct Vec8 {
     int a[8];
@@ -167,10 +172,11 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
     T* part1 = tb + (int64_t)d.hs_tslots * kmax * wc;      // kHW x 64 x wc (phase 1 partial sums)
     T* part2 = part1 + kHT * wc;                           // 2 x kHW x 64 x wc (early sums, by step parity)
     // staged diagonal leaf (64 x 64, ld 64) and its diagonal entries, two buffers by step parity:
-    // the solve of step s reads buffer s & 1 while the helpers stage step s + 1 in the other
+    // the solve of step s reads buffer s & 1 while the helpers stage step s + 1 in the other; a
+    // third row of diagonal slots takes the writes of the lanes off the diagonal
     T* Dg2 = part2 + 2 * kHT * wc;
     T* Dd2 = Dg2 + 2 * kHsolveMaxRow * kHsolveMaxRow;
-    int* rk = reinterpret_cast<int*>(Dd2 + 2 * kHsolveMaxRow);
+    int* rk = reinterpret_cast<int*>(Dd2 + 3 * kHsolveMaxRow);
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // phase 2 roles: waves [0, wce) solve; helpers h0 .. 7 gather for the next leaf and stage
     const int h0 = wc < kHW ? wc : 0, nh = kHW - h0;
@@ -180,6 +186,7 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
     const HsStep* steps = d.hs_steps;
     const HsRec* recs = d.hs_recs;
     for (int s = threadIdx.x; s < d.nslots; s += kHT) rk[s] = d.ranks[s];
+    for (int q = threadIdx.x; q < 2 * kHT * wc; q += kHT) part2[q] = T(0);
     const double* Bs = d.B + (int64_t)step * d.bstep + (int64_t)c0 * d.ldb;
     double* Xs = d.X + (int64_t)step * d.xstep + (int64_t)c0 * d.ldx;
     for (int idx = threadIdx.x; idx < Nd * wc; idx += kHT) {
@@ -194,13 +201,20 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
     // the staged leaf of a step: the strict lower (forward) or upper (backward) triangle, zero
     // elsewhere and in the rows and columns beyond the leaf, so the substitution needs no masks;
     // backward steps also keep the diagonal in Dd
+    // (rows lo < row < hi of column c are kept; every lane stores, the diagonal's lane into the
+    // buffer's diagonal slots and the others into the junk row, so no store sits on a branch)
     auto stage = [&](T v, int c, int nd, bool fwdst, int buf) {
         int ln = lane;   // opaque: the per-column masks are not hoisted out of the step loop
         asm volatile("" : "+v"(ln));
-        const bool in = ln < nd && c < nd;
-        T* Dg = Dg2 + buf * kHsolveMaxRow * kHsolveMaxRow;
-        Dg[ln + c * kHsolveMaxRow] = (in && (fwdst ? c < ln : c > ln)) ? v : T(0);
-        if (c == ln) Dd2[buf * kHsolveMaxRow + ln] = in ? v : T(1);
+        const int lo = fwdst ? c : -1, hi = c < nd ? (fwdst ? nd : c) : 0;
+        Dg2[buf * kHsolveMaxRow * kHsolveMaxRow + ln + c * kHsolveMaxRow] = (ln > lo && ln < hi) ? v : T(0);
+        Dd2[(c == ln ? buf : 2) * kHsolveMaxRow + ln] = c < nd ? v : T(1);
+    };
+    // a value loaded off the prefetch path is waited for where it is loaded: no load stays in
+    // flight past a branch, which would make the compiler wait for every load at the join
+    auto consume = [&](const T(&vv)[kHsChunk]) {
+#pragma unroll
+        for (int c = 0; c < kHsChunk; ++c) asm volatile("" ::"v"(vv[c]));
     };
     for (int c = wave; c < kHsolveMaxRow; c += kHW) {
         const bool in = lane < S0.nrow && c < S0.nrow;
@@ -218,7 +232,7 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
             const bool live = k < np;
             const RecS r = rec_lane(R, min(k, 63));
             const bool late = k < S.nlate;
-            const int cols = late ? r.n : rk[live && !late ? r.slot : 0];
+            const int cols = late ? r.n : kmax;   // low rank: the stored columns (masked by the rank at use)
             load_block(av1[i], arena, live ? r.off : 0, live ? r.ld : 0, live ? (late ? S.nrow : r.n) : 1,
                        live ? cols : 1, 0, lane);
         }
@@ -231,7 +245,7 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
             const int e = hw + nh * i;
             const bool live = helper && e < S.nearly;
             const RecS r = rec_lane(R, min(base + e, 63));
-            const int cols = r.kind == HS_DENSE ? r.n : rk[live && r.kind != HS_DENSE ? r.slot : 0];
+            const int cols = r.kind == HS_DENSE ? r.n : kmax;
             load_block(av2[i], arena, live ? r.off : 0, live ? r.ld : 0, live ? rows : 1, live ? cols : 1, 0, lane);
         }
     };
@@ -297,16 +311,22 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
                 const RecS r = rec_lane(R0, k);
                 if (k < S0.nlate) {
                     // late chunk: rows of this leaf times entries of the leaf solved just before
-                    if (lane == 0) flops += 2.0 * n * r.n * wce;
+                    // (columns past the chunk masked, value and factor, without branches)
+                    flops += 2.0 * n * r.n * wce;
 #pragma unroll
-                    for (int c = 0; c < kHsChunk; ++c)
-                        if (c < r.n)
+                    for (int c = 0; c < kHsChunk; ++c) {
+                        const bool keep = c < r.n;
+                        const T a = keep ? vv[c] : T(0);
 #pragma unroll
-                            for (int j = 0; j < WC; ++j)
-                                if (j < wc) acc[j] += vv[c] * X[r.col0 + c + (int64_t)j * Nd];
+                        for (int j = 0; j < WC; ++j)
+                            if (j < wc) {
+                                const T xv = X[r.col0 + c + (int64_t)j * Nd];
+                                acc[j] = fma_t(a, keep ? xv : T(0), acc[j]);
+                            }
+                    }
                 } else {
                     // increment of t_B by the rows of the leaf solved just before
-                    if (lane == 0) flops += 2.0 * r.n * rk[r.slot] * wce;
+                    flops += 2.0 * r.n * rk[r.slot] * wce;
                     inc_chunk(r, vv, 0);
                 }
             };
@@ -322,6 +342,7 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
                 T vv[kHsChunk];
                 if (k < S0.nlate) load_block(vv, arena, r.off, r.ld, n, r.n, 0, lane);
                 else load_block(vv, arena, r.off, r.ld, r.n, rk[r.slot], 0, lane);
+                consume(vv);
                 p1_item(k, vv);
             }
             for (int k = wave; k < np1; k += kHW) {
@@ -331,14 +352,14 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
                 for (int cb = kHsChunk; cb < rank; cb += kHsChunk) {
                     T vv[kHsChunk];
                     load_block(vv, arena, r.off, r.ld, r.n, rank, cb, lane);
+                    consume(vv);
                     inc_chunk(r, vv, cb);
                 }
             }
-            if (wave < S0.nlate) {
+            // every wavefront stores its partial sums (zeros without late chunks)
 #pragma unroll
-                for (int j = 0; j < WC; ++j)
-                    if (j < wc) part1[(wave * 64 + lane) * wc + j] = acc[j];
-            }
+            for (int j = 0; j < WC; ++j)
+                if (j < wc) part1[(wave * 64 + lane) * wc + j] = acc[j];
         }
         // the next step's phase-1 values, the records two steps ahead, the step after those
         prefetch1(S1, R1);
@@ -350,12 +371,20 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
         if (wave < wce) {
             // solve: y = b - late partials - early partials; T^{-1} y with the leaf in registers
             const int j = wave;
-            T y = lane < n ? X[S0.row0 + lane + (int64_t)j * Nd] : T(0);
-            const int nw1 = min(kHW, S0.nlate), nw2 = min(nh, nearly_prev);
+            const int li = min(lane, n - 1);
+            T y = X[S0.row0 + li + (int64_t)j * Nd];
+            y = lane < n ? y : T(0);
+            // every wavefront's partial sums, zero where it had nothing to add (all read at once)
             const T* p2 = part2 + (s & 1) * kHT * wc;
-            for (int w = 0; w < nw1; ++w) y -= part1[(w * 64 + lane) * wc + j];
-            for (int h = 0; h < nw2; ++h) y -= p2[(h * 64 + lane) * wc + j];
-            if (lane == 0) flops += (double)n * n;
+            T ps[2 * kHW];
+#pragma unroll
+            for (int w = 0; w < kHW; ++w) {
+                ps[w] = part1[(w * 64 + lane) * wc + j];
+                ps[kHW + w] = p2[(w * 64 + lane) * wc + j];
+            }
+#pragma unroll
+            for (int w = 0; w < 2 * kHW; ++w) y -= ps[w];
+            flops += (double)n * n;
             T x = y * dinv;
             // the staged triangle is zero outside the leaf, so blocks of 8 columns up to n need no
             // masks; the lane's row is read from LDS a block ahead of the substitution
@@ -389,7 +418,8 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
                     for (int i = 0; i < 8; ++i) cur[i] = nxt[i];
                 }
             }
-            if (lane < n) X[S0.row0 + lane + (int64_t)j * Nd] = x;
+            // rows past the leaf store into the junk diagonal row
+            *(lane < n ? X + S0.row0 + lane + (int64_t)j * Nd : Dd2 + 2 * kHsolveMaxRow + lane) = x;
             phase(8);   // thread 0 (a solving wavefront): the triangular solve done
         }
         if (helper) {
@@ -403,27 +433,28 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
             }
             // early items: contributions to the next leaf's rows from leaves before this one
             const int m = S1.nrow, base = S0.nlate + S0.ninc;
-            if (hw < S0.nearly) {
+            {
                 T acc[WC];
 #pragma unroll
                 for (int j = 0; j < WC; ++j) acc[j] = T(0);
-                // columns cb..cb+7 of an early item (dense chunk, or U_B rows times t_B)
+                // columns cb..cb+7 of an early item: element (c, j) of the right factor is
+                // src[c * sc + j * sj] (dense chunk: x of an older leaf; low rank: t_B); columns from
+                // `cols` on are masked, value and factor, without branches
                 auto p2_chunk = [&](const RecS& r, const T (&vv)[kHsChunk], int cb, int cols) {
-                    if (r.kind == HS_DENSE) {
+                    const bool dense = r.kind == HS_DENSE;
+                    const T* src = dense ? X + r.col0 : tb + (int64_t)r.tslot * kmax * wc;
+                    const int sc = dense ? 1 : wc;
+                    const int64_t sj = dense ? (int64_t)Nd : 1;
 #pragma unroll
-                        for (int c = 0; c < kHsChunk; ++c)
-                            if (c < cols)
+                    for (int c = 0; c < kHsChunk; ++c) {
+                        const bool keep = cb + c < cols;
+                        const T a = keep ? vv[c] : T(0);
 #pragma unroll
-                                for (int j = 0; j < WC; ++j)
-                                    if (j < wc) acc[j] += vv[c] * X[r.col0 + c + (int64_t)j * Nd];
-                    } else {
-                        const T* t = tb + (int64_t)r.tslot * kmax * wc;
-#pragma unroll
-                        for (int c = 0; c < kHsChunk; ++c)
-                            if (cb + c < cols)
-#pragma unroll
-                                for (int j = 0; j < WC; ++j)
-                                    if (j < wc) acc[j] += vv[c] * t[(cb + c) * wc + j];
+                        for (int j = 0; j < WC; ++j)
+                            if (j < wc) {
+                                const T xv = src[(int64_t)(cb + c) * sc + j * sj];
+                                acc[j] = fma_t(a, keep ? xv : T(0), acc[j]);
+                            }
                     }
                 };
                 auto cols_of = [&](const RecS& r) { return r.kind == HS_DENSE ? r.n : rk[r.slot]; };
@@ -434,7 +465,7 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
                     if (e < S0.nearly) {
                         const RecS r = rec_lane(R0, base + e);
                         const int cols = cols_of(r);
-                        if (lane == 0) flops += 2.0 * m * cols * wce;
+                        flops += 2.0 * m * cols * wce;
                         p2_chunk(r, av2[i], 0, cols);
                     }
                 }
@@ -442,9 +473,10 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
                 for (int e = hw + nh * D::kP2; e < S0.nearly; e += nh) {
                     const RecS r = rec_lane(R0, base + e);
                     const int cols = cols_of(r);
-                    if (lane == 0) flops += 2.0 * m * cols * wce;
+                    flops += 2.0 * m * cols * wce;
                     T vv[kHsChunk];
                     load_block(vv, arena, r.off, r.ld, m, cols, 0, lane);
+                    consume(vv);
                     p2_chunk(r, vv, 0, cols);
                 }
                 for (int e = hw; e < S0.nearly; e += nh) {
@@ -453,9 +485,11 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
                     for (int cb = kHsChunk; cb < cols; cb += kHsChunk) {
                         T vv[kHsChunk];
                         load_block(vv, arena, r.off, r.ld, m, cols, cb, lane);
+                        consume(vv);
                         p2_chunk(r, vv, cb, cols);
                     }
                 }
+                // every helper stores (zeros without items); slots of non-helpers stay zero
                 T* p2 = part2 + ((s + 1) & 1) * kHT * wc;
 #pragma unroll
                 for (int j = 0; j < WC; ++j)
@@ -464,7 +498,9 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
             // columns of the next leaf beyond the prefetch depth (chunks of several columns)
             for (int c = hw + D::kD * nh; c < kHsolveMaxRow; c += nh) {
                 const bool in = lane < S1.nrow && c < S1.nrow;
-                stage(in ? gmem(arena)[S1.diag + lane + (int64_t)c * S1.nrow] : T(0), c, S1.nrow, fwd1, (s + 1) & 1);
+                const T v = gmem(arena)[in ? S1.diag + lane + (int64_t)c * S1.nrow : 0];
+                asm volatile("" ::"v"(v));
+                stage(v, c, S1.nrow, fwd1, (s + 1) & 1);
             }
             if (d.prof && lane == 0 && hw == 0) pt[3] += wall_clock64() - th0;   // the first helper
         }
@@ -517,7 +553,7 @@ void allow_lds(K kernel, size_t bytes) {
 
 size_t hsolve_lds_bytes(int Nd, int tslots, int kmax, int nslots, int wc, size_t esz) {
     return ((size_t)Nd + (size_t)tslots * kmax + 3 * kHT) * wc * esz +
-           2 * (size_t)(kHsolveMaxRow + 1) * kHsolveMaxRow * esz + (size_t)nslots * sizeof(int) + 16;
+           (size_t)(2 * kHsolveMaxRow + 3) * kHsolveMaxRow * esz + (size_t)nslots * sizeof(int) + 16;
 }
 
 size_t device_lds_limit(int device) {
