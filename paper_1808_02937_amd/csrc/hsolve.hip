@@ -249,18 +249,24 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
             load_block(av2[i], arena, live ? r.off : 0, live ? r.ld : 0, live ? rows : 1, live ? cols : 1, 0, lane);
         }
     };
-    // leaf of step S staged by the helpers, helper hw taking columns hw, hw + nh, ...
+    // leaf of step S staged by the helpers, helper hw taking columns hw, hw + nh, ... Every
+    // wavefront loads, rows and columns clamped into the leaf (a step past the end has no rows and
+    // reads the arena's first entry): straight-line loads, so the compiler counts them exactly
+    // and waits for no later prefetch where the values are staged
     auto prefetch_diag = [&](const StepS& S) {
+        const int nr = max(S.nrow, 1);
+        const int li = min(lane, nr - 1);
 #pragma unroll
         for (int q = 0; q < D::kD; ++q) {
-            const int c = hw + q * nh;
-            const bool live = helper && lane < S.nrow && c < S.nrow;
-            dv[q] = gmem(arena)[live ? S.diag + lane + (int64_t)c * S.nrow : 0];
+            const int c = min(hw + q * nh, nr - 1);
+            dv[q] = gmem(arena)[S.diag + li + (int64_t)c * nr];
         }
     };
+    // the same issue order as at the end of a step (diagonal leaf, then early values): the
+    // compiler's wait counts merge the two at the loop head and stay exact
     prefetch1(S0, R0);
-    prefetch2(S0, R0, S1.nrow);
     prefetch_diag(S1);
+    prefetch2(S0, R0, S1.nrow);
     // op profile: step phases timed by thread 0 and the first helper's lane 0, added to the
     // profile once after the loop (no atomics in the loop: a pending flat atomic makes every
     // later wait for a prefetched value a wait for all loads)
