@@ -32,6 +32,7 @@ struct Inst {
     const HsRec* hs_recs;
     int hs_nleaf, hs_tslots;
     int hs_wc;                // leaf-step H-solve: columns per workgroup (1, 2, 4 or 8)
+    const T* hs_prep;         // leaf-step H-solve: 2 * hs_nleaf solve-ready diagonal leaves (kHsPrepStride each)
     double tol;
     int kmax;
     double pivot_floor;
@@ -54,6 +55,9 @@ void launch_interp_one(hipStream_t st, const Inst<T>& d);
 // H-solve with the right-hand sides in LDS: workgroup b solves columns [c*w, c*w + w) of
 // instance b / nchunk (c = b % nchunk, w = its hs_wc <= wc, wc in {1, 2, 4, 8}); lds_bytes
 // from hsolve_lds_bytes, the largest over the instances
+// the solve-ready diagonal leaves of every leaf step (2 * nleaf of them) from the factors
+template <class T>
+void launch_hs_prepare(hipStream_t st, const T* arena, const HsStep* steps, int nleaf, T* prep);
 template <class T>
 void launch_hsolve(hipStream_t st, int ninst, int nchunk, int wc, const Inst<T>* d_insts, int step,
                    size_t lds_bytes);
@@ -63,6 +67,11 @@ void launch_hsolve_one(hipStream_t st, const Inst<T>& d, int nchunk, int wc, siz
 size_t hsolve_lds_bytes(int Nd, int tslots, int kmax, int nslots, int wc, size_t esz);
 constexpr int kHsolveMaxRow = 64;   // leaf-step H-solve: leaves of at most this many rows
 constexpr int kHsolveMaxCols = 8;
+// leaf-step H-solve: per step, its diagonal leaf in solve-ready form (64 x 64, column-major, the
+// strict lower triangle of L forward, the strict upper triangle of U with each row divided by its
+// diagonal entry backward, zero elsewhere), then 64 row scales (1 forward, 1/U_ii backward, 1
+// past the leaf)
+constexpr int kHsPrepStride = kHsolveMaxRow * kHsolveMaxRow + kHsolveMaxRow;
 // largest dynamic LDS of one workgroup on the device (bytes)
 size_t device_lds_limit(int device);
 

@@ -46,6 +46,7 @@ struct HLUObj {
     int kmax = 8;
     size_t esz = 4;               // bytes per factor element
     DevBuf<char> arena, work_lu, scr, sv_rhs, sv_work;
+    DevBuf<char> hs_prep;              // leaf-step H-solve: solve-ready diagonal leaves (after each factorisation)
     DevBuf<double> scrd;
     DevBuf<int> ranks, status;
     DevBuf<unsigned long long> prof;   // op profile (FDE_PROFILE_OPS=1)
@@ -79,6 +80,7 @@ struct HLUObj {
         d.hs_recs = plan->d_hs_recs.p;
         d.hs_nleaf = plan->hs.nleaf;
         d.hs_tslots = plan->hs.tslots;
+        d.hs_prep = reinterpret_cast<const T*>(hs_prep.p);
         d.tol = tol;
         d.kmax = kmax;
         d.pivot_floor = pivot_floor;

@@ -231,6 +231,11 @@ void factor_batch_run(Ctx* c, std::vector<HLUObj*>& fs, const char* what) {
         if (prof_levels) FDE_HIP(hipEventRecord(lev_ev.back(), c->stream));
     }
     FDE_HIP(hipEventRecord(ev.b, c->stream));
+    // the H-solve's diagonal leaves in solve-ready form, from the factors just computed
+    for (HLUObj* f : fs)
+        if (f->plan->sv_lds)
+            launch_hs_prepare<T>(c->stream, reinterpret_cast<const T*>(f->arena.p), f->plan->d_hs_steps.p,
+                                 f->plan->hs.nleaf, reinterpret_cast<T*>(f->hs_prep.p));
     if (prof_levels) {
         // per level: time, tasks and the op mix of the first factorisation; the slowest levels
         FDE_HIP(hipEventSynchronize(lev_ev.back()));
@@ -336,6 +341,7 @@ void factor_prepare(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
     f->work_lu.alloc(c, std::max<int64_t>(P.lu.work_elems, 1) * f->esz);
     f->scr.alloc(c, P.lu.scr_t * f->esz);
     f->scrd.alloc(c, P.lu.scr_d);
+    if (P.sv_lds) f->hs_prep.alloc(c, (int64_t)2 * P.hs.nleaf * kHsPrepStride * f->esz);
     f->status.alloc(c, 2);
     FDE_HIP(hipMemsetAsync(f->status.p, 0, 2 * sizeof(int), c->stream));
     f->flops.alloc(c, 2);

@@ -198,30 +198,22 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
     StepS S1 = step_of(load_step(steps, 1, nsteps));
     StepS S2 = step_of(load_step(steps, 2, nsteps));
     Vec8 R0 = load_recs(recs, S0, lane, steps), R1 = load_recs(recs, S1, lane, steps), R2;
-    // the staged leaf of a step: the strict lower (forward) or upper (backward) triangle, zero
-    // elsewhere and in the rows and columns beyond the leaf, so the substitution needs no masks;
-    // backward steps also keep the diagonal in Dd
-    // (rows lo < row < hi of column c are kept; every lane stores, the diagonal's lane into the
-    // buffer's diagonal slots and the others into the junk row, so no store sits on a branch)
-    auto stage = [&](T v, int c, int nd, bool fwdst, int buf) {
-        int ln = lane;   // opaque: the per-column masks are not hoisted out of the step loop
-        asm volatile("" : "+v"(ln));
-        const int lo = fwdst ? c : -1, hi = c < nd ? (fwdst ? nd : c) : 0;
-        Dg2[buf * kHsolveMaxRow * kHsolveMaxRow + ln + c * kHsolveMaxRow] = (ln > lo && ln < hi) ? v : T(0);
-        Dd2[(c == ln ? buf : 2) * kHsolveMaxRow + ln] = c < nd ? v : T(1);
-    };
+    // the staged leaf of a step is its solve-ready form (the strict triangle, rows divided by
+    // their diagonal entry backward, zero elsewhere and past the leaf, so the substitution needs
+    // no masks), copied as it is; its row scales go to Dd
+    const T* prep = d.hs_prep;
+    auto prep_of = [&](int si) { return prep + (int64_t)min(si, nsteps - 1) * kHsPrepStride; };
+    auto stage = [&](T v, int c, int buf) { Dg2[buf * kHsolveMaxRow * kHsolveMaxRow + lane + c * kHsolveMaxRow] = v; };
     // a value loaded off the prefetch path is waited for where it is loaded: no load stays in
     // flight past a branch, which would make the compiler wait for every load at the join
     auto consume = [&](const T(&vv)[kHsChunk]) {
 #pragma unroll
         for (int c = 0; c < kHsChunk; ++c) asm volatile("" ::"v"(vv[c]));
     };
-    for (int c = wave; c < kHsolveMaxRow; c += kHW) {
-        const bool in = lane < S0.nrow && c < S0.nrow;
-        stage(in ? gmem(arena)[S0.diag + lane + (int64_t)c * S0.nrow] : T(0), c, S0.nrow, 0 < L, 0);
-    }
+    for (int c = wave; c < kHsolveMaxRow; c += kHW) stage(gmem(prep)[lane + c * kHsolveMaxRow], c, 0);
+    if (wave == 0) Dd2[lane] = gmem(prep)[kHsolveMaxRow * kHsolveMaxRow + lane];
     __syncthreads();   // ranks and the first leaf in LDS
-    T av1[D::kP1][kHsChunk], av2[D::kP2][kHsChunk], dv[D::kD];
+    T av1[D::kP1][kHsChunk], av2[D::kP2][kHsChunk], dv[D::kD], dvs;
     // phase-1 values of step S: wavefront w takes items w, w + 8, ... (late chunks: rows of S's
     // leaf; increments: rows of the leaf before, columns up to the rank)
     auto prefetch1 = [&](const StepS& S, const Vec8& R) {
@@ -249,23 +241,20 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
             load_block(av2[i], arena, live ? r.off : 0, live ? r.ld : 0, live ? rows : 1, live ? cols : 1, 0, lane);
         }
     };
-    // leaf of step S staged by the helpers, helper hw taking columns hw, hw + nh, ... Every
-    // wavefront loads, rows and columns clamped into the leaf (a step past the end has no rows and
-    // reads the arena's first entry): straight-line loads, so the compiler counts them exactly
-    // and waits for no later prefetch where the values are staged
-    auto prefetch_diag = [&](const StepS& S) {
-        const int nr = max(S.nrow, 1);
-        const int li = min(lane, nr - 1);
+    // solve-ready leaf of step si staged by the helpers, helper hw taking columns hw, hw + nh, ...,
+    // and its row scales. Every wavefront loads (columns clamped into the leaf, a step past the
+    // end reads the last one): straight-line loads, so the compiler counts them exactly and waits
+    // for no later prefetch where the values are staged
+    auto prefetch_diag = [&](int si) {
+        const auto pp = gmem(prep_of(si));
 #pragma unroll
-        for (int q = 0; q < D::kD; ++q) {
-            const int c = min(hw + q * nh, nr - 1);
-            dv[q] = gmem(arena)[S.diag + li + (int64_t)c * nr];
-        }
+        for (int q = 0; q < D::kD; ++q) dv[q] = pp[lane + min(hw + q * nh, kHsolveMaxRow - 1) * kHsolveMaxRow];
+        dvs = pp[kHsolveMaxRow * kHsolveMaxRow + lane];
     };
     // the same issue order as at the end of a step (diagonal leaf, then early values): the
     // compiler's wait counts merge the two at the loop head and stay exact
     prefetch1(S0, R0);
-    prefetch_diag(S1);
+    prefetch_diag(1);
     prefetch2(S0, R0, S1.nrow);
     // op profile: step phases timed by thread 0 and the first helper's lane 0, added to the
     // profile once after the loop (no atomics in the loop: a pending flat atomic makes every
@@ -286,7 +275,7 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
         const bool fwd = s < L;
         // ---------------- phase 1
         const int n = S0.nrow;
-        if (wave < wce) dinv = fwd ? T(1) : T(1) / Dd2[(s & 1) * kHsolveMaxRow + lane];   // backward: row / diagonal
+        if (wave < wce) dinv = Dd2[(s & 1) * kHsolveMaxRow + lane];   // 1 forward, 1 / diagonal backward
         {
             T acc[WC];
 #pragma unroll
@@ -413,11 +402,11 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
             } else {
                 const int top = ((n - 1) / 8) * 8;   // first block holding a column < n
 #pragma unroll
-                for (int i = 0; i < 8; ++i) cur[i] = drow[(top + i) * kHsolveMaxRow] * dinv;
+                for (int i = 0; i < 8; ++i) cur[i] = drow[(top + i) * kHsolveMaxRow];
                 for (int cb = top; cb >= 0; cb -= 8) {
                     if (cb >= 8)
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) nxt[i] = drow[(cb - 8 + i) * kHsolveMaxRow] * dinv;
+                        for (int i = 0; i < 8; ++i) nxt[i] = drow[(cb - 8 + i) * kHsolveMaxRow];
 #pragma unroll
                     for (int i = 7; i >= 0; --i) x -= cur[i] * lane_bcast(x, cb + i);
 #pragma unroll
@@ -431,12 +420,12 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
         if (helper) {
             const unsigned long long th0 = (d.prof && lane == 0 && hw == 0) ? wall_clock64() : 0ull;
             // the next leaf into LDS (loaded a step ago)
-            const bool fwd1 = s + 1 < L;
 #pragma unroll
             for (int q = 0; q < D::kD; ++q) {
                 const int c = hw + q * nh;
-                if (c < kHsolveMaxRow) stage(dv[q], c, S1.nrow, fwd1, (s + 1) & 1);
+                if (c < kHsolveMaxRow) stage(dv[q], c, (s + 1) & 1);
             }
+            if (hw == 0) Dd2[((s + 1) & 1) * kHsolveMaxRow + lane] = dvs;
             // early items: contributions to the next leaf's rows from leaves before this one
             const int m = S1.nrow, base = S0.nlate + S0.ninc;
             {
@@ -503,15 +492,14 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
             }
             // columns of the next leaf beyond the prefetch depth (chunks of several columns)
             for (int c = hw + D::kD * nh; c < kHsolveMaxRow; c += nh) {
-                const bool in = lane < S1.nrow && c < S1.nrow;
-                const T v = gmem(arena)[in ? S1.diag + lane + (int64_t)c * S1.nrow : 0];
+                const T v = gmem(prep_of(s + 1))[lane + c * kHsolveMaxRow];
                 asm volatile("" ::"v"(v));
-                stage(v, c, S1.nrow, fwd1, (s + 1) & 1);
+                stage(v, c, (s + 1) & 1);
             }
             if (d.prof && lane == 0 && hw == 0) pt[3] += wall_clock64() - th0;   // the first helper
         }
         // every wavefront: the leaf after next, the next step's early values
-        prefetch_diag(S2);
+        prefetch_diag(s + 2);
         prefetch2(S1, R1, S2.nrow);
         __syncthreads();
         phase(7);
@@ -532,6 +520,32 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
             if (pt[k]) atomicAdd(&d.prof[2 * kOpCodes + 6 + k], pt[k]);
         if (threadIdx.x == 0) atomicAdd(&d.prof[2 * OP_TRSM + 1], (unsigned long long)nsteps);
     }
+}
+
+// Solve-ready diagonal leaf of each step (workgroup = step): forward, the strict lower triangle of
+// the packed L\U leaf (L has a unit diagonal); backward, the strict upper triangle with row i
+// multiplied by 1 / U_ii, and the row scales 1 / U_ii (the substitution then runs without a
+// division or a mask). Zero outside the triangle and past the leaf's rows and columns.
+template <class T>
+__global__ void __launch_bounds__(256) k_hs_prepare(const T* __restrict__ arena, const HsStep* __restrict__ steps,
+                                                   int nleaf, T* __restrict__ prep) {
+    const int s = blockIdx.x;
+    const HsStep st = steps[s];
+    const bool fwd = s < nleaf;
+    const int n = st.nrow;
+    const T* D = arena + st.diag;
+    T* P = prep + (int64_t)s * kHsPrepStride;
+    for (int q = threadIdx.x; q < kHsolveMaxRow * kHsolveMaxRow; q += blockDim.x) {
+        const int i = q % kHsolveMaxRow, c = q / kHsolveMaxRow;
+        T v = T(0);
+        if (i < n && c < n && (fwd ? c < i : c > i)) {
+            v = D[i + (int64_t)c * n];
+            if (!fwd) v = v * (T(1) / D[i + (int64_t)i * n]);
+        }
+        P[q] = v;
+    }
+    for (int i = threadIdx.x; i < kHsolveMaxRow; i += blockDim.x)
+        P[kHsolveMaxRow * kHsolveMaxRow + i] = (fwd || i >= n) ? T(1) : T(1) / D[i + (int64_t)i * n];
 }
 
 template <class T, int WC>
@@ -585,6 +599,15 @@ void launch_hsolve_one_wc(hipStream_t st, const Inst<T>& d, int nchunk, size_t l
 }
 
 }  // namespace
+
+template <class T>
+void launch_hs_prepare(hipStream_t st, const T* arena, const HsStep* steps, int nleaf, T* prep) {
+    if (nleaf <= 0) return;
+    hipLaunchKernelGGL((k_hs_prepare<T>), dim3(2 * nleaf), dim3(256), 0, st, arena, steps, nleaf, prep);
+    FDE_LAUNCH_CHECK();
+}
+template void launch_hs_prepare<float>(hipStream_t, const float*, const HsStep*, int, float*);
+template void launch_hs_prepare<double>(hipStream_t, const double*, const HsStep*, int, double*);
 
 template <class T>
 void launch_hsolve(hipStream_t st, int ninst, int nchunk, int wc, const Inst<T>* d_insts, int step, size_t lds) {
