@@ -120,11 +120,14 @@ __device__ inline T reduce8(const T (&v)[8], int lane) {
         const T send = b4 ? w[i] : w[i + 2], keep = b4 ? w[i + 2] : w[i];
         u[i] = keep + __shfl_xor(send, 16, 64);
     }
+    // within rows of 16 lanes through DPP: the mirror pairs lane i of a row with lane 15 - i (the
+    // other half of the row, same upper lane bits, as xor 8 would); the sums after it run over
+    // whole groups of 8 lanes, so any pairing inside a group does (half mirror, then quads)
     const T send = b3 ? u[0] : u[1], keep = b3 ? u[1] : u[0];
-    T s = keep + __shfl_xor(send, 8, 64);
-    s += __shfl_xor(s, 4, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 1, 64);
+    T s = keep + dpp_move<kDppRowMirror>(send);
+    s += dpp_move<kDppRowHalfMirror>(s);
+    s += dpp_move<kDppXor2>(s);
+    s += dpp_move<kDppXor1>(s);
     return s;
 }
 

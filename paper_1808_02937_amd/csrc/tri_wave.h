@@ -37,6 +37,8 @@ __device__ inline double lane_bcast(double x, int s) {
 // of the row).
 constexpr int kDppXor1 = 0xB1;   // quad_perm(1, 0, 3, 2)
 constexpr int kDppXor2 = 0x4E;   // quad_perm(2, 3, 0, 1)
+constexpr int kDppRowMirror = 0x140;       // lane i of each row reads lane 15 - i of the row
+constexpr int kDppRowHalfMirror = 0x141;   // lane i of each half row (8 lanes) reads lane 7 - i
 constexpr int dpp_row_ror(int n) { return 0x120 + n; }
 constexpr int dpp_row_newbcast(int n) { return 0x150 + n; }
 template <int CTRL>
