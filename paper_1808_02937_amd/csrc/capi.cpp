@@ -387,6 +387,13 @@ void build_op(Op* op, const double* nodes, int N, int P, double alpha, double th
     op->d_h.alloc(c, N);
     upload(c, op->d_x.p, op->x.data(), (N + 1) * sizeof(double));
     upload(c, op->d_h.p, op->h.data(), N * sizeof(double));
+    {
+        // the scale of the Toeplitz moments, K^{ef} = (h_e/2)^(2-alpha) (h_f/2) G_{e-f}: one pow per element
+        std::vector<double> hp(N);
+        for (int e = 0; e < N; ++e) hp[e] = std::pow(0.5 * op->h[e], 2.0 - alpha);
+        op->d_hpow.alloc(c, N);
+        upload(c, op->d_hpow.p, hp.data(), N * sizeof(double));
+    }
     std::vector<double> rules(2 * (P + 1) + 2 * P);
     gauss_jacobi(P + 1, 0.0, 2.0 - alpha, rules.data(), rules.data() + P + 1);
     gauss_jacobi(P, 0.0, 1.0 - alpha, rules.data() + 2 * (P + 1), rules.data() + 2 * (P + 1) + P);

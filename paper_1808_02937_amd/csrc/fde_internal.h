@@ -152,6 +152,7 @@ struct Op {
     int L = 0;           // FFT length (power of two >= 2N)
     // device data
     DevBuf<double> d_x, d_h;
+    DevBuf<double> d_hpow;       // (h_e / 2)^(2 - alpha) per element (the Toeplitz moments' scale)
     DevBuf<double> d_rules;      // GJ(0,2-alpha) n=P+1 then GJ(0,1-alpha) n=P: x then w
     DevBuf<double> d_lmass;      // (P+1)^2 local mass in [phi_L, phi_R, psi_1..]
     DevBuf<double> d_mom;        // dense: N(N+1)/2 pairs x P x P

@@ -15,6 +15,7 @@ struct FacSideDev {    // one factor (U or V) of a low-rank leaf
     int d0, rows;      // internal indices [d0, d0+rows)
     int sing, alt;     // sing: mult*coef_nu*r^nu*(sgn(x-c))^{1-alpha-nu}; else mult*((x-c)/r)^nu
     double c, r, sgn, mult;
+    int nq, pad;       // Gauss-Legendre nodes per element
 };
 
 struct SegDev {        // contiguous copy with conversion
@@ -26,7 +27,8 @@ struct LeafDev {       // leaf block for reconstruction
     int r0, c0, m, n, lowrank, slot;
 };
 
-void launch_hbuild_dense(Op* op, int nblk, const DenseBlkDev* d_blks, const int* d_h2p, double* arena);
+// blocks of at most max_elems entries
+void launch_hbuild_dense(Op* op, int nblk, int max_elems, const DenseBlkDev* d_blks, const int* d_h2p, double* arena);
 // sides: host copy of the table at d_sides (the launch splits every side into chunks of rows)
 void launch_hbuild_factors(Op* op, int R, const std::vector<FacSideDev>& sides, const FacSideDev* d_sides,
                            double* arena);

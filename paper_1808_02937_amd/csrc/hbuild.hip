@@ -15,10 +15,14 @@ namespace fde {
 
 namespace {
 
+// workgroup (x, y): entries [y kDenseChunk, (y + 1) kDenseChunk) of block x (a few entries per
+// thread: each entry is a chain of dependent loads, so many workgroups hide their latency)
+constexpr int kDenseChunk = 1024;
 __global__ void k_hbuild_dense(SemDev s, const DenseBlkDev* __restrict__ blks, const int* __restrict__ h2p,
                                double* __restrict__ arena) {
     const DenseBlkDev b = blks[blockIdx.x];
-    for (int q = threadIdx.x; q < b.m * b.n; q += blockDim.x) {
+    const int q1 = min(b.m * b.n, (int)(blockIdx.y + 1) * kDenseChunk);
+    for (int q = blockIdx.y * kDenseChunk + threadIdx.x; q < q1; q += blockDim.x) {
         const int i = q % b.m, j = q / b.m;
         arena[b.off + q] = sem_entry(s, h2p[b.r0 + i], h2p[b.c0 + j]);
     }
@@ -44,7 +48,7 @@ __global__ void __launch_bounds__(kRowsPerChunk) k_hbuild_factors(int P, int R, 
     __shared__ double s_x[kMaxGL], s_w[kMaxGL], s_leg[(kFacMaxP + 1) * kMaxGL];
     const int2 ch = chunks[blockIdx.x];
     const FacSideDev f = sides[ch.x];
-    const int nq = f.sing ? min(kMaxGL, P + 24) : min(kMaxGL, (R + P) / 2 + 2);
+    const int nq = min(kMaxGL, f.nq);   // chosen per side on the host
     const int off_n = nq * (nq - 1) / 2;
     const int wbase = kMaxGL * (kMaxGL + 1) / 2;
     for (int k = threadIdx.x; k < nq; k += blockDim.x) {
@@ -163,10 +167,12 @@ __global__ void k_to_dense(const T* __restrict__ arena, const int* __restrict__ 
 
 }  // namespace
 
-void launch_hbuild_dense(Op* op, int nblk, const DenseBlkDev* d_blks, const int* d_h2p, double* arena) {
-    if (nblk == 0) return;
-    hipLaunchKernelGGL(k_hbuild_dense, dim3(nblk), dim3(256), 0, op->ctx->stream, sem_dev(op), d_blks, d_h2p,
-                       arena);
+void launch_hbuild_dense(Op* op, int nblk, int max_elems, const DenseBlkDev* d_blks, const int* d_h2p,
+                         double* arena) {
+    if (nblk == 0 || max_elems <= 0) return;
+    const unsigned chunks = (unsigned)((max_elems + kDenseChunk - 1) / kDenseChunk);
+    hipLaunchKernelGGL(k_hbuild_dense, dim3(nblk, chunks), dim3(256), 0, op->ctx->stream, sem_dev(op), d_blks,
+                       d_h2p, arena);
     FDE_LAUNCH_CHECK();
 }
 

@@ -79,14 +79,37 @@ void build_hmat(fde_hmat* hm, Op* op, const fde_hparams* prm) {
     upload_vec(c, hm->d_h2p, t.h2p);
     // dense near blocks: exact entries of A
     std::vector<DenseBlkDev> dbl;
+    int max_elems = 0;
     for (int b : t.dense_blocks) {
         const Block& B = t.bl[b];
         dbl.push_back(DenseBlkDev{B.off, t.cl[B.tau].d0, t.cl[B.sigma].d0, t.cl[B.tau].size(), t.cl[B.sigma].size()});
+        max_elems = std::max(max_elems, dbl.back().m * dbl.back().n);
     }
     DevBuf<DenseBlkDev> d_dbl;
     upload_vec(c, d_dbl, dbl);
-    launch_hbuild_dense(op, (int)dbl.size(), d_dbl.p, hm->d_h2p.p, hm->d_arena.p);
+    launch_hbuild_dense(op, (int)dbl.size(), max_elems, d_dbl.p, hm->d_h2p.p, hm->d_arena.p);
     // low-rank factors from the Taylor expansion (Lemma; Section 3.2)
+    // Gauss-Legendre nodes per element for a singular side (cluster id, expansion centre c0): the
+    // integrand (x - c0)^(1-alpha-nu) L_m(x) is analytic inside the Bernstein ellipse of parameter
+    // rho = (2q+1) + sqrt((2q+1)^2 - 1), q = dist(c0, cluster) / (widest element there), so n nodes
+    // err like rho^-(2n - P); half of log rho is used (the negative powers grow towards the
+    // singularity) for 1e-20, within [P/2 + 4, P + 24]
+    const int P = op->P;
+    std::vector<double> hmax_cl(t.cl.size(), -1.0);
+    auto singular_nodes = [&](int id, double c0) {
+        const Cluster& X = t.cl[id];
+        if (hmax_cl[id] < 0.0) {
+            double hm = 0.0;
+            for (int e = std::max(X.e0 - 1, 0); e < std::min(X.e1 + 1, op->N); ++e) hm = std::max(hm, op->h[e]);
+            hmax_cl[id] = hm;
+        }
+        const int n_max = P + 24, n_min = P / 2 + 4;
+        const double delta = std::max({X.lo - c0, c0 - X.hi, 0.0});
+        if (!(delta > 0.0) || !(hmax_cl[id] > 0.0)) return n_max;
+        const double a = 2.0 * delta / hmax_cl[id] + 1.0, lr = std::log(a + std::sqrt(a * a - 1.0));
+        const int n = (int)std::ceil((P + 1 + 2.0 * 20.0 * std::log(10.0) / lr) / 2.0) + 2;
+        return std::min(n_max, std::max(n_min, n));
+    };
     std::vector<FacSideDev> sides;
     hm->init_rank.assign(t.lr_blocks.size(), R);
     for (size_t k = 0; k < t.lr_blocks.size(); ++k) {
@@ -104,6 +127,11 @@ void build_hmat(fde_hmat* hm, Op* op, const fde_hparams* prm) {
             ts = FacSideDev{0, Tc.d0, Tc.size(), 0, 0, t0, rT, 1.0, 1.0};
             ss = FacSideDev{0, Sc.d0, Sc.size(), 1, 1, t0, rT, -1.0, op->gamma0};
         }
+        // nodes per element: the regular side's integrand is a polynomial of degree R - 1 + P (exact);
+        // the singular side's is analytic on each element away from the expansion centre
+        const int t_id = B.lower ? B.tau : B.sigma, s_id = B.lower ? B.sigma : B.tau;
+        ts.nq = ts.sing ? singular_nodes(t_id, ts.c) : (R + P) / 2 + 2;
+        ss.nq = ss.sing ? singular_nodes(s_id, ss.c) : (R + P) / 2 + 2;
         FacSideDev u = B.lower ? ts : ss, v = B.lower ? ss : ts;
         const double w = B.lower ? op->theta : 1.0 - op->theta;
         u.mult *= w;

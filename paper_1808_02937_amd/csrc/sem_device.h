@@ -48,13 +48,14 @@ struct SemDev {
     const double* mom;    // dense: packed lower-triangular pairs
     const double* gen;    // Toeplitz generators
     const double* lmass;  // (P+1)^2 reference mass
+    const double* hpow;   // Toeplitz: (h_e / 2)^(2 - alpha) per element
 };
 
 // K^{ef}_{mn}, f <= e
 __device__ inline double moment(const SemDev& s, int e, int f, int m, int n) {
     const int P = s.P;
     if (!s.toep) return s.mom[(tri(e) + f) * P * P + m * P + n];
-    const double sc = pow(0.5 * s.h[e], 2.0 - s.alpha) * 0.5 * s.h[f];
+    const double sc = s.hpow[e] * 0.5 * s.h[f];
     return sc * s.gen[(int64_t)(e - f) * P * P + m * P + n];
 }
 
@@ -102,6 +103,7 @@ inline SemDev sem_dev(const Op* op) {
     s.mom = op->d_mom.p;
     s.gen = op->d_gen.p;
     s.lmass = op->d_lmass.p;
+    s.hpow = op->d_hpow.p;
     return s;
 }
 
