@@ -1,6 +1,8 @@
 // C entry points: context, operator, load vector, stiffness apply, utilities.
 // Every entry point catches the library's internal failures and returns a
 // status code; the message is kept per thread for fde_last_error().
+#include <mutex>
+#include <map>
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -409,11 +411,24 @@ void build_op(Op* op, const double* nodes, int N, int P, double alpha, double th
         if (L < 4) L = 4;
         op->L = L;
         const int M = L / 2;
-        std::vector<double2> tw(M + 1);
-        // exp(-2 pi i j / L): j / L is exact (L a power of two), cos and sin in FP64
-        for (int j = 0; j <= M; ++j) {
-            const double ang = -2.0 * 3.14159265358979323846 * ((double)j / L);
-            tw[j] = make_double2(std::cos(ang), std::sin(ang));
+        // exp(-2 pi i j / L): j / L is exact (L a power of two), cos and sin in FP64; the host table
+        // is kept per L for the process (operators of one size share it)
+        static std::mutex tw_mu;
+        static std::map<int, std::vector<double2>> tw_memo;
+        std::vector<double2> tw;
+        {
+            std::lock_guard<std::mutex> lk(tw_mu);
+            auto it = tw_memo.find(L);
+            if (it != tw_memo.end()) tw = it->second;
+        }
+        if (tw.empty()) {
+            tw.resize(M + 1);
+            for (int j = 0; j <= M; ++j) {
+                const double ang = -2.0 * 3.14159265358979323846 * ((double)j / L);
+                tw[j] = make_double2(std::cos(ang), std::sin(ang));
+            }
+            std::lock_guard<std::mutex> lk(tw_mu);
+            tw_memo.emplace(L, tw);
         }
         op->d_tw.alloc(c, M + 1);
         upload(c, op->d_tw.p, tw.data(), tw.size() * sizeof(double2));

@@ -10,6 +10,10 @@
 // by Sturm-sequence bisection and polished by Newton steps on the degree-n
 // orthonormal polynomial; the weights are the Christoffel numbers
 // w_i = 1 / sum_{k<n} p_k(x_i)^2 of the orthonormal polynomials.
+#include <algorithm>
+#include <tuple>
+#include <mutex>
+#include <map>
 #include <cmath>
 #include <vector>
 
@@ -85,9 +89,37 @@ void orthonormal(const Recurrence& r, int n, double x, double* pn, double* dpn, 
 
 }  // namespace
 
+namespace {
+void gauss_jacobi_compute(int n, double a, double b, double* x, double* w);
+}  // namespace
+
 void gauss_jacobi(int n, double a, double b, double* x, double* w) {
     if (n < 1 || !(a > -1.0) || !(b > -1.0))
         fail(FDE_EINVAL, "gauss_jacobi: need n >= 1, a > -1, b > -1 (n=%d a=%g b=%g)", n, a, b);
+    // rules are memoised per (n, a, b) for the process: every operator of a given P and alpha asks
+    // for the same few, and the bisection below costs tens of microseconds per rule
+    static std::mutex mu;
+    static std::map<std::tuple<int, double, double>, std::vector<double>> memo;
+    const auto key = std::make_tuple(n, a, b);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = memo.find(key);
+        if (it != memo.end()) {
+            std::copy(it->second.begin(), it->second.begin() + n, x);
+            std::copy(it->second.begin() + n, it->second.end(), w);
+            return;
+        }
+    }
+    gauss_jacobi_compute(n, a, b, x, w);
+    std::vector<double> v(x, x + n);
+    v.insert(v.end(), w, w + n);
+    std::lock_guard<std::mutex> lk(mu);
+    memo.emplace(key, std::move(v));
+}
+
+namespace {
+
+void gauss_jacobi_compute(int n, double a, double b, double* x, double* w) {
     Recurrence r = jacobi_recurrence(n, a, b);
     for (int i = 0; i < n; ++i) {
         // the i-th smallest eigenvalue lies in [lo, hi] with count(lo) <= i < count(hi)
@@ -114,6 +146,8 @@ void gauss_jacobi(int n, double a, double b, double* x, double* w) {
         w[i] = 1.0 / s;
     }
 }
+
+}  // namespace
 
 const double* gauss_legendre_table() {
     // built once per process (thread-safe static initialisation); the rules are
