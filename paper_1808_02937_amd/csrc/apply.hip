@@ -302,16 +302,18 @@ __global__ void __launch_bounds__(kThreads) k_rfft_inverse(int N, int P, int M, 
 
 // per frequency: uniform  Y[m] = sum_n S[m][n] X[n];
 //                geometric Yc[m] = sum_n K[m][n] Xc[n],  Yr[m] = sum_n conj(K[n][m]) Xr[n]
+// (one thread per right-hand side, output row m and frequency k)
 __global__ void k_symbol_apply(int P, int M, int parts, const double2* __restrict__ sym,
                                const double2* __restrict__ spec, int nrhs, double2* __restrict__ out) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int K1 = M + 1;
-    if (idx >= (int64_t)nrhs * K1) return;
-    const int r = (int)(idx / K1), k = (int)(idx % K1);
+    if (idx >= (int64_t)nrhs * P * K1) return;
+    const int r = (int)(idx / ((int64_t)P * K1)), rem = (int)(idx % ((int64_t)P * K1));
+    const int m = rem / K1, k = rem % K1;
     for (int part = 0; part < parts; ++part) {
         const double2* X = spec + ((int64_t)r * parts + part) * P * K1;
         double2* Y = out + ((int64_t)r * parts + part) * P * K1;
-        for (int m = 0; m < P; ++m) {
+        {
             double2 s = make_double2(0.0, 0.0);
             for (int n = 0; n < P; ++n) {
                 double2 a;
@@ -434,7 +436,7 @@ void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int 
         hipLaunchKernelGGL(k_rfft_forward, dim3(P, nrhs, parts), dim3(kThreads), sizeof(double2) * M, st,
                            N, P, M, logM, P, in, op->uniform ? 2 : 0, op->d_tw.p, specA);
         FDE_LAUNCH_CHECK();
-        const int64_t nk = (int64_t)nrhs * (M + 1);
+        const int64_t nk = (int64_t)nrhs * P * (M + 1);
         hipLaunchKernelGGL(k_symbol_apply, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, st, P, M,
                            parts, op->d_sym.p, specA, nrhs, specB);
         FDE_LAUNCH_CHECK();

@@ -1,4 +1,4 @@
-// Kernels of the batched FGMRES: one 256-thread workgroup per system (one
+// Kernels of the batched FGMRES: one 1024-thread workgroup per system (one
 // right-hand side of one operator) for every reduction, so each system's
 // arithmetic is independent of what else is in the batch (a result is the
 // same alone and in a mix).
@@ -14,7 +14,7 @@ namespace fde {
 
 namespace {
 
-constexpr int kT = 256;
+constexpr int kT = 1024;   // a system's vectors (Nd up to tens of thousands) over 16 wavefronts
 constexpr int kW = kT / 64;
 constexpr int kChunk = 16;
 
@@ -56,10 +56,11 @@ __device__ void block_dots(const double* base, int64_t stride, int nv, const dou
                 if (c < cn) part[c] += base[(int64_t)(c0 + c) * stride + i] * wi;
         }
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c) {
-            const double v = wave_sum(part[c]);
-            if (c < cn && lane == 0) r.w[wave][c] = v;
-        }
+        for (int c = 0; c < kChunk; ++c)
+            if (c < cn) {   // uniform: only the vectors of this chunk are reduced
+                const double v = wave_sum(part[c]);
+                if (lane == 0) r.w[wave][c] = v;
+            }
         __syncthreads();
         if (threadIdx.x < cn) {
             double s = 0.0;
