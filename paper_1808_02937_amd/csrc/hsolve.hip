@@ -343,7 +343,8 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
                 consume(vv);
                 p1_item(k, vv);
             }
-            for (int k = wave; k < np1; k += kHW) {
+            // (ranks reach past the first chunk only when the rank capacity does)
+            for (int k = wave; kmax > kHsChunk && k < np1; k += kHW) {
                 if (k < S0.nlate) continue;
                 const RecS r = rec_lane(R0, k);
                 const int rank = rk[r.slot];
@@ -477,7 +478,7 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
                     consume(vv);
                     p2_chunk(r, vv, 0, cols);
                 }
-                for (int e = hw; e < S0.nearly; e += nh) {
+                for (int e = hw; kmax > kHsChunk && e < S0.nearly; e += nh) {
                     const RecS r = rec_lane(R0, base + e);
                     const int cols = cols_of(r);
                     for (int cb = kHsChunk; cb < cols; cb += kHsChunk) {
