@@ -393,6 +393,22 @@ void factor_prepare(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
         segs.push_back(SegDev{S.uoff, D.uoff, (int64_t)P.t.cl[S.tau].size() * R});
         segs.push_back(SegDev{S.voff, D.voff, (int64_t)P.t.cl[S.sigma].size() * R});
     }
+    // runs contiguous on both sides are merged (with a rank capacity of R the whole arena is one
+    // run), then cut into pieces of at most 8192 entries, one workgroup each
+    {
+        std::vector<SegDev> runs;
+        for (const SegDev& g : segs) {
+            if (!runs.empty() && runs.back().src + runs.back().len == g.src && runs.back().dst + runs.back().len == g.dst)
+                runs.back().len += g.len;
+            else
+                runs.push_back(g);
+        }
+        constexpr int64_t kPiece = 8192;
+        segs.clear();
+        for (const SegDev& g : runs)
+            for (int64_t o = 0; o < g.len; o += kPiece)
+                segs.push_back(SegDev{g.src + o, g.dst + o, std::min(kPiece, g.len - o)});
+    }
     DevBuf<SegDev> d_segs;
     upload_vec(c, d_segs, segs);
     if (f->prec == FDE_FP64)
