@@ -9,8 +9,9 @@
 // Ops: GETRF (dense LU without pivoting, Section 4.1 takes L_H unit lower and
 // no pivoting; a pivot below the floor is a breakdown), TRSM, GEMM, ZERO, and
 // LRSUB -- C <- trunc(U_C V_C^T - X Y^T). Up to the variant's width KS the
-// recompression works on Gram matrices (pivoted Cholesky, a second pass in FP64,
-// the core R_u R_v^T decomposed by one-sided Jacobi in registers); wider sums
+// recompression works on Gram matrices (pivoted Cholesky in FP32; shifted
+// Cholesky QR3 in FP64, the core R_u R_v^T decomposed by one-sided Jacobi in
+// registers); wider sums (the general variant, which the host no longer selects)
 // take a thin QR of [U_C, -X] and [V_C, Y] by classical Gram-Schmidt with one
 // reorthogonalisation and a one-sided Jacobi SVD of the core in FP64. Either way
 // the singular values above tol * sigma_1 are kept, at most kmax of them (the
@@ -41,7 +42,7 @@ struct GemmLds {
 constexpr int kLU = 64;            // GETRF leaves factored in registers up to this size
 
 // small recompression (k' <= KS): staged rows, Gram matrices, Cholesky factors
-template <int KS>
+template <int KS, bool F64>
 struct LrsLds {
     static constexpr int K = KS;                     // widest k'
     static constexpr int CH = KS <= 16 ? 64 : 32;    // rows per staged chunk
@@ -49,9 +50,10 @@ struct LrsLds {
     double A[2][CH * LD];   // staged rows of both sides (row-major, stride LD); later C_u, C_v (ld K)
     double G[2][KS * KS];   // Gram matrices; then the core M and rotations Z; then C_u, C_v
     double R[2][KS * KS];   // Cholesky factors R[a][j] (row a, original column j)
+    double R2[F64 ? 2 : 1][F64 ? KS * KS : 1];   // FP64: the second pass's factor while the third runs
     double sig[KS];
     int perm[2][KS], perm2[2][KS];
-    int q[2], q2[2];
+    int q[2], q2[2], q3[2];
 };
 
 // LDS of one interpreter workgroup. KS: widest recompression of the small path; GENERAL: the
@@ -61,7 +63,7 @@ struct Shared {
     static constexpr int kSmall = KS;
     static constexpr bool kGeneral = GENERAL;
     union {
-        LrsLds<KS> ls;
+        LrsLds<KS, sizeof(T) == 8> ls;
         GemmLds<T> gm;
     };
     OpRec op;        // level kernel: this workgroup's op, rank-dependent sizes resolved
@@ -560,11 +562,15 @@ __device__ void jacobi_svd(double* M, double* W, int kp, SH& sh) {
 // With A_u = [U_C, -X] (m x k') and A_v = [V_C, Y] (n x k'), U_C V_C^T - X Y^T = A_u A_v^T.
 // The Gram matrices A^T A (FP64) are factorised by pivoted Cholesky, P^T G P = R^T R with R
 // upper trapezoidal (rank q: pivots below a relative floor are dropped), so that
-// A P = Q R with orthonormal Q = (A P)[:, :q] R11^{-1}. For FP64 factors a second Gram of Q
-// refines R (Cholesky QR2). Then A_u A_v^T = Q_u M Q_v^T with the small core
-// M = (R_u P_u^T)(R_v P_v^T)^T, whose SVD M = W S Z^T (one-sided Jacobi) is truncated to the
-// singular values above tol * s_1 (at most kmax): U_C <- A_u C_u, V_C <- A_v C_v with
+// A P = Q R with orthonormal Q = (A P)[:, :q] R11^{-1}. Then A_u A_v^T = Q_u M Q_v^T with the
+// small core M = (R_u P_u^T)(R_v P_v^T)^T, whose SVD M = W S Z^T (one-sided Jacobi) is truncated
+// to the singular values above tol * s_1 (at most kmax): U_C <- A_u C_u, V_C <- A_v C_v with
 // C_u = P_u R11_u^{-1} (W S)_r and C_v = P_v R11_v^{-1} Z_r.
+// FP64 factors need more than that single pass: the pivot floor loses directions below about
+// 1e-7 of a side's largest column and the solves with an ill-conditioned R11 amplify rounding,
+// which caps the agreement with a Householder QR + SVD near 1e-9. They take a shifted Cholesky
+// QR3 instead (A = Q R with R a general q x k' matrix) and the inverse-free coefficients
+// C_u = R_v^T Z_r, C_v = R_u^T W_r S_r^{-1}.
 
 // one side's column c at row i of [F, sgn * G] (F: current factor, ld rows; G: update view)
 template <class T>
@@ -957,6 +963,28 @@ __device__ __attribute__((noinline)) void solve_factors16(lds_ptr<LS> Sp, lds_pt
     __syncthreads();
 }
 
+// row <- y with y R[:, perm[:q]] = row[perm[:q]] (forward substitution over the pivot order; R row b
+// in original column j at R[b * kSK + j]); entries beyond q become zero. One thread per staged row.
+template <int kSK>
+__device__ inline void subst_row(double* row, const double* R, const int* perm, int q) {
+    double y[kSK];
+#pragma unroll
+    for (int b = 0; b < kSK; ++b) y[b] = 0.0;
+    for (int b = 0; b < q; ++b) {
+        const int pb = perm[b];
+        double v = row[pb];
+#pragma unroll
+        for (int c = 0; c < kSK; ++c)
+            if (c < b) v -= y[c] * R[c * kSK + pb];
+        v /= R[b * kSK + pb];
+#pragma unroll
+        for (int c = 0; c < kSK; ++c)
+            if (c == b) y[c] = v;
+    }
+#pragma unroll
+    for (int b = 0; b < kSK; ++b) row[b] = b < q ? y[b] : 0.0;
+}
+
 template <class T, class SH>
 __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const OpRec& o, SH& sh, const LRBlockDev& L, int kc, int kx) {
     auto& S = sh.ls;
@@ -999,70 +1027,85 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
     gram_tiles_store(S, gt);
     __syncthreads();
     phase(0);
-    const double floor_rel = f64 ? 1e-14 : 1e-12;
-    if (wave < 2)
-        wave_cholesky<kSK>(lmem<const double>(S.G[wave]), lmem(S.R[wave]), lmem(S.perm[wave]), lmem(&S.q[wave]), kp, true,
-                           floor_rel);
-    __syncthreads();
-    phase(1);
-    if (f64) {
-        // second pass: rows of Q1 = (A P)[:, :q] R11^{-1} (forward substitution per row), their
-        // Gram G2 = R2^T R2 and R <- R2 R
-        GramTiles<LS> g2;
-        gram_tiles_clear(g2);
-        load_rows<T, LS>(su, sv, 0, kp, rows);
-        for (int c0 = 0; c0 < rmax; c0 += kCH) {
-            store_rows<T, LS>(su, sv, c0, kp, rows, S);
-            __syncthreads();
-            if (c0 + kCH < rmax) load_rows<T, LS>(su, sv, c0 + kCH, kp, rows);
-            for (int idx = threadIdx.x; idx < 2 * kCH; idx += kT) {
-                const int s = idx / kCH, rr = idx % kCH, q = S.q[s];
-                double* row = &S.A[s][rr * kLD];
-                double y[kSK];
-#pragma unroll
-                for (int b = 0; b < kSK; ++b) y[b] = 0.0;
-                // y R11 = a P: y_b = (a_{perm b} - sum_{c<b} y_c R[c][perm b]) / R[b][perm b]
-                for (int b = 0; b < q; ++b) {
-                    const int pb = S.perm[s][b];
-                    double v = row[pb];
-#pragma unroll
-                    for (int c = 0; c < kSK; ++c)
-                        if (c < b) v -= y[c] * S.R[s][c * kSK + pb];
-                    v /= S.R[s][b * kSK + pb];
-#pragma unroll
-                    for (int c = 0; c < kSK; ++c)
-                        if (c == b) y[c] = v;
+    if constexpr (sizeof(T) == 4) {
+        // one pass: pivoted Cholesky of the Gram matrices, pivots below 1e-12 of the largest dropped
+        if (wave < 2)
+            wave_cholesky<kSK>(lmem<const double>(S.G[wave]), lmem(S.R[wave]), lmem(S.perm[wave]), lmem(&S.q[wave]), kp,
+                               true, 1e-12);
+        __syncthreads();
+        phase(1);
+    } else {
+        // Shifted Cholesky QR3, so that directions far below the largest column survive (exact up to
+        // rounding for any conditioning; tol = 0 gives the exact LU). Pass 1: G1 + s I = R1^T R1
+        // without pivoting, s = 11 (rows k' + k'(k'+1)) eps tr(G1): Q1 = A R1^{-1} has condition
+        // at most about 1/sqrt(s). Pass 2: pivoted Cholesky QR of Q1 (dependent columns dropped at
+        // 1e-15), Q1 P2 = Q2 R2. Pass 3: Cholesky QR of Q2, Q2 = Q3 R3. Then A = Q3 R with
+        // R = R3 (R2 P2^T) R1.
+        if (wave < 2) {
+            const int lane = threadIdx.x & 63;
+            const double dg = lane < kp ? S.G[wave][lane * kSK + lane] : 0.0;
+            const double tr = wave_sum(dg);
+            const double rows_s = wave == 0 ? (double)m : (double)n;
+            const double shift = 11.0 * (rows_s * kp + kp * (kp + 1.0)) * 2.220446049250313e-16 * tr;
+            if (lane < kp) S.G[wave][lane * kSK + lane] = dg + shift;
+        }
+        __syncthreads();
+        if (wave < 2)
+            wave_cholesky<kSK>(lmem<const double>(S.G[wave]), lmem(S.R[wave]), lmem(S.perm[wave]), lmem(&S.q[wave]), kp,
+                               false, 0.0);
+        __syncthreads();
+        phase(1);
+        for (int pass = 2; pass <= 3; ++pass) {
+            // rows of Q1 = A R1^{-1} (pass 2), of Q2 = (Q1 P2)[:, :q2] R2_11^{-1} (pass 3), and their Gram
+            GramTiles<LS> g2;
+            gram_tiles_clear(g2);
+            load_rows<T, LS>(su, sv, 0, kp, rows);
+            for (int c0 = 0; c0 < rmax; c0 += kCH) {
+                store_rows<T, LS>(su, sv, c0, kp, rows, S);
+                __syncthreads();
+                if (c0 + kCH < rmax) load_rows<T, LS>(su, sv, c0 + kCH, kp, rows);
+                for (int idx = threadIdx.x; idx < 2 * kCH; idx += kT) {
+                    const int sd = idx / kCH, rr = idx % kCH;
+                    double* row = &S.A[sd][rr * kLD];
+                    subst_row<kSK>(row, S.R[sd], S.perm[sd], S.q[sd]);
+                    if (pass == 3) subst_row<kSK>(row, S.R2[sd], S.perm2[sd], S.q2[sd]);
                 }
-#pragma unroll
-                for (int b = 0; b < kSK; ++b) row[b] = b < q ? y[b] : 0.0;
+                __syncthreads();
+                gram_tiles_accumulate(S, g2);
+                __syncthreads();
+            }
+            gram_tiles_store(S, g2);
+            __syncthreads();
+            if (wave < 2) {
+                if (pass == 2)
+                    wave_cholesky<kSK>(lmem<const double>(S.G[wave]), lmem(S.R2[wave]), lmem(S.perm2[wave]),
+                                       lmem(&S.q2[wave]), S.q[wave], true, 1e-15);
+                else   // R3 (row a, column b) into A[wave]: the staged rows are no longer needed
+                    wave_cholesky<kSK>(lmem<const double>(S.G[wave]), lmem(S.A[wave]), lmem(S.perm[wave] + 0),
+                                       lmem(&S.q3[wave]), S.q2[wave], false, 1e-30);
             }
             __syncthreads();
-            gram_tiles_accumulate(S, g2);
+            if (pass == 2) continue;
+            // R1's pivot order is the natural one (no pivoting), so perm may be overwritten above.
+            // T = (R2 P2^T) R1 (q2 x k') into G, then R = R3 T (q3 x k') into R
+            for (int idx = threadIdx.x; idx < 2 * kSK * kp; idx += kT) {
+                const int sd = idx / (kSK * kp), rem = idx % (kSK * kp), a = rem / kp, j = rem % kp;
+                double v = 0.0;
+                if (a < S.q2[sd])
+                    for (int b = 0; b < S.q[sd]; ++b) v += S.R2[sd][a * kSK + b] * S.R[sd][b * kSK + j];
+                S.G[sd][a * kSK + j] = v;
+            }
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < 2 * kSK * kp; idx += kT) {
+                const int sd = idx / (kSK * kp), rem = idx % (kSK * kp), a = rem / kp, j = rem % kp;
+                double v = 0.0;
+                if (a < S.q3[sd])
+                    for (int c = a; c < S.q2[sd]; ++c) v += S.A[sd][a * kSK + c] * S.G[sd][c * kSK + j];
+                S.R[sd][a * kSK + j] = v;
+            }
+            if (threadIdx.x < 2) S.q[threadIdx.x] = S.q3[threadIdx.x];
             __syncthreads();
         }
-        gram_tiles_store(S, g2);
-        __syncthreads();
-        if (wave < 2) {
-            // G2 (q x q) = L2 L2^T without pivoting, in A[wave] as scratch for R2 (row a, col b)
-            wave_cholesky<kSK>(lmem<const double>(S.G[wave]), lmem(S.A[wave]), lmem(S.perm2[wave]), lmem(&S.q2[wave]),
-                               S.q[wave], false, 1e-30);
-        }
-        __syncthreads();
-        // R <- R2 R (rows a < q2): R'[a][j] = sum_{b >= a} R2[a][b] R[b][j]; R2 row a in A[s][a*kSK + b]
-        for (int idx = threadIdx.x; idx < 2 * kSK * kp; idx += kT) {
-            const int s = idx / (kSK * kp), rem = idx % (kSK * kp), a = rem / kp, j = rem % kp;
-            double v = 0.0;
-            if (a < S.q2[s])
-                for (int b = a; b < S.q[s]; ++b) v += S.A[s][a * kSK + b] * S.R[s][b * kSK + j];
-            S.G[s][a * kSK + j] = v;   // G no longer needed: holds R' for the copy below
-        }
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < 2 * kSK * kp; idx += kT) {
-            const int s = idx / (kSK * kp), rem = idx % (kSK * kp), a = rem / kp, j = rem % kp;
-            S.R[s][a * kSK + j] = S.G[s][a * kSK + j];
-        }
-        if (threadIdx.x < 2) S.q[threadIdx.x] = S.q2[threadIdx.x];
-        __syncthreads();
     }
     phase(2);
     const int qu = S.q[0], qv = S.q[1];
@@ -1090,20 +1133,45 @@ __device__ __attribute__((noinline)) void op_lrsub_small(const Inst<T>& d, const
         int r = 0;
         if (qu > 0 && qv > 0) {
             const double smax = S.sig[sh.order[0]];
+            // singular values below 1e-30 sigma_1 are rounding noise and dropped even at tol = 0 (the
+            // FP64 factors divide by sigma_r^2)
             if (smax > 0.0)
-                while (r < qv && S.sig[sh.order[r]] > tol * smax) ++r;
+                while (r < qv && S.sig[sh.order[r]] > tol * smax && S.sig[sh.order[r]] > 1e-30 * smax) ++r;
         }
         if (r > kmax) r = kmax;
         sh.r = r;
         const double K = kp;
-        sh.lrsub_flops = (m + n) * K * (K + 1.0) * (f64 ? 3.0 : 1.0) + 2.0 * (m + n) * K * r + 2.0 * K * K * K / 3.0 +
-                         2.0 * K * K * K;
+        sh.lrsub_flops = (m + n) * K * (K + 1.0) * (f64 ? 5.0 : 1.0) + 2.0 * (m + n) * K * r +
+                         2.0 * K * K * K * (f64 ? 3.0 : 1.0) / 3.0 + 2.0 * K * K * K;
     }
     __syncthreads();
     const int r = sh.r;
-    // C_u (kp x r) = P_u R11_u^{-1} (M Z)_order and C_v = P_v R11_v^{-1} Z_order, by back
-    // substitution in the pivot order, into G[side] (row l, column c; M and Z are read first)
-    if constexpr (kSK == 16) {
+    if constexpr (sizeof(T) == 8) {
+        // C_u = R_v^T Z_r and C_v = R_u^T (M Z)_r S_r^{-2}: then A_u C_u = Q_u M Z_r = Q_u W_r S_r and
+        // A_v C_v = Q_v M^T W_r S_r^{-1} = Q_v Z_r, with no inverse of R (row l, column c; into A, then G)
+        for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) S.A[idx / (kSK * kSK)][idx % (kSK * kSK)] = 0.0;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 2 * kp * r; idx += kT) {
+            const int sd = idx / (kp * r), rem = idx % (kp * r), l = rem % kp, c = rem / kp, oc = sh.order[c];
+            double v = 0.0;
+            if (sd == 0) {
+                for (int b = 0; b < qv; ++b) v += S.R[1][b * kSK + l] * S.G[1][b + oc * kSK];
+            } else {
+                for (int a = 0; a < qu; ++a) v += S.R[0][a * kSK + l] * S.G[0][a + oc * kSK];
+                const double sg = S.sig[oc];
+                v /= sg * sg;
+            }
+            S.A[sd][l * kSK + c] = v;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 2 * kSK * kSK; idx += kT) {
+            const int sd = idx / (kSK * kSK), e = idx % (kSK * kSK);
+            S.G[sd][e] = S.A[sd][e];
+        }
+        __syncthreads();
+    } else if constexpr (kSK == 16) {
+        // C_u (kp x r) = P_u R11_u^{-1} (M Z)_order and C_v = P_v R11_v^{-1} Z_order, by back
+        // substitution in the pivot order, into G[side] (row l, column c; M and Z are read first)
         solve_factors16(lmem(&S), lmem<const int>(sh.order), r);
     } else {
         // one lane per (side, output column), into A[side], then moved to G

@@ -462,6 +462,10 @@ void make_plan_host(const HTree& hmt, int kmax, Plan& p, bool check) {
     for (const OpRec& o : p.lu.ops)
         if (o.code == OP_LRSUB) widest = std::max(widest, p.t.kmax + (o.dim[2] >= 0 ? o.dim[2] : p.t.kmax));
     p.lu_variant = widest <= 16 ? 16 : widest <= 32 ? 32 : 0;
+    // Recompressions wider than 32 would run the Gram-Schmidt / Jacobi path of the general kernel
+    // variant. That path once faulted the GPU in exact mode with no cause shown, so it is refused.
+    if (p.lu_variant == 0)
+        fail(FDE_EUNSUPPORTED, "H-LU needs recompression of width %d > 32 (rank capacity above 16)", widest);
     if (p.kpmax > kMaxKp) fail(FDE_EUNSUPPORTED, "H-LU needs recompression of width %d > %d", p.kpmax, kMaxKp);
     validate_program(p.t, p.lu, p.t.arena_elems, p.lu.work_elems, 1, false);
     validate_program(p.t, p.sv, p.t.arena_elems, p.sv.work_elems, 1, true);

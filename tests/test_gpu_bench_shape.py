@@ -1,0 +1,96 @@
+"""GPU parity at the benchmark's shapes: uniform mesh, N = 1024, P = 8 (Nd = 8191), R = 8, leaf 8,
+lambda = 1, tol 1e-3 -- the structure the bench factors (64-row leaves, recompressions of k' <= 16,
+solve-ready leaves and the one-right-hand-side leaf-step H-solve), in its launch configuration
+(one batched factorisation of two operators). Every output is compared element by element with the
+FP64 oracle's H-matrix and H-LU of the same operator."""
+import numpy as np
+import pytest
+import torch
+
+import fde_inputs as fi
+from oracle import toeplitz
+from oracle.hmatrix import HLU as OHLU
+from oracle.hmatrix import HMatrix as OHMatrix
+from oracle.hmatrix import to_dense
+from oracle.sem import SEM
+from tests.gpu_common import EPS32, EPS64, kappa1, lu_residual, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+# Bounds. Device and oracle truncate the same exact sums at the same ranks, so their factors
+# differ by the rounding of the factor precision (eps = 2^-24 in FP32, 2^-53 in FP64):
+# - the factors: ||L U - A~|| <= 2 ||L_o U_o - A~|| + 20 eps ||A~|| (the oracle's truncation error
+#   plus rounding; a wrong update in any block moves it by that block's size);
+# - the H-solve: the rounding perturbs L U by O(eps) relative, which moves the solution by at most
+#   kappa_1(A~) times that: ||x - x_o|| <= 10 kappa_1(A~) eps ||x_o||. With kappa_1(A~) = 1.1e5
+#   here, the H-solve bound is also capped at about ten times the errors measured on the MI355X
+#   (FP32 5.6e-4, FP64 1.75e-12), frozen below.
+FP32_CAP = 5e-3
+FP64_CAP = 2e-11
+
+
+@pytest.fixture(scope="module")
+def bench_case():
+    fde = need_gpu()
+    say("bench shape: oracle H-matrix and H-LU (N=1024, P=8)")
+    inst = fi.config_uniform_grid(1.5, 0.5)
+    other = fi.config_uniform_grid(1.8, 0.3)
+    sem = SEM(inst.nodes, inst.P, inst.alpha, inst.theta, inst.rho)
+    A = toeplitz.dense_matrix(sem, toeplitz.generators(sem, 1.0))
+    oh = OHMatrix(sem, inst.R, 1.0, inst.leaf, A=A)
+    del A
+    ofac = OHLU(oh, tol=1e-3)
+    say("bench shape: device operators")
+    ctx = fde.Context(0)
+    ops = [fde.Operator(ctx, i.nodes, i.P, i.alpha, i.theta, i.rho) for i in (inst, other)]
+    hms = [fde.HMatrix(o, R=i.R, lam=1.0, leaf_elems=i.leaf) for o, i in zip(ops, (inst, other))]
+    g = np.random.default_rng(21).standard_normal((2, sem.Nd))
+    xo = ofac.solve(g.T).T
+    Ah = to_dense(oh.root)
+    kap = kappa1(Ah)
+    Lo, Uo = ofac.dense_factors()
+    res_o = lu_residual(torch.tensor(np.tril(Lo, -1) + Uo, device="cuda"), Ah)
+    del Lo, Uo
+    say(f"  kappa_1(A~) = {kap:.3e}, oracle |L U - A~|/|A~| = {res_o:.2e}")
+    yield dict(fde=fde, ctx=ctx, sem=sem, oh=oh, ofac=ofac, hms=hms, g=g, xo=xo, Ah=Ah, kappa=kap, res_o=res_o)
+    for o in ops:
+        o.close()
+    ctx.close()
+
+
+def test_bench_hmatrix_matches_oracle(bench_case):
+    c = bench_case
+    say("bench shape: H-matrix vs oracle")
+    hm = c["hms"][0]
+    assert hm.counts() == c["oh"].counts()
+    At = hm.dense().cpu().numpy()
+    ref = np.empty_like(At)
+    h2p = c["oh"].h2p
+    ref[np.ix_(h2p, h2p)] = to_dense(c["oh"].root)
+    rel = np.abs(At - ref).max() / np.abs(ref).max()
+    say(f"  max |A~_gpu - A~| / max |A~| = {rel:.2e}")
+    assert rel <= 1e-13, rel
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_bench_hlu_and_hsolve_match_oracle(bench_case, precision):
+    c = bench_case
+    fde = c["fde"]
+    say(f"bench shape: batched {precision} H-LU and H-solve vs oracle")
+    lus = fde.factor_batched(c["hms"], tol=1e-3, precision=precision)
+    lu = lus[0]
+    assert lu.max_rank() <= 8
+    x = lu.solve(torch.tensor(c["g"], device="cuda")).cpu().numpy()
+    x1 = torch.stack([lu.solve(torch.tensor(c["g"][j], device="cuda")) for j in range(2)]).cpu().numpy()
+    err = np.linalg.norm(x - c["xo"]) / np.linalg.norm(c["xo"])
+    err1 = np.linalg.norm(x1 - c["xo"]) / np.linalg.norm(c["xo"])
+    F, _ = lu.dense()
+    rel = lu_residual(F, c["Ah"])
+    eps = EPS32 if precision == "fp32" else EPS64
+    bound = min(10 * c["kappa"] * eps, FP32_CAP if precision == "fp32" else FP64_CAP)
+    say(f"  {precision} H-solve vs oracle: 2 rhs {err:.2e}, 1 rhs {err1:.2e} (bound {bound:.2e}); "
+        f"|LU - A~|/|A~| {rel:.2e} (bound {2 * c['res_o'] + 20 * eps:.2e})")
+    assert err <= bound and err1 <= bound, (err, err1, bound)
+    assert rel <= 2 * c["res_o"] + 20 * eps, rel
+    for l in lus:
+        l.close()
