@@ -4,6 +4,7 @@ from __future__ import annotations
 import atexit
 import ctypes as C
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfde.so")
@@ -107,16 +108,29 @@ SIGNATURES = {
 
 _lib = None
 _shutting_down = False
+# root handles (contexts) still open; closing one closes every handle made from it
+_roots = weakref.WeakSet()
 
 
-def _mark_shutdown():
+def register_root(obj):
+    _roots.add(obj)
+
+
+def _shutdown():
+    """At interpreter exit, while the HIP runtime is still whole: close every open context (its
+    streams, events, pinned staging ring and cached device blocks go back to the runtime), then
+    stop finalisers from calling into the library. Nothing of the library is left for the
+    runtime's own teardown."""
     global _shutting_down
+    for r in list(_roots):
+        try:
+            r.close()
+        except Exception:
+            pass
     _shutting_down = True
 
 
-# Finalisers that run while the interpreter exits must not call into the HIP
-# runtime (it may already be tearing down); the process releases those handles.
-atexit.register(_mark_shutdown)
+atexit.register(_shutdown)
 
 
 def shutting_down() -> bool:

@@ -93,6 +93,7 @@ class Context(_Handle):
         h = C.c_void_p()
         check(lib.fde_ctx_create(device, C.c_void_p(s.cuda_stream), budget_bytes, C.byref(h)))
         self._init_handle(h)
+        A.register_root(self)
 
     def set_stream(self, stream: torch.cuda.Stream):
         self._stream = stream
