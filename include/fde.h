@@ -165,6 +165,19 @@ int  fde_load_vector_powers(fde_op* op, int nterms, const double* coef_host, con
 int  fde_stiffness_apply(fde_op* op, int nrhs, const double* X_dev, int ldx,
                          double* Y_dev, int ldy);
 
+/* Same result as fde_stiffness_apply, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops): the workspace
+ * (gathered coefficients, tile partials or FFT spectra) is a fixed 8 MiB device
+ * array per GPU, set up by fde_ctx_create and held until the process ends; no
+ * hipMalloc, hipFree or allocating library call is made. Every call on one GPU
+ * shares that array, so calls that overlap on one GPU (other streams, other
+ * threads, other contexts) race. Returns FDE_EINVAL when nrhs columns of this
+ * operator need more workspace than the array holds (Toeplitz apply:
+ * 2 nrhs N P + 4 nrhs parts P (L/2 + 1) doubles; dense apply:
+ * 2 nrhs N P + nrhs T(T+1) TE P doubles, TE = max(1, 64 / P), T = ceil(N / TE)). */
+int  fde_stiffness_apply_noalloc(fde_op* op, int nrhs, const double* X_dev, int ldx,
+                                 double* Y_dev, int ldy);
+
 /* ---- H-matrix (Section 3) --------------------------------------------- */
 
 int  fde_build_hmatrix(fde_op* op, const fde_hparams* prm, fde_hmat** out);

@@ -21,10 +21,42 @@
 // symbol, on a geometric mesh the two parts carry different diagonal scalings
 // and are transformed separately.
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "fde_internal.h"
 
 namespace fde {
+
+// Workspace of the allocation-free apply (fde_stiffness_apply_noalloc): one array on every GPU the
+// library runs on, held until the process ends. Host code never uses this name as an address; it
+// uses the per-device address that init_apply_scratch takes from the runtime.
+static __device__ __align__(256) double scratch[kApplyScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;   // per device ordinal
+}  // namespace
+
+void init_apply_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+    if (g_scratch_ptr[device]) return;
+    int cur = -1;
+    FDE_HIP(hipGetDevice(&cur));
+    if (cur != device) fail(FDE_EDEVICE, "apply scratch: device %d is not current (%d is)", device, cur);
+    void* p = nullptr;
+    FDE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(FDE_EDEVICE, "apply scratch: no device address on device %d", device);
+    g_scratch_ptr[device] = static_cast<double*>(p);
+}
+
+double* apply_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= (int)g_scratch_ptr.size() || !g_scratch_ptr[device])
+        fail(FDE_EDEVICE, "apply scratch of device %d was not set up (fde_ctx_create does that)", device);
+    return g_scratch_ptr[device];
+}
 
 namespace {
 
@@ -392,16 +424,19 @@ void build_symbol(Op* op) {
 }
 
 void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int ldy, double bc0,
-                     double bcN, bool zero_x, hipStream_t on) {
+                     double bcN, bool zero_x, hipStream_t on, double* ws) {
     const int N = op->N, P = op->P, Nd = op->Nd;
     hipStream_t st = on ? on : op->ctx->stream;
-    const size_t need = op->apply_ws_doubles(nrhs);
-    if (op->ws.n < need) {
-        // blocks come from the context's cache, ordered on its stream: another stream must not get one
-        if (on && on != op->ctx->stream) fail(FDE_EDEVICE, "apply workspace not reserved before a side-stream apply");
-        op->ws.alloc(op->ctx, need);
+    if (!ws) {
+        const size_t need = op->apply_ws_doubles(nrhs);
+        if (op->ws.n < need) {
+            // blocks come from the context's cache, ordered on its stream: another stream must not get one
+            if (on && on != op->ctx->stream) fail(FDE_EDEVICE, "apply workspace not reserved before a side-stream apply");
+            op->ws.alloc(op->ctx, need);
+        }
+        ws = op->ws.p;
     }
-    double* c = op->ws.p;
+    double* c = ws;
     double* z = c + (size_t)nrhs * N * P;
     double* rest = z + (size_t)nrhs * N * P;
     const double* Xin = zero_x ? nullptr : X;

@@ -498,6 +498,7 @@ int fde_ctx_create(int device, void* hip_stream, size_t budget, fde_ctx** out) {
     c->budget = budget;
     try {
         init_ctx_tables(c);
+        init_apply_scratch(device);
     } catch (...) {
         delete c;
         throw;
@@ -670,6 +671,20 @@ int fde_stiffness_apply(fde_op* op, int nrhs, const double* X, int ldx, double* 
         fail(FDE_EINVAL, "bad arguments");
     if (nrhs == 0) return FDE_OK;
     stiffness_apply(op, nrhs, X, ldx, Y, ldy, 0.0, 0.0, false);
+    FDE_API_END
+}
+
+int fde_stiffness_apply_noalloc(fde_op* op, int nrhs, const double* X, int ldx, double* Y, int ldy) {
+    FDE_API_BEGIN
+    if (!op || nrhs < 0 || (nrhs && (!X || !Y)) || ldx < op->Nd || ldy < op->Nd)
+        fail(FDE_EINVAL, "bad arguments");
+    if (nrhs == 0) return FDE_OK;
+    const size_t need = op->apply_ws_doubles(nrhs);
+    if (need > kApplyScratchDoubles)
+        fail(FDE_EINVAL, "fde_stiffness_apply_noalloc: %d columns of this operator need %zu doubles of workspace, "
+             "the fixed scratch holds %zu (use fde_stiffness_apply, or fewer columns per call)", nrhs, need,
+             kApplyScratchDoubles);
+    stiffness_apply(op, nrhs, X, ldx, Y, ldy, 0.0, 0.0, false, nullptr, apply_scratch(op->ctx->device));
     FDE_API_END
 }
 

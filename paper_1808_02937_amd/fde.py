@@ -185,6 +185,14 @@ class Operator(_Handle):
         check(load().fde_stiffness_apply(self.h, X2.shape[0], _dptr(X2), X2.stride(0), _dptr(Y), Y.stride(0)))
         return Y.view_as(X) if out is None else out
 
+    def apply_noalloc(self, X: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """Y = A X into `out` with the library's fixed per-GPU workspace (no device allocation)."""
+        X2 = _as_block(X, self.Nd, self.ctx.device)
+        Y = _as_block(out, self.Nd, self.ctx.device)
+        check(load().fde_stiffness_apply_noalloc(self.h, X2.shape[0], _dptr(X2), X2.stride(0), _dptr(Y),
+                                                 Y.stride(0)))
+        return out
+
 
 class HMatrix(_Handle):
     """A~ = rho M + H (Section 3)."""
