@@ -242,6 +242,9 @@ class HArith:
         self.tol = tol
         self.kmax = kmax
         self.pivot_floor = pivot_floor
+        # floating-point operations of the factorisation, counted per primitive at its actual
+        # dimensions and ranks (the algorithmic work of the H-LU, not a model of it)
+        self.flops = 0.0
 
     # -- truncation (reading of the "prescribed tolerance" of Section 4.1) --
     def truncate(self, U: np.ndarray, V: np.ndarray):
@@ -255,13 +258,20 @@ class HArith:
         else:
             k = int(np.count_nonzero(s > self.tol * s[0]))
         k = min(k, self.kmax)
+        m, n, kk = U.shape[0], V.shape[0], U.shape[1]
+        # Householder QR with the thin Q formed (2 x (2 m k^2 - 2 k^3 / 3)), the core product,
+        # an SVD with both factors (22 k^3), the truncated products
+        self.flops += 4.0 * (m + n) * kk * kk - 8.0 * kk ** 3 / 3.0 + 2.0 * kk ** 3 + 22.0 * kk ** 3 + \
+            2.0 * (m + n) * kk * k
         return Qu @ (a[:, :k] * s[:k]), Qv @ bt[:k].T
 
     # -- products of a block with a dense slab --
     def matmul(self, A: Block, X: np.ndarray) -> np.ndarray:
         if A.kind == "D":
+            self.flops += 2.0 * A.D.shape[0] * A.D.shape[1] * X.shape[1]
             return A.D @ X
         if A.kind == "R":
+            self.flops += 2.0 * (A.U.shape[0] + A.V.shape[0]) * A.U.shape[1] * X.shape[1]
             return A.U @ (A.V.T @ X)
         n0 = A.ch[0][0].shape[1]
         X0, X1 = X[:n0], X[n0:]
@@ -270,8 +280,10 @@ class HArith:
 
     def matmul_T(self, A: Block, X: np.ndarray) -> np.ndarray:
         if A.kind == "D":
+            self.flops += 2.0 * A.D.shape[0] * A.D.shape[1] * X.shape[1]
             return A.D.T @ X
         if A.kind == "R":
+            self.flops += 2.0 * (A.U.shape[0] + A.V.shape[0]) * A.U.shape[1] * X.shape[1]
             return A.V @ (A.U.T @ X)
         m0 = A.ch[0][0].shape[0]
         X0, X1 = X[:m0], X[m0:]
@@ -281,6 +293,7 @@ class HArith:
     # -- C <- C - X Y^T --
     def lr_sub(self, C: Block, X: np.ndarray, Y: np.ndarray):
         if C.kind == "D":
+            self.flops += 2.0 * X.shape[0] * Y.shape[0] * X.shape[1]
             C.D -= X @ Y.T
         elif C.kind == "R":
             C.U, C.V = self.truncate(np.hstack([C.U, -X]), np.hstack([C.V, Y]))
@@ -301,6 +314,7 @@ class HArith:
                 self.lr_sub(C, self.matmul(A, B.U), B.V)
         elif A.kind == "D" and B.kind == "D":
             if C.kind == "D":
+                self.flops += 2.0 * A.D.shape[0] * B.D.shape[1] * A.D.shape[1]
                 C.D -= A.D @ B.D
             elif C.kind == "R":
                 self.lr_sub(C, A.D, B.D.T)
@@ -318,6 +332,7 @@ class HArith:
     def solve_L(self, L: Block, X: np.ndarray):
         """X <- L^{-1} X (unit lower), in place."""
         if L.kind == "D":
+            self.flops += float(L.D.shape[0]) ** 2 * X.shape[1]
             X[:] = sla.solve_triangular(L.D, X, lower=True, unit_diagonal=True)
             return
         n0 = L.ch[0][0].shape[0]
@@ -328,6 +343,7 @@ class HArith:
     def solve_U(self, U: Block, X: np.ndarray):
         """X <- U^{-1} X (upper), in place."""
         if U.kind == "D":
+            self.flops += float(U.D.shape[0]) ** 2 * X.shape[1]
             X[:] = sla.solve_triangular(U.D, X, lower=False)
             return
         n0 = U.ch[0][0].shape[0]
@@ -338,6 +354,7 @@ class HArith:
     def solve_UT(self, U: Block, X: np.ndarray):
         """X <- U^{-T} X, in place."""
         if U.kind == "D":
+            self.flops += float(U.D.shape[0]) ** 2 * X.shape[1]
             X[:] = sla.solve_triangular(U.D, X, lower=False, trans="T")
             return
         n0 = U.ch[0][0].shape[0]
@@ -380,6 +397,7 @@ class HArith:
     def getrf(self, A: np.ndarray):
         """Dense LU without pivoting, in place (unit L below, U on and above the diagonal)."""
         n = A.shape[0]
+        self.flops += 2.0 * n ** 3 / 3.0
         scale = np.max(np.abs(A)) if A.size else 0.0
         for k in range(n):
             if abs(A[k, k]) <= self.pivot_floor * scale or A[k, k] == 0.0:
@@ -408,6 +426,7 @@ class HLU:
         self.ar = HArith(tol, H.R if kmax is None else kmax, pivot_floor)
         self.root = copy_block(H.root)
         self.ar.hlu(self.root)
+        self.flops = self.ar.flops   # floating-point operations of the factorisation
 
     def solve(self, G: np.ndarray) -> np.ndarray:
         """X ~= A~^{-1} G, G and X in paper order (1-D or Nd x k)."""

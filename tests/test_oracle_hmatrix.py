@@ -125,6 +125,29 @@ def test_hlu_accuracy_follows_tolerance(tol):
     assert rel < 1e4 * tol
 
 
+@pytest.mark.parametrize("N,leaf", [(4, 8), (4, 2)])
+def test_hlu_flop_count_of_all_dense_structures_is_the_dense_lu_count(N, leaf):
+    """With no admissible block (one leaf, or two adjacent leaves) the H-LU is the dense LU without
+    pivoting: LU(A00), two triangular solves, one Schur update, LU(A11); its counted work adds up to
+    2 Nd^3 / 3 for any split (2 n0^3/3 + n0^2 n1 + n0^2 n1 + 2 n1^2 n0 + 2 n1^3/3 = 2 (n0+n1)^3/3)."""
+    sem = SEM(fi.uniform_mesh(N), 3, 1.5, 0.5, 0.0)
+    H = HMatrix(sem, 4, 1.0, leaf)
+    assert all(b.kind == "D" for b in leaves(H.root))
+    F = HLU(H, tol=1e-3)
+    assert F.flops == pytest.approx(2.0 * sem.Nd ** 3 / 3.0, rel=1e-12)
+
+
+def test_hlu_flop_count_grows_like_the_stated_complexity():
+    """Section 4.1: the H-LU costs O(R^2 Nd log^2 N) + O(R^3 Nd log N), far below the dense 2 Nd^3 / 3;
+    doubling N at fixed R and leaf size roughly doubles it (times a log factor)."""
+    fl = []
+    for N in (64, 128):
+        sem = SEM(fi.uniform_mesh(N), 4, 1.5, 0.5, 0.0)
+        fl.append(HLU(HMatrix(sem, 4, 1.0, 4), tol=1e-3).flops)
+        assert fl[-1] < 0.5 * 2.0 * sem.Nd ** 3 / 3.0
+    assert 1.8 < fl[1] / fl[0] < 3.5, fl
+
+
 def test_hsolve_is_forward_then_backward_substitution():
     sem = sem_small(theta=0.5, rho=0.0)
     H = HMatrix(sem, 4, 1.0, 2)
