@@ -54,6 +54,11 @@ extern "C" {
 
 /* Krylov method */
 #define FDE_FGMRES        0   /* right-preconditioned flexible GMRES(restart) */
+#define FDE_BICGSTAB      1   /* left-preconditioned BiCGSTAB on A~^{-1} A X = A~^{-1} G (Section 4.2,
+                                 eq. (precondsys)): stops when the preconditioned residual
+                                 |A~^{-1}(G - A X)| <= rtol |A~^{-1} G|, as the paper does; info.relres
+                                 is the true |G - A X| / |G| at exit, info.iters counts full steps
+                                 (two preconditioned products each); restart is ignored */
 
 /* stiffness-apply strategy */
 #define FDE_APPLY_AUTO     0  /* FFT block-Toeplitz on uniform / constant-ratio meshes, dense otherwise */

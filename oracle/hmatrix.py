@@ -253,7 +253,7 @@ class HArith:
         Qu, Ru = np.linalg.qr(U)
         Qv, Rv = np.linalg.qr(V)
         a, s, bt = np.linalg.svd(Ru @ Rv.T)
-        if s[0] == 0.0:
+        if s.size == 0 or s[0] == 0.0:   # an empty block (no rows or no columns) or a zero sum
             k = 0
         else:
             k = int(np.count_nonzero(s > self.tol * s[0]))

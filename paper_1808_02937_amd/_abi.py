@@ -19,6 +19,7 @@ FDE_EUNSUPPORTED = -6
 FDE_FP64 = 0
 FDE_FP32 = 1
 FDE_FGMRES = 0
+FDE_BICGSTAB = 1
 FDE_APPLY_AUTO = 0
 FDE_APPLY_DENSE = 1
 FDE_APPLY_TOEPLITZ = 2

@@ -1,4 +1,5 @@
-// Host driver of the batched, right-preconditioned FGMRES(m) (Section 4.2).
+// Host driver of the batched Krylov solvers (Section 4.2): right-preconditioned FGMRES(m), and the
+// paper's left-preconditioned BiCGSTAB.
 //
 // The paper preconditions A X = G with the H-LU of A~ and iterates with
 // BiCGSTAB (eq. (precondsys)); here the preconditioner is applied on the right
@@ -14,6 +15,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "bicgstab.h"
 #include "hlu.h"
 #include "krylov.h"
 
@@ -93,6 +95,108 @@ Inst<T> group_inst(Group& g, int m) {
     return d;
 }
 
+// Left-preconditioned BiCGSTAB of every system in lock step: per step two applies of A per
+// operator (on the side streams), two H-solves per group and two fused update kernels; the host
+// reads back the number of systems still iterating once per step.
+void run_bicgstab(Ctx* c, std::vector<Group>& groups, int ns, int maxit, double rtol, fde_solve_info* info,
+                  int* rc_out) {
+    hipStream_t st = c->stream;
+    struct BGroup {
+        DevBuf<double> r, rh, p, s, v, t, W;
+    };
+    std::vector<BGroup> bg(groups.size());
+    std::vector<BicgDev> sys;
+    std::vector<int> mask;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        Group& g = groups[gi];
+        if (!g.nr) continue;
+        BGroup& b = bg[gi];
+        const size_t bs = (size_t)g.op->Nd * g.nr;
+        for (DevBuf<double>* d : {&b.r, &b.rh, &b.p, &b.s, &b.v, &b.t, &b.W}) d->alloc(c, bs);
+        for (int k = 0; k < g.nr; ++k) {
+            BicgDev d{};
+            d.G = g.G + (int64_t)k * g.ldg;
+            d.X = g.X + (int64_t)k * g.ldx;
+            d.r = b.r.p;
+            d.rh = b.rh.p;
+            d.p = b.p.p;
+            d.s = b.s.p;
+            d.v = b.v.p;
+            d.t = b.t.p;
+            d.W = b.W.p;
+            d.Nd = g.op->Nd;
+            d.c = k;
+            sys.push_back(d);
+            mask.push_back(g.prec ? 0 : 1);
+        }
+        const size_t need = g.op->apply_ws_doubles(g.nr);
+        if (g.op->ws.n < need) g.op->ws.alloc(c, need);
+    }
+    DevBuf<BicgDev> d_sys;
+    DevBuf<BicgState> d_ss;
+    DevBuf<int> d_mask, d_count;
+    d_sys.alloc(c, sys.size());
+    d_ss.alloc(c, ns);
+    d_mask.alloc(c, ns);
+    d_count.alloc(c, 1);
+    upload(c, d_sys.p, sys.data(), sys.size() * sizeof(BicgDev));
+    upload(c, d_mask.p, mask.data(), ns * sizeof(int));
+    const bool any_copy = std::any_of(mask.begin(), mask.end(), [](int v) { return v != 0; });
+    // M applied to the blocks of every group with a preconditioner: dst <- A~^{-1} src
+    auto precond = [&](int which) {
+        if (any_copy) bc_copy(st, ns, d_sys.p, d_mask.p, which);
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            Group& g = groups[gi];
+            if (!g.nr || !g.prec) continue;
+            BGroup& b = bg[gi];
+            const int Nd = g.op->Nd;
+            if (which == 0)
+                hlu_solve(g.prec, g.nr, g.G, g.ldg, b.r.p, Nd);
+            else
+                hlu_solve(g.prec, g.nr, b.W.p, Nd, which == 1 ? b.v.p : b.t.p, Nd);
+        }
+    };
+    auto apply_into_W = [&](int which) {   // W <- A p (0), A s (1), A x (2)
+        apply_groups(c, groups, [&](Group& g, hipStream_t s) {
+            BGroup& b = bg[&g - groups.data()];
+            const double* src = which == 0 ? b.p.p : (which == 1 ? b.s.p : nullptr);
+            if (which == 2)
+                stiffness_apply(g.op, g.nr, g.X, g.ldx, b.W.p, g.op->Nd, 0.0, 0.0, false, s);
+            else
+                stiffness_apply(g.op, g.nr, src, g.op->Nd, b.W.p, g.op->Nd, 0.0, 0.0, false, s);
+        });
+    };
+    precond(0);
+    bc_init(st, ns, d_sys.p, d_ss.p, maxit);
+    for (int it = 0; it < maxit; ++it) {
+        apply_into_W(0);
+        precond(1);
+        bc_half1(st, ns, d_sys.p, d_ss.p, rtol);
+        apply_into_W(1);
+        precond(2);
+        bc_half2(st, ns, d_sys.p, d_ss.p, rtol, maxit);
+        int active = 0;
+        bc_count_active(st, ns, d_ss.p, d_count.p);
+        FDE_HIP(hipMemcpyAsync(&active, d_count.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        FDE_HIP(hipStreamSynchronize(st));
+        if (active == 0) break;
+    }
+    apply_into_W(2);
+    bc_true_residual(st, ns, d_sys.p, d_ss.p);
+    std::vector<BicgState> hs(ns);
+    FDE_HIP(hipMemcpyAsync(hs.data(), d_ss.p, ns * sizeof(BicgState), hipMemcpyDeviceToHost, st));
+    FDE_HIP(hipStreamSynchronize(st));
+    int rc = FDE_OK;
+    for (int k = 0; k < ns; ++k) {
+        info[k].iters = hs[k].iters;
+        info[k].relres = hs[k].truerel;
+        info[k].status = hs[k].conv ? FDE_OK
+                                    : (hs[k].status == -3 ? FDE_EBREAKDOWN : (hs[k].status ? FDE_EDEVICE : FDE_ENOCONV));
+        if (!hs[k].conv) rc = hs[k].status == -3 ? FDE_EBREAKDOWN : FDE_ENOCONV;
+    }
+    *rc_out = rc;
+}
+
 void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nrhs, const double* const* G,
          const int* ldg, double* const* X, const int* ldx, const fde_solve_params* prm, fde_solve_info* info,
          int* rc_out) {
@@ -100,8 +204,9 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
     const int maxit = prm ? prm->maxit : 500;
     const double rtol = prm ? prm->rtol : 1e-10;
     const int method = prm ? prm->method : FDE_FGMRES;
-    if (method != FDE_FGMRES) fail(FDE_EINVAL, "unknown Krylov method %d", method);
-    if (m < 1 || m > kMaxRestart) fail(FDE_EINVAL, "restart must be in [1, %d] (got %d)", kMaxRestart, m);
+    if (method != FDE_FGMRES && method != FDE_BICGSTAB) fail(FDE_EINVAL, "unknown Krylov method %d", method);
+    if (method == FDE_FGMRES && (m < 1 || m > kMaxRestart))
+        fail(FDE_EINVAL, "restart must be in [1, %d] (got %d)", kMaxRestart, m);
     if (maxit < 1) fail(FDE_EINVAL, "maxit must be >= 1");
     if (!(rtol > 0.0)) fail(FDE_EINVAL, "rtol must be > 0");
     hipStream_t st = c->stream;
@@ -127,6 +232,10 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
     }
     if (ns == 0) {
         *rc_out = FDE_OK;
+        return;
+    }
+    if (method == FDE_BICGSTAB) {
+        run_bicgstab(c, groups, ns, maxit, rtol, info, rc_out);
         return;
     }
     std::vector<SysDev> sys;
@@ -292,7 +401,8 @@ int fde_solve(fde_op* op, fde_hlu* prec, int nrhs, const double* G, int ldg, dou
         set_error("unexpected internal error");
         return FDE_EDEVICE;
     }
-    if (rc == FDE_ENOCONV) set_error("FGMRES did not reach rtol within maxit for at least one right-hand side");
+    if (rc == FDE_ENOCONV) set_error("the Krylov solver did not reach rtol within maxit for at least one right-hand side");
+    if (rc == FDE_EBREAKDOWN) set_error("BiCGSTAB broke down (a vanishing inner product) for at least one right-hand side");
     return rc;
 }
 
@@ -314,7 +424,8 @@ int fde_solve_batched(fde_ctx* ctx, int n, fde_op* const* ops, fde_hlu* const* p
         set_error("unexpected internal error");
         return FDE_EDEVICE;
     }
-    if (rc == FDE_ENOCONV) set_error("FGMRES did not reach rtol within maxit for at least one right-hand side");
+    if (rc == FDE_ENOCONV) set_error("the Krylov solver did not reach rtol within maxit for at least one right-hand side");
+    if (rc == FDE_EBREAKDOWN) set_error("BiCGSTAB broke down (a vanishing inner product) for at least one right-hand side");
     return rc;
 }
 

@@ -280,18 +280,23 @@ def factor_batched(hms: Sequence[HMatrix], tol: float = 1e-3, rank_cap: int = 0,
     return res
 
 
-def _solve_params(rtol, restart, maxit):
-    return A.SolveParams(A.FDE_FGMRES, int(restart), int(maxit), float(rtol))
+_METHODS = {"fgmres": A.FDE_FGMRES, "bicgstab": A.FDE_BICGSTAB}
+
+
+def _solve_params(rtol, restart, maxit, method="fgmres"):
+    return A.SolveParams(_METHODS[method], int(restart), int(maxit), float(rtol))
 
 
 def solve(op: Operator, G: torch.Tensor, prec: Optional[HLU] = None, rtol: float = 1e-10,
-          restart: int = 30, maxit: int = 500, raise_on_noconv: bool = True):
-    """X with ||G - A X|| <= rtol ||G|| per column (right-preconditioned FGMRES). Returns (X, infos)."""
+          restart: int = 30, maxit: int = 500, raise_on_noconv: bool = True, method: str = "fgmres"):
+    """X with ||G - A X|| <= rtol ||G|| per column (right-preconditioned FGMRES), or the paper's
+    left-preconditioned BiCGSTAB (method="bicgstab": preconditioned residual <= rtol). Returns
+    (X, infos)."""
     G2 = _as_block(G, op.Nd, op.ctx.device)
     X = torch.empty_like(G2)
     nrhs = G2.shape[0]
     info = (A.SolveInfo * nrhs)()
-    p = _solve_params(rtol, restart, maxit)
+    p = _solve_params(rtol, restart, maxit, method)
     rc = load().fde_solve(op.h, prec.h if prec is not None else None, nrhs, _dptr(G2), G2.stride(0),
                           _dptr(X), X.stride(0), C.byref(p), info)
     if rc != A.FDE_ENOCONV or raise_on_noconv:
@@ -303,7 +308,7 @@ def solve(op: Operator, G: torch.Tensor, prec: Optional[HLU] = None, rtol: float
 def solve_batched(ctx: Context, ops: Sequence[Operator], Gs: Sequence[torch.Tensor],
                   precs: Optional[Sequence[Optional[HLU]]] = None, rtol: float = 1e-10,
                   restart: int = 30, maxit: int = 500, raise_on_noconv: bool = True,
-                  outs: Optional[Sequence[torch.Tensor]] = None):
+                  outs: Optional[Sequence[torch.Tensor]] = None, method: str = "fgmres"):
     """Solve several independent systems in lock-step launches. Returns (Xs, infos per system)."""
     n = len(ops)
     precs = precs if precs is not None else [None] * n
@@ -319,7 +324,7 @@ def solve_batched(ctx: Context, ops: Sequence[Operator], Gs: Sequence[torch.Tens
     x_p = (C.c_void_p * n)(*[x.data_ptr() for x in Xs])
     tot = sum(g.shape[0] for g in G2)
     info = (A.SolveInfo * tot)()
-    p = _solve_params(rtol, restart, maxit)
+    p = _solve_params(rtol, restart, maxit, method)
     rc = load().fde_solve_batched(ctx.h, n, op_h, pr_h, nr, g_p, ldg, x_p, ldx, C.byref(p), info)
     if rc != A.FDE_ENOCONV or raise_on_noconv:
         check(rc)
