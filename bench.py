@@ -58,6 +58,65 @@ def level_traffic_bytes():
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
+# HBM traffic of the moment-streaming kernel of the dense apply (two-sided graded N=4096, P=8, one
+# right-hand side), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by the
+# same counters on a plain device copy; valid for the apply sources whose digest is recorded.
+MATVEC_TRAFFIC = {"fetch_kib": 2099298.4, "write_kib": 131328.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                  "sources_sha256": "d8d1c55be4f78c5d402fa473bb9a8f170d7b8c9b6efd9ee6a667a8105f49b910"}
+MATVEC_SOURCES = ("paper_1808_02937_amd/csrc/apply.hip", "paper_1808_02937_amd/csrc/fde_internal.h",
+                  "paper_1808_02937_amd/build.py")
+FP64_PEAK_TFLOPS = 78.6
+
+
+def sources_sha256(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def matvec_roofline(fde, torch, ctx, N=4096, P=8, reps=10):
+    """The dense stiffness apply on a two-sided graded mesh (not Toeplitz): its moment stream reads
+    8 P^2 N(N+1)/2 bytes once per apply (4.3 GB here, far above the 256 MB MALL)."""
+    nodes = fi.two_sided_graded_mesh(N, 20, 0.5)
+    op = fde.Operator(ctx, nodes, P, 1.7, 0.4, 0.0)
+    g = torch.Generator(device="cuda").manual_seed(1808029373)
+    X = torch.randn(1, op.Nd, dtype=torch.float64, device="cuda", generator=g)
+    Y = torch.empty_like(X)
+    op.apply(X, out=Y)
+    core = [op.apply_timed(X, Y) for _ in range(reps)]
+    t_all = kernel_time_ms(torch, lambda: op.apply(X, out=Y), reps)
+    op.close()
+    core_ms = float(np.mean(core))
+    moment_bytes = 8.0 * P * P * N * (N + 1) / 2
+    achieved = moment_bytes / (core_ms * 1e-3) / 1e9
+    traffic = None
+    t = MATVEC_TRAFFIC
+    if t is not None and t["sources_sha256"] == sources_sha256(MATVEC_SOURCES):
+        traffic = 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+    return {"kernel": f"k_dense_stream<{P}> (dense apply: moment stream, one read per apply)", "bound": "hbm",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic, "algorithmic_bytes": moment_bytes, "kernel_ms": core_ms,
+            "apply_ms": t_all, "apply_GBps": (moment_bytes + 16.0 * op.Nd) / (t_all * 1e-3) / 1e9,
+            "workload": f"two-sided graded mesh N={N}, P={P} (Nd={N * P - 1}), alpha=1.7, theta=0.4, 1 RHS"}
+
+
+def multi_rhs_apply(fde, torch, ctx, N=256, P=16, nrhs=64, reps=10):
+    """The graded multi-right-hand-side workload: a 4095 x 4095 x 64 FP64 dense apply."""
+    nodes = fi.two_sided_graded_mesh(N, 20, 0.5)
+    op = fde.Operator(ctx, nodes, P, 1.7, 0.4, 0.0)
+    g = torch.Generator(device="cuda").manual_seed(1808029372)
+    X = torch.randn(nrhs, op.Nd, dtype=torch.float64, device="cuda", generator=g)
+    Y = torch.empty_like(X)
+    ms = kernel_time_ms(torch, lambda: op.apply(X, out=Y), reps)
+    op.close()
+    flops = 4.0 * P * P * N * (N + 1) / 2 * nrhs
+    return {"workload": f"two-sided graded N={N}, P={P} (Nd={N * P - 1}), {nrhs} RHS", "apply_ms": ms,
+            "TFLOPs": flops / (ms * 1e-3) / 1e12, "fp64_peak_TFLOPs": FP64_PEAK_TFLOPS}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -263,6 +322,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the extra measurements")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="only the dense-apply roofline (for profiling its kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the solver has no multi-GPU path",
@@ -272,6 +333,9 @@ def main():
     import paper_1808_02937_amd as fde
     torch.cuda.init()
     ctx = fde.Context(0)
+    if args.matvec_only:
+        print(json.dumps({"roofline_matvec": matvec_roofline(fde, torch, ctx)}))
+        return
     insts = make_instances()
     nsys = len(insts)
     mixed = Pipeline(fde, ctx, insts, "fp32")
@@ -338,6 +402,8 @@ def main():
     for o in kept_ops:
         o.close()
     mixed.kept = None
+    log("dense apply roofline")
+    out["roofline_matvec"] = matvec_roofline(fde, torch, ctx)
     if not args.quick:
         # plain FP64 path, same algorithm
         log("fp64 path")
@@ -372,6 +438,7 @@ def main():
         t_hs = kernel_time_ms(torch, lambda: lus[0].solve(v), 20)
         t_ap = kernel_time_ms(torch, lambda: ops[0].apply(v), 50)
         out["kernels_ms"] = {"hsolve_fp32": t_hs, "apply_toeplitz": t_ap}
+        out["multi_rhs_apply"] = multi_rhs_apply(fde, torch, ctx)
         log("serving stream")
         out["serving"] = serving_stream(fde, torch, ctx)
         out["latency_ms"] = {"p50": out["serving"]["p50_ms"], "p99": out["serving"]["p99_ms"],

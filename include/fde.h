@@ -170,6 +170,13 @@ int  fde_load_vector_powers(fde_op* op, int nterms, const double* coef_host, con
 int  fde_stiffness_apply(fde_op* op, int nrhs, const double* X_dev, int ldx,
                          double* Y_dev, int ldy);
 
+/* fde_stiffness_apply, then wait for it; *core_ms_host is the HIP-event time on
+ * the context's stream of the kernels that read the operator (the moment stream
+ * of the dense apply, the per-frequency symbol product of the Toeplitz apply).
+ * For measurement; nrhs >= 1. */
+int  fde_stiffness_apply_timed(fde_op* op, int nrhs, const double* X_dev, int ldx,
+                               double* Y_dev, int ldy, double* core_ms_host);
+
 /* Same result as fde_stiffness_apply, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops): the workspace
  * (gathered coefficients, tile partials or FFT spectra) is a fixed 8 MiB device

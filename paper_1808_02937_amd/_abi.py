@@ -81,6 +81,7 @@ SIGNATURES = {
     "fde_load_vector_powers": (i32, [vp, i32, dp, dp, ip, f64, f64, vp]),
     "fde_stiffness_apply": (i32, [vp, i32, vp, i32, vp, i32]),
     "fde_stiffness_apply_noalloc": (i32, [vp, i32, vp, i32, vp, i32]),
+    "fde_stiffness_apply_timed": (i32, [vp, i32, vp, i32, vp, i32, dp]),
     "fde_build_hmatrix": (i32, [vp, C.POINTER(HParams), C.POINTER(vp)]),
     "fde_hmat_destroy": (None, [vp]),
     "fde_hmat_counts": (i32, [vp, ip, ip]),

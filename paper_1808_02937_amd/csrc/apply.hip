@@ -5,10 +5,11 @@
 // block-lower element operator of the moments K^{ef}.
 //
 // Dense apply (any mesh; the O(Nd^2) product of Section 4.2): the packed lower
-// triangle of K is streamed once in tiles of TE x TE element pairs through LDS;
-// each tile yields a row partial (K c) and a column partial (K^T c), so every
-// moment byte is read from HBM once and used for both S_l and S_l^T (Section 4.3
-// forms S_l^T X "in a similar way"). Partials are reduced in a fixed order
+// triangle of K is streamed once in tiles of T x T element pairs (T = 64 / P)
+// through LDS, with wide non-temporal loads and the next tile in flight; each
+// tile yields a row partial (K c) and a column partial (K^T c), so every moment
+// byte is read from HBM once and used for both S_l and S_l^T (Section 4.3 forms
+// S_l^T X the same way from S_l). Partials are reduced in a fixed order
 // (deterministic, no atomics).
 //
 // Block-Toeplitz apply (uniform or constant-ratio meshes, Section 4.3 and
@@ -20,6 +21,7 @@
 // symbol is applied; on a uniform mesh theta Khat + (1-theta) Khat^H is one
 // symbol, on a geometric mesh the two parts carry different diagonal scalings
 // and are transformed separately.
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -141,72 +143,159 @@ __device__ inline void tile_ij(int64_t t, int* I, int* J) {
     *J = (int)(t - tri(i));
 }
 
-__global__ void __launch_bounds__(kThreads) k_dense_tiles(int N, int P, int TE, const double* __restrict__ mom,
-                                                        const double* __restrict__ c, int nrhs,
-                                                        double* __restrict__ part, int64_t ntiles) {
-    extern __shared__ double Kt[];   // TE x TE x P x P
-    const int64_t t = blockIdx.x;
+// Streaming dense apply for up to kStreamRhs right-hand sides. The packed lower triangle of the
+// moments is cut into tiles of T x T element pairs (T P <= 64, about 32 KB of moments per tile);
+// workgroups loop over the tiles. A tile's rows are contiguous runs of T P^2 doubles in HBM; each
+// thread fetches its share with 16-byte loads (8-byte loads for odd P, whose pair blocks start at
+// odd offsets), all issued at once, and the next tile's loads are in flight while the current tile
+// is used from LDS. In LDS a pair block's rows have stride P + 1, so the row-partial threads
+// (consecutive m) read distinct banks. Row partials (K c)_e and column partials (K^T c)_f of the
+// tile go to `part` in the layout k_dense_reduce sums (fixed order: deterministic).
+constexpr int kStreamRhs = 4;
+constexpr int kStreamThreads = 256;
+
+template <int P>
+struct StreamTile {
+    static constexpr int T = P >= 64 ? 1 : 64 / P;   // elements per tile side
+    static constexpr int PP = P * P;
+    static constexpr int LDP = P + 1;                // padded row of a pair block in LDS
+    static constexpr int BLK = P * LDP;              // padded pair block
+    static constexpr bool W16 = (P % 2) == 0;        // pair blocks start at even offsets
+    static constexpr int GW = W16 ? 2 : 1;           // doubles per granule
+    static constexpr int GR = T * PP / GW;           // granules per tile row
+    static constexpr int KL = (T * GR + kStreamThreads - 1) / kStreamThreads;   // granules per thread
+    static constexpr int TP = T * P;
+};
+
+template <int P>
+__device__ __attribute__((always_inline)) inline void stream_load(const double* __restrict__ mom, int N, int64_t t,
+                                                                  double (&v)[StreamTile<P>::KL][2]) {
+    using S = StreamTile<P>;
     int I, J;
     tile_ij(t, &I, &J);
-    const int e0 = I * TE, f0 = J * TE;
-    const int ne = min(TE, N - e0), nf = min(TE, N - f0);
-    const int PP = P * P;
-    const int TEP = TE * P;
-    // stage the moments: row el holds pairs (e0+el, f0..f0+nf-1), zero where f > e
-    for (int el = 0; el < ne; ++el) {
+    const int e0 = I * S::T, f0 = J * S::T;
+    const int ne = min(S::T, N - e0), nf = min(S::T, N - f0);
+#pragma unroll
+    for (int j = 0; j < S::KL; ++j) {
+        const int g = j * kStreamThreads + threadIdx.x;
+        const int el = g / S::GR, off = (g % S::GR) * S::GW;
         const int e = e0 + el;
-        const int nvalid = min(nf, e - f0 + 1);   // f <= e
-        const double* src = mom + (tri(e) + f0) * PP;
-        double* dst = Kt + (int64_t)el * TE * PP;
-        for (int q = threadIdx.x; q < TE * PP; q += kThreads) dst[q] = (q < nvalid * PP) ? src[q] : 0.0;
-    }
-    for (int q = threadIdx.x + ne * TE * PP; q < TE * TE * PP; q += kThreads) Kt[q] = 0.0;
-    __syncthreads();
-    // outputs: for each rhs, TEP row partials then TEP column partials
-    const int nout = 2 * TEP;
-    for (int q = threadIdx.x; q < nrhs * nout; q += kThreads) {
-        const int r = q / nout;
-        const int o = q % nout;
-        const double* cr = c + (int64_t)r * N * P;
-        double s = 0.0;
-        if (o < TEP) {
-            const int el = o / P, m = o % P;
-            if (el < ne) {
-                const double* krow = Kt + (int64_t)el * TE * PP + m * P;
-                for (int fl = 0; fl < nf; ++fl) {
-                    const double* cf = cr + (f0 + fl) * P;
-                    const double* kb = krow + fl * PP;
-                    for (int n = 0; n < P; ++n) s += kb[n] * cf[n];
-                }
-            }
+        const int nvalid = el < ne ? min(nf, e - f0 + 1) : 0;   // pairs (e, f) with f <= e
+        const bool ok = g < S::T * S::GR && off < nvalid * S::PP;
+        const double* src = ok ? mom + (tri(e) + f0) * S::PP + off : mom;
+        // read once: non-temporal loads keep the stream out of the caches
+        if constexpr (S::W16) {
+            typedef double d2v __attribute__((ext_vector_type(2)));
+            const d2v w = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(src));
+            v[j][0] = ok ? w[0] : 0.0;
+            v[j][1] = ok ? w[1] : 0.0;
         } else {
-            const int fl = (o - TEP) / P, n = (o - TEP) % P;
-            if (fl < nf) {
-                for (int el = 0; el < ne; ++el) {
-                    const double* ce = cr + (e0 + el) * P;
-                    const double* kb = Kt + ((int64_t)el * TE + fl) * PP + n;
-                    for (int m = 0; m < P; ++m) s += kb[m * P] * ce[m];
-                }
-            }
+            const double w = __builtin_nontemporal_load(src);
+            v[j][0] = ok ? w : 0.0;
         }
-        part[((int64_t)r * ntiles + t) * nout + o] = s;
     }
 }
 
-__global__ void k_dense_reduce(int N, int P, int TE, int nT, double theta, const double* __restrict__ part,
-                               int nrhs, int64_t ntiles, double* __restrict__ z) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)nrhs * N * P) return;
-    const int r = (int)(idx / ((int64_t)N * P));
-    const int rem = (int)(idx % ((int64_t)N * P));
-    const int e = rem / P, m = rem % P;
-    const int T = e / TE, el = e % TE;
-    const int TEP = TE * P, nout = 2 * TEP;
+template <int P>
+__global__ void __launch_bounds__(kStreamThreads) k_dense_stream(int N, const double* __restrict__ mom,
+                                                                 const double* __restrict__ c, int nrhs,
+                                                                 double* __restrict__ part, int64_t ntiles) {
+    using S = StreamTile<P>;
+    __shared__ double Kt[S::T * S::T * S::BLK];
+    __shared__ double ce[kStreamRhs][S::TP], cf[kStreamRhs][S::TP];
+    const int tid = threadIdx.x;
+    const int nout = 2 * S::TP;
+    double v[S::KL][2];
+    int64_t t = blockIdx.x;
+    if (t < ntiles) stream_load<P>(mom, N, t, v);
+    for (; t < ntiles; t += gridDim.x) {
+        int I, J;
+        tile_ij(t, &I, &J);
+        const int e0 = I * S::T, f0 = J * S::T;
+        // this tile's moments into LDS (padded pair rows), its coefficient vectors beside them
+#pragma unroll
+        for (int j = 0; j < S::KL; ++j) {
+            const int g = j * kStreamThreads + tid;
+            if (g < S::T * S::GR) {
+                const int el = g / S::GR, k = (g % S::GR) * S::GW;
+                const int fl = k / S::PP, w = k % S::PP, m = w / P, n = w % P;
+                double* dst = Kt + (el * S::T + fl) * S::BLK + m * S::LDP + n;
+                dst[0] = v[j][0];
+                if constexpr (S::W16) dst[1] = v[j][1];
+            }
+        }
+        for (int q = tid; q < nrhs * S::TP; q += kStreamThreads) {
+            const int r = q / S::TP, i = q % S::TP;
+            const int ei = e0 * P + i, fi = f0 * P + i;
+            ce[r][i] = ei < N * P ? c[(int64_t)r * N * P + ei] : 0.0;
+            cf[r][i] = fi < N * P ? c[(int64_t)r * N * P + fi] : 0.0;
+        }
+        __syncthreads();
+        // the next tile's loads fly while this one is used
+        if (t + gridDim.x < ntiles) stream_load<P>(mom, N, t + gridDim.x, v);
+        // threads [0, 2 TP): row partials, two half sums over fl per output; [128, 128 + 2 TP):
+        // column partials, two half sums over el
+        const bool row = tid < 128;
+        const int u = row ? tid : tid - 128;
+        const int o = u >> 1, h = u & 1;
+        if (o < S::TP) {
+            double acc[kStreamRhs];
+#pragma unroll
+            for (int r = 0; r < kStreamRhs; ++r) acc[r] = 0.0;
+            const int a = o / P, b = o % P;   // row: (el, m); column: (fl, n)
+            const int lo = h ? S::T / 2 : 0, hi = h ? S::T : S::T / 2;
+            for (int x = lo; x < hi; ++x) {
+#pragma unroll
+                for (int y = 0; y < P; ++y) {
+                    // row: K[el=a][fl=x][m=b][n=y] c_f[x][y]; column: K[el=x][fl=a][m=y][n=b] c_e[x][y]
+                    const double kv = row ? Kt[(a * S::T + x) * S::BLK + b * S::LDP + y]
+                                          : Kt[(x * S::T + a) * S::BLK + y * S::LDP + b];
+#pragma unroll
+                    for (int r = 0; r < kStreamRhs; ++r)
+                        if (r < nrhs) acc[r] += kv * (row ? cf[r][x * P + y] : ce[r][x * P + y]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kStreamRhs; ++r) {
+                const double tot = acc[r] + __shfl_xor(acc[r], 1, 64);
+                if (r < nrhs && h == 0) part[((int64_t)r * ntiles + t) * nout + (row ? 0 : S::TP) + o] = tot;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// z = theta (K c) + (1 - theta) (K^T c) from the tile partials: workgroup (I, r) sums, for the TE
+// elements of tile row I, the row partials of tiles (I, J <= I) and the column partials of tiles
+// (I' >= I, I); 16 groups of 64 threads take every 16th tile, then the groups are added in order
+// (deterministic).
+constexpr int kReduceThreads = 1024;
+__global__ void __launch_bounds__(kReduceThreads) k_dense_reduce(int N, int P, int TE, int nT, double theta,
+                                                               const double* __restrict__ part, int64_t ntiles,
+                                                               double* __restrict__ z) {
+    constexpr int kG = kReduceThreads / 64;
+    __shared__ double sr[kG][64], sc[kG][64];
+    const int I = blockIdx.x, r = blockIdx.y;
+    const int TP = TE * P, nout = 2 * TP;
+    const int o = threadIdx.x & 63, k = threadIdx.x >> 6;
     const double* pr = part + (int64_t)r * ntiles * nout;
-    double sr = 0.0, sc = 0.0;
-    for (int J = 0; J <= T; ++J) sr += pr[(tri(T) + J) * nout + el * P + m];
-    for (int I = T; I < nT; ++I) sc += pr[(tri(I) + T) * nout + TEP + el * P + m];
-    z[idx] = theta * sr + (1.0 - theta) * sc;
+    double a = 0.0, b = 0.0;
+    if (o < TP) {
+        for (int J = k; J <= I; J += kG) a += pr[(tri(I) + J) * nout + o];
+        for (int Ip = I + k; Ip < nT; Ip += kG) b += pr[(tri(Ip) + I) * nout + TP + o];
+    }
+    sr[k][o] = a;
+    sc[k][o] = b;
+    __syncthreads();
+    if (threadIdx.x < TP) {
+        double ra = 0.0, cb = 0.0;
+        for (int q = 0; q < kG; ++q) {
+            ra += sr[q][threadIdx.x];
+            cb += sc[q][threadIdx.x];
+        }
+        const int e = I * TE + threadIdx.x / P;
+        if (e < N) z[((int64_t)r * N + e) * P + threadIdx.x % P] = theta * ra + (1.0 - theta) * cb;
+    }
 }
 
 // ----------------------------------------------------------------- FFT
@@ -384,6 +473,35 @@ int dense_tile_elems(int P) {
     return te;
 }
 
+// launch the streaming dense apply for degree P (tile side 64 / P: the same tiles as
+// dense_tile_elems for every P in [2, 32])
+template <int P>
+void launch_stream_p(hipStream_t st, int N, const double* mom, const double* c, int nrhs, double* part,
+                     int64_t ntiles) {
+    static_assert(StreamTile<P>::T * P <= 64, "row partial threads");
+    // a few workgroups per CU loop over the tiles (grids of 2048 to 8192 measured the same)
+    const int64_t grid = std::min<int64_t>(ntiles, 2048);
+    hipLaunchKernelGGL(k_dense_stream<P>, dim3((unsigned)grid), dim3(kStreamThreads), 0, st, N, mom, c, nrhs, part,
+                       ntiles);
+    FDE_LAUNCH_CHECK();
+}
+
+bool launch_stream(hipStream_t st, int N, int P, const double* mom, const double* c, int nrhs, double* part,
+                   int64_t ntiles) {
+    switch (P) {
+#define FDE_STREAM_P(p) \
+    case p: launch_stream_p<p>(st, N, mom, c, nrhs, part, ntiles); return true;
+        FDE_STREAM_P(2) FDE_STREAM_P(3) FDE_STREAM_P(4) FDE_STREAM_P(5) FDE_STREAM_P(6) FDE_STREAM_P(7)
+        FDE_STREAM_P(8) FDE_STREAM_P(9) FDE_STREAM_P(10) FDE_STREAM_P(11) FDE_STREAM_P(12) FDE_STREAM_P(13)
+        FDE_STREAM_P(14) FDE_STREAM_P(15) FDE_STREAM_P(16) FDE_STREAM_P(17) FDE_STREAM_P(18) FDE_STREAM_P(19)
+        FDE_STREAM_P(20) FDE_STREAM_P(21) FDE_STREAM_P(22) FDE_STREAM_P(23) FDE_STREAM_P(24) FDE_STREAM_P(25)
+        FDE_STREAM_P(26) FDE_STREAM_P(27) FDE_STREAM_P(28) FDE_STREAM_P(29) FDE_STREAM_P(30) FDE_STREAM_P(31)
+        FDE_STREAM_P(32)
+#undef FDE_STREAM_P
+        default: return false;
+    }
+}
+
 int ilog2(int v) {
     int l = 0;
     while ((1 << l) < v) ++l;
@@ -424,7 +542,7 @@ void build_symbol(Op* op) {
 }
 
 void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int ldy, double bc0,
-                     double bcN, bool zero_x, hipStream_t on, double* ws) {
+                     double bcN, bool zero_x, hipStream_t on, double* ws, hipEvent_t* core_events) {
     const int N = op->N, P = op->P, Nd = op->Nd;
     hipStream_t st = on ? on : op->ctx->stream;
     if (!ws) {
@@ -448,12 +566,17 @@ void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int 
         hipLaunchKernelGGL(k_gather, dim3((unsigned)((nzp + 255) / 256)), dim3(256), 0, st, N, P,
                            op->d_h.p, Xin, ldx, nrhs, bc0, bcN, c);
         FDE_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_dense_tiles, dim3((unsigned)ntiles), dim3(kThreads),
-                           sizeof(double) * TE * TE * P * P, st, N, P, TE, op->d_mom.p, c, nrhs, rest,
-                           ntiles);
-        FDE_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_dense_reduce, dim3((unsigned)((nzp + 255) / 256)), dim3(256), 0, st, N, P,
-                           TE, nT, op->theta, rest, nrhs, ntiles, z);
+        // up to kStreamRhs columns per streaming pass (each pass reads the moments once)
+        if (core_events) FDE_HIP(hipEventRecord(core_events[0], st));
+        for (int r0 = 0; r0 < nrhs; r0 += kStreamRhs) {
+            const int nr = std::min(kStreamRhs, nrhs - r0);
+            if (!launch_stream(st, N, P, op->d_mom.p, c + (int64_t)r0 * N * P, nr,
+                               rest + (int64_t)r0 * ntiles * 2 * TE * P, ntiles))
+                fail(FDE_EUNSUPPORTED, "dense apply: no streaming kernel for P = %d", P);
+        }
+        if (core_events) FDE_HIP(hipEventRecord(core_events[1], st));
+        hipLaunchKernelGGL(k_dense_reduce, dim3((unsigned)nT, (unsigned)nrhs), dim3(kReduceThreads), 0, st, N, P,
+                           TE, nT, op->theta, rest, ntiles, z);
         FDE_LAUNCH_CHECK();
     } else {
         const int M = op->L / 2, logM = ilog2(M);
@@ -471,10 +594,12 @@ void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int 
         hipLaunchKernelGGL(k_rfft_forward, dim3(P, nrhs, parts), dim3(kThreads), sizeof(double2) * M, st,
                            N, P, M, logM, P, in, op->uniform ? 2 : 0, op->d_tw.p, specA);
         FDE_LAUNCH_CHECK();
+        if (core_events) FDE_HIP(hipEventRecord(core_events[0], st));
         const int64_t nk = (int64_t)nrhs * P * (M + 1);
         hipLaunchKernelGGL(k_symbol_apply, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, st, P, M,
                            parts, op->d_sym.p, specA, nrhs, specB);
         FDE_LAUNCH_CHECK();
+        if (core_events) FDE_HIP(hipEventRecord(core_events[1], st));
         InvOut io;
         io.parts = parts;
         io.s_uniform = std::pow(0.5 * op->h[0], 3.0 - op->alpha);

@@ -674,6 +674,27 @@ int fde_stiffness_apply(fde_op* op, int nrhs, const double* X, int ldx, double* 
     FDE_API_END
 }
 
+int fde_stiffness_apply_timed(fde_op* op, int nrhs, const double* X, int ldx, double* Y, int ldy, double* core_ms) {
+    FDE_API_BEGIN
+    if (!op || nrhs <= 0 || !X || !Y || !core_ms || ldx < op->Nd || ldy < op->Nd) fail(FDE_EINVAL, "bad arguments");
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    FDE_HIP(hipEventCreate(&ev[0]));
+    try {
+        FDE_HIP(hipEventCreate(&ev[1]));
+        stiffness_apply(op, nrhs, X, ldx, Y, ldy, 0.0, 0.0, false, nullptr, nullptr, ev);
+        FDE_HIP(hipEventSynchronize(ev[1]));
+        float ms = 0.0f;
+        FDE_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        *core_ms = ms;
+    } catch (...) {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        throw;
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    FDE_API_END
+}
+
 int fde_stiffness_apply_noalloc(fde_op* op, int nrhs, const double* X, int ldx, double* Y, int ldy) {
     FDE_API_BEGIN
     if (!op || nrhs < 0 || (nrhs && (!X || !Y)) || ldx < op->Nd || ldy < op->Nd)

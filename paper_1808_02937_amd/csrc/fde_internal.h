@@ -197,8 +197,11 @@ void launch_dense_matrix(Op* op, double* A, int lda);
 // on: the stream to run on (nullptr: the context's); on another stream the workspace for nrhs
 // columns must already exist (reserve_apply on the context's stream)
 // ws: the workspace (op->apply_ws_doubles(nrhs) doubles) or nullptr for the operator's own
+// core_events: if set, [0] and [1] are recorded around the kernels that read the operator (the
+// moment stream of the dense apply, the symbol product of the Toeplitz apply)
 void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int ldy, double bc0,
-                     double bcN, bool zero_x, hipStream_t on = nullptr, double* ws = nullptr);
+                     double bcN, bool zero_x, hipStream_t on = nullptr, double* ws = nullptr,
+                     hipEvent_t* core_events = nullptr);
 // allocation-free apply: a fixed device array per GPU (8 MiB), its address taken once per device
 constexpr size_t kApplyScratchDoubles = size_t(1) << 20;
 void init_apply_scratch(int device);   // with `device` current; once per device (later calls return)

@@ -185,6 +185,16 @@ class Operator(_Handle):
         check(load().fde_stiffness_apply(self.h, X2.shape[0], _dptr(X2), X2.stride(0), _dptr(Y), Y.stride(0)))
         return Y.view_as(X) if out is None else out
 
+    def apply_timed(self, X: torch.Tensor, out: torch.Tensor) -> float:
+        """Y = A X into `out`, waited for; returns the HIP-event milliseconds of the kernels that
+        read the operator (dense: the moment stream; Toeplitz: the symbol product)."""
+        X2 = _as_block(X, self.Nd, self.ctx.device)
+        Y = _as_block(out, self.Nd, self.ctx.device)
+        ms = C.c_double()
+        check(load().fde_stiffness_apply_timed(self.h, X2.shape[0], _dptr(X2), X2.stride(0), _dptr(Y), Y.stride(0),
+                                               C.byref(ms)))
+        return ms.value
+
     def apply_noalloc(self, X: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
         """Y = A X into `out` with the library's fixed per-GPU workspace (no device allocation)."""
         X2 = _as_block(X, self.Nd, self.ctx.device)
