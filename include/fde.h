@@ -299,6 +299,25 @@ void fde_server_destroy(fde_server* s);
 int  fde_server_solve(fde_server* s, int n, const fde_problem* probs, const int* nrhs,
                       const double* const* G_dev, const int* ldg, double* const* X_dev, const int* ldx,
                       fde_solve_info* info, int* cached);
+/* Continuous serving. fde_server_submit queues a request (problem, nrhs
+ * right-hand sides G, solutions X: device arrays the caller keeps alive until
+ * the request is done) and returns its ticket at once. Each fde_server_step
+ * admits queued requests in arrival order as engine slots (256 right-hand
+ * sides in flight) and the HBM budget allow -- building, in one batched H-LU,
+ * the factors of problems not cached yet, and evicting unused cached problems
+ * -- then advances every request in flight by one FGMRES step in shared
+ * launches and retires the requests that have converged; requests join and
+ * leave between steps, while others are on the device. A request's arithmetic
+ * does not depend on what else is in flight, so its X is the same alone and in
+ * a mix. *in_flight (optional): requests queued or running after the step.
+ * fde_server_poll reports whether a ticket is done; once done it fills info
+ * (nrhs entries, host) and cached (1 if its factors were cached at admission),
+ * forgets the ticket, and returns the request's status (FDE_ENOMEM if its
+ * problem can never fit the budget, FDE_ENOCONV, a build failure). */
+int  fde_server_submit(fde_server* s, const fde_problem* prob, int nrhs, const double* G_dev, int ldg,
+                       double* X_dev, int ldx, long long* ticket);
+int  fde_server_step(fde_server* s, int* in_flight);
+int  fde_server_poll(fde_server* s, long long ticket, int* done, fde_solve_info* info_host, int* cached);
 /* cached problems, their device bytes, and the cache's hits, misses and evictions */
 int  fde_server_stats(const fde_server* s, int* entries, size_t* bytes, long long* hits, long long* misses,
                       long long* evictions);

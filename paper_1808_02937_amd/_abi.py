@@ -102,6 +102,9 @@ SIGNATURES = {
     "fde_server_destroy": (None, [vp]),
     "fde_server_solve": (i32, [vp, i32, C.POINTER(Problem), ip, C.POINTER(vp), ip, C.POINTER(vp), ip,
                                C.POINTER(SolveInfo), ip]),
+    "fde_server_submit": (i32, [vp, C.POINTER(Problem), i32, vp, i32, vp, i32, C.POINTER(C.c_longlong)]),
+    "fde_server_step": (i32, [vp, ip]),
+    "fde_server_poll": (i32, [vp, C.c_longlong, ip, C.POINTER(SolveInfo), ip]),
     "fde_server_stats": (i32, [vp, ip, C.POINTER(sz), C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
                                C.POINTER(C.c_longlong)]),
     "fde_gauss_jacobi": (i32, [i32, f64, f64, dp, dp]),

@@ -15,7 +15,11 @@
 #include <algorithm>
 #include <cstring>
 
+#include <list>
+#include <memory>
+
 #include "bicgstab.h"
+#include "engine.h"
 #include "hlu.h"
 #include "krylov.h"
 
@@ -377,6 +381,304 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ continuous engine
+//
+// Every request owns its Krylov blocks and nrhs system slots in the engine's fixed device arrays
+// (SysDev, SysState), and keeps its own Arnoldi step j. A step launches, over the requests
+// running a cycle: the copy of unpreconditioned blocks, one H-solve launch per precision (each
+// request's instance points at its own block j), the applies (side streams), and one Arnoldi
+// launch whose blocks read their slot and step from index arrays. Requests whose cycle ended get
+// the update, the true residual and the check, read back at the next step; they then finish or
+// start a new cycle. The kernels act per system, so a request's bits do not depend on the others.
+
+struct EGroup {
+    long long id = 0;
+    Op* op = nullptr;
+    HLUObj* prec = nullptr;
+    int nr = 0;
+    const double* G = nullptr;
+    int ldg = 0;
+    double* X = nullptr;
+    int ldx = 0;
+    std::vector<int> slots;
+    DevBuf<int> d_slots;
+    int j = 0;
+    enum Phase { START, RUN, CHECK } phase = START;
+    bool finished = false;
+    DevBuf<double> V, Z, W, R;
+    DevBuf<char> rhs, work;
+    int hs_wc = 0;            // LDS H-solve columns per workgroup (0: interpreter)
+    size_t hs_bytes = 0;
+};
+
+struct KrylovEngine {
+    Ctx* c = nullptr;
+    int m = 30, maxit = 500;
+    double rtol = 1e-10;
+    int cap = 0;
+    DevBuf<SysDev> d_sys;
+    DevBuf<SysState> d_ss;
+    DevBuf<int> d_mask, d_sel, d_jv, d_sel_all, d_start;
+    DevBuf<SysStatus> d_stat;
+    DevBuf<Inst<float>> d_i32;
+    DevBuf<Inst<double>> d_i64;
+    std::vector<int> free_slots;
+    std::list<std::unique_ptr<EGroup>> groups;
+};
+
+KrylovEngine* engine_create(Ctx* c, int restart, int maxit, double rtol, int max_systems) {
+    if (restart < 1 || restart > kMaxRestart) fail(FDE_EINVAL, "restart must be in [1, %d]", kMaxRestart);
+    if (maxit < 1 || !(rtol > 0.0) || max_systems < 1) fail(FDE_EINVAL, "bad engine parameters");
+    auto e = std::make_unique<KrylovEngine>();
+    e->c = c;
+    e->m = restart;
+    e->maxit = maxit;
+    e->rtol = rtol;
+    e->cap = max_systems;
+    e->d_sys.alloc(c, max_systems);
+    e->d_ss.alloc(c, max_systems);
+    e->d_mask.alloc(c, max_systems);
+    for (DevBuf<int>* b : {&e->d_sel, &e->d_jv, &e->d_sel_all, &e->d_start}) b->alloc(c, max_systems);
+    e->d_stat.alloc(c, max_systems);
+    e->d_i32.alloc(c, max_systems);
+    e->d_i64.alloc(c, max_systems);
+    for (int k = max_systems - 1; k >= 0; --k) e->free_slots.push_back(k);
+    return e.release();
+}
+
+void engine_destroy(KrylovEngine* e) {
+    if (!e) return;
+    (void)hipStreamSynchronize(e->c->stream);
+    delete e;
+}
+
+int engine_free_slots(const KrylovEngine* e) { return (int)e->free_slots.size(); }
+int engine_groups(const KrylovEngine* e) { return (int)e->groups.size(); }
+
+void engine_add(KrylovEngine* e, Op* op, HLUObj* prec, int nrhs, const double* G, int ldg, double* X, int ldx,
+                long long id) {
+    Ctx* c = e->c;
+    hipStream_t st = c->stream;
+    if (nrhs < 1 || nrhs > (int)e->free_slots.size()) fail(FDE_EINVAL, "engine: %d columns, %zu free slots", nrhs,
+                                                            e->free_slots.size());
+    if (!op || op->ctx != c || (prec && prec->op != op)) fail(FDE_EINVAL, "engine: operator or preconditioner");
+    if (!G || !X || ldg < op->Nd || ldx < op->Nd) fail(FDE_EINVAL, "engine: bad right-hand side arguments");
+    auto g = std::make_unique<EGroup>();
+    g->id = id;
+    g->op = op;
+    g->prec = prec;
+    g->nr = nrhs;
+    g->G = G;
+    g->ldg = ldg;
+    g->X = X;
+    g->ldx = ldx;
+    const int64_t bs = (int64_t)op->Nd * nrhs;
+    g->V.alloc(c, (e->m + 1) * bs);
+    g->Z.alloc(c, e->m * bs);
+    g->W.alloc(c, bs);
+    g->R.alloc(c, bs);
+    FDE_HIP(hipMemsetAsync(g->V.p, 0, g->V.bytes(), st));
+    FDE_HIP(hipMemsetAsync(g->Z.p, 0, g->Z.bytes(), st));
+    FDE_HIP(hipMemsetAsync(g->R.p, 0, g->R.bytes(), st));   // A x_0 = 0: the first cycle starts from G
+    if (prec) {
+        g->rhs.alloc(c, bs * prec->esz);
+        g->work.alloc(c, std::max<int64_t>(prec->plan->sv.work_elems, 1) * nrhs * prec->esz);
+        g->hs_wc = hsolve_cols(c, prec, nrhs, &g->hs_bytes);
+    }
+    const size_t need = op->apply_ws_doubles(nrhs);
+    if (op->ws.n < need) op->ws.alloc(c, need);
+    for (int k = 0; k < nrhs; ++k) {
+        const int slot = e->free_slots.back();
+        e->free_slots.pop_back();
+        g->slots.push_back(slot);
+        SysDev d{};
+        d.V = g->V.p;
+        d.Z = g->Z.p;
+        d.W = g->W.p;
+        d.R = g->R.p;
+        d.G = G + (int64_t)k * ldg;
+        d.X = X + (int64_t)k * ldx;
+        d.bs = bs;
+        d.Nd = op->Nd;
+        d.c = k;
+        upload(c, e->d_sys.p + slot, &d, sizeof d);
+        const int mk = prec ? 0 : 1;
+        upload(c, e->d_mask.p + slot, &mk, sizeof mk);
+    }
+    g->d_slots.alloc(c, nrhs);
+    upload(c, g->d_slots.p, g->slots.data(), nrhs * sizeof(int));
+    fg_gnorm(st, nrhs, e->d_sys.p, e->d_ss.p, g->d_slots.p);
+    fg_zero_x(st, nrhs, e->d_sys.p, g->d_slots.p);
+    e->groups.push_back(std::move(g));
+}
+
+namespace {
+
+// H-solves of block j of every running group with a preconditioner of precision T, one launch
+template <class T>
+void engine_hsolve(KrylovEngine* e, std::vector<EGroup*>& run, DevBuf<Inst<T>>& d_inst, int prec_code) {
+    std::vector<Inst<T>> insts;
+    bool lds = true;
+    int wc = 1, nchunk = 1;
+    size_t bytes = 0;
+    for (EGroup* g : run) {
+        if (!g->prec || g->prec->prec != prec_code) continue;
+        const int64_t bs = (int64_t)g->op->Nd * g->nr;
+        Inst<T> d = g->prec->inst<T>(true, g->nr, g->V.p + g->j * bs, g->op->Nd, g->Z.p + g->j * bs, g->op->Nd);
+        d.work = reinterpret_cast<T*>(g->work.p);
+        d.rhs = reinterpret_cast<T*>(g->rhs.p);
+        d.flops = g->prec->flops.p + 1;
+        d.hs_wc = g->hs_wc;
+        insts.push_back(d);
+        if (g->hs_wc == 0) {
+            lds = false;
+        } else {
+            wc = std::max(wc, g->hs_wc);
+            nchunk = std::max(nchunk, (g->nr + g->hs_wc - 1) / g->hs_wc);
+            bytes = std::max(bytes, g->hs_bytes);
+        }
+    }
+    if (insts.empty()) return;
+    upload(e->c, d_inst.p, insts.data(), insts.size() * sizeof(Inst<T>));
+    if (lds)
+        launch_hsolve<T>(e->c->stream, (int)insts.size(), nchunk, wc, d_inst.p, 0, bytes);
+    else
+        launch_interp<T>(e->c->stream, (int)insts.size(), d_inst.p, 0);
+}
+
+// fn(group, stream) over groups, each operator's groups on one of the context's streams
+template <class F>
+void engine_apply(Ctx* c, std::vector<EGroup*>& gs, F fn) {
+    if (gs.size() <= 1) {
+        for (EGroup* g : gs) fn(*g, c->stream);
+        return;
+    }
+    ensure_side_streams(c);
+    FDE_HIP(hipEventRecord(c->fork_ev, c->stream));
+    for (hipStream_t s : c->side) FDE_HIP(hipStreamWaitEvent(s, c->fork_ev, 0));
+    std::vector<Op*> seen;
+    for (EGroup* g : gs) {
+        size_t slot = std::find(seen.begin(), seen.end(), g->op) - seen.begin();
+        if (slot == seen.size()) seen.push_back(g->op);
+        const int k = (int)(slot % (kSideStreams + 1));
+        fn(*g, k == 0 ? c->stream : c->side[k - 1]);
+    }
+    for (int k = 0; k < kSideStreams; ++k) {
+        FDE_HIP(hipEventRecord(c->side_done[k], c->side[k]));
+        FDE_HIP(hipStreamWaitEvent(c->stream, c->side_done[k], 0));
+    }
+}
+
+}  // namespace
+
+void engine_step(KrylovEngine* e, std::vector<EngineDone>& done) {
+    Ctx* c = e->c;
+    hipStream_t st = c->stream;
+    if (e->groups.empty()) return;
+    // new requests start their first cycle
+    std::vector<int> start;
+    for (auto& g : e->groups)
+        if (g->phase == EGroup::START) {
+            start.insert(start.end(), g->slots.begin(), g->slots.end());
+            g->phase = EGroup::RUN;
+            g->j = 0;
+        }
+    if (!start.empty()) {
+        upload(c, e->d_start.p, start.data(), start.size() * sizeof(int));
+        fg_cycle_start(st, (int)start.size(), e->d_sys.p, e->d_ss.p, 0, e->maxit, e->d_start.p);
+    }
+    // one Arnoldi step of every running request
+    std::vector<EGroup*> run;
+    std::vector<int> sel, jv;
+    for (auto& g : e->groups)
+        if (g->phase == EGroup::RUN) {
+            run.push_back(g.get());
+            for (int s : g->slots) {
+                sel.push_back(s);
+                jv.push_back(g->j);
+            }
+        }
+    if (!run.empty()) {
+        upload(c, e->d_sel.p, sel.data(), sel.size() * sizeof(int));
+        upload(c, e->d_jv.p, jv.data(), jv.size() * sizeof(int));
+        fg_copy_step(st, (int)sel.size(), e->d_sys.p, e->d_mask.p, 0, e->d_sel.p, e->d_jv.p);
+        engine_hsolve<float>(e, run, e->d_i32, FDE_FP32);
+        engine_hsolve<double>(e, run, e->d_i64, FDE_FP64);
+        engine_apply(c, run, [&](EGroup& g, hipStream_t s) {
+            const int64_t bs = (int64_t)g.op->Nd * g.nr;
+            stiffness_apply(g.op, g.nr, g.Z.p + g.j * bs, g.op->Nd, g.W.p, g.op->Nd, 0.0, 0.0, false, s);
+        });
+        fg_arnoldi(st, (int)sel.size(), e->d_sys.p, e->d_ss.p, 0, e->m, e->rtol, e->maxit, e->d_sel.p, e->d_jv.p);
+    }
+    // status of the running requests and of those whose check was queued in the step before
+    std::vector<EGroup*> seen;
+    std::vector<int> all;
+    for (auto& g : e->groups)
+        if (g->phase == EGroup::RUN || g->phase == EGroup::CHECK) {
+            seen.push_back(g.get());
+            all.insert(all.end(), g->slots.begin(), g->slots.end());
+        }
+    std::vector<SysStatus> hst(all.size());
+    if (!all.empty()) {
+        upload(c, e->d_sel_all.p, all.data(), all.size() * sizeof(int));
+        fg_gather_status(st, (int)all.size(), e->d_ss.p, e->d_sel_all.p, e->d_stat.p);
+        FDE_HIP(hipMemcpyAsync(hst.data(), e->d_stat.p, all.size() * sizeof(SysStatus), hipMemcpyDeviceToHost, st));
+    }
+    FDE_HIP(hipStreamSynchronize(st));
+    size_t k = 0;
+    std::vector<EGroup*> cycle_end, restart;
+    for (EGroup* g : seen) {
+        const SysStatus* s = hst.data() + k;
+        k += g->slots.size();
+        if (g->phase == EGroup::CHECK) {
+            bool more = false;
+            for (int i = 0; i < g->nr; ++i)
+                if (!s[i].conv && s[i].status == 0 && s[i].iters < e->maxit) more = true;
+            if (more) {
+                restart.push_back(g);
+                continue;
+            }
+            EngineDone d;
+            d.id = g->id;
+            for (int i = 0; i < g->nr; ++i)
+                d.info.push_back(fde_solve_info{s[i].iters, s[i].relres,
+                                                s[i].conv ? FDE_OK : (s[i].status ? FDE_EINVAL : FDE_ENOCONV)});
+            done.push_back(std::move(d));
+            g->finished = true;
+            continue;
+        }
+        // running: the step was taken; the cycle ends once no system of the request is active
+        g->j += 1;
+        bool any = false;
+        for (int i = 0; i < g->nr; ++i) any = any || s[i].active;
+        if (!any) cycle_end.push_back(g);
+    }
+    // finished requests leave (their slots are free for the next admission)
+    for (auto it = e->groups.begin(); it != e->groups.end();) {
+        if ((*it)->finished) {
+            for (int s : (*it)->slots) e->free_slots.push_back(s);
+            it = e->groups.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    // cycle ends: x += Z y, the true residual G - A x, the convergence check (read at the next step)
+    for (EGroup* g : cycle_end) {
+        fg_update(st, g->nr, e->d_sys.p, e->d_ss.p, g->d_slots.p);
+        g->phase = EGroup::CHECK;
+    }
+    engine_apply(c, cycle_end, [&](EGroup& g, hipStream_t s) {
+        stiffness_apply(g.op, g.nr, g.X, g.ldx, g.R.p, g.op->Nd, 0.0, 0.0, false, s);
+    });
+    for (EGroup* g : cycle_end) fg_check(st, g->nr, e->d_sys.p, e->d_ss.p, e->rtol, g->d_slots.p);
+    // checked and not converged: a new cycle from the true residual
+    for (EGroup* g : restart) {
+        fg_cycle_start(st, g->nr, e->d_sys.p, e->d_ss.p, 0, e->maxit, g->d_slots.p);
+        g->phase = EGroup::RUN;
+        g->j = 0;
+    }
+}
 
 }  // namespace fde
 

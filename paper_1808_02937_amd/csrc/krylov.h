@@ -25,13 +25,24 @@ struct SysState {
     int active, jend, iters, conv, status, pad;
 };
 
-void fg_gnorm(hipStream_t st, int ns, const SysDev* sys, SysState* ss);
-void fg_zero_x(hipStream_t st, int ns, const SysDev* sys);
-void fg_cycle_start(hipStream_t st, int ns, const SysDev* sys, SysState* ss, int first, int maxit);
-void fg_copy_step(hipStream_t st, int ns, const SysDev* sys, const int* mask, int j);
-void fg_arnoldi(hipStream_t st, int ns, const SysDev* sys, SysState* ss, int j, int m, double rtol, int maxit);
+// sel: the slots of the systems a launch works on (block b takes slot sel[b]); nullptr: slots
+// 0 .. ns-1. jv: the Arnoldi step of each selected system; nullptr: the scalar j for all.
+void fg_gnorm(hipStream_t st, int ns, const SysDev* sys, SysState* ss, const int* sel = nullptr);
+void fg_zero_x(hipStream_t st, int ns, const SysDev* sys, const int* sel = nullptr);
+void fg_cycle_start(hipStream_t st, int ns, const SysDev* sys, SysState* ss, int first, int maxit,
+                    const int* sel = nullptr);
+void fg_copy_step(hipStream_t st, int ns, const SysDev* sys, const int* mask, int j, const int* sel = nullptr,
+                  const int* jv = nullptr);
+void fg_arnoldi(hipStream_t st, int ns, const SysDev* sys, SysState* ss, int j, int m, double rtol, int maxit,
+                const int* sel = nullptr, const int* jv = nullptr);
 void fg_count_active(hipStream_t st, int ns, const SysState* ss, int* out);
-void fg_update(hipStream_t st, int ns, const SysDev* sys, SysState* ss);
-void fg_check(hipStream_t st, int ns, const SysDev* sys, SysState* ss, double rtol);
+void fg_update(hipStream_t st, int ns, const SysDev* sys, SysState* ss, const int* sel = nullptr);
+void fg_check(hipStream_t st, int ns, const SysDev* sys, SysState* ss, double rtol, const int* sel = nullptr);
+
+struct SysStatus {   // what the host reads of a system after a step
+    double relres;
+    int active, conv, status, iters, jend, pad;
+};
+void fg_gather_status(hipStream_t st, int n, const SysState* ss, const int* sel, SysStatus* out);
 
 }  // namespace fde

@@ -71,14 +71,15 @@ __device__ void block_dots(const double* base, int64_t stride, int nv, const dou
     }
 }
 
-__global__ void k_gnorm(const SysDev* __restrict__ sys, SysState* __restrict__ ss) {
+__global__ void k_gnorm(const SysDev* __restrict__ sys, SysState* __restrict__ ss, const int* __restrict__ sel) {
     __shared__ Red r;
-    const SysDev d = sys[blockIdx.x];
+    const int slot = sel ? sel[blockIdx.x] : blockIdx.x;
+    const SysDev d = sys[slot];
     double v = 0.0;
     for (int i = threadIdx.x; i < d.Nd; i += kT) v += d.G[i] * d.G[i];
     v = block_sum(v, r);
     if (threadIdx.x == 0) {
-        SysState& s = ss[blockIdx.x];
+        SysState& s = ss[slot];
         s.gnorm = sqrt(v);
         s.iters = 0;
         s.conv = 0;
@@ -94,15 +95,17 @@ __global__ void k_gnorm(const SysDev* __restrict__ sys, SysState* __restrict__ s
     }
 }
 
-__global__ void k_zero_x(const SysDev* __restrict__ sys) {
-    const SysDev d = sys[blockIdx.y];
+__global__ void k_zero_x(const SysDev* __restrict__ sys, const int* __restrict__ sel) {
+    const SysDev d = sys[sel ? sel[blockIdx.y] : blockIdx.y];
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.Nd; i += gridDim.x * blockDim.x) d.X[i] = 0.0;
 }
 
-__global__ void k_cycle_start(const SysDev* __restrict__ sys, SysState* __restrict__ ss, int first, int maxit) {
+__global__ void k_cycle_start(const SysDev* __restrict__ sys, SysState* __restrict__ ss, int first, int maxit,
+                              const int* __restrict__ sel) {
     __shared__ Red r;
-    const SysDev d = sys[blockIdx.x];
-    SysState& s = ss[blockIdx.x];
+    const int slot = sel ? sel[blockIdx.x] : blockIdx.x;
+    const SysDev d = sys[slot];
+    SysState& s = ss[slot];
     if (s.conv || s.iters >= maxit) {
         if (threadIdx.x == 0) s.active = 0;
         return;
@@ -127,20 +130,26 @@ __global__ void k_cycle_start(const SysDev* __restrict__ sys, SysState* __restri
     }
 }
 
-__global__ void k_copy_step(const SysDev* __restrict__ sys, const int* __restrict__ mask, int j) {
-    const SysDev d = sys[blockIdx.y];
-    if (!mask[blockIdx.y]) return;
+__global__ void k_copy_step(const SysDev* __restrict__ sys, const int* __restrict__ mask, int j,
+                            const int* __restrict__ sel, const int* __restrict__ jv) {
+    const int slot = sel ? sel[blockIdx.y] : blockIdx.y;
+    const SysDev d = sys[slot];
+    if (!mask[slot]) return;
+    if (jv) j = jv[blockIdx.y];
     const double* v = d.V + (int64_t)j * d.bs + (int64_t)d.c * d.Nd;
     double* z = d.Z + (int64_t)j * d.bs + (int64_t)d.c * d.Nd;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.Nd; i += gridDim.x * blockDim.x) z[i] = v[i];
 }
 
 __global__ void __launch_bounds__(kT) k_arnoldi(const SysDev* __restrict__ sys, SysState* __restrict__ ss, int j,
-                                                int m, double rtol, int maxit) {
+                                                int m, double rtol, int maxit, const int* __restrict__ sel,
+                                                const int* __restrict__ jv) {
     __shared__ Red r;
     __shared__ double hcol[kMaxRestart + 1];
-    const SysDev d = sys[blockIdx.x];
-    SysState& s = ss[blockIdx.x];
+    const int slot = sel ? sel[blockIdx.x] : blockIdx.x;
+    if (jv) j = jv[blockIdx.x];
+    const SysDev d = sys[slot];
+    SysState& s = ss[slot];
     if (!s.active) return;
     const int n = d.Nd;
     double* w = d.W + (int64_t)d.c * n;
@@ -197,9 +206,10 @@ __global__ void k_count_active(const SysState* __restrict__ ss, int ns, int* out
     if (threadIdx.x == 0) *out = (int)v;
 }
 
-__global__ void k_update(const SysDev* __restrict__ sys, SysState* __restrict__ ss) {
-    const SysDev d = sys[blockIdx.x];
-    SysState& s = ss[blockIdx.x];
+__global__ void k_update(const SysDev* __restrict__ sys, SysState* __restrict__ ss, const int* __restrict__ sel) {
+    const int slot = sel ? sel[blockIdx.x] : blockIdx.x;
+    const SysDev d = sys[slot];
+    SysState& s = ss[slot];
     const int k = s.jend;
     if (k <= 0) return;
     if (threadIdx.x == 0) {
@@ -220,10 +230,12 @@ __global__ void k_update(const SysDev* __restrict__ sys, SysState* __restrict__ 
     if (threadIdx.x == 0) s.jend = 0;
 }
 
-__global__ void k_check(const SysDev* __restrict__ sys, SysState* __restrict__ ss, double rtol) {
+__global__ void k_check(const SysDev* __restrict__ sys, SysState* __restrict__ ss, double rtol,
+                        const int* __restrict__ sel) {
     __shared__ Red r;
-    const SysDev d = sys[blockIdx.x];
-    SysState& s = ss[blockIdx.x];
+    const int slot = sel ? sel[blockIdx.x] : blockIdx.x;
+    const SysDev d = sys[slot];
+    SysState& s = ss[slot];
     if (s.conv) return;
     const double* Rc = d.R + (int64_t)d.c * d.Nd;
     double nn = 0.0;
@@ -239,38 +251,52 @@ __global__ void k_check(const SysDev* __restrict__ sys, SysState* __restrict__ s
     }
 }
 
+// compact status of the selected systems (one 32-byte record each) for the host
+__global__ void k_gather_status(const SysState* __restrict__ ss, const int* __restrict__ sel, int n,
+                                SysStatus* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const SysState& s = ss[sel ? sel[i] : i];
+    out[i] = SysStatus{s.relres, s.active, s.conv, s.status, s.iters, s.jend, 0};
+}
+
 }  // namespace
 
-void fg_gnorm(hipStream_t st, int ns, const SysDev* sys, SysState* ss) {
-    hipLaunchKernelGGL(k_gnorm, dim3(ns), dim3(kT), 0, st, sys, ss);
+void fg_gnorm(hipStream_t st, int ns, const SysDev* sys, SysState* ss, const int* sel) {
+    hipLaunchKernelGGL(k_gnorm, dim3(ns), dim3(kT), 0, st, sys, ss, sel);
     FDE_LAUNCH_CHECK();
 }
-void fg_zero_x(hipStream_t st, int ns, const SysDev* sys) {
-    hipLaunchKernelGGL(k_zero_x, dim3(16, ns), dim3(256), 0, st, sys);
+void fg_zero_x(hipStream_t st, int ns, const SysDev* sys, const int* sel) {
+    hipLaunchKernelGGL(k_zero_x, dim3(16, ns), dim3(256), 0, st, sys, sel);
     FDE_LAUNCH_CHECK();
 }
-void fg_cycle_start(hipStream_t st, int ns, const SysDev* sys, SysState* ss, int first, int maxit) {
-    hipLaunchKernelGGL(k_cycle_start, dim3(ns), dim3(kT), 0, st, sys, ss, first, maxit);
+void fg_cycle_start(hipStream_t st, int ns, const SysDev* sys, SysState* ss, int first, int maxit, const int* sel) {
+    hipLaunchKernelGGL(k_cycle_start, dim3(ns), dim3(kT), 0, st, sys, ss, first, maxit, sel);
     FDE_LAUNCH_CHECK();
 }
-void fg_copy_step(hipStream_t st, int ns, const SysDev* sys, const int* mask, int j) {
-    hipLaunchKernelGGL(k_copy_step, dim3(16, ns), dim3(256), 0, st, sys, mask, j);
+void fg_copy_step(hipStream_t st, int ns, const SysDev* sys, const int* mask, int j, const int* sel, const int* jv) {
+    hipLaunchKernelGGL(k_copy_step, dim3(16, ns), dim3(256), 0, st, sys, mask, j, sel, jv);
     FDE_LAUNCH_CHECK();
 }
-void fg_arnoldi(hipStream_t st, int ns, const SysDev* sys, SysState* ss, int j, int m, double rtol, int maxit) {
-    hipLaunchKernelGGL(k_arnoldi, dim3(ns), dim3(kT), 0, st, sys, ss, j, m, rtol, maxit);
+void fg_arnoldi(hipStream_t st, int ns, const SysDev* sys, SysState* ss, int j, int m, double rtol, int maxit,
+                const int* sel, const int* jv) {
+    hipLaunchKernelGGL(k_arnoldi, dim3(ns), dim3(kT), 0, st, sys, ss, j, m, rtol, maxit, sel, jv);
     FDE_LAUNCH_CHECK();
 }
 void fg_count_active(hipStream_t st, int ns, const SysState* ss, int* out) {
     hipLaunchKernelGGL(k_count_active, dim3(1), dim3(kT), 0, st, ss, ns, out);
     FDE_LAUNCH_CHECK();
 }
-void fg_update(hipStream_t st, int ns, const SysDev* sys, SysState* ss) {
-    hipLaunchKernelGGL(k_update, dim3(ns), dim3(kT), 0, st, sys, ss);
+void fg_update(hipStream_t st, int ns, const SysDev* sys, SysState* ss, const int* sel) {
+    hipLaunchKernelGGL(k_update, dim3(ns), dim3(kT), 0, st, sys, ss, sel);
     FDE_LAUNCH_CHECK();
 }
-void fg_check(hipStream_t st, int ns, const SysDev* sys, SysState* ss, double rtol) {
-    hipLaunchKernelGGL(k_check, dim3(ns), dim3(kT), 0, st, sys, ss, rtol);
+void fg_check(hipStream_t st, int ns, const SysDev* sys, SysState* ss, double rtol, const int* sel) {
+    hipLaunchKernelGGL(k_check, dim3(ns), dim3(kT), 0, st, sys, ss, rtol, sel);
+    FDE_LAUNCH_CHECK();
+}
+void fg_gather_status(hipStream_t st, int n, const SysState* ss, const int* sel, SysStatus* out) {
+    hipLaunchKernelGGL(k_gather_status, dim3((n + 255) / 256), dim3(256), 0, st, ss, sel, n, out);
     FDE_LAUNCH_CHECK();
 }
 

@@ -392,6 +392,51 @@ class Server(_Handle):
             k += B.shape[0]
         return Xs, out, [bool(c) for c in cached]
 
+    # -- continuous serving --
+    def submit(self, problem, G: torch.Tensor, X: Optional[torch.Tensor] = None):
+        """Queue one request (problem = (nodes, P, alpha, theta, rho); G: (nrhs, Nd) float64 on the
+        device). Returns (ticket, X); X is written when the request is done."""
+        nodes, P, alpha, theta, rho = problem
+        x = np.ascontiguousarray(nodes, dtype=np.float64)
+        Nd = (len(x) - 1) * int(P) - 1
+        B = _as_block(G, Nd, self.ctx.device)
+        Xo = torch.empty_like(B) if X is None else _as_block(X, Nd, self.ctx.device)
+        prob = A.Problem(_np_dptr(x), len(x) - 1, int(P), float(alpha), float(theta), float(rho))
+        t = C.c_longlong()
+        check(load().fde_server_submit(self.h, C.byref(prob), B.shape[0], _dptr(B), B.stride(0), _dptr(Xo),
+                                       Xo.stride(0), C.byref(t)))
+        self._live = getattr(self, "_live", {})
+        self._live[t.value] = (B, Xo)   # keep the device arrays alive until the ticket is collected
+        return t.value, Xo
+
+    def step(self) -> int:
+        """Admit what fits, advance every request in flight by one Krylov step; returns the number of
+        requests still queued or running."""
+        n = C.c_int()
+        check(load().fde_server_step(self.h, C.byref(n)))
+        return n.value
+
+    def poll(self, ticket: int):
+        """(done, infos, cached) for a ticket; once done the ticket is forgotten. A failed request
+        raises FDEError with its status."""
+        B, Xo = self._live[ticket]
+        done = C.c_int()
+        cached = C.c_int()
+        info = (A.SolveInfo * max(B.shape[0], 1))()
+        rc = load().fde_server_poll(self.h, ticket, C.byref(done), info, C.byref(cached))
+        if rc == A.FDE_OK and not done.value:
+            return False, None, None
+        del self._live[ticket]
+        check(rc)
+        return True, [(info[j].iters, info[j].relres, info[j].status) for j in range(B.shape[0])], bool(cached.value)
+
+    def drain(self, max_steps: int = 100000):
+        """Step until nothing is queued or running."""
+        for _ in range(max_steps):
+            if self.step() == 0:
+                return
+        raise RuntimeError("server: requests still in flight after max_steps steps")
+
     def stats(self) -> dict:
         e = C.c_int()
         b = C.c_size_t()

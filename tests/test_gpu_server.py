@@ -92,3 +92,87 @@ def test_server_rejects_what_cannot_fit(ctx):
     assert infos[1][0][2] == FDE_ENOMEM
     assert true_relres(small, Gs[0], Xs[0]) <= 1e-9
     assert srv.stats()["entries"] == 1
+
+
+def _collect(srv, tickets):
+    out = {}
+    for t in tickets:
+        done, inf, cached = srv.poll(t)
+        assert done, t
+        out[t] = (inf, cached)
+    return out
+
+
+def test_continuous_serving_same_result_alone_and_in_the_mix(ctx):
+    """Requests join a server while others are in flight (iteration-level continuous batching); a
+    request's solution is bit for bit the one it gets alone."""
+    import paper_1808_02937_amd as fde
+    say("continuous serving: alone vs in a mix")
+    pa = PROBS[2]
+    GA = rhs(pa, 3, 77)
+    alone = fde.Server(ctx, R=6, leaf_elems=4, rtol=1e-12)
+    tA, XA = alone.submit(pa, GA)
+    alone.drain()
+    infA = _collect(alone, [tA])[tA][0]
+    alone.close()
+    mix = fde.Server(ctx, R=6, leaf_elems=4, rtol=1e-12)
+    GB, GC, GD = rhs(PROBS[0], 5, 78), rhs(PROBS[1], 2, 79), rhs(PROBS[3], 4, 80)
+    res = {}
+
+    def finished(tickets):   # polls (a done ticket is collected once) and says which are done
+        for t in tickets:
+            if t not in res:
+                done, inf, cached = mix.poll(t)
+                if done:
+                    res[t] = (inf, cached)
+        return [t in res for t in tickets]
+
+    tB, XB = mix.submit(PROBS[0], GB)
+    tC, XC = mix.submit(PROBS[1], GC)
+    mix.step()
+    tA2, XA2 = mix.submit(pa, GA)
+    mix.step()   # A is admitted while B (and perhaps C) are on the device
+    assert not all(finished([tB, tC])), "A should join while another request is in flight"
+    tD, XD = mix.submit(PROBS[3], GD)
+    mix.step()
+    assert not finished([tA2])[0], "D should join while A is in flight"
+    mix.drain()
+    finished([tA2, tB, tC, tD])
+    say(f"  alone iters {[i[0] for i in infA]}, in the mix {[i[0] for i in res[tA2][0]]}")
+    assert torch.equal(XA, XA2)
+    assert [i[0] for i in infA] == [i[0] for i in res[tA2][0]]
+    for t, p, G, X in ((tB, PROBS[0], GB, XB), (tC, PROBS[1], GC, XC), (tD, PROBS[3], GD, XD)):
+        assert all(s == 0 for (_, _, s) in res[t][0]), res[t]
+        assert true_relres(p, G, X) <= 5e-12
+    # the same problem again later: its factors are cached
+    tE, XE = mix.submit(PROBS[0], GB)
+    mix.drain()
+    infE, cachedE = _collect(mix, [tE])[tE]
+    assert cachedE and torch.equal(XE, XB)
+    mix.close()
+
+
+def test_continuous_serving_waits_for_memory(ctx):
+    """With room for one problem, a second problem waits in the queue until the first request is
+    done and its factors can be evicted; factors in use are never evicted."""
+    import paper_1808_02937_amd as fde
+    say("continuous serving: admission by memory")
+    probe = fde.Server(ctx, R=6, leaf_elems=4)
+    probe.solve([PROBS[0]], [rhs(PROBS[0], 1, 1)])
+    one = probe.stats()["bytes"]
+    probe.close()
+    p0, p1 = PROBS[0], (fi.uniform_mesh(30), 4, 1.5, 0.5, 1.0)
+    srv = fde.Server(ctx, R=6, leaf_elems=4, rtol=1e-12, budget_bytes=int(1.6 * one))
+    G0, G1 = rhs(p0, 2, 5), rhs(p1, 2, 6)
+    t0, X0 = srv.submit(p0, G0)
+    t1, X1 = srv.submit(p1, G1)
+    assert srv.step() == 2
+    assert srv.stats()["entries"] == 1          # p1 waits: p0's factors are in use
+    srv.drain()
+    res = _collect(srv, [t0, t1])
+    st = srv.stats()
+    assert st["evictions"] == 1 and st["entries"] == 1 and st["bytes"] <= 1.6 * one
+    for p, G, X, t in ((p0, G0, X0, t0), (p1, G1, X1, t1)):
+        assert all(s == 0 for (_, _, s) in res[t][0])
+        assert true_relres(p, G, X) <= 5e-12
+    srv.close()
