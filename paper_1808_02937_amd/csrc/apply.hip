@@ -91,6 +91,21 @@ __global__ void k_gather(int N, int P, const double* __restrict__ h, const doubl
     c[idx] = deriv_coef(X ? X + (int64_t)r * ldx : nullptr, e, m, N, P, h, bc0, bcN);
 }
 
+// the same coefficients for chunks of up to kc right-hand sides, each chunk stored unknown-major:
+// chunk k (columns [k kc, k kc + nr)) at c + k kc N P, entry (e P + m) nr + r
+__global__ void k_gather_t(int N, int P, const double* __restrict__ h, const double* __restrict__ X, int ldx,
+                           int nrhs, int kc, double bc0, double bcN, double* __restrict__ c) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t NP = (int64_t)N * P;
+    if (idx >= (int64_t)nrhs * NP) return;
+    const int64_t k = idx / (kc * NP), rem = idx % (kc * NP);
+    const int nr = (int)std::min<int64_t>(kc, nrhs - k * kc);
+    const int64_t row = rem / nr;
+    const int r = (int)(rem % nr), e = (int)(row / P), m = (int)(row % P);
+    const int col = (int)(k * kc) + r;
+    c[idx] = deriv_coef(X ? X + (int64_t)col * ldx : nullptr, e, m, N, P, h, bc0, bcN);
+}
+
 // ----------------------------------------------------------------- scatter
 __global__ void k_scatter(int N, int P, double rho, const double* __restrict__ h,
                           const double* __restrict__ lmass, const double* __restrict__ z,
@@ -265,6 +280,158 @@ __global__ void __launch_bounds__(kStreamThreads) k_dense_stream(int N, const do
     }
 }
 
+// Dense apply for many right-hand sides on the FP64 matrix cores. Same tiles, same streamed loads
+// and LDS layout as k_dense_stream; a tile is the TP x TP matrix M[(el, m)][(fl, n)] (TP = T P <=
+// 64), and its partials are two small products per chunk of up to kMfmaRhs right-hand sides:
+//   rows:    R = M C_f   (TP x nr),     columns: Q = M^T C_e   (TP x nr),
+// with C_f, C_e the tile's coefficient rows staged in LDS. Each product runs in 16 x 16 output
+// tiles of v_mfma_f64_16x16x4 (A: 16 x 4, B: 4 x 16, accumulated over TP / 4 steps); wave w
+// takes output rows [16 w, 16 w + 16) of both products for every 16-column block of the chunk.
+// Operands past TP read as zero.
+constexpr int kMfmaRhs = 64;
+constexpr int kMfmaMin = 8;   // fewer right-hand sides take the vector stream
+typedef double v4d_apply __attribute__((ext_vector_type(4)));
+
+template <int P>
+__global__ void __launch_bounds__(kStreamThreads) k_dense_mfma(int N, const double* __restrict__ mom,
+                                                               const double* __restrict__ c, int nrhs,
+                                                               double* __restrict__ part, int64_t ntiles) {
+    using S = StreamTile<P>;
+    constexpr int NB = kMfmaRhs / 16;   // 16-column blocks of a full chunk
+    __shared__ double Kt[S::T * S::T * S::BLK];
+    constexpr int LDR = kMfmaRhs + 1;   // odd row stride: the staging stores hit distinct banks
+    __shared__ double cf[64 * LDR], ce[64 * LDR];   // [row (fl, n) or (el, m)][rhs]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nout = 2 * S::TP;
+    const int nb = (nrhs + 15) / 16;
+    double v[S::KL][2];
+    int64_t t = blockIdx.x;
+    if (t < ntiles) stream_load<P>(mom, N, t, v);
+    for (; t < ntiles; t += gridDim.x) {
+        int I, J;
+        tile_ij(t, &I, &J);
+        const int e0 = I * S::T, f0 = J * S::T;
+#pragma unroll
+        for (int j = 0; j < S::KL; ++j) {
+            const int g = j * kStreamThreads + tid;
+            if (g < S::T * S::GR) {
+                const int el = g / S::GR, k = (g % S::GR) * S::GW;
+                const int fl = k / S::PP, w = k % S::PP, m = w / P, n = w % P;
+                double* dst = Kt + (el * S::T + fl) * S::BLK + m * S::LDP + n;
+                dst[0] = v[j][0];
+                if constexpr (S::W16) dst[1] = v[j][1];
+            }
+        }
+        // coefficient rows of the tile: c is unknown-major for this chunk, so the rows of the
+        // tile are one contiguous run each (TP nrhs doubles); all loads of a round in flight at once
+        {
+            const int len = S::TP * nrhs;
+            const double* srce = c + (int64_t)e0 * P * nrhs;
+            const double* srcf = c + (int64_t)f0 * P * nrhs;
+            const int lim_e = (int)std::min<int64_t>(len, ((int64_t)N * P - (int64_t)e0 * P) * nrhs);
+            const int lim_f = (int)std::min<int64_t>(len, ((int64_t)N * P - (int64_t)f0 * P) * nrhs);
+            for (int base = 0; base < 64 * kMfmaRhs; base += 8 * kStreamThreads) {
+                double a[8], b[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int q = base + u * kStreamThreads + tid;
+                    a[u] = q < lim_e ? srce[q] : 0.0;
+                    b[u] = q < lim_f ? srcf[q] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int q = base + u * kStreamThreads + tid;
+                    if (q < len) {
+                        const int i = q / nrhs, r = q % nrhs;
+                        ce[i * LDR + r] = a[u];
+                        cf[i * LDR + r] = b[u];
+                    }
+                }
+            }
+            // columns past nrhs and rows past TP read as zero in the products
+            for (int q = tid; q < 64 * LDR; q += kStreamThreads) {
+                const int i = q / LDR, r = q % LDR;
+                if (r >= nrhs || i >= S::TP) {
+                    ce[q] = 0.0;
+                    cf[q] = 0.0;
+                }
+            }
+        }
+        __syncthreads();
+        if (t + gridDim.x < ntiles) stream_load<P>(mom, N, t + gridDim.x, v);
+        // lane roles: i = lane % 16 (row of A, column of B), kq = lane / 16 (k within a step)
+        const int i = lane & 15, kq = lane >> 4;
+        const int row = 16 * wave + i;   // output row of this wave's tiles
+        v4d_apply accR[NB], accC[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            accR[b] = v4d_apply{0.0, 0.0, 0.0, 0.0};
+            accC[b] = v4d_apply{0.0, 0.0, 0.0, 0.0};
+        }
+        if (16 * wave < S::TP) {
+            const int ra = row / P, rm = row % P;   // (el, m) for R = M C_f; (fl, n) for Q = M^T C_e
+#pragma unroll 2
+            for (int ks = 0; ks < (S::TP + 3) / 4; ++ks) {
+                const int k = 4 * ks + kq;
+                const int ka = k / P, km = k % P;
+                const bool ok = row < S::TP && k < S::TP;
+                // R: A[row][k] = M[(ra, rm)][(ka, km)];  Q: A[row][k] = M[(ka, km)][(ra, rm)]
+                const double aR = ok ? Kt[(ra * S::T + ka) * S::BLK + rm * S::LDP + km] : 0.0;
+                const double aC = ok ? Kt[(ka * S::T + ra) * S::BLK + km * S::LDP + rm] : 0.0;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (b < nb) {
+                        const double bR = cf[k * LDR + 16 * b + i];
+                        const double bC = ce[k * LDR + 16 * b + i];
+                        accR[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR, bR, accR[b], 0, 0, 0);
+                        accC[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aC, bC, accC[b], 0, 0, 0);
+                    }
+                }
+            }
+            // register u of lane l holds output (16 wave + 4 u + l / 16, 16 b + l % 16); the tile's
+            // partials are stored [output][rhs] (rhs fastest: 16 lanes write 128 contiguous bytes)
+            double* pr = part + t * (int64_t)nout * nrhs;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int r = 16 * b + i;
+                if (b < nb && r < nrhs) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int o = 16 * wave + 4 * u + kq;
+                        if (o < S::TP) {
+                            pr[(int64_t)o * nrhs + r] = accR[b][u];
+                            pr[(int64_t)(S::TP + o) * nrhs + r] = accC[b][u];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int P>
+void launch_mfma_p(hipStream_t st, int N, const double* mom, const double* c, int nrhs, double* part,
+                   int64_t ntiles) {
+    const int64_t grid = std::min<int64_t>(ntiles, 1024);
+    hipLaunchKernelGGL(k_dense_mfma<P>, dim3((unsigned)grid), dim3(kStreamThreads), 0, st, N, mom, c, nrhs, part,
+                       ntiles);
+    FDE_LAUNCH_CHECK();
+}
+
+bool launch_mfma(hipStream_t st, int N, int P, const double* mom, const double* c, int nrhs, double* part,
+                 int64_t ntiles) {
+    switch (P) {
+#define FDE_MFMA_P(p) \
+    case p: launch_mfma_p<p>(st, N, mom, c, nrhs, part, ntiles); return true;
+        FDE_MFMA_P(2) FDE_MFMA_P(3) FDE_MFMA_P(4) FDE_MFMA_P(5) FDE_MFMA_P(6) FDE_MFMA_P(7) FDE_MFMA_P(8)
+        FDE_MFMA_P(9) FDE_MFMA_P(10) FDE_MFMA_P(11) FDE_MFMA_P(12) FDE_MFMA_P(13) FDE_MFMA_P(14) FDE_MFMA_P(15)
+        FDE_MFMA_P(16)
+#undef FDE_MFMA_P
+        default: return false;
+    }
+}
+
 // z = theta (K c) + (1 - theta) (K^T c) from the tile partials: workgroup (I, r) sums, for the TE
 // elements of tile row I, the row partials of tiles (I, J <= I) and the column partials of tiles
 // (I' >= I, I); 16 groups of 64 threads take every 16th tile, then the groups are added in order
@@ -295,6 +462,24 @@ __global__ void __launch_bounds__(kReduceThreads) k_dense_reduce(int N, int P, i
         }
         const int e = I * TE + threadIdx.x / P;
         if (e < N) z[((int64_t)r * N + e) * P + threadIdx.x % P] = theta * ra + (1.0 - theta) * cb;
+    }
+}
+
+// The same sums for the matrix-core partials ([tile][output][rhs], nr right-hand sides of a chunk):
+// workgroup (I, chunk) of 1024 threads, thread (o, r) pairs in 16 groups over the tiles.
+__global__ void __launch_bounds__(256) k_dense_reduce_rhs(int N, int P, int TE, int nT, double theta,
+                                                         const double* __restrict__ part, int64_t ntiles, int nr,
+                                                         int r0, int nrhs, double* __restrict__ z) {
+    const int I = blockIdx.x;
+    const int TP = TE * P, nout = 2 * TP;
+    const int q = blockIdx.y * 256 + threadIdx.x;   // output (o, r) of this tile row and chunk
+    if (q < TP * nr) {
+        const int o = q / nr, r = q % nr;
+        double a = 0.0, b = 0.0;
+        for (int J = 0; J <= I; ++J) a += part[((tri(I) + J) * nout + o) * (int64_t)nr + r];
+        for (int Ip = I; Ip < nT; ++Ip) b += part[((tri(Ip) + I) * nout + TP + o) * (int64_t)nr + r];
+        const int e = I * TE + o / P;
+        if (e < N) z[((int64_t)(r0 + r) * N + e) * P + o % P] = theta * a + (1.0 - theta) * b;
     }
 }
 
@@ -563,20 +748,40 @@ void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int 
         const int TE = dense_tile_elems(P);
         const int nT = ceil_div(N, TE);
         const int64_t ntiles = tri(nT);
-        hipLaunchKernelGGL(k_gather, dim3((unsigned)((nzp + 255) / 256)), dim3(256), 0, st, N, P,
-                           op->d_h.p, Xin, ldx, nrhs, bc0, bcN, c);
+        // many columns: chunks of up to kMfmaRhs on the matrix cores (P <= 16), their coefficients
+        // unknown-major per chunk; otherwise up to kStreamRhs columns per streaming pass (each pass
+        // reads the moments once)
+        const bool mfma = nrhs >= kMfmaMin && P <= 16;
+        const int chunk = mfma ? kMfmaRhs : kStreamRhs;
+        if (mfma)
+            hipLaunchKernelGGL(k_gather_t, dim3((unsigned)((nzp + 255) / 256)), dim3(256), 0, st, N, P, op->d_h.p,
+                               Xin, ldx, nrhs, chunk, bc0, bcN, c);
+        else
+            hipLaunchKernelGGL(k_gather, dim3((unsigned)((nzp + 255) / 256)), dim3(256), 0, st, N, P,
+                               op->d_h.p, Xin, ldx, nrhs, bc0, bcN, c);
         FDE_LAUNCH_CHECK();
-        // up to kStreamRhs columns per streaming pass (each pass reads the moments once)
         if (core_events) FDE_HIP(hipEventRecord(core_events[0], st));
-        for (int r0 = 0; r0 < nrhs; r0 += kStreamRhs) {
-            const int nr = std::min(kStreamRhs, nrhs - r0);
-            if (!launch_stream(st, N, P, op->d_mom.p, c + (int64_t)r0 * N * P, nr,
-                               rest + (int64_t)r0 * ntiles * 2 * TE * P, ntiles))
-                fail(FDE_EUNSUPPORTED, "dense apply: no streaming kernel for P = %d", P);
+        for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+            const int nr = std::min(chunk, nrhs - r0);
+            const double* cr = c + (int64_t)r0 * N * P;
+            double* pr = rest + (int64_t)r0 * ntiles * 2 * TE * P;
+            const bool ok = mfma ? launch_mfma(st, N, P, op->d_mom.p, cr, nr, pr, ntiles)
+                                 : launch_stream(st, N, P, op->d_mom.p, cr, nr, pr, ntiles);
+            if (!ok) fail(FDE_EUNSUPPORTED, "dense apply: no kernel for P = %d", P);
         }
         if (core_events) FDE_HIP(hipEventRecord(core_events[1], st));
-        hipLaunchKernelGGL(k_dense_reduce, dim3((unsigned)nT, (unsigned)nrhs), dim3(kReduceThreads), 0, st, N, P,
-                           TE, nT, op->theta, rest, ntiles, z);
+        if (mfma) {
+            for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+                const int nr = std::min(chunk, nrhs - r0);
+                hipLaunchKernelGGL(k_dense_reduce_rhs, dim3((unsigned)nT, (unsigned)ceil_div(TE * P * nr, 256)),
+                                   dim3(256), 0, st, N, P, TE, nT, op->theta,
+                                   rest + (int64_t)r0 * ntiles * 2 * TE * P, ntiles, nr, r0, nrhs, z);
+                FDE_LAUNCH_CHECK();
+            }
+        } else {
+            hipLaunchKernelGGL(k_dense_reduce, dim3((unsigned)nT, (unsigned)nrhs), dim3(kReduceThreads), 0, st, N,
+                               P, TE, nT, op->theta, rest, ntiles, z);
+        }
         FDE_LAUNCH_CHECK();
     } else {
         const int M = op->L / 2, logM = ilog2(M);

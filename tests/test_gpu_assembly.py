@@ -80,6 +80,29 @@ def test_apply_ragged_sizes_uniform_and_dense(ctx, N, P):
         assert np.abs(Y - ref).max() <= 2e-13 * np.abs(ref).max(), mode
 
 
+@pytest.mark.parametrize("N,P,nrhs", [(40, 8, 8), (37, 5, 13), (33, 16, 64), (29, 6, 70), (50, 3, 9)])
+def test_multi_rhs_dense_apply_matches_oracle(ctx, N, P, nrhs):
+    """Eight or more right-hand sides take the matrix-core apply (chunks of 64; 70 = 64 + 6, the
+    6 on the matrix cores too): every column equals the oracle's dense product and the one-column
+    apply of the same column."""
+    import paper_1808_02937_amd as fde
+    say(f"multi-rhs dense apply N={N} P={P} nrhs={nrhs}")
+    nodes = fi.two_sided_graded_mesh(N, min(6, N // 4), 0.5)
+    sem = SEM(nodes, P, 1.7, 0.4, 0.2)
+    A = sem.system_matrix()
+    X = np.random.default_rng(1000 + nrhs).standard_normal((nrhs, sem.Nd))
+    ref = (A @ X.T).T
+    op = fde.Operator(ctx, nodes, P, 1.7, 0.4, 0.2)
+    assert not op.toeplitz
+    Xt = torch.tensor(X, device="cuda")
+    Y = op.apply(Xt).cpu().numpy()
+    assert np.abs(Y - ref).max() <= 2e-13 * np.abs(ref).max()
+    for j in (0, nrhs // 2, nrhs - 1):
+        y1 = op.apply(Xt[j].contiguous()).cpu().numpy()
+        assert np.abs(Y[j] - y1).max() <= 1e-13 * np.abs(y1).max()
+    op.close()
+
+
 @pytest.mark.parametrize("case", ["small", "graded_theta1_lift", "random_modes"])
 def test_load_vector_matches_oracle(ctx, case):
     import paper_1808_02937_amd as fde
