@@ -275,6 +275,24 @@ int  fde_solve_batched(fde_ctx* ctx, int n, fde_op* const* ops, fde_hlu* const* 
 /* n-point Gauss rule for the weight (1-x)^a (1+x)^b on [-1,1] (host; the
  * library's own generator, used for every rule above). */
 int  fde_gauss_jacobi(int n, double a, double b, double* x_host, double* w_host);
+/* ---- condition-number diagnostics (Section 5's condition-number figures) -- */
+
+#define FDE_SIGMA_A            0   /* B = A                                                    */
+#define FDE_SIGMA_AINV         1   /* B = A^{-1}: each product a FGMRES solve (rtol 1e-13, f)  */
+#define FDE_SIGMA_ATILDE_INV   2   /* B = (L_H U_H)^{-1}: the H-LU solve with f                */
+#define FDE_SIGMA_PRECOND      3   /* B = (L_H U_H)^{-1} A, the preconditioned operator        */
+/* Largest and smallest singular values of the (steps + 1) x steps Hessenberg
+ * matrix of `steps` Arnoldi steps on B from a start vector seeded by `seed`
+ * (device Arnoldi with two Gram-Schmidt passes, device one-sided Jacobi). They
+ * lie in [sigma_min(B), sigma_max(B)] and reach them as the Krylov space fills
+ * (exactly when steps = Nd). Condition numbers follow as
+ * kappa(A) ~ smax(A) smax(A^{-1}), kappa(A~) ~ smax(A) smax(A~^{-1}) when f
+ * factors A~ exactly (tol 1e-13; sigma_max(A~) = sigma_max(A) up to the
+ * H-matrix error), kappa(A~^{-1} A) ~ smax / smin of FDE_SIGMA_PRECOND.
+ * 1 <= steps <= min(64, Nd); f may be NULL for FDE_SIGMA_A. Synchronous. */
+int  fde_sigma_estimate(fde_op* op, fde_hlu* f, int kind, int steps, unsigned long long seed,
+                        double* smax_host, double* smin_host);
+
 /* ---- serving (many problems, many right-hand sides) -------------------- */
 
 /* A problem: the operator of eq. (Model) on nodes[0..N] with degree P. */

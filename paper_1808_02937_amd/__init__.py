@@ -6,4 +6,4 @@ this package only marshals arguments and owns device buffers through PyTorch.
 """
 from ._abi import FDEError, load  # noqa: F401
 from .fde import (Context, HLU, HMatrix, Operator, Server, factor_batched, gauss_jacobi,  # noqa: F401
-                  plan_hlu, solve, solve_batched)
+                  plan_hlu, sigma_estimate, solve, solve_batched)

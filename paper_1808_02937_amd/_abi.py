@@ -20,6 +20,10 @@ FDE_FP64 = 0
 FDE_FP32 = 1
 FDE_FGMRES = 0
 FDE_BICGSTAB = 1
+FDE_SIGMA_A = 0
+FDE_SIGMA_AINV = 1
+FDE_SIGMA_ATILDE_INV = 2
+FDE_SIGMA_PRECOND = 3
 FDE_APPLY_AUTO = 0
 FDE_APPLY_DENSE = 1
 FDE_APPLY_TOEPLITZ = 2
@@ -107,6 +111,7 @@ SIGNATURES = {
     "fde_server_poll": (i32, [vp, C.c_longlong, ip, C.POINTER(SolveInfo), ip]),
     "fde_server_stats": (i32, [vp, ip, C.POINTER(sz), C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
                                C.POINTER(C.c_longlong)]),
+    "fde_sigma_estimate": (i32, [vp, vp, i32, i32, C.c_ulonglong, dp, dp]),
     "fde_gauss_jacobi": (i32, [i32, f64, f64, dp, dp]),
     "fde_last_error": (C.c_char_p, []),
     "fde_version": (C.c_char_p, []),

@@ -680,6 +680,94 @@ void engine_step(KrylovEngine* e, std::vector<EngineDone>& done) {
     }
 }
 
+// ------------------------------------------------------------------ singular value estimates
+//
+// m steps of Arnoldi (classical Gram-Schmidt twice, the FGMRES kernels) on an operator B from a
+// seeded start vector; the singular values of the resulting (m+1) x m Hessenberg matrix bound
+// those of B from inside [sigma_min(B), sigma_max(B)] and reach them as the Krylov space fills
+// (exactly once m = Nd). B is one of: A; A^{-1} (each product a right-preconditioned FGMRES solve
+// to 1e-13 with the given H-LU); A~^{-1} as the H-LU solve (exact when the factors are); A~^{-1} A.
+void sigma_estimate(Op* op, HLUObj* f, int kind, int m, const double* v0_host, double* smax, double* smin) {
+    Ctx* c = op->ctx;
+    hipStream_t st = c->stream;
+    const int Nd = op->Nd;
+    if (m < 1 || m > kMaxRestart || m > Nd) fail(FDE_EINVAL, "steps must be in [1, min(%d, Nd)]", kMaxRestart);
+    if (kind != FDE_SIGMA_A && !f) fail(FDE_EINVAL, "this estimate needs the H-LU factors");
+    if (f && f->op != op) fail(FDE_EINVAL, "factors built for another operator");
+    DevBuf<double> V, Z, W, R, G, X;
+    V.alloc(c, (int64_t)(m + 1) * Nd);
+    Z.alloc(c, (int64_t)m * Nd);
+    W.alloc(c, Nd);
+    R.alloc(c, Nd);
+    G.alloc(c, Nd);
+    X.alloc(c, Nd);
+    FDE_HIP(hipMemsetAsync(V.p, 0, V.bytes(), st));
+    FDE_HIP(hipMemsetAsync(R.p, 0, R.bytes(), st));
+    upload(c, G.p, v0_host, sizeof(double) * Nd);
+    SysDev d{};
+    d.V = V.p;
+    d.Z = Z.p;
+    d.W = W.p;
+    d.R = R.p;
+    d.G = G.p;
+    d.X = X.p;
+    d.bs = Nd;
+    d.Nd = Nd;
+    d.c = 0;
+    DevBuf<SysDev> d_sys;
+    DevBuf<SysState> d_ss;
+    DevBuf<double> d_out;
+    d_sys.alloc(c, 1);
+    d_ss.alloc(c, 1);
+    d_out.alloc(c, 2);
+    upload(c, d_sys.p, &d, sizeof d);
+    fg_gnorm(st, 1, d_sys.p, d_ss.p);
+    fg_cycle_start(st, 1, d_sys.p, d_ss.p, 1, m + 1);   // v_0 = G / |G|
+    const size_t need = op->apply_ws_doubles(1);
+    if (op->ws.n < need) op->ws.alloc(c, need);
+    DevBuf<double> T;
+    T.alloc(c, Nd);
+    fde_solve_params sp{FDE_FGMRES, 30, 1000, 1e-13};
+    for (int j = 0; j < m; ++j) {
+        double* vj = V.p + (int64_t)j * Nd;
+        switch (kind) {
+            case FDE_SIGMA_A:
+                stiffness_apply(op, 1, vj, Nd, W.p, Nd, 0.0, 0.0, false);
+                break;
+            case FDE_SIGMA_AINV: {
+                fde_op* ops[1] = {static_cast<fde_op*>(op)};
+                fde_hlu* precs[1] = {static_cast<fde_hlu*>(f)};
+                int nr = 1, ld = Nd;
+                const double* Gs[1] = {vj};
+                double* Xs[1] = {W.p};
+                fde_solve_info info{};
+                int rc = FDE_OK;
+                run(c, 1, ops, precs, &nr, Gs, &ld, Xs, &ld, &sp, &info, &rc);
+                if (rc != FDE_OK) fail(rc, "sigma estimate: an inner solve did not converge");
+                break;
+            }
+            case FDE_SIGMA_ATILDE_INV:
+                hlu_solve(f, 1, vj, Nd, W.p, Nd);
+                break;
+            case FDE_SIGMA_PRECOND:
+                stiffness_apply(op, 1, vj, Nd, T.p, Nd, 0.0, 0.0, false);
+                hlu_solve(f, 1, T.p, Nd, W.p, Nd);
+                break;
+            default:
+                fail(FDE_EINVAL, "unknown estimate kind %d", kind);
+        }
+        // rtol < 0: no residual test (on a well-conditioned operator the GMRES residual estimate
+        // can reach zero long before the space is full)
+        fg_arnoldi(st, 1, d_sys.p, d_ss.p, j, m, -1.0, m + 1);
+    }
+    fg_sigma(st, d_ss.p, m, d_out.p);
+    double out[2];
+    FDE_HIP(hipMemcpyAsync(out, d_out.p, sizeof out, hipMemcpyDeviceToHost, st));
+    FDE_HIP(hipStreamSynchronize(st));
+    *smax = out[0];
+    *smin = out[1];
+}
+
 }  // namespace fde
 
 using namespace fde;
@@ -706,6 +794,25 @@ int fde_solve(fde_op* op, fde_hlu* prec, int nrhs, const double* G, int ldg, dou
     if (rc == FDE_ENOCONV) set_error("the Krylov solver did not reach rtol within maxit for at least one right-hand side");
     if (rc == FDE_EBREAKDOWN) set_error("BiCGSTAB broke down (a vanishing inner product) for at least one right-hand side");
     return rc;
+}
+
+int fde_sigma_estimate(fde_op* op, fde_hlu* f, int kind, int steps, unsigned long long seed, double* smax,
+                       double* smin) {
+    FDE_API_BEGIN
+    if (!op || !smax || !smin) fail(FDE_EINVAL, "null argument");
+    // a seeded start vector with entries uniform in [-1, 1) (splitmix64), the same on every device
+    std::vector<double> v0(op->Nd);
+    unsigned long long x = seed;
+    for (double& v : v0) {
+        x += 0x9E3779B97F4A7C15ull;
+        unsigned long long z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        v = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+    sigma_estimate(op, f, kind, steps, v0.data(), smax, smin);
+    FDE_API_END
 }
 
 int fde_solve_batched(fde_ctx* ctx, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nrhs,

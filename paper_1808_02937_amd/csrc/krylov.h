@@ -44,5 +44,7 @@ struct SysStatus {   // what the host reads of a system after a step
     int active, conv, status, iters, jend, pad;
 };
 void fg_gather_status(hipStream_t st, int n, const SysState* ss, const int* sel, SysStatus* out);
+// largest and smallest singular value of the m x m triangle left in ss[0] by m Arnoldi steps (device)
+void fg_sigma(hipStream_t st, const SysState* ss, int m, double* out);
 
 }  // namespace fde

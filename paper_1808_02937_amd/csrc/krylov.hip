@@ -260,7 +260,93 @@ __global__ void k_gather_status(const SysState* __restrict__ ss, const int* __re
     out[i] = SysStatus{s.relres, s.active, s.conv, s.status, s.iters, s.jend, 0};
 }
 
+// Singular values of the m x m upper triangular R that the Arnoldi process of system 0 left in
+// its Hessenberg storage (Givens-rotated, so R has the singular values of the (m+1) x m
+// Hessenberg matrix): one-sided Jacobi on the columns of R in LDS, one 1024-thread workgroup,
+// pairs of columns in 32 groups of 32 threads. out[0] = largest, out[1] = smallest.
+__global__ void __launch_bounds__(kT) k_sigma_jacobi(const SysState* __restrict__ ss, int m, double* __restrict__ out) {
+    __shared__ double Rm[kMaxRestart][kMaxRestart + 1];   // column c in Rm[c][.]
+    __shared__ int flag;
+    const SysState& s = ss[0];
+    if (s.jend > 0 && s.jend < m) m = s.jend;   // the Krylov space was exhausted early
+    for (int q = threadIdx.x; q < kMaxRestart * kMaxRestart; q += kT) {
+        const int c = q / kMaxRestart, r = q % kMaxRestart;
+        Rm[c][r] = (c < m && r <= c) ? s.H[r + c * (kMaxRestart + 1)] : 0.0;
+    }
+    __syncthreads();
+    const int n2 = m + (m & 1), npairs = n2 / 2;
+    const int grp = threadIdx.x / 32, gl = threadIdx.x % 32;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (threadIdx.x == 0) flag = 0;
+        __syncthreads();
+        for (int round = 0; round < n2 - 1; ++round) {
+            if (grp < npairs) {
+                int p, q;
+                if (grp == 0) {
+                    p = round;
+                    q = n2 - 1;
+                } else {
+                    p = (round + grp) % (n2 - 1);
+                    q = (round - grp + n2 - 1) % (n2 - 1);
+                }
+                if (p < m && q < m) {
+                    double a = 0.0, b = 0.0, g = 0.0;
+                    for (int r = gl; r < m; r += 32) {
+                        const double x = Rm[p][r], y = Rm[q][r];
+                        a += x * x;
+                        b += y * y;
+                        g += x * y;
+                    }
+                    for (int o = 16; o > 0; o >>= 1) {
+                        a += __shfl_xor(a, o, 32);
+                        b += __shfl_xor(b, o, 32);
+                        g += __shfl_xor(g, o, 32);
+                    }
+                    if (g != 0.0 && fabs(g) > 1e-15 * sqrt(a * b)) {
+                        const double zeta = (b - a) / (2.0 * g);
+                        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                        for (int r = gl; r < m; r += 32) {
+                            const double x = Rm[p][r], y = Rm[q][r];
+                            Rm[p][r] = cs * x - sn * y;
+                            Rm[q][r] = sn * x + cs * y;
+                        }
+                        if (gl == 0) flag = 1;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        const int rot = flag;
+        __syncthreads();
+        if (!rot) break;
+    }
+    if (threadIdx.x < 32) {
+        double mx = 0.0, mn = 1e300;
+        for (int c = threadIdx.x; c < m; c += 32) {
+            double nn = 0.0;
+            for (int r = 0; r < m; ++r) nn += Rm[c][r] * Rm[c][r];
+            const double sv = sqrt(nn);
+            mx = fmax(mx, sv);
+            mn = fmin(mn, sv);
+        }
+        for (int o = 16; o > 0; o >>= 1) {
+            mx = fmax(mx, __shfl_xor(mx, o, 32));
+            mn = fmin(mn, __shfl_xor(mn, o, 32));
+        }
+        if (threadIdx.x == 0) {
+            out[0] = mx;
+            out[1] = mn;
+        }
+    }
+}
+
 }  // namespace
+
+void fg_sigma(hipStream_t st, const SysState* ss, int m, double* out) {
+    hipLaunchKernelGGL(k_sigma_jacobi, dim3(1), dim3(kT), 0, st, ss, m, out);
+    FDE_LAUNCH_CHECK();
+}
 
 void fg_gnorm(hipStream_t st, int ns, const SysDev* sys, SysState* ss, const int* sel) {
     hipLaunchKernelGGL(k_gnorm, dim3(ns), dim3(kT), 0, st, sys, ss, sel);

@@ -291,6 +291,18 @@ def factor_batched(hms: Sequence[HMatrix], tol: float = 1e-3, rank_cap: int = 0,
 
 
 _METHODS = {"fgmres": A.FDE_FGMRES, "bicgstab": A.FDE_BICGSTAB}
+_SIGMA = {"A": A.FDE_SIGMA_A, "Ainv": A.FDE_SIGMA_AINV, "Atilde_inv": A.FDE_SIGMA_ATILDE_INV,
+          "precond": A.FDE_SIGMA_PRECOND}
+
+
+def sigma_estimate(op: "Operator", kind: str, lu: Optional["HLU"] = None, steps: int = 64, seed: int = 1808029370):
+    """(largest, smallest) singular value of the Arnoldi Hessenberg matrix of B after `steps` steps:
+    B = A ("A"), A^{-1} ("Ainv"), the H-LU solve ("Atilde_inv"), or the preconditioned operator
+    ("precond")."""
+    smax, smin = C.c_double(), C.c_double()
+    check(load().fde_sigma_estimate(op.h, lu.h if lu is not None else None, _SIGMA[kind], int(steps), int(seed),
+                                    C.byref(smax), C.byref(smin)))
+    return smax.value, smin.value
 
 
 def _solve_params(rtol, restart, maxit, method="fgmres"):
