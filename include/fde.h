@@ -51,6 +51,8 @@ extern "C" {
 /* precision of the H-LU factors and H-solves */
 #define FDE_FP64          0   /* everything in FP64 (the plain FP64 path) */
 #define FDE_FP32          1   /* H-LU factors and H-solves in FP32 */
+#define FDE_FP32_BF16UV   2   /* FP32 H-LU; afterwards the low-rank factors U, V are kept in BF16 only
+                                 (dense blocks FP32) and the H-solves widen them to FP32 */
 
 /* Krylov method */
 #define FDE_FGMRES        0   /* right-preconditioned flexible GMRES(restart) */
@@ -77,7 +79,7 @@ typedef struct { int R; double lambda; int leaf_elems; } fde_hparams;
 
 /* H-LU parameters (Section 4.1): after every low-rank sum the block is
  * recompressed to the singular values above tol * sigma_1, at most rank_cap
- * (<= 0: R) of them. precision: FDE_FP64 or FDE_FP32. pivot_floor: a leaf
+ * (<= 0: R) of them. precision: FDE_FP64, FDE_FP32 or FDE_FP32_BF16UV. pivot_floor: a leaf
  * pivot of magnitude <= pivot_floor * max|leaf| is a breakdown. */
 typedef struct { double tol; int rank_cap; int precision; double pivot_floor; } fde_hlu_params;
 

@@ -18,6 +18,7 @@ FDE_EDEVICE = -5
 FDE_EUNSUPPORTED = -6
 FDE_FP64 = 0
 FDE_FP32 = 1
+FDE_FP32_BF16UV = 2
 FDE_FGMRES = 0
 FDE_BICGSTAB = 1
 FDE_SIGMA_A = 0

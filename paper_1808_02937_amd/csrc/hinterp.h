@@ -33,6 +33,8 @@ struct Inst {
     int hs_nleaf, hs_tslots;
     int hs_wc;                // leaf-step H-solve: columns per workgroup (1, 2, 4 or 8)
     const T* hs_prep;         // leaf-step H-solve: 2 * hs_nleaf solve-ready diagonal leaves (kHsPrepStride each)
+    const unsigned short* lr16;   // BF16 low-rank factors (bits), or nullptr: factor offsets >= lr_base
+    int64_t lr_base;              // are read from lr16 + (offset - lr_base) (the U, V tail of the arena)
     double tol;
     int kmax;
     double pivot_floor;
@@ -58,11 +60,15 @@ void launch_interp_one(hipStream_t st, const Inst<T>& d);
 // the solve-ready diagonal leaves of every leaf step (2 * nleaf of them) from the factors
 template <class T>
 void launch_hs_prepare(hipStream_t st, const T* arena, const HsStep* steps, int nleaf, T* prep);
+// bf16: some instance reads BF16 low-rank factors (FP32 only)
 template <class T>
 void launch_hsolve(hipStream_t st, int ninst, int nchunk, int wc, const Inst<T>* d_insts, int step,
-                   size_t lds_bytes);
+                   size_t lds_bytes, bool bf16 = false);
 template <class T>
-void launch_hsolve_one(hipStream_t st, const Inst<T>& d, int nchunk, int wc, size_t lds_bytes);
+void launch_hsolve_one(hipStream_t st, const Inst<T>& d, int nchunk, int wc, size_t lds_bytes, bool bf16 = false);
+// dst[i] = src[i] rounded to BF16 (nearest, ties to even), and back to FP32
+void launch_to_bf16(hipStream_t st, const float* src, int64_t n, unsigned short* dst);
+void launch_from_bf16(hipStream_t st, const unsigned short* src, int64_t n, float* dst);
 // LDS bytes of one workgroup of the leaf-step H-solve for wc columns
 size_t hsolve_lds_bytes(int Nd, int tslots, int kmax, int nslots, int wc, size_t esz);
 constexpr int kHsolveMaxRow = 64;   // leaf-step H-solve: leaves of at most this many rows

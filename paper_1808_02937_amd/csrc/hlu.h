@@ -41,7 +41,10 @@ struct HLUObj {
     Op* op = nullptr;
     std::shared_ptr<const Plan> plan;
     const HTree& t() const { return plan->t; }
-    int prec = FDE_FP32;
+    int prec = FDE_FP32;          // arithmetic of the factorisation and the H-solves (FP32 or FP64)
+    bool bf16uv = false;          // FDE_FP32_BF16UV: after the factorisation U, V are kept in BF16 only
+    DevBuf<char> lr16;            // the BF16 U, V (the arena's tail from lr_base; the arena keeps the head)
+    int64_t lr_base = 0;
     double tol = 1e-3, pivot_floor = 0.0;
     int kmax = 8;
     size_t esz = 4;               // bytes per factor element
@@ -88,6 +91,8 @@ struct HLUObj {
         d.prof = prof.p;
         d.flops = flops.p + (solve ? 1 : 0);
         d.op_flops = solve ? nullptr : lu_flops.p;
+        d.lr16 = bf16uv ? reinterpret_cast<const unsigned short*>(lr16.p) : nullptr;
+        d.lr_base = lr_base;
         return d;
     }
 };
@@ -101,4 +106,6 @@ void hlu_prepare_solve(HLUObj* f, int nrhs);
 void hlu_solve(HLUObj* f, int nrhs, const double* B, int ldb, double* X, int ldx);
 // columns per workgroup of the LDS H-solve for these factors and nrhs columns (0: does not fit)
 int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes);
+// FDE_EUNSUPPORTED when f keeps BF16 low-rank factors and the LDS H-solve does not fit (wc == 0)
+void require_lds_for_bf16(const HLUObj* f, int wc);
 }  // namespace fde

@@ -359,7 +359,10 @@ void factor_prepare(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
     f->prec = prm ? prm->precision : FDE_FP32;
     f->pivot_floor = prm ? prm->pivot_floor : 1e-14;
     if (!(f->tol >= 0.0) || !std::isfinite(f->tol)) fail(FDE_EINVAL, "tol must be >= 0");
-    if (f->prec != FDE_FP32 && f->prec != FDE_FP64) fail(FDE_EINVAL, "precision must be FDE_FP32 or FDE_FP64");
+    if (f->prec != FDE_FP32 && f->prec != FDE_FP64 && f->prec != FDE_FP32_BF16UV)
+        fail(FDE_EINVAL, "precision must be FDE_FP32, FDE_FP64 or FDE_FP32_BF16UV");
+    f->bf16uv = f->prec == FDE_FP32_BF16UV;
+    if (f->bf16uv) f->prec = FDE_FP32;   // the factorisation itself runs in FP32
     if (!(f->pivot_floor >= 0.0)) fail(FDE_EINVAL, "pivot_floor must be >= 0");
     f->kmax = rank_capacity(hm->t, prm);
     f->esz = f->prec == FDE_FP64 ? 8 : 4;
@@ -419,6 +422,28 @@ void factor_prepare(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
                                       reinterpret_cast<float*>(f->arena.p));
 }
 
+// FDE_FP32_BF16UV: the low-rank factors (the arena's tail, from the first U on) rounded to BF16;
+// the FP32 arena keeps the dense head only. Called once the factorisation and the solve-ready
+// leaves are queued.
+void keep_uv_in_bf16(HLUObj* f) {
+    if (!f->bf16uv) return;
+    Ctx* c = f->op->ctx;
+    const HTree& t = f->t();
+    int64_t base = t.arena_elems;
+    for (int b : t.lr_blocks) base = std::min<int64_t>(base, t.bl[b].uoff);
+    const int64_t n = t.arena_elems - base;
+    f->lr_base = base;
+    f->lr16.alloc(c, std::max<int64_t>(n, 1) * sizeof(unsigned short));
+    launch_to_bf16(c->stream, reinterpret_cast<const float*>(f->arena.p) + base, n,
+                   reinterpret_cast<unsigned short*>(f->lr16.p));
+    DevBuf<char> head;
+    head.alloc(c, std::max<int64_t>(base, 1) * sizeof(float));
+    if (base > 0) FDE_HIP(hipMemcpyAsync(head.p, f->arena.p, base * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    std::swap(f->arena.p, head.p);
+    std::swap(f->arena.n, head.n);
+    // head now holds the full FP32 arena; it goes back to the stream-ordered cache
+}
+
 void factor(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
     factor_prepare(f, hm, prm);
     std::vector<HLUObj*> one{f};
@@ -426,6 +451,7 @@ void factor(HLUObj* f, fde_hmat* hm, const fde_hlu_params* prm) {
         factor_batch_run<double>(f->op->ctx, one, "H-LU");
     else
         factor_batch_run<float>(f->op->ctx, one, "H-LU");
+    keep_uv_in_bf16(f);
 }
 
 // cache key: everything the programs depend on -- the mesh and the H-matrix and rank parameters
@@ -518,6 +544,13 @@ void hlu_prepare_solve(HLUObj* f, int nrhs) {
     }
 }
 
+// solves on factors whose U, V are BF16 need the LDS H-solve (the op-list interpreter reads FP32)
+void require_lds_for_bf16(const HLUObj* f, int wc) {
+    if (f->bf16uv && wc == 0)
+        fail(FDE_EUNSUPPORTED, "BF16 low-rank factors: the right-hand sides (Nd = %d) do not fit the LDS H-solve",
+             f->op->Nd);
+}
+
 int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes) {
     if (!f->plan->sv_lds || nrhs <= 0) return 0;
     if (!c->lds_limit) c->lds_limit = device_lds_limit(c->device);
@@ -537,6 +570,7 @@ void hlu_solve(HLUObj* f, int nrhs, const double* B, int ldb, double* X, int ldx
     hipStream_t st = c->stream;
     size_t lds = 0;
     const int wc = hsolve_cols(c, f, nrhs, &lds);
+    require_lds_for_bf16(f, wc);
     if (wc > 0) {
         // right-hand sides in LDS, one workgroup per chunk of wc columns
         const int nchunk = (nrhs + wc - 1) / wc;
@@ -547,7 +581,7 @@ void hlu_solve(HLUObj* f, int nrhs, const double* B, int ldb, double* X, int ldx
         } else {
             Inst<float> d = f->inst<float>(true, nrhs, B, ldb, X, ldx);
             d.hs_wc = wc;
-            launch_hsolve_one<float>(st, d, nchunk, wc, lds);
+            launch_hsolve_one<float>(st, d, nchunk, wc, lds, f->bf16uv);
         }
         return;
     }
@@ -676,6 +710,7 @@ int fde_hlu_factor_batched(int n, fde_hmat* const* hms, const fde_hlu_params* pr
         for (HLUObj* f : fs) (f->prec == FDE_FP64 ? f64 : f32).push_back(f);
         if (!f32.empty()) factor_batch_run<float>(c, f32, "H-LU (batched)");
         if (!f64.empty()) factor_batch_run<double>(c, f64, "H-LU (batched)");
+        for (HLUObj* f : fs) keep_uv_in_bf16(f);
     } catch (...) {
         for (HLUObj* f : fs) delete static_cast<fde_hlu*>(f);
         throw;
@@ -703,12 +738,22 @@ int fde_hlu_to_dense(fde_hlu* f, double* out, int ld, int* h2p) {
     std::vector<LeafDev> lv = leaf_table(f->t());
     DevBuf<LeafDev> d_lv;
     upload_vec(c, d_lv, lv);
-    if (f->prec == FDE_FP64)
+    if (f->prec == FDE_FP64) {
         launch_to_dense<double>(c->stream, (int)lv.size(), d_lv.p, reinterpret_cast<double*>(f->arena.p), f->ranks.p,
                                 nullptr, out, ld);
-    else
+    } else if (f->bf16uv) {   // the FP32 head and the BF16 tail widened into a full FP32 arena
+        DevBuf<float> full;
+        full.alloc(c, std::max<int64_t>(f->t().arena_elems, 1));
+        if (f->lr_base > 0)
+            FDE_HIP(hipMemcpyAsync(full.p, f->arena.p, f->lr_base * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        launch_from_bf16(c->stream, reinterpret_cast<const unsigned short*>(f->lr16.p),
+                         f->t().arena_elems - f->lr_base, full.p + f->lr_base);
+        launch_to_dense<float>(c->stream, (int)lv.size(), d_lv.p, full.p, f->ranks.p, nullptr, out, ld);
+        FDE_HIP(hipStreamSynchronize(c->stream));
+    } else {
         launch_to_dense<float>(c->stream, (int)lv.size(), d_lv.p, reinterpret_cast<float*>(f->arena.p), f->ranks.p,
                                nullptr, out, ld);
+    }
     FDE_HIP(hipStreamSynchronize(c->stream));
     if (h2p) std::memcpy(h2p, f->t().h2p.data(), f->t().h2p.size() * sizeof(int));
     FDE_API_END

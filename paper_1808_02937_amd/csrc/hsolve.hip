@@ -21,6 +21,8 @@
 // next step, its diagonal leaf and step records two steps ahead are loaded while a
 // step runs, as global (vector-memory) loads issued identically by every wavefront,
 // so the compiler's waits for them are exact and they stay in flight across barriers.
+#include <algorithm>
+
 #include "hinterp.h"
 #include "tri_wave.h"
 
@@ -147,12 +149,31 @@ __device__ inline RecS rec_lane(const Vec8& v, int k) {
     return r;
 }
 
-// kHsChunk columns of a block at `off` (ld), row = lane, rows and columns clamped
-template <class T>
-__device__ inline void load_block(T (&v)[kHsChunk], const T* arena, int64_t off, int ld, int rows, int cols, int c0,
-                                  int lane) {
+// where the factors are: the arena, and (BF) BF16 copies of the low-rank factors from lr_base on
+template <class T, bool BF>
+struct FacSrc {
+    const T* arena;
+    const unsigned short* lr16;
+    int64_t lr_base;
+};
+
+__device__ inline float bf16_bits_to_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+// kHsChunk columns of a block at `off` (ld), row = lane, rows and columns clamped; a low-rank
+// block of BF16 factors is widened to FP32 (the block is wave-uniform, so is the branch)
+template <class T, bool BF>
+__device__ inline void load_block(T (&v)[kHsChunk], const FacSrc<T, BF>& f, int64_t off, int ld, int rows, int cols,
+                                  int c0, int lane) {
     const int li = min(lane, rows - 1), cl = max(cols, 1) - 1;
-    const auto a = gmem(arena + off + li);
+    if constexpr (BF) {
+        if (f.lr16 && off >= f.lr_base) {
+            const auto a = gmem(f.lr16 + (off - f.lr_base) + li);
+#pragma unroll
+            for (int c = 0; c < kHsChunk; ++c) v[c] = (T)bf16_bits_to_float(a[(int64_t)min(c0 + c, cl) * ld]);
+            return;
+        }
+    }
+    const auto a = gmem(f.arena + off + li);
 #pragma unroll
     for (int c = 0; c < kHsChunk; ++c) v[c] = a[(int64_t)min(c0 + c, cl) * ld];
 }
@@ -162,7 +183,7 @@ __device__ inline void load_block(T (&v)[kHsChunk], const T* arena, int64_t off,
 // role and the number of items (empty slots load a valid dummy address), so the waits the
 // compiler inserts for prefetched values are exact and the prefetches stay in flight across
 // the barriers.
-template <class T, int WC>
+template <class T, int WC, bool BF>
 __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int chunk, int step, char* smem) {
     using D = HsDepth<T, WC>;
     const int wc = d.hs_wc;
@@ -185,7 +206,7 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
     const int h0 = wc < kHW ? wc : 0, nh = kHW - h0;
     const bool helper = wave >= h0;
     const int hw = helper ? wave - h0 : 0;
-    const T* arena = d.arena;
+    const FacSrc<T, BF> arena{d.arena, d.lr16, d.lr_base};
     const HsStep* steps = d.hs_steps;
     const HsRec* recs = d.hs_recs;
     for (int s = threadIdx.x; s < d.nslots; s += kHT) rk[s] = d.ranks[s];
@@ -552,18 +573,33 @@ __global__ void __launch_bounds__(256) k_hs_prepare(const T* __restrict__ arena,
         P[kHsolveMaxRow * kHsolveMaxRow + i] = (fwd || i >= n) ? T(1) : T(1) / D[i + (int64_t)i * n];
 }
 
-template <class T, int WC>
+template <class T, int WC, bool BF>
 __global__ void __launch_bounds__(kHT) k_hsolve(const Inst<T>* __restrict__ insts, int nchunk, int step) {
     extern __shared__ __align__(16) char smem[];
     const int i = blockIdx.x / nchunk, c = blockIdx.x % nchunk;
     const Inst<T> d = insts[i];
-    hsteps_body<T, WC>(d, c, step, smem);
+    hsteps_body<T, WC, BF>(d, c, step, smem);
 }
 
-template <class T, int WC>
+template <class T, int WC, bool BF>
 __global__ void __launch_bounds__(kHT) k_hsolve_one(const Inst<T> d) {
     extern __shared__ __align__(16) char smem[];
-    hsteps_body<T, WC>(d, blockIdx.x, 0, smem);
+    hsteps_body<T, WC, BF>(d, blockIdx.x, 0, smem);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ src, int64_t n, unsigned short* __restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned u = __float_as_uint(src[i]);
+        // round to nearest, ties to even, on the upper 16 bits; NaN stays a (quiet) NaN
+        const bool nan = (u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu);
+        const unsigned r = nan ? (u | 0x00400000u) : u + 0x7fffu + ((u >> 16) & 1u);
+        dst[i] = (unsigned short)(r >> 16);
+    }
+}
+
+__global__ void k_from_bf16(const unsigned short* __restrict__ src, int64_t n, float* __restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = bf16_bits_to_float(src[i]);
 }
 
 template <class K>
@@ -588,18 +624,45 @@ size_t device_lds_limit(int device) {
 
 namespace {
 
-template <class T, int WC>
+template <class T, int WC, bool BF>
 void launch_hsolve_wc(hipStream_t st, int ninst, int nchunk, const Inst<T>* d_insts, int step, size_t lds) {
-    allow_lds(k_hsolve<T, WC>, lds);
-    hipLaunchKernelGGL((k_hsolve<T, WC>), dim3(ninst * nchunk), dim3(kHT), lds, st, d_insts, nchunk, step);
+    allow_lds(k_hsolve<T, WC, BF>, lds);
+    hipLaunchKernelGGL((k_hsolve<T, WC, BF>), dim3(ninst * nchunk), dim3(kHT), lds, st, d_insts, nchunk, step);
+    FDE_LAUNCH_CHECK();
+}
+
+template <class T, int WC, bool BF>
+void launch_hsolve_one_wc(hipStream_t st, const Inst<T>& d, int nchunk, size_t lds) {
+    allow_lds(k_hsolve_one<T, WC, BF>, lds);
+    hipLaunchKernelGGL((k_hsolve_one<T, WC, BF>), dim3(nchunk), dim3(kHT), lds, st, d);
     FDE_LAUNCH_CHECK();
 }
 
 template <class T, int WC>
-void launch_hsolve_one_wc(hipStream_t st, const Inst<T>& d, int nchunk, size_t lds) {
-    allow_lds(k_hsolve_one<T, WC>, lds);
-    hipLaunchKernelGGL((k_hsolve_one<T, WC>), dim3(nchunk), dim3(kHT), lds, st, d);
-    FDE_LAUNCH_CHECK();
+void launch_hsolve_wc_bf(hipStream_t st, int ninst, int nchunk, const Inst<T>* d_insts, int step, size_t lds,
+                         bool bf16) {
+    if constexpr (sizeof(T) == 4) {
+        if (bf16) {
+            launch_hsolve_wc<T, WC, true>(st, ninst, nchunk, d_insts, step, lds);
+            return;
+        }
+    } else {
+        if (bf16) fail(FDE_EINVAL, "BF16 low-rank factors come with FP32 factorisations only");
+    }
+    launch_hsolve_wc<T, WC, false>(st, ninst, nchunk, d_insts, step, lds);
+}
+
+template <class T, int WC>
+void launch_hsolve_one_wc_bf(hipStream_t st, const Inst<T>& d, int nchunk, size_t lds, bool bf16) {
+    if constexpr (sizeof(T) == 4) {
+        if (bf16) {
+            launch_hsolve_one_wc<T, WC, true>(st, d, nchunk, lds);
+            return;
+        }
+    } else {
+        if (bf16) fail(FDE_EINVAL, "BF16 low-rank factors come with FP32 factorisations only");
+    }
+    launch_hsolve_one_wc<T, WC, false>(st, d, nchunk, lds);
 }
 
 }  // namespace
@@ -614,31 +677,46 @@ template void launch_hs_prepare<float>(hipStream_t, const float*, const HsStep*,
 template void launch_hs_prepare<double>(hipStream_t, const double*, const HsStep*, int, double*);
 
 template <class T>
-void launch_hsolve(hipStream_t st, int ninst, int nchunk, int wc, const Inst<T>* d_insts, int step, size_t lds) {
+void launch_hsolve(hipStream_t st, int ninst, int nchunk, int wc, const Inst<T>* d_insts, int step, size_t lds,
+                   bool bf16) {
     if (ninst <= 0 || nchunk <= 0) return;
     switch (wc) {
-        case 1: launch_hsolve_wc<T, 1>(st, ninst, nchunk, d_insts, step, lds); break;
-        case 2: launch_hsolve_wc<T, 2>(st, ninst, nchunk, d_insts, step, lds); break;
-        case 4: launch_hsolve_wc<T, 4>(st, ninst, nchunk, d_insts, step, lds); break;
-        case 8: launch_hsolve_wc<T, 8>(st, ninst, nchunk, d_insts, step, lds); break;
+        case 1: launch_hsolve_wc_bf<T, 1>(st, ninst, nchunk, d_insts, step, lds, bf16); break;
+        case 2: launch_hsolve_wc_bf<T, 2>(st, ninst, nchunk, d_insts, step, lds, bf16); break;
+        case 4: launch_hsolve_wc_bf<T, 4>(st, ninst, nchunk, d_insts, step, lds, bf16); break;
+        case 8: launch_hsolve_wc_bf<T, 8>(st, ninst, nchunk, d_insts, step, lds, bf16); break;
         default: fail(FDE_EDEVICE, "H-solve chunk width %d is not 1, 2, 4 or 8", wc);
     }
 }
-template void launch_hsolve<float>(hipStream_t, int, int, int, const Inst<float>*, int, size_t);
-template void launch_hsolve<double>(hipStream_t, int, int, int, const Inst<double>*, int, size_t);
+template void launch_hsolve<float>(hipStream_t, int, int, int, const Inst<float>*, int, size_t, bool);
+template void launch_hsolve<double>(hipStream_t, int, int, int, const Inst<double>*, int, size_t, bool);
 
 template <class T>
-void launch_hsolve_one(hipStream_t st, const Inst<T>& d, int nchunk, int wc, size_t lds) {
+void launch_hsolve_one(hipStream_t st, const Inst<T>& d, int nchunk, int wc, size_t lds, bool bf16) {
     if (nchunk <= 0) return;
     switch (wc) {
-        case 1: launch_hsolve_one_wc<T, 1>(st, d, nchunk, lds); break;
-        case 2: launch_hsolve_one_wc<T, 2>(st, d, nchunk, lds); break;
-        case 4: launch_hsolve_one_wc<T, 4>(st, d, nchunk, lds); break;
-        case 8: launch_hsolve_one_wc<T, 8>(st, d, nchunk, lds); break;
+        case 1: launch_hsolve_one_wc_bf<T, 1>(st, d, nchunk, lds, bf16); break;
+        case 2: launch_hsolve_one_wc_bf<T, 2>(st, d, nchunk, lds, bf16); break;
+        case 4: launch_hsolve_one_wc_bf<T, 4>(st, d, nchunk, lds, bf16); break;
+        case 8: launch_hsolve_one_wc_bf<T, 8>(st, d, nchunk, lds, bf16); break;
         default: fail(FDE_EDEVICE, "H-solve chunk width %d is not 1, 2, 4 or 8", wc);
     }
 }
-template void launch_hsolve_one<float>(hipStream_t, const Inst<float>&, int, int, size_t);
-template void launch_hsolve_one<double>(hipStream_t, const Inst<double>&, int, int, size_t);
+template void launch_hsolve_one<float>(hipStream_t, const Inst<float>&, int, int, size_t, bool);
+template void launch_hsolve_one<double>(hipStream_t, const Inst<double>&, int, int, size_t, bool);
+
+void launch_to_bf16(hipStream_t st, const float* src, int64_t n, unsigned short* dst) {
+    if (n <= 0) return;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid), dim3(256), 0, st, src, n, dst);
+    FDE_LAUNCH_CHECK();
+}
+
+void launch_from_bf16(hipStream_t st, const unsigned short* src, int64_t n, float* dst) {
+    if (n <= 0) return;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_from_bf16, dim3(grid), dim3(256), 0, st, src, n, dst);
+    FDE_LAUNCH_CHECK();
+}
 
 }  // namespace fde

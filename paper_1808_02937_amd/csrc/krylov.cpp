@@ -247,7 +247,7 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
     std::vector<Inst<float>> i32;
     std::vector<Inst<double>> i64;
     struct HsLaunch {
-        bool lds = true;
+        bool lds = true, bf16 = false;
         int wc = 1, nchunk = 1;
         size_t bytes = 0;
     } hs32, hs64;
@@ -283,6 +283,8 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
             HsLaunch& h = g.prec->prec == FDE_FP64 ? hs64 : hs32;
             size_t b = 0;
             const int w = hsolve_cols(c, g.prec, g.nr, &b);
+            require_lds_for_bf16(g.prec, w);
+            h.bf16 = h.bf16 || g.prec->bf16uv;
             if (w == 0) {
                 h.lds = false;
             } else {
@@ -337,7 +339,7 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
             if (any_copy) fg_copy_step(st, ns, d_sys.p, d_mask.p, j);
             if (!i32.empty()) {
                 if (hs32.lds)
-                    launch_hsolve<float>(st, (int)i32.size(), hs32.nchunk, hs32.wc, d_i32.p, j, hs32.bytes);
+                    launch_hsolve<float>(st, (int)i32.size(), hs32.nchunk, hs32.wc, d_i32.p, j, hs32.bytes, hs32.bf16);
                 else
                     launch_interp<float>(st, (int)i32.size(), d_i32.p, j);
             }
@@ -485,6 +487,7 @@ void engine_add(KrylovEngine* e, Op* op, HLUObj* prec, int nrhs, const double* G
         g->rhs.alloc(c, bs * prec->esz);
         g->work.alloc(c, std::max<int64_t>(prec->plan->sv.work_elems, 1) * nrhs * prec->esz);
         g->hs_wc = hsolve_cols(c, prec, nrhs, &g->hs_bytes);
+        require_lds_for_bf16(prec, g->hs_wc);
     }
     const size_t need = op->apply_ws_doubles(nrhs);
     if (op->ws.n < need) op->ws.alloc(c, need);
@@ -519,7 +522,7 @@ namespace {
 template <class T>
 void engine_hsolve(KrylovEngine* e, std::vector<EGroup*>& run, DevBuf<Inst<T>>& d_inst, int prec_code) {
     std::vector<Inst<T>> insts;
-    bool lds = true;
+    bool lds = true, bf16 = false;
     int wc = 1, nchunk = 1;
     size_t bytes = 0;
     for (EGroup* g : run) {
@@ -531,6 +534,7 @@ void engine_hsolve(KrylovEngine* e, std::vector<EGroup*>& run, DevBuf<Inst<T>>& 
         d.flops = g->prec->flops.p + 1;
         d.hs_wc = g->hs_wc;
         insts.push_back(d);
+        bf16 = bf16 || g->prec->bf16uv;
         if (g->hs_wc == 0) {
             lds = false;
         } else {
@@ -542,7 +546,7 @@ void engine_hsolve(KrylovEngine* e, std::vector<EGroup*>& run, DevBuf<Inst<T>>& 
     if (insts.empty()) return;
     upload(e->c, d_inst.p, insts.data(), insts.size() * sizeof(Inst<T>));
     if (lds)
-        launch_hsolve<T>(e->c->stream, (int)insts.size(), nchunk, wc, d_inst.p, 0, bytes);
+        launch_hsolve<T>(e->c->stream, (int)insts.size(), nchunk, wc, d_inst.p, 0, bytes, bf16);
     else
         launch_interp<T>(e->c->stream, (int)insts.size(), d_inst.p, 0);
 }

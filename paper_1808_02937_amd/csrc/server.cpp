@@ -88,7 +88,7 @@ size_t entry_bytes(const fde_op* op, const fde_hlu* f) {
     if (f)
         b += f->arena.bytes() + f->work_lu.bytes() + f->scr.bytes() + f->sv_rhs.bytes() + f->sv_work.bytes() +
              f->hs_prep.bytes() + f->scrd.bytes() + f->ranks.bytes() + f->status.bytes() + f->prof.bytes() +
-             f->flops.bytes() + f->lu_flops.bytes();
+             f->flops.bytes() + f->lu_flops.bytes() + f->lr16.bytes();
     return b;
 }
 
@@ -104,7 +104,7 @@ void drop(fde_server* s, std::unordered_map<std::string, fde_server::Entry>::ite
 size_t estimate(fde_server* s, const fde_problem& p) {
     fde_hlu_plan_info pi{};
     check_rc(fde_hlu_plan(p.nodes, p.N, p.P, &s->hp, s->lp.rank_cap, 0, &pi));
-    const size_t fac = (size_t)(s->lp.precision == FDE_FP64 ? pi.bytes_fp64 : pi.bytes_fp32);
+    const size_t fac = (size_t)(s->lp.precision == FDE_FP64 ? pi.bytes_fp64 : pi.bytes_fp32);   // BF16 U, V: less
     const size_t hmat = 8 * (size_t)pi.arena_elems;   // FP64 H-matrix, freed after the factorisation
     return op_device_bytes(p.nodes, p.N, p.P, 16) + hmat + fac;
 }

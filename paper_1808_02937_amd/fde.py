@@ -238,7 +238,7 @@ class HLU(_Handle):
         self.hm = hm
         self.Nd = hm.op.Nd
         self.device = hm.op.ctx.device
-        prec = {"fp64": A.FDE_FP64, "fp32": A.FDE_FP32}[precision]
+        prec = {"fp64": A.FDE_FP64, "fp32": A.FDE_FP32, "bf16uv": A.FDE_FP32_BF16UV}[precision]
         p = A.HLUParams(float(tol), int(rank_cap), prec, float(pivot_floor))
         h = C.c_void_p()
         check(load().fde_hlu_factor(hm.h, C.byref(p), C.byref(h)))
@@ -274,7 +274,7 @@ def factor_batched(hms: Sequence[HMatrix], tol: float = 1e-3, rank_cap: int = 0,
                    pivot_floor: float = 1e-14):
     """H-LU of several H-matrices together: each kernel launch runs one level of every factorisation."""
     n = len(hms)
-    prec = {"fp64": A.FDE_FP64, "fp32": A.FDE_FP32}[precision]
+    prec = {"fp64": A.FDE_FP64, "fp32": A.FDE_FP32, "bf16uv": A.FDE_FP32_BF16UV}[precision]
     p = A.HLUParams(float(tol), int(rank_cap), prec, float(pivot_floor))
     arr = (C.c_void_p * n)(*[hm.h.value for hm in hms])
     out = (C.c_void_p * n)()
@@ -369,7 +369,7 @@ class Server(_Handle):
         lib = load()
         self.ctx = ctx
         hp = A.HParams(int(R), float(lam), int(leaf_elems))
-        prec = {"fp64": A.FDE_FP64, "fp32": A.FDE_FP32}[precision]
+        prec = {"fp64": A.FDE_FP64, "fp32": A.FDE_FP32, "bf16uv": A.FDE_FP32_BF16UV}[precision]
         lp = A.HLUParams(float(tol), int(rank_cap), prec, float(pivot_floor))
         sp = _solve_params(rtol, restart, maxit)
         h = C.c_void_p()

@@ -26,6 +26,7 @@ pytestmark = pytest.mark.gpu
 #   here, the H-solve bound is also capped at about ten times the errors measured on the MI355X
 #   (FP32 5.6e-4, FP64 1.75e-12), frozen below.
 FP32_CAP = 5e-3
+BF16_CAP = 2.5e-3   # BF16 U, V: ten times the measured 2.4e-4
 FP64_CAP = 2e-11
 
 
@@ -70,6 +71,30 @@ def test_bench_hmatrix_matches_oracle(bench_case):
     rel = np.abs(At - ref).max() / np.abs(ref).max()
     say(f"  max |A~_gpu - A~| / max |A~| = {rel:.2e}")
     assert rel <= 1e-13, rel
+
+
+def test_bench_bf16uv_preconditioner_reaches_the_metric_residual(bench_case):
+    """BF16 low-rank factors (FP32 H-LU, U and V rounded to BF16 afterwards) as the preconditioner of
+    the FP64 FGMRES: the true residual still reaches 1e-10, in a few more iterations at most."""
+    c = bench_case
+    fde = c["fde"]
+    say("bench shape: BF16 U, V preconditioner")
+    lu16 = fde.factor_batched(c["hms"][:1], tol=1e-3, precision="bf16uv")[0]
+    lu32 = fde.factor_batched(c["hms"][:1], tol=1e-3, precision="fp32")[0]
+    x = lu16.solve(torch.tensor(c["g"], device="cuda")).cpu().numpy()
+    err = np.linalg.norm(x - c["xo"]) / np.linalg.norm(c["xo"])
+    op = c["hms"][0].op
+    G = torch.tensor(c["g"], device="cuda")
+    X16, i16 = fde.solve(op, G, lu16, rtol=1e-10)
+    X32, i32 = fde.solve(op, G, lu32, rtol=1e-10)
+    its16, its32 = [i["iters"] for i in i16], [i["iters"] for i in i32]
+    say(f"  bf16 H-solve vs oracle {err:.2e}; FGMRES iterations bf16 {its16} fp32 {its32}, "
+        f"residuals {max(i['relres'] for i in i16):.1e}")
+    assert all(i["status"] == 0 and i["relres"] <= 1e-10 for i in i16)
+    assert max(its16) <= max(its32) + 3
+    assert err <= BF16_CAP, err
+    lu16.close()
+    lu32.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

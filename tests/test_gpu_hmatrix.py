@@ -18,6 +18,7 @@ pytestmark = pytest.mark.gpu
 # H-solve bound is also capped at ten times the largest error measured on the MI355X
 # (FP32 9.9e-7, FP64 1.3e-14), frozen here.
 FP32_SMALL_CAP = 1e-5
+BF16_SMALL_CAP = 1.5e-3   # ten times the largest BF16 U, V error measured (1.35e-4)
 FP64_SMALL_CAP = 1e-13
 
 CASES = {
@@ -145,6 +146,34 @@ def test_hlu_fp32_solve_bound(ctx, name):
     say(f"  fp32 hsolve vs fp64 oracle {err:.2e} (bound {bound:.2e}); |LU - A~| {rel:.2e}, oracle {res_o:.2e}")
     assert err <= bound, err
     assert rel <= 2 * res_o + 20 * EPS32, rel
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hlu_bf16uv_solve_bound(ctx, name):
+    """FDE_FP32_BF16UV: an FP32 H-LU whose low-rank factors are then kept in BF16 (8-bit mantissa,
+    eps = 2^-8). The H-solve against the oracle's FP64 one moves by the BF16 rounding of U, V,
+    amplified by the conditioning: 10 kappa_1(A~) eps_bf16, capped at ten times the largest error
+    measured on the MI355X; the factors' residual grows by at most the rounding of U V^T."""
+    import paper_1808_02937_amd as fde
+    say(f"hlu bf16 U, V {name}")
+    sem, op, hm, oh = build(ctx, name)
+    lu = fde.HLU(hm, tol=1e-3, precision="bf16uv")
+    ref = fde.HLU(hm, tol=1e-3, precision="fp32")
+    ofac = OHLU(oh, tol=1e-3)
+    g = np.random.default_rng(12).standard_normal((2, sem.Nd))
+    x = lu.solve(torch.tensor(g, device="cuda")).cpu().numpy()
+    xo = ofac.solve(g.T).T
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    Ah = to_dense(oh.root)
+    bound = min(BF16_SMALL_CAP, 10 * kappa1(Ah) * 2.0 ** -8)
+    F, _ = lu.dense()
+    rel = lu_residual(F, Ah)
+    F32, _ = ref.dense()
+    rel32 = lu_residual(F32, Ah)
+    say(f"  bf16 U,V hsolve vs fp64 oracle {err:.2e} (bound {bound:.2e}); |LU - A~| {rel:.2e}, fp32 factors {rel32:.2e}")
+    assert err <= bound, err
+    assert rel <= rel32 + 2.0 ** -8, rel
+    assert lu.max_rank() == ref.max_rank()
 
 
 def test_hsolve_multi_rhs_equals_single(ctx):
