@@ -131,6 +131,8 @@ struct Ctx {
     size_t lds_limit = 0;   // largest dynamic LDS of one workgroup (bytes)
     // most recently used plans first, keyed by the structure they were made for
     std::vector<std::pair<std::string, std::shared_ptr<Plan>>> plans;
+    // plans whose host part was built ahead (in parallel) and that wait for their upload
+    std::map<std::string, std::shared_ptr<Plan>> host_plans;
     // task list of the last batched factorisation (it depends only on the batch's plans)
     std::shared_ptr<void> lu_tasks;
     // side streams (default priority) for independent small work forked from and joined back into

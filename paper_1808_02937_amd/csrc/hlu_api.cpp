@@ -1,5 +1,7 @@
 // C entry points of the H-matrix (Section 3) and the H-LU / H-solves (Section 4.1).
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -508,8 +510,15 @@ std::shared_ptr<const Plan> get_plan(Ctx* c, const HTree& hmt, int kmax) {
             c->plans.insert(c->plans.begin(), hit);
             return hit.second;
         }
-    auto p = std::make_shared<Plan>();
-    make_plan_host(hmt, kmax, *p, false);
+    std::shared_ptr<Plan> p;
+    auto pre = c->host_plans.find(key);   // host part built ahead (prefetch_plans)
+    if (pre != c->host_plans.end()) {
+        p = std::static_pointer_cast<Plan>(pre->second);
+        c->host_plans.erase(pre);
+    } else {
+        p = std::make_shared<Plan>();
+        make_plan_host(hmt, kmax, *p, false);
+    }
     upload_vec(c, p->h2p, p->t.h2p);
     std::vector<LRBlockDev> lrt;
     for (int b : p->t.lr_blocks) {
@@ -532,6 +541,50 @@ std::shared_ptr<const Plan> get_plan(Ctx* c, const HTree& hmt, int kmax) {
     c->plans.insert(c->plans.begin(), {key, p});
     if (c->plans.size() > kCached) c->plans.pop_back();
     return p;
+}
+
+// Host parts of the plans a batch will need and the context does not hold, built on up to 16 host
+// threads at once (each plan is independent host work: op lists, level schedule, H-solve tables);
+// get_plan then only uploads them.
+void prefetch_plans(Ctx* c, const std::vector<std::pair<const HTree*, int>>& items) {
+    std::vector<std::pair<std::string, std::pair<const HTree*, int>>> todo;
+    for (const auto& it : items) {
+        std::string key = plan_key(*it.first, it.second);
+        bool have = c->host_plans.count(key) > 0;
+        for (const auto& kv : c->plans) have = have || kv.first == key;
+        for (const auto& t : todo) have = have || t.first == key;
+        if (!have) todo.push_back({std::move(key), it});
+    }
+    if (todo.size() < 2) return;   // one plan: get_plan builds it
+    std::vector<std::shared_ptr<Plan>> built(todo.size());
+    std::vector<std::string> errs(todo.size());
+    std::vector<int> codes(todo.size(), FDE_OK);
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+        for (size_t i; (i = next.fetch_add(1)) < todo.size();) {
+            try {
+                auto p = std::make_shared<Plan>();
+                make_plan_host(*todo[i].second.first, todo[i].second.second, *p, false);
+                built[i] = p;
+            } catch (const Error& e) {
+                codes[i] = e.code;
+                errs[i] = e.msg;
+            } catch (...) {
+                codes[i] = FDE_EDEVICE;
+                errs[i] = "plan construction failed";
+            }
+        }
+    };
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({todo.size(), (size_t)hw, size_t(16)});
+    std::vector<std::thread> pool;
+    for (size_t k = 1; k < nt; ++k) pool.emplace_back(work);
+    work();
+    for (auto& t : pool) t.join();
+    for (size_t i = 0; i < todo.size(); ++i) {
+        if (codes[i] != FDE_OK) fail(codes[i], "%s", errs[i].c_str());
+        c->host_plans[todo[i].first] = built[i];
+    }
 }
 
 void hlu_prepare_solve(HLUObj* f, int nrhs) {
@@ -702,6 +755,13 @@ int fde_hlu_factor_batched(int n, fde_hmat* const* hms, const fde_hlu_params* pr
             if (!hms[i]) fail(FDE_EINVAL, "H-matrix %d is NULL", i);
             if (!c) c = hms[i]->t.op->ctx;
             if (hms[i]->t.op->ctx != c) fail(FDE_EINVAL, "H-matrices from different contexts");
+        }
+        {
+            std::vector<std::pair<const HTree*, int>> items;
+            for (int i = 0; i < n; ++i) items.push_back({&hms[i]->t, rank_capacity(hms[i]->t, prm)});
+            prefetch_plans(c, items);
+        }
+        for (int i = 0; i < n; ++i) {
             fde_hlu* f = new fde_hlu();
             fs.push_back(f);
             factor_prepare(f, hms[i], prm);
