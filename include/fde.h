@@ -235,6 +235,11 @@ typedef struct {
     long long scratch_f64;     /* recompression scratch, doubles */
     long long bytes_fp32;      /* device bytes one FP32 factorisation allocates */
     long long bytes_fp64;      /* device bytes one FP64 factorisation allocates */
+    int lr_blocks;             /* low-rank blocks of the H-matrix */
+    int hsolve_steps;          /* leaf steps of the leaf-step H-solve (0: the op-list H-solve runs) */
+    int hsolve_tslots;         /* its temporaries (slots of R values per column) */
+    long long hsolve_lds_fp32; /* its LDS bytes per workgroup, FP32, one column, right-hand side in LDS */
+    long long hsolve_lds_fp32_global_rhs;   /* the same with the right-hand side in global memory */
 } fde_hlu_plan_info;
 int  fde_hlu_plan(const double* nodes_host, int N, int P, const fde_hparams* hp, int rank_cap, int check,
                   fde_hlu_plan_info* out);
@@ -254,6 +259,17 @@ int  fde_hlu_max_rank(fde_hlu* f, int* max_rank);
 /* X = U_H^{-1} L_H^{-1} B (forward then backward H-substitution), nrhs columns,
  * FP64 in and out; the substitution runs in the factor precision. */
 int  fde_hlu_solve(fde_hlu* f, int nrhs, const double* B_dev, int ldb, double* X_dev, int ldx);
+/* Which H-solve a solve of nrhs columns on f runs (host query, no device work):
+ * FDE_HSOLVE_LDS, the leaf-step solve (one workgroup per chunk of *cols columns,
+ * *lds_bytes of LDS each) with the right-hand sides in LDS; FDE_HSOLVE_GLOBAL_RHS,
+ * the same with them in a global workspace (Nd too large for LDS);
+ * FDE_HSOLVE_OPS, the op-list interpreter (*cols = 0). The environment variable
+ * FDE_HSOLVE_VARIANT=global or =ops forces the latter two (for checks of one
+ * variant against another). Any output may be NULL. */
+#define FDE_HSOLVE_OPS 0
+#define FDE_HSOLVE_LDS 1
+#define FDE_HSOLVE_GLOBAL_RHS 2
+int  fde_hlu_solve_variant(fde_hlu* f, int nrhs, int* variant, int* cols, long long* lds_bytes);
 
 /* ---- preconditioned Krylov (Section 4.2) ------------------------------- */
 

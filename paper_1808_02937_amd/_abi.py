@@ -59,7 +59,8 @@ ll = C.c_longlong
 class PlanInfo(C.Structure):
     _fields_ = [("ops", ll), ("levels", i32), ("max_width", i32), ("solve_ops", ll), ("arena_elems", ll),
                 ("work_elems", ll), ("scratch_elems", ll), ("scratch_f64", ll), ("bytes_fp32", ll),
-                ("bytes_fp64", ll)]
+                ("bytes_fp64", ll), ("lr_blocks", i32), ("hsolve_steps", i32), ("hsolve_tslots", i32),
+                ("hsolve_lds_fp32", ll), ("hsolve_lds_fp32_global_rhs", ll)]
 
 
 class Problem(C.Structure):
@@ -99,6 +100,7 @@ SIGNATURES = {
     "fde_hlu_max_rank": (i32, [vp, ip]),
     "fde_hlu_stats": (i32, [vp, dp, dp, dp]),
     "fde_hlu_solve": (i32, [vp, i32, vp, i32, vp, i32]),
+    "fde_hlu_solve_variant": (i32, [vp, i32, ip, ip, C.POINTER(C.c_longlong)]),
     "fde_solve": (i32, [vp, vp, i32, vp, i32, vp, i32, C.POINTER(SolveParams), C.POINTER(SolveInfo)]),
     "fde_solve_batched": (i32, [vp, i32, C.POINTER(vp), C.POINTER(vp), ip, C.POINTER(vp), ip,
                                 C.POINTER(vp), ip, C.POINTER(SolveParams), C.POINTER(SolveInfo)]),

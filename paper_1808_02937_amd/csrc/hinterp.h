@@ -60,17 +60,19 @@ void launch_interp_one(hipStream_t st, const Inst<T>& d);
 // the solve-ready diagonal leaves of every leaf step (2 * nleaf of them) from the factors
 template <class T>
 void launch_hs_prepare(hipStream_t st, const T* arena, const HsStep* steps, int nleaf, T* prep);
-// bf16: some instance reads BF16 low-rank factors (FP32 only)
+// bf16: some instance reads BF16 low-rank factors (FP32 only); gx: the right-hand sides stay in
+// each instance's global workspace d.rhs (Nd x (nchunk wc) at least) instead of LDS
 template <class T>
 void launch_hsolve(hipStream_t st, int ninst, int nchunk, int wc, const Inst<T>* d_insts, int step,
-                   size_t lds_bytes, bool bf16 = false);
+                   size_t lds_bytes, bool bf16 = false, bool gx = false);
 template <class T>
-void launch_hsolve_one(hipStream_t st, const Inst<T>& d, int nchunk, int wc, size_t lds_bytes, bool bf16 = false);
+void launch_hsolve_one(hipStream_t st, const Inst<T>& d, int nchunk, int wc, size_t lds_bytes, bool bf16 = false,
+                       bool gx = false);
 // dst[i] = src[i] rounded to BF16 (nearest, ties to even), and back to FP32
 void launch_to_bf16(hipStream_t st, const float* src, int64_t n, unsigned short* dst);
 void launch_from_bf16(hipStream_t st, const unsigned short* src, int64_t n, float* dst);
 // LDS bytes of one workgroup of the leaf-step H-solve for wc columns
-size_t hsolve_lds_bytes(int Nd, int tslots, int kmax, int nslots, int wc, size_t esz);
+size_t hsolve_lds_bytes(int Nd, int tslots, int kmax, int nslots, int wc, size_t esz, bool global_rhs = false);
 constexpr int kHsolveMaxRow = 64;   // leaf-step H-solve: leaves of at most this many rows
 constexpr int kHsolveMaxCols = 8;
 // leaf-step H-solve: per step, its diagonal leaf in solve-ready form (64 x 64, column-major, the

@@ -104,8 +104,15 @@ struct fde_hlu : fde::HLUObj {};
 namespace fde {
 void hlu_prepare_solve(HLUObj* f, int nrhs);
 void hlu_solve(HLUObj* f, int nrhs, const double* B, int ldb, double* X, int ldx);
-// columns per workgroup of the LDS H-solve for these factors and nrhs columns (0: does not fit)
-int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes);
+// columns per workgroup of the leaf-step H-solve for these factors and nrhs columns (0: does not
+// fit LDS, the op-list interpreter runs); *global_rhs: only with the right-hand sides in global
+// memory, in a workspace of hsolve_rhs_elems(Nd, nrhs) elements
+int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes, bool* global_rhs);
+// elements of an H-solve right-hand side workspace for nrhs columns (also enough for the op-list
+// interpreter, which uses Nd x nrhs of it)
+int64_t hsolve_rhs_elems(int Nd, int nrhs);
+// LDS bytes of one workgroup of the leaf-step H-solve of f for wc columns
+size_t hsolve_lds_for(const HLUObj* f, int wc, bool global_rhs);
 // FDE_EUNSUPPORTED when f keeps BF16 low-rank factors and the LDS H-solve does not fit (wc == 0)
 void require_lds_for_bf16(const HLUObj* f, int wc);
 }  // namespace fde

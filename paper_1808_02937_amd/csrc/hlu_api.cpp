@@ -3,6 +3,7 @@
 #include <atomic>
 #include <thread>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 
@@ -591,7 +592,7 @@ void hlu_prepare_solve(HLUObj* f, int nrhs) {
     if (nrhs > f->sv_nrhs_cap) {
         Ctx* c = f->op->ctx;
         const int64_t cap = std::max<int64_t>(nrhs, 1);
-        f->sv_rhs.alloc(c, (int64_t)f->op->Nd * cap * f->esz);
+        f->sv_rhs.alloc(c, hsolve_rhs_elems(f->op->Nd, (int)cap) * f->esz);
         f->sv_work.alloc(c, std::max<int64_t>(f->plan->sv.work_elems, 1) * cap * f->esz);
         f->sv_nrhs_cap = cap;
     }
@@ -600,41 +601,66 @@ void hlu_prepare_solve(HLUObj* f, int nrhs) {
 // solves on factors whose U, V are BF16 need the LDS H-solve (the op-list interpreter reads FP32)
 void require_lds_for_bf16(const HLUObj* f, int wc) {
     if (f->bf16uv && wc == 0)
-        fail(FDE_EUNSUPPORTED, "BF16 low-rank factors: the right-hand sides (Nd = %d) do not fit the LDS H-solve",
-             f->op->Nd);
+        fail(FDE_EUNSUPPORTED, "BF16 low-rank factors: the leaf-step H-solve does not fit LDS (Nd = %d)", f->op->Nd);
 }
 
-int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes) {
+int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes, bool* global_rhs) {
+    *global_rhs = false;
     if (!f->plan->sv_lds || nrhs <= 0) return 0;
     if (!c->lds_limit) c->lds_limit = device_lds_limit(c->device);
-    const Plan& P = *f->plan;
+    // FDE_HSOLVE_VARIANT in the environment (checks of one variant against another): "global"
+    // keeps the right-hand sides in global memory even where they fit LDS, "ops" runs the op-list
+    // interpreter
+    const char* env = std::getenv("FDE_HSOLVE_VARIANT");
+    if (env && std::strcmp(env, "ops") == 0) return 0;
+    const bool force = env && std::strcmp(env, "global") == 0;
     // chunk widths are 1, 2, 4 or 8 columns (one kernel per width)
-    int wc = 1;
-    while (wc * 2 <= std::min(nrhs, kHsolveMaxCols)) wc *= 2;
-    auto need = [&](int w) { return hsolve_lds_bytes(f->op->Nd, P.hs.tslots, f->kmax, P.t.nslots, w, f->esz); };
-    while (wc > 1 && need(wc) > c->lds_limit) wc /= 2;
-    if (need(wc) > c->lds_limit) return 0;
-    *lds_bytes = need(wc);
-    return wc;
+    int wc0 = 1;
+    while (wc0 * 2 <= std::min(nrhs, kHsolveMaxCols)) wc0 *= 2;
+    for (const bool gx : {false, true}) {
+        if (!gx && force) continue;
+        auto need = [&](int w) { return hsolve_lds_for(f, w, gx); };
+        int wc = wc0;
+        while (wc > 1 && need(wc) > c->lds_limit) wc /= 2;
+        if (need(wc) > c->lds_limit) continue;
+        *lds_bytes = need(wc);
+        *global_rhs = gx;
+        return wc;
+    }
+    return 0;
+}
+
+size_t hsolve_lds_for(const HLUObj* f, int wc, bool global_rhs) {
+    const Plan& P = *f->plan;
+    return hsolve_lds_bytes(f->op->Nd, P.hs.tslots, f->kmax, P.t.nslots, wc, f->esz, global_rhs);
+}
+
+int64_t hsolve_rhs_elems(int Nd, int nrhs) {
+    // whole chunks of kHsolveMaxCols columns, and a row of slack: the solve reads up to a chunk of
+    // entries past the last column it needs (and discards them)
+    const int64_t cols = ((int64_t)std::max(nrhs, 1) + kHsolveMaxCols - 1) / kHsolveMaxCols * kHsolveMaxCols;
+    return (int64_t)Nd * cols + kHsolveMaxRow;
 }
 
 void hlu_solve(HLUObj* f, int nrhs, const double* B, int ldb, double* X, int ldx) {
     Ctx* c = f->op->ctx;
     hipStream_t st = c->stream;
     size_t lds = 0;
-    const int wc = hsolve_cols(c, f, nrhs, &lds);
+    bool gx = false;
+    const int wc = hsolve_cols(c, f, nrhs, &lds, &gx);
     require_lds_for_bf16(f, wc);
     if (wc > 0) {
-        // right-hand sides in LDS, one workgroup per chunk of wc columns
+        // one workgroup per chunk of wc columns; right-hand sides in LDS, or in sv_rhs (whole chunks)
         const int nchunk = (nrhs + wc - 1) / wc;
+        if (gx) hlu_prepare_solve(f, nrhs);
         if (f->prec == FDE_FP64) {
             Inst<double> d = f->inst<double>(true, nrhs, B, ldb, X, ldx);
             d.hs_wc = wc;
-            launch_hsolve_one<double>(st, d, nchunk, wc, lds);
+            launch_hsolve_one<double>(st, d, nchunk, wc, lds, false, gx);
         } else {
             Inst<float> d = f->inst<float>(true, nrhs, B, ldb, X, ldx);
             d.hs_wc = wc;
-            launch_hsolve_one<float>(st, d, nchunk, wc, lds, f->bf16uv);
+            launch_hsolve_one<float>(st, d, nchunk, wc, lds, f->bf16uv, gx);
         }
         return;
     }
@@ -725,6 +751,14 @@ int fde_hlu_plan(const double* nodes, int N, int P, const fde_hparams* hp, int r
     const long long fixed = 8 * r.scratch_f64 + 4 * (long long)p.t.nslots + 8 + 16;   // + status, flop counters
     r.bytes_fp32 = 4 * (r.arena_elems + r.work_elems + r.scratch_elems) + fixed;
     r.bytes_fp64 = 8 * (r.arena_elems + r.work_elems + r.scratch_elems) + fixed;
+    r.lr_blocks = p.t.nslots;
+    r.hsolve_steps = p.sv_lds ? 2 * p.hs.nleaf : 0;
+    r.hsolve_tslots = p.hs.tslots;
+    if (p.sv_lds) {
+        const int kmax = rank_capacity(t, &hl);
+        r.hsolve_lds_fp32 = (long long)hsolve_lds_bytes(op.Nd, p.hs.tslots, kmax, p.t.nslots, 1, 4, false);
+        r.hsolve_lds_fp32_global_rhs = (long long)hsolve_lds_bytes(op.Nd, p.hs.tslots, kmax, p.t.nslots, 1, 4, true);
+    }
     FDE_API_END
 }
 
@@ -845,6 +879,18 @@ int fde_hlu_max_rank(fde_hlu* f, int* mr) {
         FDE_HIP(hipStreamSynchronize(f->op->ctx->stream));
     }
     *mr = r.empty() ? 0 : *std::max_element(r.begin(), r.end());
+    FDE_API_END
+}
+
+int fde_hlu_solve_variant(fde_hlu* f, int nrhs, int* variant, int* cols, long long* lds_bytes) {
+    FDE_API_BEGIN
+    if (!f || nrhs < 1) fail(FDE_EINVAL, "bad arguments");
+    size_t lds = 0;
+    bool gx = false;
+    const int wc = hsolve_cols(f->op->ctx, f, nrhs, &lds, &gx);
+    if (variant) *variant = wc == 0 ? FDE_HSOLVE_OPS : gx ? FDE_HSOLVE_GLOBAL_RHS : FDE_HSOLVE_LDS;
+    if (cols) *cols = wc;
+    if (lds_bytes) *lds_bytes = wc ? (long long)lds : 0;
     FDE_API_END
 }
 

@@ -183,7 +183,7 @@ __device__ inline void load_block(T (&v)[kHsChunk], const FacSrc<T, BF>& f, int6
 // role and the number of items (empty slots load a valid dummy address), so the waits the
 // compiler inserts for prefetched values are exact and the prefetches stay in flight across
 // the barriers.
-template <class T, int WC, bool BF>
+template <class T, int WC, bool BF, bool GX>
 __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int chunk, int step, char* smem) {
     using D = HsDepth<T, WC>;
     const int wc = d.hs_wc;
@@ -191,8 +191,11 @@ __device__ __attribute__((always_inline)) void hsteps_body(const Inst<T>& d, int
     const int Nd = d.Nd, kmax = d.kmax, nsteps = 2 * d.hs_nleaf, L = d.hs_nleaf;
     const int wce = min(wc, d.nrhs - c0);
     if (wce <= 0 || wc > WC) return;
-    T* X = reinterpret_cast<T*>(smem);                    // Nd x wc, ld Nd
-    T* tb = X + (int64_t)Nd * wc;                          // tslots x kmax x wc
+    // the chunk's right-hand sides, Nd x wc (ld Nd): in LDS, or (GX, too long for LDS) in the
+    // instance's global workspace (columns c0 .. c0 + wc - 1 of d.rhs, L2-resident; the other waves
+    // of the workgroup see a wave's stores after each barrier)
+    T* X = GX ? d.rhs + (int64_t)c0 * Nd : reinterpret_cast<T*>(smem);
+    T* tb = GX ? reinterpret_cast<T*>(smem) : X + (int64_t)Nd * wc;   // tslots x kmax x wc
     T* part1 = tb + (int64_t)d.hs_tslots * kmax * wc;      // kHW x 64 x wc (phase 1 partial sums)
     T* part2 = part1 + kHT * wc;                           // 2 x kHW x 64 x wc (early sums, by step parity)
     // staged diagonal leaf (64 x 64, ld 64) and its diagonal entries, two buffers by step parity:
@@ -573,18 +576,18 @@ __global__ void __launch_bounds__(256) k_hs_prepare(const T* __restrict__ arena,
         P[kHsolveMaxRow * kHsolveMaxRow + i] = (fwd || i >= n) ? T(1) : T(1) / D[i + (int64_t)i * n];
 }
 
-template <class T, int WC, bool BF>
+template <class T, int WC, bool BF, bool GX>
 __global__ void __launch_bounds__(kHT) k_hsolve(const Inst<T>* __restrict__ insts, int nchunk, int step) {
     extern __shared__ __align__(16) char smem[];
     const int i = blockIdx.x / nchunk, c = blockIdx.x % nchunk;
     const Inst<T> d = insts[i];
-    hsteps_body<T, WC, BF>(d, c, step, smem);
+    hsteps_body<T, WC, BF, GX>(d, c, step, smem);
 }
 
-template <class T, int WC, bool BF>
+template <class T, int WC, bool BF, bool GX>
 __global__ void __launch_bounds__(kHT) k_hsolve_one(const Inst<T> d) {
     extern __shared__ __align__(16) char smem[];
-    hsteps_body<T, WC, BF>(d, blockIdx.x, 0, smem);
+    hsteps_body<T, WC, BF, GX>(d, blockIdx.x, 0, smem);
 }
 
 __global__ void k_to_bf16(const float* __restrict__ src, int64_t n, unsigned short* __restrict__ dst) {
@@ -611,8 +614,8 @@ void allow_lds(K kernel, size_t bytes) {
 
 }  // namespace
 
-size_t hsolve_lds_bytes(int Nd, int tslots, int kmax, int nslots, int wc, size_t esz) {
-    return ((size_t)Nd + (size_t)tslots * kmax + 3 * kHT) * wc * esz +
+size_t hsolve_lds_bytes(int Nd, int tslots, int kmax, int nslots, int wc, size_t esz, bool global_rhs) {
+    return ((global_rhs ? 0 : (size_t)Nd) + (size_t)tslots * kmax + 3 * kHT) * wc * esz +
            (size_t)(2 * kHsolveMaxRow + 3) * kHsolveMaxRow * esz + (size_t)nslots * sizeof(int) + 16;
 }
 
@@ -624,45 +627,49 @@ size_t device_lds_limit(int device) {
 
 namespace {
 
-template <class T, int WC, bool BF>
+template <class T, int WC, bool BF, bool GX>
 void launch_hsolve_wc(hipStream_t st, int ninst, int nchunk, const Inst<T>* d_insts, int step, size_t lds) {
-    allow_lds(k_hsolve<T, WC, BF>, lds);
-    hipLaunchKernelGGL((k_hsolve<T, WC, BF>), dim3(ninst * nchunk), dim3(kHT), lds, st, d_insts, nchunk, step);
+    allow_lds(k_hsolve<T, WC, BF, GX>, lds);
+    hipLaunchKernelGGL((k_hsolve<T, WC, BF, GX>), dim3(ninst * nchunk), dim3(kHT), lds, st, d_insts, nchunk, step);
     FDE_LAUNCH_CHECK();
 }
 
-template <class T, int WC, bool BF>
+template <class T, int WC, bool BF, bool GX>
 void launch_hsolve_one_wc(hipStream_t st, const Inst<T>& d, int nchunk, size_t lds) {
-    allow_lds(k_hsolve_one<T, WC, BF>, lds);
-    hipLaunchKernelGGL((k_hsolve_one<T, WC, BF>), dim3(nchunk), dim3(kHT), lds, st, d);
+    allow_lds(k_hsolve_one<T, WC, BF, GX>, lds);
+    hipLaunchKernelGGL((k_hsolve_one<T, WC, BF, GX>), dim3(nchunk), dim3(kHT), lds, st, d);
     FDE_LAUNCH_CHECK();
 }
 
 template <class T, int WC>
 void launch_hsolve_wc_bf(hipStream_t st, int ninst, int nchunk, const Inst<T>* d_insts, int step, size_t lds,
-                         bool bf16) {
+                         bool bf16, bool gx) {
     if constexpr (sizeof(T) == 4) {
         if (bf16) {
-            launch_hsolve_wc<T, WC, true>(st, ninst, nchunk, d_insts, step, lds);
+            if (gx) launch_hsolve_wc<T, WC, true, true>(st, ninst, nchunk, d_insts, step, lds);
+            else launch_hsolve_wc<T, WC, true, false>(st, ninst, nchunk, d_insts, step, lds);
             return;
         }
     } else {
         if (bf16) fail(FDE_EINVAL, "BF16 low-rank factors come with FP32 factorisations only");
     }
-    launch_hsolve_wc<T, WC, false>(st, ninst, nchunk, d_insts, step, lds);
+    if (gx) launch_hsolve_wc<T, WC, false, true>(st, ninst, nchunk, d_insts, step, lds);
+    else launch_hsolve_wc<T, WC, false, false>(st, ninst, nchunk, d_insts, step, lds);
 }
 
 template <class T, int WC>
-void launch_hsolve_one_wc_bf(hipStream_t st, const Inst<T>& d, int nchunk, size_t lds, bool bf16) {
+void launch_hsolve_one_wc_bf(hipStream_t st, const Inst<T>& d, int nchunk, size_t lds, bool bf16, bool gx) {
     if constexpr (sizeof(T) == 4) {
         if (bf16) {
-            launch_hsolve_one_wc<T, WC, true>(st, d, nchunk, lds);
+            if (gx) launch_hsolve_one_wc<T, WC, true, true>(st, d, nchunk, lds);
+            else launch_hsolve_one_wc<T, WC, true, false>(st, d, nchunk, lds);
             return;
         }
     } else {
         if (bf16) fail(FDE_EINVAL, "BF16 low-rank factors come with FP32 factorisations only");
     }
-    launch_hsolve_one_wc<T, WC, false>(st, d, nchunk, lds);
+    if (gx) launch_hsolve_one_wc<T, WC, false, true>(st, d, nchunk, lds);
+    else launch_hsolve_one_wc<T, WC, false, false>(st, d, nchunk, lds);
 }
 
 }  // namespace
@@ -678,32 +685,32 @@ template void launch_hs_prepare<double>(hipStream_t, const double*, const HsStep
 
 template <class T>
 void launch_hsolve(hipStream_t st, int ninst, int nchunk, int wc, const Inst<T>* d_insts, int step, size_t lds,
-                   bool bf16) {
+                   bool bf16, bool gx) {
     if (ninst <= 0 || nchunk <= 0) return;
     switch (wc) {
-        case 1: launch_hsolve_wc_bf<T, 1>(st, ninst, nchunk, d_insts, step, lds, bf16); break;
-        case 2: launch_hsolve_wc_bf<T, 2>(st, ninst, nchunk, d_insts, step, lds, bf16); break;
-        case 4: launch_hsolve_wc_bf<T, 4>(st, ninst, nchunk, d_insts, step, lds, bf16); break;
-        case 8: launch_hsolve_wc_bf<T, 8>(st, ninst, nchunk, d_insts, step, lds, bf16); break;
+        case 1: launch_hsolve_wc_bf<T, 1>(st, ninst, nchunk, d_insts, step, lds, bf16, gx); break;
+        case 2: launch_hsolve_wc_bf<T, 2>(st, ninst, nchunk, d_insts, step, lds, bf16, gx); break;
+        case 4: launch_hsolve_wc_bf<T, 4>(st, ninst, nchunk, d_insts, step, lds, bf16, gx); break;
+        case 8: launch_hsolve_wc_bf<T, 8>(st, ninst, nchunk, d_insts, step, lds, bf16, gx); break;
         default: fail(FDE_EDEVICE, "H-solve chunk width %d is not 1, 2, 4 or 8", wc);
     }
 }
-template void launch_hsolve<float>(hipStream_t, int, int, int, const Inst<float>*, int, size_t, bool);
-template void launch_hsolve<double>(hipStream_t, int, int, int, const Inst<double>*, int, size_t, bool);
+template void launch_hsolve<float>(hipStream_t, int, int, int, const Inst<float>*, int, size_t, bool, bool);
+template void launch_hsolve<double>(hipStream_t, int, int, int, const Inst<double>*, int, size_t, bool, bool);
 
 template <class T>
-void launch_hsolve_one(hipStream_t st, const Inst<T>& d, int nchunk, int wc, size_t lds, bool bf16) {
+void launch_hsolve_one(hipStream_t st, const Inst<T>& d, int nchunk, int wc, size_t lds, bool bf16, bool gx) {
     if (nchunk <= 0) return;
     switch (wc) {
-        case 1: launch_hsolve_one_wc_bf<T, 1>(st, d, nchunk, lds, bf16); break;
-        case 2: launch_hsolve_one_wc_bf<T, 2>(st, d, nchunk, lds, bf16); break;
-        case 4: launch_hsolve_one_wc_bf<T, 4>(st, d, nchunk, lds, bf16); break;
-        case 8: launch_hsolve_one_wc_bf<T, 8>(st, d, nchunk, lds, bf16); break;
+        case 1: launch_hsolve_one_wc_bf<T, 1>(st, d, nchunk, lds, bf16, gx); break;
+        case 2: launch_hsolve_one_wc_bf<T, 2>(st, d, nchunk, lds, bf16, gx); break;
+        case 4: launch_hsolve_one_wc_bf<T, 4>(st, d, nchunk, lds, bf16, gx); break;
+        case 8: launch_hsolve_one_wc_bf<T, 8>(st, d, nchunk, lds, bf16, gx); break;
         default: fail(FDE_EDEVICE, "H-solve chunk width %d is not 1, 2, 4 or 8", wc);
     }
 }
-template void launch_hsolve_one<float>(hipStream_t, const Inst<float>&, int, int, size_t, bool);
-template void launch_hsolve_one<double>(hipStream_t, const Inst<double>&, int, int, size_t, bool);
+template void launch_hsolve_one<float>(hipStream_t, const Inst<float>&, int, int, size_t, bool, bool);
+template void launch_hsolve_one<double>(hipStream_t, const Inst<double>&, int, int, size_t, bool, bool);
 
 void launch_to_bf16(hipStream_t st, const float* src, int64_t n, unsigned short* dst) {
     if (n <= 0) return;

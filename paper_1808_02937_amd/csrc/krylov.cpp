@@ -247,9 +247,10 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
     std::vector<Inst<float>> i32;
     std::vector<Inst<double>> i64;
     struct HsLaunch {
-        bool lds = true, bf16 = false;
+        bool lds = true, bf16 = false, gx = false;
         int wc = 1, nchunk = 1;
         size_t bytes = 0;
+        std::vector<std::pair<const HLUObj*, int>> members;   // factors and their chunk widths
     } hs32, hs64;
     for (auto& g : groups) {
         if (g.nr == 0) continue;
@@ -275,14 +276,18 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
             mask[g.sys0 + k] = g.prec ? 0 : 1;
         }
         if (g.prec) {
-            g.rhs.alloc(c, bs * g.prec->esz);
+            // leaf-step H-solve workspace: whole chunks of columns (where the right-hand sides
+            // stay in global memory the last chunk is written in full)
+            g.rhs.alloc(c, hsolve_rhs_elems(g.op->Nd, g.nr) * g.prec->esz);
             g.work.alloc(c, std::max<int64_t>(g.prec->plan->sv.work_elems, 1) * g.nr * g.prec->esz);
-            // LDS H-solve: each system with its own chunk width (as when solved alone); a launch per
-            // precision sized for the largest; any system that does not fit sends its precision
-            // to the global-memory interpreter
+            // leaf-step H-solve: each system with its own chunk width (as when solved alone); a
+            // launch per precision sized for the largest, with the right-hand sides in global
+            // memory for all if one needs it; any system that does not fit at all sends its
+            // precision to the op-list interpreter
             HsLaunch& h = g.prec->prec == FDE_FP64 ? hs64 : hs32;
             size_t b = 0;
-            const int w = hsolve_cols(c, g.prec, g.nr, &b);
+            bool gx = false;
+            const int w = hsolve_cols(c, g.prec, g.nr, &b, &gx);
             require_lds_for_bf16(g.prec, w);
             h.bf16 = h.bf16 || g.prec->bf16uv;
             if (w == 0) {
@@ -290,6 +295,8 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
             } else {
                 h.wc = std::max(h.wc, w);
                 h.nchunk = std::max(h.nchunk, (g.nr + w - 1) / w);
+                h.gx = h.gx || gx;
+                h.members.push_back({g.prec, w});
                 h.bytes = std::max(h.bytes, b);
             }
             if (g.prec->prec == FDE_FP64) {
@@ -301,6 +308,11 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
             }
         }
     }
+    for (HsLaunch* h : {&hs32, &hs64})
+        if (h->gx) {   // one launch: every member's chunk with its right-hand sides in global memory
+            h->bytes = 0;
+            for (auto& m : h->members) h->bytes = std::max(h->bytes, hsolve_lds_for(m.first, m.second, true));
+        }
     DevBuf<SysDev> d_sys;
     DevBuf<SysState> d_ss;
     DevBuf<int> d_mask, d_count;
@@ -339,13 +351,15 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
             if (any_copy) fg_copy_step(st, ns, d_sys.p, d_mask.p, j);
             if (!i32.empty()) {
                 if (hs32.lds)
-                    launch_hsolve<float>(st, (int)i32.size(), hs32.nchunk, hs32.wc, d_i32.p, j, hs32.bytes, hs32.bf16);
+                    launch_hsolve<float>(st, (int)i32.size(), hs32.nchunk, hs32.wc, d_i32.p, j, hs32.bytes, hs32.bf16,
+                                         hs32.gx);
                 else
                     launch_interp<float>(st, (int)i32.size(), d_i32.p, j);
             }
             if (!i64.empty()) {
                 if (hs64.lds)
-                    launch_hsolve<double>(st, (int)i64.size(), hs64.nchunk, hs64.wc, d_i64.p, j, hs64.bytes);
+                    launch_hsolve<double>(st, (int)i64.size(), hs64.nchunk, hs64.wc, d_i64.p, j, hs64.bytes, false,
+                                          hs64.gx);
                 else
                     launch_interp<double>(st, (int)i64.size(), d_i64.p, j);
             }
@@ -410,8 +424,9 @@ struct EGroup {
     bool finished = false;
     DevBuf<double> V, Z, W, R;
     DevBuf<char> rhs, work;
-    int hs_wc = 0;            // LDS H-solve columns per workgroup (0: interpreter)
+    int hs_wc = 0;            // leaf-step H-solve columns per workgroup (0: interpreter)
     size_t hs_bytes = 0;
+    bool hs_gx = false;       // its right-hand sides only fit in global memory
 };
 
 struct KrylovEngine {
@@ -484,9 +499,9 @@ void engine_add(KrylovEngine* e, Op* op, HLUObj* prec, int nrhs, const double* G
     FDE_HIP(hipMemsetAsync(g->Z.p, 0, g->Z.bytes(), st));
     FDE_HIP(hipMemsetAsync(g->R.p, 0, g->R.bytes(), st));   // A x_0 = 0: the first cycle starts from G
     if (prec) {
-        g->rhs.alloc(c, bs * prec->esz);
+        g->rhs.alloc(c, hsolve_rhs_elems(op->Nd, nrhs) * prec->esz);
         g->work.alloc(c, std::max<int64_t>(prec->plan->sv.work_elems, 1) * nrhs * prec->esz);
-        g->hs_wc = hsolve_cols(c, prec, nrhs, &g->hs_bytes);
+        g->hs_wc = hsolve_cols(c, prec, nrhs, &g->hs_bytes, &g->hs_gx);
         require_lds_for_bf16(prec, g->hs_wc);
     }
     const size_t need = op->apply_ws_doubles(nrhs);
@@ -522,7 +537,7 @@ namespace {
 template <class T>
 void engine_hsolve(KrylovEngine* e, std::vector<EGroup*>& run, DevBuf<Inst<T>>& d_inst, int prec_code) {
     std::vector<Inst<T>> insts;
-    bool lds = true, bf16 = false;
+    bool lds = true, bf16 = false, gx = false;
     int wc = 1, nchunk = 1;
     size_t bytes = 0;
     for (EGroup* g : run) {
@@ -541,12 +556,18 @@ void engine_hsolve(KrylovEngine* e, std::vector<EGroup*>& run, DevBuf<Inst<T>>& 
             wc = std::max(wc, g->hs_wc);
             nchunk = std::max(nchunk, (g->nr + g->hs_wc - 1) / g->hs_wc);
             bytes = std::max(bytes, g->hs_bytes);
+            gx = gx || g->hs_gx;
         }
     }
     if (insts.empty()) return;
+    if (lds && gx) {   // one launch: every chunk with its right-hand sides in global memory
+        bytes = 0;
+        for (EGroup* g : run)
+            if (g->prec && g->prec->prec == prec_code) bytes = std::max(bytes, hsolve_lds_for(g->prec, g->hs_wc, true));
+    }
     upload(e->c, d_inst.p, insts.data(), insts.size() * sizeof(Inst<T>));
     if (lds)
-        launch_hsolve<T>(e->c->stream, (int)insts.size(), nchunk, wc, d_inst.p, 0, bytes, bf16);
+        launch_hsolve<T>(e->c->stream, (int)insts.size(), nchunk, wc, d_inst.p, 0, bytes, bf16, gx);
     else
         launch_interp<T>(e->c->stream, (int)insts.size(), d_inst.p, 0);
 }

@@ -250,6 +250,13 @@ class HLU(_Handle):
         check(load().fde_hlu_solve(self.h, B2.shape[0], _dptr(B2), B2.stride(0), _dptr(X), X.stride(0)))
         return X.view_as(B)
 
+    def solve_variant(self, nrhs: int = 1) -> dict:
+        """Which H-solve a solve of nrhs columns runs: "lds", "global_rhs" or "ops" (op-list
+        interpreter), its columns per workgroup and LDS bytes."""
+        v, w, b = C.c_int(0), C.c_int(0), C.c_longlong(0)
+        check(load().fde_hlu_solve_variant(self.h, nrhs, C.byref(v), C.byref(w), C.byref(b)))
+        return {"variant": {0: "ops", 1: "lds", 2: "global_rhs"}[v.value], "cols": w.value, "lds_bytes": b.value}
+
     def dense(self):
         """(packed L\\U in the internal order as an Nd x Nd tensor, h2p order)."""
         Nd = self.Nd

@@ -1,0 +1,147 @@
+"""The leaf-step H-solve (the forward and backward H-substitutions of Section 4.1) with its
+right-hand sides in global memory -- the variant that runs where Nd entries per column no longer
+fit in LDS (N = 4096 at P = 8 and beyond) -- on the GPU.
+
+- Forced at sizes that fit LDS (FDE_HSOLVE_VARIANT=global) it executes the LDS variant's operations
+  in the same order, so the two give the same bits, for full and ragged chunks of columns; the
+  result is also compared with the oracle's H-solve of the same operator.
+- At Nd = 32767 (N = 4096, P = 8), where only this variant fits, the FP64 H-solve agrees with the
+  op-list interpreter's (FDE_HSOLVE_VARIANT=ops: separate code over the same factors) within the
+  1e-10 relative bound of FP64 solves.
+- At Nd = 65535 (N = 8192, P = 8, the largest operator of the serving mix) the FP32 H-LU, with its
+  low-rank factors in FP32 or BF16, preconditions FGMRES to a true relative residual of 1e-10."""
+import numpy as np
+import pytest
+import torch
+
+import fde_inputs as fi
+from oracle.hmatrix import HLU as OHLU
+from oracle.hmatrix import HMatrix as OHMatrix
+from oracle.hmatrix import to_dense
+from oracle.sem import SEM
+from tests.gpu_common import EPS32, EPS64, kappa1, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+LDS_LIMIT = 160 * 1024   # bytes of LDS one workgroup may use on the MI355X
+FP64_SOLVE_BOUND = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    fde = need_gpu()
+    c = fde.Context(0)
+    yield c
+    c.close()
+
+
+def operator(ctx, nodes, P, alpha=1.5, theta=0.5, rho=1.0, R=8, leaf=8):
+    import paper_1808_02937_amd as fde
+    op = fde.Operator(ctx, nodes, P, alpha, theta, rho)
+    hm = fde.HMatrix(op, R=R, lam=1.0, leaf_elems=leaf)
+    return op, hm
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16uv"])
+def test_forced_global_rhs_equals_lds_variant(ctx, precision, monkeypatch):
+    import paper_1808_02937_amd as fde
+    nodes = fi.two_sided_graded_mesh(96, 6, 0.5)
+    P = 6
+    say(f"global-rhs H-solve forced, N=96, P={P}, {precision}")
+    op, hm = operator(ctx, nodes, P, 1.7, 0.4, 0.0, R=6, leaf=4)
+    lu = fde.HLU(hm, tol=1e-3, precision=precision)
+    rng = np.random.default_rng(31)
+    for nrhs in (1, 3, 8, 13):
+        G = torch.tensor(rng.standard_normal((nrhs, op.Nd)), device="cuda")
+        monkeypatch.delenv("FDE_HSOLVE_VARIANT", raising=False)
+        v_lds = lu.solve_variant(nrhs)
+        X_lds = lu.solve(G)
+        monkeypatch.setenv("FDE_HSOLVE_VARIANT", "global")
+        v_gx = lu.solve_variant(nrhs)
+        X_gx = lu.solve(G)
+        monkeypatch.delenv("FDE_HSOLVE_VARIANT")
+        assert v_lds["variant"] == "lds" and v_gx["variant"] == "global_rhs", (v_lds, v_gx)
+        assert v_gx["cols"] == v_lds["cols"] and v_gx["lds_bytes"] < v_lds["lds_bytes"]
+        torch.cuda.synchronize()
+        same = torch.equal(X_lds, X_gx)
+        say(f"  nrhs {nrhs}: bitwise equal {same}")
+        assert same, float((X_lds - X_gx).abs().max())
+    if precision == "bf16uv":
+        return
+    # and the oracle's H-solve of the same operator (bound as for the LDS variant: the rounding of
+    # the factor precision amplified by the conditioning of A~, capped)
+    sem = SEM(nodes, P, 1.7, 0.4, 0.0)
+    oh = OHMatrix(sem, 6, 1.0, 4)
+    ofac = OHLU(oh, tol=1e-3)
+    g = rng.standard_normal((3, sem.Nd))
+    monkeypatch.setenv("FDE_HSOLVE_VARIANT", "global")
+    x = lu.solve(torch.tensor(g, device="cuda")).cpu().numpy()
+    monkeypatch.delenv("FDE_HSOLVE_VARIANT")
+    xo = ofac.solve(g.T).T
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    eps = EPS64 if precision == "fp64" else EPS32
+    cap = 1e-13 if precision == "fp64" else 1e-5
+    bound = min(cap, 10 * kappa1(to_dense(oh.root)) * eps)
+    say(f"  vs oracle {err:.2e} (bound {bound:.2e})")
+    assert err <= bound, err
+    lu.close()
+    op.close()
+
+
+def test_global_rhs_fp64_matches_interpreter_at_nd_32767(ctx, monkeypatch):
+    import paper_1808_02937_amd as fde
+    N, P = 4096, 8
+    nodes = fi.uniform_mesh(N)
+    info = fde.plan_hlu(nodes, P, R=8, leaf_elems=8)
+    say(f"global-rhs H-solve, N={N}, P={P}: LDS bytes {info['hsolve_lds_fp32']} (rhs in LDS), "
+        f"{info['hsolve_lds_fp32_global_rhs']} (rhs in global memory)")
+    assert info["hsolve_lds_fp32"] > LDS_LIMIT >= info["hsolve_lds_fp32_global_rhs"]
+    op, hm = operator(ctx, nodes, P)
+    lu = fde.HLU(hm, tol=1e-3, precision="fp64")
+    G = torch.tensor(np.random.default_rng(32).standard_normal((3, op.Nd)), device="cuda")
+    v = lu.solve_variant(3)
+    assert v["variant"] == "global_rhs" and v["cols"] == 2, v
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        out = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return out, a.elapsed_time(b)
+
+    X_gx, t_gx = timed(lambda: lu.solve(G))   # three columns: a chunk of two and a ragged one
+    monkeypatch.setenv("FDE_HSOLVE_VARIANT", "ops")
+    assert lu.solve_variant(3)["variant"] == "ops"
+    X_ops, t_ops = timed(lambda: lu.solve(G))
+    monkeypatch.delenv("FDE_HSOLVE_VARIANT")
+    rel = float(torch.linalg.norm(X_gx - X_ops) / torch.linalg.norm(X_ops))
+    say(f"  |X_global - X_ops| / |X_ops| = {rel:.2e}; {t_gx:.2f} ms (global rhs), {t_ops:.2f} ms (op list)")
+    assert torch.isfinite(X_gx).all()
+    assert rel <= FP64_SOLVE_BOUND, rel
+    lu.close()
+    op.close()
+
+
+def test_global_rhs_preconditions_fgmres_at_nd_65535(ctx):
+    import paper_1808_02937_amd as fde
+    N, P = 8192, 8
+    nodes = fi.uniform_mesh(N)
+    say(f"global-rhs H-solve as preconditioner, N={N}, P={P}")
+    op, hm = operator(ctx, nodes, P, 1.3, 0.7, 1.0)
+    G = torch.tensor(np.random.default_rng(33).standard_normal((2, op.Nd)), device="cuda")
+    its = {}
+    for precision in ("fp32", "bf16uv"):
+        lu = fde.HLU(hm, tol=1e-3, precision=precision)
+        assert lu.solve_variant(2)["variant"] == "global_rhs"
+        X, infos = fde.solve(op, G, lu, rtol=1e-10)
+        its[precision] = [i["iters"] for i in infos]
+        res = max(i["relres"] for i in infos)
+        # the true residual, recomputed with the full SEM matvec
+        R = G - op.apply(X)
+        true = float((torch.linalg.norm(R, dim=1) / torch.linalg.norm(G, dim=1)).max())
+        say(f"  {precision}: FGMRES iterations {its[precision]}, residual {res:.1e}, recomputed {true:.1e}")
+        assert all(i["status"] == 0 for i in infos)
+        assert res <= 1e-10 and true <= 2e-10, (res, true)
+        lu.close()
+    assert max(its["bf16uv"]) <= max(its["fp32"]) + 3
+    op.close()
