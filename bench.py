@@ -289,7 +289,8 @@ def cpu_model():
     return "unknown"
 
 
-def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=1808029375, n_keys=128, n_max=2048):
+def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=1808029375, n_keys=128, n_max=8192,
+                   precision="bf16uv"):
     """Continuous serving of a request stream (Section 5's problem class, many keys).
 
     A pool of n_keys problems: N log-uniform in [128, n_max], P in {4, 6, 8}, alpha ~ U(1.1, 1.9),
@@ -313,8 +314,8 @@ def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=18080
     total = n_req + n_warm
     keys = gen.choice(len(pool), size=total, p=w)
     nrhs = gen.integers(1, 17, size=total)
-    # cached factors: FP32 dense blocks, BF16 low-rank factors
-    srv = fde.Server(ctx, R=8, leaf_elems=8, tol=1e-3, precision="bf16uv", rtol=1e-10)
+    # cached factors: FP32 dense blocks and BF16 low-rank factors (or the plain FP64 path)
+    srv = fde.Server(ctx, R=8, leaf_elems=8, tol=1e-3, precision=precision, rtol=1e-10)
     tg = torch.Generator(device="cuda").manual_seed(seed)
 
     def rhs_of(key, k):
@@ -382,12 +383,12 @@ def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=18080
             "p50_ms": float(np.percentile(meas, 50)), "p99_ms": float(np.percentile(meas, 99)),
             "mean_ms": float(meas.mean()), "solves_per_s": float(nrhs.sum() / elapsed),
             "server_steps": steps, "mean_requests_in_flight": inflight_sum / max(steps, 1),
-            "cache": st, "cached_factor_precision": "FP32 dense blocks, BF16 U and V",
+            "cache": st,
+            "cached_factor_precision": {"bf16uv": "FP32 dense blocks, BF16 U and V", "fp32": "FP32",
+                                        "fp64": "FP64"}[precision],
             "admitted_with_cached_factors": cached_hits,
             "definition": ("latency = completion - arrival; Poisson arrivals; continuous batching (requests join "
-                           "the server between FGMRES steps while others are in flight)"),
-            "shrunk": (f"N up to {n_max} (the serving configuration allows 8192): a right-hand side of more than "
-                       "about 38k unknowns does not fit the LDS H-solve")}
+                           "the server between FGMRES steps while others are in flight)")}
 
 
 def main():

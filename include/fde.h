@@ -263,9 +263,11 @@ int  fde_hlu_solve(fde_hlu* f, int nrhs, const double* B_dev, int ldb, double* X
  * FDE_HSOLVE_LDS, the leaf-step solve (one workgroup per chunk of *cols columns,
  * *lds_bytes of LDS each) with the right-hand sides in LDS; FDE_HSOLVE_GLOBAL_RHS,
  * the same with them in a global workspace (Nd too large for LDS);
- * FDE_HSOLVE_OPS, the op-list interpreter (*cols = 0). The environment variable
- * FDE_HSOLVE_VARIANT=global or =ops forces the latter two (for checks of one
- * variant against another). Any output may be NULL. */
+ * FDE_HSOLVE_OPS, the op-list interpreter (*cols = 0). One column per workgroup
+ * unless a launch would pass the device's compute units. The environment
+ * variables FDE_HSOLVE_VARIANT=global or =ops force the latter two and
+ * FDE_HSOLVE_COLS=1|2|4|8 a chunk width (for checks of one variant against
+ * another). Any output may be NULL. */
 #define FDE_HSOLVE_OPS 0
 #define FDE_HSOLVE_LDS 1
 #define FDE_HSOLVE_GLOBAL_RHS 2

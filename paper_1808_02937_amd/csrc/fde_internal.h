@@ -129,6 +129,7 @@ struct Ctx {
     ~Ctx();
     DevBuf<double> gl;   // Gauss-Legendre n=1..kMaxGL: nodes then weights, offset n(n-1)/2
     size_t lds_limit = 0;   // largest dynamic LDS of one workgroup (bytes)
+    int num_cu = 0;         // compute units of the device
     // most recently used plans first, keyed by the structure they were made for
     std::vector<std::pair<std::string, std::shared_ptr<Plan>>> plans;
     // plans whose host part was built ahead (in parallel) and that wait for their upload

@@ -82,6 +82,7 @@ constexpr int kHsolveMaxCols = 8;
 constexpr int kHsPrepStride = kHsolveMaxRow * kHsolveMaxRow + kHsolveMaxRow;
 // largest dynamic LDS of one workgroup on the device (bytes)
 size_t device_lds_limit(int device);
+int device_cu_count(int device);
 
 // one op of a factorisation in a batch: its record (in the instance's device program), the
 // instance and the op's index in its program

@@ -105,9 +105,10 @@ namespace fde {
 void hlu_prepare_solve(HLUObj* f, int nrhs);
 void hlu_solve(HLUObj* f, int nrhs, const double* B, int ldb, double* X, int ldx);
 // columns per workgroup of the leaf-step H-solve for these factors and nrhs columns (0: does not
-// fit LDS, the op-list interpreter runs); *global_rhs: only with the right-hand sides in global
-// memory, in a workspace of hsolve_rhs_elems(Nd, nrhs) elements
-int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes, bool* global_rhs);
+// fit LDS, the op-list interpreter runs), in a launch of share_cols columns over all its
+// instances; *global_rhs: only with the right-hand sides in global memory, in a workspace of
+// hsolve_rhs_elems(Nd, nrhs) elements
+int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes, bool* global_rhs, int share_cols);
 // elements of an H-solve right-hand side workspace for nrhs columns (also enough for the op-list
 // interpreter, which uses Nd x nrhs of it)
 int64_t hsolve_rhs_elems(int Nd, int nrhs);

@@ -436,7 +436,8 @@ void keep_uv_in_bf16(HLUObj* f) {
     for (int b : t.lr_blocks) base = std::min<int64_t>(base, t.bl[b].uoff);
     const int64_t n = t.arena_elems - base;
     f->lr_base = base;
-    f->lr16.alloc(c, std::max<int64_t>(n, 1) * sizeof(unsigned short));
+    // rounded up to whole 32-bit words: the H-solve reads the word holding each element
+    f->lr16.alloc(c, (std::max<int64_t>(n, 1) + 1) / 2 * 2 * sizeof(unsigned short));
     launch_to_bf16(c->stream, reinterpret_cast<const float*>(f->arena.p) + base, n,
                    reinterpret_cast<unsigned short*>(f->lr16.p));
     DevBuf<char> head;
@@ -604,19 +605,29 @@ void require_lds_for_bf16(const HLUObj* f, int wc) {
         fail(FDE_EUNSUPPORTED, "BF16 low-rank factors: the leaf-step H-solve does not fit LDS (Nd = %d)", f->op->Nd);
 }
 
-int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes, bool* global_rhs) {
+int hsolve_cols(Ctx* c, const HLUObj* f, int nrhs, size_t* lds_bytes, bool* global_rhs, int share_cols) {
     *global_rhs = false;
     if (!f->plan->sv_lds || nrhs <= 0) return 0;
     if (!c->lds_limit) c->lds_limit = device_lds_limit(c->device);
+    if (!c->num_cu) c->num_cu = device_cu_count(c->device);
     // FDE_HSOLVE_VARIANT in the environment (checks of one variant against another): "global"
     // keeps the right-hand sides in global memory even where they fit LDS, "ops" runs the op-list
-    // interpreter
+    // interpreter; FDE_HSOLVE_COLS=w asks for chunks of w columns (1, 2, 4 or 8; narrowed where
+    // LDS requires)
     const char* env = std::getenv("FDE_HSOLVE_VARIANT");
     if (env && std::strcmp(env, "ops") == 0) return 0;
     const bool force = env && std::strcmp(env, "global") == 0;
-    // chunk widths are 1, 2, 4 or 8 columns (one kernel per width)
+    // chunk width (columns per workgroup; 1, 2, 4 or 8, one kernel each). A workgroup walks the
+    // whole chain of leaf steps for its chunk, so narrow chunks side by side finish first as long
+    // as the launch (this instance's share of share_cols columns) fills no more than the compute
+    // units; past that, wider chunks share each factor load among their columns
+    const int64_t target = std::max<int64_t>(1, (int64_t)c->num_cu * nrhs / std::max(share_cols, nrhs));
     int wc0 = 1;
-    while (wc0 * 2 <= std::min(nrhs, kHsolveMaxCols)) wc0 *= 2;
+    while (wc0 < kHsolveMaxCols && (nrhs + wc0 - 1) / wc0 > target) wc0 *= 2;
+    if (const char* ew = std::getenv("FDE_HSOLVE_COLS")) {
+        const int w = std::atoi(ew);
+        if (w == 1 || w == 2 || w == 4 || w == 8) wc0 = w;
+    }
     for (const bool gx : {false, true}) {
         if (!gx && force) continue;
         auto need = [&](int w) { return hsolve_lds_for(f, w, gx); };
@@ -647,7 +658,7 @@ void hlu_solve(HLUObj* f, int nrhs, const double* B, int ldb, double* X, int ldx
     hipStream_t st = c->stream;
     size_t lds = 0;
     bool gx = false;
-    const int wc = hsolve_cols(c, f, nrhs, &lds, &gx);
+    const int wc = hsolve_cols(c, f, nrhs, &lds, &gx, nrhs);
     require_lds_for_bf16(f, wc);
     if (wc > 0) {
         // one workgroup per chunk of wc columns; right-hand sides in LDS, or in sv_rhs (whole chunks)
@@ -887,7 +898,7 @@ int fde_hlu_solve_variant(fde_hlu* f, int nrhs, int* variant, int* cols, long lo
     if (!f || nrhs < 1) fail(FDE_EINVAL, "bad arguments");
     size_t lds = 0;
     bool gx = false;
-    const int wc = hsolve_cols(f->op->ctx, f, nrhs, &lds, &gx);
+    const int wc = hsolve_cols(f->op->ctx, f, nrhs, &lds, &gx, nrhs);
     if (variant) *variant = wc == 0 ? FDE_HSOLVE_OPS : gx ? FDE_HSOLVE_GLOBAL_RHS : FDE_HSOLVE_LDS;
     if (cols) *cols = wc;
     if (lds_bytes) *lds_bytes = wc ? (long long)lds : 0;

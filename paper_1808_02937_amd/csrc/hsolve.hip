@@ -160,18 +160,27 @@ struct FacSrc {
 __device__ inline float bf16_bits_to_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
 // kHsChunk columns of a block at `off` (ld), row = lane, rows and columns clamped; a low-rank
-// block of BF16 factors is widened to FP32 (the block is wave-uniform, so is the branch)
+// block of BF16 factors is widened to FP32. Both storages are read with one 32-bit load per
+// element (for BF16, the word holding the element), so every block issues the same loads: a
+// branch between two kinds of load would make the compiler wait for every prefetch in flight
+// where the branches join.
 template <class T, bool BF>
 __device__ inline void load_block(T (&v)[kHsChunk], const FacSrc<T, BF>& f, int64_t off, int ld, int rows, int cols,
                                   int c0, int lane) {
     const int li = min(lane, rows - 1), cl = max(cols, 1) - 1;
     if constexpr (BF) {
-        if (f.lr16 && off >= f.lr_base) {
-            const auto a = gmem(f.lr16 + (off - f.lr_base) + li);
+        static_assert(sizeof(T) == 4, "BF16 low-rank factors come with FP32 factorisations");
+        const bool h16 = f.lr16 && off >= f.lr_base;   // wave-uniform
+        const unsigned* w32 = reinterpret_cast<const unsigned*>(f.arena) + (h16 ? 0 : off + li);
+        const unsigned* w16 = reinterpret_cast<const unsigned*>(f.lr16);   // 4-byte aligned
+        const int64_t e0 = h16 ? off - f.lr_base + li : 0;
 #pragma unroll
-            for (int c = 0; c < kHsChunk; ++c) v[c] = (T)bf16_bits_to_float(a[(int64_t)min(c0 + c, cl) * ld]);
-            return;
+        for (int c = 0; c < kHsChunk; ++c) {
+            const int64_t cc = (int64_t)min(c0 + c, cl) * ld, e = e0 + cc;
+            const unsigned w = *gmem(h16 ? w16 + (e >> 1) : w32 + cc);
+            v[c] = h16 ? (T)bf16_bits_to_float((unsigned short)((e & 1) ? w >> 16 : w & 0xffffu)) : __uint_as_float(w);
         }
+        return;
     }
     const auto a = gmem(f.arena + off + li);
 #pragma unroll
@@ -623,6 +632,12 @@ size_t device_lds_limit(int device) {
     int v = 0;
     FDE_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
     return (size_t)v;
+}
+
+int device_cu_count(int device) {
+    int v = 0;
+    FDE_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device));
+    return std::max(v, 1);
 }
 
 namespace {

@@ -252,6 +252,9 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
         size_t bytes = 0;
         std::vector<std::pair<const HLUObj*, int>> members;   // factors and their chunk widths
     } hs32, hs64;
+    int prec_cols = 0;   // columns of every preconditioned group: the H-solve launches' width
+    for (auto& g : groups)
+        if (g.prec) prec_cols += g.nr;
     for (auto& g : groups) {
         if (g.nr == 0) continue;
         const int64_t bs = (int64_t)g.op->Nd * g.nr;
@@ -287,7 +290,7 @@ void run(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nr
             HsLaunch& h = g.prec->prec == FDE_FP64 ? hs64 : hs32;
             size_t b = 0;
             bool gx = false;
-            const int w = hsolve_cols(c, g.prec, g.nr, &b, &gx);
+            const int w = hsolve_cols(c, g.prec, g.nr, &b, &gx, prec_cols);
             require_lds_for_bf16(g.prec, w);
             h.bf16 = h.bf16 || g.prec->bf16uv;
             if (w == 0) {
@@ -501,7 +504,7 @@ void engine_add(KrylovEngine* e, Op* op, HLUObj* prec, int nrhs, const double* G
     if (prec) {
         g->rhs.alloc(c, hsolve_rhs_elems(op->Nd, nrhs) * prec->esz);
         g->work.alloc(c, std::max<int64_t>(prec->plan->sv.work_elems, 1) * nrhs * prec->esz);
-        g->hs_wc = hsolve_cols(c, prec, nrhs, &g->hs_bytes, &g->hs_gx);
+        g->hs_wc = hsolve_cols(c, prec, nrhs, &g->hs_bytes, &g->hs_gx, nrhs);
         require_lds_for_bf16(prec, g->hs_wc);
     }
     const size_t need = op->apply_ws_doubles(nrhs);

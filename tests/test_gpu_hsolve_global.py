@@ -51,20 +51,27 @@ def test_forced_global_rhs_equals_lds_variant(ctx, precision, monkeypatch):
     op, hm = operator(ctx, nodes, P, 1.7, 0.4, 0.0, R=6, leaf=4)
     lu = fde.HLU(hm, tol=1e-3, precision=precision)
     rng = np.random.default_rng(31)
-    for nrhs in (1, 3, 8, 13):
+    # (columns, chunk width): one column per workgroup by default; wider chunks, full and ragged
+    for nrhs, cols in ((1, None), (3, None), (3, 2), (8, 8), (13, 4), (13, 8)):
         G = torch.tensor(rng.standard_normal((nrhs, op.Nd)), device="cuda")
+        if cols:
+            monkeypatch.setenv("FDE_HSOLVE_COLS", str(cols))
         monkeypatch.delenv("FDE_HSOLVE_VARIANT", raising=False)
         v_lds = lu.solve_variant(nrhs)
         X_lds = lu.solve(G)
+        # the same chunks with the right-hand sides in global memory (LDS may have narrowed them)
+        monkeypatch.setenv("FDE_HSOLVE_COLS", str(v_lds["cols"]))
         monkeypatch.setenv("FDE_HSOLVE_VARIANT", "global")
         v_gx = lu.solve_variant(nrhs)
         X_gx = lu.solve(G)
         monkeypatch.delenv("FDE_HSOLVE_VARIANT")
+        monkeypatch.delenv("FDE_HSOLVE_COLS")
         assert v_lds["variant"] == "lds" and v_gx["variant"] == "global_rhs", (v_lds, v_gx)
-        assert v_gx["cols"] == v_lds["cols"] and v_gx["lds_bytes"] < v_lds["lds_bytes"]
+        assert 1 <= v_lds["cols"] <= (cols or 1) and v_gx["cols"] == v_lds["cols"], (v_lds, v_gx)
+        assert v_gx["lds_bytes"] < v_lds["lds_bytes"]
         torch.cuda.synchronize()
         same = torch.equal(X_lds, X_gx)
-        say(f"  nrhs {nrhs}: bitwise equal {same}")
+        say(f"  nrhs {nrhs}, {v_lds['cols']} per chunk: bitwise equal {same}")
         assert same, float((X_lds - X_gx).abs().max())
     if precision == "bf16uv":
         return
@@ -99,6 +106,7 @@ def test_global_rhs_fp64_matches_interpreter_at_nd_32767(ctx, monkeypatch):
     op, hm = operator(ctx, nodes, P)
     lu = fde.HLU(hm, tol=1e-3, precision="fp64")
     G = torch.tensor(np.random.default_rng(32).standard_normal((3, op.Nd)), device="cuda")
+    monkeypatch.setenv("FDE_HSOLVE_COLS", "2")
     v = lu.solve_variant(3)
     assert v["variant"] == "global_rhs" and v["cols"] == 2, v
     def timed(fn):
@@ -110,12 +118,18 @@ def test_global_rhs_fp64_matches_interpreter_at_nd_32767(ctx, monkeypatch):
         return out, a.elapsed_time(b)
 
     X_gx, t_gx = timed(lambda: lu.solve(G))   # three columns: a chunk of two and a ragged one
+    monkeypatch.delenv("FDE_HSOLVE_COLS")
+    X_1, t_1 = timed(lambda: lu.solve(G))     # one column per workgroup
     monkeypatch.setenv("FDE_HSOLVE_VARIANT", "ops")
     assert lu.solve_variant(3)["variant"] == "ops"
     X_ops, t_ops = timed(lambda: lu.solve(G))
     monkeypatch.delenv("FDE_HSOLVE_VARIANT")
+    rel1 = float(torch.linalg.norm(X_1 - X_ops) / torch.linalg.norm(X_ops))
+    say(f"  one column per workgroup: {rel1:.2e}, {t_1:.2f} ms")
+    assert rel1 <= FP64_SOLVE_BOUND, rel1
     rel = float(torch.linalg.norm(X_gx - X_ops) / torch.linalg.norm(X_ops))
-    say(f"  |X_global - X_ops| / |X_ops| = {rel:.2e}; {t_gx:.2f} ms (global rhs), {t_ops:.2f} ms (op list)")
+    say(f"  |X_global - X_ops| / |X_ops| = {rel:.2e}; {t_gx:.2f} ms (global rhs, chunks of 2), "
+        f"{t_ops:.2f} ms (op list)")
     assert torch.isfinite(X_gx).all()
     assert rel <= FP64_SOLVE_BOUND, rel
     lu.close()
