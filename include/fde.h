@@ -122,8 +122,24 @@ size_t fde_ctx_bytes_in_use(const fde_ctx* ctx);
  * Errors: FDE_EINVAL, FDE_ENOMEM, FDE_EDEVICE. */
 int  fde_op_create(fde_ctx* ctx, const double* nodes_host, int N, int P, double alpha,
                    double theta, double rho, int apply_mode, fde_op** out);
+/* The same with degree P_host[i] on element i (the space S_N^P with degrees
+ * P_i of Section 2.2; each in [1, 32], the largest >= 2). Its Nd = sum P_i - 1
+ * unknowns are ordered as in eq. (lsys): the P_i - 1 bubbles of each element,
+ * element by element, then the N - 1 hats; every call below that takes or
+ * returns vectors or matrices of the operator (apply, load vectors, dense
+ * forms, H-matrix, H-solves, Krylov solves) uses that order and size. The
+ * bubbles do not depend on P_i, so this system is the principal submatrix of
+ * the one-degree system with P = max P_i on the same mesh: the operator is
+ * built at that degree (pair moments, Toeplitz symbol, H-matrix structure) and
+ * the other unknowns are decoupled (their rows and columns become those of the
+ * identity), which keeps the H-LU of the space's own A~. Not available on such
+ * an operator (FDE_EUNSUPPORTED): fde_stiffness_apply_timed,
+ * fde_stiffness_apply_noalloc, fde_hlu_to_dense, fde_sigma_estimate.
+ * fde_op_pair_moments returns the max P_i x max P_i moments. */
+int  fde_op_create_hp(fde_ctx* ctx, const double* nodes_host, int N, const int* P_host, double alpha,
+                      double theta, double rho, int apply_mode, fde_op** out);
 void fde_op_destroy(fde_op* op);
-/* Nd = N*P - 1 */
+/* Nd = N*P - 1 (sum P_i - 1 with a degree per element) */
 int  fde_op_ndof(const fde_op* op);
 /* 1 if the operator uses the FFT block-Toeplitz apply, 0 for the dense apply */
 int  fde_op_is_toeplitz(const fde_op* op);

@@ -76,6 +76,7 @@ SIGNATURES = {
     "fde_ctx_set_stream": (i32, [vp, vp]),
     "fde_ctx_bytes_in_use": (sz, [vp]),
     "fde_op_create": (i32, [vp, dp, i32, i32, f64, f64, f64, i32, C.POINTER(vp)]),
+    "fde_op_create_hp": (i32, [vp, dp, i32, ip, f64, f64, f64, i32, C.POINTER(vp)]),
     "fde_op_destroy": (None, [vp]),
     "fde_op_ndof": (i32, [vp]),
     "fde_op_is_toeplitz": (i32, [vp]),

@@ -819,6 +819,7 @@ void stiffness_apply(Op* op, int nrhs, const double* X, int ldx, double* Y, int 
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, st, N, P, op->rho,
                        op->d_h.p, op->d_lmass.p, z, Xin, ldx, nrhs, bc0, bcN, Y, ldy);
     FDE_LAUNCH_CHECK();
+    hp_decouple(op, nrhs, Xin, ldx, Y, ldy, st);   // degree per element: the outside unknowns
 }
 
 }  // namespace fde

@@ -545,12 +545,52 @@ int fde_op_create(fde_ctx* c, const double* nodes, int N, int P, double alpha, d
     FDE_API_END
 }
 
+int fde_op_create_hp(fde_ctx* c, const double* nodes, int N, const int* P, double alpha, double theta, double rho,
+                     int mode, fde_op** out) {
+    FDE_API_BEGIN
+    if (!c || !out || !P) fail(FDE_EINVAL, "null argument");
+    *out = nullptr;
+    if (N < 1) fail(FDE_EINVAL, "N must be >= 1 (got %d)", N);
+    int Pmax = 0;
+    for (int e = 0; e < N; ++e) {
+        if (P[e] < 1 || P[e] > 32) fail(FDE_EINVAL, "element %d: degree must be in [1, 32] (got %d)", e, P[e]);
+        Pmax = std::max(Pmax, P[e]);
+    }
+    if (Pmax < 2) fail(FDE_EINVAL, "the largest degree must be >= 2");
+    FDE_HIP(hipSetDevice(c->device));
+    fde_op* op = new fde_op();
+    op->ctx = c;
+    try {
+        build_op(op, nodes, N, Pmax, alpha, theta, rho, mode);
+        // the space's unknowns among the extended ones: bubbles p < P_e of element e, the hats
+        op->hp = true;
+        op->hp_P.assign(P, P + N);
+        std::vector<int> map;
+        std::vector<double> keep(op->Nd, 0.0);
+        for (int e = 0; e < N; ++e)
+            for (int p = 1; p < P[e]; ++p) map.push_back(e * (Pmax - 1) + p - 1);
+        for (int j = 1; j < N; ++j) map.push_back(N * (Pmax - 1) + j - 1);
+        for (int i : map) keep[i] = 1.0;
+        op->hp_nd = (int)map.size();
+        if (op->hp_nd < 1) fail(FDE_EINVAL, "the space has no unknowns");
+        op->d_hp_map.alloc(c, map.size());
+        upload(c, op->d_hp_map.p, map.data(), map.size() * sizeof(int));
+        op->d_hp_keep.alloc(c, keep.size());
+        upload(c, op->d_hp_keep.p, keep.data(), keep.size() * sizeof(double));
+    } catch (...) {
+        delete op;
+        throw;
+    }
+    *out = op;
+    FDE_API_END
+}
+
 void fde_op_destroy(fde_op* op) {
     if (!op) return;
     delete op;   // its blocks return to the context's stream-ordered cache
 }
 
-int fde_op_ndof(const fde_op* op) { return op ? op->Nd : -1; }
+int fde_op_ndof(const fde_op* op) { return op ? op->pub_nd() : -1; }
 int fde_op_is_toeplitz(const fde_op* op) { return op ? (op->toeplitz ? 1 : 0) : -1; }
 
 int fde_op_pair_moments(fde_op* op, int npairs, const int* e, const int* f, double* out) {
@@ -576,9 +616,17 @@ int fde_op_pair_moments(fde_op* op, int npairs, const int* e, const int* f, doub
 
 int fde_op_dense(fde_op* op, double* A, int lda) {
     FDE_API_BEGIN
-    if (!op || !A || lda < op->Nd) fail(FDE_EINVAL, "bad arguments");
+    if (!op || !A || lda < op->pub_nd()) fail(FDE_EINVAL, "bad arguments");
     if (op->Nd > 65535) fail(FDE_EUNSUPPORTED, "fde_op_dense is meant for Nd <= 65535 (got %d)", op->Nd);
-    launch_dense_matrix(op, A, lda);
+    if (!op->hp) {
+        launch_dense_matrix(op, A, lda);
+        return FDE_OK;
+    }
+    DevBuf<double> Ae;   // the extended matrix, then the space's rows and columns
+    Ae.alloc(op->ctx, (size_t)op->Nd * op->Nd);
+    launch_dense_matrix(op, Ae.p, op->Nd);
+    hp_gather_matrix(op, Ae.p, op->Nd, A, lda, op->ctx->stream);
+    FDE_HIP(hipStreamSynchronize(op->ctx->stream));
     FDE_API_END
 }
 
@@ -597,17 +645,25 @@ int fde_load_nodes(fde_op* op, int* nq, double* x, double* da, double* db) {
 namespace {
 
 
-// G from the values in d_lq_f, then the lifting of the boundary values
+// G from the values in d_lq_f, then the lifting of the boundary values (a degree per element:
+// over the extended unknowns, then the space's entries)
 void assemble_load(Op* op, double c1, double c2, double* G) {
     Ctx* c = op->ctx;
-    launch_load_vector(op, G);
+    DevBuf<double> ge;
+    double* Ge = G;
+    if (op->hp) {
+        ge.alloc(c, op->Nd);
+        Ge = ge.p;
+    }
+    launch_load_vector(op, Ge);
     if (c1 != 0.0 || c2 != 0.0) {
         // lifting: G -= A [0; c1, c2] through the boundary hats
         DevBuf<double> t;
         t.alloc(c, op->Nd);
         stiffness_apply(op, 1, nullptr, op->Nd, t.p, op->Nd, c1, c2, true);
-        axpy_cols(c->stream, op->Nd, 1, -1.0, t.p, op->Nd, G, op->Nd);
+        axpy_cols(c->stream, op->Nd, 1, -1.0, t.p, op->Nd, Ge, op->Nd);
     }
+    if (op->hp) hp_gather(op, 1, Ge, op->Nd, G, op->hp_nd, c->stream);
 }
 
 }  // namespace
@@ -667,15 +723,27 @@ int fde_load_vector_fn(fde_op* op, fde_fn fn, void* user, double c1, double c2, 
 
 int fde_stiffness_apply(fde_op* op, int nrhs, const double* X, int ldx, double* Y, int ldy) {
     FDE_API_BEGIN
-    if (!op || nrhs < 0 || (nrhs && (!X || !Y)) || ldx < op->Nd || ldy < op->Nd)
+    if (!op || nrhs < 0 || (nrhs && (!X || !Y)) || ldx < op->pub_nd() || ldy < op->pub_nd())
         fail(FDE_EINVAL, "bad arguments");
     if (nrhs == 0) return FDE_OK;
-    stiffness_apply(op, nrhs, X, ldx, Y, ldy, 0.0, 0.0, false);
+    if (!op->hp) {
+        stiffness_apply(op, nrhs, X, ldx, Y, ldy, 0.0, 0.0, false);
+        return FDE_OK;
+    }
+    // a degree per element: the columns on the extended unknowns and back
+    Ctx* c = op->ctx;
+    DevBuf<double> xe, ye;
+    xe.alloc(c, (size_t)op->Nd * nrhs);
+    ye.alloc(c, (size_t)op->Nd * nrhs);
+    hp_scatter(op, nrhs, X, ldx, xe.p, op->Nd, c->stream);
+    stiffness_apply(op, nrhs, xe.p, op->Nd, ye.p, op->Nd, 0.0, 0.0, false);
+    hp_gather(op, nrhs, ye.p, op->Nd, Y, ldy, c->stream);
     FDE_API_END
 }
 
 int fde_stiffness_apply_timed(fde_op* op, int nrhs, const double* X, int ldx, double* Y, int ldy, double* core_ms) {
     FDE_API_BEGIN
+    if (op && op->hp) fail(FDE_EUNSUPPORTED, "fde_stiffness_apply_timed: one degree per operator only");
     if (!op || nrhs <= 0 || !X || !Y || !core_ms || ldx < op->Nd || ldy < op->Nd) fail(FDE_EINVAL, "bad arguments");
     hipEvent_t ev[2] = {nullptr, nullptr};
     FDE_HIP(hipEventCreate(&ev[0]));
@@ -697,6 +765,7 @@ int fde_stiffness_apply_timed(fde_op* op, int nrhs, const double* X, int ldx, do
 
 int fde_stiffness_apply_noalloc(fde_op* op, int nrhs, const double* X, int ldx, double* Y, int ldy) {
     FDE_API_BEGIN
+    if (op && op->hp) fail(FDE_EUNSUPPORTED, "fde_stiffness_apply_noalloc: one degree per operator only");
     if (!op || nrhs < 0 || (nrhs && (!X || !Y)) || ldx < op->Nd || ldy < op->Nd)
         fail(FDE_EINVAL, "bad arguments");
     if (nrhs == 0) return FDE_OK;

@@ -172,7 +172,25 @@ struct Op {
     // apply workspace
     DevBuf<double> ws;
     size_t apply_ws_doubles(int nrhs) const;
+    // a degree per element (the space S_N^P with degrees P_i, Section 2.2): the operator is built
+    // at P = max P_i on its Nd extended unknowns (the one-degree order); the space's own hp_nd
+    // unknowns (its order: bubbles element by element, then the hats) sit at d_hp_map among
+    // them, d_hp_keep marks them (1) and the outside ones (0), which every product decouples
+    bool hp = false;
+    int hp_nd = 0;
+    std::vector<int> hp_P;
+    DevBuf<int> d_hp_map;
+    DevBuf<double> d_hp_keep;
+    int pub_nd() const { return hp ? hp_nd : Nd; }   // unknowns of the public calls' vectors
 };
+
+// degree per element (hp.hip): Y = keep Y + (1 - keep) X over the extended unknowns (X null: 0;
+// nothing on a one-degree operator); public hp_nd-row columns <-> extended Nd-row columns
+// (scatter zero-fills the outside rows); Ap[i, j] = Ae[map i, map j]
+void hp_decouple(Op* op, int nrhs, const double* X, int ldx, double* Y, int ldy, hipStream_t st);
+void hp_scatter(Op* op, int nrhs, const double* Xp, int ldp, double* Xe, int lde, hipStream_t st);
+void hp_gather(Op* op, int nrhs, const double* Xe, int lde, double* Xp, int ldp, hipStream_t st);
+void hp_gather_matrix(Op* op, const double* Ae, int lde, double* Ap, int ldp, hipStream_t st);
 
 // a Gauss-Legendre panel [lo, hi] (distances from the end `side` of element elem: 0 left, 1 right)
 // of n nodes, the first at node0; ex >= 0: n nodes given explicitly from entry ex of the explicit

@@ -37,5 +37,10 @@ void launch_segcopy(hipStream_t st, int nseg, const SegDev* d_segs, const S* src
 template <class T>
 void launch_to_dense(hipStream_t st, int nleaf, const LeafDev* d_leaves, const T* arena, const int* ranks,
                      const int* perm, double* out, int ld);
+// degree per element (hp.hip): leaves of an H-matrix built at the largest degree with the rows
+// and columns of the outside unknowns zeroed and their diagonal entries 1 (h2p: internal ->
+// extended paper index)
+void hp_mask_leaves(Op* op, int nleaf, const LeafDev* d_leaves, const int* d_ranks, const int* d_h2p, double* arena,
+                    hipStream_t st);
 
 }  // namespace fde

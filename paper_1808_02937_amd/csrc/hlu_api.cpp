@@ -151,6 +151,12 @@ void build_hmat(fde_hmat* hm, Op* op, const fde_hparams* prm) {
     upload_vec(c, d_sides, sides);
     launch_hbuild_factors(op, R, sides, d_sides.p, hm->d_arena.p);
     upload_vec(c, hm->d_ranks, hm->init_rank);
+    if (op->hp) {   // a degree per element: the outside unknowns decoupled in every leaf
+        std::vector<LeafDev> lv = leaf_table(t);
+        DevBuf<LeafDev> d_lv;
+        upload_vec(c, d_lv, lv);
+        hp_mask_leaves(op, (int)lv.size(), d_lv.p, hm->d_ranks.p, hm->d_h2p.p, hm->d_arena.p, c->stream);
+    }
 }
 
 void report_profile(HLUObj* f, const char* what) {
@@ -718,12 +724,17 @@ int fde_hmat_counts(const fde_hmat* hm, int* nd, int* nr) {
 
 int fde_hmat_to_dense(fde_hmat* hm, double* out, int ld) {
     FDE_API_BEGIN
-    if (!hm || !out || ld < hm->t.op->Nd) fail(FDE_EINVAL, "bad arguments");
-    Ctx* c = hm->t.op->ctx;
+    if (!hm || !out || ld < hm->t.op->pub_nd()) fail(FDE_EINVAL, "bad arguments");
+    Op* op = hm->t.op;
+    Ctx* c = op->ctx;
     std::vector<LeafDev> lv = leaf_table(hm->t);
     DevBuf<LeafDev> d_lv;
     upload_vec(c, d_lv, lv);
-    launch_to_dense<double>(c->stream, (int)lv.size(), d_lv.p, hm->d_arena.p, hm->d_ranks.p, hm->d_h2p.p, out, ld);
+    DevBuf<double> ext;   // a degree per element: the extended matrix, then the space's part
+    if (op->hp) ext.alloc(c, (size_t)op->Nd * op->Nd);
+    launch_to_dense<double>(c->stream, (int)lv.size(), d_lv.p, hm->d_arena.p, hm->d_ranks.p, hm->d_h2p.p,
+                            op->hp ? ext.p : out, op->hp ? op->Nd : ld);
+    if (op->hp) hp_gather_matrix(op, ext.p, op->Nd, out, ld, c->stream);
     FDE_HIP(hipStreamSynchronize(c->stream));
     FDE_API_END
 }
@@ -839,6 +850,7 @@ void fde_hlu_destroy(fde_hlu* f) {
 int fde_hlu_to_dense(fde_hlu* f, double* out, int ld, int* h2p) {
     FDE_API_BEGIN
     if (!f || !out || ld < f->op->Nd) fail(FDE_EINVAL, "bad arguments");
+    if (f->op->hp) fail(FDE_EUNSUPPORTED, "fde_hlu_to_dense: one degree per operator only");
     Ctx* c = f->op->ctx;
     std::vector<LeafDev> lv = leaf_table(f->t());
     DevBuf<LeafDev> d_lv;
@@ -907,9 +919,21 @@ int fde_hlu_solve_variant(fde_hlu* f, int nrhs, int* variant, int* cols, long lo
 
 int fde_hlu_solve(fde_hlu* f, int nrhs, const double* B, int ldb, double* X, int ldx) {
     FDE_API_BEGIN
-    if (!f || nrhs < 0 || (nrhs && (!B || !X)) || ldb < f->op->Nd || ldx < f->op->Nd) fail(FDE_EINVAL, "bad arguments");
+    if (!f || nrhs < 0 || (nrhs && (!B || !X)) || ldb < f->op->pub_nd() || ldx < f->op->pub_nd())
+        fail(FDE_EINVAL, "bad arguments");
     if (nrhs == 0) return FDE_OK;
-    hlu_solve(f, nrhs, B, ldb, X, ldx);
+    Op* op = f->op;
+    if (!op->hp) {
+        hlu_solve(f, nrhs, B, ldb, X, ldx);
+        return FDE_OK;
+    }
+    // a degree per element: the columns on the extended unknowns and back
+    DevBuf<double> be, xe;
+    be.alloc(op->ctx, (size_t)op->Nd * nrhs);
+    xe.alloc(op->ctx, (size_t)op->Nd * nrhs);
+    hp_scatter(op, nrhs, B, ldb, be.p, op->Nd, op->ctx->stream);
+    hlu_solve(f, nrhs, be.p, op->Nd, xe.p, op->Nd);
+    hp_gather(op, nrhs, xe.p, op->Nd, X, ldx, op->ctx->stream);
     FDE_API_END
 }
 

@@ -796,6 +796,41 @@ void sigma_estimate(Op* op, HLUObj* f, int kind, int m, const double* v0_host, d
     *smin = out[1];
 }
 
+// run() with the systems of operators that have a degree per element taken to the extended
+// unknowns: their right-hand sides scattered (zero on the outside unknowns, which then stay zero
+// in every Krylov vector), their solutions gathered back
+void run_public(Ctx* c, int n, fde_op* const* ops, fde_hlu* const* precs, const int* nrhs, const double* const* G,
+                const int* ldg, double* const* X, const int* ldx, const fde_solve_params* prm, fde_solve_info* info,
+                int* rc_out) {
+    bool any = false;
+    for (int i = 0; i < n; ++i) any = any || (ops[i] && ops[i]->hp);
+    if (!any) {
+        run(c, n, ops, precs, nrhs, G, ldg, X, ldx, prm, info, rc_out);
+        return;
+    }
+    std::vector<const double*> g(G, G + n);
+    std::vector<double*> x(X, X + n);
+    std::vector<int> lg(ldg, ldg + n), lx(ldx, ldx + n);
+    std::vector<DevBuf<double>> ge(n), xe(n);
+    for (int i = 0; i < n; ++i) {
+        Op* op = ops[i];
+        if (!op || !op->hp || nrhs[i] <= 0) continue;
+        if (op->ctx != c) fail(FDE_EINVAL, "system %d: operator from another context", i);
+        if (!G[i] || !X[i] || ldg[i] < op->hp_nd || ldx[i] < op->hp_nd)
+            fail(FDE_EINVAL, "system %d: bad right-hand side arguments", i);
+        ge[i].alloc(c, (size_t)op->Nd * nrhs[i]);
+        xe[i].alloc(c, (size_t)op->Nd * nrhs[i]);
+        hp_scatter(op, nrhs[i], G[i], ldg[i], ge[i].p, op->Nd, c->stream);
+        g[i] = ge[i].p;
+        x[i] = xe[i].p;
+        lg[i] = lx[i] = op->Nd;
+    }
+    run(c, n, ops, precs, nrhs, g.data(), lg.data(), x.data(), lx.data(), prm, info, rc_out);
+    for (int i = 0; i < n; ++i)
+        if (ops[i]->hp && nrhs[i] > 0) hp_gather(ops[i], nrhs[i], xe[i].p, ops[i]->Nd, X[i], ldx[i], c->stream);
+    FDE_HIP(hipStreamSynchronize(c->stream));
+}
+
 }  // namespace fde
 
 using namespace fde;
@@ -811,7 +846,7 @@ int fde_solve(fde_op* op, fde_hlu* prec, int nrhs, const double* G, int ldg, dou
         fde_hlu* precs[1] = {prec};
         const double* Gs[1] = {G};
         double* Xs[1] = {X};
-        run(op->ctx, 1, ops, precs, &nrhs, Gs, &ldg, Xs, &ldx, prm, info, &rc);
+        run_public(op->ctx, 1, ops, precs, &nrhs, Gs, &ldg, Xs, &ldx, prm, info, &rc);
     } catch (const Error& e) {
         set_error("%s", e.msg.c_str());
         return e.code;
@@ -828,6 +863,7 @@ int fde_sigma_estimate(fde_op* op, fde_hlu* f, int kind, int steps, unsigned lon
                        double* smin) {
     FDE_API_BEGIN
     if (!op || !smax || !smin) fail(FDE_EINVAL, "null argument");
+    if (op->hp) fail(FDE_EUNSUPPORTED, "fde_sigma_estimate: one degree per operator only");
     // a seeded start vector with entries uniform in [-1, 1) (splitmix64), the same on every device
     std::vector<double> v0(op->Nd);
     unsigned long long x = seed;
@@ -853,7 +889,7 @@ int fde_solve_batched(fde_ctx* ctx, int n, fde_op* const* ops, fde_hlu* const* p
         std::vector<fde_op*> o(ops, ops + n);
         std::vector<fde_hlu*> p(n, nullptr);
         if (precs) std::copy(precs, precs + n, p.begin());
-        run(ctx, n, (fde_op* const*)o.data(), (fde_hlu* const*)p.data(), nrhs, G, ldg, X, ldx, prm, info, &rc);
+        run_public(ctx, n, (fde_op* const*)o.data(), (fde_hlu* const*)p.data(), nrhs, G, ldg, X, ldx, prm, info, &rc);
     } catch (const Error& e) {
         set_error("%s", e.msg.c_str());
         return e.code;

@@ -114,15 +114,23 @@ class Operator(_Handle):
 
     _destroy = "fde_op_destroy"
 
-    def __init__(self, ctx: Context, nodes, P: int, alpha: float, theta: float, rho: float,
+    def __init__(self, ctx: Context, nodes, P, alpha: float, theta: float, rho: float,
                  apply: str = "auto"):
+        """P: the degree of every element, or a sequence of N degrees (one per element)."""
         self.ctx = ctx
         x = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64))
         self.N = len(x) - 1
-        self.P, self.alpha, self.theta, self.rho = int(P), float(alpha), float(theta), float(rho)
+        self.alpha, self.theta, self.rho = float(alpha), float(theta), float(rho)
         h = C.c_void_p()
-        check(load().fde_op_create(ctx.h, _np_dptr(x), self.N, self.P, self.alpha, self.theta, self.rho,
-                                   _MODES[apply], C.byref(h)))
+        if np.ndim(P) == 0:
+            self.P, self.degrees = int(P), None
+            check(load().fde_op_create(ctx.h, _np_dptr(x), self.N, self.P, self.alpha, self.theta, self.rho,
+                                       _MODES[apply], C.byref(h)))
+        else:
+            self.degrees = np.ascontiguousarray(P, dtype=np.int32)
+            self.P = int(self.degrees.max())   # the operator's moments are of this degree
+            check(load().fde_op_create_hp(ctx.h, _np_dptr(x), self.N, self.degrees.ctypes.data_as(A.ip),
+                                          self.alpha, self.theta, self.rho, _MODES[apply], C.byref(h)))
         self._init_handle(h, ctx)
         self.Nd = int(load().fde_op_ndof(h))
         self.toeplitz = bool(load().fde_op_is_toeplitz(h))
