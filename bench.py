@@ -144,6 +144,37 @@ def graded_multi_rhs_solve(fde, torch, ctx, ranks=(4, 8, 16)):
     return out
 
 
+def hp_mesh_solve(fde, torch, ctx, N=256, nrhs=16):
+    """A degree per element: two-sided graded N=256 (20 layers of ratio 0.5 at each end), degrees
+    rising from 2 on the end layers to 12 in the middle (P_i = 2 + floor(10 min(i, N-1-i) / (N/2))),
+    alpha=1.7, theta=0.4, rho=1; 16 Gaussian right-hand sides: operator (built at degree 12 with
+    the other unknowns decoupled), H-matrix R=8 leaf 4, FP32 H-LU, one FGMRES over the 16
+    columns to 1e-10."""
+    nodes = fi.two_sided_graded_mesh(N, 20, 0.5)
+    Ps = np.array([2 + (10 * min(i, N - 1 - i)) // (N // 2) for i in range(N)], dtype=np.int32)
+    g = torch.Generator(device="cuda").manual_seed(1808029376)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = fde.Operator(ctx, nodes, Ps, 1.7, 0.4, 1.0)
+    G = torch.randn(nrhs, op.Nd, dtype=torch.float64, device="cuda", generator=g)
+    hm = fde.HMatrix(op, R=8, lam=1.0, leaf_elems=4)
+    lu = fde.HLU(hm, tol=1e-3, precision="fp32")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    X, infos = fde.solve(op, G, lu, rtol=1e-10)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    assert max(i["relres"] for i in infos) <= 1e-10
+    out = {"workload": f"two-sided graded N={N}, degrees 2..12 per element (Nd={op.Nd}; "
+                       f"{N * int(Ps.max()) - 1} at one degree 12), {nrhs} RHS, FP32 H-LU R=8, FGMRES to 1e-10",
+           "setup_ms": (t1 - t0) * 1e3, "solve_ms": (t2 - t1) * 1e3, "solves_per_s": nrhs / (t2 - t0),
+           "solves_per_s_solve_phase": nrhs / (t2 - t1), "iters_max": max(i["iters"] for i in infos)}
+    lu.close()
+    hm.close()
+    op.close()
+    return out
+
+
 def batched_uneven(fde, torch, ctx, count=256):
     """Uneven instances in shared launches: N ~ U{64..2048}, P ~ U{2..12}, alpha ~ U(1.1, 1.9),
     theta ~ U(0, 1), uniform or two-sided graded mesh, one right-hand side each: operators, load
@@ -416,7 +447,8 @@ def main():
         return
     if args.extra_only:
         print(json.dumps({"graded_multi_rhs": graded_multi_rhs_solve(fde, torch, ctx),
-                          "batched_uneven": batched_uneven(fde, torch, ctx)}))
+                          "batched_uneven": batched_uneven(fde, torch, ctx),
+                          "hp_mesh": hp_mesh_solve(fde, torch, ctx)}))
         return
     insts = make_instances()
     nsys = len(insts)
@@ -525,8 +557,12 @@ def main():
         out["graded_multi_rhs"] = graded_multi_rhs_solve(fde, torch, ctx)
         log("batched uneven instances")
         out["batched_uneven"] = batched_uneven(fde, torch, ctx)
+        log("degree per element")
+        out["hp_mesh"] = hp_mesh_solve(fde, torch, ctx)
         log("serving stream")
         out["serving"] = serving_stream(fde, torch, ctx)
+        log("serving stream, plain FP64 path")
+        out["serving_fp64"] = serving_stream(fde, torch, ctx, precision="fp64")
         out["latency_ms"] = {"p50": out["serving"]["p50_ms"], "p99": out["serving"]["p99_ms"],
                              "definition": "request completion - arrival, serving stream (see serving)",
                              "batch_p50": float(np.percentile(lat, 50) * 1e3),
