@@ -35,8 +35,8 @@ FP32_PEAK_TFLOPS = 157.3
 # dispatch, averaged over the k_level dispatches), each scaled by what the same counter reads for a
 # plain 256 MiB device copy (FETCH_SIZE reads half the bytes copied: x2; WRITE_SIZE reads them
 # all: x1). Valid for the kernel sources whose digest is recorded; `traffic` is null once they change.
-LEVEL_TRAFFIC = {"fetch_kib": 4160.1, "write_kib": 5819.2, "fetch_scale": 2.0, "write_scale": 1.0,
-                 "sources_sha256": "008e62d21d6c604b5705cae88f7dba94fbfcb28b3ac0222e276bd9b5e20e3ee1"}
+LEVEL_TRAFFIC = {"fetch_kib": 4161.3, "write_kib": 5819.3, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "sources_sha256": "625d752a10bde40ef2ec28eeb2694dfa6943be81adc07835d989bff30cfaed83"}
 LEVEL_SOURCES = ("paper_1808_02937_amd/csrc/hinterp.hip", "paper_1808_02937_amd/csrc/hinterp.h",
                  "paper_1808_02937_amd/csrc/tri_wave.h", "paper_1808_02937_amd/csrc/hmatrix.h",
                  "paper_1808_02937_amd/build.py")
@@ -61,8 +61,8 @@ def level_traffic_bytes():
 # HBM traffic of the moment-streaming kernel of the dense apply (two-sided graded N=4096, P=8, one
 # right-hand side), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by the
 # same counters on a plain device copy; valid for the apply sources whose digest is recorded.
-MATVEC_TRAFFIC = {"fetch_kib": 2099298.4, "write_kib": 131328.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                  "sources_sha256": "d8d1c55be4f78c5d402fa473bb9a8f170d7b8c9b6efd9ee6a667a8105f49b910"}
+MATVEC_TRAFFIC = {"fetch_kib": 2099303.2, "write_kib": 131328.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                  "sources_sha256": "ec7e5a9efb0b691656aa03452c60ef2f7f122f1491563961bcbb99b9509ca783"}
 MATVEC_SOURCES = ("paper_1808_02937_amd/csrc/apply.hip", "paper_1808_02937_amd/csrc/fde_internal.h",
                   "paper_1808_02937_amd/build.py")
 FP64_PEAK_TFLOPS = 78.6
