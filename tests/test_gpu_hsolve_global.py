@@ -9,7 +9,9 @@ fit in LDS (N = 4096 at P = 8 and beyond) -- on the GPU.
   op-list interpreter's (FDE_HSOLVE_VARIANT=ops: separate code over the same factors) within the
   1e-10 relative bound of FP64 solves.
 - At Nd = 65535 (N = 8192, P = 8, the largest operator of the serving mix) the FP32 H-LU, with its
-  low-rank factors in FP32 or BF16, preconditions FGMRES to a true relative residual of 1e-10."""
+  low-rank factors in FP32 or BF16, preconditions FGMRES to a true relative residual of 1e-10.
+- The op-list interpreter (the H-solve for leaves of more than 64 rows, and the forced variant)
+  against the oracle's H-solve, with the bounds of the leaf-step kernel."""
 import numpy as np
 import pytest
 import torch
@@ -158,4 +160,34 @@ def test_global_rhs_preconditions_fgmres_at_nd_65535(ctx):
         assert res <= 1e-10 and true <= 2e-10, (res, true)
         lu.close()
     assert max(its["bf16uv"]) <= max(its["fp32"]) + 3
+    op.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["forced", "leaves_over_64_rows"])
+def test_op_list_hsolve_matches_oracle(ctx, precision, case, monkeypatch):
+    import paper_1808_02937_amd as fde
+    if case == "forced":
+        nodes, P, leaf, al, th, rho = fi.two_sided_graded_mesh(48, 6, 0.5), 5, 4, 1.7, 0.4, 0.0
+    else:   # 8 elements of degree 16 per leaf: 128-row leaves, beyond the leaf-step kernel
+        nodes, P, leaf, al, th, rho = fi.uniform_mesh(40), 16, 8, 1.45, 0.6, 1.0
+    say(f"op-list H-solve ({case}), {precision}")
+    op, hm = operator(ctx, nodes, P, al, th, rho, R=6, leaf=leaf)
+    lu = fde.HLU(hm, tol=1e-3, precision=precision)
+    if case == "forced":
+        monkeypatch.setenv("FDE_HSOLVE_VARIANT", "ops")
+    assert lu.solve_variant(3)["variant"] == "ops"
+    g = np.random.default_rng(34).standard_normal((3, op.Nd))
+    x = lu.solve(torch.tensor(g, device="cuda")).cpu().numpy()
+    monkeypatch.delenv("FDE_HSOLVE_VARIANT", raising=False)
+    sem = SEM(nodes, P, al, th, rho)
+    oh = OHMatrix(sem, 6, 1.0, leaf)
+    xo = OHLU(oh, tol=1e-3).solve(g.T).T
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    eps = EPS64 if precision == "fp64" else EPS32
+    cap = 1e-13 if precision == "fp64" else 1e-5
+    bound = min(cap, 10 * kappa1(to_dense(oh.root)) * eps)
+    say(f"  vs oracle {err:.2e} (bound {bound:.2e})")
+    assert err <= bound, err
+    lu.close()
     op.close()
