@@ -46,7 +46,7 @@ extern "C" {
 #define FDE_EBREAKDOWN   -3   /* H-LU met a pivot below its floor (A~ not factorisable without pivoting) */
 #define FDE_ENOCONV      -4   /* the Krylov iteration hit maxit; X holds the last iterate, info.relres is set */
 #define FDE_EDEVICE      -5   /* a HIP runtime call failed */
-#define FDE_EUNSUPPORTED -6   /* a structure this build does not handle (message says which) */
+#define FDE_EUNSUPPORTED -6   /* a structure the library does not handle (message says which) */
 
 /* precision of the H-LU factors and H-solves */
 #define FDE_FP64          0   /* everything in FP64 (the plain FP64 path) */

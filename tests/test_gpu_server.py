@@ -176,3 +176,33 @@ def test_continuous_serving_waits_for_memory(ctx):
         assert all(s == 0 for (_, _, s) in res[t][0])
         assert true_relres(p, G, X) <= 5e-12
     srv.close()
+
+
+def test_continuous_serving_large_operator_bf16(ctx):
+    """A request whose right-hand sides are too long for LDS (uniform N = 4096, P = 8: the H-solve
+    keeps them in global memory) served with BF16 low-rank factors, alone and beside a small one in
+    the same launches (which then take the global-memory variant too): the same bits either way,
+    and the true residual of the large request at the requested 1e-10."""
+    import paper_1808_02937_amd as fde
+    say("continuous serving: N = 4096 with BF16 U, V, alone and in a mix")
+    big = (fi.uniform_mesh(4096), 8, 1.35, 0.45, 1.0)
+    small = PROBS[0]
+    GL, GS = rhs(big, 2, 91), rhs(small, 3, 92)
+    out = {}
+    for name, reqs in (("big", [(big, GL)]), ("small", [(small, GS)]), ("mix", [(big, GL), (small, GS)])):
+        srv = fde.Server(ctx, R=8, leaf_elems=8, tol=1e-3, precision="bf16uv", rtol=1e-10)
+        subs = [srv.submit(p, G) for p, G in reqs]
+        srv.drain()
+        res = _collect(srv, [t for t, _ in subs])
+        for (t, _), (p, _) in zip(subs, reqs):
+            assert all(s == 0 and r <= 1e-10 for (_, r, s) in res[t][0]), res[t]
+        out[name] = [X for _, X in subs]
+        srv.close()
+    assert torch.equal(out["mix"][0], out["big"][0])
+    assert torch.equal(out["mix"][1], out["small"][0])
+    op = fde.Operator(ctx, *big)
+    R = GL - op.apply(out["big"][0])
+    true = float((torch.linalg.norm(R, dim=1) / torch.linalg.norm(GL, dim=1)).max())
+    say(f"  large request: recomputed true residual {true:.1e}")
+    assert true <= 2e-10
+    op.close()
