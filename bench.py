@@ -260,6 +260,56 @@ class Pipeline:
         return infos
 
 
+def run_pipelines(torch, pipes, steps, keep_last=False, verbose=False):
+    """Each pipeline runs `steps` steps in its own thread on its own stream; the timed region starts
+    with every thread at a barrier and the device synchronised, and ends when all have joined and the
+    device is synchronised again. Returns (seconds, batch latencies, last infos of pipeline 0)."""
+    import threading
+    n = len(pipes)
+    lat = [[] for _ in range(n)]
+    infos = [None] * n
+    errors = []
+    gate = threading.Barrier(n + 1)
+
+    def worker(i):
+        p = pipes[i]
+        try:
+            with torch.cuda.stream(p.ctx._stream):
+                gate.wait()
+                for k in range(steps):
+                    ts = time.perf_counter()
+                    infos[i] = p.step(keep=keep_last and k == steps - 1)
+                    p.ctx._stream.synchronize()
+                    lat[i].append(time.perf_counter() - ts)
+                    if verbose:
+                        sp = " ".join(f"{x * 1e3:.1f}" for x in p.split)
+                        log(f"pipeline {i} step {k}: {lat[i][-1] * 1e3:.1f} ms (host: operators + load vectors + "
+                            f"H-matrices, H-LU, solve: {sp} ms)")
+        except BaseException as e:   # reported by the main thread
+            errors.append(e)
+            gate.abort()
+
+    th = [threading.Thread(target=worker, args=(i,)) for i in range(n)]
+    for t in th:
+        t.start()
+    torch.cuda.synchronize()
+    try:
+        gate.wait()
+    except threading.BrokenBarrierError:
+        pass
+    t0 = time.perf_counter()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    if errors:
+        raise errors[0]
+    for i in range(n):
+        for inf in infos[i]:
+            assert max(x["relres"] for x in inf) <= 1e-10
+    return total, [x for l in lat for x in l], infos[0]
+
+
 def timed(torch, fn, reps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -427,6 +477,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--pipelines", type=int, default=3,
+                    help="batches in flight: each pipeline runs its steps on its own context and stream "
+                         "(a process has 4 hardware queues, one of them taken by the default stream)")
+    ap.add_argument("--apply-streams", type=int, default=0,
+                    help="side streams per pipeline for the per-operator applies (0: its one stream)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the extra measurements")
     ap.add_argument("--matvec-only", action="store_true",
@@ -452,32 +507,29 @@ def main():
         return
     insts = make_instances()
     nsys = len(insts)
+    npipe = max(1, args.pipelines)
+    # the timed pipelines: each on its own context and stream (default priority), driven by its own
+    # host thread (the library calls release the interpreter lock), so one batch's latency-bound
+    # kernels overlap another's
+    pctx = [fde.Context(0, stream=torch.cuda.Stream(), apply_streams=args.apply_streams) for _ in range(npipe)]
+    pipes = [Pipeline(fde, c, insts, "fp32") for c in pctx]
     mixed = Pipeline(fde, ctx, insts, "fp32")
     fp64 = Pipeline(fde, ctx, insts, "fp64")
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        mixed.step()
+    log(f"warmup {args.warmup} (each of {npipe} pipelines)")
+    for p in pipes:
+        with torch.cuda.stream(p.ctx._stream):
+            for _ in range(args.warmup):
+                p.step()
     # one full collection before the timed region, and the objects alive then kept out of later
     # ones: a collection of the whole heap (torch, numpy, the warm-up's objects) inside a timed
     # step costs tens of milliseconds of host time
     gc.collect()
     gc.freeze()
-    log(f"timing {args.steps} steps")
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = None
-    for k in range(args.steps):
-        ts = time.perf_counter()
-        infos = mixed.step(keep=(k == args.steps - 1))
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - ts)
-        sp = " ".join(f"{x * 1e3:.1f}" for x in mixed.split)
-        log(f"step {k}: {lat[-1] * 1e3:.1f} ms (host: operators + load vectors + H-matrices, H-LU, solve: {sp} ms)")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
+    log(f"timing {args.steps} steps of {npipe} pipelines")
+    total, lat, infos = run_pipelines(torch, pipes, args.steps, keep_last=True, verbose=True)
     ms_per_step = total / args.steps * 1e3
-    value = nsys * args.steps / total
+    value = npipe * nsys * args.steps / total
+    mixed.kept = pipes[0].kept
     relres = max(i[0]["relres"] for i in infos)
     iters = [i[0]["iters"] for i in infos]
     assert relres <= 1e-10, relres
@@ -486,11 +538,12 @@ def main():
            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64 (H-LU and H-solves f32)", "data": "synthetic",
            "config": {"workload": "uniform N=1024 P=8 (Nd=8191), 3x3 alpha x theta grid, rho=1, 1 RHS each, "
-                                  "H-LU R=8 FP32 tol 1e-3, FGMRES(30) to 1e-10 true residual, end to end",
-                      "systems_per_step": nsys},
+                                  "H-LU R=8 FP32 tol 1e-3, FGMRES(30) to 1e-10 true residual, end to end; "
+                                  f"{npipe} batches of the nine in flight (one per context and stream)",
+                      "systems_per_step": npipe * nsys, "pipelines": npipe},
            "iters": iters, "max_relres": relres,
            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
-                          "definition": "batch completion time (every request of a step arrives at its start)"}}
+                          "definition": "batch completion time (every request of a batch arrives at its start)"}}
     # roofline of the dominant kernel: the level launches of the batched H-LU (launch l runs
     # level l of all nine factorisations; the nine share one structure, so one launch per level),
     # from the last timed step: its device-counted flops and its HIP-event time on the library stream
@@ -512,7 +565,22 @@ def main():
                        "launches": nlaunch, "flops_per_launch": flops / nlaunch, "launch_ms": kms / nlaunch,
                        "hlu_ms": kms, "ops_per_factorisation": plan["ops"],
                        "flops_source": "device counters (per op, actual dims and ranks)",
-                       "device_flops_per_operator": [min(dev_flops), max(dev_flops)]}
+                       "device_flops_per_operator": [min(dev_flops), max(dev_flops)],
+                       "pipelines": npipe,
+                       "timing": (f"HIP events on pipeline 0's stream over its last timed factorisation, with "
+                                  f"{npipe - 1} other pipelines' work running beside it")}
+    # the same factorisation with nothing else on the device: one more step of pipeline 0 alone
+    with torch.cuda.stream(pipes[0].ctx._stream):
+        pipes[0].step(keep=True)
+        pipes[0].ctx._stream.synchronize()
+    a_ops, a_lus = pipes[0].kept
+    kms_alone = a_lus[0].stats()[1]
+    out["roofline"]["hlu_ms_alone"] = kms_alone
+    out["roofline"]["launch_ms_alone"] = kms_alone / nlaunch
+    out["roofline"]["frac_alone"] = flops / (kms_alone * 1e-3) / 1e12 / FP32_PEAK_TFLOPS
+    for o in a_ops:
+        o.close()
+    pipes[0].kept = None
     for o in kept_ops:
         o.close()
     mixed.kept = None
@@ -521,9 +589,20 @@ def main():
     if not args.quick:
         # plain FP64 path, same algorithm
         log("fp64 path")
-        fp64.step()
-        t64, _ = timed(torch, fp64.step, max(1, args.steps // 2))
-        out["fp64_path"] = {"value": nsys / t64, "unit": "solves/s", "ms_per_step": t64 * 1e3}
+        p64 = [Pipeline(fde, c, insts, "fp64") for c in pctx]
+        for p in p64:
+            with torch.cuda.stream(p.ctx._stream):
+                p.step()
+        k64 = max(1, args.steps // 2)
+        t64, lat64, _ = run_pipelines(torch, p64, k64)
+        out["fp64_path"] = {"value": npipe * nsys * k64 / t64, "unit": "solves/s", "ms_per_step": t64 / k64 * 1e3,
+                            "pipelines": npipe, "batch_latency_p50_ms": float(np.percentile(lat64, 50) * 1e3)}
+        # one pipeline (no batches overlapping), mixed and FP64
+        t1, lat1, _ = run_pipelines(torch, pipes[:1], args.steps)
+        t641, _, _ = run_pipelines(torch, p64[:1], k64)
+        out["single_pipeline"] = {"mixed": nsys * args.steps / t1, "fp64": nsys * k64 / t641, "unit": "solves/s",
+                                  "mixed_ms_per_step": t1 / args.steps * 1e3,
+                                  "batch_latency_p50_ms": float(np.percentile(lat1, 50) * 1e3)}
         # solve phase with cached factors
         ops, Gs, hms, lus = mixed.setup()
         ts, r = timed(torch, lambda: mixed.solve(ops, Gs, lus), 5)
@@ -592,6 +671,7 @@ def main():
         of = 9.0 * cb["hlu_flops"]
         rf["achieved"] = of / (rf["hlu_ms"] * 1e-3) / 1e12
         rf["frac"] = rf["achieved"] / FP32_PEAK_TFLOPS
+        rf["frac_alone"] = of / (rf["hlu_ms_alone"] * 1e-3) / 1e12 / FP32_PEAK_TFLOPS
         rf["flops_per_launch"] = of / rf["launches"]
         rf["flops_source"] = ("oracle's instrumented H-LU of the alpha=1.5, theta=0.5 operator (Householder QR + "
                               "SVD truncation, counted per primitive) x 9")

@@ -107,6 +107,11 @@ int  fde_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, fde_c
 void fde_ctx_destroy(fde_ctx* ctx);
 /* switch the context to another stream (waits for the work queued on the old one) */
 int  fde_ctx_set_stream(fde_ctx* ctx, void* hip_stream);
+/* Side streams (0 to 3, default 3; default priority) the context may fork the
+ * per-operator applies of a batched Krylov step onto. 0 keeps all of a
+ * context's work on its stream: for several contexts driven side by side,
+ * where every stream takes one of the process's few hardware queues. */
+int  fde_ctx_set_apply_streams(fde_ctx* ctx, int n);
 /* bytes of device memory the context's live objects currently hold (rounded up
  * to the allocator's block sizes; cached free blocks are not counted) */
 size_t fde_ctx_bytes_in_use(const fde_ctx* ctx);

@@ -74,6 +74,7 @@ SIGNATURES = {
     "fde_ctx_create": (i32, [i32, vp, sz, C.POINTER(vp)]),
     "fde_ctx_destroy": (None, [vp]),
     "fde_ctx_set_stream": (i32, [vp, vp]),
+    "fde_ctx_set_apply_streams": (i32, [vp, i32]),
     "fde_ctx_bytes_in_use": (sz, [vp]),
     "fde_op_create": (i32, [vp, dp, i32, i32, f64, f64, f64, i32, C.POINTER(vp)]),
     "fde_op_create_hp": (i32, [vp, dp, i32, ip, f64, f64, f64, i32, C.POINTER(vp)]),

@@ -525,6 +525,14 @@ int fde_ctx_set_stream(fde_ctx* c, void* s) {
     FDE_API_END
 }
 
+int fde_ctx_set_apply_streams(fde_ctx* c, int n) {
+    FDE_API_BEGIN
+    if (!c || n < 0 || n > 3) fail(FDE_EINVAL, "need a context and 0 <= n <= 3 (got %d)", n);
+    FDE_HIP(hipStreamSynchronize(c->stream));
+    c->nside = n;
+    FDE_API_END
+}
+
 size_t fde_ctx_bytes_in_use(const fde_ctx* c) { return c ? c->in_use : 0; }
 
 int fde_op_create(fde_ctx* c, const double* nodes, int N, int P, double alpha, double theta, double rho,

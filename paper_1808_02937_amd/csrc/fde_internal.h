@@ -141,6 +141,7 @@ struct Ctx {
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> side_done;
     hipEvent_t fork_ev = nullptr;
+    int nside = 3;   // side streams the applies may use (0: everything on `stream`)
 };
 
 // ---------------------------------------------------------------- operator

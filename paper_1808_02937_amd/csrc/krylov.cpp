@@ -42,13 +42,12 @@ struct Group {
 
 // The per-operator applies of a Krylov step are independent small kernel chains (a few
 // workgroups each). They run concurrently: the groups are spread over the context's stream and up
-// to kSideStreams side streams, forked after the work queued so far and joined back before the
-// next step. Groups of one operator share a stream, since the operator's workspace is theirs.
-constexpr int kSideStreams = 3;
-
+// to c->nside side streams (3 unless set otherwise), forked after the work queued so far and joined
+// back before the next step. Groups of one operator share a stream, since the operator's workspace
+// is theirs.
 void ensure_side_streams(Ctx* c) {
-    if (!c->side.empty()) return;
-    for (int k = 0; k < kSideStreams; ++k) {
+    if ((int)c->side.size() >= c->nside) return;
+    for (int k = (int)c->side.size(); k < c->nside; ++k) {
         hipStream_t s = nullptr;
         FDE_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         c->side.push_back(s);
@@ -56,7 +55,7 @@ void ensure_side_streams(Ctx* c) {
         FDE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         c->side_done.push_back(e);
     }
-    FDE_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    if (!c->fork_ev) FDE_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
 }
 
 // fn(group, stream) for every group with right-hand sides
@@ -65,23 +64,24 @@ void apply_groups(Ctx* c, std::vector<Group>& groups, F fn) {
     int active = 0;
     for (auto& g : groups)
         if (g.nr) ++active;
-    if (active <= 1) {
+    if (active <= 1 || c->nside == 0) {
         for (auto& g : groups)
             if (g.nr) fn(g, c->stream);
         return;
     }
     ensure_side_streams(c);
+    const int ns = c->nside;
     FDE_HIP(hipEventRecord(c->fork_ev, c->stream));
-    for (hipStream_t s : c->side) FDE_HIP(hipStreamWaitEvent(s, c->fork_ev, 0));
+    for (int k = 0; k < ns; ++k) FDE_HIP(hipStreamWaitEvent(c->side[k], c->fork_ev, 0));
     std::vector<Op*> seen;   // operator -> stream slot (0: the context's stream)
     for (auto& g : groups) {
         if (!g.nr) continue;
         size_t slot = std::find(seen.begin(), seen.end(), g.op) - seen.begin();
         if (slot == seen.size()) seen.push_back(g.op);
-        const int k = (int)(slot % (kSideStreams + 1));
+        const int k = (int)(slot % (ns + 1));
         fn(g, k == 0 ? c->stream : c->side[k - 1]);
     }
-    for (int k = 0; k < kSideStreams; ++k) {
+    for (int k = 0; k < ns; ++k) {
         FDE_HIP(hipEventRecord(c->side_done[k], c->side[k]));
         FDE_HIP(hipStreamWaitEvent(c->stream, c->side_done[k], 0));
     }
@@ -578,21 +578,22 @@ void engine_hsolve(KrylovEngine* e, std::vector<EGroup*>& run, DevBuf<Inst<T>>& 
 // fn(group, stream) over groups, each operator's groups on one of the context's streams
 template <class F>
 void engine_apply(Ctx* c, std::vector<EGroup*>& gs, F fn) {
-    if (gs.size() <= 1) {
+    if (gs.size() <= 1 || c->nside == 0) {
         for (EGroup* g : gs) fn(*g, c->stream);
         return;
     }
     ensure_side_streams(c);
+    const int ns = c->nside;
     FDE_HIP(hipEventRecord(c->fork_ev, c->stream));
-    for (hipStream_t s : c->side) FDE_HIP(hipStreamWaitEvent(s, c->fork_ev, 0));
+    for (int k = 0; k < ns; ++k) FDE_HIP(hipStreamWaitEvent(c->side[k], c->fork_ev, 0));
     std::vector<Op*> seen;
     for (EGroup* g : gs) {
         size_t slot = std::find(seen.begin(), seen.end(), g->op) - seen.begin();
         if (slot == seen.size()) seen.push_back(g->op);
-        const int k = (int)(slot % (kSideStreams + 1));
+        const int k = (int)(slot % (ns + 1));
         fn(*g, k == 0 ? c->stream : c->side[k - 1]);
     }
-    for (int k = 0; k < kSideStreams; ++k) {
+    for (int k = 0; k < ns; ++k) {
         FDE_HIP(hipEventRecord(c->side_done[k], c->side[k]));
         FDE_HIP(hipStreamWaitEvent(c->stream, c->side_done[k], 0));
     }

@@ -85,7 +85,10 @@ class Context(_Handle):
 
     _destroy = "fde_ctx_destroy"
 
-    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None, budget_bytes: int = 0):
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None, budget_bytes: int = 0,
+                 apply_streams: int = 3):
+        """apply_streams: side streams for the per-operator applies of a batched Krylov step (0 keeps
+        everything on `stream`, e.g. for several contexts driven side by side)."""
         lib = load()
         self.device = torch.device("cuda", device)
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -94,6 +97,8 @@ class Context(_Handle):
         check(lib.fde_ctx_create(device, C.c_void_p(s.cuda_stream), budget_bytes, C.byref(h)))
         self._init_handle(h)
         A.register_root(self)
+        if apply_streams != 3:
+            check(lib.fde_ctx_set_apply_streams(h, int(apply_streams)))
 
     def set_stream(self, stream: torch.cuda.Stream):
         self._stream = stream
