@@ -371,16 +371,20 @@ def cpu_model():
 
 
 def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=1808029375, n_keys=128, n_max=8192,
-                   precision="bf16uv"):
+                   precision="bf16uv", shards=3):
     """Continuous serving of a request stream (Section 5's problem class, many keys).
 
     A pool of n_keys problems: N log-uniform in [128, n_max], P in {4, 6, 8}, alpha ~ U(1.1, 1.9),
     theta ~ U(0, 1), rho = 0 with probability 1/3 else log-uniform in [1e-2, 1e2], uniform or
     two-sided graded mesh (50/50). Requests pick a problem with Zipf(1.1) reuse and carry U{1..16}
-    Gaussian right-hand sides. Every problem is built once first; the saturated rate is measured
-    with all requests submitted at once; then requests arrive as a Poisson process at `load` times
-    that rate and join the server between its steps (fde_server_submit / fde_server_step), while
-    others are in flight. Latency = completion - arrival over n_req requests after n_warm."""
+    Gaussian right-hand sides. The keys are spread over `shards` servers (heaviest first, each to the
+    least loaded), each on its own context and stream and driven by its own host thread, so a key's
+    factors live in one server and the servers' latency-bound steps overlap on the device. Every
+    problem is built once first; the saturated rate is measured with all requests submitted at once;
+    then requests arrive as a Poisson process at `load` times that rate and join their server between
+    its steps (fde_server_submit / fde_server_step), while others are in flight. Latency =
+    completion - arrival over n_req requests after n_warm."""
+    import threading
     gen = np.random.default_rng(seed)
     pool = []
     for _ in range(n_keys):
@@ -395,81 +399,132 @@ def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=18080
     total = n_req + n_warm
     keys = gen.choice(len(pool), size=total, p=w)
     nrhs = gen.integers(1, 17, size=total)
+    # keys to servers by expected load: Zipf weight times the time of one Krylov step, an H-solve
+    # (about 0.2 us per unknown, a chain of leaf steps) plus an apply (on a graded mesh the dense
+    # moment stream, 8 P^2 N^2 / 2 bytes at about 4.4 TB/s; on a uniform one, small)
+    def step_us(k):
+        nodes, P = pool[k][0], pool[k][1]
+        N = len(nodes) - 1
+        uniform = np.allclose(np.diff(nodes), nodes[1] - nodes[0])
+        return 0.2 * (N * P - 1) + (0.0 if uniform else 8.0 * P * P * N * N / 2 / 4.4e6)
+    owner = np.zeros(len(pool), dtype=int)
+    loadw = np.zeros(shards)
+    cost = np.array([w[k] * step_us(k) for k in range(len(pool))])
+    for k in np.argsort(-cost):
+        j = int(np.argmin(loadw))
+        owner[k] = j
+        loadw[j] += cost[k]
     # cached factors: FP32 dense blocks and BF16 low-rank factors (or the plain FP64 path)
-    srv = fde.Server(ctx, R=8, leaf_elems=8, tol=1e-3, precision=precision, rtol=1e-10)
-    tg = torch.Generator(device="cuda").manual_seed(seed)
+    ctxs = [fde.Context(0, stream=torch.cuda.Stream(), apply_streams=0) for _ in range(shards)]
+    srvs = [fde.Server(c, R=8, leaf_elems=8, tol=1e-3, precision=precision, rtol=1e-10) for c in ctxs]
+    gens = [torch.Generator(device="cuda").manual_seed(seed + j) for j in range(shards)]
 
-    def rhs_of(key, k):
+    def rhs_of(j, key, k):
         nodes, P = pool[key][0], pool[key][1]
         Nd = (len(nodes) - 1) * P - 1
-        return torch.randn(int(k), Nd, dtype=torch.float64, device="cuda", generator=tg)
+        return torch.randn(int(k), Nd, dtype=torch.float64, device="cuda", generator=gens[j])
 
     def check(inf):
         for (_, rel, st) in inf:
             if st != 0 or not rel <= 1e-10:
                 raise RuntimeError(f"serving: a request did not converge ({st}, {rel})")
 
-    def run_all(reqs):   # submit everything, step until done
-        ts = [srv.submit(pool[k], rhs_of(k, r))[0] for k, r in reqs]
+    def in_threads(fn):   # fn(j) for every server, each in its own thread on its own stream
+        errors = []
+
+        def body(j):
+            try:
+                with torch.cuda.stream(ctxs[j]._stream):
+                    fn(j)
+                    ctxs[j]._stream.synchronize()
+            except BaseException as e:
+                errors.append(e)
+        th = [threading.Thread(target=body, args=(j,)) for j in range(shards)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        if errors:
+            raise errors[0]
+
+    def run_all(j, reqs):   # submit everything, step until done
+        srv = srvs[j]
+        ts = [srv.submit(pool[k], rhs_of(j, k, r))[0] for k, r in reqs if owner[k] == j]
         srv.drain()
         for t in ts:
             done, inf, _ = srv.poll(t)
             check(inf)
 
     # every problem built once (their factors stay cached), then the saturated rate
+    torch.cuda.synchronize()
     t = time.perf_counter()
-    run_all([(k, 1) for k in range(len(pool))])
+    in_threads(lambda j: run_all(j, [(k, 1) for k in range(len(pool))]))
     t_build = time.perf_counter() - t
     sat_n = 200
     t = time.perf_counter()
-    run_all(list(zip(keys[:sat_n], nrhs[:sat_n])))
+    in_threads(lambda j: run_all(j, list(zip(keys[:sat_n], nrhs[:sat_n]))))
     sat = sat_n / (time.perf_counter() - t)   # requests/s
     rate = load * sat
     arrivals = np.cumsum(gen.exponential(1.0 / rate, size=total))
     lat = np.zeros(total)
-    open_t = {}
-    cached_hits = 0
-    steps = 0
-    inflight_sum = 0
-    t0 = time.perf_counter()
-    nxt = 0
-    n_done = 0
-    while n_done < total:
-        now = time.perf_counter() - t0
-        while nxt < total and arrivals[nxt] <= now:
-            tk, _ = srv.submit(pool[keys[nxt]], rhs_of(keys[nxt], nrhs[nxt]))
-            open_t[tk] = nxt
-            nxt += 1
-        if not open_t:
-            time.sleep(max(0.0, min(arrivals[nxt] - now, 0.002)))
-            continue
-        inflight_sum += srv.step()
-        steps += 1
-        tnow = time.perf_counter() - t0
-        for tk in list(open_t):
-            done, inf, cached = srv.poll(tk)
-            if done:
-                check(inf)
-                i = open_t.pop(tk)
-                lat[i] = tnow - arrivals[i]
-                cached_hits += int(cached)
-                n_done += 1
-    elapsed = time.perf_counter() - t0
+    hits = np.zeros(shards, dtype=int)
+    steps = np.zeros(shards, dtype=int)
+    inflight = np.zeros(shards, dtype=int)
+    t0 = [0.0]
+    gate = threading.Barrier(shards, action=lambda: t0.__setitem__(0, time.perf_counter()))
+
+    def serve(j):
+        srv = srvs[j]
+        mine = [i for i in range(total) if owner[keys[i]] == j]
+        open_t = {}
+        nxt = 0
+        n_done = 0
+        gate.wait()
+        while n_done < len(mine):
+            now = time.perf_counter() - t0[0]
+            while nxt < len(mine) and arrivals[mine[nxt]] <= now:
+                i = mine[nxt]
+                tk, _ = srv.submit(pool[keys[i]], rhs_of(j, keys[i], nrhs[i]))
+                open_t[tk] = i
+                nxt += 1
+            if not open_t:
+                time.sleep(max(0.0, min(arrivals[mine[nxt]] - now, 0.002)))
+                continue
+            inflight[j] += srv.step()
+            steps[j] += 1
+            tnow = time.perf_counter() - t0[0]
+            for tk in list(open_t):
+                done, inf, cached = srv.poll(tk)
+                if done:
+                    check(inf)
+                    i = open_t.pop(tk)
+                    lat[i] = tnow - arrivals[i]
+                    hits[j] += int(cached)
+                    n_done += 1
+
+    in_threads(serve)
+    elapsed = time.perf_counter() - t0[0]
     meas = lat[n_warm:] * 1e3
-    st = srv.stats()
-    srv.close()
+    st = {}
+    for srv in srvs:
+        for k, v in srv.stats().items():
+            st[k] = st.get(k, 0) + v
+        srv.close()
+    for c in ctxs:
+        c.close()
     return {"requests": n_req, "warmup_requests": n_warm, "keys": len(pool), "rhs_per_request": "U{1..16}",
-            "N_range": [128, n_max], "build_all_keys_s": t_build,
+            "N_range": [128, n_max], "build_all_keys_s": t_build, "servers": shards,
             "saturated_requests_per_s": sat, "arrival_rate_per_s": rate, "load": load,
             "p50_ms": float(np.percentile(meas, 50)), "p99_ms": float(np.percentile(meas, 99)),
             "mean_ms": float(meas.mean()), "solves_per_s": float(nrhs.sum() / elapsed),
-            "server_steps": steps, "mean_requests_in_flight": inflight_sum / max(steps, 1),
+            "server_steps": int(steps.sum()), "mean_requests_in_flight": float(inflight.sum() / max(steps.sum(), 1)),
             "cache": st,
             "cached_factor_precision": {"bf16uv": "FP32 dense blocks, BF16 U and V", "fp32": "FP32",
                                         "fp64": "FP64"}[precision],
-            "admitted_with_cached_factors": cached_hits,
+            "admitted_with_cached_factors": int(hits.sum()),
             "definition": ("latency = completion - arrival; Poisson arrivals; continuous batching (requests join "
-                           "the server between FGMRES steps while others are in flight)")}
+                           "their server between FGMRES steps while others are in flight); keys spread over "
+                           f"{shards} servers, each on its own context, stream and host thread")}
 
 
 def main():
@@ -642,6 +697,11 @@ def main():
         out["serving"] = serving_stream(fde, torch, ctx)
         log("serving stream, plain FP64 path")
         out["serving_fp64"] = serving_stream(fde, torch, ctx, precision="fp64")
+        log("serving stream, one server")
+        one = serving_stream(fde, torch, ctx, shards=1)
+        out["serving_one_server"] = {k: one[k] for k in ("saturated_requests_per_s", "arrival_rate_per_s", "p50_ms",
+                                                         "p99_ms", "mean_ms", "solves_per_s",
+                                                         "mean_requests_in_flight")}
         out["latency_ms"] = {"p50": out["serving"]["p50_ms"], "p99": out["serving"]["p99_ms"],
                              "definition": "request completion - arrival, serving stream (see serving)",
                              "batch_p50": float(np.percentile(lat, 50) * 1e3),
