@@ -486,7 +486,7 @@ void make_plan_host(const HTree& hmt, int kmax, Plan& p, bool check) {
     gen_hlu(p.t, p.lu);
     Program original;
     if (check) original = p.lu;
-    schedule_levels(p.t, p.lu);
+    schedule_levels(p.t, p.lu, check);
     if (check) check_schedule(p.t, original, p.lu);
     gen_hsolve(p.t, p.sv);
     gen_hsolve_steps(p.t, p.hs);

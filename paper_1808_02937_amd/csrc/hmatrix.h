@@ -97,7 +97,7 @@ struct Program {
     std::vector<int> level_off;
     std::vector<int> origin;         // program-order index of every scheduled op
     int64_t scr_t = 0, scr_d = 0;    // recompression scratch of one level (factor type, doubles)
-    // dependencies (schedule_levels): scheduled op i may start once the scheduled ops
+    // dependencies (schedule_levels with_deps): scheduled op i may start once the scheduled ops
     // deps[dep_off[i] .. dep_off[i+1]) have finished (all earlier in the level order). They cover
     // every conflicting access to the same memory, temporaries sharing memory included; recompression
     // scratch is private to a level and not covered.
@@ -187,7 +187,8 @@ void lrsub_need(const HTree& hm, const OpRec& o, int64_t* t_elems, int64_t* d_el
 // schedule.cpp: reorder a factorisation program into levels of mutually independent ops
 // (every op after all ops it conflicts with), give the temporaries memory by their level
 // lifetimes and every OP_LRSUB private scratch within its level
-void schedule_levels(const HTree& hm, Program& prog);
+// with_deps: also the per-op dependency lists (dep_off, deps; otherwise left empty)
+void schedule_levels(const HTree& hm, Program& prog, bool with_deps);
 // element-by-element check of a schedule against the program order it came from
 // (host, slow: tests and diagnostics); fails with FDE_EDEVICE on a violated dependency
 void check_schedule(const HTree& hm, const Program& original, const Program& scheduled);

@@ -173,7 +173,7 @@ void accesses(const HTree& hm, const Regions& R, const OpRec& o, std::vector<Rec
 
 }  // namespace
 
-void schedule_levels(const HTree& hm, Program& prog) {
+void schedule_levels(const HTree& hm, Program& prog, bool with_deps) {
     const size_t nops = prog.ops.size();
     Regions R(hm, prog);
     std::vector<std::vector<Acc>> hist(R.size());
@@ -185,19 +185,22 @@ void schedule_levels(const HTree& hm, Program& prog) {
     for (size_t pc = 0; pc < nops; ++pc) {
         accesses(hm, R, prog.ops[pc], rd, wr);
         // dependencies: the last writes of what the op reads, every access since of what it writes
-        std::vector<int>& pp = preds[pc];
-        for (const Rect& x : rd)
-            for (const OpAcc& a : ohist[x.region])
-                if (a.write && overlap(x, a)) pp.push_back(a.pc);
-        for (const Rect& x : wr)
-            for (const OpAcc& a : ohist[x.region])
-                if (overlap(x, a)) pp.push_back(a.pc);
-        for (const Rect& x : wr) {
-            auto& h = ohist[x.region];
-            h.erase(std::remove_if(h.begin(), h.end(), [&](const OpAcc& a) { return contains(x, a); }), h.end());
+        // (kept per op, unmerged, so they cost more than the levels: only when asked for)
+        if (with_deps) {
+            std::vector<int>& pp = preds[pc];
+            for (const Rect& x : rd)
+                for (const OpAcc& a : ohist[x.region])
+                    if (a.write && overlap(x, a)) pp.push_back(a.pc);
+            for (const Rect& x : wr)
+                for (const OpAcc& a : ohist[x.region])
+                    if (overlap(x, a)) pp.push_back(a.pc);
+            for (const Rect& x : wr) {
+                auto& h = ohist[x.region];
+                h.erase(std::remove_if(h.begin(), h.end(), [&](const OpAcc& a) { return contains(x, a); }), h.end());
+            }
+            for (const Rect& x : rd) ohist[x.region].push_back(OpAcc{x.r0, x.r1, x.c0, x.c1, (int)pc, false});
+            for (const Rect& x : wr) ohist[x.region].push_back(OpAcc{x.r0, x.r1, x.c0, x.c1, (int)pc, true});
         }
-        for (const Rect& x : rd) ohist[x.region].push_back(OpAcc{x.r0, x.r1, x.c0, x.c1, (int)pc, false});
-        for (const Rect& x : wr) ohist[x.region].push_back(OpAcc{x.r0, x.r1, x.c0, x.c1, (int)pc, true});
         int L = 0;
         for (const Rect& x : rd)
             for (const Acc& a : hist[x.region])
@@ -276,8 +279,9 @@ void schedule_levels(const HTree& hm, Program& prog) {
             newoff[t] = fl.back();
             fl.pop_back();
             // memory handed on: every op on t waits for every op on its previous owner
-            for (int pc : temp_ops[t])
-                for (int q : temp_ops[owner.at(newoff[t])]) preds[pc].push_back(q);
+            if (with_deps)
+                for (int pc : temp_ops[t])
+                    for (int q : temp_ops[owner.at(newoff[t])]) preds[pc].push_back(q);
         } else {
             newoff[t] = top;
             top += sz;
@@ -308,8 +312,10 @@ void schedule_levels(const HTree& hm, Program& prog) {
         prog.origin[i] = (int)idx[i];
     }
     prog.ops.swap(ops);
-    // dependency lists in the level order (sorted, no repeats)
-    {
+    // dependency lists in the level order (sorted, no repeats); empty when not asked for
+    prog.dep_off.clear();
+    prog.deps.clear();
+    if (with_deps) {
         std::vector<int> where(nops);
         for (size_t i = 0; i < nops; ++i) where[idx[i]] = (int)i;
         prog.dep_off.assign(nops + 1, 0);
