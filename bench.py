@@ -35,8 +35,8 @@ FP32_PEAK_TFLOPS = 157.3
 # dispatch, averaged over the k_level dispatches), each scaled by what the same counter reads for a
 # plain 256 MiB device copy (FETCH_SIZE reads half the bytes copied: x2; WRITE_SIZE reads them
 # all: x1). Valid for the kernel sources whose digest is recorded; `traffic` is null once they change.
-LEVEL_TRAFFIC = {"fetch_kib": 4160.0, "write_kib": 5810.8, "fetch_scale": 2.0, "write_scale": 1.0,
-                 "sources_sha256": "625d752a10bde40ef2ec28eeb2694dfa6943be81adc07835d989bff30cfaed83"}
+LEVEL_TRAFFIC = {"fetch_kib": 4159.2, "write_kib": 5810.1, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "sources_sha256": "eb2b24eb4b766938c8f3c072475eec19697041b58f6f3b438253fa99cb0c5289"}
 LEVEL_SOURCES = ("paper_1808_02937_amd/csrc/hinterp.hip", "paper_1808_02937_amd/csrc/hinterp.h",
                  "paper_1808_02937_amd/csrc/tri_wave.h", "paper_1808_02937_amd/csrc/hmatrix.h",
                  "paper_1808_02937_amd/build.py")
@@ -61,7 +61,7 @@ def level_traffic_bytes():
 # HBM traffic of the moment-streaming kernel of the dense apply (two-sided graded N=4096, P=8, one
 # right-hand side), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by the
 # same counters on a plain device copy; valid for the apply sources whose digest is recorded.
-MATVEC_TRAFFIC = {"fetch_kib": 2099305.8, "write_kib": 131328.0, "fetch_scale": 2.0, "write_scale": 1.0,
+MATVEC_TRAFFIC = {"fetch_kib": 2099303.2, "write_kib": 131328.0, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources_sha256": "8e652f020ac5631186b47428ce0a858559cc4035c8ce2f6bf262e80ba984c80c"}
 MATVEC_SOURCES = ("paper_1808_02937_amd/csrc/apply.hip", "paper_1808_02937_amd/csrc/fde_internal.h",
                   "paper_1808_02937_amd/build.py")
