@@ -170,15 +170,25 @@ __device__ inline void load_block(T (&v)[kHsChunk], const FacSrc<T, BF>& f, int6
     const int li = min(lane, rows - 1), cl = max(cols, 1) - 1;
     if constexpr (BF) {
         static_assert(sizeof(T) == 4, "BF16 low-rank factors come with FP32 factorisations");
+        // one 32-bit load per element from a wave-uniform base, then one byte permute: an FP32 word
+        // as it is, or the BF16 half-word of the element moved to the top with zeros below (the
+        // element's half follows from the parity of its index, the same for every column when ld is
+        // even, alternating when it is odd)
         const bool h16 = f.lr16 && off >= f.lr_base;   // wave-uniform
-        const unsigned* w32 = reinterpret_cast<const unsigned*>(f.arena) + (h16 ? 0 : off + li);
-        const unsigned* w16 = reinterpret_cast<const unsigned*>(f.lr16);   // 4-byte aligned
-        const int64_t e0 = h16 ? off - f.lr_base + li : 0;
+        const int64_t b = h16 ? off - f.lr_base : off;
+        const unsigned* base = h16 ? reinterpret_cast<const unsigned*>(f.lr16) + (b >> 1)   // 4-byte aligned
+                                   : reinterpret_cast<const unsigned*>(f.arena) + off;
+        const unsigned sh = h16 ? 1u : 0u;
+        const unsigned A = (h16 ? (unsigned)(b & 1) : 0u) + (unsigned)li;
+        constexpr unsigned kSelLo = 0x01000C0Cu, kSelHi = 0x03020C0Cu, kSelId = 0x03020100u;
+        const unsigned sel0 = h16 ? ((A & 1u) ? kSelHi : kSelLo) : kSelId;   // index parity of A
+        const unsigned sel1 = h16 ? ((A & 1u) ? kSelLo : kSelHi) : kSelId;   // the other parity
+        const auto g = gmem(base);
 #pragma unroll
         for (int c = 0; c < kHsChunk; ++c) {
-            const int64_t cc = (int64_t)min(c0 + c, cl) * ld, e = e0 + cc;
-            const unsigned w = *gmem(h16 ? w16 + (e >> 1) : w32 + cc);
-            v[c] = h16 ? (T)bf16_bits_to_float((unsigned short)((e & 1) ? w >> 16 : w & 0xffffu)) : __uint_as_float(w);
+            const unsigned cc = (unsigned)min(c0 + c, cl) * (unsigned)ld;   // wave-uniform
+            const unsigned w = g[(A + cc) >> sh];
+            v[c] = __uint_as_float(__builtin_amdgcn_perm(0u, w, (cc & 1u) ? sel1 : sel0));
         }
         return;
     }
