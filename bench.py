@@ -370,8 +370,55 @@ def cpu_model():
     return "unknown"
 
 
+def assign_keys(sizes, weights, shards, how="size"):
+    """Server of every key from its step time (`sizes`) and request share (`weights`).
+
+    "size": size-interval assignment -- the keys sorted by step time are cut into `shards`
+    contiguous intervals, the cut points the ones that minimise the largest server load (sum of
+    weight x step time), so a server's step, which lasts as long as its slowest request's, is never
+    held up by a much longer key; server 0 takes the shortest keys. "load": heaviest key first to
+    the least loaded server (every server gets a mix of short and long keys)."""
+    sizes = np.asarray(sizes, dtype=float)
+    cost = np.asarray(weights, dtype=float) * sizes
+    n = len(sizes)
+    owner = np.zeros(n, dtype=int)
+    if shards < 1 or shards > n:
+        raise ValueError(f"shards must be in [1, {n}] (got {shards})")
+    if how == "size":
+        order = np.argsort(sizes, kind="stable")
+        pre = np.concatenate([[0.0], np.cumsum(cost[order])])
+        # best[p][lo]: (largest load, cuts) of order[lo:] split into p + 1 intervals
+        best = [{lo: (pre[n] - pre[lo], []) for lo in range(n)}]
+        for p in range(1, shards):
+            cur = {}
+            for lo in range(n - p):
+                cand = None
+                for hi in range(lo + 1, n - p + 1):
+                    rest = best[p - 1][hi]
+                    c = (max(pre[hi] - pre[lo], rest[0]), [hi] + rest[1])
+                    if cand is None or c[0] < cand[0]:
+                        cand = c
+                cur[lo] = cand
+            best.append(cur)
+        edges = [0] + best[shards - 1][0][1] + [n]
+        for j in range(shards):
+            owner[order[edges[j]:edges[j + 1]]] = j
+    elif how == "load":
+        loadw = np.zeros(shards)
+        for k in np.argsort(-cost, kind="stable"):
+            j = int(np.argmin(loadw))
+            owner[k] = j
+            loadw[j] += cost[k]
+    else:
+        raise ValueError(f"assignment must be 'size' or 'load' (got {how!r})")
+    return owner
+
+
+SERVING_RATE = 180.0   # requests/s offered to every serving configuration
+
+
 def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=1808029375, n_keys=128, n_max=8192,
-                   precision="bf16uv", shards=3):
+                   precision="bf16uv", shards=3, assign="size", rate=None):
     """Continuous serving of a request stream (Section 5's problem class, many keys).
 
     A pool of n_keys problems: N log-uniform in [128, n_max], P in {4, 6, 8}, alpha ~ U(1.1, 1.9),
@@ -381,9 +428,11 @@ def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=18080
     least loaded), each on its own context and stream and driven by its own host thread, so a key's
     factors live in one server and the servers' latency-bound steps overlap on the device. Every
     problem is built once first; the saturated rate is measured with all requests submitted at once;
-    then requests arrive as a Poisson process at `load` times that rate and join their server between
-    its steps (fde_server_submit / fde_server_step), while others are in flight. Latency =
-    completion - arrival over n_req requests after n_warm."""
+    then requests arrive as a Poisson process at `rate` requests/s (by default `load` times the
+    saturated rate; the same seed gives every configuration the same arrival sequence) and join their
+    server between its steps (fde_server_submit / fde_server_step), while others are in flight.
+    Latency = completion - arrival over n_req requests after n_warm. `precision` is one factor
+    precision for every server or a list, one per server."""
     import threading
     gen = np.random.default_rng(seed)
     pool = []
@@ -399,24 +448,22 @@ def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=18080
     total = n_req + n_warm
     keys = gen.choice(len(pool), size=total, p=w)
     nrhs = gen.integers(1, 17, size=total)
-    # keys to servers by expected load: Zipf weight times the time of one Krylov step, an H-solve
-    # (about 0.2 us per unknown, a chain of leaf steps) plus an apply (on a graded mesh the dense
-    # moment stream, 8 P^2 N^2 / 2 bytes at about 4.4 TB/s; on a uniform one, small)
+    # keys to servers (assign_keys) by the time of one Krylov step of the key, an H-solve (about
+    # 0.2 us per unknown, a chain of leaf steps) plus an apply (on a graded mesh the dense moment
+    # stream, 8 P^2 N^2 / 2 bytes at about 4.4 TB/s; on a uniform one, small), and its Zipf weight
     def step_us(k):
         nodes, P = pool[k][0], pool[k][1]
         N = len(nodes) - 1
         uniform = np.allclose(np.diff(nodes), nodes[1] - nodes[0])
         return 0.2 * (N * P - 1) + (0.0 if uniform else 8.0 * P * P * N * N / 2 / 4.4e6)
-    owner = np.zeros(len(pool), dtype=int)
-    loadw = np.zeros(shards)
-    cost = np.array([w[k] * step_us(k) for k in range(len(pool))])
-    for k in np.argsort(-cost):
-        j = int(np.argmin(loadw))
-        owner[k] = j
-        loadw[j] += cost[k]
+    sizes = np.array([step_us(k) for k in range(len(pool))])
+    cost = w * sizes
+    owner = assign_keys(sizes, w, shards, assign)
+    shard_load = [float(cost[owner == j].sum() / cost.sum()) for j in range(shards)]
     # cached factors: FP32 dense blocks and BF16 low-rank factors (or the plain FP64 path)
     ctxs = [fde.Context(0, stream=torch.cuda.Stream(), apply_streams=0) for _ in range(shards)]
-    srvs = [fde.Server(c, R=8, leaf_elems=8, tol=1e-3, precision=precision, rtol=1e-10) for c in ctxs]
+    precs = [precision] * shards if isinstance(precision, str) else list(precision)
+    srvs = [fde.Server(c, R=8, leaf_elems=8, tol=1e-3, precision=pr, rtol=1e-10) for c, pr in zip(ctxs, precs)]
     gens = [torch.Generator(device="cuda").manual_seed(seed + j) for j in range(shards)]
 
     def rhs_of(j, key, k):
@@ -463,8 +510,12 @@ def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=18080
     sat_n = 200
     t = time.perf_counter()
     in_threads(lambda j: run_all(j, list(zip(keys[:sat_n], nrhs[:sat_n]))))
-    sat = sat_n / (time.perf_counter() - t)   # requests/s
-    rate = load * sat
+    t_sat = time.perf_counter() - t
+    sat = sat_n / t_sat   # requests/s
+    sat_solves = float(nrhs[:sat_n].sum() / t_sat)
+    if rate is None:
+        rate = load * sat
+    load = rate / sat
     arrivals = np.cumsum(gen.exponential(1.0 / rate, size=total))
     lat = np.zeros(total)
     hits = np.zeros(shards, dtype=int)
@@ -505,6 +556,10 @@ def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=18080
     in_threads(serve)
     elapsed = time.perf_counter() - t0[0]
     meas = lat[n_warm:] * 1e3
+
+    def pct(j, q):   # latency percentile of one server's requests
+        mine = meas[owner[keys[n_warm:]] == j]
+        return float(np.percentile(mine, q)) if len(mine) else None
     st = {}
     for srv in srvs:
         for k, v in srv.stats().items():
@@ -514,13 +569,18 @@ def serving_stream(fde, torch, ctx, n_req=1000, n_warm=100, load=0.7, seed=18080
         c.close()
     return {"requests": n_req, "warmup_requests": n_warm, "keys": len(pool), "rhs_per_request": "U{1..16}",
             "N_range": [128, n_max], "build_all_keys_s": t_build, "servers": shards,
-            "saturated_requests_per_s": sat, "arrival_rate_per_s": rate, "load": load,
+            "saturated_requests_per_s": sat, "saturated_solves_per_s": sat_solves, "arrival_rate_per_s": rate,
+            "load": load,
             "p50_ms": float(np.percentile(meas, 50)), "p99_ms": float(np.percentile(meas, 99)),
             "mean_ms": float(meas.mean()), "solves_per_s": float(nrhs.sum() / elapsed),
             "server_steps": int(steps.sum()), "mean_requests_in_flight": float(inflight.sum() / max(steps.sum(), 1)),
+            "assignment": assign, "server_load_share": shard_load,
+            "p50_ms_per_server": [pct(j, 50) for j in range(shards)],
+            "p99_ms_per_server": [pct(j, 99) for j in range(shards)],
+            "requests_per_server": [int((owner[keys[n_warm:]] == j).sum()) for j in range(shards)],
             "cache": st,
-            "cached_factor_precision": {"bf16uv": "FP32 dense blocks, BF16 U and V", "fp32": "FP32",
-                                        "fp64": "FP64"}[precision],
+            "cached_factor_precision": [{"bf16uv": "FP32 dense blocks, BF16 U and V", "fp32": "FP32",
+                                         "fp64": "FP64"}[pr] for pr in precs],
             "admitted_with_cached_factors": int(hits.sum()),
             "definition": ("latency = completion - arrival; Poisson arrivals; continuous batching (requests join "
                            "their server between FGMRES steps while others are in flight); keys spread over "
@@ -693,15 +753,28 @@ def main():
         out["batched_uneven"] = batched_uneven(fde, torch, ctx)
         log("degree per element")
         out["hp_mesh"] = hp_mesh_solve(fde, torch, ctx)
+        # every serving line at one arrival rate (about 0.7 of the lowest saturated rate), so that
+        # their latencies compare; throughput is each configuration's saturated rate
+        rate = SERVING_RATE
+        brief = ("saturated_requests_per_s", "saturated_solves_per_s", "arrival_rate_per_s", "load", "p50_ms",
+                 "p99_ms", "mean_ms", "server_steps", "p50_ms_per_server", "p99_ms_per_server",
+                 "cached_factor_precision")
         log("serving stream")
-        out["serving"] = serving_stream(fde, torch, ctx)
+        out["serving"] = serving_stream(fde, torch, ctx, rate=rate)
         log("serving stream, plain FP64 path")
-        out["serving_fp64"] = serving_stream(fde, torch, ctx, precision="fp64")
+        out["serving_fp64"] = serving_stream(fde, torch, ctx, precision="fp64", rate=rate)
+        log("serving stream, BF16 U, V on the servers of the short keys, FP64 on the longest")
+        mix = serving_stream(fde, torch, ctx, precision=["bf16uv", "bf16uv", "fp64"], rate=rate)
+        out["serving_precision_by_size"] = {k: mix[k] for k in brief}
+        log("serving stream, FP32 factors")
+        f32 = serving_stream(fde, torch, ctx, precision="fp32", rate=rate)
+        out["serving_fp32"] = {k: f32[k] for k in brief}
+        log("serving stream, keys mixed on every server")
+        lm = serving_stream(fde, torch, ctx, assign="load", rate=rate)
+        out["serving_mixed_keys"] = {k: lm[k] for k in brief}
         log("serving stream, one server")
-        one = serving_stream(fde, torch, ctx, shards=1)
-        out["serving_one_server"] = {k: one[k] for k in ("saturated_requests_per_s", "arrival_rate_per_s", "p50_ms",
-                                                         "p99_ms", "mean_ms", "solves_per_s",
-                                                         "mean_requests_in_flight")}
+        one = serving_stream(fde, torch, ctx, shards=1, rate=rate)
+        out["serving_one_server"] = {k: one[k] for k in brief}
         out["latency_ms"] = {"p50": out["serving"]["p50_ms"], "p99": out["serving"]["p99_ms"],
                              "definition": "request completion - arrival, serving stream (see serving)",
                              "batch_p50": float(np.percentile(lat, 50) * 1e3),
