@@ -34,11 +34,13 @@ FP32_PEAK_TFLOPS = 157.3
 # --pmc runs of `bench.py --steps 1 --warmup 0 --quick` (FETCH_SIZE, then WRITE_SIZE; KiB per
 # dispatch, averaged over the k_level dispatches), each scaled by what the same counter reads for a
 # plain 256 MiB device copy (FETCH_SIZE reads half the bytes copied: x2; WRITE_SIZE reads them
-# all: x1). Valid for the kernel sources whose digest is recorded; `traffic` is null once they change.
-LEVEL_TRAFFIC = {"fetch_kib": 4159.2, "write_kib": 5810.1, "fetch_scale": 2.0, "write_scale": 1.0,
-                 "sources_sha256": "eb2b24eb4b766938c8f3c072475eec19697041b58f6f3b438253fa99cb0c5289"}
+# all: x1). Valid for the sources of the kernel, its op lists and their schedule whose digest is
+# recorded; `traffic` is null once they change.
+LEVEL_TRAFFIC = {"fetch_kib": 4058.2, "write_kib": 5688.8, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "sources_sha256": "e52165a26d68a787251e56b885a2420fb79643e852c72db536434a7c719ab046"}
 LEVEL_SOURCES = ("paper_1808_02937_amd/csrc/hinterp.hip", "paper_1808_02937_amd/csrc/hinterp.h",
                  "paper_1808_02937_amd/csrc/tri_wave.h", "paper_1808_02937_amd/csrc/hmatrix.h",
+                 "paper_1808_02937_amd/csrc/progs.cpp", "paper_1808_02937_amd/csrc/schedule.cpp",
                  "paper_1808_02937_amd/build.py")
 
 

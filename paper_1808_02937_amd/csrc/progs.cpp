@@ -100,14 +100,6 @@ class Gen {
         o.dim[1] = X.width;
         p_.ops.push_back(o);
     }
-    void zero(const Slab& s) {
-        OpRec o{};
-        o.code = OP_ZERO;
-        o.v[0] = s.v;
-        o.dim[0] = s.rows;
-        o.dim[1] = s.width;
-        p_.ops.push_back(o);
-    }
     void lrsub(int b, const Slab& X, const Slab& Y) {
         OpRec o{};
         o.code = OP_LRSUB;
@@ -120,10 +112,14 @@ class Gen {
     }
 
     // ---- H-arithmetic (same recursion and order as the FP64 reference)
-    void matmul_add(int A, const Slab& X, const Slab& Y, float alpha) {   // Y += alpha A X
+    // Y += alpha A X; with `first`, Y = alpha A X: the first product into each row range of Y
+    // overwrites it (beta = 0, the same bits as adding to zeros), so no op clears Y beforehand
+    void matmul_add(int A, const Slab& X, const Slab& Y, float alpha, bool first = false) {
         const Block& a = B(A);
+        const float beta = first ? 0.f : 1.f;
+        if (first && solve_) fail(FDE_EDEVICE, "H-solve program: overwriting product");
         if (a.kind == kDense) {
-            gemm(Y.v, dense(A), X.v, rows(A), X.width, cols(A), alpha, 1.f);
+            gemm(Y.v, dense(A), X.v, rows(A), X.width, cols(A), alpha, beta);
         } else if (a.kind == kLowRank) {
             Slab t = alloc(hm_.kmax, X.width, solve_ ? 1 : cap(X.width));
             if (solve_) {
@@ -140,28 +136,31 @@ class Gen {
                 p_.ops.push_back(o);
             } else {
                 gemm(t.v, T(V(A).v), X.v, rank_code(a), X.width, cols(A), 1.f, 0.f);
-                gemm(Y.v, U(A).v, t.v, rows(A), X.width, rank_code(a), alpha, 1.f);
+                gemm(Y.v, U(A).v, t.v, rows(A), X.width, rank_code(a), alpha, beta);
             }
             release(t);
         } else {
             for (int i = 0; i < 2; ++i)
                 for (int j = 0; j < 2; ++j)
-                    matmul_add(ch(A, i, j), half(X, a.sigma, j), half(Y, a.tau, i), alpha);
+                    matmul_add(ch(A, i, j), half(X, a.sigma, j), half(Y, a.tau, i), alpha, first && j == 0);
         }
     }
-    void matmulT_add(int A, const Slab& X, const Slab& Y, float alpha) {  // Y += alpha A^T X
+    // Y += alpha A^T X (Y = alpha A^T X with `first`, as above)
+    void matmulT_add(int A, const Slab& X, const Slab& Y, float alpha, bool first = false) {
         const Block& a = B(A);
+        const float beta = first ? 0.f : 1.f;
+        if (first && solve_) fail(FDE_EDEVICE, "H-solve program: overwriting product");
         if (a.kind == kDense) {
-            gemm(Y.v, denseT(A), X.v, cols(A), X.width, rows(A), alpha, 1.f);
+            gemm(Y.v, denseT(A), X.v, cols(A), X.width, rows(A), alpha, beta);
         } else if (a.kind == kLowRank) {
             Slab t = alloc(hm_.kmax, X.width, solve_ ? 1 : cap(X.width));
             gemm(t.v, T(U(A).v), X.v, rank_code(a), X.width, rows(A), 1.f, 0.f);
-            gemm(Y.v, V(A).v, t.v, cols(A), X.width, rank_code(a), alpha, 1.f);
+            gemm(Y.v, V(A).v, t.v, cols(A), X.width, rank_code(a), alpha, beta);
             release(t);
         } else {
             for (int j = 0; j < 2; ++j)
                 for (int i = 0; i < 2; ++i)
-                    matmulT_add(ch(A, i, j), half(X, a.tau, i), half(Y, a.sigma, j), alpha);
+                    matmulT_add(ch(A, i, j), half(X, a.tau, i), half(Y, a.sigma, j), alpha, first && i == 0);
         }
     }
     void lr_sub(int C, const Slab& X, const Slab& Y) {   // C <- C - X Y^T
@@ -179,14 +178,12 @@ class Gen {
         const Block &a = B(A), &b = B(Bb), &c = B(C);
         if (a.kind == kLowRank) {
             Slab W = alloc(cols(Bb), rank_code(a), hm_.kmax);
-            zero(W);
-            matmulT_add(Bb, V(A), W, 1.f);
+            matmulT_add(Bb, V(A), W, 1.f, true);
             lr_sub(C, U(A), W);
             release(W);
         } else if (b.kind == kLowRank) {
             Slab Z = alloc(rows(A), rank_code(b), hm_.kmax);
-            zero(Z);
-            matmul_add(A, U(Bb), Z, 1.f);
+            matmul_add(A, U(Bb), Z, 1.f, true);
             lr_sub(C, Z, V(Bb));
             release(Z);
         } else if (a.kind == kDense && b.kind == kDense) {

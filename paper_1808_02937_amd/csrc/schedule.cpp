@@ -381,6 +381,7 @@ void op_uses(const HTree& hm, const OpRec& o, size_t pc, std::vector<Use>& uses,
             const int64_t m = dimv(o.dim[0]), n = dimv(o.dim[1]), k = dimv(o.dim[2]);
             uses.push_back({o.v[1], m, k, false});
             uses.push_back({o.v[2], k, n, false});
+            if (o.beta != 0.f) uses.push_back({o.v[0], m, n, false});   // C is read unless beta = 0
             uses.push_back({o.v[0], m, n, true});
             break;
         }
@@ -502,6 +503,7 @@ void check_schedule(const HTree& hm, const Program& original, const Program& sch
     // element-wise replay in program order over the arena, the slots and the ORIGINAL temporaries
     const int64_t AE = hm.arena_elems, WE = original.work_elems, NS = hm.nslots;
     std::vector<int> lw(AE + WE + NS, 0), lr(AE + WE + NS, 0);
+    std::vector<char> wrote(WE, 0);   // temporaries start undefined: none is read before a write
     std::vector<Use> uses;
     std::vector<std::pair<int, bool>> slots;
     // every access of an op is checked against the earlier ops before any of them is recorded
@@ -516,9 +518,12 @@ void check_schedule(const HTree& hm, const Program& original, const Program& sch
             if (L <= lw[e] || (write && L <= lr[e]))
                 fail(FDE_EDEVICE, "schedule check: op %zu (level %d) conflicts with level %d", pc, L,
                      std::max(lw[e], write ? lr[e] : 0));
+            if (!write && e >= AE && e < AE + WE && !wrote[e - AE])
+                fail(FDE_EDEVICE, "schedule check: op %zu reads a temporary no earlier op wrote", pc);
         };
         auto record = [&](int64_t e, bool write) {
             if (write) {
+                if (e >= AE && e < AE + WE) wrote[e - AE] = 1;
                 lw[e] = L;
                 lr[e] = 0;
             } else {
