@@ -358,9 +358,15 @@ __device__ __attribute__((noinline)) void op_trsm(const Inst<T>& d, const OpRec&
 
 // ------------------------------------------------------------------ GETRF
 // LU without pivoting of a dense leaf (unit lower L), right-looking. Leaves up to kLU = 64 rows:
-// one wavefront, lane i holds row i in registers; both loops are unrolled, so at step k the
-// pivot row is broadcast entry by entry with readlane and every lane updates its own row, with
-// no LDS traffic and no barrier. Larger leaves: in place, two barriers per step.
+// lane i of every wavefront holds row i, wavefront w its columns 16 w .. 16 w + 15, in registers;
+// the step loop is unrolled. At step k the wavefront holding column k forms the multipliers,
+// updates its own columns past k (the pivot row broadcast entry by entry with readlane) and puts
+// the multipliers and its pivot verdict in LDS; after one barrier the wavefronts to its right
+// update their columns. Each entry sees the same operations as in a one-wavefront sweep. The
+// slot alternates with the step's parity, so a slot is rewritten only after every wavefront has
+// passed the next barrier; every step has its barrier (a counted loop, fully unrolled), and a
+// failed pivot stops the updates in every wavefront at the same step. Larger leaves: in place,
+// two barriers per step.
 template <class T, class SH>
 __device__ __attribute__((noinline)) bool op_getrf(const Inst<T>& d, const OpRec& o, SH& sh, int pc) {
     const int n = o.dim[0];
@@ -368,44 +374,62 @@ __device__ __attribute__((noinline)) bool op_getrf(const Inst<T>& d, const OpRec
     const int rs = o.v[0].rs, cs = o.v[0].cs;
     auto at = [&](int i, int j) -> T& { return A[(int64_t)i * rs + (int64_t)j * cs]; };
     if (n <= kLU) {
-        if (threadIdx.x < 64) {
-            const int i = threadIdx.x;
-            const int ri = min(i, n - 1);
-            T a[kLU];
+        static_assert(kLU == 16 * kW, "four wavefronts of 16 columns");
+        static_assert(sizeof(GemmLds<T>) >= 2 * 65 * sizeof(T), "GETRF step slots");
+        T* slots = reinterpret_cast<T*>(&sh.gm);   // [2][65]: the step's multipliers, then its verdict
+        const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
+        const int ri = min(i, n - 1);
+        T a[16];
 #pragma unroll
-            for (int j = 0; j < kLU; ++j) a[j] = A[(int64_t)ri * rs + (int64_t)min(j, n - 1) * cs];
-            double amax = 0.0;
+        for (int c = 0; c < 16; ++c) a[c] = A[(int64_t)ri * rs + (int64_t)min(16 * w + c, n - 1) * cs];
+        double amax = 0.0;
 #pragma unroll
-            for (int j = 0; j < kLU; ++j) {
-                if (i >= n || j >= n) a[j] = T(0);
-                amax = fmax(amax, fabs((double)a[j]));
+        for (int c = 0; c < 16; ++c) {
+            if (i >= n || 16 * w + c >= n) a[c] = T(0);
+            amax = fmax(amax, fabs((double)a[c]));
+        }
+        amax = wave_max(amax);
+        if (i == 0) sh.red[w][0] = amax;
+        __syncthreads();
+        amax = fmax(fmax(sh.red[0][0], sh.red[1][0]), fmax(sh.red[2][0], sh.red[3][0]));
+        int fail_at = -1;
+#pragma unroll
+        for (int k = 0; k < kLU; ++k) {
+            const bool live = k < n && fail_at < 0;   // the same in every thread
+            const int kw = k >> 4, kc = k & 15;
+            T* sl = slots + (k & 1) * 65;
+            if (live && w == kw) {
+                const T akk = lane_bcast(a[kc], k);
+                const bool bad = !(fabs((double)akk) > d.pivot_floor * amax) || !(fabs((double)akk) > 0.0);
+                if (!bad) {
+                    // an opaque copy of the row index: the per-step row masks are formed here rather
+                    // than hoisted and held in registers across the elimination
+                    int ii = i;
+                    asm volatile("" : "+v"(ii));
+                    const T l = ii > k ? a[kc] / akk : T(0);
+                    if (ii > k) a[kc] = l;
+                    sl[i] = l;
+#pragma unroll
+                    for (int c = kc + 1; c < 16; ++c) a[c] -= l * lane_bcast(a[c], k);
+                }
+                if (i == 0) sl[64] = bad ? T(1) : T(0);
             }
-            for (int o2 = 32; o2 > 0; o2 >>= 1) amax = fmax(amax, __shfl_xor(amax, o2, 64));
-            int fail_at = -1;
+            __syncthreads();
+            if (live) {
+                if (sl[64] != T(0)) {
+                    fail_at = k;
+                } else if (w > kw) {
+                    const T l = sl[i];
 #pragma unroll
-            for (int k = 0; k < kLU; ++k) {
-                if (k < n && fail_at < 0) {
-                    const T akk = lane_bcast(a[k], k);
-                    if (!(fabs((double)akk) > d.pivot_floor * amax) || !(fabs((double)akk) > 0.0)) {
-                        fail_at = k;
-                    } else {
-                        // an opaque copy of the row index: the 64 per-step row masks are formed here
-                        // rather than hoisted and held in registers across the elimination
-                        int ii = i;
-                        asm volatile("" : "+v"(ii));
-                        const T l = ii > k ? a[k] / akk : T(0);
-                        if (ii > k) a[k] = l;
-#pragma unroll
-                        for (int j = k + 1; j < kLU; ++j) a[j] -= l * lane_bcast(a[j], k);
-                    }
+                    for (int c = 0; c < 16; ++c) a[c] -= l * lane_bcast(a[c], k);
                 }
             }
-            if (fail_at < 0 && i < n)
-#pragma unroll
-                for (int j = 0; j < kLU; ++j)
-                    if (j < n) A[(int64_t)i * rs + (int64_t)j * cs] = a[j];
-            if (i == 0) sh.flag = fail_at;
         }
+        if (fail_at < 0 && i < n)
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (16 * w + c < n) A[(int64_t)i * rs + (int64_t)(16 * w + c) * cs] = a[c];
+        if (threadIdx.x == 0) sh.flag = fail_at;
         __syncthreads();
         if (sh.flag >= 0) {
             if (threadIdx.x == 0) {
