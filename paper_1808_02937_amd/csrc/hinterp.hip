@@ -272,8 +272,8 @@ __device__ void op_zero(const Inst<T>& d, const OpRec& o) {
 }
 
 // ------------------------------------------------------------------ TRSM
-template <class T>
-__device__ __attribute__((noinline)) void op_trsm(const Inst<T>& d, const OpRec& o) {
+template <class T, class SH>
+__device__ __attribute__((noinline)) void op_trsm(const Inst<T>& d, const OpRec& o, SH& sh) {
     const int n = dimval(d, o.dim[0]), w = dimval(d, o.dim[1]);
     if (n <= 0 || w <= 0) return;
     T* X = vptr(d, o.v[0]);
@@ -282,6 +282,22 @@ __device__ __attribute__((noinline)) void op_trsm(const Inst<T>& d, const OpRec&
     const bool lower = o.flags & 1, unit = o.flags & 2;
     auto Tat = [&](int i, int j) -> T { return Tm[(int64_t)i * trs + (int64_t)j * tcs]; };
     if (n <= 64) {
+        if (tcs == 1 && trs != 1) {
+            // a triangle read row-wise (the transposed view of a column-major block): every lane
+            // would load its own row, 64 cache lines per load instruction. Staged through LDS
+            // instead, consecutive threads along each row, padded row stride 65 (no bank conflicts).
+            static_assert(sizeof(GemmLds<T>) >= 64 * 65 * sizeof(T), "TRSM triangle stage");
+            T* st = reinterpret_cast<T*>(&sh.gm);
+            __syncthreads();   // the previous op's use of this LDS is over
+            for (int idx = threadIdx.x; idx < 64 * 64; idx += kT) {
+                const int i = idx >> 6, c = idx & 63;
+                if (i < n && c < n) st[i * 65 + c] = Tm[(int64_t)i * trs + c];
+            }
+            __syncthreads();
+            tri_wave(static_cast<const T*>(st), 65, 1, n, lower, unit, X, xrs, xcs, w, (int)(threadIdx.x >> 6), kW);
+            __syncthreads();
+            return;
+        }
         tri_wave(Tm, trs, tcs, n, lower, unit, X, xrs, xcs, w, (int)(threadIdx.x >> 6), kW);
         return;
     }
@@ -1375,7 +1391,7 @@ __device__ bool run_op(const Inst<T>& d, const OpRec& o, int pc, SH& sh, int ste
     switch (o.code) {
         case OP_GEMM: op_gemm(d, o, sh); break;
         case OP_ZERO: op_zero(d, o); break;
-        case OP_TRSM: op_trsm(d, o); break;
+        case OP_TRSM: op_trsm(d, o, sh); break;
         case OP_LRSUB: op_lrsub(d, o, sh); break;
         case OP_GETRF: ok = op_getrf(d, o, sh, pc); break;
         case OP_LRMV: {
