@@ -132,9 +132,11 @@ __device__ inline int dimval(const Inst<T>& d, int code) {
 }
 
 // ------------------------------------------------------------------ GEMM / ZERO
-// C = beta C + alpha A B. Blocks of at least 16 x 16 outputs go through LDS tiles (64 x 64
-// outputs, k in chunks of 32; each thread a 4 x 4 register tile); thin products use G lanes
-// per output, consecutive lanes along k, reduced by shuffles, or one thread per output.
+// C = beta C + alpha A B. Products of at least 16 rows go through LDS tiles (64 x 64 outputs, k
+// in chunks of 32; each thread a 4 x 4 register tile, masked at the edges) when they have at
+// least 16 columns, or more outputs than threads and k >= 16 (one thread per output would walk
+// its outputs one after another, a memory latency each); thin products use G lanes per output,
+// consecutive lanes along k, reduced by shuffles, or one thread per output.
 template <class T, class SH>
 __device__ __attribute__((noinline)) void op_gemm(const Inst<T>& d, const OpRec& o, SH& sh) {
     const int m = dimval(d, o.dim[0]), n = dimval(d, o.dim[1]), k = dimval(d, o.dim[2]);
@@ -146,7 +148,7 @@ __device__ __attribute__((noinline)) void op_gemm(const Inst<T>& d, const OpRec&
     const int crs = o.v[0].rs, ccs = o.v[0].cs;
     if (m <= 0 || n <= 0) return;
     const int t = threadIdx.x;
-    if (m >= 16 && n >= 16 && k >= 4) {
+    if (m >= 16 && (n >= 16 || (k >= 16 && (int64_t)m * n > kT))) {
         // The loads of an operand's stage are issued before any is used (addresses of elements
         // outside the operand are clamped to its first entry), and the 16 entries of C a thread
         // updates are read together after the products: a tile costs a few memory latencies
